@@ -1,0 +1,319 @@
+"""CPU oracle for the out-of-core compressed stencil path (arXiv 2109.05410).
+
+TEST INFRASTRUCTURE. Only the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package. The GPU library
+shares no code with it and never calls it.
+
+Thin ctypes wrapper over ``oracle.c`` (plain C, FP64 stencils, FP32 variants
+with a fixed operation order, the reference fixed-rate codec, and the replay
+of the compressed out-of-core schedule), plus the error metrics of Sec. VI-C
+written in numpy.
+
+Arrays are numpy, shaped (nz, ny, nx), C order (x contiguous).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        src = os.path.join(_HERE, "oracle.c")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+        L = C.CDLL(path)
+        P = C.c_void_p
+        l = C.c_long
+        L.orc_heat7_f64.argtypes = [P, l, l, l, C.c_double, l]
+        L.orc_heat7_f32.argtypes = [P, l, l, l, C.c_float, l]
+        L.orc_lap25_f64.argtypes = [P, P, l, l, l]
+        L.orc_wave25_f64.argtypes = [P, P, P, l, l, l, l, P, l]
+        L.orc_wave25_f32.argtypes = [P, P, P, l, l, l, l, P, l]
+        L.orc_codec_perm.argtypes = [P]
+        L.orc_fwd_xform.argtypes = [P, P]
+        L.orc_inv_xform.argtypes = [P, P]
+        L.orc_encode_block.argtypes = [P, C.c_int, P, P]
+        L.orc_decode_block.argtypes = [P, C.c_int, P, P]
+        L.orc_codec_words.argtypes = [l, l, l, C.c_int]
+        L.orc_codec_words.restype = C.c_size_t
+        L.orc_codec_encode.argtypes = [P, l, l, l, C.c_int, P]
+        L.orc_codec_decode.argtypes = [P, l, l, l, C.c_int, P]
+        L.orc_codec_roundtrip.argtypes = [P, l, l, l, C.c_int]
+        L.orc_codec_roundtrip_f64.argtypes = [P, l, l, l, C.c_int]
+        L.orc_code_ints.argtypes = [P, l, P]
+        L.orc_code_ints.restype = C.c_long
+        L.orc_decode_ints.argtypes = [P, l, P]
+        L.orc_replay_heat_f32.argtypes = [P, l, l, l, C.c_float, l, l, C.c_int]
+        L.orc_replay_heat_f64.argtypes = [P, l, l, l, C.c_double, l, l, C.c_int]
+        L.orc_replay_wave_f32.argtypes = [P, P, P, l, l, l, l, l, P, l, C.c_int, C.c_int, C.c_int]
+        L.orc_replay_wave_f64.argtypes = [P, P, P, l, l, l, l, l, P, l, C.c_int, C.c_int, C.c_int]
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dims(a: np.ndarray):
+    nz, ny, nx = a.shape
+    return nx, ny, nz
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+# --------------------------------------------------------------------------
+# Stencils
+# --------------------------------------------------------------------------
+
+def heat7_f64(u0: np.ndarray, alpha: float, steps: int) -> np.ndarray:
+    """`steps` Jacobi steps of the 7-point heat stencil, zero Dirichlet ghosts, FP64."""
+    u = np.ascontiguousarray(u0, dtype=np.float64).copy()
+    _check(lib().orc_heat7_f64(_ptr(u), *_dims(u), float(alpha), int(steps)), "heat7_f64")
+    return u
+
+
+def heat7_f32(u0: np.ndarray, alpha: float, steps: int) -> np.ndarray:
+    """FP32 heat steps in the fixed operation order (bit-exact reference)."""
+    u = np.ascontiguousarray(u0, dtype=np.float32).copy()
+    _check(lib().orc_heat7_f32(_ptr(u), *_dims(u), float(np.float32(alpha)), int(steps)), "heat7_f32")
+    return u
+
+
+def lap25_f64(p: np.ndarray) -> np.ndarray:
+    """8th-order Laplacian in grid-index units with zero ghosts of width 4, FP64."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.empty_like(p)
+    _check(lib().orc_lap25_f64(_ptr(p), _ptr(out), *_dims(p)), "lap25_f64")
+    return out
+
+
+def _src_args(src, dtype, steps):
+    if src is None:
+        return None, -1, None
+    amps, index = src
+    a = np.ascontiguousarray(amps, dtype=dtype)
+    if a.size < steps:
+        raise ValueError("source needs one amplitude per step")
+    return a, int(index), _ptr(a)
+
+
+def wave25_f64(p0, pm0, w, steps, src=None):
+    """Leapfrog steps of the 25-point wave, FP64.
+
+    (pm0, p0) = (p(n-1), p(n)); returns (p(n+steps), p(n+steps-1)).
+    ``src`` = (amplitudes[steps], flat cell index) or None.
+    """
+    p = np.ascontiguousarray(p0, dtype=np.float64).copy()
+    pm = np.ascontiguousarray(pm0, dtype=np.float64).copy()
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    a, idx, ap = _src_args(src, np.float64, steps)
+    _check(lib().orc_wave25_f64(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), ap, idx), "wave25_f64")
+    return p, pm
+
+
+def wave25_f32(p0, pm0, w, steps, src=None):
+    """FP32 wave steps in the fixed operation order (bit-exact reference)."""
+    p = np.ascontiguousarray(p0, dtype=np.float32).copy()
+    pm = np.ascontiguousarray(pm0, dtype=np.float32).copy()
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    a, idx, ap = _src_args(src, np.float32, steps)
+    _check(lib().orc_wave25_f32(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), ap, idx), "wave25_f32")
+    return p, pm
+
+
+# --------------------------------------------------------------------------
+# Codec
+# --------------------------------------------------------------------------
+
+class Stages(C.Structure):
+    _fields_ = [
+        ("emax", C.c_int32),
+        ("q", C.c_int32 * 64),
+        ("t", C.c_int32 * 64),
+        ("u", C.c_uint32 * 64),
+        ("plane", C.c_uint64 * 32),
+        ("bits_used", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "emax": int(self.emax),
+            "q": np.array(self.q[:], dtype=np.int32),
+            "t": np.array(self.t[:], dtype=np.int32),
+            "u": np.array(self.u[:], dtype=np.uint32),
+            "plane": np.array(self.plane[:], dtype=np.uint64),
+            "bits_used": int(self.bits_used),
+        }
+
+
+EMAX_ZERO = -(2 ** 31)
+
+
+def codec_perm() -> np.ndarray:
+    out = np.zeros(64, dtype=np.int32)
+    _check(lib().orc_codec_perm(_ptr(out)), "codec_perm")
+    return out
+
+
+def fwd_xform(q64: np.ndarray) -> np.ndarray:
+    q = np.ascontiguousarray(q64, dtype=np.int32).reshape(64)
+    out = np.zeros(64, dtype=np.int32)
+    _check(lib().orc_fwd_xform(_ptr(q), _ptr(out)), "fwd_xform")
+    return out
+
+
+def inv_xform(t64: np.ndarray) -> np.ndarray:
+    t = np.ascontiguousarray(t64, dtype=np.int32).reshape(64)
+    out = np.zeros(64, dtype=np.int32)
+    _check(lib().orc_inv_xform(_ptr(t), _ptr(out)), "inv_xform")
+    return out
+
+
+def encode_block(vals64, rate: int):
+    """One 4^3 block (natural order i+4j+16l) -> (rate uint64 words, stages dict)."""
+    v = np.ascontiguousarray(vals64, dtype=np.float32).reshape(64)
+    out = np.zeros(rate, dtype=np.uint64)
+    st = Stages()
+    _check(lib().orc_encode_block(_ptr(v), int(rate), _ptr(out), C.byref(st)), "encode_block")
+    return out, st.as_dict()
+
+
+def decode_block(words, rate: int):
+    w = np.ascontiguousarray(words, dtype=np.uint64).reshape(rate)
+    out = np.zeros(64, dtype=np.float32)
+    st = Stages()
+    _check(lib().orc_decode_block(_ptr(w), int(rate), _ptr(out), C.byref(st)), "decode_block")
+    return out, st.as_dict()
+
+
+def code_ints(u64, budget: int):
+    """Bit-plane coder alone: 64 negabinary words -> (stream words, bits used)."""
+    u = np.ascontiguousarray(u64, dtype=np.uint32).reshape(64)
+    out = np.zeros(max(1, (budget + 63) // 64), dtype=np.uint64)
+    used = int(lib().orc_code_ints(_ptr(u), int(budget), _ptr(out)))
+    return out, used
+
+
+def decode_ints(words, budget: int) -> np.ndarray:
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size * 64 < budget:
+        raise ValueError("stream shorter than budget")
+    out = np.zeros(64, dtype=np.uint32)
+    _check(lib().orc_decode_ints(_ptr(w), int(budget), _ptr(out)), "decode_ints")
+    return out
+
+
+def codec_words(nx: int, ny: int, nz: int, rate: int) -> int:
+    return int(lib().orc_codec_words(nx, ny, nz, rate))
+
+
+def codec_encode(f: np.ndarray, rate: int) -> np.ndarray:
+    """Whole field (nz, ny, nx) FP32, dims multiples of 4 -> uint64 words."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    nx, ny, nz = _dims(f)
+    out = np.zeros(codec_words(nx, ny, nz, rate), dtype=np.uint64)
+    _check(lib().orc_codec_encode(_ptr(f), nx, ny, nz, int(rate), _ptr(out)), "codec_encode")
+    return out
+
+
+def codec_decode(words: np.ndarray, shape, rate: int) -> np.ndarray:
+    nz, ny, nx = shape
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size != codec_words(nx, ny, nz, rate):
+        raise ValueError("word count does not match shape and rate")
+    out = np.zeros((nz, ny, nx), dtype=np.float32)
+    _check(lib().orc_codec_decode(_ptr(w), nx, ny, nz, int(rate), _ptr(out)), "codec_decode")
+    return out
+
+
+def codec_roundtrip(f: np.ndarray, rate: int) -> np.ndarray:
+    """Q(f) = decode(encode(f)) for an FP32 field."""
+    g = np.ascontiguousarray(f, dtype=np.float32).copy()
+    _check(lib().orc_codec_roundtrip(_ptr(g), *_dims(g), int(rate)), "codec_roundtrip")
+    return g
+
+
+# --------------------------------------------------------------------------
+# Replay of the compressed out-of-core schedule (Sec. V-A)
+# --------------------------------------------------------------------------
+
+def replay_heat_f32(u0, alpha, steps, k, rate):
+    u = np.ascontiguousarray(u0, dtype=np.float32).copy()
+    _check(lib().orc_replay_heat_f32(_ptr(u), *_dims(u), float(np.float32(alpha)), int(steps), int(k), int(rate)),
+           "replay_heat_f32")
+    return u
+
+
+def replay_heat_f64(u0, alpha, steps, k, rate):
+    u = np.ascontiguousarray(u0, dtype=np.float64).copy()
+    _check(lib().orc_replay_heat_f64(_ptr(u), *_dims(u), float(alpha), int(steps), int(k), int(rate)),
+           "replay_heat_f64")
+    return u
+
+
+def replay_wave_f32(p0, pm0, w0, steps, k, src=None, rate_p=0, rate_pm=0, rate_w=0):
+    """Returns (p, pm, Q(w)) after `steps` with k steps per residency."""
+    p = np.ascontiguousarray(p0, dtype=np.float32).copy()
+    pm = np.ascontiguousarray(pm0, dtype=np.float32).copy()
+    w = np.ascontiguousarray(w0, dtype=np.float32).copy()
+    a, idx, ap = _src_args(src, np.float32, steps)
+    _check(lib().orc_replay_wave_f32(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), int(k), ap, idx,
+                                     int(rate_p), int(rate_pm), int(rate_w)), "replay_wave_f32")
+    return p, pm, w
+
+
+def replay_wave_f64(p0, pm0, w0, steps, k, src=None, rate_p=0, rate_pm=0, rate_w=0):
+    p = np.ascontiguousarray(p0, dtype=np.float64).copy()
+    pm = np.ascontiguousarray(pm0, dtype=np.float64).copy()
+    w = np.ascontiguousarray(w0, dtype=np.float64).copy()
+    a, idx, ap = _src_args(src, np.float64, steps)
+    _check(lib().orc_replay_wave_f64(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), int(k), ap, idx,
+                                     int(rate_p), int(rate_pm), int(rate_w)), "replay_wave_f64")
+    return p, pm, w
+
+
+# --------------------------------------------------------------------------
+# Error metrics (Sec. VI-C: mean point-wise relative error over 100 sampled
+# points per plane; plus normwise max and L2 relative errors)
+# --------------------------------------------------------------------------
+
+def sample_points(shape, per_plane: int = 100, seed: int = 0) -> np.ndarray:
+    """Flat indices of `per_plane` seeded points in every z-plane."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    ij = rng.integers(0, nx * ny, size=(nz, per_plane))
+    return (np.arange(nz)[:, None] * (nx * ny) + ij).reshape(-1)
+
+
+def errors(a: np.ndarray, ref: np.ndarray, per_plane: int = 100, seed: int = 0) -> dict:
+    """Error of `a` against reference `ref` (both full fields)."""
+    a64 = np.asarray(a, dtype=np.float64)
+    r64 = np.asarray(ref, dtype=np.float64)
+    d = a64 - r64
+    rmax = float(np.max(np.abs(r64)))
+    l2r = float(np.linalg.norm(r64.ravel()))
+    idx = sample_points(r64.shape, per_plane, seed)
+    av, rv = a64.ravel()[idx], r64.ravel()[idx]
+    keep = np.abs(rv) > 1e-30 * max(rmax, 1e-300)
+    pw = np.abs(av[keep] - rv[keep]) / np.abs(rv[keep])
+    return {
+        "max_rel": float(np.max(np.abs(d))) / rmax if rmax > 0 else float(np.max(np.abs(d))),
+        "l2_rel": float(np.linalg.norm(d.ravel())) / l2r if l2r > 0 else float(np.linalg.norm(d.ravel())),
+        "pointwise_mean_rel": float(pw.mean()) if pw.size else 0.0,
+        "sampled_points": int(idx.size),
+        "sampled_used": int(pw.size),
+    }
