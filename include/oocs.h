@@ -1,0 +1,287 @@
+/*
+ * oocs.h -- C ABI of liboocs, an MI355X (gfx950) library for out-of-core
+ * stencil computation with on-the-fly fixed-rate compression, after
+ * Shen, Wu, Okita, Ino, "Accelerating GPU-Based Out-of-Core Stencil
+ * Computation with On-the-Fly Compression" (arXiv 2109.05410).
+ *
+ * Conventions for every call:
+ *  - Return value: OOCS_OK (0) or a negative OOCS_E_* code. The text of the
+ *    last error on the calling thread is returned by oocs_last_error().
+ *    No C++ exception crosses this boundary.
+ *  - Pointers named d_* are device (HIP) memory, h_* are host memory.
+ *    Host buffers handed to oocs_run and the store calls should be pinned
+ *    (hipHostMalloc, or torch pin_memory); pageable memory works but the
+ *    copies are then synchronous and do not overlap.
+ *  - The caller owns every buffer. The library never allocates device
+ *    memory: all device scratch of the out-of-core pipeline lives in the one
+ *    arena the caller passes to oocs_plan_create, so the device-memory cap is
+ *    exact by construction (the paper preallocates fixed-size buffers so that
+ *    nothing is allocated while it runs, Sec. IV).
+ *  - Streams are hipStream_t passed as void* (NULL = the default stream).
+ *    Calls that take a stream are asynchronous with respect to the host.
+ *  - Fields are FP32, x fastest: cell (x, y, z) is at x + ld_y*y + ld_z*z
+ *    (ld_y = nx, ld_z = nx*ny for dense fields).
+ *  - A plan is not thread-safe; distinct plans may be used from distinct
+ *    threads.
+ */
+#ifndef OOCS_H
+#define OOCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OOCS_OK 0
+#define OOCS_E_ARG -1    /* null pointer, unknown enum, non-positive size */
+#define OOCS_E_ALIGN -2  /* a size or chunk boundary is not a multiple of 4 where the codec needs it */
+#define OOCS_E_HALO -3   /* halo 2h = 2*r*k exceeds the slab thickness */
+#define OOCS_E_CAP -4    /* the pipeline does not fit the device arena */
+#define OOCS_E_RATE -5   /* rate outside [1, 34] (0 = uncompressed where allowed) */
+#define OOCS_E_SIZE -6   /* a caller buffer is too small */
+#define OOCS_E_HIP -7    /* a HIP runtime call failed (message has the HIP error) */
+#define OOCS_E_STATE -8  /* the object cannot do this (e.g. a planning-only plan asked to run) */
+
+#define OOCS_HEAT7 1  /* 7-point Jacobi heat stencil, radius 1 */
+#define OOCS_WAVE25 2 /* 25-point 8th-order acoustic wave, radius 4, two time levels */
+
+#define OOCS_MAX_RATE 34 /* rate at which no block is ever truncated */
+
+/* Library version (integer, increases with every ABI change). */
+int oocs_version(void);
+
+/* Message of the last error on this thread ("" if none). Valid until the
+ * next call on this thread. */
+const char* oocs_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Fixed-rate codec (Sec. IV: the user fixes the number of bits kept per
+ * value, so the compressed size is known in advance and buffers can be
+ * preallocated). Format: 4x4x4 blocks, 64*rate bits each; block b of a
+ * field (x fastest, then y, then z over blocks) occupies 64-bit words
+ * [b*rate, (b+1)*rate). Inside a block: 1-bit nonzero flag, 8-bit biased
+ * common exponent, block-floating-point integers with 30 fraction bits,
+ * the separable 4-point decorrelating transform of Lindstrom (IEEE TVCG
+ * 20(12), 2014), total-sequency ordering, negabinary, and embedded
+ * bit-plane coding with group tests, truncated at the bit budget.
+ * Because blocks are independent, any run of whole 4-plane layers of a
+ * field is a contiguous byte range of the field's stream; the pipeline
+ * relies on this to code the remainder and common region of a slab as
+ * separate chunks (Sec. V-A).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of a compressed field: (nx/4)*(ny/4)*(nz/4)*rate*8. Returns 0 if a
+ * dimension is not a positive multiple of 4 or rate is outside [1, 34]. */
+size_t oocs_codec_bytes(int64_t nx, int64_t ny, int64_t nz, int rate);
+
+/* Encode the FP32 field d_in (nx, ny, nz multiples of 4; leading dimensions
+ * ld_y >= nx, ld_z >= ld_y*ny, in elements) into d_out, which must hold
+ * oocs_codec_bytes(nx, ny, nz, rate) bytes (out_bytes). Stream-ordered; no
+ * allocation, no synchronisation. NaN and infinity are not supported.
+ * Errors: OOCS_E_ARG, OOCS_E_ALIGN, OOCS_E_RATE, OOCS_E_SIZE, OOCS_E_HIP. */
+int oocs_codec_encode(const float* d_in, int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t ld_z, int rate,
+                      uint64_t* d_out, size_t out_bytes, void* stream);
+
+/* Decode a stream made by oocs_codec_encode with the same dimensions and
+ * rate into d_out. A corrupted stream decodes to some values without any
+ * out-of-bounds access (every block has a fixed position and budget).
+ * Errors as for encode. */
+int oocs_codec_decode(const uint64_t* d_in, size_t in_bytes, int64_t nx, int64_t ny, int64_t nz, int rate, float* d_out,
+                      int64_t ld_y, int64_t ld_z, void* stream);
+
+/* Diagnostic: encode nblocks independent blocks (64 floats each, natural
+ * in-block order i + 4j + 16l, block after block in d_blocks) and write every
+ * intermediate stage. Any output pointer may be NULL. Per block:
+ *   d_emax[b]          common exponent (INT32_MIN for an all-zero block)
+ *   d_q[64b + i]       block-floating-point integers, natural order
+ *   d_t[64b + i]       after the forward transform, natural order
+ *   d_u[64b + k]       negabinary coefficients in sequency order
+ *   d_planes[32b + p]  bit plane p as a 64-bit word (bit k = bit p of u[k])
+ *   d_words[rate*b+w]  the coded block
+ *   d_bits[b]          bits written before padding (header included)
+ * Uses the same device code as oocs_codec_encode. */
+int oocs_codec_encode_stages(const float* d_blocks, int64_t nblocks, int rate, int32_t* d_emax, int32_t* d_q,
+                             int32_t* d_t, uint32_t* d_u, uint64_t* d_planes, uint64_t* d_words, int32_t* d_bits,
+                             void* stream);
+
+/* Diagnostic: decode nblocks blocks (rate words each) and write the stages:
+ * d_emax[b], d_planes[32b + p], d_u[64b + k] (sequency order), d_q[64b + i]
+ * (integers after the inverse transform, natural order) and the values
+ * d_out[64b + i]. Any output pointer may be NULL. */
+int oocs_codec_decode_stages(const uint64_t* d_words, int64_t nblocks, int rate, int32_t* d_emax, uint64_t* d_planes,
+                             uint32_t* d_u, int32_t* d_q, float* d_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Stencil steps on device-resident fields (Sec. III: every cell is updated
+ * from its neighbours each time step; cells outside the grid are zero).
+ * ------------------------------------------------------------------------ */
+
+/* k Jacobi steps of u' = u + alpha*((xm+xp)+(ym+yp)+(zm+zp) - 6u) on the
+ * dense nx*ny*nz field d_u. d_tmp is caller scratch of the same size. The
+ * result is left in d_u. FP32, fixed operation order, no fused multiply-add.
+ * Errors: OOCS_E_ARG, OOCS_E_HIP. */
+int oocs_heat7_step_k(float* d_u, float* d_tmp, int64_t nx, int64_t ny, int64_t nz, float alpha, int64_t k,
+                      void* stream);
+
+/* k leapfrog steps of the 25-point acoustic wave (Sec. VI: two read-write
+ * fields, one read-only field, radius HALO = 4):
+ *   p(n+1) = 2 p(n) - p(n-1) + w * L p(n) + s(n) at the source cell,
+ *   L p = 3 c0 p + sum_{m=1..4} c_m * sum_axes (p[+m] + p[-m]),
+ *   c = (-205/72, 8/5, -1/5, 8/315, -1/560), w = (v dt / dx)^2.
+ * On entry (d_pm, d_p) = (p(n-1), p(n)); on exit (p(n+k-1), p(n+k)).
+ * h_src holds k host amplitudes (s(n) .. s(n+k-1)) or is NULL; the source
+ * cell is (src_x, src_y, src_z) or any coordinate < 0 for none.
+ * Errors: OOCS_E_ARG, OOCS_E_HIP. */
+int oocs_wave25_step_k(float* d_p, float* d_pm, const float* d_w, int64_t nx, int64_t ny, int64_t nz, int64_t k,
+                       const float* h_src, int64_t src_x, int64_t src_y, int64_t src_z, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Out-of-core plan (Sec. III and V). The grid is split along z into
+ * nslabs blocks [a_i, a_{i+1}), a_i = i*nz/nslabs. One residency advances a
+ * block k steps, which needs a halo of h = r*k planes on each side
+ * (r = stencil radius). The 2h planes straddling each boundary a_{i+1} form
+ * the common region C_i = [a_{i+1}-h, a_{i+1}+h); the rest of the block is
+ * its remainder R_i. Region sharing: block i reads R_i and C_i from the host
+ * and reuses C_{i-1}, still on the device from block i-1. Separate
+ * compression: R_i and C_i are independent chunks of the host store, so
+ * after block i the library writes back R_i and C_{i-1} (Fig. 3).
+ * ------------------------------------------------------------------------ */
+
+typedef struct oocs_plan oocs_plan;
+
+/* Field slots: heat uses slot 0 (u). The wave uses 0 = p(n), 1 = p(n-1)
+ * (both read-write) and 2 = w (read-only, compressed once, never
+ * rewritten). */
+#define OOCS_MAX_FIELDS 3
+
+typedef struct {
+    int64_t nx, ny, nz;             /* grid; nx, ny multiples of 4 */
+    int32_t stencil;                /* OOCS_HEAT7 or OOCS_WAVE25 */
+    int32_t nslabs;                 /* blocks along z; nz % nslabs == 0 */
+    int32_t k;                      /* steps per residency (temporal blocking), >= 1 */
+    int32_t group;                  /* planes per pipeline group (multiple of 4); 0 = largest that fits */
+    int32_t rate[OOCS_MAX_FIELDS];  /* bits per value of each field's host store; 0 = uncompressed */
+    int32_t nstage;                 /* staging slots per direction (>= 2); 0 = default (3) */
+    float alpha;                    /* heat diffusion number (u += alpha * Laplacian) */
+    int32_t pad0;
+    int64_t src_x, src_y, src_z;    /* wave source cell; any < 0 = no source */
+} oocs_config;
+
+/* Create a plan. d_arena (arena_bytes long) is the only device memory the
+ * pipeline will use; pass NULL to make a planning-only plan that can be
+ * queried but not run (no HIP call is made for it). Chooses the group size
+ * (when cfg->group == 0) as the largest multiple of 4 whose rings and
+ * staging fit arena_bytes. The plan keeps d_arena; the caller keeps it
+ * alive until oocs_plan_destroy.
+ * Errors: OOCS_E_ARG, OOCS_E_ALIGN (a compressed field with nz/nslabs or h
+ * not a multiple of 4), OOCS_E_HALO (2h > nz/nslabs), OOCS_E_RATE, OOCS_E_CAP
+ * (nothing fits arena_bytes), OOCS_E_HIP (stream or event creation). */
+int oocs_plan_create(const oocs_config* cfg, void* d_arena, size_t arena_bytes, oocs_plan** out);
+
+/* Release the plan's streams and events (not the arena). NULL is allowed. */
+int oocs_plan_destroy(oocs_plan* plan);
+
+typedef struct {
+    int64_t group;              /* planes per pipeline group */
+    int64_t halo;               /* h = r * k */
+    int64_t radius;             /* r */
+    int64_t nlevels;            /* time levels held on the device (inputs + k computed) */
+    int64_t nrings;             /* device plane rings (levels + the read-only field) */
+    int64_t ring_planes[16];    /* planes per ring; index = level, then the read-only ring */
+    int64_t plane_bytes;        /* nx * ny * 4 */
+    int64_t arena_needed;       /* device bytes the plan uses (<= arena size) */
+    int64_t nstage;             /* staging slots per direction */
+    int64_t store_bytes[OOCS_MAX_FIELDS]; /* host store bytes per field (0 for an unused slot) */
+} oocs_plan_info;
+
+int oocs_plan_get_info(const oocs_plan* plan, oocs_plan_info* out);
+
+typedef struct {
+    int64_t z0, z1;         /* the block [a_i, a_{i+1}) */
+    int64_t r0, r1;         /* remainder R_i */
+    int64_t c0, c1;         /* common region C_i (empty for the last block) */
+    int64_t r_off[OOCS_MAX_FIELDS], r_bytes[OOCS_MAX_FIELDS]; /* R_i in each field's host store */
+    int64_t c_off[OOCS_MAX_FIELDS], c_bytes[OOCS_MAX_FIELDS]; /* C_i in each field's host store */
+} oocs_slab_info;
+
+int oocs_plan_slab(const oocs_plan* plan, int i, oocs_slab_info* out);
+
+/* The per-residency schedule as a list of operations on three streams
+ * (0 = host-to-device copies, 1 = compute, 2 = device-to-host copies),
+ * exposed so that its ordering can be checked without a GPU. kr is the
+ * number of steps of the residency (k, or the remainder of the last one). */
+#define OOCS_OP_H2D 1     /* copy a group of host-store planes into an input staging slot */
+#define OOCS_OP_DECODE 2  /* decode (or copy, if uncompressed) a staging slot into a level ring */
+#define OOCS_OP_LEVEL 3   /* compute planes [z0, z1) of one time level */
+#define OOCS_OP_ENCODE 4  /* encode (or copy) planes of an output level into an output staging slot */
+#define OOCS_OP_D2H 5     /* copy an output staging slot to the host store */
+#define OOCS_OP_LAUNCH 6  /* issue the jobs accumulated on the compute stream as one kernel launch */
+#define OOCS_OP_RECORD 7  /* record event `event` on `stream` */
+#define OOCS_OP_WAIT 8    /* make `stream` wait for the last record of `event` */
+
+typedef struct {
+    int32_t kind;    /* OOCS_OP_* */
+    int32_t stream;  /* 0, 1, 2 */
+    int32_t field;   /* field slot (H2D/DECODE/ENCODE/D2H) */
+    int32_t level;   /* ring index: DECODE/ENCODE source or target level; LEVEL: computed level */
+    int32_t slot;    /* staging slot (H2D/DECODE/ENCODE/D2H) */
+    int32_t block;   /* slab index */
+    int32_t tick;    /* compute tick the op belongs to */
+    int32_t event;   /* RECORD/WAIT */
+    int64_t z0, z1;  /* planes */
+} oocs_op;
+
+/* Number of operations of the residency schedule for kr steps (1 <= kr <= k),
+ * building and caching it on first use. Returns < 0 on error. */
+int64_t oocs_plan_schedule_len(oocs_plan* plan, int kr);
+int oocs_plan_schedule_op(oocs_plan* plan, int kr, int64_t index, oocs_op* out);
+
+/* Host store size for a field slot: the field's compressed stream, or
+ * nx*ny*nz*4 bytes if uncompressed; 0 for an unused slot. */
+size_t oocs_store_bytes(const oocs_plan* plan, int field);
+
+/* Build a field's host store from the FP32 host field h_field (initial
+ * compression, done once; for the read-only field the only time it is ever
+ * compressed). Streams through the plan's arena on the GPU. Blocking. */
+int oocs_store_put(oocs_plan* plan, int field, const float* h_field, void* h_store);
+
+/* Decode a field's host store into the FP32 host field h_field. Blocking. */
+int oocs_store_get(oocs_plan* plan, int field, const void* h_store, float* h_field);
+
+typedef struct {
+    double wall_ms;          /* host wall time of the call */
+    int64_t rounds;          /* residencies executed */
+    int64_t launches;        /* fused kernel launches issued */
+    int64_t h2d_bytes;       /* bytes copied host -> device */
+    int64_t d2h_bytes;       /* bytes copied device -> host */
+    int64_t cell_updates;    /* nx*ny*nz*steps */
+    int64_t kernel_bytes;    /* algorithmic device-memory bytes of all launches: every
+                                input plane read once and every output plane written
+                                once per job (heat 8 B per cell update, wave 16 B,
+                                decode/encode 4 + rate/8 B per value, raw copy 8 B) */
+    double kernel_ms;        /* summed GPU time of the launches, measured with
+                                timing events around each launch on the compute
+                                stream when profiling is on; 0 otherwise */
+} oocs_stats;
+
+/* Turn per-launch kernel timing on (1) or off (0) for later oocs_run calls
+ * on this plan. Timing events are recorded on the plan's compute stream
+ * around every fused launch; the sum of their elapsed times is returned in
+ * oocs_stats.kernel_ms. */
+int oocs_plan_set_profiling(oocs_plan* plan, int on);
+
+/* Advance the out-of-core state held in the host stores h_store[field]
+ * (one pointer per used field slot) by `steps` time steps, k per residency
+ * (the last residency does steps mod k). The wave source adds h_src[s] at
+ * the source cell when the field after the s-th step of this call is
+ * formed (s = 0 .. steps-1); h_src holds `steps` values or is NULL. Host
+ * stores are updated in place. Blocks until done; st may be NULL.
+ * Errors: OOCS_E_ARG, OOCS_E_STATE (planning-only plan), OOCS_E_HIP. */
+int oocs_run(oocs_plan* plan, void* const* h_store, int64_t steps, const float* h_src, oocs_stats* st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OOCS_H */

@@ -1,0 +1,128 @@
+"""ctypes binding of liboocs (include/oocs.h): same names, argument
+marshalling only. Every computation happens in the HIP library; if the
+library is missing this module raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liboocs.so")
+
+OOCS_OK = 0
+OOCS_E_ARG = -1
+OOCS_E_ALIGN = -2
+OOCS_E_HALO = -3
+OOCS_E_CAP = -4
+OOCS_E_RATE = -5
+OOCS_E_SIZE = -6
+OOCS_E_HIP = -7
+OOCS_E_STATE = -8
+
+OOCS_HEAT7 = 1
+OOCS_WAVE25 = 2
+OOCS_MAX_FIELDS = 3
+OOCS_MAX_RATE = 34
+
+OP_H2D, OP_DECODE, OP_LEVEL, OP_ENCODE, OP_D2H, OP_LAUNCH, OP_RECORD, OP_WAIT = range(1, 9)
+
+
+class OocsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"liboocs error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+        ("stencil", C.c_int32), ("nslabs", C.c_int32), ("k", C.c_int32), ("group", C.c_int32),
+        ("rate", C.c_int32 * OOCS_MAX_FIELDS), ("nstage", C.c_int32),
+        ("alpha", C.c_float), ("pad0", C.c_int32),
+        ("src_x", C.c_int64), ("src_y", C.c_int64), ("src_z", C.c_int64),
+    ]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [
+        ("group", C.c_int64), ("halo", C.c_int64), ("radius", C.c_int64), ("nlevels", C.c_int64),
+        ("nrings", C.c_int64), ("ring_planes", C.c_int64 * 16), ("plane_bytes", C.c_int64),
+        ("arena_needed", C.c_int64), ("nstage", C.c_int64), ("store_bytes", C.c_int64 * OOCS_MAX_FIELDS),
+    ]
+
+
+class SlabInfo(C.Structure):
+    _fields_ = [
+        ("z0", C.c_int64), ("z1", C.c_int64), ("r0", C.c_int64), ("r1", C.c_int64),
+        ("c0", C.c_int64), ("c1", C.c_int64),
+        ("r_off", C.c_int64 * OOCS_MAX_FIELDS), ("r_bytes", C.c_int64 * OOCS_MAX_FIELDS),
+        ("c_off", C.c_int64 * OOCS_MAX_FIELDS), ("c_bytes", C.c_int64 * OOCS_MAX_FIELDS),
+    ]
+
+
+class Op(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("stream", C.c_int32), ("field", C.c_int32), ("level", C.c_int32),
+        ("slot", C.c_int32), ("block", C.c_int32), ("tick", C.c_int32), ("event", C.c_int32),
+        ("z0", C.c_int64), ("z1", C.c_int64),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("wall_ms", C.c_double), ("rounds", C.c_int64), ("launches", C.c_int64),
+        ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("cell_updates", C.c_int64),
+        ("kernel_bytes", C.c_int64), ("kernel_ms", C.c_double),
+    ]
+
+
+# name -> (restype, argtypes); this list is the binding of every symbol in include/oocs.h
+_P = C.c_void_p
+_I64 = C.c_int64
+_SIGS = {
+    "oocs_version": (C.c_int, []),
+    "oocs_last_error": (C.c_char_p, []),
+    "oocs_codec_bytes": (C.c_size_t, [_I64, _I64, _I64, C.c_int]),
+    "oocs_codec_encode": (C.c_int, [_P, _I64, _I64, _I64, _I64, _I64, C.c_int, _P, C.c_size_t, _P]),
+    "oocs_codec_decode": (C.c_int, [_P, C.c_size_t, _I64, _I64, _I64, C.c_int, _P, _I64, _I64, _P]),
+    "oocs_codec_encode_stages": (C.c_int, [_P, _I64, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "oocs_codec_decode_stages": (C.c_int, [_P, _I64, C.c_int, _P, _P, _P, _P, _P, _P]),
+    "oocs_heat7_step_k": (C.c_int, [_P, _P, _I64, _I64, _I64, C.c_float, _I64, _P]),
+    "oocs_wave25_step_k": (C.c_int, [_P, _P, _P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P]),
+    "oocs_plan_create": (C.c_int, [C.POINTER(Config), _P, C.c_size_t, C.POINTER(_P)]),
+    "oocs_plan_destroy": (C.c_int, [_P]),
+    "oocs_plan_get_info": (C.c_int, [_P, C.POINTER(PlanInfo)]),
+    "oocs_plan_slab": (C.c_int, [_P, C.c_int, C.POINTER(SlabInfo)]),
+    "oocs_plan_schedule_len": (C.c_int64, [_P, C.c_int]),
+    "oocs_plan_schedule_op": (C.c_int, [_P, C.c_int, _I64, C.POINTER(Op)]),
+    "oocs_store_bytes": (C.c_size_t, [_P, C.c_int]),
+    "oocs_store_put": (C.c_int, [_P, C.c_int, _P, _P]),
+    "oocs_store_get": (C.c_int, [_P, C.c_int, _P, _P]),
+    "oocs_run": (C.c_int, [_P, C.POINTER(_P), _I64, _P, C.POINTER(Stats)]),
+    "oocs_plan_set_profiling": (C.c_int, [_P, C.c_int]),
+}
+SYMBOLS = tuple(_SIGS)
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise OocsError(OOCS_E_STATE, f"{LIB_PATH} is not built; run paper_2109_05410_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        msg = lib().oocs_last_error()
+        raise OocsError(rc, msg.decode() if msg else "")
+    return rc

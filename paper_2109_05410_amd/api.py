@@ -1,0 +1,266 @@
+"""Python API over liboocs. PyTorch supplies device memory, pinned host
+memory and streams; every step of the computation runs in the HIP library.
+
+Fields are torch tensors shaped (nz, ny, nx), float32, C-contiguous
+(x fastest), on the current CUDA (HIP) device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _field(t: torch.Tensor, name: str):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 3:
+        raise ValueError(f"{name} must be a contiguous float32 (nz, ny, nx) device tensor")
+    nz, ny, nx = t.shape
+    return nx, ny, nz
+
+
+# ---------------------------------------------------------------------------
+# Codec
+# ---------------------------------------------------------------------------
+
+def codec_bytes(nx: int, ny: int, nz: int, rate: int) -> int:
+    return int(L.lib().oocs_codec_bytes(nx, ny, nz, rate))
+
+
+def codec_encode(field: torch.Tensor, rate: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Encode a (nz, ny, nx) float32 field; returns the words as an int64
+    tensor (bit pattern of the uint64 words)."""
+    nx, ny, nz = _field(field, "field")
+    nb = codec_bytes(nx, ny, nz, rate)
+    if nb == 0:
+        L.check(L.OOCS_E_ALIGN if rate > 0 else L.OOCS_E_RATE)
+    if out is None:
+        out = torch.empty(nb // 8, dtype=torch.int64, device=field.device)
+    L.check(L.lib().oocs_codec_encode(_dptr(field), nx, ny, nz, nx, nx * ny, rate, _dptr(out),
+                                      out.numel() * 8, _stream_ptr(stream)))
+    return out
+
+
+def codec_decode(words: torch.Tensor, shape, rate: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    nz, ny, nx = shape
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=words.device)
+    _field(out, "out")
+    L.check(L.lib().oocs_codec_decode(_dptr(words), words.numel() * words.element_size(), nx, ny, nz, rate,
+                                      _dptr(out), nx, nx * ny, _stream_ptr(stream)))
+    return out
+
+
+def codec_encode_stages(blocks: torch.Tensor, rate: int) -> dict:
+    """blocks: (N, 64) float32 device tensor, natural in-block order."""
+    n = blocks.shape[0]
+    dev = blocks.device
+    o = {
+        "emax": torch.empty(n, dtype=torch.int32, device=dev),
+        "q": torch.empty((n, 64), dtype=torch.int32, device=dev),
+        "t": torch.empty((n, 64), dtype=torch.int32, device=dev),
+        "u": torch.empty((n, 64), dtype=torch.int32, device=dev),
+        "plane": torch.empty((n, 32), dtype=torch.int64, device=dev),
+        "words": torch.empty((n, rate), dtype=torch.int64, device=dev),
+        "bits_used": torch.empty(n, dtype=torch.int32, device=dev),
+    }
+    L.check(L.lib().oocs_codec_encode_stages(_dptr(blocks.contiguous()), n, rate, _dptr(o["emax"]), _dptr(o["q"]),
+                                             _dptr(o["t"]), _dptr(o["u"]), _dptr(o["plane"]), _dptr(o["words"]),
+                                             _dptr(o["bits_used"]), _stream_ptr()))
+    return o
+
+
+def codec_decode_stages(words: torch.Tensor, rate: int) -> dict:
+    """words: (N, rate) int64 device tensor."""
+    n = words.shape[0]
+    dev = words.device
+    o = {
+        "emax": torch.empty(n, dtype=torch.int32, device=dev),
+        "plane": torch.empty((n, 32), dtype=torch.int64, device=dev),
+        "u": torch.empty((n, 64), dtype=torch.int32, device=dev),
+        "q": torch.empty((n, 64), dtype=torch.int32, device=dev),
+        "out": torch.empty((n, 64), dtype=torch.float32, device=dev),
+    }
+    L.check(L.lib().oocs_codec_decode_stages(_dptr(words.contiguous()), n, rate, _dptr(o["emax"]), _dptr(o["plane"]),
+                                             _dptr(o["u"]), _dptr(o["q"]), _dptr(o["out"]), _stream_ptr()))
+    return o
+
+
+# ---------------------------------------------------------------------------
+# In-core steps
+# ---------------------------------------------------------------------------
+
+def heat7_step_k(u: torch.Tensor, alpha: float, k: int, tmp: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    nx, ny, nz = _field(u, "u")
+    if tmp is None:
+        tmp = torch.empty_like(u)
+    L.check(L.lib().oocs_heat7_step_k(_dptr(u), _dptr(tmp), nx, ny, nz, C.c_float(alpha), k, _stream_ptr(stream)))
+    return u
+
+
+def wave25_step_k(p: torch.Tensor, pm: torch.Tensor, w: torch.Tensor, k: int, src=None, stream=None):
+    """k leapfrog steps in place on (pm, p) = (p(n-1), p(n)).
+    src = (amplitudes (k,) float32 array, (x, y, z)) or None."""
+    nx, ny, nz = _field(p, "p")
+    _field(pm, "pm")
+    _field(w, "w")
+    amps = None
+    sx = sy = sz = -1
+    if src is not None:
+        a, (sx, sy, sz) = src
+        amps = np.ascontiguousarray(a, dtype=np.float32)
+        if amps.size < k:
+            raise ValueError("need one source amplitude per step")
+    ap = amps.ctypes.data_as(C.c_void_p) if amps is not None else None
+    L.check(L.lib().oocs_wave25_step_k(_dptr(p), _dptr(pm), _dptr(w), nx, ny, nz, k, ap, sx, sy, sz,
+                                       _stream_ptr(stream)))
+    return p, pm
+
+
+# ---------------------------------------------------------------------------
+# Out-of-core plan
+# ---------------------------------------------------------------------------
+
+HEAT7 = L.OOCS_HEAT7
+WAVE25 = L.OOCS_WAVE25
+
+
+@dataclass
+class RunStats:
+    wall_ms: float
+    rounds: int
+    launches: int
+    h2d_bytes: int
+    d2h_bytes: int
+    cell_updates: int
+    kernel_bytes: int
+    kernel_ms: float
+
+    @property
+    def gcells_per_s(self) -> float:
+        return self.cell_updates / (self.wall_ms * 1e-3) / 1e9 if self.wall_ms > 0 else 0.0
+
+
+class OutOfCorePlan:
+    """An out-of-core pipeline over a host store, using at most `arena_bytes`
+    of device memory (one torch allocation made here, handed to the library).
+
+    Field slots: heat uses 0 (u); the wave uses 0 = p(n), 1 = p(n-1),
+    2 = w (read-only)."""
+
+    def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
+                 alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
+                 planning_only: bool = False, device=None):
+        nz, ny, nx = shape
+        cfg = L.Config()
+        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+        cfg.stencil = stencil
+        cfg.nslabs = nslabs
+        cfg.k = k
+        cfg.group = group
+        for i in range(L.OOCS_MAX_FIELDS):
+            cfg.rate[i] = rates[i] if i < len(rates) else 0
+        cfg.nstage = nstage
+        cfg.alpha = alpha
+        sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
+        cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
+        self.cfg = cfg
+        self.shape = (nz, ny, nx)
+        self.stencil = stencil
+        self.arena = None
+        ptr = None
+        if not planning_only:
+            self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device or "cuda")
+            ptr = C.c_void_p(self.arena.data_ptr())
+        h = C.c_void_p()
+        L.check(L.lib().oocs_plan_create(C.byref(cfg), ptr, arena_bytes, C.byref(h)))
+        self._h = h
+        self.nfields = 1 if stencil == HEAT7 else 3
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().oocs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self) -> dict:
+        i = L.PlanInfo()
+        L.check(L.lib().oocs_plan_get_info(self._h, C.byref(i)))
+        return {
+            "group": i.group, "halo": i.halo, "radius": i.radius, "nlevels": i.nlevels, "nrings": i.nrings,
+            "ring_planes": list(i.ring_planes[: i.nrings]), "plane_bytes": i.plane_bytes,
+            "arena_needed": i.arena_needed, "nstage": i.nstage, "store_bytes": list(i.store_bytes),
+        }
+
+    def slab(self, i: int) -> dict:
+        s = L.SlabInfo()
+        L.check(L.lib().oocs_plan_slab(self._h, i, C.byref(s)))
+        return {k: (list(getattr(s, k)) if k.endswith(("_off", "_bytes")) else getattr(s, k)) for k, _ in s._fields_}
+
+    def schedule(self, kr: int) -> list[dict]:
+        n = L.check(L.lib().oocs_plan_schedule_len(self._h, kr))
+        ops = []
+        o = L.Op()
+        for i in range(n):
+            L.check(L.lib().oocs_plan_schedule_op(self._h, kr, i, C.byref(o)))
+            ops.append({k: getattr(o, k) for k, _ in o._fields_})
+        return ops
+
+    def store_bytes(self, f: int) -> int:
+        return int(L.lib().oocs_store_bytes(self._h, f))
+
+    def new_store(self, f: int) -> torch.Tensor:
+        """A pinned host buffer for field slot f's store."""
+        return torch.empty(self.store_bytes(f), dtype=torch.uint8, pin_memory=True)
+
+    def put(self, f: int, field, store: torch.Tensor):
+        """Build store f from a host FP32 field (numpy or CPU tensor)."""
+        a = np.ascontiguousarray(field.numpy() if isinstance(field, torch.Tensor) else field, dtype=np.float32)
+        if a.shape != self.shape:
+            raise ValueError("field shape mismatch")
+        L.check(L.lib().oocs_store_put(self._h, f, a.ctypes.data_as(C.c_void_p), C.c_void_p(store.data_ptr())))
+
+    def get(self, f: int, store: torch.Tensor) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float32)
+        L.check(L.lib().oocs_store_get(self._h, f, C.c_void_p(store.data_ptr()), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def run(self, stores, steps: int, src_amps=None) -> RunStats:
+        ptrs = (C.c_void_p * L.OOCS_MAX_FIELDS)()
+        for i, s in enumerate(stores):
+            ptrs[i] = s.data_ptr() if s is not None else None
+        amps = None
+        if src_amps is not None:
+            amps = np.ascontiguousarray(src_amps, dtype=np.float32)
+            if amps.size < steps:
+                raise ValueError("need one source amplitude per step")
+        st = L.Stats()
+        L.check(L.lib().oocs_run(self._h, ptrs, steps, amps.ctypes.data_as(C.c_void_p) if amps is not None else None,
+                                 C.byref(st)))
+        return RunStats(st.wall_ms, st.rounds, st.launches, st.h2d_bytes, st.d2h_bytes, st.cell_updates,
+                        st.kernel_bytes, st.kernel_ms)
+
+    def set_profiling(self, on: bool):
+        L.check(L.lib().oocs_plan_set_profiling(self._h, 1 if on else 0))

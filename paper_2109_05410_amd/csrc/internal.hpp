@@ -1,0 +1,83 @@
+// internal.hpp -- structures shared by the host planner/executor and the
+// gfx950 kernels of liboocs. Not part of the public ABI (include/oocs.h).
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+
+#include <hip/hip_runtime.h>
+
+namespace oocs {
+
+// A ring of FP32 planes in device memory. Plane z lives in slot z mod W.
+// A dense field is the special case W >= nz (no wrap-around).
+struct Ring {
+    float* base;
+    int64_t W;     // planes in the ring
+    int64_t ld_z;  // elements from one plane to the next
+};
+
+__host__ __device__ inline float* ring_plane(const Ring& r, int64_t z) { return r.base + (z % r.W) * r.ld_z; }
+
+enum JobKind : int32_t {
+    JOB_HEAT = 1,    // one heat time level over planes [z0, z1)
+    JOB_WAVE = 2,    // one wave time level over planes [z0, z1)
+    JOB_DECODE = 3,  // staging (compressed words) -> ring planes
+    JOB_ENCODE = 4,  // ring planes -> staging (compressed words)
+    JOB_COPY_IN = 5, // staging (raw planes) -> ring planes
+    JOB_COPY_OUT = 6 // ring planes -> staging (raw planes)
+};
+
+// One job of a fused launch. For stencil jobs src = level l-1, src2 = level
+// l-2 (wave), ro = read-only field ring (wave), dst = level l. For codec
+// and copy jobs `ring` is the level ring and `stage` the staging slot.
+struct Job {
+    int32_t kind;
+    int32_t z0, z1;
+    int32_t rate;      // codec jobs
+    int32_t has_src;   // wave: add `amp` at the source cell
+    float amp;
+    int32_t wg_count;  // workgroups of this job
+    int32_t pad;
+    Ring src, src2, ro, dst;  // stencil jobs (dst doubles as `ring` for codec/copy jobs)
+    void* stage;              // codec/copy jobs
+};
+
+constexpr int kMaxJobs = 24;
+constexpr int kBlockThreads = 256;  // every job runs 256-thread workgroups (4 waves)
+constexpr int kTileX = 64;          // stencil xy tile: 64 x 4 threads
+constexpr int kTileY = 4;
+constexpr int kZChunk = 16;         // planes one stencil thread marches
+
+struct LaunchParams {
+    int32_t nx, ny, nz;
+    float alpha;
+    int32_t src_x, src_y, src_z;
+    int32_t njobs;
+    int32_t wg_begin[kMaxJobs + 1];  // prefix sums of wg_count
+    Job jobs[kMaxJobs];
+};
+
+// Workgroups a job needs (host side).
+int32_t job_workgroups(const Job& j, int nx, int ny);
+
+// Launch the fused kernel for the jobs in p (p.wg_begin is filled here).
+hipError_t launch_jobs(LaunchParams& p, hipStream_t stream);
+
+// Standalone codec launches on dense (non-ring) fields.
+hipError_t launch_codec_field(bool encode, const float* in_f, float* out_f, const uint64_t* in_w, uint64_t* out_w,
+                              int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t ld_z, int rate,
+                              hipStream_t stream);
+
+// Exchange the contents of two device arrays of n floats.
+hipError_t launch_swap(float* a, float* b, int64_t n, hipStream_t stream);
+
+struct EncStages {
+    int32_t* emax; int32_t* q; int32_t* t; uint32_t* u; uint64_t* planes; uint64_t* words; int32_t* bits;
+};
+struct DecStages {
+    int32_t* emax; uint64_t* planes; uint32_t* u; int32_t* q; float* out;
+};
+hipError_t launch_encode_stages(const float* blocks, int64_t nblocks, int rate, EncStages s, hipStream_t stream);
+hipError_t launch_decode_stages(const uint64_t* words, int64_t nblocks, int rate, DecStages s, hipStream_t stream);
+
+}  // namespace oocs

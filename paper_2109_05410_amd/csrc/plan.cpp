@@ -1,0 +1,354 @@
+// plan.cpp -- out-of-core planner of liboocs (host only, no HIP calls).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <array>
+#include <climits>
+#include <cstdio>
+
+namespace oocs {
+
+namespace {
+std::string fmt(const char* f, long long a = 0, long long b = 0, long long c = 0)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, f, a, b, c);
+    return buf;
+}
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+}  // namespace
+
+int Planner::init(const oocs_config& c, std::string& err)
+{
+    cfg = c;
+    nx = c.nx; ny = c.ny; nz = c.nz;
+    if (nx <= 0 || ny <= 0 || nz <= 0) { err = "grid dimensions must be positive"; return OOCS_E_ARG; }
+    if (nx % 4 || ny % 4) { err = "nx and ny must be multiples of 4"; return OOCS_E_ALIGN; }
+    if (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20)) { err = "grid dimension too large"; return OOCS_E_ARG; }
+    if (c.stencil == OOCS_HEAT7) {
+        r = 1; nin = 1; has_ro = false; nfields = 1;
+        in_fields = {0}; out_fields = {0};
+    } else if (c.stencil == OOCS_WAVE25) {
+        r = 4; nin = 2; has_ro = true; nfields = 3;
+        in_fields = {0, 1, 2}; out_fields = {0, 1};
+    } else {
+        err = "unknown stencil"; return OOCS_E_ARG;
+    }
+    n = c.nslabs; k = c.k;
+    if (n < 1 || nz % n) { err = fmt("nslabs (%lld) must be >= 1 and divide nz (%lld)", n, nz); return OOCS_E_ARG; }
+    if (k < 1 || k > 16) { err = fmt("k (%lld) must be in [1, 16]", k); return OOCS_E_ARG; }
+    slab = nz / n;
+    h = (int64_t)r * k;
+    if (2 * h > slab && n > 1) { err = fmt("halo 2h = %lld exceeds the slab thickness %lld", 2 * h, slab); return OOCS_E_HALO; }
+    bool any_rate = false;
+    for (int f = 0; f < nfields; ++f) {
+        if (c.rate[f] < 0 || c.rate[f] > OOCS_MAX_RATE) { err = fmt("rate[%lld] = %lld outside [0, 34]", f, c.rate[f]); return OOCS_E_RATE; }
+        any_rate |= c.rate[f] > 0;
+    }
+    for (int f = nfields; f < OOCS_MAX_FIELDS; ++f)
+        if (c.rate[f] != 0) { err = "rate set for a field slot the stencil does not use"; return OOCS_E_ARG; }
+    if (any_rate && (nz % 4 || slab % 4 || h % 4)) {
+        err = fmt("compressed chunks need nz (%lld), the slab (%lld) and h (%lld) to be multiples of 4", nz, slab, h);
+        return OOCS_E_ALIGN;
+    }
+    if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
+    if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
+    nstage = c.nstage ? c.nstage : 3;
+    a.resize(n + 1);
+    for (int i = 0; i <= n; ++i) a[i] = (int64_t)i * slab;
+    return OOCS_OK;
+}
+
+int Planner::in_ring(int f) const
+{
+    if (cfg.stencil == OOCS_HEAT7) return 0;
+    return f == 0 ? 1 : (f == 1 ? 0 : ro_ring());
+}
+
+int Planner::out_ring(int f, int kr) const
+{
+    if (cfg.stencil == OOCS_HEAT7) return kr;     // u(t+kr)
+    return f == 0 ? kr + 1 : kr;                  // p(t+kr), p(t+kr-1)
+}
+
+int64_t Planner::store_plane_bytes(int f) const
+{
+    const int rate = cfg.rate[f];
+    if (rate == 0) return plane_elems() * 4;
+    return (nx / 4) * (ny / 4) * (int64_t)rate * 8 / 4;  // one 4-plane layer / 4
+}
+
+int64_t Planner::store_bytes(int f) const
+{
+    if (f < 0 || f >= nfields) return 0;
+    return store_plane_bytes(f) * nz;
+}
+
+int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
+{
+    s.ticks.clear(); s.in_groups.clear(); s.out_groups.clear();
+    const int nl = nin + kr;  // levels in use: 0 .. nl-1
+    std::vector<int64_t> f(nl), lo(nl), hi(nl);
+    int64_t load_front = 0;
+    const int64_t align = 4;
+    for (int i = 0; i < n; ++i) {
+        const int64_t e_end = std::min(a[i + 1] + h, nz);
+        for (int lv = nin; lv < nl; ++lv) {
+            const int64_t st = lv - nin + 1;
+            lo[lv] = std::max<int64_t>(a[i] - h + st * r, 0);
+            hi[lv] = std::min<int64_t>(a[i + 1] + h - st * r, nz);
+            f[lv] = lo[lv];
+        }
+        int64_t out_front = a[i];
+        int guard = 0;
+        while (out_front < a[i + 1]) {
+            if (++guard > 1000000) { err = "schedule does not terminate"; return OOCS_E_STATE; }
+            Tick t;
+            t.block = i;
+            std::vector<int64_t> prev = f;
+            for (int lv = 0; lv < nin; ++lv) prev[lv] = load_front;
+            // decode the next input group
+            if (load_front < e_end) {
+                t.in_group = (int64_t)s.in_groups.size();
+                t.dz0 = load_front;
+                t.dz1 = std::min(load_front + G, e_end);
+                s.in_groups.push_back({t.dz0, t.dz1, (int64_t)s.ticks.size(), i, false});
+                load_front = t.dz1;
+            }
+            // advance every computed level from the previous tick's fronts
+            for (int lv = nin; lv < nl; ++lv) {
+                const int64_t below = prev[lv - 1];
+                const int64_t avail = below >= nz ? nz : below - r;
+                int64_t top = std::min(std::min(hi[lv], avail), prev[lv] + G);
+                if (lv >= 2) top = std::min(top, prev[lv - 2]);
+                if (top > prev[lv]) {
+                    t.levels.push_back({lv, prev[lv], top});
+                    f[lv] = top;
+                }
+            }
+            // encode the next finished output group
+            int64_t fo = nz;
+            for (int fld : out_fields) {
+                const int lv = out_ring(fld, kr);
+                fo = std::min(fo, lv < nin ? prev[0] : prev[lv]);
+            }
+            int64_t e = fo >= a[i + 1] ? a[i + 1] : a[i] + (fo - a[i]) / align * align;
+            e = std::min(e, out_front + G);
+            if (e > out_front) {
+                t.out_group = (int64_t)s.out_groups.size();
+                t.ez0 = out_front;
+                t.ez1 = e;
+                t.last_out_of_block = e == a[i + 1];
+                s.out_groups.push_back({out_front, e, (int64_t)s.ticks.size(), i, t.last_out_of_block});
+                out_front = e;
+            }
+            if (t.in_group < 0 && t.levels.empty() && t.out_group < 0) {
+                err = fmt("schedule stalled in block %lld", i);
+                return OOCS_E_STATE;
+            }
+            s.ticks.push_back(std::move(t));
+        }
+    }
+    return OOCS_OK;
+}
+
+int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
+{
+    G = Gc;
+    nstage = ns;
+    const int R = nrings();
+    std::vector<int64_t> W(R, 1);
+    // Size every ring by a liveness sweep over the tick lists of all
+    // residency lengths 1..k (the last residency may be shorter).
+    for (int kr = 1; kr <= k; ++kr) {
+        Schedule s;
+        if (build_ticks(kr, s, err) != OOCS_OK) return -1;
+        const int64_t T = (int64_t)s.ticks.size();
+        // per ring: current version of each plane -> (write tick, last read tick)
+        struct Live { int64_t w = -1, rd = -1; };
+        std::vector<std::vector<Live>> cur(R, std::vector<Live>(nz));
+        std::vector<std::vector<std::pair<int64_t, int64_t>>> spans_lo(R), spans_hi(R);
+        // intervals (z, tw, tr) collected per ring
+        std::vector<std::vector<std::array<int64_t, 3>>> iv(R);
+        auto close = [&](int ring, int64_t z) {
+            Live& L = cur[ring][z];
+            if (L.w >= 0) iv[ring].push_back({z, L.w, std::max(L.w, L.rd)});
+            L = Live{};
+        };
+        bool bad = false;
+        auto write = [&](int ring, int64_t z0, int64_t z1, int64_t tick) {
+            for (int64_t z = z0; z < z1; ++z) {
+                if (cur[ring][z].rd >= tick) bad = true;  // a plane may not be rewritten while still read
+                close(ring, z);
+                cur[ring][z].w = tick;
+            }
+        };
+        auto read = [&](int ring, int64_t z0, int64_t z1, int64_t tick) {
+            for (int64_t z = std::max<int64_t>(z0, 0); z < std::min(z1, nz); ++z) {
+                Live& L = cur[ring][z];
+                if (L.w < 0 || L.w >= tick) bad = true;  // must be written by an earlier tick
+                L.rd = std::max(L.rd, tick);
+            }
+        };
+        for (int64_t ti = 0; ti < T; ++ti) {
+            const Tick& t = s.ticks[ti];
+            for (const LevelRange& L : t.levels) {
+                read(L.lv - 1, L.z0 - r, L.z1 + r, ti);
+                if (nin == 2) {
+                    read(L.lv - 2, L.z0, L.z1, ti);
+                    read(ro_ring(), L.z0, L.z1, ti);
+                }
+            }
+            if (t.out_group >= 0)
+                for (int fld : out_fields) read(out_ring(fld, kr), t.ez0, t.ez1, ti);
+            if (t.in_group >= 0)
+                for (int fld : in_fields) write(in_ring(fld), t.dz0, t.dz1, ti);
+            for (const LevelRange& L : t.levels) write(L.lv, L.z0, L.z1, ti);
+        }
+        if (bad) { err = "schedule reads a plane before it is written, or rewrites it while read"; return -1; }
+        for (int ring = 0; ring < R; ++ring)
+            for (int64_t z = 0; z < nz; ++z) close(ring, z);
+        // W = max over ticks of the span of planes live at that tick
+        for (int ring = 0; ring < R; ++ring) {
+            std::vector<int64_t> mn(T, INT64_MAX), mx(T, INT64_MIN);
+            for (const auto& v : iv[ring])
+                for (int64_t ti = v[1]; ti <= v[2]; ++ti) {
+                    mn[ti] = std::min(mn[ti], v[0]);
+                    mx[ti] = std::max(mx[ti], v[0]);
+                }
+            for (int64_t ti = 0; ti < T; ++ti)
+                if (mx[ti] >= mn[ti]) W[ring] = std::max(W[ring], mx[ti] - mn[ti] + 1);
+        }
+    }
+    ringW = W;
+    ringOff.assign(R, 0);
+    const int64_t pb = plane_elems() * 4;
+    int64_t off = 0;
+    for (int ring = 0; ring < R; ++ring) {
+        ringOff[ring] = off;
+        off = align_up(off + W[ring] * pb, 256);
+    }
+    for (int f = 0; f < OOCS_MAX_FIELDS; ++f) { in_slot_bytes[f] = out_slot_bytes[f] = in_off[f] = out_off[f] = 0; }
+    for (int fld : in_fields) {
+        in_slot_bytes[fld] = align_up(G * store_plane_bytes(fld), 256);
+        in_off[fld] = off;
+        off += in_slot_bytes[fld] * nstage;
+    }
+    for (int fld : out_fields) {
+        out_slot_bytes[fld] = align_up(G * store_plane_bytes(fld), 256);
+        out_off[fld] = off;
+        off += out_slot_bytes[fld] * nstage;
+    }
+    arena_needed = off;
+    return off;
+}
+
+int Planner::choose(size_t arena_bytes, std::string& err)
+{
+    bool any_rate = false;
+    for (int f = 0; f < nfields; ++f) any_rate |= cfg.rate[f] > 0;
+    std::vector<int64_t> cands;
+    if (cfg.group > 0) {
+        cands.push_back(cfg.group);
+    } else {
+        for (int64_t g = 32; g >= 4; g -= 4) cands.push_back(g);
+        if (!any_rate) { cands.push_back(2); cands.push_back(1); }
+    }
+    int64_t best_need = -1;
+    for (int64_t g : cands) {
+        const int64_t need = layout(g, nstage, err);
+        if (need < 0) return OOCS_E_STATE;
+        if (best_need < 0 || need < best_need) best_need = need;
+        if ((size_t)need <= arena_bytes) { cache_.clear(); return OOCS_OK; }
+    }
+    err = fmt("the pipeline needs at least %lld bytes of device arena, %lld given", best_need, (long long)arena_bytes);
+    return OOCS_E_CAP;
+}
+
+int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
+{
+    s.ops.clear();
+    auto op = [&](int kind, int stream) {
+        oocs_op o{};
+        o.kind = kind; o.stream = stream; o.event = -1; o.slot = -1; o.field = -1; o.level = -1; o.block = -1; o.tick = -1;
+        return o;
+    };
+    auto block_of = [&](int64_t z) { return (int)std::min<int64_t>(z / slab, n - 1); };
+    auto emit_h2d = [&](int64_t j, int64_t tick) {
+        const GroupRec& g = s.in_groups[j];
+        const int sl = (int)(j % nstage);
+        oocs_op w = op(OOCS_OP_WAIT, 0); w.event = ev_decoded(sl); w.tick = (int)tick; s.ops.push_back(w);
+        // host planes were last written by the previous residency's write-back
+        oocs_op w2 = op(OOCS_OP_WAIT, 0); w2.event = ev_blk_prev(block_of(g.z1 - 1)); w2.tick = (int)tick; s.ops.push_back(w2);
+        for (int fld : in_fields) {
+            oocs_op c = op(OOCS_OP_H2D, 0);
+            c.field = fld; c.slot = sl; c.z0 = g.z0; c.z1 = g.z1; c.block = g.block; c.tick = (int)tick;
+            c.level = in_ring(fld);
+            s.ops.push_back(c);
+        }
+        oocs_op rcd = op(OOCS_OP_RECORD, 0); rcd.event = ev_loaded(sl); rcd.tick = (int)tick; s.ops.push_back(rcd);
+    };
+    const int64_t nin_groups = (int64_t)s.in_groups.size();
+    for (int64_t j = 0; j < std::min<int64_t>(nstage, nin_groups); ++j) emit_h2d(j, -1);
+    for (int64_t ti = 0; ti < (int64_t)s.ticks.size(); ++ti) {
+        const Tick& t = s.ticks[ti];
+        const int isl = t.in_group >= 0 ? (int)(t.in_group % nstage) : -1;
+        const int osl = t.out_group >= 0 ? (int)(t.out_group % nstage) : -1;
+        if (isl >= 0) { oocs_op w = op(OOCS_OP_WAIT, 1); w.event = ev_loaded(isl); w.tick = (int)ti; s.ops.push_back(w); }
+        if (osl >= 0) { oocs_op w = op(OOCS_OP_WAIT, 1); w.event = ev_stored(osl); w.tick = (int)ti; s.ops.push_back(w); }
+        if (isl >= 0)
+            for (int fld : in_fields) {
+                oocs_op d = op(OOCS_OP_DECODE, 1);
+                d.field = fld; d.slot = isl; d.level = in_ring(fld); d.z0 = t.dz0; d.z1 = t.dz1; d.block = t.block; d.tick = (int)ti;
+                s.ops.push_back(d);
+            }
+        for (const LevelRange& L : t.levels) {
+            oocs_op l = op(OOCS_OP_LEVEL, 1);
+            l.level = L.lv; l.z0 = L.z0; l.z1 = L.z1; l.block = t.block; l.tick = (int)ti;
+            s.ops.push_back(l);
+        }
+        if (osl >= 0)
+            for (int fld : out_fields) {
+                oocs_op e = op(OOCS_OP_ENCODE, 1);
+                e.field = fld; e.slot = osl; e.level = out_ring(fld, kr); e.z0 = t.ez0; e.z1 = t.ez1; e.block = t.block; e.tick = (int)ti;
+                s.ops.push_back(e);
+            }
+        { oocs_op l = op(OOCS_OP_LAUNCH, 1); l.tick = (int)ti; l.block = t.block; s.ops.push_back(l); }
+        if (isl >= 0) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_decoded(isl); r2.tick = (int)ti; s.ops.push_back(r2); }
+        if (osl >= 0) {
+            oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_encoded(osl); r2.tick = (int)ti; s.ops.push_back(r2);
+            oocs_op w = op(OOCS_OP_WAIT, 2); w.event = ev_encoded(osl); w.tick = (int)ti; s.ops.push_back(w);
+            for (int fld : out_fields) {
+                oocs_op c = op(OOCS_OP_D2H, 2);
+                c.field = fld; c.slot = osl; c.z0 = t.ez0; c.z1 = t.ez1; c.block = t.block; c.tick = (int)ti;
+                c.level = out_ring(fld, kr);
+                s.ops.push_back(c);
+            }
+            oocs_op r3 = op(OOCS_OP_RECORD, 2); r3.event = ev_stored(osl); r3.tick = (int)ti; s.ops.push_back(r3);
+            if (t.last_out_of_block) {
+                oocs_op r4 = op(OOCS_OP_RECORD, 2); r4.event = ev_blk_cur(t.block); r4.tick = (int)ti; r4.block = t.block;
+                s.ops.push_back(r4);
+            }
+        }
+        if (isl >= 0 && t.in_group + nstage < nin_groups) emit_h2d(t.in_group + nstage, ti);
+    }
+    (void)err;
+    return OOCS_OK;
+}
+
+const Schedule* Planner::schedule(int kr, std::string& err)
+{
+    if (kr < 1 || kr > k) { err = "residency length out of range"; return nullptr; }
+    auto it = cache_.find(kr);
+    if (it != cache_.end()) return &it->second;
+    Schedule s;
+    if (build_ticks(kr, s, err) != OOCS_OK) return nullptr;
+    if (emit_ops(kr, s, err) != OOCS_OK) return nullptr;
+    for (const Tick& t : s.ticks) {
+        const size_t jobs = t.levels.size() + (t.in_group >= 0 ? in_fields.size() : 0) + (t.out_group >= 0 ? out_fields.size() : 0);
+        if (jobs > 24) { err = "too many jobs in one tick"; return nullptr; }
+    }
+    return &cache_.emplace(kr, std::move(s)).first->second;
+}
+
+}  // namespace oocs

@@ -1,0 +1,141 @@
+"""GPU out-of-core pipeline parity (Sec. III region sharing and temporal
+blocking, Sec. V-A separate compression, Sec. V-B three-stream pipeline).
+
+Small grids that span several slabs, several pipeline groups per slab, a
+ragged last residency and rings that wrap: the host store after the run
+equals the oracle's replay of the compressed schedule bit for bit (the
+oracle's FP32 stencil and codec), and the uncompressed run matches the
+FP64 oracle within 1e-5. At the benchmark's full size (512^3, 8 slabs, k=4,
+100 steps, 128 MiB device cap) the out-of-core result equals the GPU's
+in-core replay bit for bit, and sampled cells equal the oracle computed on
+their light cones."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2109_05410_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+MiB = 1 << 20
+
+
+def store_of(plan, f, field):
+    s = plan.new_store(f)
+    plan.put(f, field, s)
+    return s
+
+
+def decoded(store, shape, rate):
+    b = store.numpy()
+    if rate:
+        return O.codec_decode(b.view(np.uint64), shape, rate)
+    return b.view(np.float32).reshape(shape).copy()
+
+
+@pytest.mark.parametrize("rate,k,steps,n,arena", [
+    (0, 4, 10, 8, 2 * MiB), (8, 4, 10, 8, 2 * MiB), (16, 4, 9, 4, 3 * MiB), (5, 4, 7, 2, 64 * MiB),
+    (0, 3, 8, 4, 2 * MiB),
+    (12, 4, 12, 1, 2 * MiB),
+])
+def test_heat_out_of_core_matches_replay(rate, k, steps, n, arena):
+    shape = (128, 64, 64)
+    u0 = inputs.heat_uniform(shape, seed=rate + k)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena)
+    s = store_of(plan, 0, u0)
+    plan.run([s], steps)
+    got = decoded(s, shape, rate)
+    assert np.array_equal(got, O.replay_heat_f32(u0, 0.1, steps, k, rate))
+    assert np.array_equal(plan.get(0, s), got)
+    if rate == 0:
+        ref = O.heat7_f64(u0.astype(np.float64), 0.1, steps)
+        assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= 1e-5
+
+
+@pytest.mark.parametrize("rates,k,steps", [([0, 0, 0], 4, 10), ([8, 12, 8], 4, 10), ([16, 16, 16], 3, 7),
+                                           ([12, 0, 12], 1, 3)])
+def test_wave_out_of_core_matches_replay(rates, k, steps):
+    shape = (96, 36, 40)
+    rng = np.random.default_rng(k)
+    p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    pm0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    amps = rng.standard_normal(steps).astype(np.float32)
+    cell = (17, 20, 50)
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 2, k, rates, 16 * MiB, src_cell=cell)
+    st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
+    plan.run(st, steps, src_amps=amps)
+    nz, ny, nx = shape
+    idx = cell[0] + nx * (cell[1] + ny * cell[2])
+    wp, wpm, _ = O.replay_wave_f32(p0, pm0, w, steps, k, src=(amps, idx), rate_p=rates[0], rate_pm=rates[1],
+                                   rate_w=rates[2])
+    assert np.array_equal(decoded(st[0], shape, rates[0]), wp)
+    assert np.array_equal(decoded(st[1], shape, rates[1]), wpm)
+    # the read-only store is never rewritten
+    assert np.array_equal(decoded(st[2], shape, rates[2]), O.codec_roundtrip(w, rates[2]) if rates[2] else w)
+
+
+def test_repeated_runs_continue_the_state():
+    """Checkpoint/resume: 6 + 4 steps equal 10 steps (k divides 6)."""
+    shape = (64, 32, 32)
+    u0 = inputs.heat_uniform(shape, seed=9)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, 4, 2, [8], 4 * MiB)
+    s1 = store_of(plan, 0, u0)
+    plan.run([s1], 6)
+    plan.run([s1], 4)
+    s2 = store_of(plan, 0, u0)
+    plan.run([s2], 10)
+    assert torch.equal(s1, s2)
+
+
+def test_deterministic():
+    shape = (64, 32, 32)
+    u0 = inputs.heat_uniform(shape, seed=3)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, 4, 4, [16], 4 * MiB)
+    a = store_of(plan, 0, u0)
+    b = store_of(plan, 0, u0)
+    plan.run([a], 12)
+    plan.run([b], 12)
+    assert torch.equal(a, b)
+
+
+def light_cone_point(u0, steps, z, y, x, alpha=0.1):
+    """Oracle FP32 value of one cell after `steps` plain steps, computed on
+    the sub-box that holds its light cone (zero ghosts at the real faces;
+    the artificial faces are more than `steps` cells away)."""
+    nz, ny, nx = u0.shape
+    R = steps + 1
+    z0, z1 = max(z - R, 0), min(z + R + 1, nz)
+    y0, y1 = max(y - R, 0), min(y + R + 1, ny)
+    x0, x1 = max(x - R, 0), min(x + R + 1, nx)
+    sub = np.ascontiguousarray(u0[z0:z1, y0:y1, x0:x1])
+    out = O.heat7_f32(sub, alpha, steps)
+    return out[z - z0, y - y0, x - x0]
+
+
+@pytest.mark.parametrize("rate", [0, 8])
+def test_full_size_benchmark_configuration(rate):
+    """512^3, 8 slabs of 64 planes, k = 4 (h = 4), 100 steps, device arena
+    capped at two slabs (128 MiB): the configuration the benchmark times."""
+    shape = (512, 512, 512)
+    steps, k = 100, 4
+    u0 = inputs.heat_uniform(shape, seed=0)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, 8, k, [rate], 128 * MiB)
+    assert plan.info["arena_needed"] <= 128 * MiB
+    s = store_of(plan, 0, u0)
+    plan.run([s], steps)
+    got = plan.get(0, s)
+    # in-core replay on the GPU with the same kernels (no cap)
+    u = torch.from_numpy(u0).to(DEV)
+    tmp = torch.empty_like(u)
+    if rate:
+        u = api.codec_decode(api.codec_encode(u, rate), shape, rate)
+    for _ in range(steps // k):
+        api.heat7_step_k(u, 0.1, k, tmp=tmp)
+        if rate:
+            u = api.codec_decode(api.codec_encode(u, rate), shape, rate)
+    assert np.array_equal(got, u.cpu().numpy())
+    if rate == 0:
+        for (z, y, x) in ((0, 0, 0), (63, 255, 300), (64, 17, 511), (300, 500, 2)):
+            assert got[z, y, x] == light_cone_point(u0, steps, z, y, x), (z, y, x)

@@ -1,0 +1,403 @@
+"""Host logic of the out-of-core pipeline, checked without a GPU.
+
+The planner's per-residency operation list (three streams: host-to-device
+copies, compute, device-to-host copies; Sec. V-B) is
+  1. checked for races: a vector-clock happens-before analysis over several
+     residencies flags any two conflicting accesses (staging slots, ring
+     slots, host-store planes) not ordered by stream order or event edges,
+     and any two jobs of one fused launch that touch the same ring slot;
+  2. executed sequentially in host order with numpy and the oracle's codec,
+     and the resulting host store compared bit for bit with the oracle's
+     replay of the compressed schedule. Together with 1 this covers every
+     legal concurrent execution.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2109_05410_amd import _lib as L
+from paper_2109_05410_amd.api import HEAT7, WAVE25, OutOfCorePlan
+
+MiB = 1 << 20
+
+
+def plan(shape, stencil, n, k, rates, arena, **kw):
+    return OutOfCorePlan(shape, stencil, n, k, rates, arena, planning_only=True, **kw)
+
+
+# ---------------------------------------------------------------------------
+# validation and geometry
+# ---------------------------------------------------------------------------
+
+def test_config_errors():
+    with pytest.raises(L.OocsError) as e:
+        plan((512, 512, 510), HEAT7, 8, 4, [8], 1 << 30)
+    assert e.value.code == L.OOCS_E_ALIGN
+    with pytest.raises(L.OocsError) as e:
+        plan((1024, 64, 64), WAVE25, 16, 12, [0, 0, 0], 1 << 30)   # 2h = 96 > slab 64
+    assert e.value.code == L.OOCS_E_HALO
+    with pytest.raises(L.OocsError) as e:
+        plan((96, 32, 32), HEAT7, 4, 3, [8], 1 << 30)               # h = 3 not a multiple of 4
+    assert e.value.code == L.OOCS_E_ALIGN
+    with pytest.raises(L.OocsError) as e:
+        plan((64, 32, 32), HEAT7, 4, 4, [35], 1 << 30)
+    assert e.value.code == L.OOCS_E_RATE
+    with pytest.raises(L.OocsError) as e:
+        plan((512, 512, 512), HEAT7, 8, 4, [0], 4 * MiB)
+    assert e.value.code == L.OOCS_E_CAP
+    with pytest.raises(L.OocsError) as e:
+        plan((100, 32, 32), HEAT7, 8, 4, [0], 1 << 30)              # 8 does not divide 100
+    assert e.value.code == L.OOCS_E_ARG
+
+
+@pytest.mark.parametrize("rate", [0, 8, 16])
+def test_heat_512_fits_two_slab_cap(rate):
+    """512^3 FP32 in 8 slabs of 64 MiB with the device capped at two slabs."""
+    p = plan((512, 512, 512), HEAT7, 8, 4, [rate], 128 * MiB)
+    info = p.info
+    assert info["halo"] == 4 and info["arena_needed"] <= 128 * MiB
+    assert info["group"] % 4 == 0 and info["group"] >= 4
+
+
+@pytest.mark.parametrize("rate", [0, 8, 12, 16])
+def test_wave_1024_fits_8gib_cap(rate):
+    p = plan((1024, 1024, 1024), WAVE25, 8, 12, [rate, rate, rate], 8 << 30)
+    info = p.info
+    assert info["halo"] == 48 and info["arena_needed"] <= 8 << 30
+
+
+def test_slab_chunks_partition_the_axis_and_the_store():
+    p = plan((1024, 64, 64), WAVE25, 8, 12, [12, 12, 8], 1 << 30)
+    prev_end = 0
+    for i in range(8):
+        s = p.slab(i)
+        assert s["z1"] - s["z0"] == 128
+        assert s["r0"] == prev_end
+        assert s["r1"] == s["c0"]
+        prev_end = s["c1"]
+        if i < 7:
+            assert (s["c0"], s["c1"]) == (s["z1"] - 48, s["z1"] + 48)
+        for f, rate in enumerate((12, 12, 8)):
+            per_plane = (64 // 4) * (64 // 4) * rate * 8 // 4  # one 4-plane layer of blocks / 4
+            assert s["r_off"][f] == s["r0"] * per_plane
+            assert s["r_bytes"][f] == (s["r1"] - s["r0"]) * per_plane
+    assert prev_end == 1024
+    assert p.store_bytes(0) == 1024 * 64 * 64 * 12 // 8
+    assert p.store_bytes(2) == 1024 * 64 * 64 * 8 // 8
+
+
+def test_region_sharing_loads_each_plane_once_per_residency():
+    """Every input plane crosses the host link once per residency: the
+    common regions are not transferred twice (Sec. III, Fig. 2)."""
+    for shape, st, n, k, rates in (((512, 64, 64), HEAT7, 8, 4, [8]), ((1024, 32, 32), WAVE25, 8, 12, [8, 8, 8])):
+        p = plan(shape, st, n, k, rates, 1 << 30)
+        ops = p.schedule(k)
+        for f in range(len(rates)):
+            planes = np.zeros(shape[0], dtype=int)
+            for o in ops:
+                if o["kind"] == L.OP_H2D and o["field"] == f:
+                    planes[o["z0"]:o["z1"]] += 1
+            assert np.all(planes == 1)
+        for f in ([0] if st == HEAT7 else [0, 1]):
+            planes = np.zeros(shape[0], dtype=int)
+            for o in ops:
+                if o["kind"] == L.OP_D2H and o["field"] == f:
+                    planes[o["z0"]:o["z1"]] += 1
+            assert np.all(planes == 1)
+
+
+def test_separate_write_back_pairs_remainder_and_previous_common_region():
+    """After block i the planes written back are C_{i-1} (upper half) and
+    R_i, and the lower half of C_i (Fig. 3b): the write-back of block i
+    covers [a_i, a_{i+1}) and nothing else."""
+    p = plan((512, 32, 32), HEAT7, 8, 4, [8], 1 << 30)
+    for o in p.schedule(4):
+        if o["kind"] == L.OP_D2H:
+            assert 64 * o["block"] <= o["z0"] < o["z1"] <= 64 * (o["block"] + 1)
+            assert o["z0"] % 4 == 0 and o["z1"] % 4 == 0
+
+
+# ---------------------------------------------------------------------------
+# race detector
+# ---------------------------------------------------------------------------
+
+class Geometry:
+    def __init__(self, p: OutOfCorePlan):
+        self.info = p.info
+        self.nz = p.shape[0]
+        self.r = self.info["radius"]
+        self.W = self.info["ring_planes"]
+        self.wave = p.stencil == WAVE25
+        self.nin = 2 if self.wave else 1
+        self.k = p.cfg.k
+        self.ro = self.nin + self.k
+        self.nslabs = p.cfg.nslabs
+        self.nstage = self.info["nstage"]
+
+
+def accesses(o, g):
+    """(resource, is_write) pairs of one op."""
+    K = o["kind"]
+    out = []
+    if K == L.OP_H2D:
+        out.append((("in", o["field"], o["slot"]), True))
+        out += [(("host", o["field"], z), False) for z in range(o["z0"], o["z1"])]
+    elif K == L.OP_D2H:
+        out.append((("out", o["field"], o["slot"]), False))
+        out += [(("host", o["field"], z), True) for z in range(o["z0"], o["z1"])]
+    elif K == L.OP_DECODE:
+        out.append((("in", o["field"], o["slot"]), False))
+        R = o["level"]
+        out += [(("ring", R, z % g.W[R]), True) for z in range(o["z0"], o["z1"])]
+    elif K == L.OP_ENCODE:
+        out.append((("out", o["field"], o["slot"]), True))
+        R = o["level"]
+        out += [(("ring", R, z % g.W[R]), False) for z in range(o["z0"], o["z1"])]
+    elif K == L.OP_LEVEL:
+        lv = o["level"]
+        for z in range(max(o["z0"] - g.r, 0), min(o["z1"] + g.r, g.nz)):
+            out.append((("ring", lv - 1, z % g.W[lv - 1]), False))
+        if g.wave:
+            for z in range(o["z0"], o["z1"]):
+                out.append((("ring", lv - 2, z % g.W[lv - 2]), False))
+                out.append((("ring", g.ro, z % g.W[g.ro]), False))
+        out += [(("ring", lv, z % g.W[lv]), True) for z in range(o["z0"], o["z1"])]
+    return out
+
+
+def race_check(p: OutOfCorePlan, steps: int):
+    g = Geometry(p)
+    ns, n = g.nstage, g.nslabs
+    vc = [[0, 0, 0] for _ in range(3)]
+    ev_clock = {}
+    last_write = {}   # resource -> (stream, stamp, launch_id)
+    reads = {}        # resource -> list of (stream, stamp, launch_id)
+    pending = []      # compute jobs of the current launch
+    launch_id = [0]
+
+    def hb(a_stream, a_stamp, b_stream):
+        return vc[b_stream][a_stream] >= a_stamp
+
+    def access(res, write, stream, stamp, lid):
+        lw = last_write.get(res)
+        if lw is not None:
+            s, t, l = lw
+            if s == stream:
+                assert not (stream == 1 and l == lid), f"write/access in one launch on {res}"
+            else:
+                assert hb(s, t, stream), f"unordered access after write on {res}"
+        if write:
+            for s, t, l in reads.get(res, []):
+                if s == stream:
+                    assert not (stream == 1 and l == lid), f"read/write in one launch on {res}"
+                else:
+                    assert hb(s, t, stream), f"write not ordered after read on {res}"
+            last_write[res] = (stream, stamp, lid)
+            reads[res] = []
+        else:
+            reads.setdefault(res, []).append((stream, stamp, lid))
+
+    done, rnd = 0, 0
+    while done < steps:
+        kr = min(g.k, steps - done)
+        par = rnd % 2
+
+        def phys(e):
+            if e < 4 * ns:
+                return e
+            i = e - 4 * ns
+            prev = i >= n
+            if prev:
+                i -= n
+            return ("blk", (1 - par) if prev else par, i)
+
+        for o in p.schedule(kr):
+            s = o["stream"]
+            K = o["kind"]
+            if K == L.OP_RECORD:
+                ev_clock[phys(o["event"])] = list(vc[s])
+            elif K == L.OP_WAIT:
+                if o["event"] >= 4 * ns + n and rnd == 0:
+                    continue
+                c = ev_clock.get(phys(o["event"]))
+                if c is not None:
+                    vc[s] = [max(a, b) for a, b in zip(vc[s], c)]
+            elif K in (L.OP_DECODE, L.OP_LEVEL, L.OP_ENCODE):
+                pending.append(o)
+            elif K == L.OP_LAUNCH:
+                vc[1][1] += 1
+                launch_id[0] += 1
+                # gather the launch's accesses, then check them together
+                acc = []
+                for j in pending:
+                    acc += accesses(j, g)
+                writes = {}
+                for res, w in acc:
+                    if w:
+                        assert res not in writes, f"two writes of {res} in one launch"
+                        writes[res] = True
+                for res, w in acc:
+                    if not w:
+                        assert res not in writes, f"read and write of {res} in one launch"
+                for res, w in acc:
+                    access(res, w, 1, vc[1][1], launch_id[0])
+                pending.clear()
+            else:  # copies
+                vc[s][s] += 1
+                for res, w in accesses(o, g):
+                    access(res, w, s, vc[s][s], -1)
+        assert not pending
+        done += kr
+        rnd += 1
+
+
+@pytest.mark.parametrize("shape,st,n,k,rates,arena,steps", [
+    ((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, 11),
+    ((48, 12, 16), HEAT7, 4, 2, [0], 1 * MiB // 4, 9),
+    ((64, 12, 12), WAVE25, 2, 3, [8, 12, 8], 4 * MiB, 8),
+    ((64, 12, 12), WAVE25, 2, 3, [0, 0, 0], 4 * MiB, 7),
+    ((512, 32, 32), HEAT7, 8, 4, [8], 4 * MiB, 12),
+    ((1024, 16, 16), WAVE25, 8, 12, [8, 8, 8], 64 * MiB, 36),
+])
+def test_schedule_has_no_races(shape, st, n, k, rates, arena, steps):
+    p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None)
+    race_check(p, steps)
+
+
+def test_full_size_heat_schedule_has_no_races():
+    race_check(plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB), 12)
+
+
+# ---------------------------------------------------------------------------
+# sequential execution with numpy + the oracle codec
+# ---------------------------------------------------------------------------
+
+C0X3 = np.float32(-205.0 / 24.0)
+CM = [None, np.float32(8.0 / 5.0), np.float32(-1.0 / 5.0), np.float32(8.0 / 315.0), np.float32(-1.0 / 560.0)]
+
+
+def shift(a, d, axis):
+    """a shifted so that out[i] = a[i + d] along axis, zeros outside."""
+    out = np.zeros_like(a)
+    n = a.shape[axis]
+    src = [slice(None)] * a.ndim
+    dst = [slice(None)] * a.ndim
+    if d >= 0:
+        src[axis] = slice(d, n)
+        dst[axis] = slice(0, n - d)
+    else:
+        src[axis] = slice(0, n + d)
+        dst[axis] = slice(-d, n)
+    out[tuple(dst)] = a[tuple(src)]
+    return out
+
+
+def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
+    g = Geometry(p)
+    nz, ny, nx = p.shape
+    rates = list(p.cfg.rate)
+    rings = [np.zeros((w, ny, nx), np.float32) for w in g.W]
+    stage_in, stage_out = {}, {}
+    sx, sy, sz = p.cfg.src_x, p.cfg.src_y, p.cfg.src_z
+    layer_words = lambda rate: (nx // 4) * (ny // 4) * rate
+
+    def plane(R, z):
+        if z < 0 or z >= nz:
+            return np.zeros((ny, nx), np.float32)
+        return rings[R][z % g.W[R]]
+
+    done = 0
+    while done < steps:
+        kr = min(g.k, steps - done)
+        for o in p.schedule(kr):
+            K = o["kind"]
+            z0, z1 = o["z0"], o["z1"]
+            if K == L.OP_H2D:
+                f, rate = o["field"], rates[o["field"]]
+                if rate:
+                    stage_in[(f, o["slot"])] = store[f][z0 // 4 * layer_words(rate): z1 // 4 * layer_words(rate)].copy()
+                else:
+                    stage_in[(f, o["slot"])] = store[f][z0:z1].copy()
+            elif K == L.OP_DECODE:
+                f, rate = o["field"], rates[o["field"]]
+                data = stage_in[(f, o["slot"])]
+                planes = O.codec_decode(data, (z1 - z0, ny, nx), rate) if rate else data
+                for z in range(z0, z1):
+                    rings[o["level"]][z % g.W[o["level"]]] = planes[z - z0]
+            elif K == L.OP_LEVEL:
+                lv = o["level"]
+                for z in range(z0, z1):
+                    c = plane(lv - 1, z)
+                    if not g.wave:
+                        s = (shift(c, -1, 1) + shift(c, 1, 1)) + (shift(c, -1, 0) + shift(c, 1, 0))
+                        s = s + (plane(lv - 1, z - 1) + plane(lv - 1, z + 1))
+                        s = s - np.float32(6.0) * c
+                        v = c + alpha * s
+                    else:
+                        acc = C0X3 * c
+                        for m in range(1, 5):
+                            sm = (shift(c, m, 1) + shift(c, -m, 1)) + (shift(c, m, 0) + shift(c, -m, 0))
+                            sm = sm + (plane(lv - 1, z + m) + plane(lv - 1, z - m))
+                            acc = acc + CM[m] * sm
+                        v = (np.float32(2.0) * c - plane(lv - 2, z)) + plane(g.ro, z) * acc
+                        if src_amps is not None and z == sz:
+                            v = v.copy()
+                            v[sy, sx] = v[sy, sx] + src_amps[done + lv - g.nin]
+                    rings[lv][z % g.W[lv]] = v
+            elif K == L.OP_ENCODE:
+                f, rate = o["field"], rates[o["field"]]
+                planes = np.stack([plane(o["level"], z) for z in range(z0, z1)])
+                stage_out[(f, o["slot"])] = O.codec_encode(planes, rate) if rate else planes.copy()
+            elif K == L.OP_D2H:
+                f, rate = o["field"], rates[o["field"]]
+                data = stage_out[(f, o["slot"])]
+                if rate:
+                    store[f][z0 // 4 * layer_words(rate): z1 // 4 * layer_words(rate)] = data
+                else:
+                    store[f][z0:z1] = data
+        done += kr
+    return store
+
+
+def to_store(field, rate):
+    return O.codec_encode(field, rate) if rate else field.astype(np.float32).copy()
+
+
+def from_store(s, shape, rate):
+    return O.codec_decode(s, shape, rate) if rate else s
+
+
+@pytest.mark.parametrize("rate,k,steps,arena", [(0, 2, 9, MiB // 4), (8, 4, 11, 2 * MiB), (16, 4, 8, 2 * MiB),
+                                                (5, 8, 17, 1 * MiB)])
+def test_heat_schedule_computes_the_replay(rate, k, steps, arena):
+    shape = (48, 12, 16)
+    n = 4 if k < 8 else 2
+    p = plan(shape, HEAT7, n, k, [rate], arena)
+    u0 = np.random.default_rng(rate).random(shape, dtype=np.float32)
+    store = [to_store(u0, rate)]
+    # the initial store passes the field through the codec once
+    execute(p, store, steps, None)
+    got = from_store(store[0], shape, rate)
+    want = O.replay_heat_f32(u0, 0.1, steps, k, rate)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("rates,k,steps", [([0, 0, 0], 3, 7), ([8, 12, 6], 3, 8), ([16, 16, 0], 1, 3), ([12, 12, 12], 4, 9)])
+def test_wave_schedule_computes_the_replay(rates, k, steps):
+    shape = (64, 12, 12)
+    rng = np.random.default_rng(k)
+    p0 = rng.standard_normal(shape).astype(np.float32)
+    pm0 = rng.standard_normal(shape).astype(np.float32)
+    w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    amps = rng.standard_normal(steps).astype(np.float32)
+    src = (5, 6, 20)
+    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src)
+    store = [to_store(p0, rates[0]), to_store(pm0, rates[1]), to_store(w, rates[2])]
+    execute(p, store, steps, amps)
+    got_p = from_store(store[0], shape, rates[0])
+    got_pm = from_store(store[1], shape, rates[1])
+    idx = src[0] + shape[2] * (src[1] + shape[1] * src[2])
+    wp, wpm, _ = O.replay_wave_f32(p0, pm0, w, steps, k, src=(amps, idx), rate_p=rates[0], rate_pm=rates[1],
+                                   rate_w=rates[2])
+    assert np.array_equal(got_p, wp)
+    assert np.array_equal(got_pm, wpm)
