@@ -77,7 +77,8 @@ const char* oocs_last_error(void);
 size_t oocs_codec_bytes(int64_t nx, int64_t ny, int64_t nz, int rate);
 
 /* Encode the FP32 field d_in (nx, ny, nz multiples of 4; leading dimensions
- * ld_y >= nx, ld_z >= ld_y*ny, in elements) into d_out, which must hold
+ * ld_y >= nx, ld_z >= ld_y*ny, in elements, both multiples of 4; d_in
+ * 16-byte aligned, d_out 8-byte aligned) into d_out, which must hold
  * oocs_codec_bytes(nx, ny, nz, rate) bytes (out_bytes). Stream-ordered; no
  * allocation, no synchronisation. NaN and infinity are not supported.
  * Errors: OOCS_E_ARG, OOCS_E_ALIGN, OOCS_E_RATE, OOCS_E_SIZE, OOCS_E_HIP. */
@@ -252,23 +253,27 @@ int oocs_store_get(oocs_plan* plan, int field, const void* h_store, float* h_fie
 
 typedef struct {
     double wall_ms;          /* host wall time of the call */
+    double enqueue_ms;       /* host time spent issuing the work (before the final wait) */
     int64_t rounds;          /* residencies executed */
-    int64_t launches;        /* fused kernel launches issued */
     int64_t h2d_bytes;       /* bytes copied host -> device */
     int64_t d2h_bytes;       /* bytes copied device -> host */
     int64_t cell_updates;    /* nx*ny*nz*steps */
-    int64_t kernel_bytes;    /* algorithmic device-memory bytes of all launches: every
-                                input plane read once and every output plane written
-                                once per job (heat 8 B per cell update, wave 16 B,
-                                decode/encode 4 + rate/8 B per value, raw copy 8 B) */
-    double kernel_ms;        /* summed GPU time of the launches, measured with
-                                timing events around each launch on the compute
-                                stream when profiling is on; 0 otherwise */
+    /* Each tick is one launch of the pipeline kernel on the compute stream:
+     * decode and encode jobs plus one z-range of every time level. Reported:
+     * launches, the algorithmic device-memory bytes of all launches (every
+     * input plane read once and every output plane written once per job:
+     * heat 8 B per cell update, wave 16 B, decode and encode 4 + rate/8 B
+     * per value, uncompressed copy 8 B per value), split into codec and
+     * stencil jobs, and the summed GPU time of the launches measured with
+     * timing events around each launch when profiling is on (0 otherwise). */
+    int64_t launches;
+    int64_t codec_bytes, stencil_bytes;
+    double kernel_ms;
 } oocs_stats;
 
 /* Turn per-launch kernel timing on (1) or off (0) for later oocs_run calls
  * on this plan. Timing events are recorded on the plan's compute stream
- * around every fused launch; the sum of their elapsed times is returned in
+ * around every launch; the sum of their elapsed times is returned in
  * oocs_stats.kernel_ms. */
 int oocs_plan_set_profiling(oocs_plan* plan, int on);
 

@@ -247,6 +247,13 @@ def codec_roundtrip(f: np.ndarray, rate: int) -> np.ndarray:
     return g
 
 
+def codec_roundtrip_f64(f: np.ndarray, rate: int) -> np.ndarray:
+    """Q for an FP64 field: round to FP32, decode(encode()), widen back."""
+    g = np.ascontiguousarray(f, dtype=np.float64).copy()
+    _check(lib().orc_codec_roundtrip_f64(_ptr(g), *_dims(g), int(rate)), "codec_roundtrip_f64")
+    return g
+
+
 # --------------------------------------------------------------------------
 # Replay of the compressed out-of-core schedule (Sec. V-A)
 # --------------------------------------------------------------------------

@@ -71,9 +71,10 @@ class Op(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [
-        ("wall_ms", C.c_double), ("rounds", C.c_int64), ("launches", C.c_int64),
+        ("wall_ms", C.c_double), ("enqueue_ms", C.c_double), ("rounds", C.c_int64),
         ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("cell_updates", C.c_int64),
-        ("kernel_bytes", C.c_int64), ("kernel_ms", C.c_double),
+        ("launches", C.c_int64), ("codec_bytes", C.c_int64), ("stencil_bytes", C.c_int64),
+        ("kernel_ms", C.c_double),
     ]
 
 

@@ -144,12 +144,14 @@ WAVE25 = L.OOCS_WAVE25
 @dataclass
 class RunStats:
     wall_ms: float
+    enqueue_ms: float
     rounds: int
-    launches: int
     h2d_bytes: int
     d2h_bytes: int
     cell_updates: int
-    kernel_bytes: int
+    launches: int
+    codec_bytes: int
+    stencil_bytes: int
     kernel_ms: float
 
     @property
@@ -259,8 +261,7 @@ class OutOfCorePlan:
         st = L.Stats()
         L.check(L.lib().oocs_run(self._h, ptrs, steps, amps.ctypes.data_as(C.c_void_p) if amps is not None else None,
                                  C.byref(st)))
-        return RunStats(st.wall_ms, st.rounds, st.launches, st.h2d_bytes, st.d2h_bytes, st.cell_updates,
-                        st.kernel_bytes, st.kernel_ms)
+        return RunStats(*(getattr(st, name) for name, _ in L.Stats._fields_))
 
     def set_profiling(self, on: bool):
         L.check(L.lib().oocs_plan_set_profiling(self._h, 1 if on else 0))

@@ -2,55 +2,56 @@
 // (Sec. IV: fixed rate, the user chooses the bits kept per value; transform
 // of Lindstrom, IEEE TVCG 20(12), 2014).
 //
-// Mapping: one 64-lane wavefront codes one block; lane i holds value i of
-// the block (i = x + 4y + 16z inside the block). The three separable
-// lifting passes exchange the four values of each line with lane shuffles,
-// the 32 bit planes come out of 32 ballots (bit k of plane p = bit p of
-// coefficient k), and the variable-length group-test code is produced (or
-// parsed) by code that is uniform across the wave, so it runs once per
-// block rather than once per lane. Every lane keeps one 64-bit output word
-// (lane w owns word w of the block) and stores it with an ordinary vector
-// store.
+// Mapping: one lane codes one whole block. A wavefront takes 64 blocks that
+// are consecutive in x, so every row load or store of the field is one
+// 1 KiB contiguous access per wave instruction, and the 64 blocks' words
+// are one contiguous run of the compressed stream. All 64 values of a block
+// stay in registers: the separable lifting, the sequency reorder (compile
+// time register renaming) and the negabinary map need no data exchange,
+// and the 64 x 32 bit matrix of coefficients is turned into 32 bit-plane
+// words by two in-register 32 x 32 bit transposes. The variable-length
+// group-test code is then written (or parsed) by each lane on its own,
+// through a per-wave LDS buffer that holds the block words transposed
+// (word w of lane L at w*64 + L), which the wave moves to or from global
+// memory with coalesced accesses.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace oocs {
 namespace codec {
 
-// Total-sequency order of the 64 coefficients: by i+j+l, then i^2+j^2+l^2,
-// then (l, j, i) lexicographically. fwd[k] = in-block index of the k-th
-// coefficient; inv[idx] = its position k.
-struct SeqOrder {
-    int8_t fwd[64];
-    int8_t inv[64];
-};
-
+// ---- total-sequency order ---------------------------------------------------
+// Coefficients are ordered by i+j+l, then i^2+j^2+l^2, then (l, j, i)
+// lexicographically. kFwd<k> = in-block index of the k-th coefficient.
 constexpr int seq_key(int idx)
 {
-    // (s, e, l, j, i) packed so that integer order = lexicographic order
-    return (((((idx & 3) + ((idx >> 2) & 3) + (idx >> 4)) * 32 +
-              ((idx & 3) * (idx & 3) + ((idx >> 2) & 3) * ((idx >> 2) & 3) + (idx >> 4) * (idx >> 4))) * 4 +
-             (idx >> 4)) * 4 + ((idx >> 2) & 3)) * 4 + (idx & 3);
+    const int i = idx & 3, j = (idx >> 2) & 3, l = idx >> 4;
+    return ((((i + j + l) * 32 + (i * i + j * j + l * l)) * 4 + l) * 4 + j) * 4 + i;
 }
 
-constexpr SeqOrder make_seq_order()
+constexpr int seq_rank(int idx)
 {
-    SeqOrder o{};
-    // rank of each index = number of indices with a smaller key
-    for (int idx = 0; idx < 64; ++idx) {
-        int rank = 0;
-        for (int other = 0; other < 64; ++other) rank += seq_key(other) < seq_key(idx);
-        o.inv[idx] = (int8_t)rank;
-        o.fwd[rank] = (int8_t)idx;
-    }
-    return o;
+    int rank = 0;
+    for (int o = 0; o < 64; ++o) rank += seq_key(o) < seq_key(idx);
+    return rank;
 }
 
-__constant__ const SeqOrder kSeq = make_seq_order();
+constexpr int seq_fwd(int k)
+{
+    for (int idx = 0; idx < 64; ++idx)
+        if (seq_rank(idx) == k) return idx;
+    return -1;
+}
 
-// ---- lifting ----------------------------------------------------------------
-// Arithmetic in uint32 (wrap-around is defined); >> is an arithmetic shift.
+template <int K> constexpr int kFwd = seq_fwd(K);
+template <int I> constexpr int kRank = seq_rank(I);
+
+constexpr uint32_t kNB = 0xAAAAAAAAu;  // negabinary mask
+
+// ---- lifting (uint32 arithmetic wraps; >> is arithmetic) ---------------------
 __device__ inline int add_(int a, int b) { return (int)((uint32_t)a + (uint32_t)b); }
 __device__ inline int sub_(int a, int b) { return (int)((uint32_t)a - (uint32_t)b); }
 
@@ -72,43 +73,102 @@ __device__ inline void inv_lift(int& a, int& b, int& c, int& d)
     d = add_(d, a);      a = sub_(add_(a, a), d);
 }
 
-// One pass along the axis whose in-block stride is S (1 = x, 4 = y, 16 = z).
-template <bool INVERSE>
-__device__ inline int lift_pass(int v, int lane, int S)
+// Forward transform along x, then y, then z (in-block index i + 4j + 16l).
+__device__ inline void fwd_xform(int (&v)[64])
 {
-    const int pos = (lane / S) & 3;
-    const int base = lane - pos * S;
-    int a = __shfl(v, base);
-    int b = __shfl(v, base + S);
-    int c = __shfl(v, base + 2 * S);
-    int d = __shfl(v, base + 3 * S);
-    if (INVERSE) inv_lift(a, b, c, d); else fwd_lift(a, b, c, d);
-    return pos == 0 ? a : (pos == 1 ? b : (pos == 2 ? c : d));
+#pragma unroll
+    for (int o = 0; o < 16; ++o) fwd_lift(v[4 * o], v[4 * o + 1], v[4 * o + 2], v[4 * o + 3]);
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fwd_lift(v[16 * l + i], v[16 * l + i + 4], v[16 * l + i + 8], v[16 * l + i + 12]);
+#pragma unroll
+    for (int o = 0; o < 16; ++o) fwd_lift(v[o], v[o + 16], v[o + 32], v[o + 48]);
 }
 
-constexpr uint32_t kNB = 0xAAAAAAAAu;  // negabinary mask
+// Inverse transform along z, then y, then x.
+__device__ inline void inv_xform(int (&v)[64])
+{
+#pragma unroll
+    for (int o = 0; o < 16; ++o) inv_lift(v[o], v[o + 16], v[o + 32], v[o + 48]);
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) inv_lift(v[16 * l + i], v[16 * l + i + 4], v[16 * l + i + 8], v[16 * l + i + 12]);
+#pragma unroll
+    for (int o = 0; o < 16; ++o) inv_lift(v[4 * o], v[4 * o + 1], v[4 * o + 2], v[4 * o + 3]);
+}
+
+// u[k] = negabinary of coefficient kFwd<k> (sequency order).
+template <int... K>
+__device__ inline void to_sequency(const int (&t)[64], uint32_t (&u)[64], std::integer_sequence<int, K...>)
+{
+    ((u[K] = ((uint32_t)t[kFwd<K>] + kNB) ^ kNB), ...);
+}
+
+// t[idx] = integer of the coefficient at sequency position kRank<idx>.
+template <int... I>
+__device__ inline void from_sequency(const uint32_t (&u)[64], int (&t)[64], std::integer_sequence<int, I...>)
+{
+    ((t[I] = (int)((u[kRank<I>] ^ kNB) - kNB)), ...);
+}
+
+// One stage of the in-place 32 x 32 bit transpose: swap the off-diagonal
+// S x S sub-blocks of every 2S x 2S block.
+template <int S, uint32_t M>
+__device__ inline void transpose_stage(uint32_t (&a)[32])
+{
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+        if (r & S) continue;
+        const uint32_t t = ((a[r] >> S) ^ a[r + S]) & M;
+        a[r + S] ^= t;
+        a[r] ^= t << S;
+    }
+}
+
+// In-place transpose of a 32 x 32 bit matrix held as 32 rows: afterwards
+// bit c of a[r] is what bit r of a[c] was.
+__device__ inline void transpose32(uint32_t (&a)[32])
+{
+    transpose_stage<16, 0x0000FFFFu>(a);
+    transpose_stage<8, 0x00FF00FFu>(a);
+    transpose_stage<4, 0x0F0F0F0Fu>(a);
+    transpose_stage<2, 0x33333333u>(a);
+    transpose_stage<1, 0x55555555u>(a);
+}
+
+// Bit planes of the 64 sequency-ordered coefficients: bit k of plane p is
+// bit p of u[k]. lo[p] holds coefficients 0..31, hi[p] 32..63.
+__device__ inline void planes_of(const uint32_t (&u)[64], uint32_t (&lo)[32], uint32_t (&hi)[32])
+{
+#pragma unroll
+    for (int i = 0; i < 32; ++i) { lo[i] = u[i]; hi[i] = u[32 + i]; }
+    transpose32(lo);
+    transpose32(hi);
+}
+
+__device__ inline void coefficients_of(uint32_t (&lo)[32], uint32_t (&hi)[32], uint32_t (&u)[64])
+{
+    transpose32(lo);
+    transpose32(hi);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) { u[i] = lo[i]; u[32 + i] = hi[i]; }
+}
+
+__device__ inline uint64_t plane_word(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
 
 __device__ inline int exponent_of(float x)
 {
-    int e = __builtin_amdgcn_frexp_expf(x);
+    const int e = __builtin_amdgcn_frexp_expf(x);
     return e < -126 ? -126 : e;
 }
 
-__device__ inline uint64_t readlane64(uint64_t v, int lane)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Appends bits to a block stream held one word per lane (uniform control).
-struct BitSink {
-    uint64_t acc;   // partially filled word
-    int off;        // bits already in acc
-    int wi;         // index of the word being filled
-    int budget;     // bits still allowed
-    uint64_t mine;  // this lane's finished word
-    int lane;
+// ---- per-lane bit writer over the wave's LDS words --------------------------
+struct LaneWriter {
+    uint64_t* lds;  // this wave's buffer; word w of this lane at lds[w * 64]
+    uint64_t acc;
+    int off, wi, budget;
 
     __device__ void put(uint64_t v, int m)
     {
@@ -118,7 +178,7 @@ struct BitSink {
         acc |= v << off;
         int end = off + m;
         if (end >= 64) {
-            if (lane == wi) mine = acc;
+            lds[wi * 64] = acc;
             ++wi;
             acc = off == 0 ? 0 : (v >> (64 - off));
             end -= 64;
@@ -126,165 +186,218 @@ struct BitSink {
         off = end;
         budget -= m;
     }
-    __device__ void finish()
-    {
-        if (off > 0 && lane == wi) mine = acc;
-    }
 };
 
 struct EncStageOut {
     int32_t* emax; int32_t* q; int32_t* t; uint32_t* u; uint64_t* planes; int32_t* bits;
 };
 
-// Encode one block. `v` is this lane's value (natural order). Returns the
-// lane's output word (valid for lanes < rate).
+// Encode this lane's block x[64] (natural order) into words w*64 of `lds`
+// (rate words, zero padded). With STAGES the intermediate stages of block b
+// are written out.
 template <bool STAGES>
-__device__ inline uint64_t encode_block(float v, int lane, int rate, EncStageOut st = {}, int64_t b = 0)
+__device__ inline void encode_lane(const float (&x)[64], int rate, uint64_t* lds, EncStageOut st = {}, int64_t b = 0)
 {
-    // 1. common exponent
-    int e = v != 0.0f ? exponent_of(v) : -1000;
-    for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o));
-    const int emax = __builtin_amdgcn_readfirstlane(e);
-    BitSink s{0, 0, 0, 64 * rate, 0, lane};
+    int emax = -1000;
+#pragma unroll
+    for (int i = 0; i < 64; ++i)
+        if (x[i] != 0.0f) emax = max(emax, exponent_of(x[i]));
+    LaneWriter w{lds, 0, 0, 0, 64 * rate};
     if (emax == -1000) {  // all-zero block: a single 0 bit
+        w.put(0, 1);
         if (STAGES) {
-            if (lane == 0) { if (st.emax) st.emax[b] = INT32_MIN; if (st.bits) st.bits[b] = 1; }
-            if (st.q) st.q[64 * b + lane] = 0;
-            if (st.t) st.t[64 * b + lane] = 0;
-            if (st.u) st.u[64 * b + lane] = 0;
-            if (st.planes && lane < 32) st.planes[32 * b + lane] = 0;
-        }
-        return 0;
-    }
-    // 2. block floating point: exact scaling, then truncation toward zero
-    const int q = (int)ldexpf(v, 30 - emax);
-    // 3. forward transform along x, y, z
-    int t = lift_pass<false>(q, lane, 1);
-    t = lift_pass<false>(t, lane, 4);
-    t = lift_pass<false>(t, lane, 16);
-    // 4. sequency order and negabinary
-    const int tk = __shfl(t, (int)kSeq.fwd[lane]);
-    const uint32_t u = ((uint32_t)tk + kNB) ^ kNB;
-    if (STAGES) {
-        if (lane == 0 && st.emax) st.emax[b] = emax;
-        if (st.q) st.q[64 * b + lane] = q;
-        if (st.t) st.t[64 * b + lane] = t;
-        if (st.u) st.u[64 * b + lane] = u;
-    }
-    // 5. header: 1, then emax + 127 (8 bits, least significant first)
-    s.put(1u | ((uint64_t)(uint32_t)(emax + 127) << 1), 9);
-    // 6. bit planes with group testing
-    int n = 0;  // coefficients already significant (uniform)
-    for (int p = 31; p >= 0; --p) {
-        const uint64_t X = __ballot((u >> p) & 1u);
-        if (STAGES && st.planes && lane == 0) st.planes[32 * b + p] = X;
-        if (s.budget <= 0) {
-            if (STAGES) continue;
-            break;
-        }
-        s.put(X, n);  // verbatim bits of the significant coefficients
-        while (n < 64 && s.budget > 0) {
-            const uint64_t Y = X >> n;
-            if (Y == 0) { s.put(0, 1); break; }
-            const int m = __builtin_ctzll(Y);  // zeros before the next 1
-            if (n + m == 63) {                 // that 1 is the last coefficient: implied
-                s.put(1, 1 + m);
-                n = 64;
-                break;
+            if (st.emax) st.emax[b] = INT32_MIN;
+            if (st.bits) st.bits[b] = 1;
+#pragma unroll
+            for (int i = 0; i < 64; ++i) {
+                if (st.q) st.q[64 * b + i] = 0;
+                if (st.t) st.t[64 * b + i] = 0;
+                if (st.u) st.u[64 * b + i] = 0;
             }
-            s.put(1u | ((uint64_t)1 << (m + 1)), m + 2);  // test 1, m zeros, the 1
-            n += m + 1;
+#pragma unroll
+            for (int p = 0; p < 32; ++p)
+                if (st.planes) st.planes[32 * b + p] = 0;
+        }
+    } else {
+        int t[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) t[i] = (int)ldexpf(x[i], 30 - emax);  // exact scaling, truncation
+        if (STAGES) {
+            if (st.emax) st.emax[b] = emax;
+#pragma unroll
+            for (int i = 0; i < 64; ++i)
+                if (st.q) st.q[64 * b + i] = t[i];
+        }
+        fwd_xform(t);
+        uint32_t u[64];
+        to_sequency(t, u, std::make_integer_sequence<int, 64>{});
+        if (STAGES) {
+#pragma unroll
+            for (int i = 0; i < 64; ++i) {
+                if (st.t) st.t[64 * b + i] = t[i];
+                if (st.u) st.u[64 * b + i] = u[i];
+            }
+        }
+        uint32_t lo[32], hi[32];
+        planes_of(u, lo, hi);
+        if (STAGES) {
+#pragma unroll
+            for (int p = 0; p < 32; ++p)
+                if (st.planes) st.planes[32 * b + p] = plane_word(lo[p], hi[p]);
+        }
+        w.put(1u | ((uint64_t)(uint32_t)(emax + 127) << 1), 9);
+        int n = 0;  // coefficients already significant
+        for (int p = 31; p >= 0; --p) {
+            if (w.budget > 0) {
+                const uint64_t X = plane_word(lo[p], hi[p]);
+                w.put(X, n);  // verbatim bits of the significant coefficients
+                while (n < 64 && w.budget > 0) {
+                    const uint64_t Y = X >> n;
+                    if (Y == 0) { w.put(0, 1); break; }
+                    const int m = __builtin_ctzll(Y);  // zeros before the next 1
+                    if (n + m == 63) {                 // the last coefficient: its 1 is implied
+                        w.put(1, 1 + m);
+                        n = 64;
+                        break;
+                    }
+                    w.put(1u | ((uint64_t)1 << (m + 1)), m + 2);  // test 1, m zeros, the 1
+                    n += m + 1;
+                }
+            }
         }
     }
-    if (STAGES && st.bits && lane == 0) st.bits[b] = 64 * rate - s.budget;
-    s.finish();
-    return s.mine;
+    if (STAGES && st.bits && emax != -1000) st.bits[b] = 64 * rate - w.budget;
+    if (w.off > 0) { lds[w.wi * 64] = w.acc; ++w.wi; }
+    for (int k = w.wi; k < rate; ++k) lds[k * 64] = 0;
 }
 
-struct DecStageOut {
-    int32_t* emax; uint64_t* planes; uint32_t* u; int32_t* q;
-};
+// ---- per-lane bit reader over the wave's LDS words --------------------------
+struct LaneReader {
+    const uint64_t* lds;  // word w of this lane at lds[w * 64]
+    int rate;
+    uint64_t cur, nxt;    // words wi and wi+1 (0 past the block)
+    int wi, off;
 
-// Reads a block stream held one word per lane (uniform control).
-struct BitSource {
-    uint64_t mine;  // this lane's word (0 beyond the block)
-    int pos;
-
-    __device__ uint64_t window() const  // 64 bits starting at pos
+    __device__ void init()
     {
-        const int wi = pos >> 6, off = pos & 63;
-        const uint64_t w0 = readlane64(mine, wi);
-        if (off == 0) return w0;
-        const uint64_t w1 = wi + 1 < 64 ? readlane64(mine, wi + 1) : 0;
-        return (w0 >> off) | (w1 << (64 - off));
+        wi = 0; off = 0;
+        cur = lds[0];
+        nxt = rate > 1 ? lds[64] : 0;
+    }
+    __device__ uint64_t window() const { return off == 0 ? cur : (cur >> off) | (nxt << (64 - off)); }
+    __device__ void skip(int m)
+    {
+        off += m;
+        while (off >= 64) {
+            off -= 64;
+            ++wi;
+            cur = nxt;
+            nxt = wi + 1 < rate ? lds[(wi + 1) * 64] : 0;
+        }
     }
     __device__ uint64_t get(int m)  // m in [0, 64]
     {
         if (m <= 0) return 0;
         uint64_t v = window();
         if (m < 64) v &= ((uint64_t)1 << m) - 1;
-        pos += m;
+        skip(m);
         return v;
     }
 };
 
-// Decode one block; `word` is this lane's word of the block (0 for lanes >=
-// rate). Returns this lane's value (natural order).
+struct DecStageOut {
+    int32_t* emax; uint64_t* planes; uint32_t* u; int32_t* q;
+};
+
+// Decode this lane's block from words w*64 of `lds` into x[64] (natural order).
 template <bool STAGES>
-__device__ inline float decode_block(uint64_t word, int lane, int rate, DecStageOut st = {}, int64_t b = 0)
+__device__ inline void decode_lane(const uint64_t* lds, int rate, float (&x)[64], DecStageOut st = {}, int64_t b = 0)
 {
-    BitSource s{word, 0};
-    if (s.get(1) == 0) {
+    LaneReader r{lds, rate, 0, 0, 0, 0};
+    r.init();
+    if (r.get(1) == 0) {
+#pragma unroll
+        for (int i = 0; i < 64; ++i) x[i] = 0.0f;
         if (STAGES) {
-            if (lane == 0 && st.emax) st.emax[b] = INT32_MIN;
-            if (st.planes && lane < 32) st.planes[32 * b + lane] = 0;
-            if (st.u) st.u[64 * b + lane] = 0;
-            if (st.q) st.q[64 * b + lane] = 0;
+            if (st.emax) st.emax[b] = INT32_MIN;
+#pragma unroll
+            for (int i = 0; i < 64; ++i) {
+                if (st.u) st.u[64 * b + i] = 0;
+                if (st.q) st.q[64 * b + i] = 0;
+            }
+#pragma unroll
+            for (int p = 0; p < 32; ++p)
+                if (st.planes) st.planes[32 * b + p] = 0;
         }
-        return 0.0f;
+        return;
     }
-    const int emax = (int)s.get(8) - 127;
+    const int emax = (int)r.get(8) - 127;
     int budget = 64 * rate - 9;
     int n = 0;
-    uint32_t u = 0;
+    uint32_t lo[32], hi[32];
     for (int p = 31; p >= 0; --p) {
         uint64_t X = 0;
         if (budget > 0) {
             const int m = n < budget ? n : budget;
-            X = s.get(m);
+            X = r.get(m);
             budget -= m;
             while (n < 64 && budget > 0) {
-                const uint64_t g = s.get(1);
+                const uint64_t g = r.get(1);
                 --budget;
                 if (!g) break;
-                const uint64_t win = s.window();
+                const uint64_t win = r.window();
                 int z = win ? __builtin_ctzll(win) : 64;  // zeros before the next 1
                 const int maxscan = 63 - n;
                 if (z > maxscan) z = maxscan;
                 if (z > budget) z = budget;
-                s.pos += z; budget -= z; n += z;
+                r.skip(z); budget -= z; n += z;
                 if (n == 63) { X |= (uint64_t)1 << 63; n = 64; break; }
                 if (budget == 0) break;
-                s.pos += 1; --budget;  // the 1 that ends the run
+                r.skip(1); --budget;  // the 1 that ends the run
                 X |= (uint64_t)1 << n;
                 ++n;
             }
         }
-        if (STAGES && st.planes && lane == 0) st.planes[32 * b + p] = X;
-        u = (u << 1) | (uint32_t)((X >> lane) & 1u);
+        lo[p] = (uint32_t)X;
+        hi[p] = (uint32_t)(X >> 32);
+        if (STAGES && st.planes) st.planes[32 * b + p] = X;
     }
-    // inverse negabinary (lane k = sequency position k), back to natural order
-    const int qk = (int)((u ^ kNB) - kNB);
-    int q = __shfl(qk, (int)kSeq.inv[lane]);
-    q = lift_pass<true>(q, lane, 16);
-    q = lift_pass<true>(q, lane, 4);
-    q = lift_pass<true>(q, lane, 1);
+    uint32_t u[64];
+    coefficients_of(lo, hi, u);
+    int t[64];
+    from_sequency(u, t, std::make_integer_sequence<int, 64>{});
+    inv_xform(t);
     if (STAGES) {
-        if (lane == 0 && st.emax) st.emax[b] = emax;
-        if (st.u) st.u[64 * b + lane] = u;
-        if (st.q) st.q[64 * b + lane] = q;
+        if (st.emax) st.emax[b] = emax;
+#pragma unroll
+        for (int i = 0; i < 64; ++i) {
+            if (st.u) st.u[64 * b + i] = u[i];
+            if (st.q) st.q[64 * b + i] = t[i];
+        }
     }
-    return ldexpf((float)q, emax - 30);
+#pragma unroll
+    for (int i = 0; i < 64; ++i) x[i] = ldexpf((float)t[i], emax - 30);
+}
+
+// ---- wave-level movement of block words between global memory and LDS ------
+// The 64 blocks of a wave own words [0, 64*rate) of `g` (block-major:
+// block k's word w at k*rate + w). LDS holds them transposed (w*64 + k).
+__device__ inline void words_to_lds(const uint64_t* g, uint64_t* lds, int rate, int nblocks, int lane)
+{
+    const int total = 64 * rate;
+    for (int f = lane; f < total; f += 64) {
+        const int k = f / rate, w = f - k * rate;
+        lds[w * 64 + k] = k < nblocks ? g[f] : 0;
+    }
+}
+
+__device__ inline void lds_to_words(const uint64_t* lds, uint64_t* g, int rate, int nblocks, int lane)
+{
+    const int total = nblocks * rate;
+    for (int f = lane; f < total; f += 64) {
+        const int k = f / rate, w = f - k * rate;
+        g[f] = lds[w * 64 + k];
+    }
 }
 
 }  // namespace codec

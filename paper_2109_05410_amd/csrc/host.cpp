@@ -78,6 +78,7 @@ static int codec_check(int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t
     if (!dims_ok4(nx, ny, nz)) return fail(OOCS_E_ALIGN, "codec dimensions must be multiples of 4");
     if (rate < 1 || rate > OOCS_MAX_RATE) return fail(OOCS_E_RATE, "rate must be in [1, 34]");
     if (ld_y < nx || ld_z < ld_y * ny) return fail(OOCS_E_ARG, "leading dimensions too small");
+    if (ld_y % 4 || ld_z % 4) return fail(OOCS_E_ALIGN, "leading dimensions must be multiples of 4");
     if (bytes < oocs_codec_bytes(nx, ny, nz, rate)) return fail(OOCS_E_SIZE, "compressed buffer too small");
     if (nx / 4 > (1 << 30) || (nx / 4) * (ny / 4) * (nz / 4) > ((int64_t)1 << 40)) return fail(OOCS_E_ARG, "field too large");
     return OOCS_OK;
@@ -87,6 +88,7 @@ int oocs_codec_encode(const float* d_in, int64_t nx, int64_t ny, int64_t nz, int
                       uint64_t* d_out, size_t out_bytes, void* stream)
 {
     if (!d_in || !d_out) return fail(OOCS_E_ARG, "null pointer");
+    if ((uintptr_t)d_in % 16 || (uintptr_t)d_out % 8) return fail(OOCS_E_ALIGN, "field must be 16-byte aligned, words 8-byte aligned");
     int rc = codec_check(nx, ny, nz, ld_y, ld_z, rate, out_bytes);
     if (rc) return rc;
     HIP_TRY(oocs::launch_codec_field(true, d_in, nullptr, nullptr, d_out, nx, ny, nz, ld_y, ld_z, rate,
@@ -98,6 +100,7 @@ int oocs_codec_decode(const uint64_t* d_in, size_t in_bytes, int64_t nx, int64_t
                       int64_t ld_y, int64_t ld_z, void* stream)
 {
     if (!d_in || !d_out) return fail(OOCS_E_ARG, "null pointer");
+    if ((uintptr_t)d_out % 16 || (uintptr_t)d_in % 8) return fail(OOCS_E_ALIGN, "field must be 16-byte aligned, words 8-byte aligned");
     int rc = codec_check(nx, ny, nz, ld_y, ld_z, rate, in_bytes);
     if (rc) return rc;
     HIP_TRY(oocs::launch_codec_field(false, nullptr, d_out, d_in, nullptr, nx, ny, nz, ld_y, ld_z, rate,
@@ -415,7 +418,8 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     auto ring = [&](int idx) {
         return oocs::Ring{reinterpret_cast<float*>(pl->arena + P.ringOff[idx]), P.ringW[idx], pe};
     };
-    int64_t h2d = 0, d2h = 0, launches = 0, rounds = 0, kbytes = 0;
+    int64_t h2d = 0, d2h = 0, rounds = 0, launches = 0;
+    int64_t kbytes[2] = {0, 0};  // codec jobs, stencil jobs
     size_t tused = 0;
     const int ns = P.nstage;
     int64_t done = 0;
@@ -456,11 +460,11 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
             }
             case OOCS_OP_DECODE:
             case OOCS_OP_ENCODE: {
+                const int rate = P.cfg.rate[o.field];
                 if (lp.njobs >= oocs::kMaxJobs) return fail(OOCS_E_STATE, "too many jobs in a tick");
                 oocs::Job& j = lp.jobs[lp.njobs++];
                 std::memset(&j, 0, sizeof j);
                 const bool dec = o.kind == OOCS_OP_DECODE;
-                const int rate = P.cfg.rate[o.field];
                 j.kind = rate ? (dec ? oocs::JOB_DECODE : oocs::JOB_ENCODE) : (dec ? oocs::JOB_COPY_IN : oocs::JOB_COPY_OUT);
                 j.z0 = (int32_t)o.z0; j.z1 = (int32_t)o.z1;
                 j.rate = rate;
@@ -490,7 +494,8 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
             }
             case OOCS_OP_LAUNCH:
                 if (lp.njobs > 0) {
-                    for (int i = 0; i < lp.njobs; ++i) kbytes += job_bytes(lp.jobs[i], pe);
+                    for (int i = 0; i < lp.njobs; ++i)
+                        kbytes[oocs::is_codec_job(lp.jobs[i].kind) ? 0 : 1] += job_bytes(lp.jobs[i], pe);
                     if (pl->profiling) {
                         while (pl->tev.size() < tused + 2) {
                             hipEvent_t e;
@@ -522,6 +527,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
         done += kr;
         ++rounds;
     }
+    const double enq = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     for (int i = 0; i < 3; ++i) HIP_TRY(hipStreamSynchronize(pl->st[i]));
     const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     double kms = 0.0;
@@ -532,12 +538,14 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     }
     if (st) {
         st->wall_ms = wall;
+        st->enqueue_ms = enq;
         st->rounds = rounds;
-        st->launches = launches;
         st->h2d_bytes = h2d;
         st->d2h_bytes = d2h;
         st->cell_updates = P.nx * P.ny * P.nz * steps;
-        st->kernel_bytes = kbytes;
+        st->launches = launches;
+        st->codec_bytes = kbytes[0];
+        st->stencil_bytes = kbytes[1];
         st->kernel_ms = kms;
     }
     return OOCS_OK;

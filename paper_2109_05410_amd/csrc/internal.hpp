@@ -16,7 +16,12 @@ struct Ring {
     int64_t ld_z;  // elements from one plane to the next
 };
 
-__host__ __device__ inline float* ring_plane(const Ring& r, int64_t z) { return r.base + (z % r.W) * r.ld_z; }
+// Planes and ring sizes stay below 2^31 (the planner caps grid dimensions at
+// 2^20), so the slot is a 32-bit remainder.
+__host__ __device__ inline float* ring_plane(const Ring& r, int64_t z)
+{
+    return r.base + (int64_t)((uint32_t)z % (uint32_t)r.W) * r.ld_z;
+}
 
 enum JobKind : int32_t {
     JOB_HEAT = 1,    // one heat time level over planes [z0, z1)
@@ -60,7 +65,11 @@ struct LaunchParams {
 // Workgroups a job needs (host side).
 int32_t job_workgroups(const Job& j, int nx, int ny);
 
-// Launch the fused kernel for the jobs in p (p.wg_begin is filled here).
+// True for the decode and encode jobs.
+bool is_codec_job(int kind);
+
+// Launch the fused kernel for the jobs in p (reorders p.jobs so that codec
+// jobs come first; fills p.wg_begin).
 hipError_t launch_jobs(LaunchParams& p, hipStream_t stream);
 
 // Standalone codec launches on dense (non-ring) fields.

@@ -1,10 +1,10 @@
 // kernels.hip -- the gfx950 kernels of liboocs and their host launchers.
 //
-// The out-of-core pipeline issues one launch per tick. A tick's jobs
-// (decode of the next input group, one z-range of every time level, encode
-// of the finished output group) are independent by construction of the
-// schedule, so they share one launch: the workgroup index selects the job
-// and the job's own workgroup. All jobs use 256-thread workgroups.
+// The out-of-core pipeline issues one launch per tick. A tick's jobs (decode
+// of the next input group, one z-range of every time level, encode of the
+// finished output group) are independent by construction of the schedule,
+// so they share one launch: the workgroup index selects the job and the
+// job's own workgroup. All jobs use 256-thread workgroups.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -16,39 +16,68 @@ namespace oocs {
 
 static_assert(sizeof(LaunchParams) <= 4096, "kernel arguments must stay within 4 KiB");
 
-constexpr int kWavesPerWG = kBlockThreads / 64;  // codec: one 4^3 block per wave
+constexpr int kWavesPerWG = kBlockThreads / 64;
 constexpr int kCopyFloat4PerThread = 4;
+
+extern __shared__ uint64_t dyn_lds[];  // codec jobs: 64 * rate words per wave
 
 // ---------------------------------------------------------------------------
 // Codec and copy jobs on ring planes
 // ---------------------------------------------------------------------------
 
-// Staging slot of compressed words: the 4-plane layers of [z0, z1) in z
-// order, each layer's blocks x fastest then y; rate words per block.
+// Each wave codes 64 blocks consecutive in x (one lane per block). Staging
+// slot of compressed words: the 4-plane layers of [z0, z1) in z order, each
+// layer's blocks x fastest then y; rate words per block.
 __device__ inline void codec_job(const Job& j, int nx, int ny, int wg, bool encode)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int wave = (int)(threadIdx.x >> 6);
     const int nbx = nx >> 2, nby = ny >> 2;
-    const int groups_x = (nbx + kWavesPerWG - 1) / kWavesPerWG;
-    const int per_layer = groups_x * nby;
-    const int layer = wg / per_layer;
-    const int rem = wg % per_layer;
-    const int by = rem / groups_x;
-    const int bx = (rem % groups_x) * kWavesPerWG + wave;
+    const int chunks = (nbx + 63) / 64;
+    const int c = wg * kWavesPerWG + wave;  // wave chunk within the job
+    const int layer = c / (chunks * nby);
+    const int rem = c % (chunks * nby);
+    const int by = rem / chunks;
+    const int bx0 = (rem % chunks) * 64;
     const int z = j.z0 + 4 * layer;
-    if (bx >= nbx || z >= j.z1) return;  // whole wave leaves together
+    const bool wave_active = z < j.z1;
+    const int nblocks = wave_active ? min(64, nbx - bx0) : 0;
+    const bool active = lane < nblocks;
     const int rate = j.rate;
-    const int64_t blk = ((int64_t)layer * nby + by) * nbx + bx;
-    uint64_t* words = static_cast<uint64_t*>(j.stage) + blk * rate;
-    const int i = lane & 3, jy = (lane >> 2) & 3, l = lane >> 4;
-    float* cell = ring_plane(j.dst, z + l) + (int64_t)(4 * by + jy) * nx + 4 * bx + i;
+    uint64_t* lds = dyn_lds + (size_t)wave * 64 * rate;
+    uint64_t* words = static_cast<uint64_t*>(j.stage) + (((int64_t)layer * nby + by) * nbx + bx0) * rate;
+    const int64_t row0 = (int64_t)(4 * by) * nx + 4 * (bx0 + lane);
+    float x[64];
     if (encode) {
-        const uint64_t w = codec::encode_block<false>(*cell, lane, rate);
-        if (lane < rate) words[lane] = w;
+        if (active) {
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const float* pl = ring_plane(j.dst, z + l) + row0;
+#pragma unroll
+                for (int jy = 0; jy < 4; ++jy) {
+                    const float4 v = *reinterpret_cast<const float4*>(pl + (int64_t)jy * nx);
+                    x[16 * l + 4 * jy] = v.x; x[16 * l + 4 * jy + 1] = v.y;
+                    x[16 * l + 4 * jy + 2] = v.z; x[16 * l + 4 * jy + 3] = v.w;
+                }
+            }
+            codec::encode_lane<false>(x, rate, lds + lane);
+        }
+        __syncthreads();
+        if (nblocks > 0) codec::lds_to_words(lds, words, rate, nblocks, lane);
     } else {
-        const uint64_t w = lane < rate ? words[lane] : 0;
-        *cell = codec::decode_block<false>(w, lane, rate);
+        if (nblocks > 0) codec::words_to_lds(words, lds, rate, nblocks, lane);
+        __syncthreads();
+        if (active) {
+            codec::decode_lane<false>(lds + lane, rate, x);
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                float* pl = ring_plane(j.dst, z + l) + row0;
+#pragma unroll
+                for (int jy = 0; jy < 4; ++jy)
+                    *reinterpret_cast<float4*>(pl + (int64_t)jy * nx) =
+                        make_float4(x[16 * l + 4 * jy], x[16 * l + 4 * jy + 1], x[16 * l + 4 * jy + 2], x[16 * l + 4 * jy + 3]);
+            }
+        }
     }
 }
 
@@ -74,7 +103,32 @@ __device__ inline void copy_job(const Job& j, int nx, int ny, int wg, bool in)
     }
 }
 
+// All jobs of a tick share one launch. Codec jobs come first in the job list
+// so that their workgroups, whose lanes each run a whole block's serial bit
+// coding, are dispatched first and the short stencil workgroups fill the
+// machine around them.
 __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
+{
+    const int wg = (int)blockIdx.x;
+    int jdx = 0;
+    while (jdx + 1 < p.njobs && wg >= p.wg_begin[jdx + 1]) ++jdx;
+    const Job& j = p.jobs[jdx];
+    const int local = wg - p.wg_begin[jdx];
+    switch (j.kind) {
+    case JOB_DECODE: codec_job(j, p.nx, p.ny, local, false); break;
+    case JOB_ENCODE: codec_job(j, p.nx, p.ny, local, true); break;
+    case JOB_HEAT: stencil::heat_level(j, p.nx, p.ny, p.nz, p.alpha, local); break;
+    case JOB_WAVE: stencil::wave_level(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, local); break;
+    case JOB_COPY_IN: copy_job(j, p.nx, p.ny, local, true); break;
+    case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
+    default: break;
+    }
+}
+
+// Launches without codec jobs use this kernel: a stencil thread needs about
+// 40 VGPRs, and the codec path of the fused kernel would cap it at the
+// codec's occupancy.
+__global__ void __launch_bounds__(kBlockThreads) stencil_kernel(LaunchParams p)
 {
     const int wg = (int)blockIdx.x;
     int jdx = 0;
@@ -84,13 +138,13 @@ __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
     switch (j.kind) {
     case JOB_HEAT: stencil::heat_level(j, p.nx, p.ny, p.nz, p.alpha, local); break;
     case JOB_WAVE: stencil::wave_level(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, local); break;
-    case JOB_DECODE: codec_job(j, p.nx, p.ny, local, false); break;
-    case JOB_ENCODE: codec_job(j, p.nx, p.ny, local, true); break;
     case JOB_COPY_IN: copy_job(j, p.nx, p.ny, local, true); break;
     case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
     default: break;
     }
 }
+
+bool is_codec_job(int kind) { return kind == JOB_DECODE || kind == JOB_ENCODE; }
 
 int32_t job_workgroups(const Job& j, int nx, int ny)
 {
@@ -105,7 +159,8 @@ int32_t job_workgroups(const Job& j, int nx, int ny)
     case JOB_DECODE:
     case JOB_ENCODE: {
         const int nbx = nx / 4, nby = ny / 4;
-        return ((nbx + kWavesPerWG - 1) / kWavesPerWG) * nby * ((planes + 3) / 4);
+        const int waves = ((nbx + 63) / 64) * nby * ((planes + 3) / 4);
+        return (waves + kWavesPerWG - 1) / kWavesPerWG;
     }
     case JOB_COPY_IN:
     case JOB_COPY_OUT: {
@@ -119,15 +174,29 @@ int32_t job_workgroups(const Job& j, int nx, int ny)
 
 hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
 {
+    // codec jobs first (stable order otherwise)
+    Job sorted[kMaxJobs];
+    int n = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < p.njobs; ++i)
+            if (is_codec_job(p.jobs[i].kind) == (pass == 0)) sorted[n++] = p.jobs[i];
     int32_t total = 0;
-    for (int i = 0; i < p.njobs; ++i) {
+    int max_rate = 0;
+    for (int i = 0; i < n; ++i) {
+        p.jobs[i] = sorted[i];
         p.wg_begin[i] = total;
         p.jobs[i].wg_count = job_workgroups(p.jobs[i], p.nx, p.ny);
         total += p.jobs[i].wg_count;
+        if (is_codec_job(p.jobs[i].kind)) max_rate = max(max_rate, p.jobs[i].rate);
     }
     p.wg_begin[p.njobs] = total;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(fused_kernel, dim3((unsigned)total), dim3(kBlockThreads), 0, stream, p);
+    if (max_rate > 0) {
+        const size_t lds = (size_t)kWavesPerWG * 64 * max_rate * sizeof(uint64_t);
+        hipLaunchKernelGGL(fused_kernel, dim3((unsigned)total), dim3(kBlockThreads), lds, stream, p);
+    } else {
+        hipLaunchKernelGGL(stencil_kernel, dim3((unsigned)total), dim3(kBlockThreads), 0, stream, p);
+    }
     return hipGetLastError();
 }
 
@@ -141,23 +210,44 @@ codec_field_kernel(bool encode, const float* in_f, float* out_f, const uint64_t*
 {
     const int lane = (int)(threadIdx.x & 63);
     const int wave = (int)(threadIdx.x >> 6);
-    const int groups_x = (nbx + kWavesPerWG - 1) / kWavesPerWG;
-    const int64_t wg = blockIdx.x;
-    const int64_t per_layer = (int64_t)groups_x * nby;
-    const int bz = (int)(wg / per_layer);
-    const int rem = (int)(wg % per_layer);
-    const int by = rem / groups_x;
-    const int bx = (rem % groups_x) * kWavesPerWG + wave;
-    if (bx >= nbx || bz >= nbz) return;
-    const int64_t blk = ((int64_t)bz * nby + by) * nbx + bx;
-    const int i = lane & 3, jy = (lane >> 2) & 3, l = lane >> 4;
-    const int64_t cell = (int64_t)(4 * bz + l) * ld_z + (int64_t)(4 * by + jy) * ld_y + 4 * bx + i;
+    const int chunks = (nbx + 63) / 64;
+    const int64_t c = (int64_t)blockIdx.x * kWavesPerWG + wave;
+    const int bz = (int)(c / ((int64_t)chunks * nby));
+    const int rem = (int)(c % ((int64_t)chunks * nby));
+    const int by = rem / chunks;
+    const int bx0 = (rem % chunks) * 64;
+    const int nblocks = bz < nbz ? min(64, nbx - bx0) : 0;
+    const bool active = lane < nblocks;
+    uint64_t* lds = dyn_lds + (size_t)wave * 64 * rate;
+    const int64_t blk0 = ((int64_t)bz * nby + by) * nbx + bx0;
+    const int64_t base = (int64_t)(4 * bz) * ld_z + (int64_t)(4 * by) * ld_y + 4 * (bx0 + lane);
+    float x[64];
     if (encode) {
-        const uint64_t w = codec::encode_block<false>(in_f[cell], lane, rate);
-        if (lane < rate) out_w[blk * rate + lane] = w;
+        if (active) {
+#pragma unroll
+            for (int l = 0; l < 4; ++l)
+#pragma unroll
+                for (int jy = 0; jy < 4; ++jy) {
+                    const float4 v = *reinterpret_cast<const float4*>(in_f + base + l * ld_z + jy * ld_y);
+                    x[16 * l + 4 * jy] = v.x; x[16 * l + 4 * jy + 1] = v.y;
+                    x[16 * l + 4 * jy + 2] = v.z; x[16 * l + 4 * jy + 3] = v.w;
+                }
+            codec::encode_lane<false>(x, rate, lds + lane);
+        }
+        __syncthreads();
+        if (nblocks > 0) codec::lds_to_words(lds, out_w + blk0 * rate, rate, nblocks, lane);
     } else {
-        const uint64_t w = lane < rate ? in_w[blk * rate + lane] : 0;
-        out_f[cell] = codec::decode_block<false>(w, lane, rate);
+        if (nblocks > 0) codec::words_to_lds(in_w + blk0 * rate, lds, rate, nblocks, lane);
+        __syncthreads();
+        if (active) {
+            codec::decode_lane<false>(lds + lane, rate, x);
+#pragma unroll
+            for (int l = 0; l < 4; ++l)
+#pragma unroll
+                for (int jy = 0; jy < 4; ++jy)
+                    *reinterpret_cast<float4*>(out_f + base + l * ld_z + jy * ld_y) =
+                        make_float4(x[16 * l + 4 * jy], x[16 * l + 4 * jy + 1], x[16 * l + 4 * jy + 2], x[16 * l + 4 * jy + 3]);
+        }
     }
 }
 
@@ -166,9 +256,11 @@ hipError_t launch_codec_field(bool encode, const float* in_f, float* out_f, cons
                               hipStream_t stream)
 {
     const int nbx = (int)(nx / 4), nby = (int)(ny / 4), nbz = (int)(nz / 4);
-    const int64_t groups = (int64_t)((nbx + kWavesPerWG - 1) / kWavesPerWG) * nby * nbz;
+    const int64_t waves = (int64_t)((nbx + 63) / 64) * nby * nbz;
+    const int64_t groups = (waves + kWavesPerWG - 1) / kWavesPerWG;
     if (groups == 0) return hipSuccess;
-    hipLaunchKernelGGL(codec_field_kernel, dim3((unsigned)groups), dim3(kBlockThreads), 0, stream, encode, in_f,
+    const size_t lds = (size_t)kWavesPerWG * 64 * rate * sizeof(uint64_t);
+    hipLaunchKernelGGL(codec_field_kernel, dim3((unsigned)groups), dim3(kBlockThreads), lds, stream, encode, in_f,
                        out_f, in_w, out_w, nbx, nby, nbz, ld_y, ld_z, rate);
     return hipGetLastError();
 }
@@ -199,38 +291,59 @@ __global__ void __launch_bounds__(kBlockThreads)
 encode_stages_kernel(const float* blocks, int64_t nblocks, int rate, EncStages s)
 {
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t b = (int64_t)blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
-    if (b >= nblocks) return;
-    codec::EncStageOut st{s.emax, s.q, s.t, s.u, s.planes, s.bits};
-    const uint64_t w = codec::encode_block<true>(blocks[64 * b + lane], lane, rate, st, b);
-    if (s.words && lane < rate) s.words[b * rate + lane] = w;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int64_t b0 = ((int64_t)blockIdx.x * kWavesPerWG + wave) * 64;
+    const int nb = (int)max<int64_t>(0, min<int64_t>(64, nblocks - b0));
+    const int64_t b = b0 + lane;
+    uint64_t* lds = dyn_lds + (size_t)wave * 64 * rate;
+    if (lane < nb) {
+        float x[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) x[i] = blocks[64 * b + i];
+        codec::EncStageOut st{s.emax, s.q, s.t, s.u, s.planes, s.bits};
+        codec::encode_lane<true>(x, rate, lds + lane, st, b);
+    }
+    __syncthreads();
+    if (nb > 0 && s.words) codec::lds_to_words(lds, s.words + b0 * rate, rate, nb, lane);
 }
 
 __global__ void __launch_bounds__(kBlockThreads)
 decode_stages_kernel(const uint64_t* words, int64_t nblocks, int rate, DecStages s)
 {
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t b = (int64_t)blockIdx.x * kWavesPerWG + (threadIdx.x >> 6);
-    if (b >= nblocks) return;
-    codec::DecStageOut st{s.emax, s.planes, s.u, s.q};
-    const uint64_t w = lane < rate ? words[b * rate + lane] : 0;
-    const float v = codec::decode_block<true>(w, lane, rate, st, b);
-    if (s.out) s.out[64 * b + lane] = v;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int64_t b0 = ((int64_t)blockIdx.x * kWavesPerWG + wave) * 64;
+    const int nb = (int)max<int64_t>(0, min<int64_t>(64, nblocks - b0));
+    const int64_t b = b0 + lane;
+    uint64_t* lds = dyn_lds + (size_t)wave * 64 * rate;
+    if (nb > 0) codec::words_to_lds(words + b0 * rate, lds, rate, nb, lane);
+    __syncthreads();
+    if (lane < nb) {
+        float x[64];
+        codec::DecStageOut st{s.emax, s.planes, s.u, s.q};
+        codec::decode_lane<true>(lds + lane, rate, x, st, b);
+        if (s.out) {
+#pragma unroll
+            for (int i = 0; i < 64; ++i) s.out[64 * b + i] = x[i];
+        }
+    }
 }
 
 hipError_t launch_encode_stages(const float* blocks, int64_t nblocks, int rate, EncStages s, hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
-    const unsigned g = (unsigned)((nblocks + kWavesPerWG - 1) / kWavesPerWG);
-    hipLaunchKernelGGL(encode_stages_kernel, dim3(g), dim3(kBlockThreads), 0, stream, blocks, nblocks, rate, s);
+    const unsigned g = (unsigned)((nblocks + 64 * kWavesPerWG - 1) / (64 * kWavesPerWG));
+    const size_t lds = (size_t)kWavesPerWG * 64 * rate * sizeof(uint64_t);
+    hipLaunchKernelGGL(encode_stages_kernel, dim3(g), dim3(kBlockThreads), lds, stream, blocks, nblocks, rate, s);
     return hipGetLastError();
 }
 
 hipError_t launch_decode_stages(const uint64_t* words, int64_t nblocks, int rate, DecStages s, hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
-    const unsigned g = (unsigned)((nblocks + kWavesPerWG - 1) / kWavesPerWG);
-    hipLaunchKernelGGL(decode_stages_kernel, dim3(g), dim3(kBlockThreads), 0, stream, words, nblocks, rate, s);
+    const unsigned g = (unsigned)((nblocks + 64 * kWavesPerWG - 1) / (64 * kWavesPerWG));
+    const size_t lds = (size_t)kWavesPerWG * 64 * rate * sizeof(uint64_t);
+    hipLaunchKernelGGL(decode_stages_kernel, dim3(g), dim3(kBlockThreads), lds, stream, words, nblocks, rate, s);
     return hipGetLastError();
 }
 

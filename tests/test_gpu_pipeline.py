@@ -77,15 +77,16 @@ def test_wave_out_of_core_matches_replay(rates, k, steps):
 
 
 def test_repeated_runs_continue_the_state():
-    """Checkpoint/resume: 6 + 4 steps equal 10 steps (k divides 6)."""
+    """Checkpoint/resume: 8 + 5 steps equal 13 steps (k = 4 divides 8); the
+    host store between calls is the whole state."""
     shape = (64, 32, 32)
     u0 = inputs.heat_uniform(shape, seed=9)
-    plan = api.OutOfCorePlan(shape, api.HEAT7, 4, 2, [8], 4 * MiB)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, 4, 4, [8], 4 * MiB)
     s1 = store_of(plan, 0, u0)
-    plan.run([s1], 6)
-    plan.run([s1], 4)
+    plan.run([s1], 8)
+    plan.run([s1], 5)
     s2 = store_of(plan, 0, u0)
-    plan.run([s2], 10)
+    plan.run([s2], 13)
     assert torch.equal(s1, s2)
 
 
