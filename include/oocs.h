@@ -277,6 +277,12 @@ typedef struct {
  * oocs_stats.kernel_ms. */
 int oocs_plan_set_profiling(oocs_plan* plan, int on);
 
+/* Choose how oocs_run issues a residency (default 1): as one replay of a HIP
+ * graph built once per residency length and set of host stores (1), or op by
+ * op on the three streams with events (0). Both run the same kernels with the
+ * same parameters; graph replays of consecutive residencies do not overlap. */
+int oocs_plan_set_graphs(oocs_plan* plan, int on);
+
 /* Advance the out-of-core state held in the host stores h_store[field]
  * (one pointer per used field slot) by `steps` time steps, k per residency
  * (the last residency does steps mod k). The wave source adds h_src[s] at

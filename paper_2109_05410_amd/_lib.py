@@ -102,6 +102,7 @@ _SIGS = {
     "oocs_store_get": (C.c_int, [_P, C.c_int, _P, _P]),
     "oocs_run": (C.c_int, [_P, C.POINTER(_P), _I64, _P, C.POINTER(Stats)]),
     "oocs_plan_set_profiling": (C.c_int, [_P, C.c_int]),
+    "oocs_plan_set_graphs": (C.c_int, [_P, C.c_int]),
 }
 SYMBOLS = tuple(_SIGS)
 

@@ -265,3 +265,6 @@ class OutOfCorePlan:
 
     def set_profiling(self, on: bool):
         L.check(L.lib().oocs_plan_set_profiling(self._h, 1 if on else 0))
+
+    def set_graphs(self, on: bool):
+        L.check(L.lib().oocs_plan_set_graphs(self._h, 1 if on else 0))

@@ -8,10 +8,13 @@
 // launch, and the ordering edges as event records and waits. It makes no
 // device allocation and no synchronisation until the last residency has
 // been issued.
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -45,6 +48,15 @@ bool dims_ok4(int64_t nx, int64_t ny, int64_t nz) { return nx > 0 && ny > 0 && n
 
 }  // namespace
 
+// One residency's operation list built as a HIP graph (replayed once per
+// residency; graph launches on one stream run one after another, so the
+// waits that order a residency after the previous one are not needed inside).
+struct ResidencyGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> timing;  // start/end pairs around each kernel node (profiling)
+    int64_t launches = 0, codec_bytes = 0, stencil_bytes = 0, h2d = 0, d2h = 0;
+};
+
 struct oocs_plan {
     oocs::Planner P;
     char* arena = nullptr;
@@ -53,7 +65,10 @@ struct oocs_plan {
     hipStream_t st[3] = {nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> ev;  // 4*nstage logical + 2*n block events (two parities)
     bool profiling = false;
-    std::vector<hipEvent_t> tev;  // timing events, two per launch, grown on demand
+    bool graphs = true;
+    std::vector<hipEvent_t> tev;  // eager timing events, two per launch, grown on demand
+    // graphs by (residency length, store pointers, source on)
+    std::map<std::tuple<int, const void*, const void*, const void*, bool, bool>, ResidencyGraph> gcache;
 };
 
 extern "C" {
@@ -247,6 +262,11 @@ int oocs_plan_destroy(oocs_plan* pl)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : pl->tev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& kv : pl->gcache) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        for (hipEvent_t e : kv.second.timing)
+            if (e) (void)hipEventDestroy(e);
+    }
     for (hipStream_t s : pl->st)
         if (s) (void)hipStreamDestroy(s);
     delete pl;
@@ -406,6 +426,194 @@ static int64_t job_bytes(const oocs::Job& j, int64_t plane_elems)
     }
 }
 
+int oocs_plan_set_graphs(oocs_plan* pl, int on)
+{
+    if (!pl) return fail(OOCS_E_ARG, "null pointer");
+    if (!pl->runnable) return fail(OOCS_E_STATE, "planning-only plan");
+    pl->graphs = on != 0;
+    return OOCS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Translates the planner's copy and job ops into H2D/D2H transfers and
+// launch parameters; shared by the eager and the graph executors.
+struct OpTranslator {
+    oocs_plan* pl;
+    void* const* h_store;
+    bool src_on;
+    oocs::LaunchParams lp;
+
+    OpTranslator(oocs_plan* p, void* const* hs, bool src) : pl(p), h_store(hs), src_on(src)
+    {
+        const oocs::Planner& P = pl->P;
+        lp = base_params(P.nx, P.ny, P.nz, P.cfg.alpha, P.cfg.src_x, P.cfg.src_y, P.cfg.src_z);
+        if (src_on) {
+            lp.src_table = reinterpret_cast<const float*>(pl->arena + P.src_table_off);
+            lp.step_ctr = reinterpret_cast<const int32_t*>(pl->arena + P.step_ctr_off);
+        }
+    }
+    oocs::Ring ring(int idx) const
+    {
+        const oocs::Planner& P = pl->P;
+        return oocs::Ring{reinterpret_cast<float*>(pl->arena + P.ringOff[idx]), P.ringW[idx], P.plane_elems()};
+    }
+    // H2D / D2H of an op: device pointer, host pointer, bytes
+    void copy_args(const oocs_op& o, void** dev, void** host, size_t* bytes) const
+    {
+        const oocs::Planner& P = pl->P;
+        const int64_t spb = P.store_plane_bytes(o.field);
+        *bytes = (size_t)((o.z1 - o.z0) * spb);
+        *host = static_cast<char*>(h_store[o.field]) + o.z0 * spb;
+        *dev = o.kind == OOCS_OP_H2D ? pl->arena + P.in_off[o.field] + (int64_t)o.slot * P.in_slot_bytes[o.field]
+                                     : pl->arena + P.out_off[o.field] + (int64_t)o.slot * P.out_slot_bytes[o.field];
+    }
+    // Adds a decode/encode/level op to the pending launch; returns false on overflow.
+    bool add_job(const oocs_op& o)
+    {
+        const oocs::Planner& P = pl->P;
+        if (lp.njobs >= oocs::kMaxJobs) return false;
+        oocs::Job& j = lp.jobs[lp.njobs++];
+        std::memset(&j, 0, sizeof j);
+        j.z0 = (int32_t)o.z0;
+        j.z1 = (int32_t)o.z1;
+        if (o.kind == OOCS_OP_LEVEL) {
+            j.src = ring(o.level - 1);
+            j.dst = ring(o.level);
+            if (P.cfg.stencil == OOCS_HEAT7) {
+                j.kind = oocs::JOB_HEAT;
+            } else {
+                j.kind = oocs::JOB_WAVE;
+                j.src2 = ring(o.level - 2);
+                j.ro = ring(P.ro_ring());
+                j.has_src = src_on && lp.src_x >= 0 && lp.src_z >= o.z0 && lp.src_z < o.z1;
+                j.src_off = o.level - P.nin;  // step of this level within the residency
+            }
+        } else {
+            const bool dec = o.kind == OOCS_OP_DECODE;
+            const int rate = P.cfg.rate[o.field];
+            j.kind = rate ? (dec ? oocs::JOB_DECODE : oocs::JOB_ENCODE) : (dec ? oocs::JOB_COPY_IN : oocs::JOB_COPY_OUT);
+            j.rate = rate;
+            j.dst = ring(o.level);
+            j.stage = dec ? (void*)(pl->arena + P.in_off[o.field] + (int64_t)o.slot * P.in_slot_bytes[o.field])
+                          : (void*)(pl->arena + P.out_off[o.field] + (int64_t)o.slot * P.out_slot_bytes[o.field]);
+        }
+        return true;
+    }
+    void count_bytes(int64_t* codec, int64_t* stencil) const
+    {
+        for (int i = 0; i < lp.njobs; ++i)
+            (oocs::is_codec_job(lp.jobs[i].kind) ? *codec : *stencil) += job_bytes(lp.jobs[i], pl->P.plane_elems());
+    }
+};
+
+// Builds the graph of one residency of kr steps.
+int build_graph(oocs_plan* pl, int kr, void* const* h_store, bool src_on, ResidencyGraph& out)
+{
+    oocs::Planner& P = pl->P;
+    std::string err;
+    const oocs::Schedule* sch = P.schedule(kr, err);
+    if (!sch) return fail(OOCS_E_STATE, err);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipGraphCreate(&g, 0));
+    struct GraphGuard { hipGraph_t g; ~GraphGuard() { if (g) (void)hipGraphDestroy(g); } } guard{g};
+    hipGraphNode_t last[3] = {nullptr, nullptr, nullptr};
+    std::vector<hipGraphNode_t> pending[3];
+    std::map<int, hipGraphNode_t> rec;  // logical event -> node it stands for, recorded in this graph
+    auto deps_of = [&](int s) {
+        std::vector<hipGraphNode_t> d;
+        if (last[s]) d.push_back(last[s]);
+        for (hipGraphNode_t n : pending[s])
+            if (n && std::find(d.begin(), d.end(), n) == d.end()) d.push_back(n);
+        pending[s].clear();
+        return d;
+    };
+    OpTranslator tr(pl, h_store, src_on);
+    for (const oocs_op& o : sch->ops) {
+        switch (o.kind) {
+        case OOCS_OP_H2D:
+        case OOCS_OP_D2H: {
+            void *dev, *host;
+            size_t bytes;
+            tr.copy_args(o, &dev, &host, &bytes);
+            std::vector<hipGraphNode_t> d = deps_of(o.stream);
+            hipGraphNode_t n;
+            if (o.kind == OOCS_OP_H2D) {
+                HIP_TRY(hipGraphAddMemcpyNode1D(&n, g, d.data(), d.size(), dev, host, bytes, hipMemcpyHostToDevice));
+                out.h2d += (int64_t)bytes;
+            } else {
+                HIP_TRY(hipGraphAddMemcpyNode1D(&n, g, d.data(), d.size(), host, dev, bytes, hipMemcpyDeviceToHost));
+                out.d2h += (int64_t)bytes;
+            }
+            last[o.stream] = n;
+            break;
+        }
+        case OOCS_OP_DECODE:
+        case OOCS_OP_ENCODE:
+        case OOCS_OP_LEVEL:
+            if (!tr.add_job(o)) return fail(OOCS_E_STATE, "too many jobs in a tick");
+            break;
+        case OOCS_OP_LAUNCH: {
+            if (tr.lp.njobs == 0) break;
+            tr.count_bytes(&out.codec_bytes, &out.stencil_bytes);
+            std::vector<hipGraphNode_t> d = deps_of(1);
+            if (pl->profiling) {
+                hipEvent_t e0, e1;
+                HIP_TRY(hipEventCreate(&e0));
+                out.timing.push_back(e0);
+                HIP_TRY(hipEventCreate(&e1));
+                out.timing.push_back(e1);
+                hipGraphNode_t n0;
+                HIP_TRY(hipGraphAddEventRecordNode(&n0, g, d.data(), d.size(), e0));
+                d.assign(1, n0);
+            }
+            hipGraphNode_t n;
+            HIP_TRY(oocs::add_jobs_node(tr.lp, g, d.data(), d.size(), &n));
+            if (pl->profiling) {
+                hipGraphNode_t n1;
+                HIP_TRY(hipGraphAddEventRecordNode(&n1, g, &n, 1, out.timing.back()));
+                n = n1;
+            }
+            last[1] = n;
+            ++out.launches;
+            tr.lp.njobs = 0;
+            break;
+        }
+        case OOCS_OP_RECORD:
+            if (!pending[o.stream].empty()) {  // carry waits that no node has absorbed yet
+                std::vector<hipGraphNode_t> d = deps_of(o.stream);
+                hipGraphNode_t n;
+                HIP_TRY(hipGraphAddEmptyNode(&n, g, d.data(), d.size()));
+                last[o.stream] = n;
+            }
+            rec[o.event] = last[o.stream];
+            break;
+        case OOCS_OP_WAIT: {
+            auto it = rec.find(o.event);
+            if (it != rec.end() && it->second) pending[o.stream].push_back(it->second);
+            break;  // events of earlier residencies are complete before this graph starts
+        }
+        default:
+            return fail(OOCS_E_STATE, "unknown op");
+        }
+    }
+    if (src_on) {  // advance the source step counter after this residency's levels
+        std::vector<hipGraphNode_t> d = deps_of(1);
+        hipGraphNode_t n;
+        HIP_TRY(oocs::add_step_ctr_node(reinterpret_cast<int32_t*>(pl->arena + P.step_ctr_off), true, kr, g, d.data(),
+                                        d.size(), &n));
+        last[1] = n;
+    }
+    HIP_TRY(hipGraphInstantiate(&out.exec, g, nullptr, nullptr, 0));
+    return OOCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_src, oocs_stats* st)
 {
     if (!pl || !h_store || steps < 0) return fail(OOCS_E_ARG, "bad argument");
@@ -414,123 +622,135 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     for (int f : P.in_fields)
         if (!h_store[f]) return fail(OOCS_E_ARG, "missing host store pointer");
     const auto t_start = std::chrono::steady_clock::now();
-    const int64_t pe = P.plane_elems();
-    auto ring = [&](int idx) {
-        return oocs::Ring{reinterpret_cast<float*>(pl->arena + P.ringOff[idx]), P.ringW[idx], pe};
-    };
+    const bool src_on = h_src != nullptr && P.cfg.stencil == OOCS_WAVE25 && P.cfg.src_x >= 0 && P.cfg.src_x < P.nx &&
+                        P.cfg.src_y >= 0 && P.cfg.src_y < P.ny && P.cfg.src_z >= 0 && P.cfg.src_z < P.nz;
+    int32_t* step_ctr = src_on ? reinterpret_cast<int32_t*>(pl->arena + P.step_ctr_off) : nullptr;
+    float* src_table = src_on ? reinterpret_cast<float*>(pl->arena + P.src_table_off) : nullptr;
+    // the source table holds a whole number of residencies
+    const int64_t chunk_steps = src_on ? oocs::Planner::kSrcTable / P.k * P.k : steps;
     int64_t h2d = 0, d2h = 0, rounds = 0, launches = 0;
     int64_t kbytes[2] = {0, 0};  // codec jobs, stencil jobs
+    double kms = 0.0;
     size_t tused = 0;
     const int ns = P.nstage;
+
     int64_t done = 0;
     while (done < steps) {
-        const int kr = (int)std::min<int64_t>(P.k, steps - done);
-        std::string err;
-        const oocs::Schedule* sch = P.schedule(kr, err);
-        if (!sch) return fail(OOCS_E_STATE, err);
-        const int parity = (int)(rounds & 1);
-        auto phys = [&](int e) -> hipEvent_t {
-            if (e < 4 * ns) return pl->ev[e];
-            int i = e - 4 * ns;
-            const bool prev = i >= P.n;
-            if (prev) i -= P.n;
-            const int par = prev ? 1 - parity : parity;
-            return pl->ev[4 * ns + par * P.n + i];
-        };
-        oocs::LaunchParams lp = base_params(P.nx, P.ny, P.nz, P.cfg.alpha, P.cfg.src_x, P.cfg.src_y, P.cfg.src_z);
-        for (const oocs_op& o : sch->ops) {
-            switch (o.kind) {
-            case OOCS_OP_H2D: {
-                const int64_t spb = P.store_plane_bytes(o.field);
-                const size_t bytes = (size_t)((o.z1 - o.z0) * spb);
-                char* dst = pl->arena + P.in_off[o.field] + (int64_t)o.slot * P.in_slot_bytes[o.field];
-                const char* src = static_cast<const char*>(h_store[o.field]) + o.z0 * spb;
-                HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, pl->st[0]));
-                h2d += (int64_t)bytes;
-                break;
-            }
-            case OOCS_OP_D2H: {
-                const int64_t spb = P.store_plane_bytes(o.field);
-                const size_t bytes = (size_t)((o.z1 - o.z0) * spb);
-                const char* src = pl->arena + P.out_off[o.field] + (int64_t)o.slot * P.out_slot_bytes[o.field];
-                char* dst = static_cast<char*>(h_store[o.field]) + o.z0 * spb;
-                HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, pl->st[2]));
-                d2h += (int64_t)bytes;
-                break;
-            }
-            case OOCS_OP_DECODE:
-            case OOCS_OP_ENCODE: {
-                const int rate = P.cfg.rate[o.field];
-                if (lp.njobs >= oocs::kMaxJobs) return fail(OOCS_E_STATE, "too many jobs in a tick");
-                oocs::Job& j = lp.jobs[lp.njobs++];
-                std::memset(&j, 0, sizeof j);
-                const bool dec = o.kind == OOCS_OP_DECODE;
-                j.kind = rate ? (dec ? oocs::JOB_DECODE : oocs::JOB_ENCODE) : (dec ? oocs::JOB_COPY_IN : oocs::JOB_COPY_OUT);
-                j.z0 = (int32_t)o.z0; j.z1 = (int32_t)o.z1;
-                j.rate = rate;
-                j.dst = ring(o.level);
-                j.stage = dec ? (void*)(pl->arena + P.in_off[o.field] + (int64_t)o.slot * P.in_slot_bytes[o.field])
-                              : (void*)(pl->arena + P.out_off[o.field] + (int64_t)o.slot * P.out_slot_bytes[o.field]);
-                break;
-            }
-            case OOCS_OP_LEVEL: {
-                if (lp.njobs >= oocs::kMaxJobs) return fail(OOCS_E_STATE, "too many jobs in a tick");
-                oocs::Job& j = lp.jobs[lp.njobs++];
-                std::memset(&j, 0, sizeof j);
-                j.z0 = (int32_t)o.z0; j.z1 = (int32_t)o.z1;
-                j.src = ring(o.level - 1);
-                j.dst = ring(o.level);
-                if (P.cfg.stencil == OOCS_HEAT7) {
-                    j.kind = oocs::JOB_HEAT;
-                } else {
-                    j.kind = oocs::JOB_WAVE;
-                    j.src2 = ring(o.level - 2);
-                    j.ro = ring(P.ro_ring());
-                    const int64_t step = done + (o.level - P.nin);  // index of this step within the call
-                    j.has_src = h_src != nullptr && lp.src_x >= 0 && lp.src_z >= o.z0 && lp.src_z < o.z1;
-                    j.amp = h_src ? h_src[step] : 0.0f;
-                }
-                break;
-            }
-            case OOCS_OP_LAUNCH:
-                if (lp.njobs > 0) {
-                    for (int i = 0; i < lp.njobs; ++i)
-                        kbytes[oocs::is_codec_job(lp.jobs[i].kind) ? 0 : 1] += job_bytes(lp.jobs[i], pe);
-                    if (pl->profiling) {
-                        while (pl->tev.size() < tused + 2) {
-                            hipEvent_t e;
-                            HIP_TRY(hipEventCreate(&e));
-                            pl->tev.push_back(e);
-                        }
-                        HIP_TRY(hipEventRecord(pl->tev[tused], pl->st[1]));
-                    }
-                    HIP_TRY(oocs::launch_jobs(lp, pl->st[1]));
-                    if (pl->profiling) {
-                        HIP_TRY(hipEventRecord(pl->tev[tused + 1], pl->st[1]));
-                        tused += 2;
-                    }
-                    ++launches;
-                }
-                lp.njobs = 0;
-                break;
-            case OOCS_OP_RECORD:
-                HIP_TRY(hipEventRecord(phys(o.event), pl->st[o.stream]));
-                break;
-            case OOCS_OP_WAIT:
-                if (o.event >= P.ev_blk_prev(0) && rounds == 0) break;  // nothing written back yet in this call
-                HIP_TRY(hipStreamWaitEvent(pl->st[o.stream], phys(o.event), 0));
-                break;
-            default:
-                return fail(OOCS_E_STATE, "unknown op");
-            }
+        const int64_t chunk_end = std::min(steps, done + chunk_steps);
+        if (src_on) {  // amplitudes of this chunk, counter at 0
+            HIP_TRY(hipStreamSynchronize(pl->st[1]));
+            HIP_TRY(hipMemcpyAsync(src_table, h_src + done, (size_t)(chunk_end - done) * 4, hipMemcpyHostToDevice,
+                                   pl->st[1]));
+            HIP_TRY(oocs::launch_step_ctr(step_ctr, false, 0, pl->st[1]));
         }
-        done += kr;
-        ++rounds;
+        int64_t chunk_round = 0;
+        while (done < chunk_end) {
+            const int kr = (int)std::min<int64_t>(P.k, chunk_end - done);
+            std::string err;
+            const oocs::Schedule* sch = P.schedule(kr, err);
+            if (!sch) return fail(OOCS_E_STATE, err);
+            if (pl->graphs) {
+                auto key = std::make_tuple(kr, (const void*)h_store[0], (const void*)(P.nfields > 1 ? h_store[1] : nullptr),
+                                           (const void*)(P.nfields > 2 ? h_store[2] : nullptr), src_on, pl->profiling);
+                auto it = pl->gcache.find(key);
+                if (it == pl->gcache.end()) {
+                    ResidencyGraph rg;
+                    const int rc = build_graph(pl, kr, h_store, src_on, rg);
+                    if (rc != OOCS_OK) {
+                        if (rg.exec) (void)hipGraphExecDestroy(rg.exec);
+                        for (hipEvent_t e : rg.timing) (void)hipEventDestroy(e);
+                        return rc;
+                    }
+                    it = pl->gcache.emplace(key, std::move(rg)).first;
+                }
+                ResidencyGraph& rg = it->second;
+                HIP_TRY(hipGraphLaunch(rg.exec, pl->st[1]));
+                h2d += rg.h2d;
+                d2h += rg.d2h;
+                launches += rg.launches;
+                kbytes[0] += rg.codec_bytes;
+                kbytes[1] += rg.stencil_bytes;
+                if (pl->profiling) {  // the timing events hold this replay's times once it completes
+                    HIP_TRY(hipStreamSynchronize(pl->st[1]));
+                    for (size_t i = 0; i + 1 < rg.timing.size(); i += 2) {
+                        float ms = 0.0f;
+                        HIP_TRY(hipEventElapsedTime(&ms, rg.timing[i], rg.timing[i + 1]));
+                        kms += ms;
+                    }
+                }
+            } else {
+                const int parity = (int)(rounds & 1);
+                auto phys = [&](int e) -> hipEvent_t {
+                    if (e < 4 * ns) return pl->ev[e];
+                    int i = e - 4 * ns;
+                    const bool prev = i >= P.n;
+                    if (prev) i -= P.n;
+                    const int par = prev ? 1 - parity : parity;
+                    return pl->ev[4 * ns + par * P.n + i];
+                };
+                OpTranslator tr(pl, h_store, src_on);
+                for (const oocs_op& o : sch->ops) {
+                    switch (o.kind) {
+                    case OOCS_OP_H2D:
+                    case OOCS_OP_D2H: {
+                        void *dev, *host;
+                        size_t bytes;
+                        tr.copy_args(o, &dev, &host, &bytes);
+                        if (o.kind == OOCS_OP_H2D) {
+                            HIP_TRY(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, pl->st[0]));
+                            h2d += (int64_t)bytes;
+                        } else {
+                            HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, pl->st[2]));
+                            d2h += (int64_t)bytes;
+                        }
+                        break;
+                    }
+                    case OOCS_OP_DECODE:
+                    case OOCS_OP_ENCODE:
+                    case OOCS_OP_LEVEL:
+                        if (!tr.add_job(o)) return fail(OOCS_E_STATE, "too many jobs in a tick");
+                        break;
+                    case OOCS_OP_LAUNCH:
+                        if (tr.lp.njobs > 0) {
+                            tr.count_bytes(&kbytes[0], &kbytes[1]);
+                            if (pl->profiling) {
+                                while (pl->tev.size() < tused + 2) {
+                                    hipEvent_t e;
+                                    HIP_TRY(hipEventCreate(&e));
+                                    pl->tev.push_back(e);
+                                }
+                                HIP_TRY(hipEventRecord(pl->tev[tused], pl->st[1]));
+                            }
+                            HIP_TRY(oocs::launch_jobs(tr.lp, pl->st[1]));
+                            if (pl->profiling) {
+                                HIP_TRY(hipEventRecord(pl->tev[tused + 1], pl->st[1]));
+                                tused += 2;
+                            }
+                            ++launches;
+                        }
+                        tr.lp.njobs = 0;
+                        break;
+                    case OOCS_OP_RECORD:
+                        HIP_TRY(hipEventRecord(phys(o.event), pl->st[o.stream]));
+                        break;
+                    case OOCS_OP_WAIT:
+                        if (o.event >= P.ev_blk_prev(0) && chunk_round == 0 && rounds == 0) break;
+                        HIP_TRY(hipStreamWaitEvent(pl->st[o.stream], phys(o.event), 0));
+                        break;
+                    default:
+                        return fail(OOCS_E_STATE, "unknown op");
+                    }
+                }
+                if (src_on) HIP_TRY(oocs::launch_step_ctr(step_ctr, true, kr, pl->st[1]));
+            }
+            done += kr;
+            ++rounds;
+            ++chunk_round;
+        }
     }
     const double enq = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     for (int i = 0; i < 3; ++i) HIP_TRY(hipStreamSynchronize(pl->st[i]));
     const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    double kms = 0.0;
     for (size_t i = 0; i + 1 < tused; i += 2) {
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, pl->tev[i], pl->tev[i + 1]));

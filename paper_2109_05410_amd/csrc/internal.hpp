@@ -39,10 +39,10 @@ struct Job {
     int32_t kind;
     int32_t z0, z1;
     int32_t rate;      // codec jobs
-    int32_t has_src;   // wave: add `amp` at the source cell
-    float amp;
+    int32_t has_src;   // wave: add the source amplitude at the source cell
+    float amp;         // the amplitude when LaunchParams::src_table is null
+    int32_t src_off;   // else the amplitude is src_table[*step_ctr + src_off]
     int32_t wg_count;  // workgroups of this job
-    int32_t pad;
     Ring src, src2, ro, dst;  // stencil jobs (dst doubles as `ring` for codec/copy jobs)
     void* stage;              // codec/copy jobs
 };
@@ -58,6 +58,8 @@ struct LaunchParams {
     float alpha;
     int32_t src_x, src_y, src_z;
     int32_t njobs;
+    const float* src_table;    // wave source amplitudes of the current run chunk (device), or null
+    const int32_t* step_ctr;   // device counter: steps done in the chunk before this residency
     int32_t wg_begin[kMaxJobs + 1];  // prefix sums of wg_count
     Job jobs[kMaxJobs];
 };
@@ -71,6 +73,16 @@ bool is_codec_job(int kind);
 // Launch the fused kernel for the jobs in p (reorders p.jobs so that codec
 // jobs come first; fills p.wg_begin).
 hipError_t launch_jobs(LaunchParams& p, hipStream_t stream);
+
+// The same launch as a kernel node of graph g after `deps` (node left in *node;
+// no node and hipSuccess if there is no work).
+hipError_t add_jobs_node(LaunchParams& p, hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node);
+
+// Device step counter of the wave source table: set to `value` (add = false)
+// or advanced by `value` (add = true); as a launch or as a graph node.
+hipError_t launch_step_ctr(int32_t* ctr, bool add, int32_t value, hipStream_t stream);
+hipError_t add_step_ctr_node(int32_t* ctr, bool add, int32_t value, hipGraph_t g, const hipGraphNode_t* deps,
+                             size_t ndeps, hipGraphNode_t* node);
 
 // Standalone codec launches on dense (non-ring) fields.
 hipError_t launch_codec_field(bool encode, const float* in_f, float* out_f, const uint64_t* in_w, uint64_t* out_w,

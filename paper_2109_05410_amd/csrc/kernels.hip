@@ -118,7 +118,9 @@ __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
     case JOB_DECODE: codec_job(j, p.nx, p.ny, local, false); break;
     case JOB_ENCODE: codec_job(j, p.nx, p.ny, local, true); break;
     case JOB_HEAT: stencil::heat_level(j, p.nx, p.ny, p.nz, p.alpha, local); break;
-    case JOB_WAVE: stencil::wave_level(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, local); break;
+    case JOB_WAVE:
+        stencil::wave_level(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local);
+        break;
     case JOB_COPY_IN: copy_job(j, p.nx, p.ny, local, true); break;
     case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
     default: break;
@@ -137,7 +139,9 @@ __global__ void __launch_bounds__(kBlockThreads) stencil_kernel(LaunchParams p)
     const int local = wg - p.wg_begin[jdx];
     switch (j.kind) {
     case JOB_HEAT: stencil::heat_level(j, p.nx, p.ny, p.nz, p.alpha, local); break;
-    case JOB_WAVE: stencil::wave_level(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, local); break;
+    case JOB_WAVE:
+        stencil::wave_level(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local);
+        break;
     case JOB_COPY_IN: copy_job(j, p.nx, p.ny, local, true); break;
     case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
     default: break;
@@ -172,9 +176,10 @@ int32_t job_workgroups(const Job& j, int nx, int ny)
     }
 }
 
-hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
+// Orders the jobs (codec first), fills the workgroup prefix sums and picks
+// the kernel. Returns false if there is no work.
+static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, size_t* lds)
 {
-    // codec jobs first (stable order otherwise)
     Job sorted[kMaxJobs];
     int n = 0;
     for (int pass = 0; pass < 2; ++pass)
@@ -190,14 +195,73 @@ hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
         if (is_codec_job(p.jobs[i].kind)) max_rate = max(max_rate, p.jobs[i].rate);
     }
     p.wg_begin[p.njobs] = total;
-    if (total == 0) return hipSuccess;
+    if (total == 0) return false;
+    *grid = (unsigned)total;
     if (max_rate > 0) {
-        const size_t lds = (size_t)kWavesPerWG * 64 * max_rate * sizeof(uint64_t);
-        hipLaunchKernelGGL(fused_kernel, dim3((unsigned)total), dim3(kBlockThreads), lds, stream, p);
+        *func = reinterpret_cast<const void*>(&fused_kernel);
+        *lds = (size_t)kWavesPerWG * 64 * max_rate * sizeof(uint64_t);
     } else {
-        hipLaunchKernelGGL(stencil_kernel, dim3((unsigned)total), dim3(kBlockThreads), 0, stream, p);
+        *func = reinterpret_cast<const void*>(&stencil_kernel);
+        *lds = 0;
     }
+    return true;
+}
+
+hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
+{
+    const void* func;
+    unsigned grid;
+    size_t lds;
+    if (!prepare_jobs(p, &func, &grid, &lds)) return hipSuccess;
+    if (func == reinterpret_cast<const void*>(&fused_kernel))
+        hipLaunchKernelGGL(fused_kernel, dim3(grid), dim3(kBlockThreads), lds, stream, p);
+    else
+        hipLaunchKernelGGL(stencil_kernel, dim3(grid), dim3(kBlockThreads), 0, stream, p);
     return hipGetLastError();
+}
+
+hipError_t add_jobs_node(LaunchParams& p, hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node)
+{
+    const void* func;
+    unsigned grid;
+    size_t lds;
+    *node = nullptr;
+    if (!prepare_jobs(p, &func, &grid, &lds)) return hipSuccess;
+    void* args[] = {&p};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(func);
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(kBlockThreads);
+    kp.sharedMemBytes = (unsigned)lds;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, deps, ndeps, &kp);
+}
+
+__global__ void step_ctr_kernel(int32_t* ctr, int add, int32_t value)
+{
+    if (threadIdx.x == 0) *ctr = add ? *ctr + value : value;
+}
+
+hipError_t launch_step_ctr(int32_t* ctr, bool add, int32_t value, hipStream_t stream)
+{
+    hipLaunchKernelGGL(step_ctr_kernel, dim3(1), dim3(64), 0, stream, ctr, add ? 1 : 0, value);
+    return hipGetLastError();
+}
+
+hipError_t add_step_ctr_node(int32_t* ctr, bool add, int32_t value, hipGraph_t g, const hipGraphNode_t* deps,
+                             size_t ndeps, hipGraphNode_t* node)
+{
+    int a = add ? 1 : 0;
+    void* args[] = {&ctr, &a, &value};
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void*>(&step_ctr_kernel);
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, deps, ndeps, &kp);
 }
 
 // ---------------------------------------------------------------------------

@@ -239,6 +239,13 @@ int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
         out_off[fld] = off;
         off += out_slot_bytes[fld] * nstage;
     }
+    src_table_off = step_ctr_off = -1;
+    if (cfg.stencil == OOCS_WAVE25) {
+        src_table_off = off;
+        off += kSrcTable * 4;
+        step_ctr_off = off;
+        off += 256;
+    }
     arena_needed = off;
     return off;
 }

@@ -96,6 +96,9 @@ public:
     int64_t in_slot_bytes[OOCS_MAX_FIELDS] = {0, 0, 0}, in_off[OOCS_MAX_FIELDS] = {0, 0, 0};
     int64_t out_slot_bytes[OOCS_MAX_FIELDS] = {0, 0, 0}, out_off[OOCS_MAX_FIELDS] = {0, 0, 0};
     int64_t arena_needed = 0;
+    // wave source: amplitudes of up to kSrcTable steps and the device step counter
+    static constexpr int64_t kSrcTable = 65536;
+    int64_t src_table_off = -1, step_ctr_off = -1;
 
     // event ids used by the op lists
     int ev_loaded(int s) const { return s; }

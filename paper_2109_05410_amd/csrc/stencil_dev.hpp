@@ -57,7 +57,8 @@ __device__ inline void heat_level(const Job& j, int nx, int ny, int nz, float al
 // Wave, 25 points:
 //   acc = C0X3*p;  for m = 1..4: acc = acc + C_m * (((x+m + x-m) + (y+m + y-m)) + (z+m + z-m))
 //   p'  = (2p - pm) + w*acc  (+ amp at the source cell)
-__device__ inline void wave_level(const Job& j, int nx, int ny, int nz, int sx, int sy, int sz, int wg)
+__device__ inline void wave_level(const Job& j, int nx, int ny, int nz, int sx, int sy, int sz,
+                                  const float* src_table, const int32_t* step_ctr, int wg)
 {
     const float C0X3 = (float)(-205.0 / 24.0);
     const float C1 = (float)(8.0 / 5.0);
@@ -91,7 +92,7 @@ __device__ inline void wave_level(const Job& j, int nx, int ny, int nz, int sx, 
         const float pm = ring_plane(j.src2, z)[xy];
         const float w = ring_plane(j.ro, z)[xy];
         float v = (2.0f * q4 - pm) + w * acc;
-        if (src_col && z == sz) v = v + j.amp;
+        if (src_col && z == sz) v = v + (src_table ? src_table[*step_ctr + j.src_off] : j.amp);
         ring_plane(j.dst, z)[xy] = v;
         q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7; q7 = q8;
     }

@@ -34,15 +34,17 @@ def decoded(store, shape, rate):
     return b.view(np.float32).reshape(shape).copy()
 
 
+@pytest.mark.parametrize("graphs", [True, False], ids=["graph", "eager"])
 @pytest.mark.parametrize("rate,k,steps,n,arena", [
     (0, 4, 10, 8, 2 * MiB), (8, 4, 10, 8, 2 * MiB), (16, 4, 9, 4, 3 * MiB), (5, 4, 7, 2, 64 * MiB),
     (0, 3, 8, 4, 2 * MiB),
     (12, 4, 12, 1, 2 * MiB),
 ])
-def test_heat_out_of_core_matches_replay(rate, k, steps, n, arena):
+def test_heat_out_of_core_matches_replay(rate, k, steps, n, arena, graphs):
     shape = (128, 64, 64)
     u0 = inputs.heat_uniform(shape, seed=rate + k)
     plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena)
+    plan.set_graphs(graphs)
     s = store_of(plan, 0, u0)
     plan.run([s], steps)
     got = decoded(s, shape, rate)
@@ -53,9 +55,10 @@ def test_heat_out_of_core_matches_replay(rate, k, steps, n, arena):
         assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= 1e-5
 
 
+@pytest.mark.parametrize("graphs", [True, False], ids=["graph", "eager"])
 @pytest.mark.parametrize("rates,k,steps", [([0, 0, 0], 4, 10), ([8, 12, 8], 4, 10), ([16, 16, 16], 3, 7),
                                            ([12, 0, 12], 1, 3)])
-def test_wave_out_of_core_matches_replay(rates, k, steps):
+def test_wave_out_of_core_matches_replay(rates, k, steps, graphs):
     shape = (96, 36, 40)
     rng = np.random.default_rng(k)
     p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
@@ -64,6 +67,7 @@ def test_wave_out_of_core_matches_replay(rates, k, steps):
     amps = rng.standard_normal(steps).astype(np.float32)
     cell = (17, 20, 50)
     plan = api.OutOfCorePlan(shape, api.WAVE25, 2, k, rates, 16 * MiB, src_cell=cell)
+    plan.set_graphs(graphs)
     st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
     plan.run(st, steps, src_amps=amps)
     nz, ny, nx = shape
@@ -88,6 +92,43 @@ def test_repeated_runs_continue_the_state():
     s2 = store_of(plan, 0, u0)
     plan.run([s2], 13)
     assert torch.equal(s1, s2)
+
+
+def test_graph_replays_with_profiling_match_eager():
+    """Graph replays (several residencies of each length, profiling timing
+    nodes included) give the same store as op-by-op issue."""
+    shape = (64, 32, 32)
+    u0 = inputs.heat_uniform(shape, seed=4)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, 4, 4, [8], 4 * MiB)
+    a = store_of(plan, 0, u0)
+    b = store_of(plan, 0, u0)
+    plan.set_profiling(True)
+    st = plan.run([a], 14)
+    assert st.kernel_ms > 0 and st.launches > 0
+    plan.set_profiling(False)
+    plan.set_graphs(False)
+    plan.run([b], 14)
+    assert torch.equal(a, b)
+
+
+def test_wave_source_longer_than_the_source_table():
+    """Runs longer than the device amplitude table are split into chunks of
+    whole residencies; the source timing stays exact."""
+    from paper_2109_05410_amd import _lib as L  # noqa: F401
+    shape = (16, 8, 8)
+    steps, k = 65536 + 9, 3
+    rng = np.random.default_rng(0)
+    w = np.full(shape, 0.05, np.float32)
+    amps = rng.standard_normal(steps).astype(np.float32) * 1e-3
+    cell = (3, 4, 7)
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 1, k, [0, 0, 0], 16 * MiB, src_cell=cell)
+    z = np.zeros(shape, np.float32)
+    st = [store_of(plan, 0, z), store_of(plan, 1, z), store_of(plan, 2, w)]
+    plan.run(st, steps, src_amps=amps)
+    p = torch.zeros(shape, device=DEV)
+    pm = torch.zeros(shape, device=DEV)
+    api.wave25_step_k(p, pm, torch.from_numpy(w).to(DEV), steps, src=(amps, cell))
+    assert np.array_equal(decoded(st[0], shape, 0), p.cpu().numpy())
 
 
 def test_deterministic():

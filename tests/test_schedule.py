@@ -165,7 +165,10 @@ def accesses(o, g):
     return out
 
 
-def race_check(p: OutOfCorePlan, steps: int):
+def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
+    """graph_mode: each residency is one graph replay, so everything of the
+    previous residency is complete before it starts, and only edges recorded
+    inside the residency order its own work."""
     g = Geometry(p)
     ns, n = g.nstage, g.nslabs
     vc = [[0, 0, 0] for _ in range(3)]
@@ -201,6 +204,11 @@ def race_check(p: OutOfCorePlan, steps: int):
     while done < steps:
         kr = min(g.k, steps - done)
         par = rnd % 2
+        if graph_mode:
+            vc = [[0, 0, 0] for _ in range(3)]
+            ev_clock.clear()
+            last_write.clear()
+            reads.clear()
 
         def phys(e):
             if e < 4 * ns:
@@ -217,7 +225,7 @@ def race_check(p: OutOfCorePlan, steps: int):
             if K == L.OP_RECORD:
                 ev_clock[phys(o["event"])] = list(vc[s])
             elif K == L.OP_WAIT:
-                if o["event"] >= 4 * ns + n and rnd == 0:
+                if o["event"] >= 4 * ns + n and (rnd == 0 or graph_mode):
                     continue
                 c = ev_clock.get(phys(o["event"]))
                 if c is not None:
@@ -262,10 +270,13 @@ def race_check(p: OutOfCorePlan, steps: int):
 def test_schedule_has_no_races(shape, st, n, k, rates, arena, steps):
     p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None)
     race_check(p, steps)
+    race_check(p, steps, graph_mode=True)
 
 
 def test_full_size_heat_schedule_has_no_races():
-    race_check(plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB), 12)
+    p = plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB)
+    race_check(p, 12)
+    race_check(p, 12, graph_mode=True)
 
 
 # ---------------------------------------------------------------------------
