@@ -53,6 +53,11 @@ def lib() -> C.CDLL:
         L.orc_code_ints.argtypes = [P, l, P]
         L.orc_code_ints.restype = C.c_long
         L.orc_decode_ints.argtypes = [P, l, P]
+        L.orc_wave_forward_states_f64.argtypes = [P, l, l, l, l, P, l, P, l, P, P]
+        L.orc_wave_adjoint_f64.argtypes = [P, l, l, l, l, P, l, P, P, P, l, P]
+        L.orc_wave_misfit_grad_f64.argtypes = [P, l, l, l, l, P, l, P, l, P, P, P]
+        L.orc_wave_forward_states_f32.argtypes = [P, l, l, l, l, P, l, P, l, P, P]
+        L.orc_wave_adjoint_f32.argtypes = [P, l, l, l, l, P, l, P, P, P, l, P]
         L.orc_replay_heat_f32.argtypes = [P, l, l, l, C.c_float, l, l, C.c_int]
         L.orc_replay_heat_f64.argtypes = [P, l, l, l, C.c_double, l, l, C.c_int]
         L.orc_replay_wave_f32.argtypes = [P, P, P, l, l, l, l, l, P, l, C.c_int, C.c_int, C.c_int]
@@ -291,6 +296,57 @@ def replay_wave_f64(p0, pm0, w0, steps, k, src=None, rate_p=0, rate_pm=0, rate_w
     _check(lib().orc_replay_wave_f64(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), int(k), ap, idx,
                                      int(rate_p), int(rate_pm), int(rate_w)), "replay_wave_f64")
     return p, pm, w
+
+
+# --------------------------------------------------------------------------
+# Misfit gradient by the discrete adjoint (see oracle.c for the recursion)
+# --------------------------------------------------------------------------
+
+def _rcv_array(rcv):
+    return np.ascontiguousarray(rcv, dtype=np.int64)
+
+
+def wave_forward_states(w, T, src, rcv, dtype=np.float64):
+    """All states p_0..p_T (shape (T+1, nz, ny, nx)) and receiver records
+    (T, nr) of the forward run from rest. src = (amplitudes[T], flat index)."""
+    w = np.ascontiguousarray(w, dtype=dtype)
+    r = _rcv_array(rcv)
+    a, idx, ap = _src_args(src, dtype, T)
+    states = np.zeros((T + 1,) + w.shape, dtype=dtype)
+    rec = np.zeros((T, r.size), dtype=dtype)
+    fn = lib().orc_wave_forward_states_f64 if dtype == np.float64 else lib().orc_wave_forward_states_f32
+    _check(fn(_ptr(w), *_dims(w), int(T), ap, idx, _ptr(r), r.size, _ptr(rec), _ptr(states)), "wave_forward_states")
+    return states, rec
+
+
+def wave_adjoint(w, T, rcv, res, states=None, src_index=-1, dtype=np.float64):
+    """Adjoint run driven by residuals res (T, nr). Returns (grad or None,
+    src_adj or None): grad = sum_t lam_t . L p_{t-1} (needs states),
+    src_adj[t] = lam_{t+1} at src_index."""
+    w = np.ascontiguousarray(w, dtype=dtype)
+    r = _rcv_array(rcv)
+    res = np.ascontiguousarray(res, dtype=dtype)
+    grad = np.zeros(w.shape, dtype=dtype) if states is not None else None
+    sadj = np.zeros(T, dtype=dtype) if src_index >= 0 else None
+    st = np.ascontiguousarray(states, dtype=dtype) if states is not None else None
+    fn = lib().orc_wave_adjoint_f64 if dtype == np.float64 else lib().orc_wave_adjoint_f32
+    _check(fn(_ptr(w), *_dims(w), int(T), _ptr(r), r.size, _ptr(res), _ptr(st) if st is not None else None,
+              _ptr(grad) if grad is not None else None, int(src_index), _ptr(sadj) if sadj is not None else None),
+           "wave_adjoint")
+    return grad, sadj
+
+
+def wave_misfit_grad_f64(w, T, src, rcv, d):
+    """J = 1/2 sum |r_t - d_t|^2 and dJ/dw (FP64)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    r = _rcv_array(rcv)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    a, idx, ap = _src_args(src, np.float64, T)
+    grad = np.zeros(w.shape)
+    J = C.c_double(0.0)
+    _check(lib().orc_wave_misfit_grad_f64(_ptr(w), *_dims(w), int(T), ap, idx, _ptr(r), r.size, _ptr(d),
+                                          C.byref(J), _ptr(grad)), "wave_misfit_grad_f64")
+    return J.value, grad
 
 
 # --------------------------------------------------------------------------

@@ -662,3 +662,203 @@ int orc_decode_ints(const uint64_t* in, long budget, uint32_t* u64)
     decode_planes(u64, budget, &s, NULL);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Misfit gradient of the wave propagator by the discrete adjoint.          */
+/*                                                                          */
+/* Forward (p_0 = p_-1 = 0):  p_{t+1} = 2 p_t - p_{t-1} + w . L p_t + s_t   */
+/* at the source cell, t = 0..T-1. Receivers record r_t = p_t at nr cells,  */
+/* t = 1..T; J = 1/2 sum_t |r_t - d_t|^2.                                   */
+/* Stationarity of the Lagrangian with one multiplier per step gives, with  */
+/* lam_{T+1} = lam_{T+2} = 0 and L symmetric under zero ghosts:             */
+/*   lam_t = 2 lam_{t+1} - lam_{t+2} + L (w . lam_{t+1}) + res_t at rcvs    */
+/*   dJ/dw = sum_{t=1..T} lam_t . L p_{t-1},   res_t = r_t - d_t.           */
+/* Every forward state is kept (small grids only).                          */
+/* ------------------------------------------------------------------------ */
+
+static double lap_at_f64(const double* p, long i, long j, long l, long nx, long ny, long nz)
+{
+    double acc = W_C0X3 * at_f64(p, i, j, l, nx, ny, nz);
+    for (int m = 1; m <= 4; ++m) {
+        double sm = (at_f64(p, i + m, j, l, nx, ny, nz) + at_f64(p, i - m, j, l, nx, ny, nz))
+                  + (at_f64(p, i, j + m, l, nx, ny, nz) + at_f64(p, i, j - m, l, nx, ny, nz));
+        sm = sm + (at_f64(p, i, j, l + m, nx, ny, nz) + at_f64(p, i, j, l - m, nx, ny, nz));
+        acc = acc + W_C[m] * sm;
+    }
+    return acc;
+}
+
+/* L (w . lam) at one cell, FP64 */
+static double lapw_at_f64(const double* lam, const double* w, long i, long j, long l, long nx, long ny, long nz)
+{
+#define WL(a, b, c) (at_f64(w, a, b, c, nx, ny, nz) * at_f64(lam, a, b, c, nx, ny, nz))
+    double acc = W_C0X3 * WL(i, j, l);
+    for (int m = 1; m <= 4; ++m) {
+        double sm = (WL(i + m, j, l) + WL(i - m, j, l)) + (WL(i, j + m, l) + WL(i, j - m, l));
+        sm = sm + (WL(i, j, l + m) + WL(i, j, l - m));
+        acc = acc + W_C[m] * sm;
+    }
+    return acc;
+#undef WL
+}
+
+/* Forward run keeping every state: states[(t)*n + c] = p_t, t = 0..T.
+ * records[(t-1)*nr + i] = p_t at rcv[i], t = 1..T. */
+int orc_wave_forward_states_f64(const double* w, long nx, long ny, long nz, long T, const double* src, long src_index,
+                                const long* rcv, long nr, double* records, double* states)
+{
+    size_t n = (size_t)nx * ny * nz;
+    double* pm = (double*)calloc(n, sizeof(double));
+    double* p = (double*)calloc(n, sizeof(double));
+    if (!pm || !p) { free(pm); free(p); return -1; }
+    memcpy(states, p, n * sizeof(double));
+    for (long t = 0; t < T; ++t) {
+        int rc = orc_wave25_f64(p, pm, w, nx, ny, nz, 1, src ? src + t : NULL, src_index);
+        if (rc) { free(pm); free(p); return rc; }
+        memcpy(states + (size_t)(t + 1) * n, p, n * sizeof(double));
+        for (long i = 0; i < nr; ++i) records[t * nr + i] = p[rcv[i]];
+    }
+    free(pm);
+    free(p);
+    return 0;
+}
+
+/* Adjoint run driven by the receiver residual series res (T x nr, row t-1
+ * for time t). If states != NULL, accumulates grad (n values, overwritten)
+ * = sum_t lam_t . L p_{t-1}. If src_adj != NULL, src_adj[t] = lam_{t+1} at
+ * src_index for t = 0..T-1 (the transpose of source -> receivers). */
+int orc_wave_adjoint_f64(const double* w, long nx, long ny, long nz, long T, const long* rcv, long nr,
+                         const double* res, const double* states, double* grad, long src_index, double* src_adj)
+{
+    size_t n = (size_t)nx * ny * nz;
+    double* l1 = (double*)calloc(n, sizeof(double)); /* lam_{t+1} */
+    double* l2 = (double*)calloc(n, sizeof(double)); /* lam_{t+2} */
+    double* l0 = (double*)calloc(n, sizeof(double)); /* lam_t */
+    if (!l1 || !l2 || !l0) { free(l1); free(l2); free(l0); return -1; }
+    if (grad) memset(grad, 0, n * sizeof(double));
+    for (long t = T; t >= 1; --t) {
+#pragma omp parallel for schedule(static)
+        for (long l = 0; l < nz; ++l)
+            for (long j = 0; j < ny; ++j)
+                for (long i = 0; i < nx; ++i) {
+                    size_t c = IDX(i, j, l, nx, ny);
+                    l0[c] = (2.0 * l1[c] - l2[c]) + lapw_at_f64(l1, w, i, j, l, nx, ny, nz);
+                }
+        for (long i = 0; i < nr; ++i) l0[rcv[i]] = l0[rcv[i]] + res[(t - 1) * nr + i];
+        if (grad && states) {
+            const double* pt = states + (size_t)(t - 1) * n;
+#pragma omp parallel for schedule(static)
+            for (long l = 0; l < nz; ++l)
+                for (long j = 0; j < ny; ++j)
+                    for (long i = 0; i < nx; ++i) {
+                        size_t c = IDX(i, j, l, nx, ny);
+                        grad[c] += l0[c] * lap_at_f64(pt, i, j, l, nx, ny, nz);
+                    }
+        }
+        if (src_adj) src_adj[t - 1] = l0[src_index];
+        double* tmp = l2; l2 = l1; l1 = l0; l0 = tmp;
+    }
+    free(l1);
+    free(l2);
+    free(l0);
+    return 0;
+}
+
+/* J and dJ/dw for observed records d (T x nr). */
+int orc_wave_misfit_grad_f64(const double* w, long nx, long ny, long nz, long T, const double* src, long src_index,
+                             const long* rcv, long nr, const double* d, double* J, double* grad)
+{
+    size_t n = (size_t)nx * ny * nz;
+    double* states = (double*)malloc((size_t)(T + 1) * n * sizeof(double));
+    double* rec = (double*)malloc((size_t)T * nr * sizeof(double));
+    if (!states || !rec) { free(states); free(rec); return -1; }
+    int rc = orc_wave_forward_states_f64(w, nx, ny, nz, T, src, src_index, rcv, nr, rec, states);
+    double j = 0.0;
+    for (long q = 0; q < T * nr; ++q) {
+        rec[q] -= d[q];
+        j += rec[q] * rec[q];
+    }
+    *J = 0.5 * j;
+    if (rc == 0 && grad) rc = orc_wave_adjoint_f64(w, nx, ny, nz, T, rcv, nr, rec, states, grad, 0, NULL);
+    free(states);
+    free(rec);
+    return rc;
+}
+
+/* FP32 adjoint in a fixed operation order. Iteration t = T..1:
+ *   lam_t = (2*lam1 - lam2) + accw,  accw = C0X3*(w*lam1) + sum_m C_m*(((wl[x+m] + wl[x-m]) +
+ *           (wl[y+m] + wl[y-m])) + (wl[z+m] + wl[z-m])), wl[q] = w[q]*lam1[q]
+ *   grad  = grad + lam1 * Lp_t (lam1 = lam_{t+1} after its receiver injection,
+ *           Lp_t in the forward order)
+ *   then lam_t = lam_t + res_t at each receiver, in receiver order.
+ * Forward states come from the FP32 forward (orc_wave25_f32 order). res is
+ * given (T x nr, FP32). src_adj optional as in the FP64 version. */
+static float at32(const float* u, long i, long j, long l, long nx, long ny, long nz) { return at_f32(u, i, j, l, nx, ny, nz); }
+
+int orc_wave_adjoint_f32(const float* w, long nx, long ny, long nz, long T, const long* rcv, long nr,
+                         const float* res, const float* states, float* grad, long src_index, float* src_adj)
+{
+    const float c0x3 = (float)(-205.0 / 24.0);
+    const float cm[5] = {0.0f, (float)(8.0 / 5.0), (float)(-1.0 / 5.0), (float)(8.0 / 315.0), (float)(-1.0 / 560.0)};
+    size_t n = (size_t)nx * ny * nz;
+    float* l1 = (float*)calloc(n, sizeof(float));
+    float* l2 = (float*)calloc(n, sizeof(float));
+    float* l0 = (float*)calloc(n, sizeof(float));
+    if (!l1 || !l2 || !l0) { free(l1); free(l2); free(l0); return -1; }
+    if (grad) memset(grad, 0, n * sizeof(float));
+    for (long t = T; t >= 1; --t) {
+        const float* pt = states ? states + (size_t)t * n : NULL;
+#pragma omp parallel for schedule(static)
+        for (long l = 0; l < nz; ++l)
+            for (long j = 0; j < ny; ++j)
+                for (long i = 0; i < nx; ++i) {
+                    size_t c = IDX(i, j, l, nx, ny);
+#define WL(a, b, e) (at32(w, a, b, e, nx, ny, nz) * at32(l1, a, b, e, nx, ny, nz))
+                    float acc = c0x3 * WL(i, j, l);
+                    for (int m = 1; m <= 4; ++m) {
+                        float sm = (WL(i + m, j, l) + WL(i - m, j, l)) + (WL(i, j + m, l) + WL(i, j - m, l));
+                        sm = sm + (WL(i, j, l + m) + WL(i, j, l - m));
+                        acc = acc + cm[m] * sm;
+                    }
+#undef WL
+                    l0[c] = (2.0f * l1[c] - l2[c]) + acc;
+                    if (grad && pt) {
+                        float lp = c0x3 * pt[c];
+                        for (int m = 1; m <= 4; ++m) {
+                            float sm = (at32(pt, i + m, j, l, nx, ny, nz) + at32(pt, i - m, j, l, nx, ny, nz))
+                                     + (at32(pt, i, j + m, l, nx, ny, nz) + at32(pt, i, j - m, l, nx, ny, nz));
+                            sm = sm + (at32(pt, i, j, l + m, nx, ny, nz) + at32(pt, i, j, l - m, nx, ny, nz));
+                            lp = lp + cm[m] * sm;
+                        }
+                        grad[c] = grad[c] + l1[c] * lp;
+                    }
+                }
+        for (long i = 0; i < nr; ++i) l0[rcv[i]] = l0[rcv[i]] + res[(t - 1) * nr + i];
+        if (src_adj) src_adj[t - 1] = l0[src_index];
+        float* tmp = l2; l2 = l1; l1 = l0; l0 = tmp;
+    }
+    free(l1);
+    free(l2);
+    free(l0);
+    return 0;
+}
+
+/* FP32 forward keeping every state (states[t*n], t = 0..T) and records. */
+int orc_wave_forward_states_f32(const float* w, long nx, long ny, long nz, long T, const float* src, long src_index,
+                                const long* rcv, long nr, float* records, float* states)
+{
+    size_t n = (size_t)nx * ny * nz;
+    float* pm = (float*)calloc(n, sizeof(float));
+    float* p = (float*)calloc(n, sizeof(float));
+    if (!pm || !p) { free(pm); free(p); return -1; }
+    memcpy(states, p, n * sizeof(float));
+    for (long t = 0; t < T; ++t) {
+        int rc = orc_wave25_f32(p, pm, w, nx, ny, nz, 1, src ? src + t : NULL, src_index);
+        if (rc) { free(pm); free(p); return rc; }
+        memcpy(states + (size_t)(t + 1) * n, p, n * sizeof(float));
+        for (long i = 0; i < nr; ++i) records[t * nr + i] = p[rcv[i]];
+    }
+    free(pm);
+    free(p);
+    return 0;
+}
