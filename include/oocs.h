@@ -292,6 +292,102 @@ int oocs_plan_set_graphs(oocs_plan* plan, int on);
  * Errors: OOCS_E_ARG, OOCS_E_STATE (planning-only plan), OOCS_E_HIP. */
 int oocs_run(oocs_plan* plan, void* const* h_store, int64_t steps, const float* h_src, oocs_stats* st);
 
+/* ------------------------------------------------------------------------
+ * Batched in-core heat domains. Many independent domains of uneven sizes
+ * advance together: one launch covers every domain for one step (a
+ * work-list table maps each workgroup to its domain, tile and z-chunk), and
+ * `steps` such launches are replayed as one HIP graph. The tile shape and the
+ * planes each thread marches are chosen per size bucket by a timing
+ * autotuner whose choices persist in a cache file.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    float* d_u;        /* state (nz, ny, nx), x fastest; before and after a run */
+    float* d_scratch;  /* caller scratch of the same size */
+    int64_t nx, ny, nz;
+} oocs_domain;
+
+typedef struct oocs_batch oocs_batch;
+
+/* Device bytes of the work-list table for nd domains. */
+size_t oocs_batch_table_bytes(int nd);
+
+/* Create a batch of nd domains (heat, u' = u + alpha*Laplacian, zero
+ * ghosts). d_table: device memory of oocs_batch_table_bytes(nd) bytes.
+ * tune: 1 = time the tile candidates on this GPU for every size bucket not
+ * found in the cache (the domains' own u buffers are read, their scratch
+ * buffers written; states are unchanged), 0 = use the cache, else the
+ * default tile. tune_cache: path of the cache file (NULL = no cache). The
+ * caller keeps the domain buffers and d_table alive until destroy. */
+int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_table, size_t table_bytes,
+                      const char* tune_cache, int tune, void* stream, oocs_batch** out);
+
+/* Advance every domain `steps` steps as one graph launch on `stream`
+ * (built once per step count). Asynchronous. */
+int oocs_batch_run(oocs_batch* b, int64_t steps, void* stream);
+
+/* Baseline: the same steps as separate launches, domain after domain. */
+int oocs_batch_run_per_domain(oocs_batch* b, int64_t steps, void* stream);
+
+/* Tile configuration chosen for a domain: threads per tile in x and y and
+ * planes marched per thread. */
+int oocs_batch_domain_tile(const oocs_batch* b, int domain, int* tx, int* ty, int* zc);
+
+int oocs_batch_destroy(oocs_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Misfit gradient of the wave propagator by its discrete adjoint, with
+ * compressed forward checkpoints in host memory.
+ *
+ * Forward from rest: p(t+1) = 2p(t) - p(t-1) + w . L p(t) + s(t) at the
+ * source cell, w = (v * vscale)^2 (vscale = dt/dx), t = 0..T-1; receivers
+ * record r(t) = p(t) at nrcv cells for t = 1..T; J = 1/2 sum_t |r(t) - d(t)|^2.
+ * Adjoint (L symmetric under zero ghosts): lam(t) = 2 lam(t+1) - lam(t+2) +
+ * L(w . lam(t+1)) + S^T (r(t) - d(t)), lam(T+1) = lam(T+2) = 0;
+ * dJ/dw = sum_t lam(t) . L p(t-1);  dJ/dv = dJ/dw . 2 v vscale^2.
+ * The forward pass stores (p(t), p(t-1)) every ckpt_every steps through the
+ * fixed-rate codec (ckpt_rate bits per value, 0 = uncompressed) into a host
+ * store (the same fixed-rate format as Sec. IV, here applied to checkpoints);
+ * the backward pass decodes them in reverse, recomputes each segment's
+ * states on the device and runs the adjoint over it. With uncompressed
+ * checkpoints the gradient is the exact FP32 gradient.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t nx, ny, nz;          /* grid, x fastest; nx, ny, nz multiples of 4 if ckpt_rate > 0 */
+    int64_t steps;               /* T >= 1 */
+    int64_t ckpt_every;          /* steps between checkpoints, >= 1 */
+    int32_t ckpt_rate;           /* bits per value of the checkpoints; 0 = uncompressed */
+    int32_t nrcv;                /* receivers, >= 0 */
+    int64_t src_x, src_y, src_z; /* source cell */
+    float vscale;                /* dt / dx */
+    int32_t pad0;
+} oocs_adjoint_cfg;
+
+/* Device workspace bytes the two calls below need (one caller allocation,
+ * passed as d_work): w, ckpt_every + 2 state fields, three multiplier
+ * fields, the w-gradient field and the checkpoint codec staging. */
+size_t oocs_adjoint_workspace_bytes(const oocs_adjoint_cfg* cfg);
+
+/* Host checkpoint store bytes (pinned memory recommended). */
+size_t oocs_adjoint_ckpt_bytes(const oocs_adjoint_cfg* cfg);
+
+/* Forward pass. d_v: velocity field; h_src: T source amplitudes (host);
+ * d_rcv: nrcv flat cell indices (device, int64; indices outside the grid
+ * are ignored); d_obs: observed records
+ * (device, T x nrcv, row t-1 for time t). Writes the residuals r - d into
+ * d_res (device, T x nrcv), the checkpoints into h_ckpt, and J (FP64 sum of
+ * the FP32 residuals) into *J. Blocking. */
+int oocs_wave_forward_ckpt(const oocs_adjoint_cfg* cfg, const float* d_v, const float* h_src, const int64_t* d_rcv,
+                           const float* d_obs, float* d_res, void* d_work, size_t work_bytes, void* h_ckpt, double* J,
+                           void* stream);
+
+/* Backward pass after oocs_wave_forward_ckpt with the same arguments:
+ * writes dJ/dv into d_grad_v. Blocking. */
+int oocs_wave_adjoint(const oocs_adjoint_cfg* cfg, const float* d_v, const float* h_src, const int64_t* d_rcv,
+                      const float* d_res, void* d_work, size_t work_bytes, const void* h_ckpt, float* d_grad_v,
+                      void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,19 @@ class Op(C.Structure):
     ]
 
 
+class AdjointCfg(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64), ("steps", C.c_int64), ("ckpt_every", C.c_int64),
+        ("ckpt_rate", C.c_int32), ("nrcv", C.c_int32), ("src_x", C.c_int64), ("src_y", C.c_int64),
+        ("src_z", C.c_int64), ("vscale", C.c_float), ("pad0", C.c_int32),
+    ]
+
+
+class Domain(C.Structure):
+    _fields_ = [("d_u", C.c_void_p), ("d_scratch", C.c_void_p), ("nx", C.c_int64), ("ny", C.c_int64),
+                ("nz", C.c_int64)]
+
+
 class Stats(C.Structure):
     _fields_ = [
         ("wall_ms", C.c_double), ("enqueue_ms", C.c_double), ("rounds", C.c_int64),
@@ -103,6 +116,18 @@ _SIGS = {
     "oocs_run": (C.c_int, [_P, C.POINTER(_P), _I64, _P, C.POINTER(Stats)]),
     "oocs_plan_set_profiling": (C.c_int, [_P, C.c_int]),
     "oocs_plan_set_graphs": (C.c_int, [_P, C.c_int]),
+    "oocs_batch_table_bytes": (C.c_size_t, [C.c_int]),
+    "oocs_batch_create": (C.c_int, [C.POINTER(Domain), C.c_int, C.c_float, _P, C.c_size_t, C.c_char_p, C.c_int, _P,
+                                    C.POINTER(_P)]),
+    "oocs_batch_run": (C.c_int, [_P, _I64, _P]),
+    "oocs_batch_run_per_domain": (C.c_int, [_P, _I64, _P]),
+    "oocs_batch_domain_tile": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "oocs_batch_destroy": (C.c_int, [_P]),
+    "oocs_adjoint_workspace_bytes": (C.c_size_t, [C.POINTER(AdjointCfg)]),
+    "oocs_adjoint_ckpt_bytes": (C.c_size_t, [C.POINTER(AdjointCfg)]),
+    "oocs_wave_forward_ckpt": (C.c_int, [C.POINTER(AdjointCfg), _P, _P, _P, _P, _P, _P, C.c_size_t, _P,
+                                         C.POINTER(C.c_double), _P]),
+    "oocs_wave_adjoint": (C.c_int, [C.POINTER(AdjointCfg), _P, _P, _P, _P, _P, C.c_size_t, _P, _P, _P]),
 }
 SYMBOLS = tuple(_SIGS)
 

@@ -268,3 +268,136 @@ class OutOfCorePlan:
 
     def set_graphs(self, on: bool):
         L.check(L.lib().oocs_plan_set_graphs(self._h, 1 if on else 0))
+
+
+# ---------------------------------------------------------------------------
+# Misfit gradient (adjoint with compressed checkpoints) and autograd
+# ---------------------------------------------------------------------------
+
+class WaveProblem:
+    """A wave misfit problem: source wavelet, receivers, observed records and
+    checkpoint policy. Holds the device workspace and the pinned host
+    checkpoint store (allocated here with torch, handed to the library)."""
+
+    def __init__(self, shape, steps: int, src_amps, src_cell, rcv_cells, observed, vscale: float,
+                 ckpt_every: int = 10, ckpt_rate: int = 0, device="cuda"):
+        nz, ny, nx = shape
+        c = L.AdjointCfg()
+        c.nx, c.ny, c.nz = nx, ny, nz
+        c.steps = steps
+        c.ckpt_every = ckpt_every
+        c.ckpt_rate = ckpt_rate
+        rcv = np.ascontiguousarray(rcv_cells, dtype=np.int64).reshape(-1)
+        if rcv.size and (rcv.min() < 0 or rcv.max() >= nx * ny * nz):
+            raise ValueError("receiver index outside the grid")
+        c.nrcv = rcv.size
+        c.src_x, c.src_y, c.src_z = src_cell
+        c.vscale = vscale
+        self.cfg = c
+        self.shape = (nz, ny, nx)
+        self.src = np.ascontiguousarray(src_amps, dtype=np.float32)
+        if self.src.size < steps:
+            raise ValueError("need one source amplitude per step")
+        self.rcv = torch.from_numpy(rcv).to(device)
+        obs = torch.as_tensor(observed, dtype=torch.float32).reshape(steps, rcv.size)
+        self.obs = obs.to(device).contiguous()
+        self.res = torch.empty_like(self.obs)
+        wb = int(L.lib().oocs_adjoint_workspace_bytes(C.byref(c)))
+        if wb == 0:
+            L.check(L.OOCS_E_ARG)
+        self.work = torch.empty(wb, dtype=torch.uint8, device=device)
+        self.ckpt = torch.empty(int(L.lib().oocs_adjoint_ckpt_bytes(C.byref(c))), dtype=torch.uint8, pin_memory=True)
+
+    def _common(self, v):
+        _field(v, "v")
+        return (C.byref(self.cfg), _dptr(v), self.src.ctypes.data_as(C.c_void_p), _dptr(self.rcv))
+
+    def forward(self, v: torch.Tensor) -> float:
+        J = C.c_double()
+        cfg, pv, ps, pr = self._common(v)
+        L.check(L.lib().oocs_wave_forward_ckpt(cfg, pv, ps, pr, _dptr(self.obs), _dptr(self.res), _dptr(self.work),
+                                               self.work.numel(), C.c_void_p(self.ckpt.data_ptr()), C.byref(J),
+                                               _stream_ptr()))
+        return J.value
+
+    def gradient(self, v: torch.Tensor) -> torch.Tensor:
+        """dJ/dv for the checkpoints of the last forward() call."""
+        g = torch.empty_like(v)
+        cfg, pv, ps, pr = self._common(v)
+        L.check(L.lib().oocs_wave_adjoint(cfg, pv, ps, pr, _dptr(self.res), _dptr(self.work), self.work.numel(),
+                                          C.c_void_p(self.ckpt.data_ptr()), _dptr(g), _stream_ptr()))
+        return g
+
+
+class WaveMisfit(torch.autograd.Function):
+    """J(v) = 1/2 sum |S p(t) - d(t)|^2 for the 25-point wave from rest;
+    backward runs the adjoint with checkpoint recompute on the GPU."""
+
+    @staticmethod
+    def forward(ctx, v, problem: WaveProblem):
+        v = v.detach().contiguous()
+        J = problem.forward(v)
+        ctx.problem = problem
+        ctx.save_for_backward(v)
+        return torch.tensor(J, dtype=torch.float64, device=v.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (v,) = ctx.saved_tensors
+        g = ctx.problem.gradient(v)
+        return (g * gJ.to(g.dtype)), None
+
+
+# ---------------------------------------------------------------------------
+# Batched in-core heat domains
+# ---------------------------------------------------------------------------
+
+class HeatBatch:
+    """Independent heat domains advanced together (one launch per step for
+    all domains, all steps replayed as one graph). `fields` are (nz, ny, nx)
+    float32 device tensors, updated in place by run()."""
+
+    def __init__(self, fields, alpha: float = 0.1, tune: bool = True, tune_cache: str | None = None):
+        self.fields = [f for f in fields]
+        for f in self.fields:
+            _field_any(f)
+        self.scratch = [torch.empty_like(f) for f in self.fields]
+        n = len(self.fields)
+        arr = (L.Domain * n)()
+        for i, (f, s) in enumerate(zip(self.fields, self.scratch)):
+            nz, ny, nx = f.shape
+            arr[i] = L.Domain(f.data_ptr(), s.data_ptr(), nx, ny, nz)
+        self._arr = arr
+        self.table = torch.empty(int(L.lib().oocs_batch_table_bytes(n)), dtype=torch.uint8, device=self.fields[0].device)
+        h = C.c_void_p()
+        L.check(L.lib().oocs_batch_create(arr, n, C.c_float(alpha), _dptr(self.table), self.table.numel(),
+                                          tune_cache.encode() if tune_cache else None, 1 if tune else 0,
+                                          _stream_ptr(), C.byref(h)))
+        self._h = h
+
+    def run(self, steps: int, stream=None):
+        L.check(L.lib().oocs_batch_run(self._h, steps, _stream_ptr(stream)))
+
+    def run_per_domain(self, steps: int, stream=None):
+        L.check(L.lib().oocs_batch_run_per_domain(self._h, steps, _stream_ptr(stream)))
+
+    def tile(self, i: int):
+        tx, ty, zc = C.c_int(), C.c_int(), C.c_int()
+        L.check(L.lib().oocs_batch_domain_tile(self._h, i, C.byref(tx), C.byref(ty), C.byref(zc)))
+        return tx.value, ty.value, zc.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().oocs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _field_any(t: torch.Tensor):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 3:
+        raise ValueError("domain fields must be contiguous float32 (nz, ny, nx) device tensors")

@@ -34,6 +34,8 @@ SOURCES = {
     "kernels.hip": True,   # device code
     "plan.cpp": False,     # host only
     "host.cpp": False,     # host only (HIP runtime API)
+    "adjoint.cpp": False,  # host only (HIP runtime API)
+    "batch.cpp": False,    # host only (HIP runtime API)
 }
 
 

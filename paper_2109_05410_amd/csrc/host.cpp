@@ -23,8 +23,9 @@
 #include "oocs.h"
 #include "plan.hpp"
 
-namespace {
+#include "abi_util.hpp"
 
+namespace oocs {
 thread_local std::string g_err;
 
 int fail(int code, const std::string& msg)
@@ -37,12 +38,11 @@ int hip_fail(hipError_t e, const char* what)
 {
     return fail(OOCS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
+}  // namespace oocs
 
-#define HIP_TRY(call)                                        \
-    do {                                                     \
-        hipError_t e_ = (call);                              \
-        if (e_ != hipSuccess) return hip_fail(e_, #call);    \
-    } while (0)
+namespace {
+using oocs::fail;
+using oocs::hip_fail;
 
 bool dims_ok4(int64_t nx, int64_t ny, int64_t nz) { return nx > 0 && ny > 0 && nz > 0 && nx % 4 == 0 && ny % 4 == 0 && nz % 4 == 0; }
 
@@ -75,7 +75,7 @@ extern "C" {
 
 int oocs_version(void) { return 1; }
 
-const char* oocs_last_error(void) { return g_err.c_str(); }
+const char* oocs_last_error(void) { return oocs::g_err.c_str(); }
 
 // ---------------------------------------------------------------------------
 // Codec

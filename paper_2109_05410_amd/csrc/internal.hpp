@@ -92,6 +92,48 @@ hipError_t launch_codec_field(bool encode, const float* in_f, float* out_f, cons
 // Exchange the contents of two device arrays of n floats.
 hipError_t launch_swap(float* a, float* b, int64_t n, hipStream_t stream);
 
+// Adjoint helpers (in-core fields, nx*ny*nz floats, x fastest).
+hipError_t launch_adjoint_step(const float* l1, const float* l2, const float* w, const float* p, float* l0,
+                               float* grad, int64_t nx, int64_t ny, int64_t nz, hipStream_t stream);
+// Receivers outside [0, n) are skipped.
+hipError_t launch_rcv_sample(const float* p, const int64_t* rcv, int nr, const float* obs, float* res, int64_t n,
+                             hipStream_t s);
+hipError_t launch_rcv_inject(float* lam, const int64_t* rcv, int nr, const float* res, int64_t n, hipStream_t s);
+hipError_t launch_v_to_w(const float* v, float c, float* w, int64_t n, hipStream_t s);
+hipError_t launch_grad_w_to_v(const float* gw, const float* v, float c, float* gv, int64_t n, hipStream_t s);
+hipError_t launch_fill(float* x, float value, int64_t n, hipStream_t s);
+
+// ---- batched heat domains ---------------------------------------------------
+// Tile configurations the batch autotuner chooses from (TX x TY threads,
+// ZC planes per thread).
+struct TileCfg {
+    int tx, ty, zc;
+};
+constexpr int kNumTileCfgs = 6;
+extern const TileCfg kTileCfgs[kNumTileCfgs];
+
+struct BatchDomain {   // one entry of the device work-list table
+    float* a;          // field at even steps (the caller's u)
+    float* b;          // field at odd steps (the caller's scratch)
+    int32_t nx, ny, nz;
+    int32_t cfg;       // index into kTileCfgs
+    int32_t wg_begin;  // first workgroup of this domain in a launch
+    int32_t pad;
+};
+
+// Workgroups one domain needs with tile configuration cfg.
+int32_t batch_domain_workgroups(int nx, int ny, int nz, int cfg);
+
+// One step of every domain: parity 0 reads a and writes b, 1 the reverse.
+hipError_t launch_batch_step(const BatchDomain* d_table, int nd, int32_t total_wg, int parity, float alpha,
+                             hipStream_t stream);
+hipError_t add_batch_step_node(const BatchDomain* d_table, int nd, int32_t total_wg, int parity, float alpha,
+                               hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node);
+// One step of one dense domain with tile configuration cfg (tuning and the
+// per-domain baseline).
+hipError_t launch_heat_dense(const float* src, float* dst, int nx, int ny, int nz, float alpha, int cfg,
+                             hipStream_t stream);
+
 struct EncStages {
     int32_t* emax; int32_t* q; int32_t* t; uint32_t* u; uint64_t* planes; uint64_t* words; int32_t* bits;
 };

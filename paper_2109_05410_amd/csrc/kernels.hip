@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "adjoint_dev.hpp"
 #include "codec_dev.hpp"
 #include "internal.hpp"
 #include "stencil_dev.hpp"
@@ -344,6 +345,192 @@ hipError_t launch_swap(float* a, float* b, int64_t n, hipStream_t stream)
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(swap_kernel, dim3((unsigned)((n + kBlockThreads - 1) / kBlockThreads)), dim3(kBlockThreads), 0,
                        stream, a, b, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched heat domains: one launch advances every domain one step
+// ---------------------------------------------------------------------------
+
+const TileCfg kTileCfgs[kNumTileCfgs] = {{64, 4, 16}, {64, 4, 32}, {64, 4, 64}, {32, 8, 16}, {128, 2, 16}, {64, 4, 8}};
+
+template <int C>
+__device__ inline void heat_dense_cfg(const float* src, float* dst, int nx, int ny, int nz, float alpha, int wg)
+{
+    constexpr TileCfg t = C == 0 ? TileCfg{64, 4, 16} : C == 1 ? TileCfg{64, 4, 32} : C == 2 ? TileCfg{64, 4, 64}
+                        : C == 3 ? TileCfg{32, 8, 16} : C == 4 ? TileCfg{128, 2, 16} : TileCfg{64, 4, 8};
+    stencil::heat_dense<t.tx, t.ty, t.zc>(src, dst, nx, ny, nz, alpha, wg);
+}
+
+__device__ inline void heat_dense_any(int cfg, const float* src, float* dst, int nx, int ny, int nz, float alpha, int wg)
+{
+    switch (cfg) {
+    case 0: heat_dense_cfg<0>(src, dst, nx, ny, nz, alpha, wg); break;
+    case 1: heat_dense_cfg<1>(src, dst, nx, ny, nz, alpha, wg); break;
+    case 2: heat_dense_cfg<2>(src, dst, nx, ny, nz, alpha, wg); break;
+    case 3: heat_dense_cfg<3>(src, dst, nx, ny, nz, alpha, wg); break;
+    case 4: heat_dense_cfg<4>(src, dst, nx, ny, nz, alpha, wg); break;
+    default: heat_dense_cfg<5>(src, dst, nx, ny, nz, alpha, wg); break;
+    }
+}
+
+int32_t batch_domain_workgroups(int nx, int ny, int nz, int cfg)
+{
+    const TileCfg& t = kTileCfgs[cfg];
+    return ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty) * ((nz + t.zc - 1) / t.zc);
+}
+
+__global__ void __launch_bounds__(kBlockThreads)
+batch_step_kernel(const BatchDomain* __restrict__ table, int nd, int parity, float alpha)
+{
+    const int wg = (int)blockIdx.x;
+    int lo = 0, hi = nd - 1;  // last domain with wg_begin <= wg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (table[mid].wg_begin <= wg) lo = mid; else hi = mid - 1;
+    }
+    const BatchDomain& d = table[lo];
+    const float* src = parity ? d.b : d.a;
+    float* dst = parity ? d.a : d.b;
+    heat_dense_any(d.cfg, src, dst, d.nx, d.ny, d.nz, alpha, wg - d.wg_begin);
+}
+
+__global__ void __launch_bounds__(kBlockThreads)
+heat_dense_kernel(const float* src, float* dst, int nx, int ny, int nz, float alpha, int cfg)
+{
+    heat_dense_any(cfg, src, dst, nx, ny, nz, alpha, (int)blockIdx.x);
+}
+
+hipError_t launch_batch_step(const BatchDomain* d_table, int nd, int32_t total_wg, int parity, float alpha,
+                             hipStream_t stream)
+{
+    if (total_wg <= 0 || nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_step_kernel, dim3((unsigned)total_wg), dim3(kBlockThreads), 0, stream, d_table, nd,
+                       parity, alpha);
+    return hipGetLastError();
+}
+
+hipError_t add_batch_step_node(const BatchDomain* d_table, int nd, int32_t total_wg, int parity, float alpha,
+                               hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node)
+{
+    void* args[] = {&d_table, &nd, &parity, &alpha};
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void*>(&batch_step_kernel);
+    kp.gridDim = dim3((unsigned)total_wg);
+    kp.blockDim = dim3(kBlockThreads);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, deps, ndeps, &kp);
+}
+
+hipError_t launch_heat_dense(const float* src, float* dst, int nx, int ny, int nz, float alpha, int cfg,
+                             hipStream_t stream)
+{
+    const int32_t wgs = batch_domain_workgroups(nx, ny, nz, cfg);
+    if (wgs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(heat_dense_kernel, dim3((unsigned)wgs), dim3(kBlockThreads), 0, stream, src, dst, nx, ny, nz,
+                       alpha, cfg);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the wave propagator and its small helpers
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBlockThreads) adjoint_step_kernel(adjoint::StepArgs a)
+{
+    adjoint::adjoint_step(a, (int)blockIdx.x);
+}
+
+hipError_t launch_adjoint_step(const float* l1, const float* l2, const float* w, const float* p, float* l0,
+                               float* grad, int64_t nx, int64_t ny, int64_t nz, hipStream_t stream)
+{
+    adjoint::StepArgs a{l1, l2, w, p, l0, grad, (int)nx, (int)ny, (int)nz};
+    const int64_t tiles = ((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
+    const int64_t wgs = tiles * ((nz + kZChunk - 1) / kZChunk);
+    if (wgs == 0) return hipSuccess;
+    hipLaunchKernelGGL(adjoint_step_kernel, dim3((unsigned)wgs), dim3(kBlockThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+// res[i] = p[rcv[i]] - obs[i]; receivers outside [0, n) are skipped
+__global__ void rcv_sample_kernel(const float* p, const int64_t* rcv, int nr, const float* obs, float* res, int64_t n)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < nr) {
+        const int64_t r = rcv[i];
+        res[i] = (r >= 0 && r < n) ? p[r] - obs[i] : 0.0f;
+    }
+}
+
+// lam[rcv[i]] += res[i], receivers in order (one thread: receivers may share a cell)
+__global__ void rcv_inject_kernel(float* lam, const int64_t* rcv, int nr, const float* res, int64_t n)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int i = 0; i < nr; ++i) {
+            const int64_t r = rcv[i];
+            if (r >= 0 && r < n) lam[r] = lam[r] + res[i];
+        }
+}
+
+hipError_t launch_rcv_sample(const float* p, const int64_t* rcv, int nr, const float* obs, float* res, int64_t n,
+                             hipStream_t s)
+{
+    if (nr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rcv_sample_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, p, rcv, nr, obs, res, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_rcv_inject(float* lam, const int64_t* rcv, int nr, const float* res, int64_t n, hipStream_t s)
+{
+    if (nr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rcv_inject_kernel, dim3(1), dim3(64), 0, s, lam, rcv, nr, res, n);
+    return hipGetLastError();
+}
+
+// w = (v*c)*(v*c);  gv = gw*((2*v)*(c*c));  x = 0
+__global__ void v_to_w_kernel(const float* v, float c, float* w, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+    if (i < n) {
+        const float t = v[i] * c;
+        w[i] = t * t;
+    }
+}
+
+__global__ void grad_w_to_v_kernel(const float* gw, const float* v, float c, float* gv, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+    if (i < n) gv[i] = gw[i] * ((2.0f * v[i]) * (c * c));
+}
+
+__global__ void fill_kernel(float* x, float value, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+    if (i < n) x[i] = value;
+}
+
+static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlockThreads - 1) / kBlockThreads); }
+
+hipError_t launch_v_to_w(const float* v, float c, float* w, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(v_to_w_kernel, dim3(blocks_for(n)), dim3(kBlockThreads), 0, s, v, c, w, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_w_to_v(const float* gw, const float* v, float c, float* gv, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(grad_w_to_v_kernel, dim3(blocks_for(n)), dim3(kBlockThreads), 0, s, gw, v, c, gv, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* x, float value, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n)), dim3(kBlockThreads), 0, s, x, value, n);
     return hipGetLastError();
 }
 

@@ -54,6 +54,42 @@ __device__ inline void heat_level(const Job& j, int nx, int ny, int nz, float al
     }
 }
 
+// Heat on a dense field with a tile shape chosen at compile time (batched
+// domains): tile TX x TY columns per 256-thread workgroup (TX*TY = 256),
+// ZC planes marched per thread. Same operation order as heat_level.
+template <int TX, int TY, int ZC>
+__device__ inline void heat_dense(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
+                                  float alpha, int wg)
+{
+    const int tiles_x = (nx + TX - 1) / TX;
+    const int tiles_y = (ny + TY - 1) / TY;
+    const int tile = wg % (tiles_x * tiles_y);
+    const int zc = wg / (tiles_x * tiles_y);
+    const int x = (tile % tiles_x) * TX + (int)(threadIdx.x % TX);
+    const int y = (tile / tiles_x) * TY + (int)(threadIdx.x / TX);
+    const int z0 = zc * ZC;
+    const int z1 = min(nz, z0 + ZC);
+    if (x >= nx || y >= ny || z0 >= z1) return;
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t xy = (int64_t)y * nx + x;
+    float cm = z0 > 0 ? src[(z0 - 1) * plane + xy] : 0.0f;
+    float cc = src[z0 * plane + xy];
+    for (int z = z0; z < z1; ++z) {
+        const float* pl = src + z * plane + xy;
+        const float cp = z + 1 < nz ? pl[plane] : 0.0f;
+        const float xm = x > 0 ? pl[-1] : 0.0f;
+        const float xp = x + 1 < nx ? pl[1] : 0.0f;
+        const float ym = y > 0 ? pl[-nx] : 0.0f;
+        const float yp = y + 1 < ny ? pl[nx] : 0.0f;
+        float s = (xm + xp) + (ym + yp);
+        s = s + (cm + cp);
+        s = s - 6.0f * cc;
+        dst[z * plane + xy] = cc + alpha * s;
+        cm = cc;
+        cc = cp;
+    }
+}
+
 // Wave, 25 points:
 //   acc = C0X3*p;  for m = 1..4: acc = acc + C_m * (((x+m + x-m) + (y+m + y-m)) + (z+m + z-m))
 //   p'  = (2p - pm) + w*acc  (+ amp at the source cell)

@@ -1,0 +1,67 @@
+"""Batched uneven heat domains (one launch per step for all domains, all
+steps in one graph launch; autotuned tiles): every domain equals the
+oracle's FP32 steps bit for bit (small domains) and the per-domain launch
+baseline bit for bit (the 64-domain workload at full size)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2109_05410_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.mark.parametrize("steps", [7, 8, 1])
+def test_small_uneven_domains_match_oracle(steps, tmp_path):
+    shapes = [(9, 17, 33), (64, 64, 64), (100, 40, 70), (5, 3, 130), (1, 1, 1), (31, 129, 66)]
+    u0 = [inputs.heat_uniform(s, seed=i) for i, s in enumerate(shapes)]
+    fields = [torch.from_numpy(u).to(DEV) for u in u0]
+    b = api.HeatBatch(fields, alpha=0.1, tune=True, tune_cache=str(tmp_path / "tune.json"))
+    b.run(steps)
+    torch.cuda.synchronize()
+    for u, f in zip(u0, fields):
+        assert np.array_equal(f.cpu().numpy(), O.heat7_f32(u, 0.1, steps))
+    assert os.path.exists(tmp_path / "tune.json")
+    # the per-domain baseline computes the same
+    fields2 = [torch.from_numpy(u).to(DEV) for u in u0]
+    b2 = api.HeatBatch(fields2, alpha=0.1, tune=False, tune_cache=str(tmp_path / "tune.json"))
+    b2.run_per_domain(steps)
+    torch.cuda.synchronize()
+    for f, g in zip(fields, fields2):
+        assert torch.equal(f, g)
+
+
+def test_graph_replays():
+    shapes = [(16, 16, 16), (20, 24, 28)]
+    u0 = [inputs.heat_uniform(s, seed=10 + i) for i, s in enumerate(shapes)]
+    fields = [torch.from_numpy(u).to(DEV) for u in u0]
+    b = api.HeatBatch(fields, tune=False)
+    for _ in range(3):
+        b.run(4)
+    torch.cuda.synchronize()
+    for u, f in zip(u0, fields):
+        assert np.array_equal(f.cpu().numpy(), O.heat7_f32(u, 0.1, 12))
+
+
+def test_full_size_batched_workload(tmp_path):
+    """64 cubes with sides uniform in [64, 384], 200 steps: batched graph
+    launch equals per-domain launches bit for bit; the smallest domain
+    equals the oracle."""
+    sides = inputs.batch_sides()
+    fields = [torch.from_numpy(inputs.heat_uniform((s, s, s), seed=3 + j)).to(DEV) for j, s in enumerate(sides)]
+    ref = [f.clone() for f in fields]
+    b = api.HeatBatch(fields, tune=True, tune_cache=str(tmp_path / "tune.json"))
+    b.run(200)
+    b2 = api.HeatBatch(ref, tune=False, tune_cache=str(tmp_path / "tune.json"))
+    b2.run_per_domain(200)
+    torch.cuda.synchronize()
+    for f, g in zip(fields, ref):
+        assert torch.equal(f, g)
+    j = int(np.argmin(sides))
+    s = int(sides[j])
+    want = O.heat7_f32(inputs.heat_uniform((s, s, s), seed=3 + j), 0.1, 200)
+    assert np.array_equal(fields[j].cpu().numpy(), want)
