@@ -166,9 +166,21 @@ typedef struct {
     int32_t rate[OOCS_MAX_FIELDS];  /* bits per value of each field's host store; 0 = uncompressed */
     int32_t nstage;                 /* staging slots per direction (>= 2); 0 = default (3) */
     float alpha;                    /* heat diffusion number (u += alpha * Laplacian) */
-    int32_t pad0;
+    int32_t flags;                  /* 0 or OOCS_PLAN_BLOCK_RESTART */
     int64_t src_x, src_y, src_z;    /* wave source cell; any < 0 = no source */
 } oocs_config;
+
+/* Plan flag. Without it a residency streams the whole grid through the
+ * level rings once, so the halo planes of block i at every intermediate
+ * time level are the planes block i-1 already computed and stay in the
+ * ring (region sharing at every level, not only at the input level): each
+ * plane of each level is computed once. With it, every block restarts the
+ * level fronts at its extended range [a_i - h, a_{i+1} + h) and recomputes
+ * its halo as in Fig. 2. Both give bit-identical results, since every
+ * computed plane has fully valid inputs either way; the flag only changes
+ * the work and the tick count. The host store layout, the R_i / C_i
+ * chunks and the write-back order are the same. */
+#define OOCS_PLAN_BLOCK_RESTART 1
 
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be

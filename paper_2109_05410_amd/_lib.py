@@ -24,6 +24,7 @@ OOCS_HEAT7 = 1
 OOCS_WAVE25 = 2
 OOCS_MAX_FIELDS = 3
 OOCS_MAX_RATE = 34
+OOCS_PLAN_BLOCK_RESTART = 1
 
 OP_H2D, OP_DECODE, OP_LEVEL, OP_ENCODE, OP_D2H, OP_LAUNCH, OP_RECORD, OP_WAIT = range(1, 9)
 
@@ -39,7 +40,7 @@ class Config(C.Structure):
         ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
         ("stencil", C.c_int32), ("nslabs", C.c_int32), ("k", C.c_int32), ("group", C.c_int32),
         ("rate", C.c_int32 * OOCS_MAX_FIELDS), ("nstage", C.c_int32),
-        ("alpha", C.c_float), ("pad0", C.c_int32),
+        ("alpha", C.c_float), ("flags", C.c_int32),
         ("src_x", C.c_int64), ("src_y", C.c_int64), ("src_z", C.c_int64),
     ]
 

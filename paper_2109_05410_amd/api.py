@@ -168,7 +168,7 @@ class OutOfCorePlan:
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
-                 planning_only: bool = False, device=None):
+                 planning_only: bool = False, device=None, block_restart: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -180,6 +180,7 @@ class OutOfCorePlan:
             cfg.rate[i] = rates[i] if i < len(rates) else 0
         cfg.nstage = nstage
         cfg.alpha = alpha
+        cfg.flags = L.OOCS_PLAN_BLOCK_RESTART if block_restart else 0
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg

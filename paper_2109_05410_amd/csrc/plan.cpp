@@ -54,6 +54,8 @@ int Planner::init(const oocs_config& c, std::string& err)
     if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
     nstage = c.nstage ? c.nstage : 3;
+    if (c.flags & ~OOCS_PLAN_BLOCK_RESTART) { err = "unknown plan flags"; return OOCS_E_ARG; }
+    restart = (c.flags & OOCS_PLAN_BLOCK_RESTART) != 0;
     a.resize(n + 1);
     for (int i = 0; i <= n; ++i) a[i] = (int64_t)i * slab;
     return OOCS_OK;
@@ -91,20 +93,30 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
     std::vector<int64_t> f(nl), lo(nl), hi(nl);
     int64_t load_front = 0;
     const int64_t align = 4;
-    for (int i = 0; i < n; ++i) {
-        const int64_t e_end = std::min(a[i + 1] + h, nz);
+    auto block_of = [&](int64_t z) { return (int)std::min<int64_t>(z / slab, n - 1); };
+    // A pass streams the z-range [p0, p1) through all levels. With block
+    // restarts every block is one pass over its extended range (levels
+    // shrink by r per step inside [a_i - h, a_{i+1} + h)); with shared
+    // levels the whole grid is one pass and every plane of every level is
+    // computed once, the halo planes of a block being those its neighbour
+    // already computed.
+    const int npass = restart ? n : 1;
+    for (int pi = 0; pi < npass; ++pi) {
+        const int64_t p0 = restart ? a[pi] : 0;
+        const int64_t p1 = restart ? a[pi + 1] : nz;
+        const int64_t e_end = restart ? std::min(a[pi + 1] + h, nz) : nz;
         for (int lv = nin; lv < nl; ++lv) {
             const int64_t st = lv - nin + 1;
-            lo[lv] = std::max<int64_t>(a[i] - h + st * r, 0);
-            hi[lv] = std::min<int64_t>(a[i + 1] + h - st * r, nz);
+            lo[lv] = restart ? std::max<int64_t>(a[pi] - h + st * r, 0) : 0;
+            hi[lv] = restart ? std::min<int64_t>(a[pi + 1] + h - st * r, nz) : nz;
             f[lv] = lo[lv];
         }
-        int64_t out_front = a[i];
+        int64_t out_front = p0;
         int guard = 0;
-        while (out_front < a[i + 1]) {
+        while (out_front < p1) {
             if (++guard > 1000000) { err = "schedule does not terminate"; return OOCS_E_STATE; }
             Tick t;
-            t.block = i;
+            t.block = restart ? pi : block_of(std::min(load_front, nz - 1));
             std::vector<int64_t> prev = f;
             for (int lv = 0; lv < nin; ++lv) prev[lv] = load_front;
             // decode the next input group
@@ -112,7 +124,7 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
                 t.in_group = (int64_t)s.in_groups.size();
                 t.dz0 = load_front;
                 t.dz1 = std::min(load_front + G, e_end);
-                s.in_groups.push_back({t.dz0, t.dz1, (int64_t)s.ticks.size(), i, false});
+                s.in_groups.push_back({t.dz0, t.dz1, (int64_t)s.ticks.size(), restart ? pi : block_of(t.dz0), false});
                 load_front = t.dz1;
             }
             // advance every computed level from the previous tick's fronts
@@ -126,24 +138,28 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
                     f[lv] = top;
                 }
             }
-            // encode the next finished output group
+            // encode the next finished output group (never across a block end,
+            // so that the write-back of every block completes with one group)
             int64_t fo = nz;
             for (int fld : out_fields) {
                 const int lv = out_ring(fld, kr);
                 fo = std::min(fo, lv < nin ? prev[0] : prev[lv]);
             }
-            int64_t e = fo >= a[i + 1] ? a[i + 1] : a[i] + (fo - a[i]) / align * align;
+            const int ob = block_of(out_front);
+            const int64_t bend = a[ob + 1];
+            int64_t e = fo >= bend ? bend : out_front + (fo - out_front) / align * align;
             e = std::min(e, out_front + G);
             if (e > out_front) {
                 t.out_group = (int64_t)s.out_groups.size();
                 t.ez0 = out_front;
                 t.ez1 = e;
-                t.last_out_of_block = e == a[i + 1];
-                s.out_groups.push_back({out_front, e, (int64_t)s.ticks.size(), i, t.last_out_of_block});
+                t.out_block = ob;
+                t.last_out_of_block = e == bend;
+                s.out_groups.push_back({out_front, e, (int64_t)s.ticks.size(), ob, t.last_out_of_block});
                 out_front = e;
             }
             if (t.in_group < 0 && t.levels.empty() && t.out_group < 0) {
-                err = fmt("schedule stalled in block %lld", i);
+                err = fmt("schedule stalled in pass %lld", pi);
                 return OOCS_E_STATE;
             }
             s.ticks.push_back(std::move(t));
@@ -317,7 +333,7 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
         if (osl >= 0)
             for (int fld : out_fields) {
                 oocs_op e = op(OOCS_OP_ENCODE, 1);
-                e.field = fld; e.slot = osl; e.level = out_ring(fld, kr); e.z0 = t.ez0; e.z1 = t.ez1; e.block = t.block; e.tick = (int)ti;
+                e.field = fld; e.slot = osl; e.level = out_ring(fld, kr); e.z0 = t.ez0; e.z1 = t.ez1; e.block = t.out_block; e.tick = (int)ti;
                 s.ops.push_back(e);
             }
         { oocs_op l = op(OOCS_OP_LAUNCH, 1); l.tick = (int)ti; l.block = t.block; s.ops.push_back(l); }
@@ -327,13 +343,13 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
             oocs_op w = op(OOCS_OP_WAIT, 2); w.event = ev_encoded(osl); w.tick = (int)ti; s.ops.push_back(w);
             for (int fld : out_fields) {
                 oocs_op c = op(OOCS_OP_D2H, 2);
-                c.field = fld; c.slot = osl; c.z0 = t.ez0; c.z1 = t.ez1; c.block = t.block; c.tick = (int)ti;
+                c.field = fld; c.slot = osl; c.z0 = t.ez0; c.z1 = t.ez1; c.block = t.out_block; c.tick = (int)ti;
                 c.level = out_ring(fld, kr);
                 s.ops.push_back(c);
             }
             oocs_op r3 = op(OOCS_OP_RECORD, 2); r3.event = ev_stored(osl); r3.tick = (int)ti; s.ops.push_back(r3);
             if (t.last_out_of_block) {
-                oocs_op r4 = op(OOCS_OP_RECORD, 2); r4.event = ev_blk_cur(t.block); r4.tick = (int)ti; r4.block = t.block;
+                oocs_op r4 = op(OOCS_OP_RECORD, 2); r4.event = ev_blk_cur(t.out_block); r4.tick = (int)ti; r4.block = t.out_block;
                 s.ops.push_back(r4);
             }
         }

@@ -7,8 +7,8 @@
 // Separate compression (Sec. V-A): R_i and C_i are independent chunks of
 // the host store.
 //
-// Streaming inside a block: a residency never holds a whole block. It
-// streams the block through the device in groups of G planes. Every time
+// Streaming: a residency never holds a whole block. It streams planes
+// through the device in groups of G planes. Every time
 // level of the residency has a ring of planes; a level advances at most G
 // planes per tick, one radius behind the level it reads, so that all jobs
 // of a tick (decode the next input group, one z-range of every level,
@@ -38,6 +38,7 @@ struct Tick {
     std::vector<LevelRange> levels;
     int64_t out_group = -1;  // encoded this tick (all output fields), or -1
     int64_t ez0 = 0, ez1 = 0;
+    int32_t out_block = 0;   // block the encoded group belongs to
     bool last_out_of_block = false;
 };
 
@@ -75,6 +76,7 @@ public:
     bool has_ro = false;
     int n = 1;         // slabs
     int k = 1;
+    bool restart = false;    // every block restarts the level fronts (halo recomputed)
     int64_t slab = 0, h = 0;
     std::vector<int64_t> a;  // n+1 block bounds
 

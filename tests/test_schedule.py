@@ -267,16 +267,49 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
     ((512, 32, 32), HEAT7, 8, 4, [8], 4 * MiB, 12),
     ((1024, 16, 16), WAVE25, 8, 12, [8, 8, 8], 64 * MiB, 36),
 ])
-def test_schedule_has_no_races(shape, st, n, k, rates, arena, steps):
-    p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None)
+@pytest.mark.parametrize("restart", [False, True])
+def test_schedule_has_no_races(shape, st, n, k, rates, arena, steps, restart):
+    p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, block_restart=restart)
     race_check(p, steps)
     race_check(p, steps, graph_mode=True)
 
 
-def test_full_size_heat_schedule_has_no_races():
-    p = plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB)
+@pytest.mark.parametrize("restart", [False, True])
+def test_full_size_heat_schedule_has_no_races(restart):
+    p = plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB, block_restart=restart)
     race_check(p, 12)
     race_check(p, 12, graph_mode=True)
+
+
+@pytest.mark.parametrize("shape,st,n,k,rates", [((512, 64, 64), HEAT7, 8, 4, [8]),
+                                                ((1024, 32, 32), WAVE25, 8, 12, [8, 8, 8])])
+def test_level_work_with_and_without_block_restarts(shape, st, n, k, rates):
+    """Shared levels compute every plane of every level once per residency;
+    block restarts compute each block's shrinking extended range
+    [a_i - h + s r, a_{i+1} + h - s r) at step s (Fig. 2), so the halo
+    planes are computed twice."""
+    nz = shape[0]
+    slab = nz // n
+    r = 1 if st == HEAT7 else 4
+    h = r * k
+    nin = 1 if st == HEAT7 else 2
+    for restart in (False, True):
+        p = plan(shape, st, n, k, rates, 1 << 30, block_restart=restart)
+        cover = {}
+        for o in p.schedule(k):
+            if o["kind"] == L.OP_LEVEL:
+                c = cover.setdefault(o["level"], np.zeros(nz, dtype=int))
+                c[o["z0"]:o["z1"]] += 1
+        assert sorted(cover) == list(range(nin, nin + k))
+        for lv, c in cover.items():
+            s = lv - nin + 1
+            want = np.zeros(nz, dtype=int)
+            if restart:
+                for i in range(n):
+                    want[max(i * slab - h + s * r, 0):min((i + 1) * slab + h - s * r, nz)] += 1
+            else:
+                want[:] = 1
+            assert np.array_equal(c, want), (restart, lv)
 
 
 # ---------------------------------------------------------------------------
@@ -380,10 +413,11 @@ def from_store(s, shape, rate):
 
 @pytest.mark.parametrize("rate,k,steps,arena", [(0, 2, 9, MiB // 4), (8, 4, 11, 2 * MiB), (16, 4, 8, 2 * MiB),
                                                 (5, 8, 17, 1 * MiB)])
-def test_heat_schedule_computes_the_replay(rate, k, steps, arena):
+@pytest.mark.parametrize("restart", [False, True])
+def test_heat_schedule_computes_the_replay(rate, k, steps, arena, restart):
     shape = (48, 12, 16)
     n = 4 if k < 8 else 2
-    p = plan(shape, HEAT7, n, k, [rate], arena)
+    p = plan(shape, HEAT7, n, k, [rate], arena, block_restart=restart)
     u0 = np.random.default_rng(rate).random(shape, dtype=np.float32)
     store = [to_store(u0, rate)]
     # the initial store passes the field through the codec once
@@ -394,7 +428,8 @@ def test_heat_schedule_computes_the_replay(rate, k, steps, arena):
 
 
 @pytest.mark.parametrize("rates,k,steps", [([0, 0, 0], 3, 7), ([8, 12, 6], 3, 8), ([16, 16, 0], 1, 3), ([12, 12, 12], 4, 9)])
-def test_wave_schedule_computes_the_replay(rates, k, steps):
+@pytest.mark.parametrize("restart", [False, True])
+def test_wave_schedule_computes_the_replay(rates, k, steps, restart):
     shape = (64, 12, 12)
     rng = np.random.default_rng(k)
     p0 = rng.standard_normal(shape).astype(np.float32)
@@ -402,7 +437,7 @@ def test_wave_schedule_computes_the_replay(rates, k, steps):
     w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
     amps = rng.standard_normal(steps).astype(np.float32)
     src = (5, 6, 20)
-    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src)
+    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src, block_restart=restart)
     store = [to_store(p0, rates[0]), to_store(pm0, rates[1]), to_store(w, rates[2])]
     execute(p, store, steps, amps)
     got_p = from_store(store[0], shape, rates[0])
