@@ -65,8 +65,9 @@ def measured_traffic():
     return c.get("hbm_bytes_per_launch")
 
 
-def run_variant(api, torch, u0, rate, steps, warmup):
+def run_variant(api, torch, u0, rate, steps, warmup, graphs):
     plan = api.OutOfCorePlan(SHAPE, api.HEAT7, NSLABS, K, [rate], CAP, alpha=ALPHA)
+    plan.set_graphs(graphs)
     store = plan.new_store(0)
     plan.put(0, u0, store)
     for _ in range(warmup):
@@ -218,6 +219,8 @@ def main():
     ap.add_argument("--rates", default=",".join(str(r) for r in VARIANTS),
                     help="comma-separated rates to time (0 = uncompressed)")
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
+    ap.add_argument("--graphs", type=int, default=0,
+                    help="1: replay each residency as a HIP graph; 0: issue it on the three streams directly")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -238,7 +241,7 @@ def main():
     rates = [int(r) for r in args.rates.split(",")]
     results = {}
     for r in rates:
-        results[r] = run_variant(api, torch, u0, r, args.steps, args.warmup)
+        results[r] = run_variant(api, torch, u0, r, args.steps, args.warmup, bool(args.graphs))
         print(f"# rate {r}: {results[r]['gcells_per_s']:.1f} GCell-updates/s, "
               f"{results[r]['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
     head = results.get(HEADLINE_RATE, results[rates[-1]])

@@ -166,7 +166,7 @@ typedef struct {
     int32_t rate[OOCS_MAX_FIELDS];  /* bits per value of each field's host store; 0 = uncompressed */
     int32_t nstage;                 /* staging slots per direction (>= 2); 0 = default (3) */
     float alpha;                    /* heat diffusion number (u += alpha * Laplacian) */
-    int32_t flags;                  /* 0 or OOCS_PLAN_BLOCK_RESTART */
+    int32_t flags;                  /* OOCS_PLAN_* flags, or 0 */
     int64_t src_x, src_y, src_z;    /* wave source cell; any < 0 = no source */
 } oocs_config;
 
@@ -181,6 +181,21 @@ typedef struct {
  * the work and the tick count. The host store layout, the R_i / C_i
  * chunks and the write-back order are the same. */
 #define OOCS_PLAN_BLOCK_RESTART 1
+
+/* Plan flag: how groups cross the host link (Sec. V-B).
+ * Without it (default) the pipeline kernel moves them itself: each launch
+ * holds, next to the decode, level and encode jobs of its tick, a FETCH job
+ * that copies the next input group from the pinned host store into a device
+ * staging slot and a STORE job that copies the previous tick's encoded
+ * group from its staging slot into the host store. Everything runs on one
+ * stream as one launch per tick, so the host issues nothing else, and the
+ * copies overlap the tick's compute inside the launch. The host stores must
+ * then be pinned host memory that the device can address (hipHostMalloc,
+ * or a torch tensor allocated with pin_memory=True).
+ * With it, the copies are hipMemcpyAsync calls on two copy streams (one per
+ * direction) ordered against the compute stream with events, as in the
+ * paper's three-stream pipeline. Both give bit-identical host stores. */
+#define OOCS_PLAN_COPY_ENGINES 2
 
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be
@@ -224,7 +239,9 @@ int oocs_plan_slab(const oocs_plan* plan, int i, oocs_slab_info* out);
 /* The per-residency schedule as a list of operations on three streams
  * (0 = host-to-device copies, 1 = compute, 2 = device-to-host copies),
  * exposed so that its ordering can be checked without a GPU. kr is the
- * number of steps of the residency (k, or the remainder of the last one). */
+ * number of steps of the residency (k, or the remainder of the last one).
+ * Without OOCS_PLAN_COPY_ENGINES every op is on stream 1 and the copies
+ * are FETCH / STORE jobs of the launches. */
 #define OOCS_OP_H2D 1     /* copy a group of host-store planes into an input staging slot */
 #define OOCS_OP_DECODE 2  /* decode (or copy, if uncompressed) a staging slot into a level ring */
 #define OOCS_OP_LEVEL 3   /* compute planes [z0, z1) of one time level */
@@ -233,6 +250,8 @@ int oocs_plan_slab(const oocs_plan* plan, int i, oocs_slab_info* out);
 #define OOCS_OP_LAUNCH 6  /* issue the jobs accumulated on the compute stream as one kernel launch */
 #define OOCS_OP_RECORD 7  /* record event `event` on `stream` */
 #define OOCS_OP_WAIT 8    /* make `stream` wait for the last record of `event` */
+#define OOCS_OP_FETCH 9   /* job: copy a group of host-store planes into an input staging slot */
+#define OOCS_OP_STORE 10  /* job: copy an output staging slot to the host store */
 
 typedef struct {
     int32_t kind;    /* OOCS_OP_* */
@@ -281,6 +300,10 @@ typedef struct {
     int64_t launches;
     int64_t codec_bytes, stencil_bytes;
     double kernel_ms;
+    /* FETCH / STORE jobs (kernel-driven transfers): bytes they move across
+     * the host link, which are also the device-memory bytes they write or
+     * read in the staging slots. Included in h2d_bytes / d2h_bytes too. */
+    int64_t xfer_bytes;
 } oocs_stats;
 
 /* Turn per-launch kernel timing on (1) or off (0) for later oocs_run calls
@@ -289,10 +312,10 @@ typedef struct {
  * oocs_stats.kernel_ms. */
 int oocs_plan_set_profiling(oocs_plan* plan, int on);
 
-/* Choose how oocs_run issues a residency (default 1): as one replay of a HIP
+/* Choose how oocs_run issues a residency (default 0): as one replay of a HIP
  * graph built once per residency length and set of host stores (1), or op by
- * op on the three streams with events (0). Both run the same kernels with the
- * same parameters; graph replays of consecutive residencies do not overlap. */
+ * op on the streams (0). Both run the same kernels with the same parameters;
+ * graph replays of consecutive residencies do not overlap. */
 int oocs_plan_set_graphs(oocs_plan* plan, int on);
 
 /* Advance the out-of-core state held in the host stores h_store[field]
@@ -301,7 +324,10 @@ int oocs_plan_set_graphs(oocs_plan* plan, int on);
  * the source cell when the field after the s-th step of this call is
  * formed (s = 0 .. steps-1); h_src holds `steps` values or is NULL. Host
  * stores are updated in place. Blocks until done; st may be NULL.
- * Errors: OOCS_E_ARG, OOCS_E_STATE (planning-only plan), OOCS_E_HIP. */
+ * Without OOCS_PLAN_COPY_ENGINES the kernels read and write the stores
+ * directly, so each must be pinned, device-addressable host memory.
+ * Errors: OOCS_E_ARG (also: a store the device cannot address), OOCS_E_STATE
+ * (planning-only plan), OOCS_E_HIP. */
 int oocs_run(oocs_plan* plan, void* const* h_store, int64_t steps, const float* h_src, oocs_stats* st);
 
 /* ------------------------------------------------------------------------

@@ -25,8 +25,9 @@ OOCS_WAVE25 = 2
 OOCS_MAX_FIELDS = 3
 OOCS_MAX_RATE = 34
 OOCS_PLAN_BLOCK_RESTART = 1
+OOCS_PLAN_COPY_ENGINES = 2
 
-OP_H2D, OP_DECODE, OP_LEVEL, OP_ENCODE, OP_D2H, OP_LAUNCH, OP_RECORD, OP_WAIT = range(1, 9)
+OP_H2D, OP_DECODE, OP_LEVEL, OP_ENCODE, OP_D2H, OP_LAUNCH, OP_RECORD, OP_WAIT, OP_FETCH, OP_STORE = range(1, 11)
 
 
 class OocsError(RuntimeError):
@@ -88,7 +89,7 @@ class Stats(C.Structure):
         ("wall_ms", C.c_double), ("enqueue_ms", C.c_double), ("rounds", C.c_int64),
         ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("cell_updates", C.c_int64),
         ("launches", C.c_int64), ("codec_bytes", C.c_int64), ("stencil_bytes", C.c_int64),
-        ("kernel_ms", C.c_double),
+        ("kernel_ms", C.c_double), ("xfer_bytes", C.c_int64),
     ]
 
 

@@ -153,6 +153,7 @@ class RunStats:
     codec_bytes: int
     stencil_bytes: int
     kernel_ms: float
+    xfer_bytes: int
 
     @property
     def gcells_per_s(self) -> float:
@@ -164,11 +165,18 @@ class OutOfCorePlan:
     of device memory (one torch allocation made here, handed to the library).
 
     Field slots: heat uses 0 (u); the wave uses 0 = p(n), 1 = p(n-1),
-    2 = w (read-only)."""
+    2 = w (read-only).
+
+    block_restart: every block restarts the level fronts and recomputes its
+    halo (the per-block schedule of Fig. 2) instead of sharing every level's
+    planes with its neighbour. copy_engines: move groups with hipMemcpyAsync
+    on two copy streams (the three-stream pipeline of Sec. V-B) instead of
+    transfer jobs inside the pipeline kernel. Results are identical."""
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
-                 planning_only: bool = False, device=None, block_restart: bool = False):
+                 planning_only: bool = False, device=None, block_restart: bool = False,
+                 copy_engines: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -180,7 +188,7 @@ class OutOfCorePlan:
             cfg.rate[i] = rates[i] if i < len(rates) else 0
         cfg.nstage = nstage
         cfg.alpha = alpha
-        cfg.flags = L.OOCS_PLAN_BLOCK_RESTART if block_restart else 0
+        cfg.flags = (L.OOCS_PLAN_BLOCK_RESTART if block_restart else 0) | (L.OOCS_PLAN_COPY_ENGINES if copy_engines else 0)
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg

@@ -54,7 +54,7 @@ bool dims_ok4(int64_t nx, int64_t ny, int64_t nz) { return nx > 0 && ny > 0 && n
 struct ResidencyGraph {
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> timing;  // start/end pairs around each kernel node (profiling)
-    int64_t launches = 0, codec_bytes = 0, stencil_bytes = 0, h2d = 0, d2h = 0;
+    int64_t launches = 0, codec_bytes = 0, stencil_bytes = 0, xfer_bytes = 0, h2d = 0, d2h = 0;
 };
 
 struct oocs_plan {
@@ -65,7 +65,7 @@ struct oocs_plan {
     hipStream_t st[3] = {nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> ev;  // 4*nstage logical + 2*n block events (two parities)
     bool profiling = false;
-    bool graphs = true;
+    bool graphs = false;
     std::vector<hipEvent_t> tev;  // eager timing events, two per launch, grown on demand
     // graphs by (residency length, store pointers, source on)
     std::map<std::tuple<int, const void*, const void*, const void*, bool, bool>, ResidencyGraph> gcache;
@@ -422,6 +422,8 @@ static int64_t job_bytes(const oocs::Job& j, int64_t plane_elems)
     case oocs::JOB_WAVE: return planes * pb * 4;        // read p, p(n-1), w; write p(n+1)
     case oocs::JOB_DECODE:
     case oocs::JOB_ENCODE: return planes * (pb + plane_elems * j.rate / 8);
+    case oocs::JOB_FETCH:
+    case oocs::JOB_STORE: return j.bytes;               // staging side; the other side is the host link
     default: return planes * pb * 2;                    // raw copies
     }
 }
@@ -443,10 +445,12 @@ namespace {
 struct OpTranslator {
     oocs_plan* pl;
     void* const* h_store;
+    void* const* d_store;  // device addresses of the host stores (kernel-driven transfers), or null
     bool src_on;
     oocs::LaunchParams lp;
+    int64_t h2d = 0, d2h = 0;  // bytes of the transfer jobs added so far
 
-    OpTranslator(oocs_plan* p, void* const* hs, bool src) : pl(p), h_store(hs), src_on(src)
+    OpTranslator(oocs_plan* p, void* const* hs, void* const* ds, bool src) : pl(p), h_store(hs), d_store(ds), src_on(src)
     {
         const oocs::Planner& P = pl->P;
         lp = base_params(P.nx, P.ny, P.nz, P.cfg.alpha, P.cfg.src_x, P.cfg.src_y, P.cfg.src_z);
@@ -479,7 +483,16 @@ struct OpTranslator {
         std::memset(&j, 0, sizeof j);
         j.z0 = (int32_t)o.z0;
         j.z1 = (int32_t)o.z1;
-        if (o.kind == OOCS_OP_LEVEL) {
+        if (o.kind == OOCS_OP_FETCH || o.kind == OOCS_OP_STORE) {
+            const bool in = o.kind == OOCS_OP_FETCH;
+            const int64_t spb = P.store_plane_bytes(o.field);
+            j.kind = in ? oocs::JOB_FETCH : oocs::JOB_STORE;
+            j.bytes = (o.z1 - o.z0) * spb;
+            j.host = static_cast<char*>(d_store[o.field]) + o.z0 * spb;
+            j.stage = in ? (void*)(pl->arena + P.in_off[o.field] + (int64_t)o.slot * P.in_slot_bytes[o.field])
+                         : (void*)(pl->arena + P.out_off[o.field] + (int64_t)o.slot * P.out_slot_bytes[o.field]);
+            (in ? h2d : d2h) += j.bytes;
+        } else if (o.kind == OOCS_OP_LEVEL) {
             j.src = ring(o.level - 1);
             j.dst = ring(o.level);
             if (P.cfg.stencil == OOCS_HEAT7) {
@@ -502,15 +515,19 @@ struct OpTranslator {
         }
         return true;
     }
-    void count_bytes(int64_t* codec, int64_t* stencil) const
+    // algorithmic device-memory bytes of the pending launch: codec, stencil and copy, transfer jobs
+    void count_bytes(int64_t* codec, int64_t* stencil, int64_t* xfer) const
     {
-        for (int i = 0; i < lp.njobs; ++i)
-            (oocs::is_codec_job(lp.jobs[i].kind) ? *codec : *stencil) += job_bytes(lp.jobs[i], pl->P.plane_elems());
+        for (int i = 0; i < lp.njobs; ++i) {
+            const int kind = lp.jobs[i].kind;
+            int64_t* b = oocs::is_codec_job(kind) ? codec : (oocs::is_xfer_job(kind) ? xfer : stencil);
+            *b += job_bytes(lp.jobs[i], pl->P.plane_elems());
+        }
     }
 };
 
 // Builds the graph of one residency of kr steps.
-int build_graph(oocs_plan* pl, int kr, void* const* h_store, bool src_on, ResidencyGraph& out)
+int build_graph(oocs_plan* pl, int kr, void* const* h_store, void* const* d_store, bool src_on, ResidencyGraph& out)
 {
     oocs::Planner& P = pl->P;
     std::string err;
@@ -530,7 +547,7 @@ int build_graph(oocs_plan* pl, int kr, void* const* h_store, bool src_on, Reside
         pending[s].clear();
         return d;
     };
-    OpTranslator tr(pl, h_store, src_on);
+    OpTranslator tr(pl, h_store, d_store, src_on);
     for (const oocs_op& o : sch->ops) {
         switch (o.kind) {
         case OOCS_OP_H2D:
@@ -553,11 +570,13 @@ int build_graph(oocs_plan* pl, int kr, void* const* h_store, bool src_on, Reside
         case OOCS_OP_DECODE:
         case OOCS_OP_ENCODE:
         case OOCS_OP_LEVEL:
+        case OOCS_OP_FETCH:
+        case OOCS_OP_STORE:
             if (!tr.add_job(o)) return fail(OOCS_E_STATE, "too many jobs in a tick");
             break;
         case OOCS_OP_LAUNCH: {
             if (tr.lp.njobs == 0) break;
-            tr.count_bytes(&out.codec_bytes, &out.stencil_bytes);
+            tr.count_bytes(&out.codec_bytes, &out.stencil_bytes, &out.xfer_bytes);
             std::vector<hipGraphNode_t> d = deps_of(1);
             if (pl->profiling) {
                 hipEvent_t e0, e1;
@@ -607,6 +626,8 @@ int build_graph(oocs_plan* pl, int kr, void* const* h_store, bool src_on, Reside
         last[1] = n;
     }
     HIP_TRY(hipGraphInstantiate(&out.exec, g, nullptr, nullptr, 0));
+    out.h2d += tr.h2d;
+    out.d2h += tr.d2h;
     return OOCS_OK;
 }
 
@@ -629,7 +650,18 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     // the source table holds a whole number of residencies
     const int64_t chunk_steps = src_on ? oocs::Planner::kSrcTable / P.k * P.k : steps;
     int64_t h2d = 0, d2h = 0, rounds = 0, launches = 0;
-    int64_t kbytes[2] = {0, 0};  // codec jobs, stencil jobs
+    int64_t kbytes[3] = {0, 0, 0};  // codec jobs, stencil and copy jobs, transfer jobs
+    // kernel-driven transfers address the host stores from the device
+    void* d_store[OOCS_MAX_FIELDS] = {nullptr, nullptr, nullptr};
+    if (!P.copy_engines)
+        for (int f = 0; f < P.nfields; ++f) {
+            if (!h_store[f]) continue;
+            if (hipHostGetDevicePointer(&d_store[f], h_store[f], 0) != hipSuccess || !d_store[f]) {
+                (void)hipGetLastError();
+                return fail(OOCS_E_ARG, "host store of field " + std::to_string(f) +
+                                            " is not pinned host memory the device can address");
+            }
+        }
     double kms = 0.0;
     size_t tused = 0;
     const int ns = P.nstage;
@@ -655,7 +687,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                 auto it = pl->gcache.find(key);
                 if (it == pl->gcache.end()) {
                     ResidencyGraph rg;
-                    const int rc = build_graph(pl, kr, h_store, src_on, rg);
+                    const int rc = build_graph(pl, kr, h_store, d_store, src_on, rg);
                     if (rc != OOCS_OK) {
                         if (rg.exec) (void)hipGraphExecDestroy(rg.exec);
                         for (hipEvent_t e : rg.timing) (void)hipEventDestroy(e);
@@ -670,6 +702,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                 launches += rg.launches;
                 kbytes[0] += rg.codec_bytes;
                 kbytes[1] += rg.stencil_bytes;
+                kbytes[2] += rg.xfer_bytes;
                 if (pl->profiling) {  // the timing events hold this replay's times once it completes
                     HIP_TRY(hipStreamSynchronize(pl->st[1]));
                     for (size_t i = 0; i + 1 < rg.timing.size(); i += 2) {
@@ -688,7 +721,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                     const int par = prev ? 1 - parity : parity;
                     return pl->ev[4 * ns + par * P.n + i];
                 };
-                OpTranslator tr(pl, h_store, src_on);
+                OpTranslator tr(pl, h_store, d_store, src_on);
                 for (const oocs_op& o : sch->ops) {
                     switch (o.kind) {
                     case OOCS_OP_H2D:
@@ -708,11 +741,13 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                     case OOCS_OP_DECODE:
                     case OOCS_OP_ENCODE:
                     case OOCS_OP_LEVEL:
+                    case OOCS_OP_FETCH:
+                    case OOCS_OP_STORE:
                         if (!tr.add_job(o)) return fail(OOCS_E_STATE, "too many jobs in a tick");
                         break;
                     case OOCS_OP_LAUNCH:
                         if (tr.lp.njobs > 0) {
-                            tr.count_bytes(&kbytes[0], &kbytes[1]);
+                            tr.count_bytes(&kbytes[0], &kbytes[1], &kbytes[2]);
                             if (pl->profiling) {
                                 while (pl->tev.size() < tused + 2) {
                                     hipEvent_t e;
@@ -742,6 +777,8 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                     }
                 }
                 if (src_on) HIP_TRY(oocs::launch_step_ctr(step_ctr, true, kr, pl->st[1]));
+                h2d += tr.h2d;
+                d2h += tr.d2h;
             }
             done += kr;
             ++rounds;
@@ -766,6 +803,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
         st->launches = launches;
         st->codec_bytes = kbytes[0];
         st->stencil_bytes = kbytes[1];
+        st->xfer_bytes = kbytes[2];
         st->kernel_ms = kms;
     }
     return OOCS_OK;

@@ -29,7 +29,9 @@ enum JobKind : int32_t {
     JOB_DECODE = 3,  // staging (compressed words) -> ring planes
     JOB_ENCODE = 4,  // ring planes -> staging (compressed words)
     JOB_COPY_IN = 5, // staging (raw planes) -> ring planes
-    JOB_COPY_OUT = 6 // ring planes -> staging (raw planes)
+    JOB_COPY_OUT = 6,// ring planes -> staging (raw planes)
+    JOB_FETCH = 7,   // host store bytes -> staging slot
+    JOB_STORE = 8    // staging slot -> host store bytes
 };
 
 // One job of a fused launch. For stencil jobs src = level l-1, src2 = level
@@ -44,7 +46,9 @@ struct Job {
     int32_t src_off;   // else the amplitude is src_table[*step_ctr + src_off]
     int32_t wg_count;  // workgroups of this job
     Ring src, src2, ro, dst;  // stencil jobs (dst doubles as `ring` for codec/copy jobs)
-    void* stage;              // codec/copy jobs
+    void* stage;              // codec/copy/transfer jobs
+    void* host;               // transfer jobs: device address of the host-store bytes
+    int64_t bytes;            // transfer jobs: bytes to move (a multiple of 8)
 };
 
 constexpr int kMaxJobs = 24;
@@ -69,6 +73,9 @@ int32_t job_workgroups(const Job& j, int nx, int ny);
 
 // True for the decode and encode jobs.
 bool is_codec_job(int kind);
+
+// True for the host-link transfer jobs (FETCH / STORE).
+inline bool is_xfer_job(int kind) { return kind == JOB_FETCH || kind == JOB_STORE; }
 
 // Launch the fused kernel for the jobs in p (reorders p.jobs so that codec
 // jobs come first; fills p.wg_begin).

@@ -19,6 +19,8 @@ static_assert(sizeof(LaunchParams) <= 4096, "kernel arguments must stay within 4
 
 constexpr int kWavesPerWG = kBlockThreads / 64;
 constexpr int kCopyFloat4PerThread = 4;
+constexpr int kHeatBatch = 8;  // planes whose loads a heat thread issues together
+constexpr int kWaveBatch = 2;  // same for the wave
 
 extern __shared__ uint64_t dyn_lds[];  // codec jobs: 64 * rate words per wave
 
@@ -104,7 +106,36 @@ __device__ inline void copy_job(const Job& j, int nx, int ny, int wg, bool in)
     }
 }
 
-// All jobs of a tick share one launch. Codec jobs come first in the job list
+// Host-link transfer: `bytes` (a multiple of 8) between the staging slot and
+// the host store, 16 KiB per workgroup in 8-byte words. Every thread issues
+// all its loads before its stores, so a workgroup keeps 16 KiB in flight
+// across the link.
+constexpr int kXferWordsPerThread = 8;
+constexpr int64_t kXferBytesPerWG = (int64_t)kBlockThreads * kXferWordsPerThread * 8;
+
+__device__ inline void xfer_job(const Job& j, int wg)
+{
+    const bool fetch = j.kind == JOB_FETCH;
+    const uint2* src = static_cast<const uint2*>(fetch ? j.host : j.stage);
+    uint2* dst = static_cast<uint2*>(fetch ? j.stage : j.host);
+    const int64_t n = j.bytes / 8;
+    const int64_t base = (int64_t)wg * (kXferBytesPerWG / 8) + threadIdx.x;
+    uint2 v[kXferWordsPerThread];
+#pragma unroll
+    for (int k = 0; k < kXferWordsPerThread; ++k) {
+        const int64_t e = base + (int64_t)k * kBlockThreads;
+        if (e < n) v[k] = src[e];
+    }
+#pragma unroll
+    for (int k = 0; k < kXferWordsPerThread; ++k) {
+        const int64_t e = base + (int64_t)k * kBlockThreads;
+        if (e < n) dst[e] = v[k];
+    }
+}
+
+// All jobs of a tick share one launch. Transfer jobs come first in the job
+// list, so that their link-bound workgroups start at once and run for the
+// whole tick; codec jobs come next
 // so that their workgroups, whose lanes each run a whole block's serial bit
 // coding, are dispatched first and the short stencil workgroups fill the
 // machine around them.
@@ -118,12 +149,14 @@ __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
     switch (j.kind) {
     case JOB_DECODE: codec_job(j, p.nx, p.ny, local, false); break;
     case JOB_ENCODE: codec_job(j, p.nx, p.ny, local, true); break;
-    case JOB_HEAT: stencil::heat_level(j, p.nx, p.ny, p.nz, p.alpha, local); break;
+    case JOB_HEAT: stencil::heat_level<kHeatBatch>(j, p.nx, p.ny, p.nz, p.alpha, local); break;
     case JOB_WAVE:
-        stencil::wave_level(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local);
+        stencil::wave_level<kWaveBatch>(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local);
         break;
     case JOB_COPY_IN: copy_job(j, p.nx, p.ny, local, true); break;
     case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
+    case JOB_FETCH:
+    case JOB_STORE: xfer_job(j, local); break;
     default: break;
     }
 }
@@ -139,12 +172,14 @@ __global__ void __launch_bounds__(kBlockThreads) stencil_kernel(LaunchParams p)
     const Job& j = p.jobs[jdx];
     const int local = wg - p.wg_begin[jdx];
     switch (j.kind) {
-    case JOB_HEAT: stencil::heat_level(j, p.nx, p.ny, p.nz, p.alpha, local); break;
+    case JOB_HEAT: stencil::heat_level<kHeatBatch>(j, p.nx, p.ny, p.nz, p.alpha, local); break;
     case JOB_WAVE:
-        stencil::wave_level(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local);
+        stencil::wave_level<kWaveBatch>(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local);
         break;
     case JOB_COPY_IN: copy_job(j, p.nx, p.ny, local, true); break;
     case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
+    case JOB_FETCH:
+    case JOB_STORE: xfer_job(j, local); break;
     default: break;
     }
 }
@@ -173,19 +208,24 @@ int32_t job_workgroups(const Job& j, int nx, int ny)
         const int64_t per_wg = (int64_t)kBlockThreads * kCopyFloat4PerThread;
         return (int32_t)(((n4 + per_wg - 1) / per_wg) * planes);
     }
+    case JOB_FETCH:
+    case JOB_STORE: return (int32_t)((j.bytes + kXferBytesPerWG - 1) / kXferBytesPerWG);
     default: return 0;
     }
 }
 
-// Orders the jobs (codec first), fills the workgroup prefix sums and picks
-// the kernel. Returns false if there is no work.
+// Orders the jobs (transfers, then codec, then the rest), fills the
+// workgroup prefix sums and picks the kernel. Returns false if there is no
+// work.
+static int dispatch_class(int kind) { return is_xfer_job(kind) ? 0 : (is_codec_job(kind) ? 1 : 2); }
+
 static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, size_t* lds)
 {
     Job sorted[kMaxJobs];
     int n = 0;
-    for (int pass = 0; pass < 2; ++pass)
+    for (int pass = 0; pass < 3; ++pass)
         for (int i = 0; i < p.njobs; ++i)
-            if (is_codec_job(p.jobs[i].kind) == (pass == 0)) sorted[n++] = p.jobs[i];
+            if (dispatch_class(p.jobs[i].kind) == pass) sorted[n++] = p.jobs[i];
     int32_t total = 0;
     int max_rate = 0;
     for (int i = 0; i < n; ++i) {

@@ -53,9 +53,11 @@ int Planner::init(const oocs_config& c, std::string& err)
     }
     if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
-    nstage = c.nstage ? c.nstage : 3;
-    if (c.flags & ~OOCS_PLAN_BLOCK_RESTART) { err = "unknown plan flags"; return OOCS_E_ARG; }
+    if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_COPY_ENGINES)) { err = "unknown plan flags"; return OOCS_E_ARG; }
     restart = (c.flags & OOCS_PLAN_BLOCK_RESTART) != 0;
+    copy_engines = (c.flags & OOCS_PLAN_COPY_ENGINES) != 0;
+    // kernel-driven transfers fetch one group ahead inside the launch: two slots suffice
+    nstage = c.nstage ? c.nstage : (copy_engines ? 3 : 2);
     a.resize(n + 1);
     for (int i = 0; i <= n; ++i) a[i] = (int64_t)i * slab;
     return OOCS_OK;
@@ -296,6 +298,7 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
         o.kind = kind; o.stream = stream; o.event = -1; o.slot = -1; o.field = -1; o.level = -1; o.block = -1; o.tick = -1;
         return o;
     };
+    if (!copy_engines) return emit_direct(kr, s, op);
     auto block_of = [&](int64_t z) { return (int)std::min<int64_t>(z / slab, n - 1); };
     auto emit_h2d = [&](int64_t j, int64_t tick) {
         const GroupRec& g = s.in_groups[j];
@@ -359,6 +362,75 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
     return OOCS_OK;
 }
 
+// Kernel-driven transfers: one launch per tick on stream 1, holding
+// FETCH of the next input group (slot j+1), DECODE of the current one
+// (slot j), the levels, ENCODE of the finished output group (slot m) and
+// STORE of the one encoded before it (slot m-1). A prologue launch fetches
+// the first group and an epilogue launch stores the last one. Launches on
+// one stream are ordered, and no two jobs of a launch touch the same slot,
+// so no events are needed.
+template <class MakeOp>
+int Planner::emit_direct(int kr, Schedule& s, MakeOp op) const
+{
+    const int64_t nin_groups = (int64_t)s.in_groups.size();
+    const int64_t nout_groups = (int64_t)s.out_groups.size();
+    auto fetch = [&](int64_t j, int tick) {
+        const GroupRec& g = s.in_groups[j];
+        for (int fld : in_fields) {
+            oocs_op c = op(OOCS_OP_FETCH, 1);
+            c.field = fld; c.slot = (int)(j % nstage); c.z0 = g.z0; c.z1 = g.z1; c.block = g.block; c.tick = tick;
+            c.level = in_ring(fld);
+            s.ops.push_back(c);
+        }
+    };
+    auto store = [&](int64_t m, int tick) {
+        const GroupRec& g = s.out_groups[m];
+        for (int fld : out_fields) {
+            oocs_op c = op(OOCS_OP_STORE, 1);
+            c.field = fld; c.slot = (int)(m % nstage); c.z0 = g.z0; c.z1 = g.z1; c.block = g.block; c.tick = tick;
+            c.level = out_ring(fld, kr);
+            s.ops.push_back(c);
+        }
+    };
+    auto launch = [&](int tick, int block) { oocs_op l = op(OOCS_OP_LAUNCH, 1); l.tick = tick; l.block = block; s.ops.push_back(l); };
+    if (nin_groups > 0) {
+        fetch(0, -1);
+        launch(-1, s.in_groups[0].block);
+    }
+    for (int64_t ti = 0; ti < (int64_t)s.ticks.size(); ++ti) {
+        const Tick& t = s.ticks[ti];
+        if (t.in_group >= 0) {
+            if (t.in_group + 1 < nin_groups) fetch(t.in_group + 1, (int)ti);
+            for (int fld : in_fields) {
+                oocs_op d = op(OOCS_OP_DECODE, 1);
+                d.field = fld; d.slot = (int)(t.in_group % nstage); d.level = in_ring(fld); d.z0 = t.dz0; d.z1 = t.dz1;
+                d.block = t.block; d.tick = (int)ti;
+                s.ops.push_back(d);
+            }
+        }
+        for (const LevelRange& L : t.levels) {
+            oocs_op l = op(OOCS_OP_LEVEL, 1);
+            l.level = L.lv; l.z0 = L.z0; l.z1 = L.z1; l.block = t.block; l.tick = (int)ti;
+            s.ops.push_back(l);
+        }
+        if (t.out_group >= 0) {
+            for (int fld : out_fields) {
+                oocs_op e = op(OOCS_OP_ENCODE, 1);
+                e.field = fld; e.slot = (int)(t.out_group % nstage); e.level = out_ring(fld, kr); e.z0 = t.ez0; e.z1 = t.ez1;
+                e.block = t.out_block; e.tick = (int)ti;
+                s.ops.push_back(e);
+            }
+            if (t.out_group > 0) store(t.out_group - 1, (int)ti);
+        }
+        launch((int)ti, t.block);
+    }
+    if (nout_groups > 0) {
+        store(nout_groups - 1, (int)s.ticks.size());
+        launch((int)s.ticks.size(), s.out_groups.back().block);
+    }
+    return OOCS_OK;
+}
+
 const Schedule* Planner::schedule(int kr, std::string& err)
 {
     if (kr < 1 || kr > k) { err = "residency length out of range"; return nullptr; }
@@ -368,7 +440,9 @@ const Schedule* Planner::schedule(int kr, std::string& err)
     if (build_ticks(kr, s, err) != OOCS_OK) return nullptr;
     if (emit_ops(kr, s, err) != OOCS_OK) return nullptr;
     for (const Tick& t : s.ticks) {
-        const size_t jobs = t.levels.size() + (t.in_group >= 0 ? in_fields.size() : 0) + (t.out_group >= 0 ? out_fields.size() : 0);
+        const size_t per_in = copy_engines ? 1 : 2, per_out = copy_engines ? 1 : 2;
+        const size_t jobs = t.levels.size() + (t.in_group >= 0 ? per_in * in_fields.size() : 0) +
+                            (t.out_group >= 0 ? per_out * out_fields.size() : 0);
         if (jobs > 24) { err = "too many jobs in one tick"; return nullptr; }
     }
     return &cache_.emplace(kr, std::move(s)).first->second;

@@ -77,6 +77,7 @@ public:
     int n = 1;         // slabs
     int k = 1;
     bool restart = false;    // every block restarts the level fronts (halo recomputed)
+    bool copy_engines = false;  // transfers by hipMemcpyAsync on copy streams, not by the kernel
     int64_t slab = 0, h = 0;
     std::vector<int64_t> a;  // n+1 block bounds
 
@@ -113,6 +114,8 @@ public:
 
 private:
     int emit_ops(int kr, Schedule& s, std::string& err) const;
+    template <class MakeOp>
+    int emit_direct(int kr, Schedule& s, MakeOp op) const;
     std::map<int, Schedule> cache_;
 };
 

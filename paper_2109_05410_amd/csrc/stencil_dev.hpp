@@ -23,6 +23,11 @@ namespace oocs {
 namespace stencil {
 
 // Heat, 7 points: u' = c + alpha * (((xm+xp) + (ym+yp)) + (zm+zp) - 6c).
+// A thread loads the inputs of NB planes before it computes and stores any
+// of them: the loads of a batch are independent of the stores (which the
+// compiler cannot prove for ring pointers), so a wave waits on memory once
+// per batch instead of once per plane.
+template <int NB>
 __device__ inline void heat_level(const Job& j, int nx, int ny, int nz, float alpha, int wg)
 {
     const int tiles_x = (nx + kTileX - 1) / kTileX;
@@ -35,22 +40,41 @@ __device__ inline void heat_level(const Job& j, int nx, int ny, int nz, float al
     const int z1 = min(j.z1, z0 + kZChunk);
     if (x >= nx || y >= ny || z0 >= z1) return;
     const int64_t xy = (int64_t)y * nx + x;
-    auto at = [&](int z) -> const float* { return ring_plane(j.src, z) + xy; };
-    float cm = z0 - 1 >= 0 ? *at(z0 - 1) : 0.0f;
-    float cc = *at(z0);
-    for (int z = z0; z < z1; ++z) {
-        const float cp = z + 1 < nz ? *at(z + 1) : 0.0f;
-        const float* pl = at(z);
-        const float xm = x > 0 ? pl[-1] : 0.0f;
-        const float xp = x + 1 < nx ? pl[1] : 0.0f;
-        const float ym = y > 0 ? pl[-nx] : 0.0f;
-        const float yp = y + 1 < ny ? pl[nx] : 0.0f;
-        float s = (xm + xp) + (ym + yp);
-        s = s + (cm + cp);
-        s = s - 6.0f * cc;
-        ring_plane(j.dst, z)[xy] = cc + alpha * s;
-        cm = cc;
-        cc = cp;
+    const bool hx0 = x > 0, hx1 = x + 1 < nx, hy0 = y > 0, hy1 = y + 1 < ny;
+    float cm = z0 - 1 >= 0 ? ring_plane(j.src, z0 - 1)[xy] : 0.0f;
+    for (int zb = z0; zb < z1; zb += NB) {
+        float c[NB + 1], xm[NB], xp[NB], ym[NB], yp[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            c[i] = xm[i] = xp[i] = ym[i] = yp[i] = 0.0f;
+            if (zb + i < z1) {
+                const float* pl = ring_plane(j.src, zb + i) + xy;
+                c[i] = pl[0];
+                if (hx0) xm[i] = pl[-1];
+                if (hx1) xp[i] = pl[1];
+                if (hy0) ym[i] = pl[-nx];
+                if (hy1) yp[i] = pl[nx];
+            }
+        }
+        // the plane above the last one of the batch
+        const int zt = min(zb + NB, z1);
+        c[NB] = 0.0f;
+#pragma unroll
+        for (int i = 1; i <= NB; ++i)
+            if (zt == zb + i && zt < nz) c[i] = ring_plane(j.src, zt)[xy];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (zb + i < z1) {
+                const float zm = i == 0 ? cm : c[i - 1];
+                const float cc = c[i];
+                const float zp = c[i + 1];
+                float s = (xm[i] + xp[i]) + (ym[i] + yp[i]);
+                s = s + (zm + zp);
+                s = s - 6.0f * cc;
+                ring_plane(j.dst, zb + i)[xy] = cc + alpha * s;
+            }
+        }
+        cm = c[NB - 1];
     }
 }
 
@@ -93,6 +117,9 @@ __device__ inline void heat_dense(const float* __restrict__ src, float* __restri
 // Wave, 25 points:
 //   acc = C0X3*p;  for m = 1..4: acc = acc + C_m * (((x+m + x-m) + (y+m + y-m)) + (z+m + z-m))
 //   p'  = (2p - pm) + w*acc  (+ amp at the source cell)
+// Each thread keeps the column p(z-4 .. z+NB+3) in registers and loads the
+// x / y neighbours, pm and w of NB planes before computing them.
+template <int NB>
 __device__ inline void wave_level(const Job& j, int nx, int ny, int nz, int sx, int sy, int sz,
                                   const float* src_table, const int32_t* step_ctr, int wg)
 {
@@ -101,6 +128,7 @@ __device__ inline void wave_level(const Job& j, int nx, int ny, int nz, int sx, 
     const float C2 = (float)(-1.0 / 5.0);
     const float C3 = (float)(8.0 / 315.0);
     const float C4 = (float)(-1.0 / 560.0);
+    const float CM[4] = {C1, C2, C3, C4};
     const int tiles_x = (nx + kTileX - 1) / kTileX;
     const int tiles_y = (ny + kTileY - 1) / kTileY;
     const int tile = wg % (tiles_x * tiles_y);
@@ -112,25 +140,47 @@ __device__ inline void wave_level(const Job& j, int nx, int ny, int nz, int sx, 
     if (x >= nx || y >= ny || z0 >= z1) return;
     const int64_t xy = (int64_t)y * nx + x;
     auto col = [&](int z) -> float { return (z >= 0 && z < nz) ? ring_plane(j.src, z)[xy] : 0.0f; };
-    float q0 = col(z0 - 4), q1 = col(z0 - 3), q2 = col(z0 - 2), q3 = col(z0 - 1);
-    float q4 = col(z0), q5 = col(z0 + 1), q6 = col(z0 + 2), q7 = col(z0 + 3);
+    float q[NB + 8];  // q[i] = p(zb - 4 + i)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = col(z0 - 4 + i);
     const bool src_col = j.has_src && x == sx && y == sy;
-    for (int z = z0; z < z1; ++z) {
-        const float q8 = col(z + 4);
-        const float* pl = ring_plane(j.src, z) + xy;
-        auto X = [&](int d) -> float { return (x + d >= 0 && x + d < nx) ? pl[d] : 0.0f; };
-        auto Y = [&](int d) -> float { return (y + d >= 0 && y + d < ny) ? pl[(int64_t)d * nx] : 0.0f; };
-        float acc = C0X3 * q4;
-        acc = acc + C1 * (((X(1) + X(-1)) + (Y(1) + Y(-1))) + (q5 + q3));
-        acc = acc + C2 * (((X(2) + X(-2)) + (Y(2) + Y(-2))) + (q6 + q2));
-        acc = acc + C3 * (((X(3) + X(-3)) + (Y(3) + Y(-3))) + (q7 + q1));
-        acc = acc + C4 * (((X(4) + X(-4)) + (Y(4) + Y(-4))) + (q8 + q0));
-        const float pm = ring_plane(j.src2, z)[xy];
-        const float w = ring_plane(j.ro, z)[xy];
-        float v = (2.0f * q4 - pm) + w * acc;
-        if (src_col && z == sz) v = v + (src_table ? src_table[*step_ctr + j.src_off] : j.amp);
-        ring_plane(j.dst, z)[xy] = v;
-        q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7; q7 = q8;
+    for (int zb = z0; zb < z1; zb += NB) {
+        float xs[NB][8], ys[NB][8], pm[NB], w[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            q[8 + i] = 0.0f;
+            pm[i] = w[i] = 0.0f;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) xs[i][m] = ys[i][m] = 0.0f;
+            if (zb + i < z1) {
+                q[8 + i] = col(zb + i + 4);
+                const float* pl = ring_plane(j.src, zb + i) + xy;
+#pragma unroll
+                for (int m = 1; m <= 4; ++m) {
+                    if (x + m < nx) xs[i][2 * m - 2] = pl[m];
+                    if (x - m >= 0) xs[i][2 * m - 1] = pl[-m];
+                    if (y + m < ny) ys[i][2 * m - 2] = pl[(int64_t)m * nx];
+                    if (y - m >= 0) ys[i][2 * m - 1] = pl[-(int64_t)m * nx];
+                }
+                pm[i] = ring_plane(j.src2, zb + i)[xy];
+                w[i] = ring_plane(j.ro, zb + i)[xy];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (zb + i < z1) {
+                float acc = C0X3 * q[i + 4];
+#pragma unroll
+                for (int m = 1; m <= 4; ++m)
+                    acc = acc + CM[m - 1] * (((xs[i][2 * m - 2] + xs[i][2 * m - 1]) + (ys[i][2 * m - 2] + ys[i][2 * m - 1])) +
+                                             (q[i + 4 + m] + q[i + 4 - m]));
+                float v = (2.0f * q[i + 4] - pm[i]) + w[i] * acc;
+                if (src_col && zb + i == sz) v = v + (src_table ? src_table[*step_ctr + j.src_off] : j.amp);
+                ring_plane(j.dst, zb + i)[xy] = v;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) q[i] = q[i + NB];
     }
 }
 

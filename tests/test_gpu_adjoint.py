@@ -89,9 +89,10 @@ def test_autograd_function():
     ref = api.WaveProblem(shape, steps, amps, cell, rcv, obs, float(c), ckpt_every=10)
     ref.forward(vd.detach())
     assert torch.equal(vd.grad, ref.gradient(vd.detach()))
-    # first-order check in FP32 along the gradient direction
-    d = vd.grad / torch.linalg.norm(vd.grad) * float(torch.linalg.norm(vd.detach())) * 1e-3
+    # first-order check in FP32 along the gradient direction, at most 1 m/s
+    # per cell (velocities are 1500-4500 m/s, so the misfit stays linear)
+    d = vd.grad / torch.max(torch.abs(vd.grad))
     Jp = prob.forward((vd.detach() + d).contiguous())
     Jm = prob.forward((vd.detach() - d).contiguous())
     pred = float(torch.sum(vd.grad * d))
-    assert (Jp - Jm) / 2 == pytest.approx(pred, rel=2e-2)
+    assert (Jp - Jm) / 2 == pytest.approx(pred, rel=1e-2)

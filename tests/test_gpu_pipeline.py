@@ -1,5 +1,6 @@
 """GPU out-of-core pipeline parity (Sec. III region sharing and temporal
-blocking, Sec. V-A separate compression, Sec. V-B three-stream pipeline).
+blocking, Sec. V-A separate compression, Sec. V-B pipelined transfers, both
+as transfer jobs inside the pipeline kernel and on copy-engine streams).
 
 Small grids that span several slabs, several pipeline groups per slab, a
 ragged last residency and rings that wrap: the host store after the run
@@ -34,16 +35,20 @@ def decoded(store, shape, rate):
     return b.view(np.float32).reshape(shape).copy()
 
 
-@pytest.mark.parametrize("graphs", [True, False], ids=["graph", "eager"])
+MODES = [(False, False), (True, False), (False, True), (True, True)]
+MODE_IDS = ["kernel-xfer-eager", "kernel-xfer-graph", "copy-engines-eager", "copy-engines-graph"]
+
+
+@pytest.mark.parametrize("graphs,ce", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("rate,k,steps,n,arena", [
     (0, 4, 10, 8, 2 * MiB), (8, 4, 10, 8, 2 * MiB), (16, 4, 9, 4, 3 * MiB), (5, 4, 7, 2, 64 * MiB),
     (0, 3, 8, 4, 2 * MiB),
     (12, 4, 12, 1, 2 * MiB),
 ])
-def test_heat_out_of_core_matches_replay(rate, k, steps, n, arena, graphs):
+def test_heat_out_of_core_matches_replay(rate, k, steps, n, arena, graphs, ce):
     shape = (128, 64, 64)
     u0 = inputs.heat_uniform(shape, seed=rate + k)
-    plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena, copy_engines=ce)
     plan.set_graphs(graphs)
     s = store_of(plan, 0, u0)
     plan.run([s], steps)
@@ -55,10 +60,10 @@ def test_heat_out_of_core_matches_replay(rate, k, steps, n, arena, graphs):
         assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= 1e-5
 
 
-@pytest.mark.parametrize("graphs", [True, False], ids=["graph", "eager"])
+@pytest.mark.parametrize("graphs,ce", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("rates,k,steps", [([0, 0, 0], 4, 10), ([8, 12, 8], 4, 10), ([16, 16, 16], 3, 7),
                                            ([12, 0, 12], 1, 3)])
-def test_wave_out_of_core_matches_replay(rates, k, steps, graphs):
+def test_wave_out_of_core_matches_replay(rates, k, steps, graphs, ce):
     shape = (96, 36, 40)
     rng = np.random.default_rng(k)
     p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
@@ -66,7 +71,7 @@ def test_wave_out_of_core_matches_replay(rates, k, steps, graphs):
     w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
     amps = rng.standard_normal(steps).astype(np.float32)
     cell = (17, 20, 50)
-    plan = api.OutOfCorePlan(shape, api.WAVE25, 2, k, rates, 16 * MiB, src_cell=cell)
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 2, k, rates, 16 * MiB, src_cell=cell, copy_engines=ce)
     plan.set_graphs(graphs)
     st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
     plan.run(st, steps, src_amps=amps)
@@ -78,6 +83,36 @@ def test_wave_out_of_core_matches_replay(rates, k, steps, graphs):
     assert np.array_equal(decoded(st[1], shape, rates[1]), wpm)
     # the read-only store is never rewritten
     assert np.array_equal(decoded(st[2], shape, rates[2]), O.codec_roundtrip(w, rates[2]) if rates[2] else w)
+
+
+@pytest.mark.parametrize("graphs,ce", MODES, ids=MODE_IDS)
+def test_block_restart_schedule_matches_replay(graphs, ce):
+    """The per-block schedule with recomputed halos (Fig. 2) and the shared-level
+    schedule give the same bits."""
+    shape = (128, 64, 64)
+    u0 = inputs.heat_uniform(shape, seed=3)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, 8, 4, [8], 2 * MiB, block_restart=True, copy_engines=ce)
+    plan.set_graphs(graphs)
+    s = store_of(plan, 0, u0)
+    plan.run([s], 10)
+    assert np.array_equal(decoded(s, shape, 8), O.replay_heat_f32(u0, 0.1, 10, 4, 8))
+    shape = (96, 36, 40)
+    rng = np.random.default_rng(5)
+    p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    pm0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    amps = rng.standard_normal(9).astype(np.float32)
+    cell = (17, 20, 50)
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 2, 4, [8, 12, 8], 16 * MiB, src_cell=cell, block_restart=True,
+                             copy_engines=ce)
+    plan.set_graphs(graphs)
+    st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
+    plan.run(st, 9, src_amps=amps)
+    nz, ny, nx = shape
+    idx = cell[0] + nx * (cell[1] + ny * cell[2])
+    wp, wpm, _ = O.replay_wave_f32(p0, pm0, w, 9, 4, src=(amps, idx), rate_p=8, rate_pm=12, rate_w=8)
+    assert np.array_equal(decoded(st[0], shape, 8), wp)
+    assert np.array_equal(decoded(st[1], shape, 12), wpm)
 
 
 def test_repeated_runs_continue_the_state():
@@ -102,6 +137,7 @@ def test_graph_replays_with_profiling_match_eager():
     plan = api.OutOfCorePlan(shape, api.HEAT7, 4, 4, [8], 4 * MiB)
     a = store_of(plan, 0, u0)
     b = store_of(plan, 0, u0)
+    plan.set_graphs(True)
     plan.set_profiling(True)
     st = plan.run([a], 14)
     assert st.kernel_ms > 0 and st.launches > 0

@@ -95,13 +95,13 @@ def test_region_sharing_loads_each_plane_once_per_residency():
         for f in range(len(rates)):
             planes = np.zeros(shape[0], dtype=int)
             for o in ops:
-                if o["kind"] == L.OP_H2D and o["field"] == f:
+                if o["kind"] in (L.OP_H2D, L.OP_FETCH) and o["field"] == f:
                     planes[o["z0"]:o["z1"]] += 1
             assert np.all(planes == 1)
         for f in ([0] if st == HEAT7 else [0, 1]):
             planes = np.zeros(shape[0], dtype=int)
             for o in ops:
-                if o["kind"] == L.OP_D2H and o["field"] == f:
+                if o["kind"] in (L.OP_D2H, L.OP_STORE) and o["field"] == f:
                     planes[o["z0"]:o["z1"]] += 1
             assert np.all(planes == 1)
 
@@ -110,11 +110,12 @@ def test_separate_write_back_pairs_remainder_and_previous_common_region():
     """After block i the planes written back are C_{i-1} (upper half) and
     R_i, and the lower half of C_i (Fig. 3b): the write-back of block i
     covers [a_i, a_{i+1}) and nothing else."""
-    p = plan((512, 32, 32), HEAT7, 8, 4, [8], 1 << 30)
-    for o in p.schedule(4):
-        if o["kind"] == L.OP_D2H:
-            assert 64 * o["block"] <= o["z0"] < o["z1"] <= 64 * (o["block"] + 1)
-            assert o["z0"] % 4 == 0 and o["z1"] % 4 == 0
+    for ce in (False, True):
+        p = plan((512, 32, 32), HEAT7, 8, 4, [8], 1 << 30, copy_engines=ce)
+        for o in p.schedule(4):
+            if o["kind"] in (L.OP_D2H, L.OP_STORE):
+                assert 64 * o["block"] <= o["z0"] < o["z1"] <= 64 * (o["block"] + 1)
+                assert o["z0"] % 4 == 0 and o["z1"] % 4 == 0
 
 
 # ---------------------------------------------------------------------------
@@ -139,10 +140,10 @@ def accesses(o, g):
     """(resource, is_write) pairs of one op."""
     K = o["kind"]
     out = []
-    if K == L.OP_H2D:
+    if K in (L.OP_H2D, L.OP_FETCH):
         out.append((("in", o["field"], o["slot"]), True))
         out += [(("host", o["field"], z), False) for z in range(o["z0"], o["z1"])]
-    elif K == L.OP_D2H:
+    elif K in (L.OP_D2H, L.OP_STORE):
         out.append((("out", o["field"], o["slot"]), False))
         out += [(("host", o["field"], z), True) for z in range(o["z0"], o["z1"])]
     elif K == L.OP_DECODE:
@@ -230,7 +231,8 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
                 c = ev_clock.get(phys(o["event"]))
                 if c is not None:
                     vc[s] = [max(a, b) for a, b in zip(vc[s], c)]
-            elif K in (L.OP_DECODE, L.OP_LEVEL, L.OP_ENCODE):
+            elif K in (L.OP_DECODE, L.OP_LEVEL, L.OP_ENCODE, L.OP_FETCH, L.OP_STORE):
+                assert s == 1
                 pending.append(o)
             elif K == L.OP_LAUNCH:
                 vc[1][1] += 1
@@ -267,16 +269,17 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
     ((512, 32, 32), HEAT7, 8, 4, [8], 4 * MiB, 12),
     ((1024, 16, 16), WAVE25, 8, 12, [8, 8, 8], 64 * MiB, 36),
 ])
-@pytest.mark.parametrize("restart", [False, True])
-def test_schedule_has_no_races(shape, st, n, k, rates, arena, steps, restart):
-    p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, block_restart=restart)
+@pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
+def test_schedule_has_no_races(shape, st, n, k, rates, arena, steps, restart, ce):
+    p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, block_restart=restart,
+             copy_engines=ce)
     race_check(p, steps)
     race_check(p, steps, graph_mode=True)
 
 
-@pytest.mark.parametrize("restart", [False, True])
-def test_full_size_heat_schedule_has_no_races(restart):
-    p = plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB, block_restart=restart)
+@pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
+def test_full_size_heat_schedule_has_no_races(restart, ce):
+    p = plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB, block_restart=restart, copy_engines=ce)
     race_check(p, 12)
     race_check(p, 12, graph_mode=True)
 
@@ -356,7 +359,7 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
         for o in p.schedule(kr):
             K = o["kind"]
             z0, z1 = o["z0"], o["z1"]
-            if K == L.OP_H2D:
+            if K in (L.OP_H2D, L.OP_FETCH):
                 f, rate = o["field"], rates[o["field"]]
                 if rate:
                     stage_in[(f, o["slot"])] = store[f][z0 // 4 * layer_words(rate): z1 // 4 * layer_words(rate)].copy()
@@ -392,7 +395,7 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
                 f, rate = o["field"], rates[o["field"]]
                 planes = np.stack([plane(o["level"], z) for z in range(z0, z1)])
                 stage_out[(f, o["slot"])] = O.codec_encode(planes, rate) if rate else planes.copy()
-            elif K == L.OP_D2H:
+            elif K in (L.OP_D2H, L.OP_STORE):
                 f, rate = o["field"], rates[o["field"]]
                 data = stage_out[(f, o["slot"])]
                 if rate:
@@ -413,11 +416,11 @@ def from_store(s, shape, rate):
 
 @pytest.mark.parametrize("rate,k,steps,arena", [(0, 2, 9, MiB // 4), (8, 4, 11, 2 * MiB), (16, 4, 8, 2 * MiB),
                                                 (5, 8, 17, 1 * MiB)])
-@pytest.mark.parametrize("restart", [False, True])
-def test_heat_schedule_computes_the_replay(rate, k, steps, arena, restart):
+@pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
+def test_heat_schedule_computes_the_replay(rate, k, steps, arena, restart, ce):
     shape = (48, 12, 16)
     n = 4 if k < 8 else 2
-    p = plan(shape, HEAT7, n, k, [rate], arena, block_restart=restart)
+    p = plan(shape, HEAT7, n, k, [rate], arena, block_restart=restart, copy_engines=ce)
     u0 = np.random.default_rng(rate).random(shape, dtype=np.float32)
     store = [to_store(u0, rate)]
     # the initial store passes the field through the codec once
@@ -428,8 +431,8 @@ def test_heat_schedule_computes_the_replay(rate, k, steps, arena, restart):
 
 
 @pytest.mark.parametrize("rates,k,steps", [([0, 0, 0], 3, 7), ([8, 12, 6], 3, 8), ([16, 16, 0], 1, 3), ([12, 12, 12], 4, 9)])
-@pytest.mark.parametrize("restart", [False, True])
-def test_wave_schedule_computes_the_replay(rates, k, steps, restart):
+@pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
+def test_wave_schedule_computes_the_replay(rates, k, steps, restart, ce):
     shape = (64, 12, 12)
     rng = np.random.default_rng(k)
     p0 = rng.standard_normal(shape).astype(np.float32)
@@ -437,7 +440,7 @@ def test_wave_schedule_computes_the_replay(rates, k, steps, restart):
     w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
     amps = rng.standard_normal(steps).astype(np.float32)
     src = (5, 6, 20)
-    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src, block_restart=restart)
+    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src, block_restart=restart, copy_engines=ce)
     store = [to_store(p0, rates[0]), to_store(pm0, rates[1]), to_store(w, rates[2])]
     execute(p, store, steps, amps)
     got_p = from_store(store[0], shape, rates[0])
