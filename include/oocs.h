@@ -164,7 +164,7 @@ typedef struct {
     int32_t k;                      /* steps per residency (temporal blocking), >= 1 */
     int32_t group;                  /* planes per pipeline group (multiple of 4); 0 = largest that fits */
     int32_t rate[OOCS_MAX_FIELDS];  /* bits per value of each field's host store; 0 = uncompressed */
-    int32_t nstage;                 /* staging slots per direction (>= 2); 0 = default (3) */
+    int32_t nstage;                 /* staging slots per direction (>= 2); 0 = default (4, or 2 with kernel transfers) */
     float alpha;                    /* heat diffusion number (u += alpha * Laplacian) */
     int32_t flags;                  /* OOCS_PLAN_* flags, or 0 */
     int64_t src_x, src_y, src_z;    /* wave source cell; any < 0 = no source */
@@ -183,19 +183,21 @@ typedef struct {
 #define OOCS_PLAN_BLOCK_RESTART 1
 
 /* Plan flag: how groups cross the host link (Sec. V-B).
- * Without it (default) the pipeline kernel moves them itself: each launch
- * holds, next to the decode, level and encode jobs of its tick, a FETCH job
- * that copies the next input group from the pinned host store into a device
+ * Without it (default) the copies are hipMemcpyAsync calls on two copy
+ * streams (one per direction) ordered against the compute stream with
+ * events, as in the paper's three-stream pipeline; the copy of a tick's
+ * output and the load that reuses its input slot are issued after the next
+ * tick's launch, when the events they wait for have usually completed.
+ * With it, the pipeline kernel moves the groups itself: each launch holds,
+ * next to the decode, level and encode jobs of its tick, a FETCH job that
+ * copies the next input group from the pinned host store into a device
  * staging slot and a STORE job that copies the previous tick's encoded
- * group from its staging slot into the host store. Everything runs on one
- * stream as one launch per tick, so the host issues nothing else, and the
- * copies overlap the tick's compute inside the launch. The host stores must
- * then be pinned host memory that the device can address (hipHostMalloc,
- * or a torch tensor allocated with pin_memory=True).
- * With it, the copies are hipMemcpyAsync calls on two copy streams (one per
- * direction) ordered against the compute stream with events, as in the
- * paper's three-stream pipeline. Both give bit-identical host stores. */
-#define OOCS_PLAN_COPY_ENGINES 2
+ * group into the host store. Everything then runs on one stream, one
+ * launch per tick, and the host issues nothing else; the host stores must
+ * be pinned host memory that the device can address (hipHostMalloc, or a
+ * torch tensor allocated with pin_memory=True). Both give bit-identical
+ * host stores. */
+#define OOCS_PLAN_KERNEL_TRANSFERS 2
 
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be
@@ -240,7 +242,7 @@ int oocs_plan_slab(const oocs_plan* plan, int i, oocs_slab_info* out);
  * (0 = host-to-device copies, 1 = compute, 2 = device-to-host copies),
  * exposed so that its ordering can be checked without a GPU. kr is the
  * number of steps of the residency (k, or the remainder of the last one).
- * Without OOCS_PLAN_COPY_ENGINES every op is on stream 1 and the copies
+ * With OOCS_PLAN_KERNEL_TRANSFERS every op is on stream 1 and the copies
  * are FETCH / STORE jobs of the launches. */
 #define OOCS_OP_H2D 1     /* copy a group of host-store planes into an input staging slot */
 #define OOCS_OP_DECODE 2  /* decode (or copy, if uncompressed) a staging slot into a level ring */
@@ -304,12 +306,17 @@ typedef struct {
      * the host link, which are also the device-memory bytes they write or
      * read in the staging slots. Included in h2d_bytes / d2h_bytes too. */
     int64_t xfer_bytes;
+    /* The launches that carried timing events (every N-th launch with
+     * oocs_plan_set_profiling(plan, N)) and their algorithmic bytes:
+     * kernel_ms / timed_launches is the average launch duration and
+     * timed_bytes / kernel_ms the achieved algorithmic bandwidth. */
+    int64_t timed_launches, timed_bytes;
 } oocs_stats;
 
-/* Turn per-launch kernel timing on (1) or off (0) for later oocs_run calls
- * on this plan. Timing events are recorded on the plan's compute stream
- * around every launch; the sum of their elapsed times is returned in
- * oocs_stats.kernel_ms. */
+/* Per-launch kernel timing for later oocs_run calls on this plan: 0 turns it
+ * off, N > 0 records timing events on the compute stream around every N-th
+ * launch (N = 1: every launch). The sum of their elapsed times is returned in
+ * oocs_stats.kernel_ms, with the timed launches and their bytes. */
 int oocs_plan_set_profiling(oocs_plan* plan, int on);
 
 /* Choose how oocs_run issues a residency (default 0): as one replay of a HIP
@@ -324,7 +331,7 @@ int oocs_plan_set_graphs(oocs_plan* plan, int on);
  * the source cell when the field after the s-th step of this call is
  * formed (s = 0 .. steps-1); h_src holds `steps` values or is NULL. Host
  * stores are updated in place. Blocks until done; st may be NULL.
- * Without OOCS_PLAN_COPY_ENGINES the kernels read and write the stores
+ * With OOCS_PLAN_KERNEL_TRANSFERS the kernels read and write the stores
  * directly, so each must be pinned, device-addressable host memory.
  * Errors: OOCS_E_ARG (also: a store the device cannot address), OOCS_E_STATE
  * (planning-only plan), OOCS_E_HIP. */

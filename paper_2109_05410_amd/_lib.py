@@ -25,7 +25,7 @@ OOCS_WAVE25 = 2
 OOCS_MAX_FIELDS = 3
 OOCS_MAX_RATE = 34
 OOCS_PLAN_BLOCK_RESTART = 1
-OOCS_PLAN_COPY_ENGINES = 2
+OOCS_PLAN_KERNEL_TRANSFERS = 2
 
 OP_H2D, OP_DECODE, OP_LEVEL, OP_ENCODE, OP_D2H, OP_LAUNCH, OP_RECORD, OP_WAIT, OP_FETCH, OP_STORE = range(1, 11)
 
@@ -90,6 +90,7 @@ class Stats(C.Structure):
         ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("cell_updates", C.c_int64),
         ("launches", C.c_int64), ("codec_bytes", C.c_int64), ("stencil_bytes", C.c_int64),
         ("kernel_ms", C.c_double), ("xfer_bytes", C.c_int64),
+        ("timed_launches", C.c_int64), ("timed_bytes", C.c_int64),
     ]
 
 

@@ -154,6 +154,8 @@ class RunStats:
     stencil_bytes: int
     kernel_ms: float
     xfer_bytes: int
+    timed_launches: int
+    timed_bytes: int
 
     @property
     def gcells_per_s(self) -> float:
@@ -169,14 +171,14 @@ class OutOfCorePlan:
 
     block_restart: every block restarts the level fronts and recomputes its
     halo (the per-block schedule of Fig. 2) instead of sharing every level's
-    planes with its neighbour. copy_engines: move groups with hipMemcpyAsync
-    on two copy streams (the three-stream pipeline of Sec. V-B) instead of
-    transfer jobs inside the pipeline kernel. Results are identical."""
+    planes with its neighbour. kernel_transfers: move groups with transfer
+    jobs inside the pipeline kernel instead of hipMemcpyAsync on two copy
+    streams (the three-stream pipeline of Sec. V-B). Results are identical."""
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
                  planning_only: bool = False, device=None, block_restart: bool = False,
-                 copy_engines: bool = False):
+                 kernel_transfers: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -188,7 +190,7 @@ class OutOfCorePlan:
             cfg.rate[i] = rates[i] if i < len(rates) else 0
         cfg.nstage = nstage
         cfg.alpha = alpha
-        cfg.flags = (L.OOCS_PLAN_BLOCK_RESTART if block_restart else 0) | (L.OOCS_PLAN_COPY_ENGINES if copy_engines else 0)
+        cfg.flags = (L.OOCS_PLAN_BLOCK_RESTART if block_restart else 0) | (L.OOCS_PLAN_KERNEL_TRANSFERS if kernel_transfers else 0)
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg
@@ -272,8 +274,9 @@ class OutOfCorePlan:
                                  C.byref(st)))
         return RunStats(*(getattr(st, name) for name, _ in L.Stats._fields_))
 
-    def set_profiling(self, on: bool):
-        L.check(L.lib().oocs_plan_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on, every: int = 1):
+        """Time every `every`-th launch with events (on=False: no timing)."""
+        L.check(L.lib().oocs_plan_set_profiling(self._h, int(every) if on else 0))
 
     def set_graphs(self, on: bool):
         L.check(L.lib().oocs_plan_set_graphs(self._h, 1 if on else 0))

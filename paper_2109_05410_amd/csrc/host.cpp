@@ -55,6 +55,7 @@ struct ResidencyGraph {
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> timing;  // start/end pairs around each kernel node (profiling)
     int64_t launches = 0, codec_bytes = 0, stencil_bytes = 0, xfer_bytes = 0, h2d = 0, d2h = 0;
+    int64_t timed_bytes = 0;  // algorithmic bytes of the launches that have timing nodes
 };
 
 struct oocs_plan {
@@ -64,7 +65,7 @@ struct oocs_plan {
     bool runnable = false;
     hipStream_t st[3] = {nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> ev;  // 4*nstage logical + 2*n block events (two parities)
-    bool profiling = false;
+    int profiling = 0;  // 0: off; N: time every N-th launch
     bool graphs = false;
     std::vector<hipEvent_t> tev;  // eager timing events, two per launch, grown on demand
     // graphs by (residency length, store pointers, source on)
@@ -407,7 +408,7 @@ int oocs_plan_set_profiling(oocs_plan* pl, int on)
 {
     if (!pl) return fail(OOCS_E_ARG, "null pointer");
     if (!pl->runnable) return fail(OOCS_E_STATE, "planning-only plan");
-    pl->profiling = on != 0;
+    pl->profiling = on > 0 ? on : 0;
     return OOCS_OK;
 }
 
@@ -576,9 +577,15 @@ int build_graph(oocs_plan* pl, int kr, void* const* h_store, void* const* d_stor
             break;
         case OOCS_OP_LAUNCH: {
             if (tr.lp.njobs == 0) break;
-            tr.count_bytes(&out.codec_bytes, &out.stencil_bytes, &out.xfer_bytes);
+            int64_t lb[3] = {0, 0, 0};
+            tr.count_bytes(&lb[0], &lb[1], &lb[2]);
+            out.codec_bytes += lb[0];
+            out.stencil_bytes += lb[1];
+            out.xfer_bytes += lb[2];
+            const bool timed = pl->profiling > 0 && out.launches % pl->profiling == 0;
+            if (timed) out.timed_bytes += lb[0] + lb[1] + lb[2];
             std::vector<hipGraphNode_t> d = deps_of(1);
-            if (pl->profiling) {
+            if (timed) {
                 hipEvent_t e0, e1;
                 HIP_TRY(hipEventCreate(&e0));
                 out.timing.push_back(e0);
@@ -590,7 +597,7 @@ int build_graph(oocs_plan* pl, int kr, void* const* h_store, void* const* d_stor
             }
             hipGraphNode_t n;
             HIP_TRY(oocs::add_jobs_node(tr.lp, g, d.data(), d.size(), &n));
-            if (pl->profiling) {
+            if (timed) {
                 hipGraphNode_t n1;
                 HIP_TRY(hipGraphAddEventRecordNode(&n1, g, &n, 1, out.timing.back()));
                 n = n1;
@@ -651,6 +658,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     const int64_t chunk_steps = src_on ? oocs::Planner::kSrcTable / P.k * P.k : steps;
     int64_t h2d = 0, d2h = 0, rounds = 0, launches = 0;
     int64_t kbytes[3] = {0, 0, 0};  // codec jobs, stencil and copy jobs, transfer jobs
+    int64_t tbytes = 0, tlaunches = 0;  // the timed launches (profiling)
     // kernel-driven transfers address the host stores from the device
     void* d_store[OOCS_MAX_FIELDS] = {nullptr, nullptr, nullptr};
     if (!P.copy_engines)
@@ -704,6 +712,8 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                 kbytes[1] += rg.stencil_bytes;
                 kbytes[2] += rg.xfer_bytes;
                 if (pl->profiling) {  // the timing events hold this replay's times once it completes
+                    tbytes += rg.timed_bytes;
+                    tlaunches += (int64_t)rg.timing.size() / 2;
                     HIP_TRY(hipStreamSynchronize(pl->st[1]));
                     for (size_t i = 0; i + 1 < rg.timing.size(); i += 2) {
                         float ms = 0.0f;
@@ -747,8 +757,13 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                         break;
                     case OOCS_OP_LAUNCH:
                         if (tr.lp.njobs > 0) {
-                            tr.count_bytes(&kbytes[0], &kbytes[1], &kbytes[2]);
-                            if (pl->profiling) {
+                            int64_t lb[3] = {0, 0, 0};
+                            tr.count_bytes(&lb[0], &lb[1], &lb[2]);
+                            for (int q = 0; q < 3; ++q) kbytes[q] += lb[q];
+                            const bool timed = pl->profiling > 0 && launches % pl->profiling == 0;
+                            if (timed) {
+                                tbytes += lb[0] + lb[1] + lb[2];
+                                ++tlaunches;
                                 while (pl->tev.size() < tused + 2) {
                                     hipEvent_t e;
                                     HIP_TRY(hipEventCreate(&e));
@@ -757,7 +772,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                                 HIP_TRY(hipEventRecord(pl->tev[tused], pl->st[1]));
                             }
                             HIP_TRY(oocs::launch_jobs(tr.lp, pl->st[1]));
-                            if (pl->profiling) {
+                            if (timed) {
                                 HIP_TRY(hipEventRecord(pl->tev[tused + 1], pl->st[1]));
                                 tused += 2;
                             }
@@ -768,10 +783,17 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                     case OOCS_OP_RECORD:
                         HIP_TRY(hipEventRecord(phys(o.event), pl->st[o.stream]));
                         break;
-                    case OOCS_OP_WAIT:
+                    case OOCS_OP_WAIT: {
                         if (o.event >= P.ev_blk_prev(0) && chunk_round == 0 && rounds == 0) break;
-                        HIP_TRY(hipStreamWaitEvent(pl->st[o.stream], phys(o.event), 0));
+                        // A completed event orders nothing: skip the wait, which would
+                        // otherwise cost the host a cross-queue barrier.
+                        const hipEvent_t e = phys(o.event);
+                        const hipError_t q = hipEventQuery(e);
+                        if (q == hipSuccess) break;
+                        if (q != hipErrorNotReady) return oocs::hip_fail(q, "event query");
+                        HIP_TRY(hipStreamWaitEvent(pl->st[o.stream], e, 0));
                         break;
+                    }
                     default:
                         return fail(OOCS_E_STATE, "unknown op");
                     }
@@ -804,6 +826,8 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
         st->codec_bytes = kbytes[0];
         st->stencil_bytes = kbytes[1];
         st->xfer_bytes = kbytes[2];
+        st->timed_launches = tlaunches;
+        st->timed_bytes = tbytes;
         st->kernel_ms = kms;
     }
     return OOCS_OK;

@@ -53,11 +53,12 @@ int Planner::init(const oocs_config& c, std::string& err)
     }
     if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
-    if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_COPY_ENGINES)) { err = "unknown plan flags"; return OOCS_E_ARG; }
+    if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS)) { err = "unknown plan flags"; return OOCS_E_ARG; }
     restart = (c.flags & OOCS_PLAN_BLOCK_RESTART) != 0;
-    copy_engines = (c.flags & OOCS_PLAN_COPY_ENGINES) != 0;
-    // kernel-driven transfers fetch one group ahead inside the launch: two slots suffice
-    nstage = c.nstage ? c.nstage : (copy_engines ? 3 : 2);
+    copy_engines = (c.flags & OOCS_PLAN_KERNEL_TRANSFERS) == 0;
+    // kernel-driven transfers fetch one group ahead inside the launch: two slots suffice;
+    // copy engines keep three groups in flight ahead of the decode
+    nstage = c.nstage ? c.nstage : (copy_engines ? 4 : 2);
     a.resize(n + 1);
     for (int i = 0; i <= n; ++i) a[i] = (int64_t)i * slab;
     return OOCS_OK;
@@ -300,22 +301,27 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
     };
     if (!copy_engines) return emit_direct(kr, s, op);
     auto block_of = [&](int64_t z) { return (int)std::min<int64_t>(z / slab, n - 1); };
-    auto emit_h2d = [&](int64_t j, int64_t tick) {
+    auto emit_h2d = [&](int64_t j, int64_t tick, std::vector<oocs_op>& out) {
         const GroupRec& g = s.in_groups[j];
         const int sl = (int)(j % nstage);
-        oocs_op w = op(OOCS_OP_WAIT, 0); w.event = ev_decoded(sl); w.tick = (int)tick; s.ops.push_back(w);
+        oocs_op w = op(OOCS_OP_WAIT, 0); w.event = ev_decoded(sl); w.tick = (int)tick; out.push_back(w);
         // host planes were last written by the previous residency's write-back
-        oocs_op w2 = op(OOCS_OP_WAIT, 0); w2.event = ev_blk_prev(block_of(g.z1 - 1)); w2.tick = (int)tick; s.ops.push_back(w2);
+        oocs_op w2 = op(OOCS_OP_WAIT, 0); w2.event = ev_blk_prev(block_of(g.z1 - 1)); w2.tick = (int)tick; out.push_back(w2);
         for (int fld : in_fields) {
             oocs_op c = op(OOCS_OP_H2D, 0);
             c.field = fld; c.slot = sl; c.z0 = g.z0; c.z1 = g.z1; c.block = g.block; c.tick = (int)tick;
             c.level = in_ring(fld);
-            s.ops.push_back(c);
+            out.push_back(c);
         }
-        oocs_op rcd = op(OOCS_OP_RECORD, 0); rcd.event = ev_loaded(sl); rcd.tick = (int)tick; s.ops.push_back(rcd);
+        oocs_op rcd = op(OOCS_OP_RECORD, 0); rcd.event = ev_loaded(sl); rcd.tick = (int)tick; out.push_back(rcd);
     };
     const int64_t nin_groups = (int64_t)s.in_groups.size();
-    for (int64_t j = 0; j < std::min<int64_t>(nstage, nin_groups); ++j) emit_h2d(j, -1);
+    for (int64_t j = 0; j < std::min<int64_t>(nstage, nin_groups); ++j) emit_h2d(j, -1, s.ops);
+    // The copies a tick makes possible (write-back of its output group, load
+    // of the group that reuses its input slot) are issued after the next
+    // tick's launch: by then the events they wait for have usually
+    // completed, and a wait on a completed event costs the host nothing.
+    std::vector<oocs_op> lagged, next;
     for (int64_t ti = 0; ti < (int64_t)s.ticks.size(); ++ti) {
         const Tick& t = s.ticks[ti];
         const int isl = t.in_group >= 0 ? (int)(t.in_group % nstage) : -1;
@@ -341,23 +347,27 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
             }
         { oocs_op l = op(OOCS_OP_LAUNCH, 1); l.tick = (int)ti; l.block = t.block; s.ops.push_back(l); }
         if (isl >= 0) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_decoded(isl); r2.tick = (int)ti; s.ops.push_back(r2); }
+        if (osl >= 0) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_encoded(osl); r2.tick = (int)ti; s.ops.push_back(r2); }
+        s.ops.insert(s.ops.end(), lagged.begin(), lagged.end());
+        next.clear();
         if (osl >= 0) {
-            oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_encoded(osl); r2.tick = (int)ti; s.ops.push_back(r2);
-            oocs_op w = op(OOCS_OP_WAIT, 2); w.event = ev_encoded(osl); w.tick = (int)ti; s.ops.push_back(w);
+            oocs_op w = op(OOCS_OP_WAIT, 2); w.event = ev_encoded(osl); w.tick = (int)ti; next.push_back(w);
             for (int fld : out_fields) {
                 oocs_op c = op(OOCS_OP_D2H, 2);
                 c.field = fld; c.slot = osl; c.z0 = t.ez0; c.z1 = t.ez1; c.block = t.out_block; c.tick = (int)ti;
                 c.level = out_ring(fld, kr);
-                s.ops.push_back(c);
+                next.push_back(c);
             }
-            oocs_op r3 = op(OOCS_OP_RECORD, 2); r3.event = ev_stored(osl); r3.tick = (int)ti; s.ops.push_back(r3);
+            oocs_op r3 = op(OOCS_OP_RECORD, 2); r3.event = ev_stored(osl); r3.tick = (int)ti; next.push_back(r3);
             if (t.last_out_of_block) {
                 oocs_op r4 = op(OOCS_OP_RECORD, 2); r4.event = ev_blk_cur(t.out_block); r4.tick = (int)ti; r4.block = t.out_block;
-                s.ops.push_back(r4);
+                next.push_back(r4);
             }
         }
-        if (isl >= 0 && t.in_group + nstage < nin_groups) emit_h2d(t.in_group + nstage, ti);
+        if (isl >= 0 && t.in_group + nstage < nin_groups) emit_h2d(t.in_group + nstage, ti, next);
+        lagged.swap(next);
     }
+    s.ops.insert(s.ops.end(), lagged.begin(), lagged.end());
     (void)err;
     return OOCS_OK;
 }

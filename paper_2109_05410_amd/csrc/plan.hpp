@@ -77,7 +77,7 @@ public:
     int n = 1;         // slabs
     int k = 1;
     bool restart = false;    // every block restarts the level fronts (halo recomputed)
-    bool copy_engines = false;  // transfers by hipMemcpyAsync on copy streams, not by the kernel
+    bool copy_engines = true;   // transfers by hipMemcpyAsync on copy streams (else by the kernel)
     int64_t slab = 0, h = 0;
     std::vector<int64_t> a;  // n+1 block bounds
 

@@ -114,6 +114,97 @@ __device__ inline void heat_dense(const float* __restrict__ src, float* __restri
     }
 }
 
+// Heat, K steps of a dense field in one pass (temporal blocking). A 256-thread
+// workgroup owns a 64 x TY column tile whose outer K cells on each side are
+// halo (recomputed by the neighbouring tiles), and streams z over its chunk
+// [z0, z1) extended by K planes on both ends. Each thread owns TY/4 cells of
+// the tile (one column x, rows ly0 + 4c) for every plane; per cell it keeps
+// the last three planes of every intermediate level in registers (the z
+// neighbours), and publishes each new plane of levels 0..K-1 in LDS (the x /
+// y neighbours), double-buffered by plane parity, so one barrier per plane
+// suffices: level s at plane q = p - s reads level s-1 at plane q from the
+// buffer written in the previous iteration. Cells outside the grid are zero
+// at every level; tile-border cells have no neighbours and are set to zero
+// (they are outside the region a level can compute). Level K is written for
+// the tile interior and planes [z0, z1). Same per-cell operation order as
+// heat_level, so the result equals K single steps bit for bit. lds holds
+// K * 2 * TY * 64 floats.
+template <int TY, int K>
+__device__ inline void heat_tb(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
+                               float alpha, int zch, int wg, float* lds)
+{
+    constexpr int TX = 64, CPT = TY / 4, OX = TX - 2 * K, OY = TY - 2 * K;
+    static_assert(TY % 4 == 0 && OY > 0, "tile too small for the depth");
+    const int tiles_x = (nx + OX - 1) / OX, tiles_y = (ny + OY - 1) / OY;
+    const int tile = wg % (tiles_x * tiles_y);
+    const int zc = wg / (tiles_x * tiles_y);
+    const int ox = (tile % tiles_x) * OX - K, oy = (tile / tiles_x) * OY - K;
+    const int lx = (int)(threadIdx.x % TX), ly0 = (int)(threadIdx.x / TX);
+    const int z0 = zc * zch, z1 = min(nz, z0 + zch);
+    const int64_t plane = (int64_t)nx * ny;
+    const int gx = ox + lx;
+    const bool xin = gx >= 0 && gx < nx;
+    const bool xedge = lx == 0 || lx == TX - 1;
+    const bool xout = lx >= K && lx < TX - K;
+    bool in[CPT], ok_xy[CPT], out_xy[CPT];
+    int64_t off[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int ly = ly0 + 4 * c, gy = oy + ly;
+        in[c] = xin && gy >= 0 && gy < ny;
+        ok_xy[c] = in[c] && !xedge && ly > 0 && ly < TY - 1;
+        out_xy[c] = in[c] && xout && ly >= K && ly < TY - K;
+        off[c] = (int64_t)gy * nx + gx;
+    }
+    auto L = [&](int lev, int buf, int ly, int x) -> float& { return lds[((lev * 2 + buf) * TY + ly) * TX + x]; };
+    float w[K][CPT][3];
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) w[s][c][0] = w[s][c][1] = w[s][c][2] = 0.0f;
+    for (int p = z0 - K; p < z1 + K; ++p) {
+        const int b = p & 1;
+        const bool pin = p >= 0 && p < nz;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const float v = (in[c] && pin) ? src[p * plane + off[c]] : 0.0f;
+            w[0][c][0] = w[0][c][1];
+            w[0][c][1] = w[0][c][2];
+            w[0][c][2] = v;
+            L(0, b, ly0 + 4 * c, lx) = v;
+        }
+#pragma unroll
+        for (int s = 1; s <= K; ++s) {
+            const int q = p - s;
+            const int qb = q & 1;
+            const bool qin = q >= 0 && q < nz;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int ly = ly0 + 4 * c;
+                float v = 0.0f;
+                if (ok_xy[c] && qin) {
+                    const float cc = w[s - 1][c][1];
+                    const float xm = L(s - 1, qb, ly, lx - 1), xp = L(s - 1, qb, ly, lx + 1);
+                    const float ym = L(s - 1, qb, ly - 1, lx), yp = L(s - 1, qb, ly + 1, lx);
+                    float t = (xm + xp) + (ym + yp);
+                    t = t + (w[s - 1][c][0] + w[s - 1][c][2]);
+                    t = t - 6.0f * cc;
+                    v = cc + alpha * t;
+                }
+                if (s < K) {
+                    w[s][c][0] = w[s][c][1];
+                    w[s][c][1] = w[s][c][2];
+                    w[s][c][2] = v;
+                    L(s, qb, ly, lx) = v;
+                } else if (out_xy[c] && q >= z0 && q < z1) {
+                    dst[q * plane + off[c]] = v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Wave, 25 points:
 //   acc = C0X3*p;  for m = 1..4: acc = acc + C_m * (((x+m + x-m) + (y+m + y-m)) + (z+m + z-m))
 //   p'  = (2p - pm) + w*acc  (+ amp at the source cell)

@@ -111,7 +111,7 @@ def test_separate_write_back_pairs_remainder_and_previous_common_region():
     R_i, and the lower half of C_i (Fig. 3b): the write-back of block i
     covers [a_i, a_{i+1}) and nothing else."""
     for ce in (False, True):
-        p = plan((512, 32, 32), HEAT7, 8, 4, [8], 1 << 30, copy_engines=ce)
+        p = plan((512, 32, 32), HEAT7, 8, 4, [8], 1 << 30, kernel_transfers=ce)
         for o in p.schedule(4):
             if o["kind"] in (L.OP_D2H, L.OP_STORE):
                 assert 64 * o["block"] <= o["z0"] < o["z1"] <= 64 * (o["block"] + 1)
@@ -272,14 +272,14 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
 @pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
 def test_schedule_has_no_races(shape, st, n, k, rates, arena, steps, restart, ce):
     p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, block_restart=restart,
-             copy_engines=ce)
+             kernel_transfers=ce)
     race_check(p, steps)
     race_check(p, steps, graph_mode=True)
 
 
 @pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
 def test_full_size_heat_schedule_has_no_races(restart, ce):
-    p = plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB, block_restart=restart, copy_engines=ce)
+    p = plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB, block_restart=restart, kernel_transfers=ce)
     race_check(p, 12)
     race_check(p, 12, graph_mode=True)
 
@@ -420,7 +420,7 @@ def from_store(s, shape, rate):
 def test_heat_schedule_computes_the_replay(rate, k, steps, arena, restart, ce):
     shape = (48, 12, 16)
     n = 4 if k < 8 else 2
-    p = plan(shape, HEAT7, n, k, [rate], arena, block_restart=restart, copy_engines=ce)
+    p = plan(shape, HEAT7, n, k, [rate], arena, block_restart=restart, kernel_transfers=ce)
     u0 = np.random.default_rng(rate).random(shape, dtype=np.float32)
     store = [to_store(u0, rate)]
     # the initial store passes the field through the codec once
@@ -440,7 +440,7 @@ def test_wave_schedule_computes_the_replay(rates, k, steps, restart, ce):
     w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
     amps = rng.standard_normal(steps).astype(np.float32)
     src = (5, 6, 20)
-    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src, block_restart=restart, copy_engines=ce)
+    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src, block_restart=restart, kernel_transfers=ce)
     store = [to_store(p0, rates[0]), to_store(pm0, rates[1]), to_store(w, rates[2])]
     execute(p, store, steps, amps)
     got_p = from_store(store[0], shape, rates[0])
