@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
     ap.add_argument("--graphs", type=int, default=0,
                     help="1: replay each residency as a HIP graph; 0: issue it on the three streams directly")
+    ap.add_argument("--pipeline-only", action="store_true",
+                    help="time the pipeline variants only (no in-core rate, no link probe); for profiler runs")
     ap.add_argument("--kernel-transfers", type=int, default=0,
                     help="1: move groups with transfer jobs inside the pipeline kernel instead of copy engines")
     args = ap.parse_args()
@@ -256,6 +258,9 @@ def main():
               f"{results[r]['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
     head = results.get(HEADLINE_RATE, results[rates[-1]])
     raw = results.get(0)
+    if args.pipeline_only:
+        print(json.dumps({"variants": {r: _rounded(res) for r, res in results.items()}}), flush=True)
+        return
     incore = in_core_rate(api, torch, u0)
     link = link_probe(torch)
     traffic = measured_traffic()
@@ -296,6 +301,15 @@ def main():
             "bytes_per_launch": round(kstat["bytes_per_launch"]),
             "avg_launch_us": round(kstat["avg_launch_us"], 2),
         },
+    }
+    # the transfers against the host link: both directions run at once, so the
+    # peak is the measured bidirectional rate per direction
+    bidir = link.get("bidir_GBps_each")
+    line["host_link_roofline"] = {
+        "achieved_GBps_each_way": round(head["h2d_GBps"], 2),
+        "peak_GBps_each_way": round(bidir, 2) if bidir else None,
+        "frac": round(head["h2d_GBps"] / bidir, 4) if bidir else None,
+        "peak_source": "pinned 256 MiB copies in both directions at once (host_link)",
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(u0, args.cpu_seconds)

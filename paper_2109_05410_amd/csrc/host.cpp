@@ -171,6 +171,7 @@ int oocs_heat7_step_k(float* d_u, float* d_tmp, int64_t nx, int64_t ny, int64_t 
 {
     if (!d_u || !d_tmp || k < 0) return fail(OOCS_E_ARG, "bad argument");
     if (!grid_ok(nx, ny, nz)) return fail(OOCS_E_ARG, "bad grid (nx must be a multiple of 4)");
+    if (((uintptr_t)d_u | (uintptr_t)d_tmp) % 16) return fail(OOCS_E_ALIGN, "fields must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     float* a = d_u;
     float* b = d_tmp;

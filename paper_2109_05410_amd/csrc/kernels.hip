@@ -19,7 +19,7 @@ static_assert(sizeof(LaunchParams) <= 4096, "kernel arguments must stay within 4
 
 constexpr int kWavesPerWG = kBlockThreads / 64;
 constexpr int kCopyFloat4PerThread = 4;
-constexpr int kHeatBatch = 8;  // planes whose loads a heat thread issues together
+constexpr int kHeatBatch = 4;  // planes whose loads a heat lane issues together
 constexpr int kWaveBatch = 2;  // same for the wave
 
 extern __shared__ uint64_t dyn_lds[];  // codec jobs: 64 * rate words per wave
@@ -191,7 +191,10 @@ int32_t job_workgroups(const Job& j, int nx, int ny)
     const int planes = j.z1 - j.z0;
     if (planes <= 0) return 0;
     switch (j.kind) {
-    case JOB_HEAT:
+    case JOB_HEAT: {
+        const int tiles = ((nx + kHeatTileX - 1) / kHeatTileX) * ((ny + kHeatTileY - 1) / kHeatTileY);
+        return tiles * ((planes + kZChunk - 1) / kZChunk);
+    }
     case JOB_WAVE: {
         const int tiles = ((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
         return tiles * ((planes + kZChunk - 1) / kZChunk);

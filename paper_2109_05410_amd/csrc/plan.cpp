@@ -5,6 +5,7 @@
 #include <array>
 #include <climits>
 #include <cstdio>
+#include <deque>
 
 namespace oocs {
 
@@ -280,13 +281,20 @@ int Planner::choose(size_t arena_bytes, std::string& err)
         for (int64_t g = 32; g >= 4; g -= 4) cands.push_back(g);
         if (!any_rate) { cands.push_back(2); cands.push_back(1); }
     }
+    // staging depth: the caller's, else 4 then 3 slots for copy engines (a larger
+    // group is worth more than a deeper queue), 2 for kernel transfers
+    std::vector<int> depths;
+    if (cfg.nstage) depths = {cfg.nstage};
+    else if (copy_engines) depths = {4, 3};
+    else depths = {2};
     int64_t best_need = -1;
-    for (int64_t g : cands) {
-        const int64_t need = layout(g, nstage, err);
-        if (need < 0) return OOCS_E_STATE;
-        if (best_need < 0 || need < best_need) best_need = need;
-        if ((size_t)need <= arena_bytes) { cache_.clear(); return OOCS_OK; }
-    }
+    for (int64_t g : cands)
+        for (int ns : depths) {
+            const int64_t need = layout(g, ns, err);
+            if (need < 0) return OOCS_E_STATE;
+            if (best_need < 0 || need < best_need) best_need = need;
+            if ((size_t)need <= arena_bytes) { cache_.clear(); return OOCS_OK; }
+        }
     err = fmt("the pipeline needs at least %lld bytes of device arena, %lld given", best_need, (long long)arena_bytes);
     return OOCS_E_CAP;
 }
@@ -318,10 +326,14 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
     const int64_t nin_groups = (int64_t)s.in_groups.size();
     for (int64_t j = 0; j < std::min<int64_t>(nstage, nin_groups); ++j) emit_h2d(j, -1, s.ops);
     // The copies a tick makes possible (write-back of its output group, load
-    // of the group that reuses its input slot) are issued after the next
-    // tick's launch: by then the events they wait for have usually
-    // completed, and a wait on a completed event costs the host nothing.
-    std::vector<oocs_op> lagged, next;
+    // of the group that reuses its input slot) are issued `lag` ticks later:
+    // by then the events they wait for have usually completed, and a wait on
+    // a completed event costs the host nothing. lag < nstage keeps every
+    // wait on the record it was meant for (a slot is recorded again only
+    // nstage ticks later).
+    const int lag = std::max(1, std::min(2, nstage - 1));
+    std::deque<std::vector<oocs_op>> lagged;
+    std::vector<oocs_op> next;
     for (int64_t ti = 0; ti < (int64_t)s.ticks.size(); ++ti) {
         const Tick& t = s.ticks[ti];
         const int isl = t.in_group >= 0 ? (int)(t.in_group % nstage) : -1;
@@ -348,7 +360,10 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
         { oocs_op l = op(OOCS_OP_LAUNCH, 1); l.tick = (int)ti; l.block = t.block; s.ops.push_back(l); }
         if (isl >= 0) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_decoded(isl); r2.tick = (int)ti; s.ops.push_back(r2); }
         if (osl >= 0) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_encoded(osl); r2.tick = (int)ti; s.ops.push_back(r2); }
-        s.ops.insert(s.ops.end(), lagged.begin(), lagged.end());
+        if ((int)lagged.size() >= lag) {
+            s.ops.insert(s.ops.end(), lagged.front().begin(), lagged.front().end());
+            lagged.pop_front();
+        }
         next.clear();
         if (osl >= 0) {
             oocs_op w = op(OOCS_OP_WAIT, 2); w.event = ev_encoded(osl); w.tick = (int)ti; next.push_back(w);
@@ -365,9 +380,9 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
             }
         }
         if (isl >= 0 && t.in_group + nstage < nin_groups) emit_h2d(t.in_group + nstage, ti, next);
-        lagged.swap(next);
+        lagged.push_back(next);
     }
-    s.ops.insert(s.ops.end(), lagged.begin(), lagged.end());
+    for (const auto& blk : lagged) s.ops.insert(s.ops.end(), blk.begin(), blk.end());
     (void)err;
     return OOCS_OK;
 }

@@ -23,55 +23,75 @@ namespace oocs {
 namespace stencil {
 
 // Heat, 7 points: u' = c + alpha * (((xm+xp) + (ym+yp)) + (zm+zp) - 6c).
-// A thread loads the inputs of NB planes before it computes and stores any
-// of them: the loads of a batch are independent of the stores (which the
-// compiler cannot prove for ring pointers), so a wave waits on memory once
-// per batch instead of once per plane.
+// Mapping: a lane owns 4 consecutive x (one float4), a wave one 256-wide
+// row segment, a workgroup 4 rows (one per wave); every lane marches up to
+// kZChunk planes in z. The x neighbours come from the adjacent lanes by
+// shuffles (the row ends of the wave from two scalar loads), the y
+// neighbours from float4 loads of the rows above and below, the z
+// neighbours from the lane's own previous planes. A lane loads the inputs
+// of NB planes before it computes and stores any of them: the loads of a
+// batch are independent of the stores (which the compiler cannot prove for
+// ring pointers), so a wave waits on memory once per batch. nx must be a
+// multiple of 4.
 template <int NB>
 __device__ inline void heat_level(const Job& j, int nx, int ny, int nz, float alpha, int wg)
 {
-    const int tiles_x = (nx + kTileX - 1) / kTileX;
-    const int tiles_y = (ny + kTileY - 1) / kTileY;
+    const int lane = (int)(threadIdx.x & 63), row = (int)(threadIdx.x >> 6);
+    const int tiles_x = (nx + kHeatTileX - 1) / kHeatTileX;
+    const int tiles_y = (ny + kHeatTileY - 1) / kHeatTileY;
     const int tile = wg % (tiles_x * tiles_y);
     const int zc = wg / (tiles_x * tiles_y);
-    const int x = (tile % tiles_x) * kTileX + (int)(threadIdx.x % kTileX);
-    const int y = (tile / tiles_x) * kTileY + (int)(threadIdx.x / kTileX);
+    const int x0 = (tile % tiles_x) * kHeatTileX + 4 * lane;
+    const int y = (tile / tiles_x) * kHeatTileY + row;
     const int z0 = j.z0 + zc * kZChunk;
     const int z1 = min(j.z1, z0 + kZChunk);
-    if (x >= nx || y >= ny || z0 >= z1) return;
-    const int64_t xy = (int64_t)y * nx + x;
-    const bool hx0 = x > 0, hx1 = x + 1 < nx, hy0 = y > 0, hy1 = y + 1 < ny;
-    float cm = z0 - 1 >= 0 ? ring_plane(j.src, z0 - 1)[xy] : 0.0f;
+    if (y >= ny || z0 >= z1) return;  // uniform over the wave
+    const bool act = x0 < nx;
+    const bool hy0 = y > 0, hy1 = y + 1 < ny;
+    const bool hl = x0 > 0, hr = x0 + 4 < nx;
+    const int64_t xy = (int64_t)y * nx + x0;
+    const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    auto ld4 = [&](const float* q) { return *reinterpret_cast<const float4*>(q); };
+    float4 cm = (act && z0 > 0) ? ld4(ring_plane(j.src, z0 - 1) + xy) : zero;
     for (int zb = z0; zb < z1; zb += NB) {
-        float c[NB + 1], xm[NB], xp[NB], ym[NB], yp[NB];
+        float4 c[NB + 1], ym[NB], yp[NB];
+        float el[NB], er[NB];
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            c[i] = xm[i] = xp[i] = ym[i] = yp[i] = 0.0f;
-            if (zb + i < z1) {
+            c[i] = ym[i] = yp[i] = zero;
+            el[i] = er[i] = 0.0f;
+            if (act && zb + i < z1) {
                 const float* pl = ring_plane(j.src, zb + i) + xy;
-                c[i] = pl[0];
-                if (hx0) xm[i] = pl[-1];
-                if (hx1) xp[i] = pl[1];
-                if (hy0) ym[i] = pl[-nx];
-                if (hy1) yp[i] = pl[nx];
+                c[i] = ld4(pl);
+                if (hy0) ym[i] = ld4(pl - nx);
+                if (hy1) yp[i] = ld4(pl + nx);
+                if (lane == 0 && hl) el[i] = pl[-1];
+                if (lane == 63 && hr) er[i] = pl[4];
             }
         }
         // the plane above the last one of the batch
         const int zt = min(zb + NB, z1);
-        c[NB] = 0.0f;
+        c[NB] = zero;
 #pragma unroll
         for (int i = 1; i <= NB; ++i)
-            if (zt == zb + i && zt < nz) c[i] = ring_plane(j.src, zt)[xy];
+            if (act && zt == zb + i && zt < nz) c[i] = ld4(ring_plane(j.src, zt) + xy);
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            if (zb + i < z1) {
-                const float zm = i == 0 ? cm : c[i - 1];
-                const float cc = c[i];
-                const float zp = c[i + 1];
-                float s = (xm[i] + xp[i]) + (ym[i] + yp[i]);
-                s = s + (zm + zp);
-                s = s - 6.0f * cc;
-                ring_plane(j.dst, zb + i)[xy] = cc + alpha * s;
+            float l = __shfl_up(c[i].w, 1);
+            float r = __shfl_down(c[i].x, 1);
+            if (lane == 0) l = el[i];
+            if (lane == 63 || !hr) r = hr ? er[i] : 0.0f;
+            if (act && zb + i < z1) {
+                const float4 zm = i == 0 ? cm : c[i - 1];
+                const float4 zp = c[i + 1];
+                const float4 cc = c[i];
+                float4 o;
+                float t;
+                t = (l + cc.y) + (ym[i].x + yp[i].x);    t = t + (zm.x + zp.x); t = t - 6.0f * cc.x; o.x = cc.x + alpha * t;
+                t = (cc.x + cc.z) + (ym[i].y + yp[i].y); t = t + (zm.y + zp.y); t = t - 6.0f * cc.y; o.y = cc.y + alpha * t;
+                t = (cc.y + cc.w) + (ym[i].z + yp[i].z); t = t + (zm.z + zp.z); t = t - 6.0f * cc.z; o.z = cc.z + alpha * t;
+                t = (cc.z + r) + (ym[i].w + yp[i].w);    t = t + (zm.w + zp.w); t = t - 6.0f * cc.w; o.w = cc.w + alpha * t;
+                *reinterpret_cast<float4*>(ring_plane(j.dst, zb + i) + xy) = o;
             }
         }
         cm = c[NB - 1];

@@ -450,3 +450,17 @@ def test_wave_schedule_computes_the_replay(rates, k, steps, restart, ce):
                                    rate_w=rates[2])
     assert np.array_equal(got_p, wp)
     assert np.array_equal(got_pm, wpm)
+
+
+@pytest.mark.parametrize("nstage", [2, 3, 5])
+def test_schedule_staging_depths(nstage):
+    """Copies issued 1 (two slots) or 2 ticks late stay ordered for any
+    staging depth, and the schedule still computes the replay."""
+    p = plan((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, nstage=nstage)
+    assert p.info["nstage"] == nstage
+    race_check(p, 11)
+    race_check(p, 11, graph_mode=True)
+    u0 = np.random.default_rng(nstage).random((48, 12, 16), dtype=np.float32)
+    store = [to_store(u0, 8)]
+    execute(p, store, 11, None)
+    assert np.array_equal(from_store(store[0], (48, 12, 16), 8), O.replay_heat_f32(u0, 0.1, 11, 4, 8))
