@@ -167,6 +167,153 @@ def in_core_rate(api, torch, u0):
     return SHAPE[0] * SHAPE[1] * SHAPE[2] * TIME_STEPS / dt / 1e9
 
 
+def _timed(torch, fn, reps=1):
+    """Wall time of fn() between device synchronizations (seconds per call)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def codec_rates(api, torch, u0):
+    """Field encode and decode of the 512^3 field at 8 bits per value:
+    values per second and algorithmic bytes (4 + rate/8 per value) per second."""
+    u = torch.from_numpy(u0).cuda()
+    w = api.codec_encode(u, HEADLINE_RATE)
+    out = torch.empty_like(u)
+    api.codec_decode(w, SHAPE, HEADLINE_RATE, out=out)
+    n = u.numel()
+    te = _timed(torch, lambda: api.codec_encode(u, HEADLINE_RATE, out=w), reps=5)
+    td = _timed(torch, lambda: api.codec_decode(w, SHAPE, HEADLINE_RATE, out=out), reps=5)
+    b = n * (4 + HEADLINE_RATE / 8)
+    return {
+        "rate": HEADLINE_RATE,
+        "encode_Gvalues_per_s": round(n / te / 1e9, 1), "encode_GBps": round(b / te / 1e9, 1),
+        "encode_hbm_frac": round(b / te / 1e9 / HBM_PEAK_GBS, 4),
+        "decode_Gvalues_per_s": round(n / td / 1e9, 1), "decode_GBps": round(b / td / 1e9, 1),
+        "decode_hbm_frac": round(b / td / 1e9 / HBM_PEAK_GBS, 4),
+    }
+
+
+BATCH_STEPS = 200
+
+
+def batched_rate(api, torch, inputs):
+    """64 heat cubes with sides uniform in [64, 384], 200 steps: one graph
+    launch (autotuned tiles and temporal-blocking depth) against separate
+    per-domain launches."""
+    import tempfile
+
+    sides = inputs.batch_sides()
+    fields = [torch.from_numpy(inputs.heat_uniform((int(s),) * 3, seed=3 + j)).cuda() for j, s in enumerate(sides)]
+    cells = float(sum(int(s) ** 3 for s in sides)) * BATCH_STEPS
+    with tempfile.TemporaryDirectory() as td:
+        t0 = time.perf_counter()
+        b = api.HeatBatch(fields, tune=True, tune_cache=os.path.join(td, "tune.json"))
+        tune_s = time.perf_counter() - t0
+    b.run(BATCH_STEPS)  # builds the graph
+    tb = _timed(torch, lambda: b.run(BATCH_STEPS))
+    b.run_per_domain(1)
+    tp = _timed(torch, lambda: b.run_per_domain(BATCH_STEPS))
+    tiles = {}
+    for i in range(len(sides)):
+        tiles[str(b.tile(i))] = tiles.get(str(b.tile(i)), 0) + 1
+    out = {
+        "domains": len(sides), "steps": BATCH_STEPS, "cells": int(cells / BATCH_STEPS),
+        "depth": b.depth, "tiles": tiles, "tune_s": round(tune_s, 2),
+        "graph_gcells_per_s": round(cells / tb / 1e9, 1),
+        "per_domain_gcells_per_s": round(cells / tp / 1e9, 1),
+        "speedup": round(tp / tb, 3),
+        "hbm_GBps_equiv": round(cells * 8 / tb / 1e9, 1),
+    }
+    b.close()
+    del fields
+    torch.cuda.empty_cache()
+    return out
+
+
+WAVE_SHAPE = (1024, 1024, 1024)
+WAVE_K = 12
+WAVE_CAP = 8 << 30
+
+
+def wave_rates(api, torch, inputs, residencies=2):
+    """The 25-point wave on 1024^3 (layered model, Ricker source) out of core
+    under an 8 GiB device cap, 8 slabs, k = 12: `residencies` timed
+    residencies (12 steps each) after one untimed, uncompressed and at 12
+    bits per value for all three fields."""
+    import numpy as np
+
+    nz, ny, nx = WAVE_SHAPE
+    dt = inputs.wave_dt()
+    w = inputs.wave_coefficient(inputs.layered_velocity(WAVE_SHAPE, seed=1), dt)
+    z = np.zeros(WAVE_SHAPE, np.float32)
+    cell = inputs.source_cell(WAVE_SHAPE)
+    steps = WAVE_K * (residencies + 1)
+    amps = inputs.ricker(steps, dt)
+    res = {}
+    for rate in (0, 12):
+        plan = api.OutOfCorePlan(WAVE_SHAPE, api.WAVE25, 8, WAVE_K, [rate] * 3, WAVE_CAP, src_cell=cell)
+        st = [plan.new_store(f) for f in range(3)]
+        plan.put(0, z, st[0])
+        plan.put(1, z, st[1])
+        plan.put(2, w, st[2])
+        plan.run(st, WAVE_K, src_amps=amps[:WAVE_K])
+        t0 = time.perf_counter()
+        stats = plan.run(st, WAVE_K * residencies, src_amps=amps[WAVE_K:])
+        dt_s = time.perf_counter() - t0
+        cells = float(nx * ny * nz) * WAVE_K * residencies
+        res["uncompressed" if rate == 0 else f"rate{rate}"] = {
+            "gcells_per_s": round(cells / dt_s / 1e9, 2), "ms_per_step": round(dt_s / (WAVE_K * residencies) * 1e3, 2),
+            "group_planes": plan.info["group"], "arena_used_bytes": plan.info["arena_needed"],
+            "h2d_GBps": round(stats.h2d_bytes / dt_s / 1e9, 2), "d2h_GBps": round(stats.d2h_bytes / dt_s / 1e9, 2),
+        }
+        plan.close()
+        del st
+    res["speedup_vs_uncompressed"] = round(res["rate12"]["gcells_per_s"] / res["uncompressed"]["gcells_per_s"], 3)
+    res["sample"] = f"{residencies} residencies ({WAVE_K * residencies} steps) of the 4320-step run"
+    return res
+
+
+def adjoint_rate(api, torch, inputs, steps=100, every=10, rate=12):
+    """Misfit gradient of the 25-point wave on 512^3 with 64 receivers on the
+    top face: forward with (p, p_prev) checkpoints every 10 steps compressed
+    at 12 bits per value to host memory, then the backward pass (restore,
+    recompute, adjoint). A bounded sample of the 2000-step workload."""
+    import numpy as np
+
+    shape = (512, 512, 512)
+    nz, ny, nx = shape
+    dt = inputs.wave_dt()
+    c = np.float32(dt / 10.0)
+    v = inputs.layered_velocity(shape, seed=1)
+    vt = torch.from_numpy(v).cuda()
+    amps = inputs.ricker(steps, dt)
+    cell = inputs.source_cell(shape)
+    rcv = np.array([(32 + 64 * (i % 8)) + nx * ((32 + 64 * (i // 8)) + ny * 2) for i in range(64)], np.int64)
+    probe = api.WaveProblem(shape, steps, amps, cell, rcv, np.zeros((steps, 64), np.float32), float(c),
+                            ckpt_every=every, ckpt_rate=rate)
+    probe.forward((vt * 1.02).contiguous())
+    obs = probe.res.cpu().numpy()
+    del probe
+    prob = api.WaveProblem(shape, steps, amps, cell, rcv, obs, float(c), ckpt_every=every, ckpt_rate=rate)
+    tf = _timed(torch, lambda: prob.forward(vt))
+    tg = _timed(torch, lambda: prob.gradient(vt))
+    cells = float(nx * ny * nz) * steps
+    out = {
+        "grid": list(shape), "steps": steps, "ckpt_every": every, "ckpt_rate": rate, "receivers": 64,
+        "forward_s": round(tf, 3), "backward_s": round(tg, 3),
+        "gradient_gcell_steps_per_s": round(cells / (tf + tg) / 1e9, 2),
+        "host_ckpt_bytes": int(prob.ckpt.numel()),
+        "sample": f"{steps} of the 2000 steps",
+    }
+    del prob
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(u0, budget_s):
     """The oracle (plain C, OpenMP) on a bounded sample of the workload:
     whole residencies (4 FP64 steps + decode(encode()) at 8 bits/value) of
@@ -228,6 +375,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
     ap.add_argument("--graphs", type=int, default=0,
                     help="1: replay each residency as a HIP graph; 0: issue it on the three streams directly")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (codec, batched heat, 1024^3 wave, adjoint)")
     ap.add_argument("--pipeline-only", action="store_true",
                     help="time the pipeline variants only (no in-core rate, no link probe); for profiler runs")
     ap.add_argument("--kernel-transfers", type=int, default=0,
@@ -263,6 +412,16 @@ def main():
         return
     incore = in_core_rate(api, torch, u0)
     link = link_probe(torch)
+    extras = {}
+    if not args.no_extras:
+        extras["codec_512"] = codec_rates(api, torch, u0)
+        print(f"# codec: {extras['codec_512']}", file=sys.stderr, flush=True)
+        extras["batched_heat"] = batched_rate(api, torch, inputs)
+        print(f"# batched: {extras['batched_heat']}", file=sys.stderr, flush=True)
+        extras["wave_1024"] = wave_rates(api, torch, inputs)
+        print(f"# wave 1024^3: {extras['wave_1024']}", file=sys.stderr, flush=True)
+        extras["adjoint_512"] = adjoint_rate(api, torch, inputs)
+        print(f"# adjoint: {extras['adjoint_512']}", file=sys.stderr, flush=True)
     traffic = measured_traffic()
     kname, kstat = "fused_kernel", head["kernel"]
     achieved = kstat["achieved_GBps"]
@@ -288,6 +447,8 @@ def main():
         "speedup_vs_uncompressed": round(head["gcells_per_s"] / raw["gcells_per_s"], 3) if raw else None,
         "variants": {("uncompressed" if r == 0 else f"rate{r}"): _rounded(res) for r, res in results.items()},
         "in_core_gcells_per_s": round(incore, 1),
+        "in_core_hbm_frac": round(incore * 8 / HBM_PEAK_GBS, 4),
+        "other_workloads": extras,
         "host_link": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in link.items()},
         "paper_context": "1.20x over uncompressed out-of-core (V100-PCIe, FP64 25-point wave, 24/64 bits, Sec. VI-A)",
         "roofline": {

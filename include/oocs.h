@@ -340,11 +340,13 @@ int oocs_run(oocs_plan* plan, void* const* h_store, int64_t steps, const float* 
 
 /* ------------------------------------------------------------------------
  * Batched in-core heat domains. Many independent domains of uneven sizes
- * advance together: one launch covers every domain for one step (a
- * work-list table maps each workgroup to its domain, tile and z-chunk), and
- * `steps` such launches are replayed as one HIP graph. The tile shape and the
- * planes each thread marches are chosen per size bucket by a timing
- * autotuner whose choices persist in a cache file.
+ * advance together: one launch covers every domain (a work-list table maps
+ * each workgroup to its domain, tile and z-chunk) for k steps, and the
+ * launches of a run are replayed as one HIP graph. k > 1 is temporal
+ * blocking: a workgroup advances its tile k steps in one pass over z,
+ * recomputing a k-cell halo, so each cell crosses HBM once per k steps.
+ * The tile shape is chosen per size bucket and the depth k (1, 2 or 4) per
+ * batch by a timing autotuner whose results persist in a cache file.
  * ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -355,29 +357,35 @@ typedef struct {
 
 typedef struct oocs_batch oocs_batch;
 
-/* Device bytes of the work-list table for nd domains. */
+/* Device bytes of the work-list tables for nd domains. */
 size_t oocs_batch_table_bytes(int nd);
 
 /* Create a batch of nd domains (heat, u' = u + alpha*Laplacian, zero
  * ghosts). d_table: device memory of oocs_batch_table_bytes(nd) bytes.
- * tune: 1 = time the tile candidates on this GPU for every size bucket not
- * found in the cache (the domains' own u buffers are read, their scratch
- * buffers written; states are unchanged), 0 = use the cache, else the
- * default tile. tune_cache: path of the cache file (NULL = no cache). The
- * caller keeps the domain buffers and d_table alive until destroy. */
+ * tune: 1 = time the tile candidates of every depth on this GPU for every
+ * size bucket not found in the cache (the domains' own u buffers are read,
+ * their scratch buffers written; states are unchanged), 0 = use the cache,
+ * else the default tiles. depth: 0 = the depth with the least estimated
+ * time per step (timed or cached; 1 if unknown), or 1, 2, 4 to force it.
+ * tune_cache: path of the cache file (NULL = no cache). The caller keeps the
+ * domain buffers and d_table alive until destroy.
+ * Errors: OOCS_E_ARG, OOCS_E_SIZE, OOCS_E_HIP. */
 int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_table, size_t table_bytes,
-                      const char* tune_cache, int tune, void* stream, oocs_batch** out);
+                      const char* tune_cache, int tune, int depth, void* stream, oocs_batch** out);
 
 /* Advance every domain `steps` steps as one graph launch on `stream`
- * (built once per step count). Asynchronous. */
+ * (steps / k launches at depth k, then steps mod k launches at depth 1;
+ * built once per step count). Asynchronous. */
 int oocs_batch_run(oocs_batch* b, int64_t steps, void* stream);
 
-/* Baseline: the same steps as separate launches, domain after domain. */
+/* Baseline: the same launches as separate kernel launches, domain after
+ * domain. */
 int oocs_batch_run_per_domain(oocs_batch* b, int64_t steps, void* stream);
 
-/* Tile configuration chosen for a domain: threads per tile in x and y and
- * planes marched per thread. */
-int oocs_batch_domain_tile(const oocs_batch* b, int domain, int* tx, int* ty, int* zc);
+/* Tile configuration chosen for a domain at the batch depth: tx, ty (threads
+ * per tile for k = 1; tile cells including the halo for k > 1), planes per
+ * z chunk, and the depth k. */
+int oocs_batch_domain_tile(const oocs_batch* b, int domain, int* tx, int* ty, int* zc, int* k);
 
 int oocs_batch_destroy(oocs_batch* b);
 

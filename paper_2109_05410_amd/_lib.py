@@ -120,11 +120,12 @@ _SIGS = {
     "oocs_plan_set_profiling": (C.c_int, [_P, C.c_int]),
     "oocs_plan_set_graphs": (C.c_int, [_P, C.c_int]),
     "oocs_batch_table_bytes": (C.c_size_t, [C.c_int]),
-    "oocs_batch_create": (C.c_int, [C.POINTER(Domain), C.c_int, C.c_float, _P, C.c_size_t, C.c_char_p, C.c_int, _P,
-                                    C.POINTER(_P)]),
+    "oocs_batch_create": (C.c_int, [C.POINTER(Domain), C.c_int, C.c_float, _P, C.c_size_t, C.c_char_p, C.c_int,
+                                    C.c_int, _P, C.POINTER(_P)]),
     "oocs_batch_run": (C.c_int, [_P, _I64, _P]),
     "oocs_batch_run_per_domain": (C.c_int, [_P, _I64, _P]),
-    "oocs_batch_domain_tile": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "oocs_batch_domain_tile": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                         C.POINTER(C.c_int)]),
     "oocs_batch_destroy": (C.c_int, [_P]),
     "oocs_adjoint_workspace_bytes": (C.c_size_t, [C.POINTER(AdjointCfg)]),
     "oocs_adjoint_ckpt_bytes": (C.c_size_t, [C.POINTER(AdjointCfg)]),

@@ -365,11 +365,13 @@ class WaveMisfit(torch.autograd.Function):
 # ---------------------------------------------------------------------------
 
 class HeatBatch:
-    """Independent heat domains advanced together (one launch per step for
-    all domains, all steps replayed as one graph). `fields` are (nz, ny, nx)
-    float32 device tensors, updated in place by run()."""
+    """Independent heat domains advanced together (one launch per k steps for
+    all domains, all launches replayed as one graph). `fields` are
+    (nz, ny, nx) float32 device tensors, updated in place by run(). depth:
+    0 = temporal-blocking depth chosen by the autotuner, or 1, 2, 4."""
 
-    def __init__(self, fields, alpha: float = 0.1, tune: bool = True, tune_cache: str | None = None):
+    def __init__(self, fields, alpha: float = 0.1, tune: bool = True, tune_cache: str | None = None,
+                 depth: int = 0):
         self.fields = [f for f in fields]
         for f in self.fields:
             _field_any(f)
@@ -384,7 +386,7 @@ class HeatBatch:
         h = C.c_void_p()
         L.check(L.lib().oocs_batch_create(arr, n, C.c_float(alpha), _dptr(self.table), self.table.numel(),
                                           tune_cache.encode() if tune_cache else None, 1 if tune else 0,
-                                          _stream_ptr(), C.byref(h)))
+                                          int(depth), _stream_ptr(), C.byref(h)))
         self._h = h
 
     def run(self, steps: int, stream=None):
@@ -394,9 +396,14 @@ class HeatBatch:
         L.check(L.lib().oocs_batch_run_per_domain(self._h, steps, _stream_ptr(stream)))
 
     def tile(self, i: int):
-        tx, ty, zc = C.c_int(), C.c_int(), C.c_int()
-        L.check(L.lib().oocs_batch_domain_tile(self._h, i, C.byref(tx), C.byref(ty), C.byref(zc)))
-        return tx.value, ty.value, zc.value
+        """(tx, ty, zc, k) of domain i's configuration at the batch depth."""
+        tx, ty, zc, k = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        L.check(L.lib().oocs_batch_domain_tile(self._h, i, C.byref(tx), C.byref(ty), C.byref(zc), C.byref(k)))
+        return tx.value, ty.value, zc.value, k.value
+
+    @property
+    def depth(self) -> int:
+        return self.tile(0)[3]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -1,9 +1,11 @@
-// batch.cpp -- batched in-core heat domains: work-list table, autotuner
-// with a cache file, graph of batched steps, per-domain baseline.
+// batch.cpp -- batched in-core heat domains: work-list tables, autotuner of
+// the tile shape (per size bucket) and of the temporal-blocking depth (per
+// batch) with a cache file, graph of batched launches, per-domain baseline.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <climits>
 #include <fstream>
 #include <map>
 #include <sstream>
@@ -20,9 +22,13 @@ using oocs::fail;
 
 struct oocs_batch {
     std::vector<oocs_domain> doms;
-    std::vector<oocs::BatchDomain> table;
-    oocs::BatchDomain* d_table = nullptr;
-    int32_t total_wg = 0;
+    // two work lists: [0] every domain at the batch depth, [1] at depth 1
+    // (the steps left when the step count is not a multiple of the depth)
+    std::vector<oocs::BatchDomain> table[2];
+    oocs::BatchDomain* d_table = nullptr;  // both lists, [0] then [1]
+    int32_t total_wg[2] = {0, 0};
+    size_t lds[2] = {0, 0};
+    int depth = 1;
     float alpha = 0.1f;
     std::map<int64_t, hipGraphExec_t> graphs;  // by step count
 };
@@ -65,7 +71,7 @@ std::map<std::string, int> read_cache(const char* path)
         size_t k = t.find(':', j);
         if (k == std::string::npos) break;
         int v = -1;
-        if (std::sscanf(t.c_str() + k + 1, "%d", &v) == 1 && v >= 0 && v < oocs::kNumTileCfgs) m[key] = v;
+        if (std::sscanf(t.c_str() + k + 1, "%d", &v) == 1 && v >= 0) m[key] = v;
         i = j + 1;
     }
     return m;
@@ -80,13 +86,12 @@ void write_cache(const char* path, const std::map<std::string, int>& m)
     size_t n = 0;
     for (const auto& kv : m) {
         f << "  \"" << kv.first << "\": " << kv.second << (++n < m.size() ? ",\n" : "\n");
-        const oocs::TileCfg& t = oocs::kTileCfgs[kv.second];
-        (void)t;
     }
     f << "}\n";
 }
 
-// Time one tile configuration on a domain: median of 3 timed launches.
+// Time one tile configuration on a domain: median of 3 timed launches (each
+// the configuration's k steps).
 int time_cfg(const oocs_domain& d, float alpha, int cfg, hipStream_t s, float* ms_out)
 {
     hipEvent_t e0, e1;
@@ -116,13 +121,14 @@ int time_cfg(const oocs_domain& d, float alpha, int cfg, hipStream_t s, float* m
 
 extern "C" {
 
-size_t oocs_batch_table_bytes(int nd) { return nd > 0 ? (size_t)nd * sizeof(oocs::BatchDomain) : 0; }
+size_t oocs_batch_table_bytes(int nd) { return nd > 0 ? 2 * (size_t)nd * sizeof(oocs::BatchDomain) : 0; }
 
 int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_table, size_t table_bytes,
-                      const char* tune_cache, int tune, void* stream, oocs_batch** out)
+                      const char* tune_cache, int tune, int depth, void* stream, oocs_batch** out)
 {
     if (!doms || nd <= 0 || !d_table || !out) return fail(OOCS_E_ARG, "bad argument");
     if (table_bytes < oocs_batch_table_bytes(nd)) return fail(OOCS_E_SIZE, "table buffer too small");
+    if (depth != 0 && depth != 1 && depth != 2 && depth != 4) return fail(OOCS_E_ARG, "depth must be 0, 1, 2 or 4");
     *out = nullptr;
     for (int i = 0; i < nd; ++i) {
         const oocs_domain& d = doms[i];
@@ -136,53 +142,90 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
     b->doms.assign(doms, doms + nd);
     b->alpha = alpha;
     b->d_table = static_cast<oocs::BatchDomain*>(d_table);
-    // autotune per size bucket
     const std::string arch = arch_name();
     std::map<std::string, int> cache = read_cache(tune_cache);
-    std::map<int, int> choice;  // bucket -> cfg
     bool cache_dirty = false;
+    std::vector<int> depths = depth ? std::vector<int>{depth} : std::vector<int>{1, 2, 4};
+    if (std::find(depths.begin(), depths.end(), 1) == depths.end()) depths.push_back(1);
+    // per (bucket, depth): the best configuration and its time per step per cell (ps), or -1 if unknown
+    std::map<std::pair<int, int>, std::pair<int, int64_t>> best;
     for (int i = 0; i < nd; ++i) {
         const int bk = bucket_of(doms[i]);
-        if (choice.count(bk)) continue;
-        const std::string key = arch + "/heat7/bucket" + std::to_string(bk);
-        auto it = cache.find(key);
-        if (it != cache.end()) { choice[bk] = it->second; continue; }
-        if (!tune) { choice[bk] = 0; continue; }
-        // representative: the largest domain of the bucket
-        int rep = i;
-        for (int q = 0; q < nd; ++q)
-            if (bucket_of(doms[q]) == bk && doms[q].nx * doms[q].ny * doms[q].nz > doms[rep].nx * doms[rep].ny * doms[rep].nz)
-                rep = q;
-        int best = 0;
-        float best_ms = 0;
-        for (int c = 0; c < oocs::kNumTileCfgs; ++c) {
-            float ms;
-            const int rc = time_cfg(doms[rep], alpha, c, s, &ms);
-            if (rc) { delete b; return rc; }
-            if (c == 0 || ms < best_ms) { best = c; best_ms = ms; }
+        for (int dk : depths) {
+            if (best.count({bk, dk})) continue;
+            const std::string key = arch + "/heat7/bucket" + std::to_string(bk) + "/k" + std::to_string(dk);
+            auto it = cache.find(key);
+            auto itp = cache.find(key + "/ps_per_cell");
+            if (it != cache.end() && it->second < oocs::kNumTileCfgs && oocs::kTileCfgs[it->second].k == dk) {
+                best[{bk, dk}] = {it->second, itp != cache.end() ? (int64_t)itp->second : -1};
+                continue;
+            }
+            int first = 0;
+            while (oocs::kTileCfgs[first].k != dk) ++first;
+            if (!tune) { best[{bk, dk}] = {first, -1}; continue; }
+            // representative: the largest domain of the bucket
+            int rep = i;
+            for (int q = 0; q < nd; ++q)
+                if (bucket_of(doms[q]) == bk &&
+                    doms[q].nx * doms[q].ny * doms[q].nz > doms[rep].nx * doms[rep].ny * doms[rep].nz)
+                    rep = q;
+            const double cells = (double)doms[rep].nx * doms[rep].ny * doms[rep].nz;
+            int bc = first;
+            float best_ms = -1;
+            for (int c = 0; c < oocs::kNumTileCfgs; ++c) {
+                if (oocs::kTileCfgs[c].k != dk) continue;
+                float ms;
+                const int rc = time_cfg(doms[rep], alpha, c, s, &ms);
+                if (rc) { delete b; return rc; }
+                if (best_ms < 0 || ms < best_ms) { bc = c; best_ms = ms; }
+            }
+            const int64_t ps = (int64_t)std::llround(best_ms * 1e9 / dk / cells);
+            best[{bk, dk}] = {bc, ps};
+            cache[key] = bc;
+            cache[key + "/ps_per_cell"] = (int)std::min<int64_t>(ps, INT32_MAX);
+            cache_dirty = true;
         }
-        choice[bk] = best;
-        cache[key] = best;
-        cache_dirty = true;
     }
     if (cache_dirty) write_cache(tune_cache, cache);
-    int32_t total = 0;
-    b->table.resize(nd);
-    for (int i = 0; i < nd; ++i) {
-        oocs::BatchDomain& e = b->table[i];
-        e.a = doms[i].d_u;
-        e.b = doms[i].d_scratch;
-        e.nx = (int32_t)doms[i].nx; e.ny = (int32_t)doms[i].ny; e.nz = (int32_t)doms[i].nz;
-        e.cfg = choice[bucket_of(doms[i])];
-        e.wg_begin = total;
-        e.pad = 0;
-        const int64_t w = oocs::batch_domain_workgroups(e.nx, e.ny, e.nz, e.cfg);
-        if (total + w > INT32_MAX / 2) { delete b; return fail(OOCS_E_ARG, "batch too large for one launch"); }
-        total += (int32_t)w;
+    // depth: the forced one, else the one with the least estimated time per step
+    b->depth = depths[0];
+    if (!depth) {
+        double best_t = -1;
+        for (int dk : depths) {
+            double t = 0;
+            bool known = true;
+            for (int i = 0; i < nd && known; ++i) {
+                const auto& e = best[{bucket_of(doms[i]), dk}];
+                if (e.second < 0) known = false;
+                t += (double)e.second * doms[i].nx * doms[i].ny * doms[i].nz;
+            }
+            if (!known) continue;
+            if (best_t < 0 || t < best_t) { best_t = t; b->depth = dk; }
+        }
+        if (best_t < 0) b->depth = 1;
     }
-    b->total_wg = total;
-    hipError_t e = hipMemcpyAsync(b->d_table, b->table.data(), b->table.size() * sizeof(oocs::BatchDomain),
-                                  hipMemcpyHostToDevice, s);
+    for (int w = 0; w < 2; ++w) {
+        const int dk = w == 0 ? b->depth : 1;
+        int32_t total = 0;
+        b->table[w].resize(nd);
+        for (int i = 0; i < nd; ++i) {
+            oocs::BatchDomain& e = b->table[w][i];
+            e.a = doms[i].d_u;
+            e.b = doms[i].d_scratch;
+            e.nx = (int32_t)doms[i].nx; e.ny = (int32_t)doms[i].ny; e.nz = (int32_t)doms[i].nz;
+            e.cfg = best[{bucket_of(doms[i]), dk}].first;
+            e.wg_begin = total;
+            e.pad = 0;
+            const int64_t wgs = oocs::batch_domain_workgroups(e.nx, e.ny, e.nz, e.cfg);
+            if (total + wgs > INT32_MAX / 2) { delete b; return fail(OOCS_E_ARG, "batch too large for one launch"); }
+            total += (int32_t)wgs;
+            b->lds[w] = std::max(b->lds[w], oocs::tile_cfg_lds(e.cfg));
+        }
+        b->total_wg[w] = total;
+    }
+    hipError_t e = hipMemcpyAsync(b->d_table, b->table[0].data(), nd * sizeof(oocs::BatchDomain), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_table + nd, b->table[1].data(), nd * sizeof(oocs::BatchDomain), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { delete b; return oocs::hip_fail(e, "table upload"); }
     *out = b;
@@ -200,14 +243,17 @@ int oocs_batch_run(oocs_batch* b, int64_t steps, void* stream)
         HIP_TRY(hipGraphCreate(&g, 0));
         hipGraphNode_t prev = nullptr;
         hipError_t e = hipSuccess;
-        for (int64_t t = 0; t < steps && e == hipSuccess; ++t) {
+        const int nd = (int)b->doms.size();
+        const int64_t full = steps / b->depth, rest = steps % b->depth;
+        int64_t launches = 0;
+        for (int64_t t = 0; t < full + rest && e == hipSuccess; ++t, ++launches) {
+            const int w = t < full ? 0 : 1;
             hipGraphNode_t n;
-            e = oocs::add_batch_step_node(b->d_table, (int)b->table.size(), b->total_wg, (int)(t & 1), b->alpha, g,
-                                          prev ? &prev : nullptr, prev ? 1 : 0, &n);
+            e = oocs::add_batch_step_node(b->d_table + (size_t)w * nd, nd, b->total_wg[w], b->lds[w], (int)(t & 1),
+                                          b->alpha, g, prev ? &prev : nullptr, prev ? 1 : 0, &n);
             prev = n;
         }
-        if (e == hipSuccess && (steps & 1)) {  // the state is in the scratch buffers: copy it back
-            std::vector<hipGraphNode_t> copies;
+        if (e == hipSuccess && (launches & 1)) {  // the state is in the scratch buffers: copy it back
             for (const oocs_domain& d : b->doms) {
                 hipGraphNode_t n;
                 e = hipGraphAddMemcpyNode1D(&n, g, &prev, 1, d.d_u, d.d_scratch, (size_t)(d.nx * d.ny * d.nz * 4),
@@ -229,27 +275,29 @@ int oocs_batch_run_per_domain(oocs_batch* b, int64_t steps, void* stream)
 {
     if (!b || steps < 0) return fail(OOCS_E_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
+    const int64_t full = steps / b->depth, rest = steps % b->depth;
     for (size_t i = 0; i < b->doms.size(); ++i) {
         const oocs_domain& d = b->doms[i];
-        const int cfg = b->table[i].cfg;
-        for (int64_t t = 0; t < steps; ++t) {
+        for (int64_t t = 0; t < full + rest; ++t) {
+            const int cfg = b->table[t < full ? 0 : 1][i].cfg;
             const float* src = (t & 1) ? d.d_scratch : d.d_u;
             float* dst = (t & 1) ? d.d_u : d.d_scratch;
             HIP_TRY(oocs::launch_heat_dense(src, dst, (int)d.nx, (int)d.ny, (int)d.nz, b->alpha, cfg, s));
         }
-        if (steps & 1)
+        if ((full + rest) & 1)
             HIP_TRY(hipMemcpyAsync(d.d_u, d.d_scratch, (size_t)(d.nx * d.ny * d.nz * 4), hipMemcpyDeviceToDevice, s));
     }
     return OOCS_OK;
 }
 
-int oocs_batch_domain_tile(const oocs_batch* b, int domain, int* tx, int* ty, int* zc)
+int oocs_batch_domain_tile(const oocs_batch* b, int domain, int* tx, int* ty, int* zc, int* k)
 {
-    if (!b || domain < 0 || domain >= (int)b->table.size()) return fail(OOCS_E_ARG, "bad argument");
-    const oocs::TileCfg& t = oocs::kTileCfgs[b->table[domain].cfg];
+    if (!b || domain < 0 || domain >= (int)b->doms.size()) return fail(OOCS_E_ARG, "bad argument");
+    const oocs::TileCfg& t = oocs::kTileCfgs[b->table[0][domain].cfg];
     if (tx) *tx = t.tx;
     if (ty) *ty = t.ty;
     if (zc) *zc = t.zc;
+    if (k) *k = t.k;
     return OOCS_OK;
 }
 

@@ -116,9 +116,10 @@ hipError_t launch_fill(float* x, float value, int64_t n, hipStream_t s);
 // Tile configurations the batch autotuner chooses from (TX x TY threads,
 // ZC planes per thread).
 struct TileCfg {
-    int tx, ty, zc;
+    int tx, ty, zc;  // threads per tile in x and y (k = 1) or tile size in cells (k > 1); planes per chunk
+    int k;           // steps per launch (temporal-blocking depth)
 };
-constexpr int kNumTileCfgs = 6;
+constexpr int kNumTileCfgs = 10;
 extern const TileCfg kTileCfgs[kNumTileCfgs];
 
 struct BatchDomain {   // one entry of the device work-list table
@@ -133,13 +134,17 @@ struct BatchDomain {   // one entry of the device work-list table
 // Workgroups one domain needs with tile configuration cfg.
 int32_t batch_domain_workgroups(int nx, int ny, int nz, int cfg);
 
+// Dynamic LDS bytes a tile configuration needs (0 for k = 1).
+size_t tile_cfg_lds(int cfg);
+
 // One step of every domain: parity 0 reads a and writes b, 1 the reverse.
-hipError_t launch_batch_step(const BatchDomain* d_table, int nd, int32_t total_wg, int parity, float alpha,
-                             hipStream_t stream);
-hipError_t add_batch_step_node(const BatchDomain* d_table, int nd, int32_t total_wg, int parity, float alpha,
-                               hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node);
-// One step of one dense domain with tile configuration cfg (tuning and the
-// per-domain baseline).
+hipError_t launch_batch_step(const BatchDomain* d_table, int nd, int32_t total_wg, size_t lds, int parity,
+                             float alpha, hipStream_t stream);
+hipError_t add_batch_step_node(const BatchDomain* d_table, int nd, int32_t total_wg, size_t lds, int parity,
+                               float alpha, hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps,
+                               hipGraphNode_t* node);
+// One launch (the configuration's k steps) of one dense domain with tile
+// configuration cfg (tuning and the per-domain baseline).
 hipError_t launch_heat_dense(const float* src, float* dst, int nx, int ny, int nz, float alpha, int cfg,
                              hipStream_t stream);
 

@@ -395,39 +395,79 @@ hipError_t launch_swap(float* a, float* b, int64_t n, hipStream_t stream)
 // Batched heat domains: one launch advances every domain one step
 // ---------------------------------------------------------------------------
 
-const TileCfg kTileCfgs[kNumTileCfgs] = {{64, 4, 16}, {64, 4, 32}, {64, 4, 64}, {32, 8, 16}, {128, 2, 16}, {64, 4, 8}};
+// k = 1: threads per tile (tx * ty = 256) and planes marched per thread.
+// k > 1: a 64 x ty cell tile (halo k cells on each side included) advanced k
+// steps per launch over z chunks of zc planes (heat_tb).
+const TileCfg kTileCfgs[kNumTileCfgs] = {{64, 4, 16, 1},  {64, 4, 32, 1},   {64, 4, 64, 1}, {32, 8, 16, 1},
+                                         {128, 2, 16, 1}, {64, 4, 8, 1},    {64, 16, 64, 2}, {64, 16, 128, 2},
+                                         {64, 32, 64, 2}, {64, 16, 64, 4}};
 
-template <int C>
-__device__ inline void heat_dense_cfg(const float* src, float* dst, int nx, int ny, int nz, float alpha, int wg)
+size_t tile_cfg_lds(int cfg)
 {
-    constexpr TileCfg t = C == 0 ? TileCfg{64, 4, 16} : C == 1 ? TileCfg{64, 4, 32} : C == 2 ? TileCfg{64, 4, 64}
-                        : C == 3 ? TileCfg{32, 8, 16} : C == 4 ? TileCfg{128, 2, 16} : TileCfg{64, 4, 8};
-    stencil::heat_dense<t.tx, t.ty, t.zc>(src, dst, nx, ny, nz, alpha, wg);
+    const TileCfg& t = kTileCfgs[cfg];
+    return t.k > 1 ? (size_t)t.k * 2 * t.ty * 64 * sizeof(float) : 0;
 }
 
-__device__ inline void heat_dense_any(int cfg, const float* src, float* dst, int nx, int ny, int nz, float alpha, int wg)
+template <int C>
+__device__ __attribute__((always_inline)) inline void heat_dense_cfg(const float* src, float* dst, int nx, int ny, int nz, float alpha, int wg,
+                                      float* lds)
 {
-    switch (cfg) {
-    case 0: heat_dense_cfg<0>(src, dst, nx, ny, nz, alpha, wg); break;
-    case 1: heat_dense_cfg<1>(src, dst, nx, ny, nz, alpha, wg); break;
-    case 2: heat_dense_cfg<2>(src, dst, nx, ny, nz, alpha, wg); break;
-    case 3: heat_dense_cfg<3>(src, dst, nx, ny, nz, alpha, wg); break;
-    case 4: heat_dense_cfg<4>(src, dst, nx, ny, nz, alpha, wg); break;
-    default: heat_dense_cfg<5>(src, dst, nx, ny, nz, alpha, wg); break;
+    if constexpr (C == 6) stencil::heat_tb<16, 2>(src, dst, nx, ny, nz, alpha, 64, wg, lds);
+    else if constexpr (C == 7) stencil::heat_tb<16, 2>(src, dst, nx, ny, nz, alpha, 128, wg, lds);
+    else if constexpr (C == 8) stencil::heat_tb<32, 2>(src, dst, nx, ny, nz, alpha, 64, wg, lds);
+    else if constexpr (C == 9) stencil::heat_tb<16, 4>(src, dst, nx, ny, nz, alpha, 64, wg, lds);
+    else {
+        constexpr TileCfg t = C == 0 ? TileCfg{64, 4, 16, 1} : C == 1 ? TileCfg{64, 4, 32, 1}
+                            : C == 2 ? TileCfg{64, 4, 64, 1} : C == 3 ? TileCfg{32, 8, 16, 1}
+                            : C == 4 ? TileCfg{128, 2, 16, 1} : TileCfg{64, 4, 8, 1};
+        stencil::heat_dense<t.tx, t.ty, t.zc>(src, dst, nx, ny, nz, alpha, wg);
+    }
+}
+
+// TB = false: the depth-1 configurations only; TB = true: the temporally
+// blocked ones. Separate kernels keep the depth-1 code at its own register
+// count (a kernel's occupancy follows its costliest path).
+template <bool TB>
+__device__ __attribute__((always_inline)) inline void heat_dense_any(int cfg, const float* src, float* dst, int nx, int ny, int nz, float alpha, int wg,
+                                      float* lds)
+{
+    if constexpr (TB) {
+        switch (cfg) {
+        case 6: heat_dense_cfg<6>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        case 7: heat_dense_cfg<7>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        case 8: heat_dense_cfg<8>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        default: heat_dense_cfg<9>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        }
+    } else {
+        switch (cfg) {
+        case 0: heat_dense_cfg<0>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        case 1: heat_dense_cfg<1>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        case 2: heat_dense_cfg<2>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        case 3: heat_dense_cfg<3>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        case 4: heat_dense_cfg<4>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        default: heat_dense_cfg<5>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        }
     }
 }
 
 int32_t batch_domain_workgroups(int nx, int ny, int nz, int cfg)
 {
     const TileCfg& t = kTileCfgs[cfg];
+    if (t.k > 1) {
+        const int ox = t.tx - 2 * t.k, oy = t.ty - 2 * t.k;
+        return ((nx + ox - 1) / ox) * ((ny + oy - 1) / oy) * ((nz + t.zc - 1) / t.zc);
+    }
     return ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty) * ((nz + t.zc - 1) / t.zc);
 }
 
+// One launch advances every domain of the table by its configuration's k
+// steps (the table holds one depth). Workgroup -> domain by binary search.
+template <bool TB>
 __global__ void __launch_bounds__(kBlockThreads)
 batch_step_kernel(const BatchDomain* __restrict__ table, int nd, int parity, float alpha)
 {
     const int wg = (int)blockIdx.x;
-    int lo = 0, hi = nd - 1;  // last domain with wg_begin <= wg
+    int lo = 0, hi = nd - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) / 2;
         if (table[mid].wg_begin <= wg) lo = mid; else hi = mid - 1;
@@ -435,33 +475,39 @@ batch_step_kernel(const BatchDomain* __restrict__ table, int nd, int parity, flo
     const BatchDomain& d = table[lo];
     const float* src = parity ? d.b : d.a;
     float* dst = parity ? d.a : d.b;
-    heat_dense_any(d.cfg, src, dst, d.nx, d.ny, d.nz, alpha, wg - d.wg_begin);
+    heat_dense_any<TB>(d.cfg, src, dst, d.nx, d.ny, d.nz, alpha, wg - d.wg_begin, reinterpret_cast<float*>(dyn_lds));
 }
 
+template <bool TB>
 __global__ void __launch_bounds__(kBlockThreads)
 heat_dense_kernel(const float* src, float* dst, int nx, int ny, int nz, float alpha, int cfg)
 {
-    heat_dense_any(cfg, src, dst, nx, ny, nz, alpha, (int)blockIdx.x);
+    heat_dense_any<TB>(cfg, src, dst, nx, ny, nz, alpha, (int)blockIdx.x, reinterpret_cast<float*>(dyn_lds));
 }
 
-hipError_t launch_batch_step(const BatchDomain* d_table, int nd, int32_t total_wg, int parity, float alpha,
-                             hipStream_t stream)
+hipError_t launch_batch_step(const BatchDomain* d_table, int nd, int32_t total_wg, size_t lds, int parity,
+                             float alpha, hipStream_t stream)
 {
     if (total_wg <= 0 || nd <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_step_kernel, dim3((unsigned)total_wg), dim3(kBlockThreads), 0, stream, d_table, nd,
-                       parity, alpha);
+    if (lds > 0)
+        hipLaunchKernelGGL(batch_step_kernel<true>, dim3((unsigned)total_wg), dim3(kBlockThreads), lds, stream, d_table,
+                           nd, parity, alpha);
+    else
+        hipLaunchKernelGGL(batch_step_kernel<false>, dim3((unsigned)total_wg), dim3(kBlockThreads), 0, stream, d_table,
+                           nd, parity, alpha);
     return hipGetLastError();
 }
 
-hipError_t add_batch_step_node(const BatchDomain* d_table, int nd, int32_t total_wg, int parity, float alpha,
-                               hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node)
+hipError_t add_batch_step_node(const BatchDomain* d_table, int nd, int32_t total_wg, size_t lds, int parity,
+                               float alpha, hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps,
+                               hipGraphNode_t* node)
 {
     void* args[] = {&d_table, &nd, &parity, &alpha};
     hipKernelNodeParams kp{};
-    kp.func = reinterpret_cast<void*>(&batch_step_kernel);
+    kp.func = lds > 0 ? reinterpret_cast<void*>(&batch_step_kernel<true>) : reinterpret_cast<void*>(&batch_step_kernel<false>);
     kp.gridDim = dim3((unsigned)total_wg);
     kp.blockDim = dim3(kBlockThreads);
-    kp.sharedMemBytes = 0;
+    kp.sharedMemBytes = (unsigned)lds;
     kp.kernelParams = args;
     kp.extra = nullptr;
     return hipGraphAddKernelNode(node, g, deps, ndeps, &kp);
@@ -472,8 +518,12 @@ hipError_t launch_heat_dense(const float* src, float* dst, int nx, int ny, int n
 {
     const int32_t wgs = batch_domain_workgroups(nx, ny, nz, cfg);
     if (wgs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(heat_dense_kernel, dim3((unsigned)wgs), dim3(kBlockThreads), 0, stream, src, dst, nx, ny, nz,
-                       alpha, cfg);
+    if (kTileCfgs[cfg].k > 1)
+        hipLaunchKernelGGL(heat_dense_kernel<true>, dim3((unsigned)wgs), dim3(kBlockThreads), tile_cfg_lds(cfg), stream,
+                           src, dst, nx, ny, nz, alpha, cfg);
+    else
+        hipLaunchKernelGGL(heat_dense_kernel<false>, dim3((unsigned)wgs), dim3(kBlockThreads), 0, stream, src, dst, nx,
+                           ny, nz, alpha, cfg);
     return hipGetLastError();
 }
 

@@ -99,12 +99,14 @@ __device__ inline void heat_level(const Job& j, int nx, int ny, int nz, float al
 }
 
 // Heat on a dense field with a tile shape chosen at compile time (batched
-// domains): tile TX x TY columns per 256-thread workgroup (TX*TY = 256),
-// ZC planes marched per thread. Same operation order as heat_level.
+// domains, any nx): tile TX x TY columns per 256-thread workgroup
+// (TX*TY = 256), ZC planes marched per thread, the inputs of 4 planes loaded
+// before any is computed. Same operation order as heat_level.
 template <int TX, int TY, int ZC>
-__device__ inline void heat_dense(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
-                                  float alpha, int wg)
+__device__ __attribute__((always_inline)) inline void heat_dense(const float* __restrict__ src, float* __restrict__ dst,
+                                                                 int nx, int ny, int nz, float alpha, int wg)
 {
+    constexpr int NB = 4;
     const int tiles_x = (nx + TX - 1) / TX;
     const int tiles_y = (ny + TY - 1) / TY;
     const int tile = wg % (tiles_x * tiles_y);
@@ -116,21 +118,37 @@ __device__ inline void heat_dense(const float* __restrict__ src, float* __restri
     if (x >= nx || y >= ny || z0 >= z1) return;
     const int64_t plane = (int64_t)nx * ny;
     const int64_t xy = (int64_t)y * nx + x;
+    const bool hx0 = x > 0, hx1 = x + 1 < nx, hy0 = y > 0, hy1 = y + 1 < ny;
     float cm = z0 > 0 ? src[(z0 - 1) * plane + xy] : 0.0f;
-    float cc = src[z0 * plane + xy];
-    for (int z = z0; z < z1; ++z) {
-        const float* pl = src + z * plane + xy;
-        const float cp = z + 1 < nz ? pl[plane] : 0.0f;
-        const float xm = x > 0 ? pl[-1] : 0.0f;
-        const float xp = x + 1 < nx ? pl[1] : 0.0f;
-        const float ym = y > 0 ? pl[-nx] : 0.0f;
-        const float yp = y + 1 < ny ? pl[nx] : 0.0f;
-        float s = (xm + xp) + (ym + yp);
-        s = s + (cm + cp);
-        s = s - 6.0f * cc;
-        dst[z * plane + xy] = cc + alpha * s;
-        cm = cc;
-        cc = cp;
+    for (int zb = z0; zb < z1; zb += NB) {
+        float c[NB + 1], xm[NB], xp[NB], ym[NB], yp[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            c[i] = xm[i] = xp[i] = ym[i] = yp[i] = 0.0f;
+            if (zb + i < z1) {
+                const float* pl = src + (zb + i) * plane + xy;
+                c[i] = pl[0];
+                if (hx0) xm[i] = pl[-1];
+                if (hx1) xp[i] = pl[1];
+                if (hy0) ym[i] = pl[-nx];
+                if (hy1) yp[i] = pl[nx];
+            }
+        }
+        const int zt = min(zb + NB, z1);
+        c[NB] = 0.0f;
+#pragma unroll
+        for (int i = 1; i <= NB; ++i)
+            if (zt == zb + i && zt < nz) c[i] = src[zt * plane + xy];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (zb + i < z1) {
+                const float zm = i == 0 ? cm : c[i - 1];
+                float t = (xm[i] + xp[i]) + (ym[i] + yp[i]);
+                t = t + (zm + c[i + 1]);
+                t = t - 6.0f * c[i];
+                dst[(zb + i) * plane + xy] = c[i] + alpha * t;
+            }
+        cm = c[NB - 1];
     }
 }
 
@@ -150,7 +168,7 @@ __device__ inline void heat_dense(const float* __restrict__ src, float* __restri
 // heat_level, so the result equals K single steps bit for bit. lds holds
 // K * 2 * TY * 64 floats.
 template <int TY, int K>
-__device__ inline void heat_tb(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
+__device__ __attribute__((always_inline)) inline void heat_tb(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
                                float alpha, int zch, int wg, float* lds)
 {
     constexpr int TX = 64, CPT = TY / 4, OX = TX - 2 * K, OY = TY - 2 * K;

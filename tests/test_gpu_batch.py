@@ -1,7 +1,8 @@
-"""Batched uneven heat domains (one launch per step for all domains, all
-steps in one graph launch; autotuned tiles): every domain equals the
-oracle's FP32 steps bit for bit (small domains) and the per-domain launch
-baseline bit for bit (the 64-domain workload at full size)."""
+"""Batched uneven heat domains (one launch per k steps for all domains, all
+launches in one graph launch; autotuned tiles and temporal-blocking depth):
+every domain equals the oracle's FP32 steps bit for bit (small domains, every
+depth, step counts that are not multiples of the depth) and the per-domain
+launch baseline bit for bit (the 64-domain workload at full size)."""
 import os
 
 import numpy as np
@@ -29,6 +30,28 @@ def test_small_uneven_domains_match_oracle(steps, tmp_path):
     # the per-domain baseline computes the same
     fields2 = [torch.from_numpy(u).to(DEV) for u in u0]
     b2 = api.HeatBatch(fields2, alpha=0.1, tune=False, tune_cache=str(tmp_path / "tune.json"))
+    b2.run_per_domain(steps)
+    torch.cuda.synchronize()
+    for f, g in zip(fields, fields2):
+        assert torch.equal(f, g)
+
+
+@pytest.mark.parametrize("depth,steps", [(2, 7), (2, 8), (4, 9), (4, 3), (1, 5)])
+def test_forced_depth_matches_oracle(depth, steps):
+    """Temporal blocking: k steps per launch over tiles with a k-cell halo
+    give the single-step result bit for bit, on domains smaller than a tile
+    and domains spanning several tiles and z chunks."""
+    shapes = [(9, 17, 33), (140, 40, 70), (5, 3, 130), (1, 1, 1), (31, 129, 66), (3, 2, 1)]
+    u0 = [inputs.heat_uniform(s, seed=20 + i) for i, s in enumerate(shapes)]
+    fields = [torch.from_numpy(u).to(DEV) for u in u0]
+    b = api.HeatBatch(fields, alpha=0.1, tune=False, depth=depth)
+    assert b.depth == depth
+    b.run(steps)
+    torch.cuda.synchronize()
+    for u, f in zip(u0, fields):
+        assert np.array_equal(f.cpu().numpy(), O.heat7_f32(u, 0.1, steps))
+    fields2 = [torch.from_numpy(u).to(DEV) for u in u0]
+    b2 = api.HeatBatch(fields2, alpha=0.1, tune=False, depth=depth)
     b2.run_per_domain(steps)
     torch.cuda.synchronize()
     for f, g in zip(fields, fields2):
