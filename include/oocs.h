@@ -326,6 +326,13 @@ int oocs_plan_set_profiling(oocs_plan* plan, int on);
  * graph replays of consecutive residencies do not overlap. */
 int oocs_plan_set_graphs(oocs_plan* plan, int on);
 
+/* Op-by-op issue (graphs off): how a wait on an event of another stream that
+ * has not completed yet is honoured (default 1): the host blocks until the
+ * event completes and then issues the dependent work (1), or the stream is
+ * made to wait with hipStreamWaitEvent (0). Waits on completed events are
+ * skipped either way. Same results; (1) keeps the host's issue cost low. */
+int oocs_plan_set_host_waits(oocs_plan* plan, int on);
+
 /* Advance the out-of-core state held in the host stores h_store[field]
  * (one pointer per used field slot) by `steps` time steps, k per residency
  * (the last residency does steps mod k). The wave source adds h_src[s] at

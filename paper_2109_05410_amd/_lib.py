@@ -119,6 +119,7 @@ _SIGS = {
     "oocs_run": (C.c_int, [_P, C.POINTER(_P), _I64, _P, C.POINTER(Stats)]),
     "oocs_plan_set_profiling": (C.c_int, [_P, C.c_int]),
     "oocs_plan_set_graphs": (C.c_int, [_P, C.c_int]),
+    "oocs_plan_set_host_waits": (C.c_int, [_P, C.c_int]),
     "oocs_batch_table_bytes": (C.c_size_t, [C.c_int]),
     "oocs_batch_create": (C.c_int, [C.POINTER(Domain), C.c_int, C.c_float, _P, C.c_size_t, C.c_char_p, C.c_int,
                                     C.c_int, _P, C.POINTER(_P)]),

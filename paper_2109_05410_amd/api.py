@@ -281,6 +281,11 @@ class OutOfCorePlan:
     def set_graphs(self, on: bool):
         L.check(L.lib().oocs_plan_set_graphs(self._h, 1 if on else 0))
 
+    def set_host_waits(self, on: bool):
+        """Op-by-op issue: block the host on pending cross-stream events (True,
+        default) or make the stream wait on them (False)."""
+        L.check(L.lib().oocs_plan_set_host_waits(self._h, 1 if on else 0))
+
 
 # ---------------------------------------------------------------------------
 # Misfit gradient (adjoint with compressed checkpoints) and autograd

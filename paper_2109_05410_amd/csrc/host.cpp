@@ -66,6 +66,7 @@ struct oocs_plan {
     hipStream_t st[3] = {nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> ev;  // 4*nstage logical + 2*n block events (two parities)
     int profiling = 0;  // 0: off; N: time every N-th launch
+    bool host_waits = true;  // eager issue: wait on the host for pending cross-stream events
     bool graphs = false;
     std::vector<hipEvent_t> tev;  // eager timing events, two per launch, grown on demand
     // graphs by (residency length, store pointers, source on)
@@ -438,6 +439,14 @@ int oocs_plan_set_graphs(oocs_plan* pl, int on)
     return OOCS_OK;
 }
 
+int oocs_plan_set_host_waits(oocs_plan* pl, int on)
+{
+    if (!pl) return fail(OOCS_E_ARG, "null pointer");
+    if (!pl->runnable) return fail(OOCS_E_STATE, "planning-only plan");
+    pl->host_waits = on != 0;
+    return OOCS_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -786,13 +795,20 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                         break;
                     case OOCS_OP_WAIT: {
                         if (o.event >= P.ev_blk_prev(0) && chunk_round == 0 && rounds == 0) break;
-                        // A completed event orders nothing: skip the wait, which would
-                        // otherwise cost the host a cross-queue barrier.
+                        // The host waits for the event itself instead of making the stream
+                        // wait: a stream wait on a pending event from another stream costs
+                        // the host ~10 us and makes the next copy call on that stream
+                        // several times dearer, while the GPU is still two ticks behind
+                        // by the time a lagged copy is issued. A completed event is free.
                         const hipEvent_t e = phys(o.event);
                         const hipError_t q = hipEventQuery(e);
                         if (q == hipSuccess) break;
                         if (q != hipErrorNotReady) return oocs::hip_fail(q, "event query");
-                        HIP_TRY(hipStreamWaitEvent(pl->st[o.stream], e, 0));
+                        if (pl->host_waits) {
+                            HIP_TRY(hipEventSynchronize(e));
+                        } else {
+                            HIP_TRY(hipStreamWaitEvent(pl->st[o.stream], e, 0));
+                        }
                         break;
                     }
                     default:

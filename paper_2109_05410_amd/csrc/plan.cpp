@@ -328,10 +328,11 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
     // The copies a tick makes possible (write-back of its output group, load
     // of the group that reuses its input slot) are issued `lag` ticks later:
     // by then the events they wait for have usually completed, and a wait on
-    // a completed event costs the host nothing. lag < nstage keeps every
-    // wait on the record it was meant for (a slot is recorded again only
-    // nstage ticks later).
-    const int lag = std::max(1, std::min(2, nstage - 1));
+    // a completed event costs the host nothing. The load of group j + nstage
+    // is then issued nstage - lag ticks before its decode; lag < nstage keeps
+    // every wait on the record it was meant for (a slot is recorded again
+    // only nstage ticks later).
+    const int lag = std::max(1, std::min(2, nstage - 2));
     std::deque<std::vector<oocs_op>> lagged;
     std::vector<oocs_op> next;
     for (int64_t ti = 0; ti < (int64_t)s.ticks.size(); ++ti) {

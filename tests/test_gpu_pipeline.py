@@ -147,6 +147,21 @@ def test_graph_replays_with_profiling_match_eager():
     assert torch.equal(a, b)
 
 
+def test_stream_waits_match_host_waits():
+    """Cross-stream dependencies honoured by stream waits or by host waits
+    give the same store, and both equal the replay."""
+    shape = (128, 64, 64)
+    u0 = inputs.heat_uniform(shape, seed=12)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, 8, 4, [8], 2 * MiB)
+    a = store_of(plan, 0, u0)
+    b = store_of(plan, 0, u0)
+    plan.run([a], 14)
+    plan.set_host_waits(False)
+    plan.run([b], 14)
+    assert torch.equal(a, b)
+    assert np.array_equal(decoded(a, shape, 8), O.replay_heat_f32(u0, 0.1, 14, 4, 8))
+
+
 def test_wave_source_longer_than_the_source_table():
     """Runs longer than the device amplitude table are split into chunks of
     whole residencies; the source timing stays exact."""
