@@ -200,6 +200,15 @@ typedef struct {
  * host stores. */
 #define OOCS_PLAN_KERNEL_TRANSFERS 2
 
+/* Plan flag (heat with k <= 4): by default each tick computes all k time
+ * levels of its planes in one temporally blocked job (tiles with a k-cell
+ * halo, the intermediate levels held in registers and LDS), so the device
+ * holds only the decoded input and the output level, and the groups can be
+ * larger under the same cap. With this flag every level is its own job and
+ * has its own ring of planes (always the case for the wave, for k > 4 and
+ * with OOCS_PLAN_BLOCK_RESTART). Same results. */
+#define OOCS_PLAN_LEVEL_BY_LEVEL 4
+
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be
  * queried but not run (no HIP call is made for it). Chooses the group size
@@ -218,7 +227,7 @@ typedef struct {
     int64_t group;              /* planes per pipeline group */
     int64_t halo;               /* h = r * k */
     int64_t radius;             /* r */
-    int64_t nlevels;            /* time levels held on the device (inputs + k computed) */
+    int64_t nlevels;            /* time levels of a residency (inputs + k computed) */
     int64_t nrings;             /* device plane rings (levels + the read-only field) */
     int64_t ring_planes[16];    /* planes per ring; index = level, then the read-only ring */
     int64_t plane_bytes;        /* nx * ny * 4 */
@@ -247,7 +256,7 @@ int oocs_plan_slab(const oocs_plan* plan, int i, oocs_slab_info* out);
  * are FETCH / STORE jobs of the launches. */
 #define OOCS_OP_H2D 1     /* copy a group of host-store planes into an input staging slot */
 #define OOCS_OP_DECODE 2  /* decode (or copy, if uncompressed) a staging slot into a level ring */
-#define OOCS_OP_LEVEL 3   /* compute planes [z0, z1) of one time level */
+#define OOCS_OP_LEVEL 3   /* compute planes [z0, z1) of ring `level` from ring level-1, `slot` steps later */
 #define OOCS_OP_ENCODE 4  /* encode (or copy) planes of an output level into an output staging slot */
 #define OOCS_OP_D2H 5     /* copy an output staging slot to the host store */
 #define OOCS_OP_LAUNCH 6  /* issue the jobs accumulated on the compute stream as one kernel launch */

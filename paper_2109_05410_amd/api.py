@@ -173,12 +173,14 @@ class OutOfCorePlan:
     halo (the per-block schedule of Fig. 2) instead of sharing every level's
     planes with its neighbour. kernel_transfers: move groups with transfer
     jobs inside the pipeline kernel instead of hipMemcpyAsync on two copy
-    streams (the three-stream pipeline of Sec. V-B). Results are identical."""
+    streams (the three-stream pipeline of Sec. V-B). level_by_level (heat,
+    k <= 4): one job and one ring per time level instead of one temporally
+    blocked job per tick. Results are identical."""
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
                  planning_only: bool = False, device=None, block_restart: bool = False,
-                 kernel_transfers: bool = False):
+                 kernel_transfers: bool = False, level_by_level: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -190,7 +192,9 @@ class OutOfCorePlan:
             cfg.rate[i] = rates[i] if i < len(rates) else 0
         cfg.nstage = nstage
         cfg.alpha = alpha
-        cfg.flags = (L.OOCS_PLAN_BLOCK_RESTART if block_restart else 0) | (L.OOCS_PLAN_KERNEL_TRANSFERS if kernel_transfers else 0)
+        cfg.flags = ((L.OOCS_PLAN_BLOCK_RESTART if block_restart else 0)
+                     | (L.OOCS_PLAN_KERNEL_TRANSFERS if kernel_transfers else 0)
+                     | (L.OOCS_PLAN_LEVEL_BY_LEVEL if level_by_level else 0))
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg

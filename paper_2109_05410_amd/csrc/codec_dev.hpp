@@ -165,25 +165,26 @@ __device__ inline int exponent_of(float x)
 }
 
 // ---- per-lane bit writer over the wave's LDS words --------------------------
+// Branch-free: every put writes the lane's current word to LDS (the last
+// write of a word wins), so no lane takes a divergent path to flush.
 struct LaneWriter {
     uint64_t* lds;  // this wave's buffer; word w of this lane at lds[w * 64]
-    uint64_t acc;
+    uint64_t acc;   // bits of word wi written so far
     int off, wi, budget;
 
-    __device__ void put(uint64_t v, int m)
+    __device__ void put(uint64_t v, int m)  // m in [0, 64]
     {
-        if (m > budget) m = budget;
-        if (m <= 0) return;
-        if (m < 64) v &= ((uint64_t)1 << m) - 1;
-        acc |= v << off;
-        int end = off + m;
-        if (end >= 64) {
-            lds[wi * 64] = acc;
-            ++wi;
-            acc = off == 0 ? 0 : (v >> (64 - off));
-            end -= 64;
-        }
-        off = end;
+        m = max(0, min(m, budget));
+        const uint64_t mask = m >= 64 ? ~(uint64_t)0 : (((uint64_t)1 << m) - 1);
+        v &= mask;
+        const uint64_t lo = acc | (v << off);
+        const uint64_t hi = off == 0 ? 0 : (v >> (64 - off));  // bits that spill into word wi+1
+        const int end = off + m;
+        if (m > 0) lds[wi * 64] = lo;
+        const bool cross = end >= 64;
+        acc = cross ? hi : lo;
+        off = cross ? end - 64 : end;
+        wi += cross ? 1 : 0;
         budget -= m;
     }
 };
@@ -272,32 +273,42 @@ __device__ inline void encode_lane(const float (&x)[64], int rate, uint64_t* lds
 }
 
 // ---- per-lane bit reader over the wave's LDS words --------------------------
+// Keeps three words (the current one and the next two) so that the word
+// loaded when a read crosses a word boundary is needed only at the crossing
+// after that; skip and get take no divergent branches.
 struct LaneReader {
     const uint64_t* lds;  // word w of this lane at lds[w * 64]
     int rate;
-    uint64_t cur, nxt;    // words wi and wi+1 (0 past the block)
+    uint64_t cur, nxt, nx2;  // words wi, wi+1, wi+2 (0 past the block)
     int wi, off;
 
+    __device__ uint64_t word(int w) const
+    {
+        const uint64_t v = lds[min(w, rate - 1) * 64];
+        return w < rate ? v : 0;
+    }
     __device__ void init()
     {
         wi = 0; off = 0;
-        cur = lds[0];
-        nxt = rate > 1 ? lds[64] : 0;
+        cur = word(0);
+        nxt = word(1);
+        nx2 = word(2);
     }
-    __device__ uint64_t window() const { return off == 0 ? cur : (cur >> off) | (nxt << (64 - off)); }
-    __device__ void skip(int m)
+    // the next 64 bits of the stream (bits past the block read as zero)
+    __device__ uint64_t window() const { return (cur >> off) | ((nxt << 1) << (63 - off)); }
+    __device__ void skip(int m)  // m in [0, 64]
     {
         off += m;
-        while (off >= 64) {
-            off -= 64;
-            ++wi;
-            cur = nxt;
-            nxt = wi + 1 < rate ? lds[(wi + 1) * 64] : 0;
-        }
+        const bool cross = off >= 64;
+        off = cross ? off - 64 : off;
+        wi += cross ? 1 : 0;
+        const uint64_t fresh = word(wi + 2);
+        cur = cross ? nxt : cur;
+        nxt = cross ? nx2 : nxt;
+        nx2 = cross ? fresh : nx2;
     }
     __device__ uint64_t get(int m)  // m in [0, 64]
     {
-        if (m <= 0) return 0;
         uint64_t v = window();
         if (m < 64) v &= ((uint64_t)1 << m) - 1;
         skip(m);

@@ -422,6 +422,7 @@ static int64_t job_bytes(const oocs::Job& j, int64_t plane_elems)
     const int64_t pb = plane_elems * 4;
     switch (j.kind) {
     case oocs::JOB_HEAT: return planes * pb * 2;        // read u, write u'
+    case oocs::JOB_HEAT_TB: return planes * pb * 2;     // read u(t), write u(t+k): k updates per cell
     case oocs::JOB_WAVE: return planes * pb * 4;        // read p, p(n-1), w; write p(n+1)
     case oocs::JOB_DECODE:
     case oocs::JOB_ENCODE: return planes * (pb + plane_elems * j.rate / 8);
@@ -506,7 +507,10 @@ struct OpTranslator {
         } else if (o.kind == OOCS_OP_LEVEL) {
             j.src = ring(o.level - 1);
             j.dst = ring(o.level);
-            if (P.cfg.stencil == OOCS_HEAT7) {
+            if (P.cfg.stencil == OOCS_HEAT7 && o.slot > 1) {
+                j.kind = oocs::JOB_HEAT_TB;  // o.slot steps in one temporally blocked pass
+                j.rate = o.slot;
+            } else if (P.cfg.stencil == OOCS_HEAT7) {
                 j.kind = oocs::JOB_HEAT;
             } else {
                 j.kind = oocs::JOB_WAVE;

@@ -31,7 +31,8 @@ enum JobKind : int32_t {
     JOB_COPY_IN = 5, // staging (raw planes) -> ring planes
     JOB_COPY_OUT = 6,// ring planes -> staging (raw planes)
     JOB_FETCH = 7,   // host store bytes -> staging slot
-    JOB_STORE = 8    // staging slot -> host store bytes
+    JOB_STORE = 8,   // staging slot -> host store bytes
+    JOB_HEAT_TB = 9  // `rate` heat steps over planes [z0, z1) in one temporally blocked pass
 };
 
 // One job of a fused launch. For stencil jobs src = level l-1, src2 = level
@@ -58,6 +59,8 @@ constexpr int kTileY = 4;
 constexpr int kZChunk = 16;         // planes one stencil thread marches
 constexpr int kHeatTileX = 256;     // heat xy tile: 4 waves, each a 256-wide row (4 x per lane)
 constexpr int kHeatTileY = 4;
+constexpr int kTbTileY = 16;        // temporally blocked heat: 64 x 16 cell tiles (k-cell halo included)
+constexpr int kMaxTbSteps = 4;
 
 struct LaunchParams {
     int32_t nx, ny, nz;

@@ -106,6 +106,20 @@ __device__ inline void copy_job(const Job& j, int nx, int ny, int wg, bool in)
     }
 }
 
+// Temporally blocked heat job: planes [z0, z1) of the output ring, j.rate steps.
+__device__ inline void heat_tb_job(const Job& j, int nx, int ny, int nz, float alpha, int wg)
+{
+    float* lds = reinterpret_cast<float*>(dyn_lds);
+    switch (j.rate) {
+    case 1: stencil::heat_tb<kTbTileY, 1>(j.src, j.dst, nx, ny, nz, alpha, j.z0, j.z1, wg, lds); break;
+    case 2: stencil::heat_tb<kTbTileY, 2>(j.src, j.dst, nx, ny, nz, alpha, j.z0, j.z1, wg, lds); break;
+    case 3: stencil::heat_tb<kTbTileY, 3>(j.src, j.dst, nx, ny, nz, alpha, j.z0, j.z1, wg, lds); break;
+    default: stencil::heat_tb<kTbTileY, 4>(j.src, j.dst, nx, ny, nz, alpha, j.z0, j.z1, wg, lds); break;
+    }
+}
+
+static size_t heat_tb_lds(int steps) { return (size_t)steps * 2 * kTbTileY * 64 * sizeof(float); }
+
 // Host-link transfer: `bytes` (a multiple of 8) between the staging slot and
 // the host store, 16 KiB per workgroup in 8-byte words. Every thread issues
 // all its loads before its stores, so a workgroup keeps 16 KiB in flight
@@ -157,6 +171,7 @@ __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
     case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
     case JOB_FETCH:
     case JOB_STORE: xfer_job(j, local); break;
+    case JOB_HEAT_TB: heat_tb_job(j, p.nx, p.ny, p.nz, p.alpha, local); break;
     default: break;
     }
 }
@@ -180,6 +195,7 @@ __global__ void __launch_bounds__(kBlockThreads) stencil_kernel(LaunchParams p)
     case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
     case JOB_FETCH:
     case JOB_STORE: xfer_job(j, local); break;
+    case JOB_HEAT_TB: heat_tb_job(j, p.nx, p.ny, p.nz, p.alpha, local); break;
     default: break;
     }
 }
@@ -198,6 +214,10 @@ int32_t job_workgroups(const Job& j, int nx, int ny)
     case JOB_WAVE: {
         const int tiles = ((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
         return tiles * ((planes + kZChunk - 1) / kZChunk);
+    }
+    case JOB_HEAT_TB: {
+        const int ox = 64 - 2 * j.rate, oy = kTbTileY - 2 * j.rate;
+        return ((nx + ox - 1) / ox) * ((ny + oy - 1) / oy);
     }
     case JOB_DECODE:
     case JOB_ENCODE: {
@@ -241,12 +261,16 @@ static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, siz
     p.wg_begin[p.njobs] = total;
     if (total == 0) return false;
     *grid = (unsigned)total;
+    size_t tb_lds = 0;
+    for (int i = 0; i < n; ++i)
+        if (p.jobs[i].kind == JOB_HEAT_TB && heat_tb_lds(p.jobs[i].rate) > tb_lds) tb_lds = heat_tb_lds(p.jobs[i].rate);
     if (max_rate > 0) {
         *func = reinterpret_cast<const void*>(&fused_kernel);
-        *lds = (size_t)kWavesPerWG * 64 * max_rate * sizeof(uint64_t);
+        const size_t codec_lds = (size_t)kWavesPerWG * 64 * max_rate * sizeof(uint64_t);
+        *lds = codec_lds > tb_lds ? codec_lds : tb_lds;
     } else {
         *func = reinterpret_cast<const void*>(&stencil_kernel);
-        *lds = 0;
+        *lds = tb_lds;
     }
     return true;
 }
@@ -260,7 +284,7 @@ hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
     if (func == reinterpret_cast<const void*>(&fused_kernel))
         hipLaunchKernelGGL(fused_kernel, dim3(grid), dim3(kBlockThreads), lds, stream, p);
     else
-        hipLaunchKernelGGL(stencil_kernel, dim3(grid), dim3(kBlockThreads), 0, stream, p);
+        hipLaunchKernelGGL(stencil_kernel, dim3(grid), dim3(kBlockThreads), lds, stream, p);
     return hipGetLastError();
 }
 
@@ -412,11 +436,13 @@ template <int C>
 __device__ __attribute__((always_inline)) inline void heat_dense_cfg(const float* src, float* dst, int nx, int ny, int nz, float alpha, int wg,
                                       float* lds)
 {
-    if constexpr (C == 6) stencil::heat_tb<16, 2>(src, dst, nx, ny, nz, alpha, 64, wg, lds);
-    else if constexpr (C == 7) stencil::heat_tb<16, 2>(src, dst, nx, ny, nz, alpha, 128, wg, lds);
-    else if constexpr (C == 8) stencil::heat_tb<32, 2>(src, dst, nx, ny, nz, alpha, 64, wg, lds);
-    else if constexpr (C == 9) stencil::heat_tb<16, 4>(src, dst, nx, ny, nz, alpha, 64, wg, lds);
-    else {
+    if constexpr (C >= 6) {
+        constexpr int TY = C == 8 ? 32 : 16, K = C == 9 ? 4 : 2, ZC = C == 7 ? 128 : 64;
+        const Ring rs{const_cast<float*>(src), nz, (int64_t)nx * ny}, rd{dst, nz, (int64_t)nx * ny};
+        const int tiles = stencil::heat_tb_tiles<TY, K>(nx, ny);
+        const int z0 = (wg / tiles) * ZC;
+        stencil::heat_tb<TY, K>(rs, rd, nx, ny, nz, alpha, z0, min(nz, z0 + ZC), wg % tiles, lds);
+    } else {
         constexpr TileCfg t = C == 0 ? TileCfg{64, 4, 16, 1} : C == 1 ? TileCfg{64, 4, 32, 1}
                             : C == 2 ? TileCfg{64, 4, 64, 1} : C == 3 ? TileCfg{32, 8, 16, 1}
                             : C == 4 ? TileCfg{128, 2, 16, 1} : TileCfg{64, 4, 8, 1};

@@ -54,8 +54,12 @@ int Planner::init(const oocs_config& c, std::string& err)
     }
     if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
-    if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS)) { err = "unknown plan flags"; return OOCS_E_ARG; }
+    if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS | OOCS_PLAN_LEVEL_BY_LEVEL)) {
+        err = "unknown plan flags";
+        return OOCS_E_ARG;
+    }
     restart = (c.flags & OOCS_PLAN_BLOCK_RESTART) != 0;
+    fused = c.stencil == OOCS_HEAT7 && k <= kMaxFusedSteps && !restart && !(c.flags & OOCS_PLAN_LEVEL_BY_LEVEL);
     copy_engines = (c.flags & OOCS_PLAN_KERNEL_TRANSFERS) == 0;
     // kernel-driven transfers fetch one group ahead inside the launch: two slots suffice;
     // copy engines keep three groups in flight ahead of the decode
@@ -73,6 +77,7 @@ int Planner::in_ring(int f) const
 
 int Planner::out_ring(int f, int kr) const
 {
+    if (fused) return 1;                          // u(t+kr), the fused job's output ring
     if (cfg.stencil == OOCS_HEAT7) return kr;     // u(t+kr)
     return f == 0 ? kr + 1 : kr;                  // p(t+kr), p(t+kr-1)
 }
@@ -115,6 +120,7 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
             hi[lv] = restart ? std::min<int64_t>(a[pi + 1] + h - st * r, nz) : nz;
             f[lv] = lo[lv];
         }
+        if (fused) f[1] = 0;  // front of the fused output ring
         int64_t out_front = p0;
         int guard = 0;
         while (out_front < p1) {
@@ -131,8 +137,20 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
                 s.in_groups.push_back({t.dz0, t.dz1, (int64_t)s.ticks.size(), restart ? pi : block_of(t.dz0), false});
                 load_front = t.dz1;
             }
+            // fused levels: the output ring advances to where its inputs
+            // [z - kr, z + kr] were decoded by the previous tick
+            if (fused) {
+                const int64_t avail = prev[0] >= nz ? nz : prev[0] - (int64_t)r * kr;
+                const int64_t top = std::min(avail, prev[1] + G);
+                if (top > prev[1]) {
+                    LevelRange L;
+                    L.lv = 1; L.z0 = prev[1]; L.z1 = top; L.steps = kr;
+                    t.levels.push_back(L);
+                    f[1] = top;
+                }
+            }
             // advance every computed level from the previous tick's fronts
-            for (int lv = nin; lv < nl; ++lv) {
+            for (int lv = nin; lv < nl && !fused; ++lv) {
                 const int64_t below = prev[lv - 1];
                 const int64_t avail = below >= nz ? nz : below - r;
                 int64_t top = std::min(std::min(hi[lv], avail), prev[lv] + G);
@@ -142,15 +160,16 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
                     f[lv] = top;
                 }
             }
-            // encode the next finished output group (never across a block end,
-            // so that the write-back of every block completes with one group)
+            // encode the next finished output group: with block restarts never
+            // across the pass's end; with shared levels any 4-aligned run (a
+            // group may complete the write-back of a block and start the next)
             int64_t fo = nz;
             for (int fld : out_fields) {
                 const int lv = out_ring(fld, kr);
                 fo = std::min(fo, lv < nin ? prev[0] : prev[lv]);
             }
             const int ob = block_of(out_front);
-            const int64_t bend = a[ob + 1];
+            const int64_t bend = restart ? a[ob + 1] : nz;
             int64_t e = fo >= bend ? bend : out_front + (fo - out_front) / align * align;
             e = std::min(e, out_front + G);
             if (e > out_front) {
@@ -158,7 +177,15 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
                 t.ez0 = out_front;
                 t.ez1 = e;
                 t.out_block = ob;
-                t.last_out_of_block = e == bend;
+                // blocks whose last plane this group writes back
+                t.done_b0 = block_of(out_front);
+                t.done_b1 = -1;
+                for (int b = t.done_b0; b < n; ++b)
+                    if (a[b + 1] > out_front && a[b + 1] <= e) t.done_b1 = b;
+                if (t.done_b1 < 0) t.done_b0 = 0;
+                else
+                    while (a[t.done_b0 + 1] <= out_front) ++t.done_b0;
+                t.last_out_of_block = t.done_b1 >= 0;
                 s.out_groups.push_back({out_front, e, (int64_t)s.ticks.size(), ob, t.last_out_of_block});
                 out_front = e;
             }
@@ -213,7 +240,7 @@ int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
         for (int64_t ti = 0; ti < T; ++ti) {
             const Tick& t = s.ticks[ti];
             for (const LevelRange& L : t.levels) {
-                read(L.lv - 1, L.z0 - r, L.z1 + r, ti);
+                read(L.lv - 1, L.z0 - (int64_t)r * L.steps, L.z1 + (int64_t)r * L.steps, ti);
                 if (nin == 2) {
                     read(L.lv - 2, L.z0, L.z1, ti);
                     read(ro_ring(), L.z0, L.z1, ti);
@@ -349,7 +376,7 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
             }
         for (const LevelRange& L : t.levels) {
             oocs_op l = op(OOCS_OP_LEVEL, 1);
-            l.level = L.lv; l.z0 = L.z0; l.z1 = L.z1; l.block = t.block; l.tick = (int)ti;
+            l.level = L.lv; l.z0 = L.z0; l.z1 = L.z1; l.block = t.block; l.tick = (int)ti; l.slot = L.steps;
             s.ops.push_back(l);
         }
         if (osl >= 0)
@@ -375,8 +402,8 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
                 next.push_back(c);
             }
             oocs_op r3 = op(OOCS_OP_RECORD, 2); r3.event = ev_stored(osl); r3.tick = (int)ti; next.push_back(r3);
-            if (t.last_out_of_block) {
-                oocs_op r4 = op(OOCS_OP_RECORD, 2); r4.event = ev_blk_cur(t.out_block); r4.tick = (int)ti; r4.block = t.out_block;
+            for (int b = t.done_b0; b <= t.done_b1; ++b) {
+                oocs_op r4 = op(OOCS_OP_RECORD, 2); r4.event = ev_blk_cur(b); r4.tick = (int)ti; r4.block = b;
                 next.push_back(r4);
             }
         }
@@ -436,7 +463,7 @@ int Planner::emit_direct(int kr, Schedule& s, MakeOp op) const
         }
         for (const LevelRange& L : t.levels) {
             oocs_op l = op(OOCS_OP_LEVEL, 1);
-            l.level = L.lv; l.z0 = L.z0; l.z1 = L.z1; l.block = t.block; l.tick = (int)ti;
+            l.level = L.lv; l.z0 = L.z0; l.z1 = L.z1; l.block = t.block; l.tick = (int)ti; l.slot = L.steps;
             s.ops.push_back(l);
         }
         if (t.out_group >= 0) {

@@ -27,8 +27,9 @@
 namespace oocs {
 
 struct LevelRange {
-    int32_t lv;
+    int32_t lv;         // ring written (computed level, or the output ring of fused levels)
     int64_t z0, z1;
+    int32_t steps = 1;  // time steps from ring lv-1 to ring lv (fused levels: the residency length)
 };
 
 struct Tick {
@@ -38,8 +39,9 @@ struct Tick {
     std::vector<LevelRange> levels;
     int64_t out_group = -1;  // encoded this tick (all output fields), or -1
     int64_t ez0 = 0, ez1 = 0;
-    int32_t out_block = 0;   // block the encoded group belongs to
-    bool last_out_of_block = false;
+    int32_t out_block = 0;   // block the encoded group starts in
+    bool last_out_of_block = false;  // the group completes the write-back of blocks done_b0..done_b1
+    int32_t done_b0 = 0, done_b1 = -1;
 };
 
 struct GroupRec {
@@ -78,6 +80,8 @@ public:
     int k = 1;
     bool restart = false;    // every block restarts the level fronts (halo recomputed)
     bool copy_engines = true;   // transfers by hipMemcpyAsync on copy streams (else by the kernel)
+    bool fused = false;         // heat: one temporally blocked job per tick computes all k levels
+    static constexpr int kMaxFusedSteps = 4;
     int64_t slab = 0, h = 0;
     std::vector<int64_t> a;  // n+1 block bounds
 
@@ -87,7 +91,7 @@ public:
     int in_ring(int f) const;                // ring a field is decoded into
     int out_ring(int f, int kr) const;       // ring an output field is encoded from
     int ro_ring() const { return nin + k; }
-    int nrings() const { return nin + k + (has_ro ? 1 : 0); }
+    int nrings() const { return fused ? 2 : nin + k + (has_ro ? 1 : 0); }
     int64_t plane_elems() const { return nx * ny; }
     int64_t store_plane_bytes(int f) const;  // host-store bytes per plane of field f (compressed or raw)
     int64_t store_bytes(int f) const;

@@ -152,34 +152,31 @@ __device__ __attribute__((always_inline)) inline void heat_dense(const float* __
     }
 }
 
-// Heat, K steps of a dense field in one pass (temporal blocking). A 256-thread
-// workgroup owns a 64 x TY column tile whose outer K cells on each side are
-// halo (recomputed by the neighbouring tiles), and streams z over its chunk
-// [z0, z1) extended by K planes on both ends. Each thread owns TY/4 cells of
-// the tile (one column x, rows ly0 + 4c) for every plane; per cell it keeps
-// the last three planes of every intermediate level in registers (the z
-// neighbours), and publishes each new plane of levels 0..K-1 in LDS (the x /
-// y neighbours), double-buffered by plane parity, so one barrier per plane
-// suffices: level s at plane q = p - s reads level s-1 at plane q from the
-// buffer written in the previous iteration. Cells outside the grid are zero
-// at every level; tile-border cells have no neighbours and are set to zero
-// (they are outside the region a level can compute). Level K is written for
-// the tile interior and planes [z0, z1). Same per-cell operation order as
-// heat_level, so the result equals K single steps bit for bit. lds holds
-// K * 2 * TY * 64 floats.
+// Heat, K steps in one pass (temporal blocking). A 256-thread workgroup owns
+// a 64 x TY column tile whose outer K cells on each side are halo
+// (recomputed by the neighbouring tiles) and produces level K on planes
+// [z0, z1) from level 0, which it streams over [z0 - K, z1 + K). Each thread
+// owns TY/4 cells of the tile (one column x, rows ly0 + 4c) in every plane;
+// per cell it keeps the last three planes of every intermediate level in
+// registers (the z neighbours), and publishes each new plane of levels
+// 0..K-1 in LDS (the x / y neighbours), double-buffered by plane parity, so
+// one barrier per plane suffices: level s at plane q = p - s reads level s-1
+// at plane q from the buffer written in the previous iteration. Cells
+// outside the grid are zero at every level; tile-border cells have no
+// neighbours and are set to zero (they are outside the region a level can
+// compute). Level K is written for the tile interior. Same per-cell
+// operation order as heat_level, so the result equals K single steps bit
+// for bit. Planes are addressed through rings (a dense field is a ring of
+// nz planes). lds holds K * 2 * TY * 64 floats.
 template <int TY, int K>
-__device__ __attribute__((always_inline)) inline void heat_tb(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny, int nz,
-                               float alpha, int zch, int wg, float* lds)
+__device__ __attribute__((always_inline)) inline void heat_tb(const Ring& src, const Ring& dst, int nx, int ny, int nz,
+                                                              float alpha, int z0, int z1, int tile, float* lds)
 {
     constexpr int TX = 64, CPT = TY / 4, OX = TX - 2 * K, OY = TY - 2 * K;
     static_assert(TY % 4 == 0 && OY > 0, "tile too small for the depth");
-    const int tiles_x = (nx + OX - 1) / OX, tiles_y = (ny + OY - 1) / OY;
-    const int tile = wg % (tiles_x * tiles_y);
-    const int zc = wg / (tiles_x * tiles_y);
+    const int tiles_x = (nx + OX - 1) / OX;
     const int ox = (tile % tiles_x) * OX - K, oy = (tile / tiles_x) * OY - K;
     const int lx = (int)(threadIdx.x % TX), ly0 = (int)(threadIdx.x / TX);
-    const int z0 = zc * zch, z1 = min(nz, z0 + zch);
-    const int64_t plane = (int64_t)nx * ny;
     const int gx = ox + lx;
     const bool xin = gx >= 0 && gx < nx;
     const bool xedge = lx == 0 || lx == TX - 1;
@@ -203,9 +200,10 @@ __device__ __attribute__((always_inline)) inline void heat_tb(const float* __res
     for (int p = z0 - K; p < z1 + K; ++p) {
         const int b = p & 1;
         const bool pin = p >= 0 && p < nz;
+        const float* sp = pin ? ring_plane(src, p) : nullptr;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const float v = (in[c] && pin) ? src[p * plane + off[c]] : 0.0f;
+            const float v = (in[c] && pin) ? sp[off[c]] : 0.0f;
             w[0][c][0] = w[0][c][1];
             w[0][c][1] = w[0][c][2];
             w[0][c][2] = v;
@@ -235,12 +233,19 @@ __device__ __attribute__((always_inline)) inline void heat_tb(const float* __res
                     w[s][c][2] = v;
                     L(s, qb, ly, lx) = v;
                 } else if (out_xy[c] && q >= z0 && q < z1) {
-                    dst[q * plane + off[c]] = v;
+                    ring_plane(dst, q)[off[c]] = v;
                 }
             }
         }
         __syncthreads();
     }
+}
+
+// Tiles of heat_tb over an nx x ny plane.
+template <int TY, int K>
+__host__ __device__ inline int heat_tb_tiles(int nx, int ny)
+{
+    return ((nx + 64 - 2 * K - 1) / (64 - 2 * K)) * ((ny + TY - 2 * K - 1) / (TY - 2 * K));
 }
 
 // Wave, 25 points:

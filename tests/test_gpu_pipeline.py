@@ -115,6 +115,23 @@ def test_block_restart_schedule_matches_replay(graphs, ce):
     assert np.array_equal(decoded(st[1], shape, 12), wpm)
 
 
+@pytest.mark.parametrize("rate,k,steps", [(8, 4, 10), (0, 3, 8), (16, 4, 7), (0, 2, 5)])
+def test_level_by_level_matches_fused(rate, k, steps):
+    """One job per time level (a ring per level) and the temporally blocked
+    job per tick (all k levels at once) give the same bits."""
+    shape = (128, 64, 64)
+    u0 = inputs.heat_uniform(shape, seed=30 + k)
+    a_plan = api.OutOfCorePlan(shape, api.HEAT7, 4, k, [rate], 4 * MiB)
+    b_plan = api.OutOfCorePlan(shape, api.HEAT7, 4, k, [rate], 4 * MiB, level_by_level=True)
+    assert a_plan.info["nrings"] == 2 and b_plan.info["nrings"] == k + 1
+    a = store_of(a_plan, 0, u0)
+    b = store_of(b_plan, 0, u0)
+    a_plan.run([a], steps)
+    b_plan.run([b], steps)
+    assert torch.equal(a, b)
+    assert np.array_equal(decoded(a, shape, rate), O.replay_heat_f32(u0, 0.1, steps, k, rate))
+
+
 def test_repeated_runs_continue_the_state():
     """Checkpoint/resume: 8 + 5 steps equal 13 steps (k = 4 divides 8); the
     host store between calls is the whole state."""

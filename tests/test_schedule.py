@@ -107,11 +107,13 @@ def test_region_sharing_loads_each_plane_once_per_residency():
 
 
 def test_separate_write_back_pairs_remainder_and_previous_common_region():
-    """After block i the planes written back are C_{i-1} (upper half) and
-    R_i, and the lower half of C_i (Fig. 3b): the write-back of block i
-    covers [a_i, a_{i+1}) and nothing else."""
+    """With block restarts, after block i the planes written back are
+    C_{i-1} (upper half) and R_i, and the lower half of C_i (Fig. 3b): the
+    write-back of block i covers [a_i, a_{i+1}) and nothing else. (With
+    shared levels the planes leave as soon as they are final, in 4-plane
+    aligned groups; every plane once, tested above.)"""
     for ce in (False, True):
-        p = plan((512, 32, 32), HEAT7, 8, 4, [8], 1 << 30, kernel_transfers=ce)
+        p = plan((512, 32, 32), HEAT7, 8, 4, [8], 1 << 30, kernel_transfers=ce, block_restart=True)
         for o in p.schedule(4):
             if o["kind"] in (L.OP_D2H, L.OP_STORE):
                 assert 64 * o["block"] <= o["z0"] < o["z1"] <= 64 * (o["block"] + 1)
@@ -155,8 +157,8 @@ def accesses(o, g):
         R = o["level"]
         out += [(("ring", R, z % g.W[R]), False) for z in range(o["z0"], o["z1"])]
     elif K == L.OP_LEVEL:
-        lv = o["level"]
-        for z in range(max(o["z0"] - g.r, 0), min(o["z1"] + g.r, g.nz)):
+        lv, steps = o["level"], max(o["slot"], 1)
+        for z in range(max(o["z0"] - g.r * steps, 0), min(o["z1"] + g.r * steps, g.nz)):
             out.append((("ring", lv - 1, z % g.W[lv - 1]), False))
         if g.wave:
             for z in range(o["z0"], o["z1"]):
@@ -297,7 +299,7 @@ def test_level_work_with_and_without_block_restarts(shape, st, n, k, rates):
     h = r * k
     nin = 1 if st == HEAT7 else 2
     for restart in (False, True):
-        p = plan(shape, st, n, k, rates, 1 << 30, block_restart=restart)
+        p = plan(shape, st, n, k, rates, 1 << 30, block_restart=restart, level_by_level=True)
         cover = {}
         for o in p.schedule(k):
             if o["kind"] == L.OP_LEVEL:
@@ -313,6 +315,15 @@ def test_level_work_with_and_without_block_restarts(shape, st, n, k, rates):
             else:
                 want[:] = 1
             assert np.array_equal(c, want), (restart, lv)
+    if st == HEAT7:  # fused levels: one job per tick advances its planes all k steps
+        p = plan(shape, st, n, k, rates, 1 << 30)
+        assert p.info["nrings"] == 2
+        cover = np.zeros(nz, dtype=int)
+        for o in p.schedule(k):
+            if o["kind"] == L.OP_LEVEL:
+                assert o["level"] == 1 and o["slot"] == k
+                cover[o["z0"]:o["z1"]] += 1
+        assert np.all(cover == 1)
 
 
 # ---------------------------------------------------------------------------
@@ -371,6 +382,26 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
                 planes = O.codec_decode(data, (z1 - z0, ny, nx), rate) if rate else data
                 for z in range(z0, z1):
                     rings[o["level"]][z % g.W[o["level"]]] = planes[z - z0]
+            elif K == L.OP_LEVEL and o["slot"] > 1:
+                # fused heat levels: `slot` steps from ring lv-1 to ring lv over
+                # [z0, z1), intermediate levels on the shrinking z ranges
+                lv, nsteps = o["level"], o["slot"]
+                cur = {z: plane(lv - 1, z) for z in range(z0 - nsteps, z1 + nsteps)}
+                for s_ in range(1, nsteps + 1):
+                    lo_, hi_ = z0 - (nsteps - s_), z1 + (nsteps - s_)
+                    nxt = {}
+                    for z in range(lo_, hi_):
+                        if z < 0 or z >= nz:
+                            nxt[z] = np.zeros((ny, nx), np.float32)
+                            continue
+                        c = cur[z]
+                        t_ = (shift(c, -1, 1) + shift(c, 1, 1)) + (shift(c, -1, 0) + shift(c, 1, 0))
+                        t_ = t_ + (cur[z - 1] + cur[z + 1])
+                        t_ = t_ - np.float32(6.0) * c
+                        nxt[z] = c + alpha * t_
+                    cur = nxt
+                for z in range(z0, z1):
+                    rings[lv][z % g.W[lv]] = cur[z]
             elif K == L.OP_LEVEL:
                 lv = o["level"]
                 for z in range(z0, z1):
