@@ -273,20 +273,16 @@ __device__ inline void encode_lane(const float (&x)[64], int rate, uint64_t* lds
 }
 
 // ---- per-lane bit reader over the wave's LDS words --------------------------
-// Keeps three words (the current one and the next two) so that the word
-// loaded when a read crosses a word boundary is needed only at the crossing
-// after that; skip and get take no divergent branches.
+// Keeps three words (the current one and the next two): the word loaded when
+// a read crosses a word boundary is first needed at the crossing after
+// that, so its LDS latency is hidden behind the bits in between.
 struct LaneReader {
     const uint64_t* lds;  // word w of this lane at lds[w * 64]
     int rate;
     uint64_t cur, nxt, nx2;  // words wi, wi+1, wi+2 (0 past the block)
     int wi, off;
 
-    __device__ uint64_t word(int w) const
-    {
-        const uint64_t v = lds[min(w, rate - 1) * 64];
-        return w < rate ? v : 0;
-    }
+    __device__ uint64_t word(int w) const { return w < rate ? lds[w * 64] : 0; }
     __device__ void init()
     {
         wi = 0; off = 0;
@@ -299,13 +295,13 @@ struct LaneReader {
     __device__ void skip(int m)  // m in [0, 64]
     {
         off += m;
-        const bool cross = off >= 64;
-        off = cross ? off - 64 : off;
-        wi += cross ? 1 : 0;
-        const uint64_t fresh = word(wi + 2);
-        cur = cross ? nxt : cur;
-        nxt = cross ? nx2 : nxt;
-        nx2 = cross ? fresh : nx2;
+        if (off >= 64) {
+            off -= 64;
+            ++wi;
+            cur = nxt;
+            nxt = nx2;
+            nx2 = word(wi + 2);
+        }
     }
     __device__ uint64_t get(int m)  // m in [0, 64]
     {
@@ -352,19 +348,22 @@ __device__ inline void decode_lane(const uint64_t* lds, int rate, float (&x)[64]
             const int m = n < budget ? n : budget;
             X = r.get(m);
             budget -= m;
+            // One window per group test: the test bit, the run of zeros and
+            // the 1 that ends it are read together (the run is at most 62
+            // bits unless it reaches the last coefficient or the budget).
             while (n < 64 && budget > 0) {
-                const uint64_t g = r.get(1);
-                --budget;
-                if (!g) break;
                 const uint64_t win = r.window();
-                int z = win ? __builtin_ctzll(win) : 64;  // zeros before the next 1
+                --budget;
+                if (!(win & 1)) { r.skip(1); break; }  // group test 0: no more ones in this plane
+                const uint64_t rest = win >> 1;
+                int z = rest ? __builtin_ctzll(rest) : 63;  // zeros before the next 1
                 const int maxscan = 63 - n;
                 if (z > maxscan) z = maxscan;
                 if (z > budget) z = budget;
-                r.skip(z); budget -= z; n += z;
-                if (n == 63) { X |= (uint64_t)1 << 63; n = 64; break; }
-                if (budget == 0) break;
-                r.skip(1); --budget;  // the 1 that ends the run
+                budget -= z; n += z;
+                if (n == 63) { r.skip(1 + z); X |= (uint64_t)1 << 63; n = 64; break; }
+                if (budget == 0) { r.skip(1 + z); break; }
+                r.skip(2 + z); --budget;  // with the 1 that ends the run
                 X |= (uint64_t)1 << n;
                 ++n;
             }

@@ -118,7 +118,7 @@ __device__ inline void heat_tb_job(const Job& j, int nx, int ny, int nz, float a
     }
 }
 
-static size_t heat_tb_lds(int steps) { return (size_t)steps * 2 * kTbTileY * 64 * sizeof(float); }
+static size_t heat_tb_lds(int steps) { return (size_t)steps * 2 * 2 * 4 * 64 * sizeof(float); }
 
 // Host-link transfer: `bytes` (a multiple of 8) between the staging slot and
 // the host store, 16 KiB per workgroup in 8-byte words. Every thread issues
@@ -424,12 +424,12 @@ hipError_t launch_swap(float* a, float* b, int64_t n, hipStream_t stream)
 // steps per launch over z chunks of zc planes (heat_tb).
 const TileCfg kTileCfgs[kNumTileCfgs] = {{64, 4, 16, 1},  {64, 4, 32, 1},   {64, 4, 64, 1}, {32, 8, 16, 1},
                                          {128, 2, 16, 1}, {64, 4, 8, 1},    {64, 16, 64, 2}, {64, 16, 128, 2},
-                                         {64, 32, 64, 2}, {64, 16, 64, 4}};
+                                         {64, 16, 32, 2}, {64, 16, 64, 4}};
 
 size_t tile_cfg_lds(int cfg)
 {
     const TileCfg& t = kTileCfgs[cfg];
-    return t.k > 1 ? (size_t)t.k * 2 * t.ty * 64 * sizeof(float) : 0;
+    return t.k > 1 ? (size_t)t.k * 2 * 2 * 4 * 64 * sizeof(float) : 0;
 }
 
 template <int C>
@@ -437,7 +437,7 @@ __device__ __attribute__((always_inline)) inline void heat_dense_cfg(const float
                                       float* lds)
 {
     if constexpr (C >= 6) {
-        constexpr int TY = C == 8 ? 32 : 16, K = C == 9 ? 4 : 2, ZC = C == 7 ? 128 : 64;
+        constexpr int TY = 16, K = C == 9 ? 4 : 2, ZC = C == 7 ? 128 : (C == 8 ? 32 : 64);
         const Ring rs{const_cast<float*>(src), nz, (int64_t)nx * ny}, rd{dst, nz, (int64_t)nx * ny};
         const int tiles = stencil::heat_tb_tiles<TY, K>(nx, ny);
         const int z0 = (wg / tiles) * ZC;

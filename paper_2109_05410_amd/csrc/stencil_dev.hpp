@@ -155,28 +155,31 @@ __device__ __attribute__((always_inline)) inline void heat_dense(const float* __
 // Heat, K steps in one pass (temporal blocking). A 256-thread workgroup owns
 // a 64 x TY column tile whose outer K cells on each side are halo
 // (recomputed by the neighbouring tiles) and produces level K on planes
-// [z0, z1) from level 0, which it streams over [z0 - K, z1 + K). Each thread
-// owns TY/4 cells of the tile (one column x, rows ly0 + 4c) in every plane;
-// per cell it keeps the last three planes of every intermediate level in
-// registers (the z neighbours), and publishes each new plane of levels
-// 0..K-1 in LDS (the x / y neighbours), double-buffered by plane parity, so
-// one barrier per plane suffices: level s at plane q = p - s reads level s-1
-// at plane q from the buffer written in the previous iteration. Cells
+// [z0, z1) from level 0, which it streams over [z0 - K, z1 + K). Wave w owns
+// the TY/4 consecutive rows [w*TY/4, (w+1)*TY/4) of the tile, one x per lane,
+// in every plane; per cell it keeps the last three planes of every
+// intermediate level in registers (the z neighbours). A cell's y neighbours
+// are in its own registers except across a strip edge, its x neighbours come
+// from the adjacent lanes by shuffles, and only the strips' first and last
+// rows of each new plane of levels 0..K-1 go through LDS, double-buffered by
+// plane parity, so one barrier per plane suffices: level s at plane q = p - s
+// reads level s-1 at plane q as written in the previous iteration. Cells
 // outside the grid are zero at every level; tile-border cells have no
 // neighbours and are set to zero (they are outside the region a level can
-// compute). Level K is written for the tile interior. Same per-cell
-// operation order as heat_level, so the result equals K single steps bit
-// for bit. Planes are addressed through rings (a dense field is a ring of
-// nz planes). lds holds K * 2 * TY * 64 floats.
+// compute). Level K is written for the tile interior. Same per-cell operation
+// order as heat_level, so the result equals K single steps bit for bit.
+// Planes are addressed through rings (a dense field is a ring of nz
+// planes). lds holds K * 2 * 2 * 4 * 64 floats.
 template <int TY, int K>
-__device__ __attribute__((always_inline)) inline void heat_tb(const Ring& src, const Ring& dst, int nx, int ny, int nz,
-                                                              float alpha, int z0, int z1, int tile, float* lds)
+__device__ __attribute__((always_inline)) inline void heat_tb(const Ring& src, const Ring& dst, int nx, int ny,
+                                                                     int nz, float alpha, int z0, int z1, int tile,
+                                                                     float* lds)
 {
     constexpr int TX = 64, CPT = TY / 4, OX = TX - 2 * K, OY = TY - 2 * K;
-    static_assert(TY % 4 == 0 && OY > 0, "tile too small for the depth");
+    static_assert(TY % 4 == 0 && OY > 0 && CPT >= 2, "tile too small for the depth");
     const int tiles_x = (nx + OX - 1) / OX;
     const int ox = (tile % tiles_x) * OX - K, oy = (tile / tiles_x) * OY - K;
-    const int lx = (int)(threadIdx.x % TX), ly0 = (int)(threadIdx.x / TX);
+    const int lx = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
     const int gx = ox + lx;
     const bool xin = gx >= 0 && gx < nx;
     const bool xedge = lx == 0 || lx == TX - 1;
@@ -185,13 +188,14 @@ __device__ __attribute__((always_inline)) inline void heat_tb(const Ring& src, c
     int64_t off[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const int ly = ly0 + 4 * c, gy = oy + ly;
+        const int ly = wv * CPT + c, gy = oy + ly;
         in[c] = xin && gy >= 0 && gy < ny;
         ok_xy[c] = in[c] && !xedge && ly > 0 && ly < TY - 1;
         out_xy[c] = in[c] && xout && ly >= K && ly < TY - K;
         off[c] = (int64_t)gy * nx + gx;
     }
-    auto L = [&](int lev, int buf, int ly, int x) -> float& { return lds[((lev * 2 + buf) * TY + ly) * TX + x]; };
+    // edge rows of the strips: E(lev, buf, side, wave) -> 64 floats; side 0 = first row, 1 = last row
+    auto E = [&](int lev, int buf, int side, int wave) -> float* { return lds + (((lev * 2 + buf) * 2 + side) * 4 + wave) * 64; };
     float w[K][CPT][3];
 #pragma unroll
     for (int s = 0; s < K; ++s)
@@ -207,34 +211,46 @@ __device__ __attribute__((always_inline)) inline void heat_tb(const Ring& src, c
             w[0][c][0] = w[0][c][1];
             w[0][c][1] = w[0][c][2];
             w[0][c][2] = v;
-            L(0, b, ly0 + 4 * c, lx) = v;
         }
+        E(0, b, 0, wv)[lx] = w[0][0][2];
+        E(0, b, 1, wv)[lx] = w[0][CPT - 1][2];
 #pragma unroll
         for (int s = 1; s <= K; ++s) {
             const int q = p - s;
             const int qb = q & 1;
             const bool qin = q >= 0 && q < nz;
+            const float above = wv > 0 ? E(s - 1, qb, 1, wv - 1)[lx] : 0.0f;       // row w*CPT - 1
+            const float below = wv < 3 ? E(s - 1, qb, 0, wv + 1)[lx] : 0.0f;       // row (w+1)*CPT
+            float nv[CPT];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
-                const int ly = ly0 + 4 * c;
+                const float cc = w[s - 1][c][1];
+                const float xm = __shfl_up(cc, 1);
+                const float xp = __shfl_down(cc, 1);
+                const float ym = c > 0 ? w[s - 1][c - 1][1] : above;
+                const float yp = c < CPT - 1 ? w[s - 1][c + 1][1] : below;
                 float v = 0.0f;
                 if (ok_xy[c] && qin) {
-                    const float cc = w[s - 1][c][1];
-                    const float xm = L(s - 1, qb, ly, lx - 1), xp = L(s - 1, qb, ly, lx + 1);
-                    const float ym = L(s - 1, qb, ly - 1, lx), yp = L(s - 1, qb, ly + 1, lx);
                     float t = (xm + xp) + (ym + yp);
                     t = t + (w[s - 1][c][0] + w[s - 1][c][2]);
                     t = t - 6.0f * cc;
                     v = cc + alpha * t;
                 }
-                if (s < K) {
+                nv[c] = v;
+            }
+            if (s < K) {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
                     w[s][c][0] = w[s][c][1];
                     w[s][c][1] = w[s][c][2];
-                    w[s][c][2] = v;
-                    L(s, qb, ly, lx) = v;
-                } else if (out_xy[c] && q >= z0 && q < z1) {
-                    ring_plane(dst, q)[off[c]] = v;
+                    w[s][c][2] = nv[c];
                 }
+                E(s, qb, 0, wv)[lx] = nv[0];
+                E(s, qb, 1, wv)[lx] = nv[CPT - 1];
+            } else {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c)
+                    if (out_xy[c] && q >= z0 && q < z1) ring_plane(dst, q)[off[c]] = nv[c];
             }
         }
         __syncthreads();
