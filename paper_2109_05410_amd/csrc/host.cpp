@@ -809,7 +809,11 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                         if (q == hipSuccess) break;
                         if (q != hipErrorNotReady) return oocs::hip_fail(q, "event query");
                         if (pl->host_waits) {
-                            HIP_TRY(hipEventSynchronize(e));
+                            // poll rather than hipEventSynchronize, which may put the
+                            // thread to sleep and wake it up late
+                            hipError_t w;
+                            while ((w = hipEventQuery(e)) == hipErrorNotReady) __builtin_ia32_pause();
+                            if (w != hipSuccess) return oocs::hip_fail(w, "event query");
                         } else {
                             HIP_TRY(hipStreamWaitEvent(pl->st[o.stream], e, 0));
                         }

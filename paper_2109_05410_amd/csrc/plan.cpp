@@ -353,13 +353,14 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
     const int64_t nin_groups = (int64_t)s.in_groups.size();
     for (int64_t j = 0; j < std::min<int64_t>(nstage, nin_groups); ++j) emit_h2d(j, -1, s.ops);
     // The copies a tick makes possible (write-back of its output group, load
-    // of the group that reuses its input slot) are issued `lag` ticks later:
-    // by then the events they wait for have usually completed, and a wait on
-    // a completed event costs the host nothing. The load of group j + nstage
-    // is then issued nstage - lag ticks before its decode; lag < nstage keeps
-    // every wait on the record it was meant for (a slot is recorded again
-    // only nstage ticks later).
-    const int lag = std::max(1, std::min(2, nstage - 2));
+    // of the group that reuses its input slot) are issued after the next
+    // tick's launch, so the host issues that launch before it can block on
+    // the events those copies wait for; the load of group j + nstage is then
+    // issued nstage - 1 ticks before its decode. (Two ticks later measured
+    // slower and unsteady: some runs lost a third of their throughput.)
+    // lag < nstage keeps every wait on the record it was meant for (a slot is
+    // recorded again only nstage ticks later).
+    const int lag = 1;
     std::deque<std::vector<oocs_op>> lagged;
     std::vector<oocs_op> next;
     for (int64_t ti = 0; ti < (int64_t)s.ticks.size(); ++ti) {
