@@ -183,22 +183,24 @@ typedef struct {
  * chunks and the write-back order are the same. */
 #define OOCS_PLAN_BLOCK_RESTART 1
 
-/* Plan flag: how groups cross the host link (Sec. V-B).
- * Without it (default) the copies are hipMemcpyAsync calls on two copy
- * streams (one per direction) ordered against the compute stream with
- * events, as in the paper's three-stream pipeline; the copy of a tick's
- * output and the load that reuses its input slot are issued after the next
- * tick's launch, when the events they wait for have usually completed.
- * With it, the pipeline kernel moves the groups itself: each launch holds,
- * next to the decode, level and encode jobs of its tick, a FETCH job that
- * copies the next input group from the pinned host store into a device
- * staging slot and a STORE job that copies the previous tick's encoded
- * group into the host store. Everything then runs on one stream, one
- * launch per tick, and the host issues nothing else; the host stores must
- * be pinned host memory that the device can address (hipHostMalloc, or a
- * torch tensor allocated with pin_memory=True). Both give bit-identical
- * host stores. */
+/* Plan flags: how groups cross the host link (Sec. V-B).
+ * Default: the paper's three streams. Groups are loaded with hipMemcpyAsync
+ * on one copy stream and written back with hipMemcpyAsync on another, both
+ * ordered against the compute stream with events. The copies a tick makes
+ * possible (write-back of its output group, load of the group that reuses
+ * its input slot) are issued after the next tick's launch, when the events
+ * they wait for have usually completed.
+ * OOCS_PLAN_KERNEL_STORES: write-back by STORE jobs inside the pipeline
+ * kernel instead: the launch of each tick copies the previous tick's encoded
+ * group from its staging slot into the host store.
+ * OOCS_PLAN_KERNEL_TRANSFERS: loads by FETCH jobs inside the kernel as well,
+ * so everything runs on one stream, one launch per tick, and the host issues
+ * nothing else.
+ * Whenever a kernel touches the host stores they must be pinned host memory
+ * that the device can address (hipHostMalloc, or a torch tensor allocated
+ * with pin_memory=True). All modes give bit-identical host stores. */
 #define OOCS_PLAN_KERNEL_TRANSFERS 2
+#define OOCS_PLAN_KERNEL_STORES 8
 
 /* Plan flag (heat with k <= 4): by default each tick computes all k time
  * levels of its planes in one temporally blocked job (tiles with a k-cell
@@ -348,8 +350,9 @@ int oocs_plan_set_host_waits(oocs_plan* plan, int on);
  * the source cell when the field after the s-th step of this call is
  * formed (s = 0 .. steps-1); h_src holds `steps` values or is NULL. Host
  * stores are updated in place. Blocks until done; st may be NULL.
- * With OOCS_PLAN_KERNEL_TRANSFERS the kernels read and write the stores
- * directly, so each must be pinned, device-addressable host memory.
+ * With OOCS_PLAN_KERNEL_STORES or OOCS_PLAN_KERNEL_TRANSFERS kernels read or
+ * write the stores directly, so each must be pinned, device-addressable host
+ * memory.
  * Errors: OOCS_E_ARG (also: a store the device cannot address), OOCS_E_STATE
  * (planning-only plan), OOCS_E_HIP. */
 int oocs_run(oocs_plan* plan, void* const* h_store, int64_t steps, const float* h_src, oocs_stats* st);

@@ -27,6 +27,7 @@ OOCS_MAX_RATE = 34
 OOCS_PLAN_BLOCK_RESTART = 1
 OOCS_PLAN_KERNEL_TRANSFERS = 2
 OOCS_PLAN_LEVEL_BY_LEVEL = 4
+OOCS_PLAN_KERNEL_STORES = 8
 
 OP_H2D, OP_DECODE, OP_LEVEL, OP_ENCODE, OP_D2H, OP_LAUNCH, OP_RECORD, OP_WAIT, OP_FETCH, OP_STORE = range(1, 11)
 

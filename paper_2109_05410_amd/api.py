@@ -171,16 +171,17 @@ class OutOfCorePlan:
 
     block_restart: every block restarts the level fronts and recomputes its
     halo (the per-block schedule of Fig. 2) instead of sharing every level's
-    planes with its neighbour. kernel_transfers: move groups with transfer
-    jobs inside the pipeline kernel instead of hipMemcpyAsync on two copy
-    streams (the three-stream pipeline of Sec. V-B). level_by_level (heat,
+    planes with its neighbour. Transfers: hipMemcpyAsync on two copy streams
+    (the three-stream pipeline of Sec. V-B, default); kernel_stores:
+    write-back by STORE jobs in the pipeline kernel; kernel_transfers: loads
+    by FETCH jobs as well. level_by_level (heat,
     k <= 4): one job and one ring per time level instead of one temporally
     blocked job per tick. Results are identical."""
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
                  planning_only: bool = False, device=None, block_restart: bool = False,
-                 kernel_transfers: bool = False, level_by_level: bool = False):
+                 kernel_transfers: bool = False, level_by_level: bool = False, kernel_stores: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -194,7 +195,8 @@ class OutOfCorePlan:
         cfg.alpha = alpha
         cfg.flags = ((L.OOCS_PLAN_BLOCK_RESTART if block_restart else 0)
                      | (L.OOCS_PLAN_KERNEL_TRANSFERS if kernel_transfers else 0)
-                     | (L.OOCS_PLAN_LEVEL_BY_LEVEL if level_by_level else 0))
+                     | (L.OOCS_PLAN_LEVEL_BY_LEVEL if level_by_level else 0)
+                     | (L.OOCS_PLAN_KERNEL_STORES if kernel_stores else 0))
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg
@@ -289,6 +291,7 @@ class OutOfCorePlan:
         """Op-by-op issue: block the host on pending cross-stream events (True,
         default) or make the stream wait on them (False)."""
         L.check(L.lib().oocs_plan_set_host_waits(self._h, 1 if on else 0))
+
 
 
 # ---------------------------------------------------------------------------

@@ -675,7 +675,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     int64_t tbytes = 0, tlaunches = 0;  // the timed launches (profiling)
     // kernel-driven transfers address the host stores from the device
     void* d_store[OOCS_MAX_FIELDS] = {nullptr, nullptr, nullptr};
-    if (!P.copy_engines)
+    if (!P.copy_engines || P.kernel_stores)
         for (int f = 0; f < P.nfields; ++f) {
             if (!h_store[f]) continue;
             if (hipHostGetDevicePointer(&d_store[f], h_store[f], 0) != hipSuccess || !d_store[f]) {

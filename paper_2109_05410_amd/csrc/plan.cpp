@@ -54,13 +54,15 @@ int Planner::init(const oocs_config& c, std::string& err)
     }
     if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
-    if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS | OOCS_PLAN_LEVEL_BY_LEVEL)) {
+    if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS | OOCS_PLAN_LEVEL_BY_LEVEL |
+                    OOCS_PLAN_KERNEL_STORES)) {
         err = "unknown plan flags";
         return OOCS_E_ARG;
     }
     restart = (c.flags & OOCS_PLAN_BLOCK_RESTART) != 0;
     fused = c.stencil == OOCS_HEAT7 && k <= kMaxFusedSteps && !restart && !(c.flags & OOCS_PLAN_LEVEL_BY_LEVEL);
     copy_engines = (c.flags & OOCS_PLAN_KERNEL_TRANSFERS) == 0;
+    kernel_stores = copy_engines && (c.flags & OOCS_PLAN_KERNEL_STORES) != 0;
     // kernel-driven transfers fetch one group ahead inside the launch: two slots suffice;
     // copy engines keep three groups in flight ahead of the decode
     nstage = c.nstage ? c.nstage : (copy_engines ? 4 : 2);
@@ -363,12 +365,34 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
     const int lag = 1;
     std::deque<std::vector<oocs_op>> lagged;
     std::vector<oocs_op> next;
+    // with kernel stores: the STORE job of the previous tick's output group
+    // rides in this tick's launch, and the block events it completes are
+    // recorded on the compute stream after it
+    int64_t pend_store = -1;
+    auto emit_store = [&](int64_t m, int tick) {
+        const GroupRec& g = s.out_groups[m];
+        for (int fld : out_fields) {
+            oocs_op c = op(OOCS_OP_STORE, 1);
+            c.field = fld; c.slot = (int)(m % nstage); c.z0 = g.z0; c.z1 = g.z1; c.block = g.block; c.tick = tick;
+            c.level = out_ring(fld, kr);
+            s.ops.push_back(c);
+        }
+    };
+    auto record_blocks_of = [&](int64_t m, int tick) {
+        const Tick& tm = s.ticks[s.out_groups[m].tick];
+        for (int b = tm.done_b0; b <= tm.done_b1; ++b) {
+            oocs_op r4 = op(OOCS_OP_RECORD, 1); r4.event = ev_blk_cur(b); r4.tick = tick; r4.block = b;
+            s.ops.push_back(r4);
+        }
+    };
     for (int64_t ti = 0; ti < (int64_t)s.ticks.size(); ++ti) {
         const Tick& t = s.ticks[ti];
         const int isl = t.in_group >= 0 ? (int)(t.in_group % nstage) : -1;
         const int osl = t.out_group >= 0 ? (int)(t.out_group % nstage) : -1;
         if (isl >= 0) { oocs_op w = op(OOCS_OP_WAIT, 1); w.event = ev_loaded(isl); w.tick = (int)ti; s.ops.push_back(w); }
-        if (osl >= 0) { oocs_op w = op(OOCS_OP_WAIT, 1); w.event = ev_stored(osl); w.tick = (int)ti; s.ops.push_back(w); }
+        if (osl >= 0 && !kernel_stores) {
+            oocs_op w = op(OOCS_OP_WAIT, 1); w.event = ev_stored(osl); w.tick = (int)ti; s.ops.push_back(w);
+        }
         if (isl >= 0)
             for (int fld : in_fields) {
                 oocs_op d = op(OOCS_OP_DECODE, 1);
@@ -386,15 +410,22 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
                 e.field = fld; e.slot = osl; e.level = out_ring(fld, kr); e.z0 = t.ez0; e.z1 = t.ez1; e.block = t.out_block; e.tick = (int)ti;
                 s.ops.push_back(e);
             }
+        const int64_t stored_now = pend_store;
+        if (kernel_stores && pend_store >= 0) emit_store(pend_store, (int)ti);
         { oocs_op l = op(OOCS_OP_LAUNCH, 1); l.tick = (int)ti; l.block = t.block; s.ops.push_back(l); }
+        if (kernel_stores && stored_now >= 0) {
+            record_blocks_of(stored_now, (int)ti);
+            pend_store = -1;
+        }
         if (isl >= 0) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_decoded(isl); r2.tick = (int)ti; s.ops.push_back(r2); }
-        if (osl >= 0) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_encoded(osl); r2.tick = (int)ti; s.ops.push_back(r2); }
+        if (osl >= 0 && !kernel_stores) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_encoded(osl); r2.tick = (int)ti; s.ops.push_back(r2); }
+        if (kernel_stores && t.out_group >= 0) pend_store = t.out_group;
         if ((int)lagged.size() >= lag) {
             s.ops.insert(s.ops.end(), lagged.front().begin(), lagged.front().end());
             lagged.pop_front();
         }
         next.clear();
-        if (osl >= 0) {
+        if (osl >= 0 && !kernel_stores) {
             oocs_op w = op(OOCS_OP_WAIT, 2); w.event = ev_encoded(osl); w.tick = (int)ti; next.push_back(w);
             for (int fld : out_fields) {
                 oocs_op c = op(OOCS_OP_D2H, 2);
@@ -410,6 +441,12 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
         }
         if (isl >= 0 && t.in_group + nstage < nin_groups) emit_h2d(t.in_group + nstage, ti, next);
         lagged.push_back(next);
+    }
+    if (kernel_stores && pend_store >= 0) {  // epilogue launch: the last output group
+        const int tt = (int)s.ticks.size();
+        emit_store(pend_store, tt);
+        oocs_op l = op(OOCS_OP_LAUNCH, 1); l.tick = tt; l.block = s.out_groups[pend_store].block; s.ops.push_back(l);
+        record_blocks_of(pend_store, tt);
     }
     for (const auto& blk : lagged) s.ops.insert(s.ops.end(), blk.begin(), blk.end());
     (void)err;
@@ -494,7 +531,7 @@ const Schedule* Planner::schedule(int kr, std::string& err)
     if (build_ticks(kr, s, err) != OOCS_OK) return nullptr;
     if (emit_ops(kr, s, err) != OOCS_OK) return nullptr;
     for (const Tick& t : s.ticks) {
-        const size_t per_in = copy_engines ? 1 : 2, per_out = copy_engines ? 1 : 2;
+        const size_t per_in = copy_engines ? 1 : 2, per_out = (copy_engines && !kernel_stores) ? 1 : 2;
         const size_t jobs = t.levels.size() + (t.in_group >= 0 ? per_in * in_fields.size() : 0) +
                             (t.out_group >= 0 ? per_out * out_fields.size() : 0);
         if (jobs > 24) { err = "too many jobs in one tick"; return nullptr; }

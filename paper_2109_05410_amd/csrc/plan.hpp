@@ -79,7 +79,8 @@ public:
     int n = 1;         // slabs
     int k = 1;
     bool restart = false;    // every block restarts the level fronts (halo recomputed)
-    bool copy_engines = true;   // transfers by hipMemcpyAsync on copy streams (else by the kernel)
+    bool copy_engines = true;   // loads by hipMemcpyAsync on a copy stream (else by the kernel)
+    bool kernel_stores = false; // with copy_engines: write-back by STORE jobs in the launches (else by D2H copies)
     bool fused = false;         // heat: one temporally blocked job per tick computes all k levels
     static constexpr int kMaxFusedSteps = 4;
     int64_t slab = 0, h = 0;

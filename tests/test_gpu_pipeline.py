@@ -35,8 +35,14 @@ def decoded(store, shape, rate):
     return b.view(np.float32).reshape(shape).copy()
 
 
-MODES = [(False, False), (True, False), (False, True), (True, True)]
-MODE_IDS = ["copy-engines-eager", "copy-engines-graph", "kernel-xfer-eager", "kernel-xfer-graph"]
+MODES = [(g, m) for m in ("copy", "hybrid", "kernel") for g in (False, True)]
+MODE_IDS = [f"{m}-{'graph' if g else 'eager'}" for g, m in MODES]
+
+
+def xfer(mode):
+    """Plan keywords of a transfer mode: copy engines both ways (the default),
+    copy-engine loads and kernel stores (hybrid), kernel jobs both ways."""
+    return {"copy": {}, "hybrid": {"kernel_stores": True}, "kernel": {"kernel_transfers": True}}[mode]
 
 
 @pytest.mark.parametrize("graphs,ce", MODES, ids=MODE_IDS)
@@ -48,7 +54,7 @@ MODE_IDS = ["copy-engines-eager", "copy-engines-graph", "kernel-xfer-eager", "ke
 def test_heat_out_of_core_matches_replay(rate, k, steps, n, arena, graphs, ce):
     shape = (128, 64, 64)
     u0 = inputs.heat_uniform(shape, seed=rate + k)
-    plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena, kernel_transfers=ce)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena, **xfer(ce))
     plan.set_graphs(graphs)
     s = store_of(plan, 0, u0)
     plan.run([s], steps)
@@ -71,7 +77,7 @@ def test_wave_out_of_core_matches_replay(rates, k, steps, graphs, ce):
     w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
     amps = rng.standard_normal(steps).astype(np.float32)
     cell = (17, 20, 50)
-    plan = api.OutOfCorePlan(shape, api.WAVE25, 2, k, rates, 16 * MiB, src_cell=cell, kernel_transfers=ce)
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 2, k, rates, 16 * MiB, src_cell=cell, **xfer(ce))
     plan.set_graphs(graphs)
     st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
     plan.run(st, steps, src_amps=amps)
@@ -91,7 +97,7 @@ def test_block_restart_schedule_matches_replay(graphs, ce):
     schedule give the same bits."""
     shape = (128, 64, 64)
     u0 = inputs.heat_uniform(shape, seed=3)
-    plan = api.OutOfCorePlan(shape, api.HEAT7, 8, 4, [8], 2 * MiB, block_restart=True, kernel_transfers=ce)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, 8, 4, [8], 2 * MiB, block_restart=True, **xfer(ce))
     plan.set_graphs(graphs)
     s = store_of(plan, 0, u0)
     plan.run([s], 10)
@@ -104,7 +110,7 @@ def test_block_restart_schedule_matches_replay(graphs, ce):
     amps = rng.standard_normal(9).astype(np.float32)
     cell = (17, 20, 50)
     plan = api.OutOfCorePlan(shape, api.WAVE25, 2, 4, [8, 12, 8], 16 * MiB, src_cell=cell, block_restart=True,
-                             kernel_transfers=ce)
+                             **xfer(ce))
     plan.set_graphs(graphs)
     st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
     plan.run(st, 9, src_amps=amps)

@@ -21,6 +21,13 @@ from paper_2109_05410_amd.api import HEAT7, WAVE25, OutOfCorePlan
 MiB = 1 << 20
 
 
+def xfer(mode):
+    """Plan keywords of a transfer mode: copy engines both ways (the default),
+    copy-engine loads and kernel stores (hybrid), kernel jobs both ways."""
+    return {"copy": {}, "hybrid": {"kernel_stores": True}, "kernel": {"kernel_transfers": True},
+            False: {}, True: {"kernel_transfers": True}}[mode]
+
+
 def plan(shape, stencil, n, k, rates, arena, **kw):
     return OutOfCorePlan(shape, stencil, n, k, rates, arena, planning_only=True, **kw)
 
@@ -112,8 +119,8 @@ def test_separate_write_back_pairs_remainder_and_previous_common_region():
     write-back of block i covers [a_i, a_{i+1}) and nothing else. (With
     shared levels the planes leave as soon as they are final, in 4-plane
     aligned groups; every plane once, tested above.)"""
-    for ce in (False, True):
-        p = plan((512, 32, 32), HEAT7, 8, 4, [8], 1 << 30, kernel_transfers=ce, block_restart=True)
+    for ce in ("copy", "hybrid", "kernel"):
+        p = plan((512, 32, 32), HEAT7, 8, 4, [8], 1 << 30, **xfer(ce), block_restart=True)
         for o in p.schedule(4):
             if o["kind"] in (L.OP_D2H, L.OP_STORE):
                 assert 64 * o["block"] <= o["z0"] < o["z1"] <= 64 * (o["block"] + 1)
@@ -271,17 +278,17 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
     ((512, 32, 32), HEAT7, 8, 4, [8], 4 * MiB, 12),
     ((1024, 16, 16), WAVE25, 8, 12, [8, 8, 8], 64 * MiB, 36),
 ])
-@pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("restart,ce", [(r, m) for r in (False, True) for m in ("copy", "hybrid", "kernel")])
 def test_schedule_has_no_races(shape, st, n, k, rates, arena, steps, restart, ce):
     p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, block_restart=restart,
-             kernel_transfers=ce)
+             **xfer(ce))
     race_check(p, steps)
     race_check(p, steps, graph_mode=True)
 
 
-@pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("restart,ce", [(r, m) for r in (False, True) for m in ("copy", "hybrid", "kernel")])
 def test_full_size_heat_schedule_has_no_races(restart, ce):
-    p = plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB, block_restart=restart, kernel_transfers=ce)
+    p = plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB, block_restart=restart, **xfer(ce))
     race_check(p, 12)
     race_check(p, 12, graph_mode=True)
 
@@ -447,11 +454,11 @@ def from_store(s, shape, rate):
 
 @pytest.mark.parametrize("rate,k,steps,arena", [(0, 2, 9, MiB // 4), (8, 4, 11, 2 * MiB), (16, 4, 8, 2 * MiB),
                                                 (5, 8, 17, 1 * MiB)])
-@pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("restart,ce", [(r, m) for r in (False, True) for m in ("copy", "hybrid", "kernel")])
 def test_heat_schedule_computes_the_replay(rate, k, steps, arena, restart, ce):
     shape = (48, 12, 16)
     n = 4 if k < 8 else 2
-    p = plan(shape, HEAT7, n, k, [rate], arena, block_restart=restart, kernel_transfers=ce)
+    p = plan(shape, HEAT7, n, k, [rate], arena, block_restart=restart, **xfer(ce))
     u0 = np.random.default_rng(rate).random(shape, dtype=np.float32)
     store = [to_store(u0, rate)]
     # the initial store passes the field through the codec once
@@ -462,7 +469,7 @@ def test_heat_schedule_computes_the_replay(rate, k, steps, arena, restart, ce):
 
 
 @pytest.mark.parametrize("rates,k,steps", [([0, 0, 0], 3, 7), ([8, 12, 6], 3, 8), ([16, 16, 0], 1, 3), ([12, 12, 12], 4, 9)])
-@pytest.mark.parametrize("restart,ce", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("restart,ce", [(r, m) for r in (False, True) for m in ("copy", "hybrid", "kernel")])
 def test_wave_schedule_computes_the_replay(rates, k, steps, restart, ce):
     shape = (64, 12, 12)
     rng = np.random.default_rng(k)
@@ -471,7 +478,7 @@ def test_wave_schedule_computes_the_replay(rates, k, steps, restart, ce):
     w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
     amps = rng.standard_normal(steps).astype(np.float32)
     src = (5, 6, 20)
-    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src, block_restart=restart, kernel_transfers=ce)
+    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src, block_restart=restart, **xfer(ce))
     store = [to_store(p0, rates[0]), to_store(pm0, rates[1]), to_store(w, rates[2])]
     execute(p, store, steps, amps)
     got_p = from_store(store[0], shape, rates[0])
