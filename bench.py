@@ -68,10 +68,11 @@ def measured_traffic():
 PROFILE_EVERY = 4  # timing events around every 4th launch of the timed region
 
 
-def run_variant(api, torch, u0, rate, steps, warmup, graphs, kernel_transfers):
+def run_variant(api, torch, u0, rate, steps, warmup, graphs, kernel_transfers, sdma=True):
     plan = api.OutOfCorePlan(SHAPE, api.HEAT7, NSLABS, K, [rate], CAP, alpha=ALPHA,
                              kernel_transfers=kernel_transfers)
     plan.set_graphs(graphs)
+    plan.set_sdma(sdma)
     store = plan.new_store(0)
     plan.put(0, u0, store)
     for _ in range(warmup):
@@ -93,6 +94,7 @@ def run_variant(api, torch, u0, rate, steps, warmup, graphs, kernel_transfers):
     tb = sum(s.timed_bytes for s in stats)
     h2d = sum(s.h2d_bytes for s in stats)
     d2h = sum(s.d2h_bytes for s in stats)
+    sdma_copies = sum(s.sdma_copies for s in stats)
     out = {
         "rate": rate,
         "gcells_per_s": cells / dt / 1e9,
@@ -101,6 +103,7 @@ def run_variant(api, torch, u0, rate, steps, warmup, graphs, kernel_transfers):
         "arena_used_bytes": info["arena_needed"],
         "h2d_GBps": h2d / dt / 1e9,
         "d2h_GBps": d2h / dt / 1e9,
+        "d2h_engine": "sdma" if sdma_copies else ("kernel" if kernel_transfers else "hipMemcpyAsync"),
         "h2d_bytes_per_step": h2d // steps,
         "gpu_busy_frac": (kms * 1e-3) * (nl / max(tl, 1)) / dt,
         "host_enqueue_frac": sum(s.enqueue_ms for s in stats) * 1e-3 / dt,
@@ -392,6 +395,8 @@ def main():
                     help="time the pipeline variants only (no in-core rate, no link probe); for profiler runs")
     ap.add_argument("--kernel-transfers", type=int, default=0,
                     help="1: move groups with transfer jobs inside the pipeline kernel instead of copy engines")
+    ap.add_argument("--sdma", type=int, default=1,
+                    help="1: write-back copies on an SDMA engine through HSA; 0: through hipMemcpyAsync")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -413,7 +418,7 @@ def main():
     results = {}
     for r in rates:
         results[r] = run_variant(api, torch, u0, r, args.steps, args.warmup, bool(args.graphs),
-                                 bool(args.kernel_transfers))
+                                 bool(args.kernel_transfers), bool(args.sdma))
         print(f"# rate {r}: {results[r]['gcells_per_s']:.1f} GCell-updates/s, "
               f"{results[r]['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
     head = results.get(HEADLINE_RATE, results[rates[-1]])

@@ -323,6 +323,9 @@ typedef struct {
      * kernel_ms / timed_launches is the average launch duration and
      * timed_bytes / kernel_ms the achieved algorithmic bandwidth. */
     int64_t timed_launches, timed_bytes;
+    /* Device-to-host copies of this call issued on SDMA engines through the
+     * HSA runtime (oocs_plan_set_sdma); the others went through hipMemcpyAsync. */
+    int64_t sdma_copies;
 } oocs_stats;
 
 /* Per-launch kernel timing for later oocs_run calls on this plan: 0 turns it
@@ -343,6 +346,19 @@ int oocs_plan_set_graphs(oocs_plan* plan, int on);
  * made to wait with hipStreamWaitEvent (0). Waits on completed events are
  * skipped either way. Same results; (1) keeps the host's issue cost low. */
 int oocs_plan_set_host_waits(oocs_plan* plan, int on);
+
+/* Device-to-host copies of op-by-op issue with host waits (default 1): on an
+ * SDMA engine through the HSA runtime that HIP has loaded (1), or with
+ * hipMemcpyAsync (0), which some HIP runtimes carry out as a blit kernel that
+ * holds compute units beside the pipeline kernel (Sec. V-B gives the copies
+ * engines of their own). The SDMA path applies only when every written-back
+ * store is pinned host memory the runtime knows and the engine is available
+ * (oocs_plan_sdma_available); otherwise hipMemcpyAsync is used. Graph issue,
+ * stream waits and kernel-driven transfers never use it. Same results. */
+int oocs_plan_set_sdma(oocs_plan* plan, int on);
+
+/* 1 if the plan found the HSA runtime and the GPU agent of its arena, else 0. */
+int oocs_plan_sdma_available(const oocs_plan* plan);
 
 /* Advance the out-of-core state held in the host stores h_store[field]
  * (one pointer per used field slot) by `steps` time steps, k per residency

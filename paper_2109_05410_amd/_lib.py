@@ -92,7 +92,7 @@ class Stats(C.Structure):
         ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("cell_updates", C.c_int64),
         ("launches", C.c_int64), ("codec_bytes", C.c_int64), ("stencil_bytes", C.c_int64),
         ("kernel_ms", C.c_double), ("xfer_bytes", C.c_int64),
-        ("timed_launches", C.c_int64), ("timed_bytes", C.c_int64),
+        ("timed_launches", C.c_int64), ("timed_bytes", C.c_int64), ("sdma_copies", C.c_int64),
     ]
 
 
@@ -122,6 +122,8 @@ _SIGS = {
     "oocs_plan_set_profiling": (C.c_int, [_P, C.c_int]),
     "oocs_plan_set_graphs": (C.c_int, [_P, C.c_int]),
     "oocs_plan_set_host_waits": (C.c_int, [_P, C.c_int]),
+    "oocs_plan_set_sdma": (C.c_int, [_P, C.c_int]),
+    "oocs_plan_sdma_available": (C.c_int, [_P]),
     "oocs_batch_table_bytes": (C.c_size_t, [C.c_int]),
     "oocs_batch_create": (C.c_int, [C.POINTER(Domain), C.c_int, C.c_float, _P, C.c_size_t, C.c_char_p, C.c_int,
                                     C.c_int, _P, C.POINTER(_P)]),

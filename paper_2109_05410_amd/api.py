@@ -156,6 +156,7 @@ class RunStats:
     xfer_bytes: int
     timed_launches: int
     timed_bytes: int
+    sdma_copies: int
 
     @property
     def gcells_per_s(self) -> float:
@@ -291,6 +292,15 @@ class OutOfCorePlan:
         """Op-by-op issue: block the host on pending cross-stream events (True,
         default) or make the stream wait on them (False)."""
         L.check(L.lib().oocs_plan_set_host_waits(self._h, 1 if on else 0))
+
+    def set_sdma(self, on: bool):
+        """Device-to-host copies on an SDMA engine through the HSA runtime
+        (True, default, where available) or with hipMemcpyAsync (False)."""
+        L.check(L.lib().oocs_plan_set_sdma(self._h, 1 if on else 0))
+
+    @property
+    def sdma_available(self) -> bool:
+        return bool(L.lib().oocs_plan_sdma_available(self._h))
 
 
 

@@ -36,6 +36,7 @@ SOURCES = {
     "host.cpp": False,     # host only (HIP runtime API)
     "adjoint.cpp": False,  # host only (HIP runtime API)
     "batch.cpp": False,    # host only (HIP runtime API)
+    "sdma.cpp": False,     # host only (HSA runtime, looked up in-process)
 }
 
 

@@ -22,6 +22,7 @@
 #include "internal.hpp"
 #include "oocs.h"
 #include "plan.hpp"
+#include "sdma.hpp"
 
 #include "abi_util.hpp"
 
@@ -68,6 +69,10 @@ struct oocs_plan {
     int profiling = 0;  // 0: off; N: time every N-th launch
     bool host_waits = true;  // eager issue: wait on the host for pending cross-stream events
     bool graphs = false;
+    // device-to-host copies on SDMA engines (op-by-op issue with host waits)
+    oocs::SdmaCopier sdma;
+    bool sdma_on = true;
+    std::vector<int64_t> ev_ticket;  // per event: SDMA ticket if last recorded on the D2H stream, else -1
     std::vector<hipEvent_t> tev;  // eager timing events, two per launch, grown on demand
     // graphs by (residency length, store pointers, source on)
     std::map<std::tuple<int, const void*, const void*, const void*, bool, bool>, ResidencyGraph> gcache;
@@ -248,6 +253,9 @@ int oocs_plan_create(const oocs_config* cfg, void* d_arena, size_t arena_bytes, 
             hipError_t e = hipEventCreateWithFlags(&pl->ev[i], hipEventDisableTiming);
             if (e != hipSuccess) { oocs_plan_destroy(pl); return hip_fail(e, "hipEventCreateWithFlags"); }
         }
+        pl->ev_ticket.assign(nev, -1);
+        std::string why;
+        (void)pl->sdma.init(d_arena, &why);  // unavailable: device-to-host copies stay on hipMemcpyAsync
         pl->runnable = true;
     }
     *out = pl;
@@ -258,6 +266,7 @@ int oocs_plan_destroy(oocs_plan* pl)
 {
     if (!pl) return OOCS_OK;
     if (pl->runnable) {
+        (void)pl->sdma.drain();
         for (hipStream_t s : pl->st)
             if (s) (void)hipStreamSynchronize(s);
     }
@@ -446,6 +455,19 @@ int oocs_plan_set_host_waits(oocs_plan* pl, int on)
     if (!pl->runnable) return fail(OOCS_E_STATE, "planning-only plan");
     pl->host_waits = on != 0;
     return OOCS_OK;
+}
+
+int oocs_plan_set_sdma(oocs_plan* pl, int on)
+{
+    if (!pl) return fail(OOCS_E_ARG, "null pointer");
+    if (!pl->runnable) return fail(OOCS_E_STATE, "planning-only plan");
+    pl->sdma_on = on != 0;
+    return OOCS_OK;
+}
+
+int oocs_plan_sdma_available(const oocs_plan* pl)
+{
+    return pl && pl->runnable && pl->sdma.ready() ? 1 : 0;
 }
 
 }  // extern "C"
@@ -687,6 +709,20 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     double kms = 0.0;
     size_t tused = 0;
     const int ns = P.nstage;
+    // Device-to-host copies go to an SDMA engine when the host honours the
+    // cross-stream waits itself (op-by-op issue with host waits): a wait on
+    // the write-back stream then becomes a wait for the copies issued before
+    // its record. Every store written back must be pinned memory of a CPU pool.
+    {
+        const int rc = pl->sdma.drain();  // copies left by a run that failed part-way
+        if (rc != OOCS_OK) return rc;
+    }
+    uint64_t cpu_agent[OOCS_MAX_FIELDS] = {0, 0, 0};
+    bool use_sdma = pl->sdma_on && pl->sdma.ready() && !pl->graphs && pl->host_waits && P.copy_engines && !P.kernel_stores;
+    for (int f : P.out_fields)
+        if (use_sdma && !pl->sdma.host_agent(h_store[f], &cpu_agent[f])) use_sdma = false;
+    std::fill(pl->ev_ticket.begin(), pl->ev_ticket.end(), (int64_t)-1);
+    int64_t sdma_copies = 0;
 
     int64_t done = 0;
     while (done < steps) {
@@ -737,13 +773,13 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                 }
             } else {
                 const int parity = (int)(rounds & 1);
-                auto phys = [&](int e) -> hipEvent_t {
-                    if (e < 4 * ns) return pl->ev[e];
+                auto phys = [&](int e) -> int {  // index into pl->ev
+                    if (e < 4 * ns) return e;
                     int i = e - 4 * ns;
                     const bool prev = i >= P.n;
                     if (prev) i -= P.n;
                     const int par = prev ? 1 - parity : parity;
-                    return pl->ev[4 * ns + par * P.n + i];
+                    return 4 * ns + par * P.n + i;
                 };
                 OpTranslator tr(pl, h_store, d_store, src_on);
                 for (const oocs_op& o : sch->ops) {
@@ -756,6 +792,11 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                         if (o.kind == OOCS_OP_H2D) {
                             HIP_TRY(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, pl->st[0]));
                             h2d += (int64_t)bytes;
+                        } else if (use_sdma) {
+                            const int rc = pl->sdma.copy(host, cpu_agent[o.field], dev, bytes);
+                            if (rc != OOCS_OK) return rc;
+                            d2h += (int64_t)bytes;
+                            ++sdma_copies;
                         } else {
                             HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, pl->st[2]));
                             d2h += (int64_t)bytes;
@@ -794,9 +835,16 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                         }
                         tr.lp.njobs = 0;
                         break;
-                    case OOCS_OP_RECORD:
-                        HIP_TRY(hipEventRecord(phys(o.event), pl->st[o.stream]));
+                    case OOCS_OP_RECORD: {
+                        const int i = phys(o.event);
+                        if (use_sdma && o.stream == 2) {
+                            pl->ev_ticket[i] = pl->sdma.issued();
+                        } else {
+                            pl->ev_ticket[i] = -1;
+                            HIP_TRY(hipEventRecord(pl->ev[i], pl->st[o.stream]));
+                        }
                         break;
+                    }
                     case OOCS_OP_WAIT: {
                         if (o.event >= P.ev_blk_prev(0) && chunk_round == 0 && rounds == 0) break;
                         // The host waits for the event itself instead of making the stream
@@ -804,7 +852,13 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                         // the host ~10 us and makes the next copy call on that stream
                         // several times dearer, while the GPU is still two ticks behind
                         // by the time a lagged copy is issued. A completed event is free.
-                        const hipEvent_t e = phys(o.event);
+                        const int ei = phys(o.event);
+                        if (pl->ev_ticket[ei] >= 0) {  // recorded behind SDMA copies
+                            const int rc = pl->sdma.wait(pl->ev_ticket[ei]);
+                            if (rc != OOCS_OK) return rc;
+                            break;
+                        }
+                        const hipEvent_t e = pl->ev[ei];
                         const hipError_t q = hipEventQuery(e);
                         if (q == hipSuccess) break;
                         if (q != hipErrorNotReady) return oocs::hip_fail(q, "event query");
@@ -834,6 +888,10 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     }
     const double enq = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     for (int i = 0; i < 3; ++i) HIP_TRY(hipStreamSynchronize(pl->st[i]));
+    {
+        const int rc = pl->sdma.drain();
+        if (rc != OOCS_OK) return rc;
+    }
     const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     for (size_t i = 0; i + 1 < tused; i += 2) {
         float ms = 0.0f;
@@ -853,6 +911,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
         st->xfer_bytes = kbytes[2];
         st->timed_launches = tlaunches;
         st->timed_bytes = tbytes;
+        st->sdma_copies = sdma_copies;
         st->kernel_ms = kms;
     }
     return OOCS_OK;

@@ -1,0 +1,163 @@
+// sdma.cpp -- SdmaCopier: HSA asynchronous copies from device to host memory.
+//
+// The HSA entry points are looked up in the runtime instance that is already
+// loaded (the one HIP itself drives), never in a second copy: device
+// pointers, agents and signals belong to that instance.
+#include "sdma.hpp"
+
+#include <dlfcn.h>
+
+#include <chrono>
+
+#include <hsa/hsa.h>
+#include <hsa/hsa_ext_amd.h>
+
+#include "oocs.h"
+
+namespace oocs {
+int fail(int code, const std::string& msg);
+}
+
+namespace {
+
+struct HsaApi {
+    decltype(&hsa_agent_get_info) agent_get_info = nullptr;
+    decltype(&hsa_signal_create) signal_create = nullptr;
+    decltype(&hsa_signal_destroy) signal_destroy = nullptr;
+    decltype(&hsa_signal_load_scacquire) signal_load = nullptr;
+    decltype(&hsa_signal_store_relaxed) signal_store = nullptr;
+    decltype(&hsa_amd_memory_async_copy) async_copy = nullptr;
+    decltype(&hsa_amd_pointer_info) pointer_info = nullptr;
+    bool ok = false;
+};
+
+const HsaApi& api()
+{
+    static const HsaApi a = [] {
+        HsaApi r;
+        // RTLD_NOLOAD: only the instance that is loaded already
+        void* h = dlopen("libhsa-runtime64.so.1", RTLD_NOW | RTLD_NOLOAD);
+        if (!h) return r;
+        r.agent_get_info = reinterpret_cast<decltype(r.agent_get_info)>(dlsym(h, "hsa_agent_get_info"));
+        r.signal_create = reinterpret_cast<decltype(r.signal_create)>(dlsym(h, "hsa_signal_create"));
+        r.signal_destroy = reinterpret_cast<decltype(r.signal_destroy)>(dlsym(h, "hsa_signal_destroy"));
+        r.signal_load = reinterpret_cast<decltype(r.signal_load)>(dlsym(h, "hsa_signal_load_scacquire"));
+        r.signal_store = reinterpret_cast<decltype(r.signal_store)>(dlsym(h, "hsa_signal_store_relaxed"));
+        r.async_copy = reinterpret_cast<decltype(r.async_copy)>(dlsym(h, "hsa_amd_memory_async_copy"));
+        r.pointer_info = reinterpret_cast<decltype(r.pointer_info)>(dlsym(h, "hsa_amd_pointer_info"));
+        r.ok = r.agent_get_info && r.signal_create && r.signal_destroy && r.signal_load && r.signal_store &&
+               r.async_copy && r.pointer_info;
+        return r;
+    }();
+    return a;
+}
+
+// Owner agent of an allocation known to the runtime, and its device type.
+bool owner_of(const void* p, hsa_agent_t* agent, hsa_device_type_t* type)
+{
+    const HsaApi& a = api();
+    hsa_amd_pointer_info_t info{};
+    info.size = sizeof info;
+    if (a.pointer_info(p, &info, nullptr, nullptr, nullptr) != HSA_STATUS_SUCCESS) return false;
+    if (info.type != HSA_EXT_POINTER_TYPE_HSA || info.agentOwner.handle == 0) return false;
+    if (a.agent_get_info(info.agentOwner, HSA_AGENT_INFO_DEVICE, type) != HSA_STATUS_SUCCESS) return false;
+    *agent = info.agentOwner;
+    return true;
+}
+
+}  // namespace
+
+namespace oocs {
+
+SdmaCopier::~SdmaCopier()
+{
+    if (!ready_) return;
+    (void)drain();
+    for (uint64_t s : sig_) api().signal_destroy(hsa_signal_t{s});
+}
+
+bool SdmaCopier::init(const void* dev, std::string* why)
+{
+    const HsaApi& a = api();
+    if (!a.ok) {
+        *why = "HSA runtime entry points not found in the process";
+        return false;
+    }
+    hsa_agent_t g;
+    hsa_device_type_t t;
+    if (!owner_of(dev, &g, &t) || t != HSA_DEVICE_TYPE_GPU) {
+        *why = "device allocation has no GPU owner agent";
+        return false;
+    }
+    for (int i = 0; i < kRing; ++i) {
+        hsa_signal_t s;
+        if (a.signal_create(0, 0, nullptr, &s) != HSA_STATUS_SUCCESS) {
+            for (uint64_t h : sig_) a.signal_destroy(hsa_signal_t{h});
+            sig_.clear();
+            *why = "hsa_signal_create failed";
+            return false;
+        }
+        sig_.push_back(s.handle);
+    }
+    gpu_ = g.handle;
+    ready_ = true;
+    return true;
+}
+
+bool SdmaCopier::host_agent(const void* host, uint64_t* agent) const
+{
+    if (!ready_) return false;
+    hsa_agent_t c;
+    hsa_device_type_t t;
+    if (!owner_of(host, &c, &t) || t != HSA_DEVICE_TYPE_CPU) return false;
+    *agent = c.handle;
+    return true;
+}
+
+int SdmaCopier::advance()
+{
+    const HsaApi& a = api();
+    while (done_ < issued_) {
+        const hsa_signal_value_t v = a.signal_load(hsa_signal_t{sig_[done_ % kRing]});
+        if (v > 0) break;
+        if (v < 0) return fail(OOCS_E_HIP, "SDMA device-to-host copy reported an error");
+        ++done_;
+    }
+    return OOCS_OK;
+}
+
+int SdmaCopier::wait(int64_t t)
+{
+    if (t > issued_) t = issued_;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 0;; ++spin) {
+        const int rc = advance();
+        if (rc != OOCS_OK) return rc;
+        if (done_ >= t) return OOCS_OK;
+        __builtin_ia32_pause();
+        if ((spin & 4095u) == 4095u &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
+            return fail(OOCS_E_HIP, "SDMA device-to-host copy did not complete within a minute");
+    }
+}
+
+int SdmaCopier::copy(void* dst, uint64_t agent, const void* src, size_t bytes)
+{
+    if (!ready_) return fail(OOCS_E_STATE, "SDMA copier not initialised");
+    if (issued_ - done_ >= kRing) {
+        const int rc = wait(issued_ - kRing + 1);
+        if (rc != OOCS_OK) return rc;
+    }
+    const HsaApi& a = api();
+    const hsa_signal_t s{sig_[issued_ % kRing]};
+    a.signal_store(s, 1);
+    const hsa_status_t st = a.async_copy(dst, hsa_agent_t{agent}, src, hsa_agent_t{gpu_}, bytes, 0, nullptr, s);
+    if (st != HSA_STATUS_SUCCESS) {
+        a.signal_store(s, 0);
+        return fail(OOCS_E_HIP, "hsa_amd_memory_async_copy failed (status " + std::to_string((int)st) + ")");
+    }
+    ++issued_;
+    return OOCS_OK;
+}
+
+}  // namespace oocs
