@@ -65,7 +65,7 @@ def measured_traffic():
     return c.get("hbm_bytes_per_launch")
 
 
-PROFILE_EVERY = 4  # timing events around every 4th launch of the timed region
+PROFILE_EVERY = 3  # time every 3rd launch: coprime with the 28 launches of a 512^3 residency
 
 
 def run_variant(api, torch, u0, rate, steps, warmup, graphs, kernel_transfers, sdma=True):

@@ -95,8 +95,8 @@ void write_cache(const char* path, const std::map<std::string, int>& m)
 int time_cfg(const oocs_domain& d, float alpha, int cfg, hipStream_t s, float* ms_out)
 {
     hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));  // timing only
+    HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
     std::vector<float> t;
     int rc = OOCS_OK;
     for (int r = 0; r < 4 && rc == OOCS_OK; ++r) {

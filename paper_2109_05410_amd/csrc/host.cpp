@@ -623,9 +623,9 @@ int build_graph(oocs_plan* pl, int kr, void* const* h_store, void* const* d_stor
             std::vector<hipGraphNode_t> d = deps_of(1);
             if (timed) {
                 hipEvent_t e0, e1;
-                HIP_TRY(hipEventCreate(&e0));
+                HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));  // timing only
                 out.timing.push_back(e0);
-                HIP_TRY(hipEventCreate(&e1));
+                HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
                 out.timing.push_back(e1);
                 hipGraphNode_t n0;
                 HIP_TRY(hipGraphAddEventRecordNode(&n0, g, d.data(), d.size(), e0));
@@ -821,7 +821,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                                 ++tlaunches;
                                 while (pl->tev.size() < tused + 2) {
                                     hipEvent_t e;
-                                    HIP_TRY(hipEventCreate(&e));
+                                    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));  // timing only
                                     pl->tev.push_back(e);
                                 }
                                 HIP_TRY(hipEventRecord(pl->tev[tused], pl->st[1]));
