@@ -360,6 +360,20 @@ int oocs_plan_set_sdma(oocs_plan* plan, int on);
 /* 1 if the plan found the HSA runtime and the GPU agent of its arena, else 0. */
 int oocs_plan_sdma_available(const oocs_plan* plan);
 
+/* Host-link probe, the link roofline of the pipeline's transfers (Sec. V-B:
+ * copies in both directions overlap). Moves `bytes` from pinned host h_in to
+ * device d_a and from device d_b to pinned host h_out in chunks of `chunk`
+ * bytes, with the engines the pipeline uses: hipMemcpyAsync on one stream
+ * host to device; device to host on an SDMA engine through HSA if `sdma` and
+ * available, else hipMemcpyAsync on a second stream. Each direction alone,
+ * then both at once; one untimed pass, then `reps` timed ones (host wall
+ * clock). out[4]: GB/s host to device alone, device to host alone, each way
+ * with both at once, and 1.0 if the SDMA path was used (else 0.0). All four
+ * buffers hold `bytes` bytes and stay the caller's. Blocking.
+ * Errors: OOCS_E_ARG, OOCS_E_HIP. */
+int oocs_link_probe(void* d_a, void* d_b, void* h_in, void* h_out, size_t bytes, size_t chunk, int reps, int sdma,
+                    double* out);
+
 /* Advance the out-of-core state held in the host stores h_store[field]
  * (one pointer per used field slot) by `steps` time steps, k per residency
  * (the last residency does steps mod k). The wave source adds h_src[s] at

@@ -124,6 +124,8 @@ _SIGS = {
     "oocs_plan_set_host_waits": (C.c_int, [_P, C.c_int]),
     "oocs_plan_set_sdma": (C.c_int, [_P, C.c_int]),
     "oocs_plan_sdma_available": (C.c_int, [_P]),
+    "oocs_link_probe": (C.c_int, [_P, _P, _P, _P, C.c_size_t, C.c_size_t, C.c_int, C.c_int,
+                                  C.POINTER(C.c_double)]),
     "oocs_batch_table_bytes": (C.c_size_t, [C.c_int]),
     "oocs_batch_create": (C.c_int, [C.POINTER(Domain), C.c_int, C.c_float, _P, C.c_size_t, C.c_char_p, C.c_int,
                                     C.c_int, _P, C.POINTER(_P)]),

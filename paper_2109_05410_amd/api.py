@@ -141,6 +141,21 @@ HEAT7 = L.OOCS_HEAT7
 WAVE25 = L.OOCS_WAVE25
 
 
+def link_probe(nbytes: int = 256 << 20, chunk: int = 4 << 20, reps: int = 3, sdma: bool = True) -> dict:
+    """Host-link bandwidth with pinned buffers, moved with the pipeline's
+    engines (host to device by hipMemcpyAsync, device to host on an SDMA
+    engine where available): each direction alone and both at once, GB/s."""
+    h_in = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    h_out = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    d_a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    d_b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = (C.c_double * 4)()
+    L.check(L.lib().oocs_link_probe(d_a.data_ptr(), d_b.data_ptr(), h_in.data_ptr(), h_out.data_ptr(), nbytes, chunk,
+                                    reps, 1 if sdma else 0, out))
+    return {"h2d_GBps": out[0], "d2h_GBps": out[1], "bidir_GBps_each": out[2],
+            "d2h_engine": "sdma" if out[3] else "hipMemcpyAsync", "bytes": nbytes, "chunk_bytes": chunk}
+
+
 @dataclass
 class RunStats:
     wall_ms: float

@@ -470,6 +470,66 @@ int oocs_plan_sdma_available(const oocs_plan* pl)
     return pl && pl->runnable && pl->sdma.ready() ? 1 : 0;
 }
 
+int oocs_link_probe(void* d_a, void* d_b, void* h_in, void* h_out, size_t bytes, size_t chunk, int reps, int sdma,
+                    double* out)
+{
+    if (!d_a || !d_b || !h_in || !h_out || !out || bytes == 0 || chunk == 0 || reps < 1)
+        return fail(OOCS_E_ARG, "bad argument");
+    const size_t n = (bytes + chunk - 1) / chunk;
+    oocs::SdmaCopier cp;
+    std::string why;
+    uint64_t agent = 0;
+    const bool use_sdma = sdma && cp.init(d_b, &why) && cp.host_agent(h_out, &agent);
+    struct Streams {
+        hipStream_t s[2] = {nullptr, nullptr};
+        ~Streams()
+        {
+            for (hipStream_t x : s)
+                if (x) { (void)hipStreamSynchronize(x); (void)hipStreamDestroy(x); }
+        }
+    } st;
+    for (hipStream_t& x : st.s) HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    auto issue = [&](int dirs) -> int {  // bit 0: host to device, bit 1: device to host
+        for (size_t i = 0; i < n; ++i) {
+            const size_t off = i * chunk, len = std::min(chunk, bytes - off);
+            if (dirs & 1)
+                HIP_TRY(hipMemcpyAsync(static_cast<char*>(d_a) + off, static_cast<const char*>(h_in) + off, len,
+                                       hipMemcpyHostToDevice, st.s[0]));
+            if (dirs & 2) {
+                if (use_sdma) {
+                    const int rc = cp.copy(static_cast<char*>(h_out) + off, agent, static_cast<const char*>(d_b) + off, len);
+                    if (rc != OOCS_OK) return rc;
+                } else {
+                    HIP_TRY(hipMemcpyAsync(static_cast<char*>(h_out) + off, static_cast<const char*>(d_b) + off, len,
+                                           hipMemcpyDeviceToHost, st.s[1]));
+                }
+            }
+        }
+        return OOCS_OK;
+    };
+    auto finish = [&]() -> int {
+        for (hipStream_t x : st.s) HIP_TRY(hipStreamSynchronize(x));
+        return cp.ready() ? cp.drain() : OOCS_OK;
+    };
+    double sec[3] = {0.0, 0.0, 0.0};
+    for (int m = 0; m < 3; ++m) {
+        const int dirs = m + 1;
+        int rc = issue(dirs);  // warm-up
+        if (rc == OOCS_OK) rc = finish();
+        if (rc != OOCS_OK) return rc;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int r = 0; r < reps && rc == OOCS_OK; ++r) rc = issue(dirs);
+        if (rc == OOCS_OK) rc = finish();
+        if (rc != OOCS_OK) return rc;
+        sec[m] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / reps;
+    }
+    out[0] = (double)bytes / sec[0] / 1e9;
+    out[1] = (double)bytes / sec[1] / 1e9;
+    out[2] = (double)bytes / sec[2] / 1e9;
+    out[3] = use_sdma ? 1.0 : 0.0;
+    return OOCS_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -227,6 +227,15 @@ def test_sdma_writeback_matches_hip_copies(stencil):
         assert np.array_equal(decoded(outs["sdma"][0], shape, 8), O.replay_heat_f32(fields[0], 0.1, steps, k, 8))
 
 
+def test_link_probe_reports_both_engines():
+    """The host-link probe runs on the pipeline's engines (SDMA write-back)
+    and on hipMemcpyAsync alone, and reports positive rates for each."""
+    for sdma in (True, False):
+        r = api.link_probe(32 << 20, 4 << 20, reps=1, sdma=sdma)
+        assert r["d2h_engine"] == ("sdma" if sdma else "hipMemcpyAsync")
+        assert min(r["h2d_GBps"], r["d2h_GBps"], r["bidir_GBps_each"]) > 1.0
+
+
 def test_wave_source_longer_than_the_source_table():
     """Runs longer than the device amplitude table are split into chunks of
     whole residencies; the source timing stays exact."""
