@@ -37,6 +37,9 @@ ALPHA = 0.1
 HEADLINE_RATE = 8
 VARIANTS = (0, 16, 8)
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 64 lanes x 2.4 GHz (one wave64 VALU instruction
+# per CU per clock, packed FP32 not used)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 METRIC = "end-to-end GCell-updates/s, compressed vs uncompressed out-of-core; HBM GB/s %"
 COUNTERS = os.path.join(ROOT, "profiles", "heat512_rate8_counters.json")
 KERNEL_SOURCES = ("paper_2109_05410_amd/csrc/kernels.hip", "paper_2109_05410_amd/csrc/codec_dev.hpp",
@@ -51,10 +54,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of each kernel ({kernel name: bytes}) from
-    committed rocprofv3 counter runs, if they were taken on the current
-    kernel source; else None."""
+def measured_counters(key):
+    """Per-launch figures of each kernel ({kernel name: value}) from committed
+    rocprofv3 counter runs, if they were taken on the current kernel source;
+    else None. key: "hbm_bytes_per_launch" (FETCH_SIZE + WRITE_SIZE,
+    calibrated) or "alu_ops_per_launch" (SQ_INSTS_VALU x 64 lanes)."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -62,7 +66,7 @@ def measured_traffic():
         return None
     if c.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return c.get("hbm_bytes_per_launch")
+    return c.get(key)
 
 
 PROFILE_EVERY = 3  # time every 3rd launch: coprime with the 28 launches of a 512^3 residency
@@ -400,7 +404,8 @@ def main():
         print(f"# wave 1024^3: {extras['wave_1024']}", file=sys.stderr, flush=True)
         extras["adjoint_512"] = adjoint_rate(api, torch, inputs)
         print(f"# adjoint: {extras['adjoint_512']}", file=sys.stderr, flush=True)
-    traffic = measured_traffic()
+    traffic = measured_counters("hbm_bytes_per_launch")
+    alu_ops = measured_counters("alu_ops_per_launch")
     kname, kstat = "fused_kernel", head["kernel"]
     achieved = kstat["achieved_GBps"]
     line = {
@@ -442,6 +447,21 @@ def main():
             "bytes_per_launch": round(kstat["bytes_per_launch"]),
             "avg_launch_us": round(kstat["avg_launch_us"], 2),
         },
+    }
+    # the same launches against the VALU issue peak: issued VALU lane operations
+    # per launch (counter run on the same kernel source) over the live average
+    # launch duration; the codec's bit-plane coding makes the kernel issue-heavy
+    ops = alu_ops.get(kname) if isinstance(alu_ops, dict) else None
+    alu_achieved = ops / (kstat["avg_launch_us"] * 1e-6) / 1e12 if ops and kstat["avg_launch_us"] else None
+    line["alu_roofline"] = {
+        "bound": "alu",
+        "kernel": kname,
+        "achieved": round(alu_achieved, 2) if alu_achieved else None,
+        "peak": round(VALU_PEAK_TOPS, 2),
+        "unit": "T VALU lane-ops/s",
+        "frac": round(alu_achieved / VALU_PEAK_TOPS, 4) if alu_achieved else None,
+        "ops_per_launch": ops,
+        "ops_source": "SQ_INSTS_VALU x 64 from profiles/heat512_rate8_counters.json (issued, not algorithmic)",
     }
     # the transfers against the host link: both directions run at once, so the
     # peak is the measured bidirectional rate per direction
