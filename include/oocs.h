@@ -469,7 +469,9 @@ typedef struct {
 
 /* Device workspace bytes the two calls below need (one caller allocation,
  * passed as d_work): w, ckpt_every + 2 state fields, three multiplier
- * fields, the w-gradient field and the checkpoint codec staging. */
+ * fields, two fields of w . multiplier, the w-gradient field and the
+ * checkpoint codec staging. The calls copy checkpoints on a second stream
+ * of their own, overlapped with the steps. */
 size_t oocs_adjoint_workspace_bytes(const oocs_adjoint_cfg* cfg);
 
 /* Host checkpoint store bytes (pinned memory recommended). */

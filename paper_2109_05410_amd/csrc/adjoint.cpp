@@ -17,7 +17,7 @@ using oocs::fail;
 struct Layout {
     int64_t n = 0, fb = 0, cb = 0;  // cells, field bytes, compressed field bytes (0 if raw)
     int64_t nseg = 0, C = 0;
-    int64_t w = 0, states = 0, lam = 0, gw = 0, stage = 0, total = 0;
+    int64_t w = 0, states = 0, lam = 0, wl = 0, gw = 0, stage = 0, total = 0;
     int64_t ckpt_field = 0, ckpt_total = 0;  // host bytes per stored field, all checkpoints
 };
 
@@ -41,6 +41,7 @@ int layout_of(const oocs_adjoint_cfg* c, Layout& L)
     L.w = off; off += L.fb;
     L.states = off; off += (L.C + 2) * L.fb;
     L.lam = off; off += 3 * L.fb;
+    L.wl = off; off += 2 * L.fb;
     L.gw = off; off += L.fb;
     L.stage = off; off += 2 * L.cb;
     L.total = off;
@@ -72,28 +73,31 @@ int wave_step(const oocs_adjoint_cfg* c, float* cur, float* prev, const float* w
     return OOCS_OK;
 }
 
-// Store one field of a checkpoint (encode or copy, then to host).
-int store_field(const oocs_adjoint_cfg* c, const Layout& L, const float* f, char* stage, char* host, hipStream_t s)
-{
-    if (c->ckpt_rate == 0) {
-        HIP_TRY(hipMemcpyAsync(host, f, (size_t)(L.n * 4), hipMemcpyDeviceToHost, s));
+// A second stream for the checkpoint copies, with the two events that order
+// it against the compute stream; synchronised and released on every exit.
+struct CopyStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int init()
+    {
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        for (hipEvent_t& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         return OOCS_OK;
     }
-    HIP_TRY(oocs::launch_codec_field(true, f, nullptr, nullptr, reinterpret_cast<uint64_t*>(stage), c->nx, c->ny, c->nz,
-                                     c->nx, c->nx * c->ny, c->ckpt_rate, s));
-    HIP_TRY(hipMemcpyAsync(host, stage, (size_t)L.ckpt_field, hipMemcpyDeviceToHost, s));
-    return OOCS_OK;
-}
+    ~CopyStream()
+    {
+        if (s) (void)hipStreamSynchronize(s);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
 
-int load_field(const oocs_adjoint_cfg* c, const Layout& L, float* f, char* stage, const char* host, hipStream_t s)
+// Order `waiter` after the work queued so far on `signaller`.
+int order_after(hipStream_t waiter, hipStream_t signaller, hipEvent_t e)
 {
-    if (c->ckpt_rate == 0) {
-        HIP_TRY(hipMemcpyAsync(f, host, (size_t)(L.n * 4), hipMemcpyHostToDevice, s));
-        return OOCS_OK;
-    }
-    HIP_TRY(hipMemcpyAsync(stage, host, (size_t)L.ckpt_field, hipMemcpyHostToDevice, s));
-    HIP_TRY(oocs::launch_codec_field(false, nullptr, f, reinterpret_cast<const uint64_t*>(stage), nullptr, c->nx, c->ny,
-                                     c->nz, c->nx, c->nx * c->ny, c->ckpt_rate, s));
+    HIP_TRY(hipEventRecord(e, signaller));
+    HIP_TRY(hipStreamWaitEvent(waiter, e, 0));
     return OOCS_OK;
 }
 
@@ -143,11 +147,33 @@ int oocs_wave_forward_ckpt(const oocs_adjoint_cfg* c, const float* d_v, const fl
     HIP_TRY(oocs::launch_fill(A, 0.0f, L.n, s));
     HIP_TRY(oocs::launch_fill(B, 0.0f, L.n, s));
     const int nr = c->nrcv;
+    // Compressed checkpoints: each field is encoded into its staging slot on
+    // the compute stream and copied to the host on the copy stream while the
+    // next steps run; the slot is encoded again only after that copy. Raw
+    // checkpoints are copied from the state fields on the compute stream
+    // (the next step overwrites p(t-1)).
+    CopyStream cs;
+    if (c->ckpt_rate && (rc = cs.init())) return rc;
+    bool pending[2] = {false, false};
     for (int64_t t = 0; t < c->steps; ++t) {
         if (t % L.C == 0) {
             char* slot = ck + (t / L.C) * 2 * L.ckpt_field;
-            if ((rc = store_field(c, L, B, stage, slot, s))) return rc;                    // p(t)
-            if ((rc = store_field(c, L, A, stage + L.cb, slot + L.ckpt_field, s))) return rc;  // p(t-1)
+            const float* f2[2] = {B, A};  // p(t), p(t-1)
+            for (int f = 0; f < 2; ++f) {
+                char* host = slot + f * L.ckpt_field;
+                if (c->ckpt_rate == 0) {
+                    HIP_TRY(hipMemcpyAsync(host, f2[f], (size_t)(L.n * 4), hipMemcpyDeviceToHost, s));
+                    continue;
+                }
+                char* st = stage + f * L.cb;
+                if (pending[f]) HIP_TRY(hipStreamWaitEvent(s, cs.ev[2 + f], 0));
+                HIP_TRY(oocs::launch_codec_field(true, f2[f], nullptr, nullptr, reinterpret_cast<uint64_t*>(st), c->nx,
+                                                 c->ny, c->nz, c->nx, c->nx * c->ny, c->ckpt_rate, s));
+                if ((rc = order_after(cs.s, s, cs.ev[f]))) return rc;
+                HIP_TRY(hipMemcpyAsync(host, st, (size_t)L.ckpt_field, hipMemcpyDeviceToHost, cs.s));
+                HIP_TRY(hipEventRecord(cs.ev[2 + f], cs.s));
+                pending[f] = true;
+            }
         }
         if ((rc = wave_step(c, B, A, w, A, h_src[t], s))) return rc;  // p(t+1) over p(t-1)
         std::swap(A, B);
@@ -156,6 +182,7 @@ int oocs_wave_forward_ckpt(const oocs_adjoint_cfg* c, const float* d_v, const fl
     std::vector<float> res((size_t)c->steps * nr);
     if (nr > 0) HIP_TRY(hipMemcpyAsync(res.data(), d_res, res.size() * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (cs.s) HIP_TRY(hipStreamSynchronize(cs.s));
     double j = 0.0;
     for (float r : res) j += (double)r * (double)r;
     *J = 0.5 * j;
@@ -177,28 +204,59 @@ int oocs_wave_adjoint(const oocs_adjoint_cfg* c, const float* d_v, const float* 
     auto S = [&](int64_t i) { return reinterpret_cast<float*>(work + L.states + i * L.fb); };
     float* lam[3] = {reinterpret_cast<float*>(work + L.lam), reinterpret_cast<float*>(work + L.lam + L.fb),
                      reinterpret_cast<float*>(work + L.lam + 2 * L.fb)};
+    float* wl[2] = {reinterpret_cast<float*>(work + L.wl), reinterpret_cast<float*>(work + L.wl + L.fb)};
     float* gw = reinterpret_cast<float*>(work + L.gw);
     char* stage = work + L.stage;
     const char* ck = static_cast<const char*>(h_ckpt);
     HIP_TRY(oocs::launch_v_to_w(d_v, c->vscale, w, L.n, s));
     for (int i = 0; i < 3; ++i) HIP_TRY(oocs::launch_fill(lam[i], 0.0f, L.n, s));
+    for (int i = 0; i < 2; ++i) HIP_TRY(oocs::launch_fill(wl[i], 0.0f, L.n, s));
     HIP_TRY(oocs::launch_fill(gw, 0.0f, L.n, s));
-    // lam[i2] = lam(t+2), lam[i1] = lam(t+1), lam[i0] = lam(t) (rotating)
-    int i0 = 0, i1 = 1, i2 = 2;
+    // The copy stream brings in segment seg-1's checkpoint while segment seg
+    // runs: into the staging slots once they are decoded (compressed), or
+    // straight into the first two state fields once the recompute has read
+    // them (raw; the adjoint steps use the later states only).
+    CopyStream cs;
+    if ((rc = cs.init())) return rc;
+    auto issue_load = [&](int64_t seg) -> int {
+        const char* slot = ck + seg * 2 * L.ckpt_field;
+        void* dst[2] = {c->ckpt_rate ? (void*)stage : (void*)S(1), c->ckpt_rate ? (void*)(stage + L.cb) : (void*)S(0)};
+        for (int f = 0; f < 2; ++f)  // p(t0), p(t0-1)
+            HIP_TRY(hipMemcpyAsync(dst[f], slot + f * L.ckpt_field, (size_t)L.ckpt_field, hipMemcpyHostToDevice, cs.s));
+        return OOCS_OK;
+    };
+    if ((rc = order_after(cs.s, s, cs.ev[0]))) return rc;  // after the fills above
+    if ((rc = issue_load(L.nseg - 1))) return rc;
+    // lam[i2] = lam(t+2), lam[i1] = lam(t+1), lam[i0] = lam(t) (rotating);
+    // wl[j1] = w . lam(t+1), wl[j0] = w . lam(t)
+    int i0 = 0, i1 = 1, i2 = 2, j0 = 0, j1 = 1;
     for (int64_t seg = L.nseg - 1; seg >= 0; --seg) {
         const int64_t t0 = seg * L.C, t1 = std::min(c->steps, t0 + L.C);
-        const char* slot = ck + seg * 2 * L.ckpt_field;
-        if ((rc = load_field(c, L, S(1), stage, slot, s))) return rc;                    // p(t0)
-        if ((rc = load_field(c, L, S(0), stage + L.cb, slot + L.ckpt_field, s))) return rc;  // p(t0-1)
+        if ((rc = order_after(s, cs.s, cs.ev[1]))) return rc;  // this segment's checkpoint is in
+        if (c->ckpt_rate) {
+            for (int f = 0; f < 2; ++f)
+                HIP_TRY(oocs::launch_codec_field(false, nullptr, S(1 - f), reinterpret_cast<const uint64_t*>(stage + f * L.cb),
+                                                 nullptr, c->nx, c->ny, c->nz, c->nx, c->nx * c->ny, c->ckpt_rate, s));
+            if (seg > 0) {
+                if ((rc = order_after(cs.s, s, cs.ev[0]))) return rc;
+                if ((rc = issue_load(seg - 1))) return rc;
+            }
+        }
         for (int64_t t = t0; t < t1; ++t)  // S(t - t0 + 1) = p(t); S(t - t0 + 2) = p(t+1)
             if ((rc = wave_step(c, S(t - t0 + 1), S(t - t0), w, S(t - t0 + 2), h_src[t], s))) return rc;
+        if (!c->ckpt_rate && seg > 0) {
+            if ((rc = order_after(cs.s, s, cs.ev[0]))) return rc;
+            if ((rc = issue_load(seg - 1))) return rc;
+        }
         for (int64_t t = t1; t > t0; --t) {
-            HIP_TRY(oocs::launch_adjoint_step(lam[i1], lam[i2], w, S(t - t0 + 1), lam[i0], gw, c->nx, c->ny, c->nz, s));
-            HIP_TRY(oocs::launch_rcv_inject(lam[i0], d_rcv, c->nrcv, d_res + (t - 1) * c->nrcv, L.n, s));
+            HIP_TRY(oocs::launch_adjoint_step(lam[i1], wl[j1], lam[i2], w, S(t - t0 + 1), lam[i0], wl[j0], gw, c->nx,
+                                              c->ny, c->nz, s));
+            HIP_TRY(oocs::launch_rcv_inject(lam[i0], wl[j0], w, d_rcv, c->nrcv, d_res + (t - 1) * c->nrcv, L.n, s));
             const int old2 = i2;
             i2 = i1;
             i1 = i0;
             i0 = old2;
+            std::swap(j0, j1);
         }
     }
     HIP_TRY(oocs::launch_grad_w_to_v(gw, d_v, c->vscale, d_grad_v, L.n, s));

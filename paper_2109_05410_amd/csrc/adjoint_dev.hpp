@@ -6,16 +6,15 @@
 // zero ghosts)
 //   lam(t) = 2 lam(t+1) - lam(t+2) + L(w . lam(t+1)) + S^T (r(t) - d(t))
 // and dJ/dw = sum_t lam(t) . L p(t-1). One launch of adjoint_step computes
-// lam(t) (without the receiver term, which a second tiny kernel adds) and
-// accumulates grad += lam(t+1) . L p(t), the term of index t+1 of the sum.
+// lam(t) and w . lam(t) (without the receiver term, which a second tiny
+// kernel adds to both) and accumulates grad += lam(t+1) . L p(t), the term
+// of index t+1 of the sum.
 //
 // FP32 operation order (fixed; compiled without contraction):
 //   acc = C0X3*(w*l1); acc = acc + C_m*(((wl[x+m] + wl[x-m]) + (wl[y+m] + wl[y-m])) + (wl[z+m] + wl[z-m]))
 //   l0  = (2*l1 - l2) + acc,            wl[q] = w[q]*l1[q]
 //   lp  = C0X3*p; lp = lp + C_m*(((p[x+m] + p[x-m]) + (p[y+m] + p[y-m])) + (p[z+m] + p[z-m]))
 //   g   = g + l1*lp
-// Mapping as the forward level: 64 x 4 thread tiles, each thread marching up
-// to kZChunk planes with 9-value register queues for w*l1 and for p.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,15 +25,24 @@ namespace oocs {
 namespace adjoint {
 
 struct StepArgs {
-    const float* l1;  // lam(t+1)
-    const float* l2;  // lam(t+2)
+    const float* l1;   // lam(t+1)
+    const float* wl1;  // w . lam(t+1), element by element (kept beside lam)
+    const float* l2;   // lam(t+2)
     const float* w;
-    const float* p;   // p(t)
-    float* l0;        // lam(t), out
-    float* grad;      // accumulated in place
+    const float* p;    // p(t)
+    float* l0;         // lam(t), out
+    float* wl0;        // w . lam(t), out (the next step's wl1)
+    float* grad;       // accumulated in place
     int nx, ny, nz;
 };
 
+// One column (x, y) of a 64 x 4 tile over up to kZChunk planes. The product
+// w . lam is formed once, when lam is written (wl0 = w * l0, the same FP32
+// product as w[q] * l1[q] formed at every use), so the step reads one array
+// for the L(w . lam) stencil instead of two. Each thread keeps the z columns
+// of w . lam(t+1) and p(t) in registers and loads the x / y neighbours and the
+// point values of NB planes before computing them.
+template <int NB>
 __device__ inline void adjoint_step(const StepArgs& a, int wg)
 {
     const float C0X3 = (float)(-205.0 / 24.0);
@@ -42,6 +50,7 @@ __device__ inline void adjoint_step(const StepArgs& a, int wg)
     const float C2 = (float)(-1.0 / 5.0);
     const float C3 = (float)(8.0 / 315.0);
     const float C4 = (float)(-1.0 / 560.0);
+    const float CM[4] = {C1, C2, C3, C4};
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int tiles_x = (nx + kTileX - 1) / kTileX;
     const int tiles_y = (ny + kTileY - 1) / kTileY;
@@ -54,41 +63,66 @@ __device__ inline void adjoint_step(const StepArgs& a, int wg)
     if (x >= nx || y >= ny || z0 >= z1) return;
     const int64_t plane = (int64_t)nx * ny;
     const int64_t xy = (int64_t)y * nx + x;
-    auto wl = [&](int z) -> float {
-        if (z < 0 || z >= nz) return 0.0f;
-        const int64_t c = z * plane + xy;
-        return a.w[c] * a.l1[c];
-    };
-    auto pp = [&](int z) -> float { return (z >= 0 && z < nz) ? a.p[z * plane + xy] : 0.0f; };
-    float u0 = wl(z0 - 4), u1 = wl(z0 - 3), u2 = wl(z0 - 2), u3 = wl(z0 - 1);
-    float u4 = wl(z0), u5 = wl(z0 + 1), u6 = wl(z0 + 2), u7 = wl(z0 + 3);
-    float q0 = pp(z0 - 4), q1 = pp(z0 - 3), q2 = pp(z0 - 2), q3 = pp(z0 - 1);
-    float q4 = pp(z0), q5 = pp(z0 + 1), q6 = pp(z0 + 2), q7 = pp(z0 + 3);
-    for (int z = z0; z < z1; ++z) {
-        const float u8 = wl(z + 4);
-        const float q8 = pp(z + 4);
-        const int64_t c = z * plane + xy;
-        auto WX = [&](int d) -> float { return (x + d >= 0 && x + d < nx) ? a.w[c + d] * a.l1[c + d] : 0.0f; };
-        auto WY = [&](int d) -> float {
-            return (y + d >= 0 && y + d < ny) ? a.w[c + (int64_t)d * nx] * a.l1[c + (int64_t)d * nx] : 0.0f;
-        };
-        auto PX = [&](int d) -> float { return (x + d >= 0 && x + d < nx) ? a.p[c + d] : 0.0f; };
-        auto PY = [&](int d) -> float { return (y + d >= 0 && y + d < ny) ? a.p[c + (int64_t)d * nx] : 0.0f; };
-        float acc = C0X3 * u4;
-        acc = acc + C1 * (((WX(1) + WX(-1)) + (WY(1) + WY(-1))) + (u5 + u3));
-        acc = acc + C2 * (((WX(2) + WX(-2)) + (WY(2) + WY(-2))) + (u6 + u2));
-        acc = acc + C3 * (((WX(3) + WX(-3)) + (WY(3) + WY(-3))) + (u7 + u1));
-        acc = acc + C4 * (((WX(4) + WX(-4)) + (WY(4) + WY(-4))) + (u8 + u0));
-        const float l1c = a.l1[c];
-        a.l0[c] = (2.0f * l1c - a.l2[c]) + acc;
-        float lp = C0X3 * q4;
-        lp = lp + C1 * (((PX(1) + PX(-1)) + (PY(1) + PY(-1))) + (q5 + q3));
-        lp = lp + C2 * (((PX(2) + PX(-2)) + (PY(2) + PY(-2))) + (q6 + q2));
-        lp = lp + C3 * (((PX(3) + PX(-3)) + (PY(3) + PY(-3))) + (q7 + q1));
-        lp = lp + C4 * (((PX(4) + PX(-4)) + (PY(4) + PY(-4))) + (q8 + q0));
-        a.grad[c] = a.grad[c] + l1c * lp;
-        u0 = u1; u1 = u2; u2 = u3; u3 = u4; u4 = u5; u5 = u6; u6 = u7; u7 = u8;
-        q0 = q1; q1 = q2; q2 = q3; q3 = q4; q4 = q5; q5 = q6; q6 = q7; q7 = q8;
+    auto colu = [&](int z) -> float { return (z >= 0 && z < nz) ? a.wl1[z * plane + xy] : 0.0f; };
+    auto colp = [&](int z) -> float { return (z >= 0 && z < nz) ? a.p[z * plane + xy] : 0.0f; };
+    float u[NB + 8], q[NB + 8];  // u[i] = (w . lam(t+1))(zb - 4 + i), q[i] = p(zb - 4 + i)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        u[i] = colu(z0 - 4 + i);
+        q[i] = colp(z0 - 4 + i);
+    }
+    for (int zb = z0; zb < z1; zb += NB) {
+        float ux[NB][8], uy[NB][8], px[NB][8], py[NB][8], l1c[NB], l2c[NB], wc[NB], gc[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            u[8 + i] = q[8 + i] = 0.0f;
+            l1c[i] = l2c[i] = wc[i] = gc[i] = 0.0f;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) ux[i][m] = uy[i][m] = px[i][m] = py[i][m] = 0.0f;
+            if (zb + i < z1) {
+                const int64_t c = (int64_t)(zb + i) * plane + xy;
+                u[8 + i] = colu(zb + i + 4);
+                q[8 + i] = colp(zb + i + 4);
+                const float* U = a.wl1 + c;
+                const float* P = a.p + c;
+#pragma unroll
+                for (int m = 1; m <= 4; ++m) {
+                    if (x + m < nx) { ux[i][2 * m - 2] = U[m]; px[i][2 * m - 2] = P[m]; }
+                    if (x - m >= 0) { ux[i][2 * m - 1] = U[-m]; px[i][2 * m - 1] = P[-m]; }
+                    if (y + m < ny) { uy[i][2 * m - 2] = U[(int64_t)m * nx]; py[i][2 * m - 2] = P[(int64_t)m * nx]; }
+                    if (y - m >= 0) { uy[i][2 * m - 1] = U[-(int64_t)m * nx]; py[i][2 * m - 1] = P[-(int64_t)m * nx]; }
+                }
+                l1c[i] = a.l1[c];
+                l2c[i] = a.l2[c];
+                wc[i] = a.w[c];
+                gc[i] = a.grad[c];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (zb + i < z1) {
+                float acc = C0X3 * u[i + 4];
+#pragma unroll
+                for (int m = 1; m <= 4; ++m)
+                    acc = acc + CM[m - 1] * (((ux[i][2 * m - 2] + ux[i][2 * m - 1]) + (uy[i][2 * m - 2] + uy[i][2 * m - 1])) +
+                                             (u[i + 4 + m] + u[i + 4 - m]));
+                const float l0 = (2.0f * l1c[i] - l2c[i]) + acc;
+                float lp = C0X3 * q[i + 4];
+#pragma unroll
+                for (int m = 1; m <= 4; ++m)
+                    lp = lp + CM[m - 1] * (((px[i][2 * m - 2] + px[i][2 * m - 1]) + (py[i][2 * m - 2] + py[i][2 * m - 1])) +
+                                           (q[i + 4 + m] + q[i + 4 - m]));
+                const int64_t c = (int64_t)(zb + i) * plane + xy;
+                a.l0[c] = l0;
+                a.wl0[c] = wc[i] * l0;
+                a.grad[c] = gc[i] + l1c[i] * lp;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            u[i] = u[i + NB];
+            q[i] = q[i + NB];
+        }
     }
 }
 

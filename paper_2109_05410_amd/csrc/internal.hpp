@@ -105,12 +105,16 @@ hipError_t launch_codec_field(bool encode, const float* in_f, float* out_f, cons
 hipError_t launch_swap(float* a, float* b, int64_t n, hipStream_t stream);
 
 // Adjoint helpers (in-core fields, nx*ny*nz floats, x fastest).
-hipError_t launch_adjoint_step(const float* l1, const float* l2, const float* w, const float* p, float* l0,
-                               float* grad, int64_t nx, int64_t ny, int64_t nz, hipStream_t stream);
+// lam(t) and w . lam(t) from lam(t+1), w . lam(t+1), lam(t+2); grad += lam(t+1) . L p(t).
+hipError_t launch_adjoint_step(const float* l1, const float* wl1, const float* l2, const float* w, const float* p,
+                               float* l0, float* wl0, float* grad, int64_t nx, int64_t ny, int64_t nz,
+                               hipStream_t stream);
 // Receivers outside [0, n) are skipped.
 hipError_t launch_rcv_sample(const float* p, const int64_t* rcv, int nr, const float* obs, float* res, int64_t n,
                              hipStream_t s);
-hipError_t launch_rcv_inject(float* lam, const int64_t* rcv, int nr, const float* res, int64_t n, hipStream_t s);
+// lam += res at the receivers, and wl = w * lam at the cells touched.
+hipError_t launch_rcv_inject(float* lam, float* wl, const float* w, const int64_t* rcv, int nr, const float* res,
+                             int64_t n, hipStream_t s);
 hipError_t launch_v_to_w(const float* v, float c, float* w, int64_t n, hipStream_t s);
 hipError_t launch_grad_w_to_v(const float* gw, const float* v, float c, float* gv, int64_t n, hipStream_t s);
 hipError_t launch_fill(float* x, float value, int64_t n, hipStream_t s);

@@ -559,13 +559,14 @@ hipError_t launch_heat_dense(const float* src, float* dst, int nx, int ny, int n
 
 __global__ void __launch_bounds__(kBlockThreads) adjoint_step_kernel(adjoint::StepArgs a)
 {
-    adjoint::adjoint_step(a, (int)blockIdx.x);
+    adjoint::adjoint_step<2>(a, (int)blockIdx.x);
 }
 
-hipError_t launch_adjoint_step(const float* l1, const float* l2, const float* w, const float* p, float* l0,
-                               float* grad, int64_t nx, int64_t ny, int64_t nz, hipStream_t stream)
+hipError_t launch_adjoint_step(const float* l1, const float* wl1, const float* l2, const float* w, const float* p,
+                               float* l0, float* wl0, float* grad, int64_t nx, int64_t ny, int64_t nz,
+                               hipStream_t stream)
 {
-    adjoint::StepArgs a{l1, l2, w, p, l0, grad, (int)nx, (int)ny, (int)nz};
+    adjoint::StepArgs a{l1, wl1, l2, w, p, l0, wl0, grad, (int)nx, (int)ny, (int)nz};
     const int64_t tiles = ((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
     const int64_t wgs = tiles * ((nz + kZChunk - 1) / kZChunk);
     if (wgs == 0) return hipSuccess;
@@ -583,13 +584,18 @@ __global__ void rcv_sample_kernel(const float* p, const int64_t* rcv, int nr, co
     }
 }
 
-// lam[rcv[i]] += res[i], receivers in order (one thread: receivers may share a cell)
-__global__ void rcv_inject_kernel(float* lam, const int64_t* rcv, int nr, const float* res, int64_t n)
+// lam[rcv[i]] += res[i], receivers in order (one thread: receivers may share a
+// cell), and wl = w * lam refreshed at each touched cell
+__global__ void rcv_inject_kernel(float* lam, float* wl, const float* w, const int64_t* rcv, int nr, const float* res,
+                                  int64_t n)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (int i = 0; i < nr; ++i) {
             const int64_t r = rcv[i];
-            if (r >= 0 && r < n) lam[r] = lam[r] + res[i];
+            if (r >= 0 && r < n) {
+                lam[r] = lam[r] + res[i];
+                wl[r] = w[r] * lam[r];
+            }
         }
 }
 
@@ -601,10 +607,11 @@ hipError_t launch_rcv_sample(const float* p, const int64_t* rcv, int nr, const f
     return hipGetLastError();
 }
 
-hipError_t launch_rcv_inject(float* lam, const int64_t* rcv, int nr, const float* res, int64_t n, hipStream_t s)
+hipError_t launch_rcv_inject(float* lam, float* wl, const float* w, const int64_t* rcv, int nr, const float* res,
+                             int64_t n, hipStream_t s)
 {
     if (nr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(rcv_inject_kernel, dim3(1), dim3(64), 0, s, lam, rcv, nr, res, n);
+    hipLaunchKernelGGL(rcv_inject_kernel, dim3(1), dim3(64), 0, s, lam, wl, w, rcv, nr, res, n);
     return hipGetLastError();
 }
 

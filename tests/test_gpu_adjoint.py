@@ -60,6 +60,37 @@ def test_gradient_matches_oracle_fp32_bitwise(ckpt_every, steps):
     assert J == pytest.approx(J64, rel=1e-4)
 
 
+@pytest.mark.parametrize("ckpt_every,steps", [(10, 45), (16, 50)])
+def test_compressed_checkpoints_match_oracle_fp32_bitwise(ckpt_every, steps):
+    """With 12-bit checkpoints the backward pass recomputes each segment from
+    decode(encode()) of its two stored states; the oracle does the same with
+    its own codec and FP32 steps, and the gradients agree bit for bit (the
+    checkpoints are prefetched on a second stream, so this also checks the
+    ordering of those copies)."""
+    shape = (32, 28, 36)
+    rate = 12
+    v, v_true, c, amps, cell, src_idx, rcv = problem_inputs(shape, steps)
+    _, obs = O.wave_forward_states(w_of(v_true, c), steps, (amps, src_idx), rcv, dtype=np.float32)
+    prob = api.WaveProblem(shape, steps, amps, cell, rcv, obs, float(c), ckpt_every=ckpt_every, ckpt_rate=rate)
+    vd = torch.from_numpy(v).to(DEV)
+    prob.forward(vd)
+    g = prob.gradient(vd).cpu().numpy()
+    w32 = w_of(v, c)
+    states, rec = O.wave_forward_states(w32, steps, (amps, src_idx), rcv, dtype=np.float32)
+    res = (rec - obs).astype(np.float32)
+    assert np.array_equal(prob.res.cpu().numpy(), res)
+    recomputed = np.zeros_like(states)
+    for t0 in range(0, steps, ckpt_every):
+        p = O.codec_roundtrip(states[t0], rate)
+        pm = O.codec_roundtrip(states[t0 - 1] if t0 > 0 else np.zeros(shape, np.float32), rate)
+        for t in range(t0, min(steps, t0 + ckpt_every)):
+            p, pm = O.wave25_f32(p, pm, w32, 1, src=(amps[t:t + 1], src_idx))
+            recomputed[t + 1] = p
+    gw, _ = O.wave_adjoint(w32, steps, rcv, res, recomputed, dtype=np.float32)
+    gv = (gw * ((np.float32(2.0) * v) * (np.float32(c) * np.float32(c)))).astype(np.float32)
+    assert np.array_equal(g, gv)
+
+
 def test_compressed_checkpoints_report_gradient_deviation():
     shape = (32, 28, 36)
     steps = 60
