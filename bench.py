@@ -126,11 +126,13 @@ def run_variant(api, torch, u0, rate, steps, warmup, graphs, kernel_transfers, s
     return out
 
 
-def link_probe(api, sdma):
+def link_probe(api, sdma, chunk):
     """Achievable host-link bandwidth with pinned memory, moved with the
-    pipeline's engines in 4 MiB chunks: host-to-device alone, device-to-host
-    alone, and both at once (256 MiB each way, mean of 3 timed passes)."""
-    return api.link_probe(256 << 20, 4 << 20, reps=3, sdma=sdma)
+    pipeline's engines in copies of the pipeline's size (one group of
+    planes): host-to-device alone, device-to-host alone, and both at once
+    (about 256 MiB each way, mean of 3 timed passes)."""
+    return api.link_probe(256 // (chunk >> 20 or 1) * chunk if chunk >= (1 << 20) else 256 << 20, chunk, reps=3,
+                          sdma=sdma)
 
 
 def in_core_rate(api, torch, u0):
@@ -392,8 +394,9 @@ def main():
         print(json.dumps({"variants": {r: _rounded(res) for r, res in results.items()}}), flush=True)
         return
     incore = in_core_rate(api, torch, u0)
-    link = link_probe(api, sdma=bool(args.sdma))
-    link_hip = link_probe(api, sdma=False) if args.sdma else None
+    copy_bytes = int(head["group_planes"] * SHAPE[1] * SHAPE[2] * (head["rate"] / 8 if head["rate"] else 4))
+    link = link_probe(api, bool(args.sdma), copy_bytes)
+    link_hip = link_probe(api, False, copy_bytes) if args.sdma else None
     extras = {}
     if not args.no_extras:
         extras["codec_512"] = codec_rates(api, torch, u0)
@@ -470,8 +473,8 @@ def main():
         "achieved_GBps_each_way": round(head["h2d_GBps"], 2),
         "peak_GBps_each_way": round(bidir, 2) if bidir else None,
         "frac": round(head["h2d_GBps"] / bidir, 4) if bidir else None,
-        "peak_source": "host_link: 256 MiB each way in 4 MiB pinned copies on the pipeline's engines, "
-                       "both directions at once",
+        "peak_source": "host_link: ~256 MiB each way in pinned copies of the pipeline's group size on its "
+                       "engines, both directions at once",
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(u0, args.cpu_seconds)

@@ -22,11 +22,25 @@
 namespace oocs {
 namespace stencil {
 
+// Neighbouring lanes' values by data-parallel moves across the whole wave
+// (DPP wave_shr:1 / wave_shl:1, a VALU operation) rather than LDS permutes:
+// lane_up(v) is lane l-1's v (lane 0 gets 0), lane_down(v) lane l+1's v
+// (lane 63 gets 0). Every lane of the wave must execute the call.
+__device__ __forceinline__ float lane_up(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float lane_down(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
 // Heat, 7 points: u' = c + alpha * (((xm+xp) + (ym+yp)) + (zm+zp) - 6c).
 // Mapping: a lane owns 4 consecutive x (one float4), a wave one 256-wide
 // row segment, a workgroup 4 rows (one per wave); every lane marches up to
 // kZChunk planes in z. The x neighbours come from the adjacent lanes by
-// shuffles (the row ends of the wave from two scalar loads), the y
+// wave shifts (the row ends of the wave from two scalar loads), the y
 // neighbours from float4 loads of the rows above and below, the z
 // neighbours from the lane's own previous planes. A lane loads the inputs
 // of NB planes before it computes and stores any of them: the loads of a
@@ -77,8 +91,8 @@ __device__ inline void heat_level(const Job& j, int nx, int ny, int nz, float al
             if (act && zt == zb + i && zt < nz) c[i] = ld4(ring_plane(j.src, zt) + xy);
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            float l = __shfl_up(c[i].w, 1);
-            float r = __shfl_down(c[i].x, 1);
+            float l = lane_up(c[i].w);
+            float r = lane_down(c[i].x);
             if (lane == 0) l = el[i];
             if (lane == 63 || !hr) r = hr ? er[i] : 0.0f;
             if (act && zb + i < z1) {
@@ -225,8 +239,8 @@ __device__ __attribute__((always_inline)) inline void heat_tb(const Ring& src, c
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
                 const float cc = w[s - 1][c][1];
-                const float xm = __shfl_up(cc, 1);
-                const float xp = __shfl_down(cc, 1);
+                const float xm = lane_up(cc);
+                const float xp = lane_down(cc);
                 const float ym = c > 0 ? w[s - 1][c - 1][1] : above;
                 const float yp = c < CPT - 1 ? w[s - 1][c + 1][1] : below;
                 float v = 0.0f;
