@@ -252,17 +252,35 @@ __device__ inline void encode_lane(const float (&x)[64], int rate, uint64_t* lds
             if (w.budget > 0) {
                 const uint64_t X = plane_word(lo[p], hi[p]);
                 w.put(X, n);  // verbatim bits of the significant coefficients
-                while (n < 64 && w.budget > 0) {
-                    const uint64_t Y = X >> n;
-                    if (Y == 0) { w.put(0, 1); break; }
-                    const int m = __builtin_ctzll(Y);  // zeros before the next 1
-                    if (n + m == 63) {                 // the last coefficient: its 1 is implied
-                        w.put(1, 1 + m);
-                        n = 64;
-                        break;
+                if (n < 64 && w.budget > 0) {
+                    // The plane's group tests as one string of at most 127 bits
+                    // (c0: bits 0..63, c1: 64..127), written with two puts: for
+                    // each 1 of X at or above n, a positive test and the bits up
+                    // to and including that 1 (the last coefficient's 1 is
+                    // implied); then a negative test if coefficients remain.
+                    // Truncation at the budget happens in put, as bit by bit.
+                    uint64_t c0 = 0, c1 = 0;
+                    int len = 0;
+                    auto append = [&](uint64_t v, int l) {  // l in [1, 64], len + l <= 127
+                        c0 |= len < 64 ? v << len : 0;
+                        c1 |= len == 0 ? 0 : (len < 64 ? v >> (64 - len) : v << (len - 64));
+                        len += l;
+                    };
+                    uint64_t Y = X >> n;
+                    while (Y != 0) {
+                        const int m = __builtin_ctzll(Y);  // zeros before the next 1
+                        if (n + m == 63) {                 // the last coefficient
+                            append(1, 1 + m);
+                            n = 64;
+                            break;
+                        }
+                        append(1u | ((uint64_t)1 << (m + 1)), m + 2);  // test 1, m zeros, the 1
+                        n += m + 1;
+                        Y >>= m + 1;
                     }
-                    w.put(1u | ((uint64_t)1 << (m + 1)), m + 2);  // test 1, m zeros, the 1
-                    n += m + 1;
+                    if (n < 64) append(0, 1);
+                    w.put(c0, min(len, 64));
+                    if (len > 64) w.put(c1, len - 64);
                 }
             }
         }
