@@ -250,7 +250,8 @@ __device__ inline void encode_lane(const float (&x)[64], int rate, uint64_t* lds
         int n = 0;  // coefficients already significant
         for (int p = 31; p >= 0; --p) {
             if (w.budget > 0) {
-                const uint64_t X = plane_word(lo[p], hi[p]);
+                const int pu = __builtin_amdgcn_readfirstlane(p);  // uniform: plain register indexing
+                const uint64_t X = plane_word(lo[pu], hi[pu]);
                 w.put(X, n);  // verbatim bits of the significant coefficients
                 if (n < 64 && w.budget > 0) {
                     // The plane's group tests as one string of at most 127 bits
@@ -291,35 +292,41 @@ __device__ inline void encode_lane(const float (&x)[64], int rate, uint64_t* lds
 }
 
 // ---- per-lane bit reader over the wave's LDS words --------------------------
-// Keeps three words (the current one and the next two): the word loaded when
-// a read crosses a word boundary is first needed at the crossing after
-// that, so its LDS latency is hidden behind the bits in between.
+// Keeps the current word and the next two, plus the word three ahead, which
+// every skip loads unconditionally and the next skip takes if it crosses a
+// word boundary: the reader has no branches, and the LDS latency of each
+// load is hidden behind the bits decoded before its first use.
 struct LaneReader {
     const uint64_t* lds;  // word w of this lane at lds[w * 64]
     int rate;
-    uint64_t cur, nxt, nx2;  // words wi, wi+1, wi+2 (0 past the block)
+    uint64_t cur, nxt, nx2, pend;  // words wi, wi+1, wi+2, wi+3 (0 past the block)
     int wi, off;
 
-    __device__ uint64_t word(int w) const { return w < rate ? lds[w * 64] : 0; }
+    __device__ uint64_t word(int w) const
+    {
+        const uint64_t v = lds[min(w, rate - 1) * 64];  // an address inside the block either way
+        return w < rate ? v : 0;
+    }
     __device__ void init()
     {
         wi = 0; off = 0;
         cur = word(0);
         nxt = word(1);
         nx2 = word(2);
+        pend = word(3);
     }
     // the next 64 bits of the stream (bits past the block read as zero)
     __device__ uint64_t window() const { return (cur >> off) | ((nxt << 1) << (63 - off)); }
     __device__ void skip(int m)  // m in [0, 64]
     {
         off += m;
-        if (off >= 64) {
-            off -= 64;
-            ++wi;
-            cur = nxt;
-            nxt = nx2;
-            nx2 = word(wi + 2);
-        }
+        const bool cross = off >= 64;
+        off -= cross ? 64 : 0;
+        wi += cross ? 1 : 0;
+        cur = cross ? nxt : cur;
+        nxt = cross ? nx2 : nxt;
+        nx2 = cross ? pend : nx2;
+        pend = word(wi + 3);
     }
     __device__ uint64_t get(int m)  // m in [0, 64]
     {
@@ -338,7 +345,7 @@ struct DecStageOut {
 template <bool STAGES>
 __device__ inline void decode_lane(const uint64_t* lds, int rate, float (&x)[64], DecStageOut st = {}, int64_t b = 0)
 {
-    LaneReader r{lds, rate, 0, 0, 0, 0};
+    LaneReader r{lds, rate, 0, 0, 0, 0, 0, 0};
     r.init();
     if (r.get(1) == 0) {
 #pragma unroll
@@ -369,25 +376,32 @@ __device__ inline void decode_lane(const uint64_t* lds, int rate, float (&x)[64]
             // One window per group test: the test bit, the run of zeros and
             // the 1 that ends it are read together (the run is at most 62
             // bits unless it reaches the last coefficient or the budget).
-            while (n < 64 && budget > 0) {
+            // The body has no branches: a negative test, a run that reaches
+            // the last coefficient (its 1 implied) or the end of the budget,
+            // and an ordinary run only select different updates.
+            bool more = n < 64 && budget > 0;
+            while (more) {
                 const uint64_t win = r.window();
-                --budget;
-                if (!(win & 1)) { r.skip(1); break; }  // group test 0: no more ones in this plane
+                const int b1 = budget - 1;                   // the test bit
+                const bool neg = !(win & 1);                 // no more ones in this plane
                 const uint64_t rest = win >> 1;
                 int z = rest ? __builtin_ctzll(rest) : 63;  // zeros before the next 1
-                const int maxscan = 63 - n;
-                if (z > maxscan) z = maxscan;
-                if (z > budget) z = budget;
-                budget -= z; n += z;
-                if (n == 63) { r.skip(1 + z); X |= (uint64_t)1 << 63; n = 64; break; }
-                if (budget == 0) { r.skip(1 + z); break; }
-                r.skip(2 + z); --budget;  // with the 1 that ends the run
-                X |= (uint64_t)1 << n;
-                ++n;
+                z = min(z, 63 - n);
+                z = min(z, b1);
+                const int n1 = n + z, b2 = b1 - z;
+                const bool last = n1 == 63;
+                const bool stop = last || b2 == 0;
+                X |= (!neg && !stop) ? (uint64_t)1 << n1 : 0;
+                X |= (!neg && last) ? (uint64_t)1 << 63 : 0;
+                r.skip(neg ? 1 : (stop ? 1 + z : 2 + z));
+                n = neg ? n : (last ? 64 : (stop ? n1 : n1 + 1));
+                budget = neg ? b1 : (stop ? b2 : b2 - 1);
+                more = !neg && !stop && budget > 0;
             }
         }
-        lo[p] = (uint32_t)X;
-        hi[p] = (uint32_t)(X >> 32);
+        const int pu = __builtin_amdgcn_readfirstlane(p);  // uniform: plain register indexing
+        lo[pu] = (uint32_t)X;
+        hi[pu] = (uint32_t)(X >> 32);
         if (STAGES && st.planes) st.planes[32 * b + p] = X;
     }
     uint32_t u[64];
