@@ -237,10 +237,14 @@ int32_t job_workgroups(const Job& j, int nx, int ny)
     }
 }
 
-// Orders the jobs (transfers, then codec, then the rest), fills the
-// workgroup prefix sums and picks the kernel. Returns false if there is no
-// work.
-static int dispatch_class(int kind) { return is_xfer_job(kind) ? 0 : (is_codec_job(kind) ? 1 : 2); }
+// Orders the jobs, fills the workgroup prefix sums and picks the kernel.
+// Returns false if there is no work. Workgroups are dispatched in index
+// order and a tick has more of them than the chip holds at once, so the
+// longest-running ones go first: transfers (on the pipeline's critical
+// path), then the stencil jobs (a temporally blocked workgroup marches its
+// whole z-range), then the codec jobs, which fill the slots the others
+// leave (a 512^2 x 20-plane tick at 8 bits: 76 -> 62 us against codec first).
+static int dispatch_class(int kind) { return is_xfer_job(kind) ? 0 : (is_codec_job(kind) ? 2 : 1); }
 
 static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, size_t* lds)
 {
