@@ -60,6 +60,7 @@ constexpr int kZChunk = 16;         // planes one stencil thread marches
 constexpr int kHeatTileX = 256;     // heat xy tile: 4 waves, each a 256-wide row (4 x per lane)
 constexpr int kHeatTileY = 4;
 constexpr int kTbTileY = 16;        // temporally blocked heat: 64 x 16 cell tiles (k-cell halo included)
+constexpr int kWaveTileY = 16;      // wave: 64 x 16 cell tiles, planes staged through LDS with a 4-cell halo
 constexpr int kMaxTbSteps = 4;
 
 struct LaunchParams {

@@ -20,7 +20,6 @@ static_assert(sizeof(LaunchParams) <= 4096, "kernel arguments must stay within 4
 constexpr int kWavesPerWG = kBlockThreads / 64;
 constexpr int kCopyFloat4PerThread = 4;
 constexpr int kHeatBatch = 4;  // planes whose loads a heat lane issues together
-constexpr int kWaveBatch = 2;  // same for the wave
 
 extern __shared__ uint64_t dyn_lds[];  // codec jobs: 64 * rate words per wave
 
@@ -165,7 +164,8 @@ __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
     case JOB_ENCODE: codec_job(j, p.nx, p.ny, local, true); break;
     case JOB_HEAT: stencil::heat_level<kHeatBatch>(j, p.nx, p.ny, p.nz, p.alpha, local); break;
     case JOB_WAVE:
-        stencil::wave_level<kWaveBatch>(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local);
+        stencil::wave_tile(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local,
+                           reinterpret_cast<float*>(dyn_lds));
         break;
     case JOB_COPY_IN: copy_job(j, p.nx, p.ny, local, true); break;
     case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
@@ -179,6 +179,10 @@ __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
 // Launches without codec jobs use this kernel: a stencil thread needs about
 // 40 VGPRs, and the codec path of the fused kernel would cap it at the
 // codec's occupancy.
+// WAVE: the variant that can run wave jobs (launches holding one); the
+// other leaves the wave's register queues and staging out, so heat and copy
+// launches keep their occupancy.
+template <bool WAVE>
 __global__ void __launch_bounds__(kBlockThreads) stencil_kernel(LaunchParams p)
 {
     const int wg = (int)blockIdx.x;
@@ -189,7 +193,9 @@ __global__ void __launch_bounds__(kBlockThreads) stencil_kernel(LaunchParams p)
     switch (j.kind) {
     case JOB_HEAT: stencil::heat_level<kHeatBatch>(j, p.nx, p.ny, p.nz, p.alpha, local); break;
     case JOB_WAVE:
-        stencil::wave_level<kWaveBatch>(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local);
+        if (WAVE)
+            stencil::wave_tile(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local,
+                               reinterpret_cast<float*>(dyn_lds));
         break;
     case JOB_COPY_IN: copy_job(j, p.nx, p.ny, local, true); break;
     case JOB_COPY_OUT: copy_job(j, p.nx, p.ny, local, false); break;
@@ -212,7 +218,7 @@ int32_t job_workgroups(const Job& j, int nx, int ny)
         return tiles * ((planes + kZChunk - 1) / kZChunk);
     }
     case JOB_WAVE: {
-        const int tiles = ((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
+        const int tiles = ((nx + 63) / 64) * ((ny + kWaveTileY - 1) / kWaveTileY);
         return tiles * ((planes + kZChunk - 1) / kZChunk);
     }
     case JOB_HEAT_TB: {
@@ -265,15 +271,20 @@ static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, siz
     p.wg_begin[p.njobs] = total;
     if (total == 0) return false;
     *grid = (unsigned)total;
-    size_t tb_lds = 0;
-    for (int i = 0; i < n; ++i)
+    size_t tb_lds = 0;  // stencil jobs' LDS: blocked heat edge rows, staged wave planes
+    bool wave = false;
+    for (int i = 0; i < n; ++i) {
+        wave = wave || p.jobs[i].kind == JOB_WAVE;
         if (p.jobs[i].kind == JOB_HEAT_TB && heat_tb_lds(p.jobs[i].rate) > tb_lds) tb_lds = heat_tb_lds(p.jobs[i].rate);
+        if (p.jobs[i].kind == JOB_WAVE && stencil::wave_tile_lds() > tb_lds) tb_lds = stencil::wave_tile_lds();
+    }
     if (max_rate > 0) {
         *func = reinterpret_cast<const void*>(&fused_kernel);
         const size_t codec_lds = (size_t)kWavesPerWG * 64 * max_rate * sizeof(uint64_t);
         *lds = codec_lds > tb_lds ? codec_lds : tb_lds;
     } else {
-        *func = reinterpret_cast<const void*>(&stencil_kernel);
+        *func = wave ? reinterpret_cast<const void*>(&stencil_kernel<true>)
+                     : reinterpret_cast<const void*>(&stencil_kernel<false>);
         *lds = tb_lds;
     }
     return true;
@@ -287,8 +298,10 @@ hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
     if (!prepare_jobs(p, &func, &grid, &lds)) return hipSuccess;
     if (func == reinterpret_cast<const void*>(&fused_kernel))
         hipLaunchKernelGGL(fused_kernel, dim3(grid), dim3(kBlockThreads), lds, stream, p);
+    else if (func == reinterpret_cast<const void*>(&stencil_kernel<true>))
+        hipLaunchKernelGGL(stencil_kernel<true>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
     else
-        hipLaunchKernelGGL(stencil_kernel, dim3(grid), dim3(kBlockThreads), lds, stream, p);
+        hipLaunchKernelGGL(stencil_kernel<false>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
     return hipGetLastError();
 }
 

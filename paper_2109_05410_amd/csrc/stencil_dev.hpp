@@ -281,11 +281,19 @@ __host__ __device__ inline int heat_tb_tiles(int nx, int ny)
 // Wave, 25 points:
 //   acc = C0X3*p;  for m = 1..4: acc = acc + C_m * (((x+m + x-m) + (y+m + y-m)) + (z+m + z-m))
 //   p'  = (2p - pm) + w*acc  (+ amp at the source cell)
-// Each thread keeps the column p(z-4 .. z+NB+3) in registers and loads the
-// x / y neighbours, pm and w of NB planes before computing them.
-template <int NB>
-__device__ inline void wave_level(const Job& j, int nx, int ny, int nz, int sx, int sy, int sz,
-                                  const float* src_table, const int32_t* step_ctr, int wg)
+// Mapping: a workgroup owns a 64 x kWaveTileY cell tile (each wave 64
+// lanes x kWaveTileY/4 consecutive rows, so a thread has kWaveTileY/4
+// cells) and marches up to kZChunk planes. Each plane of p, with its 4-cell
+// halo in x and y, is staged through LDS (double buffered; the next plane's
+// loads are issued before the current plane is computed; one barrier per
+// plane), so the 16 x / y neighbours of a cell are LDS reads, and every
+// thread keeps its cells' p(z-4 .. z+4) in registers.
+constexpr int kWaveTileW = 64 + 8, kWaveTileH = kWaveTileY + 8;
+constexpr int kWaveTilePlane = kWaveTileW * kWaveTileH;  // floats of one staged plane
+__host__ __device__ constexpr size_t wave_tile_lds() { return 2 * (size_t)kWaveTilePlane * sizeof(float); }
+
+__device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, int sy, int sz, const float* src_table,
+                                 const int32_t* step_ctr, int wg, float* lds)
 {
     const float C0X3 = (float)(-205.0 / 24.0);
     const float C1 = (float)(8.0 / 5.0);
@@ -293,58 +301,88 @@ __device__ inline void wave_level(const Job& j, int nx, int ny, int nz, int sx, 
     const float C3 = (float)(8.0 / 315.0);
     const float C4 = (float)(-1.0 / 560.0);
     const float CM[4] = {C1, C2, C3, C4};
-    const int tiles_x = (nx + kTileX - 1) / kTileX;
-    const int tiles_y = (ny + kTileY - 1) / kTileY;
+    constexpr int R = kWaveTileY / 4;                                   // cells per thread
+    constexpr int TW = kWaveTileW, TP = kWaveTilePlane;
+    constexpr int LPT = (TP + kBlockThreads - 1) / kBlockThreads;      // staged floats per thread
+    const int tiles_x = (nx + 63) / 64;
+    const int tiles_y = (ny + kWaveTileY - 1) / kWaveTileY;
     const int tile = wg % (tiles_x * tiles_y);
     const int zc = wg / (tiles_x * tiles_y);
-    const int x = (tile % tiles_x) * kTileX + (int)(threadIdx.x % kTileX);
-    const int y = (tile / tiles_x) * kTileY + (int)(threadIdx.x / kTileX);
+    const int x0 = (tile % tiles_x) * 64, y0 = (tile / tiles_x) * kWaveTileY;
     const int z0 = j.z0 + zc * kZChunk;
     const int z1 = min(j.z1, z0 + kZChunk);
-    if (x >= nx || y >= ny || z0 >= z1) return;
-    const int64_t xy = (int64_t)y * nx + x;
-    auto col = [&](int z) -> float { return (z >= 0 && z < nz) ? ring_plane(j.src, z)[xy] : 0.0f; };
-    float q[NB + 8];  // q[i] = p(zb - 4 + i)
+    if (z0 >= z1) return;  // the same for the whole workgroup
+    const int tid = (int)threadIdx.x, lx = tid & 63, wv = tid >> 6;
+    const int x = x0 + lx;
+    bool cin[R], srcc[R];
+    int64_t off[R];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) q[i] = col(z0 - 4 + i);
-    const bool src_col = j.has_src && x == sx && y == sy;
-    for (int zb = z0; zb < z1; zb += NB) {
-        float xs[NB][8], ys[NB][8], pm[NB], w[NB];
+    for (int c = 0; c < R; ++c) {
+        const int y = y0 + wv * R + c;
+        cin[c] = x < nx && y < ny;
+        srcc[c] = j.has_src && x == sx && y == sy;
+        off[c] = (int64_t)y * nx + x;
+    }
+    // staged element e = tid + kBlockThreads*i is (x0-4 + e % TW, y0-4 + e / TW)
+    int64_t soff[LPT];
+    bool sok[LPT];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            q[8 + i] = 0.0f;
-            pm[i] = w[i] = 0.0f;
+    for (int i = 0; i < LPT; ++i) {
+        const int e = tid + kBlockThreads * i;
+        const int gx = x0 - 4 + e % TW, gy = y0 - 4 + e / TW;
+        sok[i] = e < TP && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        soff[i] = (int64_t)gy * nx + gx;
+    }
+    float st[LPT];
+    auto stage_load = [&](int z) {
+        const float* pl = ring_plane(j.src, z);
 #pragma unroll
-            for (int m = 0; m < 8; ++m) xs[i][m] = ys[i][m] = 0.0f;
-            if (zb + i < z1) {
-                q[8 + i] = col(zb + i + 4);
-                const float* pl = ring_plane(j.src, zb + i) + xy;
+        for (int i = 0; i < LPT; ++i) st[i] = sok[i] ? pl[soff[i]] : 0.0f;
+    };
+    auto stage_store = [&](int buf) {
+        float* t = lds + buf * TP;
 #pragma unroll
-                for (int m = 1; m <= 4; ++m) {
-                    if (x + m < nx) xs[i][2 * m - 2] = pl[m];
-                    if (x - m >= 0) xs[i][2 * m - 1] = pl[-m];
-                    if (y + m < ny) ys[i][2 * m - 2] = pl[(int64_t)m * nx];
-                    if (y - m >= 0) ys[i][2 * m - 1] = pl[-(int64_t)m * nx];
-                }
-                pm[i] = ring_plane(j.src2, zb + i)[xy];
-                w[i] = ring_plane(j.ro, zb + i)[xy];
-            }
+        for (int i = 0; i < LPT; ++i)
+            if (tid + kBlockThreads * i < TP) t[tid + kBlockThreads * i] = st[i];
+    };
+    auto col = [&](int c, int z) -> float { return (cin[c] && z >= 0 && z < nz) ? ring_plane(j.src, z)[off[c]] : 0.0f; };
+    float q[R][9];  // q[c][i] = p(z - 4 + i) at cell c
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) q[c][i] = col(c, z0 - 4 + i);
+    stage_load(z0);
+    stage_store(0);
+    __syncthreads();
+    for (int z = z0; z < z1; ++z) {
+        const int b = (z - z0) & 1;
+        const bool more = z + 1 < z1;
+        if (more) stage_load(z + 1);  // in flight while this plane is computed
+        float pm[R], w[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            q[c][8] = col(c, z + 4);
+            pm[c] = cin[c] ? ring_plane(j.src2, z)[off[c]] : 0.0f;
+            w[c] = cin[c] ? ring_plane(j.ro, z)[off[c]] : 0.0f;
         }
+        const float* t = lds + b * TP + (wv * R + 4) * TW + lx + 4;
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            if (zb + i < z1) {
-                float acc = C0X3 * q[i + 4];
+        for (int c = 0; c < R; ++c) {
+            const float* tc = t + c * TW;
+            float acc = C0X3 * q[c][4];
 #pragma unroll
-                for (int m = 1; m <= 4; ++m)
-                    acc = acc + CM[m - 1] * (((xs[i][2 * m - 2] + xs[i][2 * m - 1]) + (ys[i][2 * m - 2] + ys[i][2 * m - 1])) +
-                                             (q[i + 4 + m] + q[i + 4 - m]));
-                float v = (2.0f * q[i + 4] - pm[i]) + w[i] * acc;
-                if (src_col && zb + i == sz) v = v + (src_table ? src_table[*step_ctr + j.src_off] : j.amp);
-                ring_plane(j.dst, zb + i)[xy] = v;
-            }
+            for (int m = 1; m <= 4; ++m)
+                acc = acc + CM[m - 1] * (((tc[m] + tc[-m]) + (tc[m * TW] + tc[-m * TW])) + (q[c][4 + m] + q[c][4 - m]));
+            float v = (2.0f * q[c][4] - pm[c]) + w[c] * acc;
+            if (srcc[c] && z == sz) v = v + (src_table ? src_table[*step_ctr + j.src_off] : j.amp);
+            if (cin[c]) ring_plane(j.dst, z)[off[c]] = v;
         }
+        if (more) stage_store(b ^ 1);
+        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 8; ++i) q[i] = q[i + NB];
+        for (int c = 0; c < R; ++c)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[c][i] = q[c][i + 1];
     }
 }
 
