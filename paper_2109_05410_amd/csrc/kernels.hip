@@ -574,9 +574,11 @@ hipError_t launch_heat_dense(const float* src, float* dst, int nx, int ny, int n
 // Adjoint of the wave propagator and its small helpers
 // ---------------------------------------------------------------------------
 
+constexpr int kAdjTileY = 8;  // adjoint step tile: 64 x 8 cells
+
 __global__ void __launch_bounds__(kBlockThreads) adjoint_step_kernel(adjoint::StepArgs a)
 {
-    adjoint::adjoint_step<2>(a, (int)blockIdx.x);
+    adjoint::adjoint_step<kAdjTileY>(a, (int)blockIdx.x, reinterpret_cast<float*>(dyn_lds));
 }
 
 hipError_t launch_adjoint_step(const float* l1, const float* wl1, const float* l2, const float* w, const float* p,
@@ -584,10 +586,11 @@ hipError_t launch_adjoint_step(const float* l1, const float* wl1, const float* l
                                hipStream_t stream)
 {
     adjoint::StepArgs a{l1, wl1, l2, w, p, l0, wl0, grad, (int)nx, (int)ny, (int)nz};
-    const int64_t tiles = ((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
+    const int64_t tiles = ((nx + 63) / 64) * ((ny + kAdjTileY - 1) / kAdjTileY);
     const int64_t wgs = tiles * ((nz + kZChunk - 1) / kZChunk);
     if (wgs == 0) return hipSuccess;
-    hipLaunchKernelGGL(adjoint_step_kernel, dim3((unsigned)wgs), dim3(kBlockThreads), 0, stream, a);
+    hipLaunchKernelGGL(adjoint_step_kernel, dim3((unsigned)wgs), dim3(kBlockThreads),
+                       adjoint::StepTile<kAdjTileY>::lds_bytes(), stream, a);
     return hipGetLastError();
 }
 
