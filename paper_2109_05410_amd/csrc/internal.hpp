@@ -54,8 +54,6 @@ struct Job {
 
 constexpr int kMaxJobs = 24;
 constexpr int kBlockThreads = 256;  // every job runs 256-thread workgroups (4 waves)
-constexpr int kTileX = 64;          // stencil xy tile: 64 x 4 threads
-constexpr int kTileY = 4;
 constexpr int kZChunk = 16;         // planes one stencil thread marches
 constexpr int kHeatTileX = 256;     // heat xy tile: 4 waves, each a 256-wide row (4 x per lane)
 constexpr int kHeatTileY = 4;

@@ -2,13 +2,14 @@
 // z-range of planes held in rings (Sec. III: each cell is updated from its
 // neighbours; cells outside the grid are zero).
 //
-// Mapping: a 64 x 4 thread tile covers 64 x 4 columns of the xy plane and
-// every thread marches up to kZChunk planes in z, keeping the z-neighbours
-// it needs in registers (3 planes for heat, 9 for the wave), so each input
-// plane value is fetched from memory once per thread column; x and y
-// neighbours come through the L1/L2 caches of the neighbouring lanes'
-// loads. Lanes of a wave cover 64 consecutive x, so every load and store
-// of a plane row is one coalesced 256-byte access.
+// Common mapping: every thread marches a column of cells up the z-range,
+// keeping the z-neighbours it needs in registers (3 planes for heat, 9 for
+// the wave), so each input plane value is fetched once per column; the
+// lanes of a wave cover consecutive x, so every load and store of a plane
+// row is one coalesced access; x neighbours come from the adjacent lanes
+// (DPP wave shifts) or from a plane staged in LDS, y neighbours from the
+// same thread's registers, the rows above and below, or the staged plane
+// (see each function).
 //
 // The FP32 operation order is fixed (see each function) and the file is
 // compiled without floating-point contraction, so a cell's value does not
