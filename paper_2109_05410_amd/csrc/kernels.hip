@@ -19,7 +19,8 @@ static_assert(sizeof(LaunchParams) <= 4096, "kernel arguments must stay within 4
 
 constexpr int kWavesPerWG = kBlockThreads / 64;
 constexpr int kCopyFloat4PerThread = 4;
-constexpr int kHeatBatch = 4;  // planes whose loads a heat lane issues together
+constexpr int kHeatBatch = 4;       // planes whose loads a heat lane issues together (shared kernels)
+constexpr int kHeatBatchAlone = 8;  // the same in launches of heat levels only (more registers)
 
 extern __shared__ uint64_t dyn_lds[];  // codec jobs: 64 * rate words per wave
 
@@ -179,10 +180,13 @@ __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
 // Launches without codec jobs use this kernel: a stencil thread needs about
 // 40 VGPRs, and the codec path of the fused kernel would cap it at the
 // codec's occupancy.
-// WAVE: the variant that can run wave jobs (launches holding one); the
-// other leaves the wave's register queues and staging out, so heat and copy
-// launches keep their occupancy.
-template <bool WAVE>
+// Variants: kStencilWave can run wave jobs (launches holding one);
+// kStencilPlain leaves the wave's register queues and staging out, so heat
+// and copy launches keep their occupancy; kStencilHeat runs heat levels only
+// (in-core steps, level-by-level ticks) with a deeper load batch.
+constexpr int kStencilPlain = 0, kStencilWave = 1, kStencilHeat = 2;
+
+template <int V>
 __global__ void __launch_bounds__(kBlockThreads) stencil_kernel(LaunchParams p)
 {
     const int wg = (int)blockIdx.x;
@@ -190,10 +194,14 @@ __global__ void __launch_bounds__(kBlockThreads) stencil_kernel(LaunchParams p)
     while (jdx + 1 < p.njobs && wg >= p.wg_begin[jdx + 1]) ++jdx;
     const Job& j = p.jobs[jdx];
     const int local = wg - p.wg_begin[jdx];
+    if (V == kStencilHeat) {
+        stencil::heat_level<kHeatBatchAlone>(j, p.nx, p.ny, p.nz, p.alpha, local);
+        return;
+    }
     switch (j.kind) {
     case JOB_HEAT: stencil::heat_level<kHeatBatch>(j, p.nx, p.ny, p.nz, p.alpha, local); break;
     case JOB_WAVE:
-        if (WAVE)
+        if (V == kStencilWave)
             stencil::wave_tile(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local,
                                reinterpret_cast<float*>(dyn_lds));
         break;
@@ -272,9 +280,10 @@ static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, siz
     if (total == 0) return false;
     *grid = (unsigned)total;
     size_t tb_lds = 0;  // stencil jobs' LDS: blocked heat edge rows, staged wave planes
-    bool wave = false;
+    bool wave = false, heat_only = true;
     for (int i = 0; i < n; ++i) {
         wave = wave || p.jobs[i].kind == JOB_WAVE;
+        heat_only = heat_only && p.jobs[i].kind == JOB_HEAT;
         if (p.jobs[i].kind == JOB_HEAT_TB && heat_tb_lds(p.jobs[i].rate) > tb_lds) tb_lds = heat_tb_lds(p.jobs[i].rate);
         if (p.jobs[i].kind == JOB_WAVE && stencil::wave_tile_lds() > tb_lds) tb_lds = stencil::wave_tile_lds();
     }
@@ -283,8 +292,9 @@ static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, siz
         const size_t codec_lds = (size_t)kWavesPerWG * 64 * max_rate * sizeof(uint64_t);
         *lds = codec_lds > tb_lds ? codec_lds : tb_lds;
     } else {
-        *func = wave ? reinterpret_cast<const void*>(&stencil_kernel<true>)
-                     : reinterpret_cast<const void*>(&stencil_kernel<false>);
+        *func = wave        ? reinterpret_cast<const void*>(&stencil_kernel<kStencilWave>)
+                : heat_only ? reinterpret_cast<const void*>(&stencil_kernel<kStencilHeat>)
+                            : reinterpret_cast<const void*>(&stencil_kernel<kStencilPlain>);
         *lds = tb_lds;
     }
     return true;
@@ -298,10 +308,12 @@ hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
     if (!prepare_jobs(p, &func, &grid, &lds)) return hipSuccess;
     if (func == reinterpret_cast<const void*>(&fused_kernel))
         hipLaunchKernelGGL(fused_kernel, dim3(grid), dim3(kBlockThreads), lds, stream, p);
-    else if (func == reinterpret_cast<const void*>(&stencil_kernel<true>))
-        hipLaunchKernelGGL(stencil_kernel<true>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
+    else if (func == reinterpret_cast<const void*>(&stencil_kernel<kStencilWave>))
+        hipLaunchKernelGGL(stencil_kernel<kStencilWave>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
+    else if (func == reinterpret_cast<const void*>(&stencil_kernel<kStencilHeat>))
+        hipLaunchKernelGGL(stencil_kernel<kStencilHeat>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
     else
-        hipLaunchKernelGGL(stencil_kernel<false>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
+        hipLaunchKernelGGL(stencil_kernel<kStencilPlain>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
     return hipGetLastError();
 }
 
