@@ -51,3 +51,25 @@ def test_calls_without_gpu_work():
     assert b"null" in lib.oocs_last_error()
     with pytest.raises(L.OocsError):
         L.check(rc)
+
+
+def test_transfer_entry_points_check_arguments_without_gpu():
+    """The SDMA switch, its availability query and the host-link probe
+    reject null handles and buffers before touching a device."""
+    lib = L.lib()
+    assert lib.oocs_plan_set_sdma(None, 1) == L.OOCS_E_ARG
+    assert lib.oocs_plan_sdma_available(None) == 0
+    out = (ctypes.c_double * 4)()
+    assert lib.oocs_link_probe(None, None, None, None, 1 << 20, 1 << 20, 1, 1, out) == L.OOCS_E_ARG
+    assert lib.oocs_link_probe(1, 1, 1, 1, 0, 1 << 20, 1, 1, out) == L.OOCS_E_ARG      # zero bytes
+    assert lib.oocs_link_probe(1, 1, 1, 1, 1 << 20, 0, 1, 1, out) == L.OOCS_E_ARG      # zero chunk
+    assert lib.oocs_link_probe(1, 1, 1, 1, 1 << 20, 1 << 20, 0, 1, out) == L.OOCS_E_ARG  # no timed pass
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asking for more exits with a message
+    before anything is imported or launched."""
+    r = subprocess.run(["python3", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
