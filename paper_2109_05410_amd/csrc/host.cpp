@@ -4,10 +4,12 @@
 // The executor walks the planner's operation list once per residency and
 // issues it on three HIP streams (Sec. V-B: three streams overlap the
 // host-to-device copies, the GPU work and the device-to-host copies):
-// copies with hipMemcpyAsync, the compute jobs of a tick as one fused
-// launch, and the ordering edges as event records and waits. It makes no
-// device allocation and no synchronisation until the last residency has
-// been issued.
+// host-to-device copies with hipMemcpyAsync, device-to-host copies on an
+// SDMA engine through the HSA runtime (sdma.cpp; hipMemcpyAsync where that
+// is unavailable or switched off), the compute jobs of a tick as one fused
+// launch, and the ordering edges as event records and waits, honoured on
+// the host by default. It makes no device allocation and no synchronisation
+// until the last residency has been issued.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
