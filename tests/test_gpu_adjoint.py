@@ -127,3 +127,86 @@ def test_autograd_function():
     Jm = prob.forward((vd.detach() - d).contiguous())
     pred = float(torch.sum(vd.grad * d))
     assert (Jp - Jm) / 2 == pytest.approx(pred, rel=1e-2)
+
+
+def _crop_bounds(center, reach, n):
+    """[lo, hi) along one axis covering center +- reach, widened to multiples
+    of 4 (whole codec blocks) and clipped to the domain."""
+    lo = max(0, (center - reach) // 4 * 4)
+    hi = min(n, -(-(center + reach + 1) // 4) * 4)
+    return lo, hi
+
+
+@pytest.mark.parametrize("rate", [0, 12])
+def test_full_size_gradient_on_light_cone_crop(rate):
+    """The gradient at the full 512^3 size, in the configuration the
+    benchmark times (checkpoints every 10 steps, raw or 12 bits per value),
+    checked cell for cell against the FP32 oracle on a crop. From rest the
+    field after t steps is zero beyond 4t cells (L1) of the source, and the
+    multipliers are zero beyond 4(T - t) cells of the receivers (the
+    stencil's radius is 4 per step; a restored checkpoint widens the support
+    by at most 3 cells per axis, to whole 4^3 blocks). A 4-aligned crop that
+    holds those supports with a margin sees the same zero ghosts as the full
+    domain, so inside it the gradient must equal the oracle's bit for bit and
+    outside it must be exactly zero."""
+    shape = (512, 512, 512)
+    nz, ny, nx = shape
+    steps, every = 20, 10
+    dt = inputs.wave_dt()
+    c = np.float32(dt / 10.0)
+    amps = inputs.ricker(steps, dt, f=60.0, t0=8 * dt)
+    sx, sy, sz = inputs.source_cell(shape)
+    offs = [(-12, -8), (-4, 0), (4, 8), (12, -12), (0, 12), (-8, 4), (8, -4), (0, 0)]
+    rcv_xy = [(sx + dx, sy + dy) for dx, dy in offs]
+    rcv = np.array([x + nx * (y + ny * 2) for x, y in rcv_xy], np.int64)
+    reach = 12 + 4 * steps + 16
+    (x0, x1), (y0, y1), (z0, z1) = (_crop_bounds(sx, reach, nx), _crop_bounds(sy, reach, ny),
+                                    _crop_bounds(sz, reach, nz))
+    assert z0 == 0 and x0 > 0 and x1 < nx and y0 > 0 and y1 < ny
+    cshape = (z1 - z0, y1 - y0, x1 - x0)
+    cz, cy, cx = cshape
+
+    def cflat(x, y, z):
+        return (x - x0) + cx * ((y - y0) + cy * (z - z0))
+
+    v = inputs.layered_velocity(shape, seed=1)
+    vc = np.ascontiguousarray(v[z0:z1, y0:y1, x0:x1])
+    src_c = cflat(sx, sy, sz)
+    rcv_c = np.array([cflat(x, y, 2) for x, y in rcv_xy], np.int64)
+    # observations: the oracle's records for a 2 % faster model, on the crop
+    _, obs = O.wave_forward_states(w_of((vc * np.float32(1.02)).astype(np.float32), c), steps, (amps, src_c), rcv_c,
+                                   dtype=np.float32)
+    obs = obs.astype(np.float32)
+
+    print(f"full-size gradient: 512^3, {steps} steps, checkpoints every {every} at rate {rate}, crop {cshape}",
+          flush=True)
+    prob = api.WaveProblem(shape, steps, amps, (sx, sy, sz), rcv, obs, float(c), ckpt_every=every, ckpt_rate=rate)
+    vd = torch.from_numpy(v).to(DEV)
+    J = prob.forward(vd)
+    g = prob.gradient(vd)
+    res_gpu = prob.res.cpu().numpy()
+    gc = g[z0:z1, y0:y1, x0:x1].cpu().numpy()
+    g[z0:z1, y0:y1, x0:x1] = 0
+    outside_nonzero = int(torch.count_nonzero(g))
+    del prob, g, vd
+    torch.cuda.empty_cache()
+
+    w32 = w_of(vc, c)
+    states, rec = O.wave_forward_states(w32, steps, (amps, src_c), rcv_c, dtype=np.float32)
+    res = (rec - obs).astype(np.float32)
+    assert np.array_equal(res_gpu, res)
+    assert J == pytest.approx(0.5 * float(np.sum(res.astype(np.float64) ** 2)), rel=1e-12)
+    if rate:
+        recomputed = np.zeros_like(states)
+        for t0 in range(0, steps, every):
+            p = O.codec_roundtrip(states[t0], rate)
+            pm = O.codec_roundtrip(states[t0 - 1] if t0 > 0 else np.zeros(cshape, np.float32), rate)
+            for t in range(t0, min(steps, t0 + every)):
+                p, pm = O.wave25_f32(p, pm, w32, 1, src=(amps[t:t + 1], src_c))
+                recomputed[t + 1] = p
+        states = recomputed
+    gw, _ = O.wave_adjoint(w32, steps, rcv_c, res, states, dtype=np.float32)
+    gv = (gw * ((np.float32(2.0) * vc) * (c * c))).astype(np.float32)
+    assert np.count_nonzero(gv) > 1000  # the cones overlap: a real gradient, not zeros on both sides
+    assert outside_nonzero == 0
+    assert np.array_equal(gc, gv)
