@@ -616,19 +616,25 @@ __global__ void rcv_sample_kernel(const float* p, const int64_t* rcv, int nr, co
     }
 }
 
-// lam[rcv[i]] += res[i], receivers in order (one thread: receivers may share a
-// cell), and wl = w * lam refreshed at each touched cell
+// lam[rcv[i]] += res[i] for i = 0, 1, ... in order, and wl = w * lam at each
+// touched cell. Receivers may share a cell: one thread per receiver, and the
+// first receiver at a cell owns it and adds the residuals of every receiver
+// there in index order (the same FP32 sums as the sequential loop); the
+// others return. Each scan is over nr indexes, read from cache.
 __global__ void rcv_inject_kernel(float* lam, float* wl, const float* w, const int64_t* rcv, int nr, const float* res,
                                   int64_t n)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int i = 0; i < nr; ++i) {
-            const int64_t r = rcv[i];
-            if (r >= 0 && r < n) {
-                lam[r] = lam[r] + res[i];
-                wl[r] = w[r] * lam[r];
-            }
-        }
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= nr) return;
+    const int64_t r = rcv[i];
+    if (r < 0 || r >= n) return;
+    for (int j = 0; j < i; ++j)
+        if (rcv[j] == r) return;
+    float l = lam[r];
+    for (int j = i; j < nr; ++j)
+        if (rcv[j] == r) l = l + res[j];
+    lam[r] = l;
+    wl[r] = w[r] * l;
 }
 
 hipError_t launch_rcv_sample(const float* p, const int64_t* rcv, int nr, const float* obs, float* res, int64_t n,
@@ -643,7 +649,8 @@ hipError_t launch_rcv_inject(float* lam, float* wl, const float* w, const int64_
                              int64_t n, hipStream_t s)
 {
     if (nr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(rcv_inject_kernel, dim3(1), dim3(64), 0, s, lam, wl, w, rcv, nr, res, n);
+    hipLaunchKernelGGL(rcv_inject_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, lam, wl, w, rcv, nr,
+                       res, n);
     return hipGetLastError();
 }
 
