@@ -117,6 +117,38 @@ int time_cfg(const oocs_domain& d, float alpha, int cfg, hipStream_t s, float* m
     return OOCS_OK;
 }
 
+// Time one launch over a whole work list (the batch step at parity 0 reads
+// every domain's field and writes its scratch buffer): median of 3 timed
+// launches after one warm-up. The list is uploaded to the first nd entries
+// of the device table, which the caller rewrites afterwards.
+int time_batch(oocs::BatchDomain* d_table, const std::vector<oocs::BatchDomain>& tab, int32_t total, size_t lds,
+               float alpha, hipStream_t s, float* ms_out)
+{
+    const int nd = (int)tab.size();
+    HIP_TRY(hipMemcpyAsync(d_table, tab.data(), nd * sizeof(oocs::BatchDomain), hipMemcpyHostToDevice, s));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));  // timing only
+    HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+    std::vector<float> t;
+    int rc = OOCS_OK;
+    for (int r = 0; r < 4 && rc == OOCS_OK; ++r) {
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = oocs::launch_batch_step(d_table, nd, total, lds, 0, alpha, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) rc = oocs::hip_fail(e, "tuning launch");
+        if (r > 0) t.push_back(ms);  // first launch warms up
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    std::sort(t.begin(), t.end());
+    *ms_out = t[t.size() / 2];
+    return OOCS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -187,9 +219,44 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
         }
     }
     if (cache_dirty) write_cache(tune_cache, cache);
-    // depth: the forced one, else the one with the least estimated time per step
+    // work list of every domain at depth dk, with its workgroup total and LDS
+    auto build_table = [&](int dk, std::vector<oocs::BatchDomain>& tab, int32_t& total, size_t& lds) -> int {
+        total = 0;
+        lds = 0;
+        tab.resize(nd);
+        for (int i = 0; i < nd; ++i) {
+            oocs::BatchDomain& e = tab[i];
+            e.a = doms[i].d_u;
+            e.b = doms[i].d_scratch;
+            e.nx = (int32_t)doms[i].nx; e.ny = (int32_t)doms[i].ny; e.nz = (int32_t)doms[i].nz;
+            e.cfg = best[{bucket_of(doms[i]), dk}].first;
+            e.wg_begin = total;
+            e.pad = 0;
+            const int64_t wgs = oocs::batch_domain_workgroups(e.nx, e.ny, e.nz, e.cfg);
+            if (total + wgs > INT32_MAX / 2) return fail(OOCS_E_ARG, "batch too large for one launch");
+            total += (int32_t)wgs;
+            lds = std::max(lds, oocs::tile_cfg_lds(e.cfg));
+        }
+        return OOCS_OK;
+    };
+    // depth: the forced one; else, when tuning, the one whose launch over the
+    // whole batch (every domain's field read, only its scratch buffer
+    // written) takes the least time per step; else the least estimated time
     b->depth = depths[0];
-    if (!depth) {
+    if (!depth && tune) {
+        double best_t = -1;
+        for (int dk : depths) {
+            std::vector<oocs::BatchDomain> tab;
+            int32_t total;
+            size_t lds;
+            int rc = build_table(dk, tab, total, lds);
+            float ms = 0;
+            if (!rc) rc = time_batch(b->d_table, tab, total, lds, alpha, s, &ms);
+            if (rc) { delete b; return rc; }
+            const double t = (double)ms / dk;
+            if (best_t < 0 || t < best_t) { best_t = t; b->depth = dk; }
+        }
+    } else if (!depth) {
         double best_t = -1;
         for (int dk : depths) {
             double t = 0;
@@ -205,23 +272,8 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
         if (best_t < 0) b->depth = 1;
     }
     for (int w = 0; w < 2; ++w) {
-        const int dk = w == 0 ? b->depth : 1;
-        int32_t total = 0;
-        b->table[w].resize(nd);
-        for (int i = 0; i < nd; ++i) {
-            oocs::BatchDomain& e = b->table[w][i];
-            e.a = doms[i].d_u;
-            e.b = doms[i].d_scratch;
-            e.nx = (int32_t)doms[i].nx; e.ny = (int32_t)doms[i].ny; e.nz = (int32_t)doms[i].nz;
-            e.cfg = best[{bucket_of(doms[i]), dk}].first;
-            e.wg_begin = total;
-            e.pad = 0;
-            const int64_t wgs = oocs::batch_domain_workgroups(e.nx, e.ny, e.nz, e.cfg);
-            if (total + wgs > INT32_MAX / 2) { delete b; return fail(OOCS_E_ARG, "batch too large for one launch"); }
-            total += (int32_t)wgs;
-            b->lds[w] = std::max(b->lds[w], oocs::tile_cfg_lds(e.cfg));
-        }
-        b->total_wg[w] = total;
+        const int rc = build_table(w == 0 ? b->depth : 1, b->table[w], b->total_wg[w], b->lds[w]);
+        if (rc) { delete b; return rc; }
     }
     hipError_t e = hipMemcpyAsync(b->d_table, b->table[0].data(), nd * sizeof(oocs::BatchDomain), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
