@@ -1,6 +1,7 @@
 // batch.cpp -- batched in-core heat domains: work-list tables, autotuner of
-// the tile shape (per size bucket) and of the temporal-blocking depth (per
-// batch) with a cache file, graph of batched launches, per-domain baseline.
+// the tile shape (per size bucket, timed on the bucket's largest domain, with
+// a cache file) and of the temporal-blocking depth (per batch, timed on one
+// launch over all domains), graph of batched launches, per-domain baseline.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
