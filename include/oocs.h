@@ -394,8 +394,8 @@ int oocs_run(oocs_plan* plan, void* const* h_store, int64_t steps, const float* 
  * launches of a run are replayed as one HIP graph. k > 1 is temporal
  * blocking: a workgroup advances its tile k steps in one pass over z,
  * recomputing a k-cell halo, so each cell crosses HBM once per k steps.
- * The tile shape is chosen per size bucket and the depth k (1, 2 or 4) per
- * batch by a timing autotuner whose results persist in a cache file.
+ * The tile shape is chosen per size bucket by a timing autotuner whose
+ * results persist in a cache file, and the depth k (1, 2 or 4) per batch.
  * ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -414,8 +414,11 @@ size_t oocs_batch_table_bytes(int nd);
  * tune: 1 = time the tile candidates of every depth on this GPU for every
  * size bucket not found in the cache (the domains' own u buffers are read,
  * their scratch buffers written; states are unchanged), 0 = use the cache,
- * else the default tiles. depth: 0 = the depth with the least estimated
- * time per step (timed or cached; 1 if unknown), or 1, 2, 4 to force it.
+ * else the default tiles. depth: 0 = with tune = 1, the depth whose launch
+ * over the whole batch (same buffers as above) takes the least time per
+ * step; with tune = 0, the least time per step estimated from the cached
+ * single-domain timings (1 if unknown); or 1, 2, 4 to force it. Every depth
+ * gives the same bits.
  * tune_cache: path of the cache file (NULL = no cache). The caller keeps the
  * domain buffers and d_table alive until destroy.
  * Errors: OOCS_E_ARG, OOCS_E_SIZE, OOCS_E_HIP. */
