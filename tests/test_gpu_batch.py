@@ -88,3 +88,22 @@ def test_full_size_batched_workload(tmp_path):
     s = int(sides[j])
     want = O.heat7_f32(inputs.heat_uniform((s, s, s), seed=3 + j), 0.1, 200)
     assert np.array_equal(fields[j].cpu().numpy(), want)
+
+
+def test_tuning_leaves_the_states_unchanged(tmp_path):
+    """Creating a batch with tuning times tile candidates on single domains
+    and one launch per depth over the whole batch; those launches write only
+    the scratch buffers, so every domain's state is what the caller put in,
+    and a run afterwards equals the oracle."""
+    shapes = [(40, 36, 64), (17, 9, 33), (64, 64, 64), (1, 1, 1), (30, 70, 20)]
+    u0 = [inputs.heat_uniform(s, seed=20 + i) for i, s in enumerate(shapes)]
+    fields = [torch.from_numpy(u).to(DEV) for u in u0]
+    b = api.HeatBatch(fields, alpha=0.1, tune=True, tune_cache=str(tmp_path / "tune.json"))
+    torch.cuda.synchronize()
+    assert b.depth in (1, 2, 4)
+    for u, f in zip(u0, fields):
+        assert np.array_equal(f.cpu().numpy(), u)
+    b.run(6)
+    torch.cuda.synchronize()
+    for u, f in zip(u0, fields):
+        assert np.array_equal(f.cpu().numpy(), O.heat7_f32(u, 0.1, 6))
