@@ -95,9 +95,13 @@ void write_cache(const char* path, const std::map<std::string, int>& m)
 // the configuration's k steps).
 int time_cfg(const oocs_domain& d, float alpha, int cfg, hipStream_t s, float* ms_out)
 {
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));  // timing only
-    HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t ce = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);  // timing only
+    if (ce == hipSuccess) ce = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+    if (ce != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return oocs::hip_fail(ce, "tuning events");
+    }
     std::vector<float> t;
     int rc = OOCS_OK;
     for (int r = 0; r < 4 && rc == OOCS_OK; ++r) {
@@ -127,9 +131,14 @@ int time_batch(oocs::BatchDomain* d_table, const std::vector<oocs::BatchDomain>&
 {
     const int nd = (int)tab.size();
     HIP_TRY(hipMemcpyAsync(d_table, tab.data(), nd * sizeof(oocs::BatchDomain), hipMemcpyHostToDevice, s));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));  // timing only
-    HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+    HIP_TRY(hipStreamSynchronize(s));  // the host list may go away on return
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t ce = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);  // timing only
+    if (ce == hipSuccess) ce = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+    if (ce != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return oocs::hip_fail(ce, "tuning events");
+    }
     std::vector<float> t;
     int rc = OOCS_OK;
     for (int r = 0; r < 4 && rc == OOCS_OK; ++r) {
