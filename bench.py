@@ -140,8 +140,15 @@ def link_probe(api, sdma, chunk):
                           sdma=sdma)
 
 
+def in_core_launches(steps):
+    """Launches of the in-core heat step: four blocked steps per launch, the
+    remainder one level each."""
+    return steps // 4 + steps % 4
+
+
 def in_core_rate(api, torch, u0):
-    """Same heat kernel on the whole field resident in HBM (no cap), for context."""
+    """The in-core heat step on the whole field resident in HBM (no cap), for
+    context: GCell-updates/s (each launch reads and writes the field once)."""
     u = torch.from_numpy(u0).cuda()
     tmp = torch.empty_like(u)
     api.heat7_step_k(u, ALPHA, 4, tmp=tmp)
@@ -151,6 +158,17 @@ def in_core_rate(api, torch, u0):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return SHAPE[0] * SHAPE[1] * SHAPE[2] * TIME_STEPS / dt / 1e9
+
+
+def small_in_core(api, torch, inputs, reps=200):
+    """The in-core step at its own small size: 10 heat steps of a 64^3
+    field (1 MiB), one call per 10 steps, averaged over reps calls."""
+    u = torch.from_numpy(inputs.heat_uniform((64, 64, 64), seed=5)).cuda()
+    tmp = torch.empty_like(u)
+    api.heat7_step_k(u, ALPHA, 10, tmp=tmp)
+    t = _timed(torch, lambda: api.heat7_step_k(u, ALPHA, 10, tmp=tmp), reps=reps)
+    return {"grid": [64, 64, 64], "steps": 10, "us_per_call": round(t * 1e6, 1),
+            "gcells_per_s": round(64 ** 3 * 10 / t / 1e9, 2), "calls": reps}
 
 
 def _timed(torch, fn, reps=1):
@@ -405,6 +423,8 @@ def main():
     link_hip = link_probe(api, False, copy_bytes) if args.sdma else None
     extras = {}
     if not args.no_extras:
+        extras["in_core_64"] = small_in_core(api, torch, inputs)
+        print(f"# in-core 64^3: {extras['in_core_64']}", file=sys.stderr, flush=True)
         extras["codec_512"] = codec_rates(api, torch, u0)
         print(f"# codec: {extras['codec_512']}", file=sys.stderr, flush=True)
         extras["batched_heat"] = batched_rate(api, torch, inputs)
@@ -439,7 +459,7 @@ def main():
         "speedup_vs_uncompressed": round(head["gcells_per_s"] / raw["gcells_per_s"], 3) if raw else None,
         "variants": {("uncompressed" if r == 0 else f"rate{r}"): _rounded(res) for r, res in results.items()},
         "in_core_gcells_per_s": round(incore, 1),
-        "in_core_hbm_frac": round(incore * 8 / HBM_PEAK_GBS, 4),
+        "in_core_hbm_frac": round(incore * 8 * in_core_launches(TIME_STEPS) / TIME_STEPS / HBM_PEAK_GBS, 4),
         "other_workloads": extras,
         "host_link": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in link.items()},
         "host_link_d2h_hipMemcpyAsync": ({k: (round(v, 2) if isinstance(v, float) else v) for k, v in link_hip.items()}

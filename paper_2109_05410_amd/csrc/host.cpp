@@ -183,7 +183,29 @@ int oocs_heat7_step_k(float* d_u, float* d_tmp, int64_t nx, int64_t ny, int64_t 
     hipStream_t s = (hipStream_t)stream;
     float* a = d_u;
     float* b = d_tmp;
-    for (int64_t t = 0; t < k; ++t) {
+    // Four steps per launch with the temporally blocked tiles (each cell and
+    // step takes the same FP32 operations as a single level, so the bits are
+    // the same) when the field gives at least 4 workgroups per compute unit
+    // (a blocked workgroup marches its z chunk serially, so on small fields
+    // the one-level launches are quicker), the launch's work-items fit the
+    // dispatch's 32-bit grid and the cell count the tiles' 32-bit indexes;
+    // the remaining k mod 4 steps, and every step otherwise, one level per
+    // launch.
+    int tb = -1;
+    for (int c = 0; c < oocs::kNumTileCfgs; ++c)
+        if (oocs::kTileCfgs[c].k == 4) tb = c;
+    int64_t t = 0;
+    if (tb >= 0 && k >= 4) {
+        const oocs::TileCfg& c = oocs::kTileCfgs[tb];
+        const int64_t ox = c.tx - 2 * c.k, oy = c.ty - 2 * c.k;
+        const int64_t wgs = ((nx + ox - 1) / ox) * ((ny + oy - 1) / oy) * ((nz + c.zc - 1) / c.zc);
+        if (wgs >= 4 * 256 && wgs * oocs::kBlockThreads < ((int64_t)1 << 32) && nx * ny * nz < ((int64_t)1 << 31))
+            for (; t + 4 <= k; t += 4) {
+                HIP_TRY(oocs::launch_heat_dense(a, b, (int)nx, (int)ny, (int)nz, alpha, tb, s));
+                std::swap(a, b);
+            }
+    }
+    for (; t < k; ++t) {
         oocs::LaunchParams p = base_params(nx, ny, nz, alpha, -1, -1, -1);
         oocs::Job& j = p.jobs[0];
         j.kind = oocs::JOB_HEAT;

@@ -28,6 +28,40 @@ def test_heat_matches_oracle(shape, k):
         assert max_rel(got, O.heat7_f64(u0.astype(np.float64), 0.1, k)) <= 1e-5
 
 
+@pytest.mark.parametrize("k", [6, 9])
+def test_heat_blocked_launches_match_oracle(k):
+    """A field large enough for the in-core step to take four steps per
+    launch with the blocked tiles (over 1024 workgroups), ragged against the
+    tiles in every axis; the remainder k mod 4 runs one level per launch."""
+    shape = (100, 509, 452)
+    u0 = inputs.heat_uniform(shape, seed=11)
+    u = torch.from_numpy(u0).to(DEV)
+    api.heat7_step_k(u, 0.1, k)
+    assert np.array_equal(u.cpu().numpy(), O.heat7_f32(u0, 0.1, k))
+
+
+def test_heat_full_size_sampled_cells():
+    """The in-core step on the 512^3 field (blocked launches), 8 steps, at
+    sampled cells: after k steps a cell depends only on the cells within k
+    of it, so the oracle on the crop of radius k around it (clipped at the
+    domain, whose zero ghosts both sides share) gives its exact value."""
+    n, k = 512, 8
+    u0 = inputs.heat_uniform((n, n, n), seed=12)
+    u = torch.from_numpy(u0).to(DEV)
+    api.heat7_step_k(u, 0.1, k)
+    got = u.cpu().numpy()
+    rng = np.random.default_rng(3)
+    pts = [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(56)]
+    pts += [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 3), (n - 1, 0, n - 2), (63, 64, 55), (64, 7, 56),
+            (255, 256, 111), (k, n - 1 - k, 200)]
+    for z, y, x in pts:
+        lo = [max(0, c - k) for c in (z, y, x)]
+        hi = [min(n, c + k + 1) for c in (z, y, x)]
+        crop = np.ascontiguousarray(u0[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]])
+        want = O.heat7_f32(crop, 0.1, k)[z - lo[0], y - lo[1], x - lo[2]]
+        assert got[z, y, x] == want, (z, y, x)
+
+
 def test_heat_eigenmode_decay():
     shape = (40, 24, 32)
     u0 = inputs.heat_eigenmode(shape, (1, 2, 1))
