@@ -124,7 +124,8 @@ int oocs_codec_decode_stages(const uint64_t* d_words, int64_t nblocks, int rate,
  * scratch of the same size; both 16-byte aligned. The result is left in
  * d_u. FP32, fixed operation order, no fused multiply-add. Fields that
  * give a launch of at least 1024 workgroups take four steps per launch in
- * temporally blocked tiles (same bits as one step per launch).
+ * temporally blocked tiles, fields of up to 2^21 cells one step per launch
+ * in 8-plane chunks (same bits either way).
  * Errors: OOCS_E_ARG, OOCS_E_ALIGN, OOCS_E_HIP. */
 int oocs_heat7_step_k(float* d_u, float* d_tmp, int64_t nx, int64_t ny, int64_t nz, float alpha, int64_t k,
                       void* stream);

@@ -205,6 +205,18 @@ int oocs_heat7_step_k(float* d_u, float* d_tmp, int64_t nx, int64_t ny, int64_t 
                 std::swap(a, b);
             }
     }
+    // Small fields (up to 2^21 cells) one level per launch in short z chunks
+    // (8 planes per workgroup): more workgroups, each with a shorter serial
+    // march, than the level job's chunks.
+    int small = -1;
+    if (nx * ny * nz <= ((int64_t)1 << 21))
+        for (int c = 0; c < oocs::kNumTileCfgs; ++c)
+            if (oocs::kTileCfgs[c].k == 1 && oocs::kTileCfgs[c].tx == 64 && oocs::kTileCfgs[c].zc == 8) small = c;
+    if (small >= 0)
+        for (; t < k; ++t) {
+            HIP_TRY(oocs::launch_heat_dense(a, b, (int)nx, (int)ny, (int)nz, alpha, small, s));
+            std::swap(a, b);
+        }
     for (; t < k; ++t) {
         oocs::LaunchParams p = base_params(nx, ny, nz, alpha, -1, -1, -1);
         oocs::Job& j = p.jobs[0];
