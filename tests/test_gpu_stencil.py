@@ -17,8 +17,10 @@ def max_rel(a, b):
 
 
 @pytest.mark.parametrize("shape,k", [((64, 64, 64), 10), ((9, 13, 68), 5), ((5, 4, 4), 1), ((12, 8, 132), 0),
-                                     ((33, 17, 64), 7)])
+                                     ((33, 17, 64), 7), ((40, 200, 300), 5)])
 def test_heat_matches_oracle(shape, k):
+    """Small fields take the short-chunk one-level launches; the last shape
+    (over 2^21 cells, too few workgroups for blocked launches) the level job."""
     u0 = inputs.heat_uniform(shape, seed=0)
     u = torch.from_numpy(u0).to(DEV)
     api.heat7_step_k(u, 0.1, k)
