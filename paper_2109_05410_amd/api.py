@@ -107,9 +107,23 @@ def codec_decode_stages(words: torch.Tensor, rate: int) -> dict:
 # ---------------------------------------------------------------------------
 
 def heat7_step_k(u: torch.Tensor, alpha: float, k: int, tmp: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """k heat steps in place on u. tmp: scratch of u's shape on u's device,
+    not overlapping u (allocated here if None)."""
     nx, ny, nz = _field(u, "u")
     if tmp is None:
         tmp = torch.empty_like(u)
+    else:
+        _field(tmp, "tmp")
+        if tmp.shape != u.shape or tmp.device != u.device:
+            raise ValueError("tmp must have u's shape and device")
+        ua, ta = u.data_ptr(), tmp.data_ptr()
+        nb = u.numel() * 4
+        if ua < ta + nb and ta < ua + nb:
+            raise ValueError("tmp must not overlap u")
+    if stream is not None:
+        # the kernels on `stream` use tmp after this call returns: keep the
+        # caching allocator from handing its block out before they finish
+        tmp.record_stream(stream)
     L.check(L.lib().oocs_heat7_step_k(_dptr(u), _dptr(tmp), nx, ny, nz, C.c_float(alpha), k, _stream_ptr(stream)))
     return u
 
@@ -356,6 +370,10 @@ class WaveProblem:
             L.check(L.OOCS_E_ARG)
         self.work = torch.empty(wb, dtype=torch.uint8, device=device)
         self.ckpt = torch.empty(int(L.lib().oocs_adjoint_ckpt_bytes(C.byref(c))), dtype=torch.uint8, pin_memory=True)
+        # forward() overwrites the one checkpoint store and residual buffer:
+        # each call gets a new generation, and a gradient is only valid for
+        # the generation it was taken from
+        self.generation = 0
 
     def _common(self, v):
         _field(v, "v")
@@ -364,13 +382,19 @@ class WaveProblem:
     def forward(self, v: torch.Tensor) -> float:
         J = C.c_double()
         cfg, pv, ps, pr = self._common(v)
+        self.generation += 1  # the store is being overwritten: earlier generations are stale from here on
         L.check(L.lib().oocs_wave_forward_ckpt(cfg, pv, ps, pr, _dptr(self.obs), _dptr(self.res), _dptr(self.work),
                                                self.work.numel(), C.c_void_p(self.ckpt.data_ptr()), C.byref(J),
                                                _stream_ptr()))
         return J.value
 
-    def gradient(self, v: torch.Tensor) -> torch.Tensor:
-        """dJ/dv for the checkpoints of the last forward() call."""
+    def gradient(self, v: torch.Tensor, generation: int | None = None) -> torch.Tensor:
+        """dJ/dv for the checkpoints of the last forward() call. generation:
+        the value of self.generation right after the forward() whose
+        gradient is wanted; a later forward() makes it stale (error)."""
+        if generation is not None and generation != self.generation:
+            raise RuntimeError(f"stale gradient request: the checkpoints of forward #{generation} were overwritten "
+                               f"by forward #{self.generation} on the same WaveProblem")
         g = torch.empty_like(v)
         cfg, pv, ps, pr = self._common(v)
         L.check(L.lib().oocs_wave_adjoint(cfg, pv, ps, pr, _dptr(self.res), _dptr(self.work), self.work.numel(),
@@ -387,13 +411,14 @@ class WaveMisfit(torch.autograd.Function):
         v = v.detach().contiguous()
         J = problem.forward(v)
         ctx.problem = problem
+        ctx.generation = problem.generation
         ctx.save_for_backward(v)
         return torch.tensor(J, dtype=torch.float64, device=v.device)
 
     @staticmethod
     def backward(ctx, gJ):
         (v,) = ctx.saved_tensors
-        g = ctx.problem.gradient(v)
+        g = ctx.problem.gradient(v, generation=ctx.generation)
         return (g * gJ.to(g.dtype)), None
 
 

@@ -74,6 +74,19 @@ def source_cell(shape, depth: int = 16):
     return (nx // 2, ny // 2, min(depth, nz - 1))
 
 
+def sample_points(shape, per_plane: int = 100, seed: int = 0) -> np.ndarray:
+    """Flat indices (into a (nz, ny, nx) field) of `per_plane` distinct seeded
+    cells in every z-plane, plane after plane (all of a plane's cells if it
+    has fewer). The sampling recipe of the point-wise error: 100 cells per
+    plane (Sec. VI-C)."""
+    nz, ny, nx = shape
+    n = nx * ny
+    k = min(per_plane, n)
+    rng = np.random.default_rng(seed)
+    ij = np.stack([rng.choice(n, k, replace=False) for _ in range(nz)]) if nz > 0 else np.zeros((0, k), np.int64)
+    return (np.arange(nz, dtype=np.int64)[:, None] * n + ij).reshape(-1)
+
+
 def batch_sides(n: int = 64, lo: int = 64, hi: int = 384, seed: int = 2) -> np.ndarray:
     """Cube sides of the batched heat domains, uniform in [lo, hi]."""
     return np.random.default_rng(seed).integers(lo, hi + 1, n)

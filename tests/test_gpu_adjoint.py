@@ -155,6 +155,27 @@ def test_autograd_function():
     assert (Jp - Jm) / 2 == pytest.approx(pred, rel=1e-2)
 
 
+def test_backward_after_a_later_forward_is_refused():
+    """The problem holds one checkpoint store: a second forward (a line
+    search evaluating J again) overwrites it, so backing through the first
+    graph must raise instead of returning the second model's gradient."""
+    shape = (16, 16, 16)
+    steps = 12
+    v, v_true, c, amps, cell, src_idx, rcv = problem_inputs(shape, steps)
+    _, obs = O.wave_forward_states(w_of(v_true, c), steps, (amps, src_idx), rcv, dtype=np.float32)
+    prob = api.WaveProblem(shape, steps, amps, cell, rcv, obs, float(c), ckpt_every=4)
+    va = torch.from_numpy(v).to(DEV).requires_grad_(True)
+    vb = (torch.from_numpy(v).to(DEV) * 1.01).requires_grad_(True)
+    Ja = api.WaveMisfit.apply(va, prob)
+    Jb = api.WaveMisfit.apply(vb, prob)
+    with pytest.raises(RuntimeError, match="stale"):
+        Ja.backward()
+    Jb.backward()  # the latest forward is still valid
+    ref = api.WaveProblem(shape, steps, amps, cell, rcv, obs, float(c), ckpt_every=4)
+    ref.forward(vb.detach())
+    assert torch.equal(vb.grad, ref.gradient(vb.detach()))
+
+
 def _crop_bounds(center, reach, n):
     """[lo, hi) along one axis covering center +- reach, widened to multiples
     of 4 (whole codec blocks) and clipped to the domain."""

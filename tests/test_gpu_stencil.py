@@ -113,3 +113,23 @@ def test_wave_layered_model_ricker_source():
     assert np.array_equal(p.cpu().numpy(), want_p)
     ref_p, _ = O.wave25_f64(z0, z0, w, 60, src=(amps, idx))
     assert max_rel(p.cpu().numpy(), ref_p) <= 1e-5
+
+
+def test_heat_scratch_argument_checks():
+    """A caller-supplied scratch must match u and must not overlap it; with
+    a side stream the result is the same as on the current stream."""
+    u0 = inputs.heat_uniform((16, 16, 16), seed=2)
+    u = torch.from_numpy(u0).to(DEV)
+    with pytest.raises(ValueError):
+        api.heat7_step_k(u, 0.1, 3, tmp=torch.empty((16, 16, 12), device=DEV))
+    with pytest.raises(ValueError):
+        api.heat7_step_k(u, 0.1, 3, tmp=u)
+    big = torch.empty((2, 16, 16, 16), device=DEV)
+    big[0].copy_(u)
+    with pytest.raises(ValueError):
+        api.heat7_step_k(big[0], 0.1, 3, tmp=big.view(-1)[8:8 + u.numel()].view(16, 16, 16))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    api.heat7_step_k(u, 0.1, 3, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    assert np.array_equal(u.cpu().numpy(), O.heat7_f32(u0, 0.1, 3))

@@ -176,3 +176,52 @@ def test_error_metrics():
     assert e["max_rel"] == pytest.approx(0.25)
     assert e["l2_rel"] == pytest.approx(0.5 / np.sqrt(63 + 4))
     assert O.errors(ref, ref)["pointwise_mean_rel"] == 0.0
+
+
+def test_sample_points_layout_without_replacement():
+    """Sec. VI-C samples a fixed number of points in every plane: each plane
+    gets exactly per_plane distinct cells of its own, and asking for the
+    whole plane returns every cell of it once."""
+    shape = (6, 5, 4)
+    full = O.sample_points(shape, per_plane=20, seed=3).reshape(6, 20)
+    for z in range(6):
+        assert sorted(full[z].tolist()) == list(range(20 * z, 20 * z + 20))
+    part = O.sample_points(shape, per_plane=7, seed=4).reshape(6, 7)
+    for z in range(6):
+        assert len(set(part[z].tolist())) == 7
+        assert all(20 * z <= i < 20 * z + 20 for i in part[z])
+    # 100 per plane on a large plane: still distinct
+    big = O.sample_points((3, 64, 64), per_plane=100, seed=0).reshape(3, 100)
+    assert all(len(set(r.tolist())) == 100 for r in big)
+
+
+def test_pointwise_mean_hand_computed():
+    """A field whose relative error is a known constant e_z on each plane
+    z: the point-wise mean is the plain average of the e_z (equal counts
+    per plane), measured against |ref| (against |a| it would be the
+    average of e/(1+e)); planes whose reference is at most 1e-30 of the
+    largest magnitude are left out, one just above that is kept."""
+    nz, ny, nx = 6, 8, 8
+    rng = np.random.default_rng(11)
+    ref = rng.uniform(0.5, 1.0, (nz, ny, nx))
+    ref[0, 0, 0] = 1.0                       # largest magnitude
+    ref[2] = 1e-31                            # skipped: <= 1e-30 * max
+    ref[3] = -2e-30                           # kept (negative: |ref| is the divisor)
+    e = np.array([0.01, 0.02, 0.5, 0.04, 0.05, 0.06])
+    a = ref * (1.0 + e)[:, None, None]
+    r = O.errors(a, ref, per_plane=10, seed=5)
+    kept = [0, 1, 3, 4, 5]
+    assert r["sampled_points"] == 60
+    assert r["sampled_used"] == 50
+    assert r["pointwise_mean_rel"] == pytest.approx(e[kept].mean(), rel=1e-12)
+    assert abs(r["pointwise_mean_rel"] - (e[kept] / (1 + e[kept])).mean()) > 1e-4
+    # normwise figures of the same field, written out
+    d = a - ref
+    assert r["max_rel"] == pytest.approx(np.abs(d).max() / 1.0, rel=1e-12)
+    assert r["l2_rel"] == pytest.approx(np.sqrt((d ** 2).sum() / (ref ** 2).sum()), rel=1e-12)
+    # one plane with a larger error moves the mean by (its change) / (planes kept)
+    a2 = a.copy()
+    a2[4] = ref[4] * 1.25
+    r2 = O.errors(a2, ref, per_plane=10, seed=5)
+    assert r2["pointwise_mean_rel"] - r["pointwise_mean_rel"] == pytest.approx((0.25 - 0.05) / 5, rel=1e-9)
+
