@@ -1,18 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the out-of-core compressed stencil pipeline on one MI355X.
 
-Workload: 7-point Jacobi heat (alpha = 0.1) on a 512^3 FP32 grid (512 MiB),
-uniform [0, 1) initial field from seed 0, split into 8 z-slabs of 64 planes,
-k = 4 steps per residency (halo 4 planes), device memory capped at two slabs
-(a 128 MiB arena). The field lives in a pinned host store; every residency
-streams it through the GPU (decode, 4 steps, encode) and back. One bench
-step = 100 time steps = 25 residencies over the whole grid.
+Headline workload: the 25-point 8th-order acoustic wave (two read-write
+fields p(n), p(n-1) and the read-only w = (v dt/dx)^2) on a 1024^3 FP32 grid
+(4 GiB per field), layered velocity model 1500..4500 m/s, 15 Hz Ricker point
+source, dt at CFL 0.4; split into 8 z-slabs of 128 planes, k = 12 steps per
+residency (halo 48 planes), device memory capped at an 8 GiB arena; all three
+fields in pinned host stores, compressed at 12 bits per value (37.5 % of the
+bits, the paper's 24/64 ratio for doubles), against the same pipeline
+uncompressed and at 8 and 16 bits per value.
 
-Reported: end-to-end GCell-updates/s of the compressed pipeline at 8 bits
-per value (the headline), next to 16 bits per value and the uncompressed
-pipeline under the same cap; the fused pipeline kernel's achieved
-algorithmic bandwidth against the HBM peak; effective host-link rates; and
-the CPU oracle timed on a bounded sample of the same workload.
+One bench step = one round of the method: every block of the grid advanced
+k = 12 steps (12 * 1024^3 cell updates), all transfers included. The timed
+rounds start from the developed wavefield of the middle of the 4,320-step
+run (step 2,160, made by an in-core GPU run of the same propagator): the
+codec's cost depends on the data, and the middle of the run is its average.
+
+Reported besides: the other rates, the paper's codes 2-4 (which fields are
+compressed), the per-block schedule of Fig. 2 (halo recompute), the
+per-stage breakdown (Sec. VI-B), the whole 4,320-step run per rate with the
+Sec. VI-C errors against the uncompressed run every 480 steps, the fused
+pipeline kernel against the HBM and VALU rooflines, the host link, the
+512^3 heat workload and the other rows' workloads, and the CPU oracle on a
+bounded sample of the headline workload.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -28,22 +38,42 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-SHAPE = (512, 512, 512)
-NSLABS = 8
-K = 4
-TIME_STEPS = 100
-CAP = 128 << 20
+T_START = time.perf_counter()
+
+# ---- headline: 1024^3 wave ------------------------------------------------------
+WAVE_SHAPE = (1024, 1024, 1024)
+WAVE_SLABS = 8
+WAVE_K = 12
+WAVE_CAP = 8 << 30
+WAVE_STEPS = 4320
+WAVE_START = 2160           # the timed rounds start here (middle of the run)
+WAVE_SEGMENT = 480          # error snapshots of the whole run every 480 steps
+HEADLINE_RATE = 12
+WAVE_RATES = (0, 16, 12, 8)
+FULL_RUN_RATES = (8, 12, 16)
+
+# ---- 512^3 heat (the other out-of-core workload) ----------------------------------
+HEAT_SHAPE = (512, 512, 512)
+HEAT_SLABS = 8
+HEAT_K = 4
+HEAT_TIME_STEPS = 100
+HEAT_CAP = 128 << 20
 ALPHA = 0.1
-HEADLINE_RATE = 8
-VARIANTS = (0, 16, 8)
+HEAT_RATES = (0, 16, 8)
+
 HBM_PEAK_GBS = 8000.0
 # VALU issue peak: 256 CUs x 64 lanes x 2.4 GHz (one wave64 VALU instruction
 # per CU per clock, packed FP32 not used)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 METRIC = "end-to-end GCell-updates/s, compressed vs uncompressed out-of-core; HBM GB/s %"
-COUNTERS = os.path.join(ROOT, "profiles", "heat512_rate8_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "wave1024_rate12_counters.json")
 KERNEL_SOURCES = ("paper_2109_05410_amd/csrc/kernels.hip", "paper_2109_05410_amd/csrc/codec_dev.hpp",
                   "paper_2109_05410_amd/csrc/stencil_dev.hpp", "paper_2109_05410_amd/csrc/internal.hpp")
+PROFILE_EVERY = 3
+
+
+def log(msg):
+    print(f"# [{time.perf_counter() - T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -56,9 +86,10 @@ def kernel_source_hash() -> str:
 
 def measured_counters(key):
     """Per-launch figures of each kernel ({kernel name: value}) from committed
-    rocprofv3 counter runs, if they were taken on the current kernel source;
-    else None. key: "hbm_bytes_per_launch" (FETCH_SIZE + WRITE_SIZE,
-    calibrated) or "alu_ops_per_launch" (SQ_INSTS_VALU x 64 lanes)."""
+    rocprofv3 counter runs of the headline workload, if they were taken on the
+    current kernel source; else None. key: "hbm_bytes_per_launch"
+    (FETCH_SIZE + WRITE_SIZE, calibrated) or "alu_ops_per_launch"
+    (SQ_INSTS_VALU x 64 lanes)."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -69,95 +100,272 @@ def measured_counters(key):
     return c.get(key)
 
 
-PROFILE_EVERY = 3  # time every 3rd launch: coprime with the 28 launches of a 512^3 residency
+def _rounded(x):
+    if isinstance(x, dict):
+        return {k: _rounded(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_rounded(v) for v in x]
+    return round(x, 3) if isinstance(x, float) else x
 
 
-def run_variant(api, torch, u0, rate, steps, warmup, graphs, kernel_transfers, sdma=True, profile=True):
-    """One rate of the 512^3 pipeline: `warmup` untimed runs, then `steps`
-    timed runs of TIME_STEPS steps. With `profile`, timing events around
-    every PROFILE_EVERY-th launch give the kernel statistics; without it the
-    run is timed by wall clock only (the events cost host time, which a
-    host-bound variant such as the uncompressed one would pay in throughput)."""
-    plan = api.OutOfCorePlan(SHAPE, api.HEAT7, NSLABS, K, [rate], CAP, alpha=ALPHA,
-                             kernel_transfers=kernel_transfers)
-    plan.set_graphs(graphs)
-    plan.set_sdma(sdma)
-    store = plan.new_store(0)
-    plan.put(0, u0, store)
-    for _ in range(warmup):
-        plan.run([store], TIME_STEPS)
-    plan.set_profiling(profile, every=PROFILE_EVERY)
+def _timed(torch, fn, reps=1):
+    """Wall time of fn() between device synchronizations (seconds per call)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = [plan.run([store], TIME_STEPS) for _ in range(steps)]
+    for _ in range(reps):
+        fn()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    plan.set_profiling(False)
-    info = plan.info
-    cells = SHAPE[0] * SHAPE[1] * SHAPE[2] * TIME_STEPS * steps
+    return (time.perf_counter() - t0) / reps
+
+
+def kernel_summary(stats, steps, profile):
+    """Launch statistics of a list of RunStats (per bench step)."""
     nl = sum(s.launches for s in stats)
-    cb = sum(s.codec_bytes for s in stats)
-    sb = sum(s.stencil_bytes for s in stats)
     kms = sum(s.kernel_ms for s in stats)
     tl = sum(s.timed_launches for s in stats)
     tb = sum(s.timed_bytes for s in stats)
-    h2d = sum(s.h2d_bytes for s in stats)
-    d2h = sum(s.d2h_bytes for s in stats)
-    sdma_copies = sum(s.sdma_copies for s in stats)
+    return {
+        "launches_per_step": nl // steps,
+        "codec_bytes_per_launch": sum(s.codec_bytes for s in stats) / max(nl, 1),
+        "stencil_bytes_per_launch": sum(s.stencil_bytes for s in stats) / max(nl, 1),
+        "bytes_per_launch": tb / max(tl, 1),
+        "timed_launches_per_step": tl // steps,
+        "avg_launch_us": kms * 1e3 / max(tl, 1) if profile and tl else None,
+        "achieved_GBps": tb / (kms * 1e-3) / 1e9 if kms > 0 else None,
+        "gpu_busy_frac": None,
+    }
+
+
+# ---------------------------------------------------------------------------
+# 1024^3 wave
+# ---------------------------------------------------------------------------
+
+class WaveInputs:
+    def __init__(self, inputs):
+        import numpy as np
+
+        self.dt = inputs.wave_dt()
+        self.w = inputs.wave_coefficient(inputs.layered_velocity(WAVE_SHAPE, seed=1), self.dt)
+        self.cell = inputs.source_cell(WAVE_SHAPE)
+        self.amps = inputs.ricker(WAVE_STEPS + 4096, self.dt)
+        self.zero = np.zeros(WAVE_SHAPE, np.float32)
+
+
+def wave_state(api, torch, wi, steps):
+    """(p(steps), p(steps - 1)) of the run from rest, by the in-core GPU
+    propagator (the uncompressed out-of-core pipeline gives the same bits)."""
+    p = torch.zeros(WAVE_SHAPE, dtype=torch.float32, device="cuda")
+    pm = torch.zeros_like(p)
+    wd = torch.from_numpy(wi.w).cuda()
+    for t0 in range(0, steps, WAVE_SEGMENT):
+        n = min(WAVE_SEGMENT, steps - t0)
+        api.wave25_step_k(p, pm, wd, n, src=(wi.amps[t0:t0 + n], wi.cell))
+        torch.cuda.synchronize()
+    out = (p.cpu().numpy(), pm.cpu().numpy())
+    del p, pm, wd
+    torch.cuda.empty_cache()
+    return out
+
+
+def wave_plan(api, wi, rates, **flags):
+    return api.OutOfCorePlan(WAVE_SHAPE, api.WAVE25, WAVE_SLABS, WAVE_K, list(rates), WAVE_CAP, src_cell=wi.cell,
+                             **flags)
+
+
+def wave_window(api, torch, wi, state, rates, rounds, warmup, profile=False, breakdown_rounds=0, **flags):
+    """`warmup` untimed rounds from the state at WAVE_START, then `rounds`
+    timed rounds (one oocs_run call); optionally `breakdown_rounds` more with
+    the per-stage breakdown on."""
+    p, pm = state
+    plan = wave_plan(api, wi, rates, **flags)
+    st = [plan.new_store(f) for f in range(3)]
+    plan.put(0, p, st[0])
+    plan.put(1, pm, st[1])
+    plan.put(2, wi.w, st[2])
+    t = WAVE_START
+    for _ in range(warmup):
+        plan.run(st, WAVE_K, src_amps=wi.amps[t:t + WAVE_K])
+        t += WAVE_K
+    plan.set_profiling(profile, every=PROFILE_EVERY)
+    n = WAVE_K * rounds
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = plan.run(st, n, src_amps=wi.amps[t:t + n])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t += n
+    plan.set_profiling(False)
+    info = plan.info
+    cells = float(WAVE_SHAPE[0] * WAVE_SHAPE[1] * WAVE_SHAPE[2]) * n
+    out = {
+        "rates": list(rates),
+        "rounds_timed": rounds,
+        "steps_timed": n,
+        "window": f"steps {t - n}..{t} of the {WAVE_STEPS}-step run",
+        "gcells_per_s": cells / dt / 1e9,
+        "ms_per_round": dt / rounds * 1e3,
+        "group_planes": info["group"],
+        "arena_used_bytes": s.arena_bytes,
+        "h2d_GBps": s.h2d_bytes / dt / 1e9,
+        "d2h_GBps": s.d2h_bytes / dt / 1e9,
+        "h2d_bytes_per_round": s.h2d_bytes // rounds,
+        "d2h_bytes_per_round": s.d2h_bytes // rounds,
+        "d2h_engine": "sdma" if s.sdma_copies else "hipMemcpyAsync",
+        "host_enqueue_frac": s.enqueue_ms * 1e-3 / dt,
+        "kernel": kernel_summary([s], rounds, profile),
+    }
+    if profile and s.timed_launches:
+        out["kernel"]["gpu_busy_frac"] = s.kernel_ms * 1e-3 * (s.launches / s.timed_launches) / dt
+    if breakdown_rounds:
+        plan.set_breakdown(True)
+        nb = WAVE_K * breakdown_rounds
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = plan.run(st, nb, src_amps=wi.amps[t:t + nb])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / breakdown_rounds
+        plan.set_breakdown(False)
+        out["breakdown_ms_per_round"] = {k: v / breakdown_rounds for k, v in b.breakdown_ms.items()}
+        out["breakdown_wall_ms_per_round"] = wall
+    plan.close()
+    del st
+    return out
+
+
+def field_errors(torch, a, ref, idx):
+    """Sec. VI-C errors of device field a against device field ref: mean
+    point-wise relative error over the sampled cells idx (cells whose
+    reference magnitude is at most 1e-30 of the largest are left out), and
+    the normwise max and L2 relative errors."""
+    d = a - ref
+    rmax = float(ref.abs().max())
+    num = float(torch.linalg.vector_norm(d, dtype=torch.float64))
+    den = float(torch.linalg.vector_norm(ref, dtype=torch.float64))
+    av = a.view(-1)[idx].double()
+    rv = ref.view(-1)[idx].double()
+    keep = rv.abs() > 1e-30 * rmax
+    pw = ((av - rv).abs() / rv.abs())[keep]
+    return {
+        "pointwise_mean_rel": float(pw.mean()) if pw.numel() else 0.0,
+        "max_rel": float(d.abs().max()) / rmax if rmax > 0 else float(d.abs().max()),
+        "l2_rel": num / den if den > 0 else num,
+        "sampled_used": int(pw.numel()),
+    }
+
+
+def wave_full_run(api, torch, inputs, wi, rates, deadline_s):
+    """The whole 4,320-step run at each rate from rest, in segments of 480
+    steps; after each segment the compressed state p(n) decoded from its host
+    store is compared with the uncompressed run (the in-core GPU propagator,
+    bit-identical to the uncompressed pipeline) at the same step. The time of
+    each rate's runs alone gives its whole-run rate. Stops at the deadline
+    (seconds since the bench started) and says so."""
+    import numpy as np
+
+    idx = torch.from_numpy(inputs.sample_points(WAVE_SHAPE, 100, seed=0)).cuda()
+    p = torch.zeros(WAVE_SHAPE, dtype=torch.float32, device="cuda")
+    pm = torch.zeros_like(p)
+    wd = torch.from_numpy(wi.w).cuda()
+    dec = torch.empty_like(p)
+    plans, stores, secs = {}, {}, {}
+    for r in rates:
+        plans[r] = wave_plan(api, wi, [r] * 3)
+        stores[r] = [plans[r].new_store(f) for f in range(3)]
+        plans[r].put(0, wi.zero, stores[r][0])
+        plans[r].put(1, wi.zero, stores[r][1])
+        plans[r].put(2, wi.w, stores[r][2])
+        secs[r] = 0.0
+    curve = []
+    done = 0
+    truncated = False
+    while done < WAVE_STEPS:
+        if time.perf_counter() - T_START > deadline_s:
+            truncated = True
+            break
+        n = min(WAVE_SEGMENT, WAVE_STEPS - done)
+        amps = wi.amps[done:done + n]
+        api.wave25_step_k(p, pm, wd, n, src=(amps, wi.cell))
+        torch.cuda.synchronize()
+        row = {"step": done + n}
+        for r in rates:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plans[r].run(stores[r], n, src_amps=amps)
+            secs[r] += time.perf_counter() - t0
+            words = stores[r][0].cuda().view(torch.int64)
+            api.codec_decode(words, WAVE_SHAPE, r, out=dec)
+            row[f"rate{r}"] = field_errors(torch, dec, p, idx)
+            del words
+        done += n
+        curve.append(row)
+        log(f"wave full run: step {done}: " +
+            ", ".join(f"rate {r} pw {row[f'rate{r}']['pointwise_mean_rel']:.2e}" for r in rates))
+    cells = float(np.prod(WAVE_SHAPE)) * done
+    out = {
+        "steps_run": done,
+        "truncated_at_deadline": truncated,
+        "rates": {f"rate{r}": {"s": secs[r], "gcells_per_s": cells / secs[r] / 1e9 if secs[r] else None}
+                  for r in rates},
+        "errors_vs_uncompressed": curve,
+        "reference": "in-core FP32 GPU run (bit-identical to the uncompressed pipeline); errors of p(n) decoded "
+                     "from each compressed host store",
+    }
+    for r in rates:
+        plans[r].close()
+    del plans, stores, p, pm, wd, dec
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 512^3 heat
+# ---------------------------------------------------------------------------
+
+def heat_variant(api, torch, u0, rate, steps, warmup, breakdown=False, **flags):
+    """One rate of the 512^3 heat pipeline: `warmup` untimed bench steps of
+    100 time steps, then `steps` timed ones (wall clock)."""
+    plan = api.OutOfCorePlan(HEAT_SHAPE, api.HEAT7, HEAT_SLABS, HEAT_K, [rate], HEAT_CAP, alpha=ALPHA, **flags)
+    store = plan.new_store(0)
+    plan.put(0, u0, store)
+    for _ in range(warmup):
+        plan.run([store], HEAT_TIME_STEPS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [plan.run([store], HEAT_TIME_STEPS) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cells = float(HEAT_SHAPE[0] * HEAT_SHAPE[1] * HEAT_SHAPE[2]) * HEAT_TIME_STEPS * steps
     out = {
         "rate": rate,
         "gcells_per_s": cells / dt / 1e9,
-        "ms_per_step": dt / steps * 1e3,
-        "group_planes": info["group"],
-        "arena_used_bytes": info["arena_needed"],
-        "h2d_GBps": h2d / dt / 1e9,
-        "d2h_GBps": d2h / dt / 1e9,
-        "d2h_engine": "sdma" if sdma_copies else ("kernel" if kernel_transfers else "hipMemcpyAsync"),
-        "h2d_bytes_per_step": h2d // steps,
-        "gpu_busy_frac": (kms * 1e-3) * (nl / max(tl, 1)) / dt if profile else None,
-        "host_enqueue_frac": sum(s.enqueue_ms for s in stats) * 1e-3 / dt,
-        "kernel": {
-            "launches_per_step": nl // steps,
-            "bytes_per_launch": tb / max(tl, 1),
-            "codec_bytes_per_launch": cb / max(nl, 1),
-            "stencil_bytes_per_launch": sb / max(nl, 1),
-            "timed_launches_per_step": tl // steps,
-            "avg_launch_us": kms * 1e3 / max(tl, 1) if profile else None,
-            "achieved_GBps": tb / (kms * 1e-3) / 1e9 if kms > 0 else None,
-        },
+        "ms_per_100_steps": dt / steps * 1e3,
+        "group_planes": plan.info["group"],
+        "arena_used_bytes": stats[0].arena_bytes,
+        "h2d_GBps": sum(s.h2d_bytes for s in stats) / dt / 1e9,
+        "d2h_GBps": sum(s.d2h_bytes for s in stats) / dt / 1e9,
+        "launches_per_100_steps": stats[0].launches,
     }
+    if breakdown:
+        plan.set_breakdown(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = plan.run([store], HEAT_TIME_STEPS)
+        torch.cuda.synchronize()
+        out["breakdown_ms_per_100_steps"] = b.breakdown_ms
+        out["breakdown_wall_ms"] = (time.perf_counter() - t0) * 1e3
+        plan.set_breakdown(False)
     plan.close()
     del store
     return out
 
 
-def link_probe(api, sdma, chunk):
-    """Achievable host-link bandwidth with pinned memory, moved with the
-    pipeline's engines in copies of the pipeline's size (one group of
-    planes): host-to-device alone, device-to-host alone, and both at once
-    (about 256 MiB each way, mean of 3 timed passes)."""
-    return api.link_probe(256 // (chunk >> 20 or 1) * chunk if chunk >= (1 << 20) else 256 << 20, chunk, reps=3,
-                          sdma=sdma)
-
-
-def in_core_launches(steps):
-    """Launches of the in-core heat step: four blocked steps per launch, the
-    remainder one level each."""
-    return steps // 4 + steps % 4
-
-
-def in_core_rate(api, torch, u0):
-    """The in-core heat step on the whole field resident in HBM (no cap), for
-    context: GCell-updates/s (each launch reads and writes the field once)."""
+def heat_in_core_rate(api, torch, u0):
+    """The in-core heat step on the whole 512^3 field resident in HBM (no cap)."""
     u = torch.from_numpy(u0).cuda()
     tmp = torch.empty_like(u)
     api.heat7_step_k(u, ALPHA, 4, tmp=tmp)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    api.heat7_step_k(u, ALPHA, TIME_STEPS, tmp=tmp)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return SHAPE[0] * SHAPE[1] * SHAPE[2] * TIME_STEPS / dt / 1e9
+    t = _timed(torch, lambda: api.heat7_step_k(u, ALPHA, HEAT_TIME_STEPS, tmp=tmp))
+    return HEAT_SHAPE[0] * HEAT_SHAPE[1] * HEAT_SHAPE[2] * HEAT_TIME_STEPS / t / 1e9
 
 
 def small_in_core(api, torch, inputs, reps=200):
@@ -171,29 +379,19 @@ def small_in_core(api, torch, inputs, reps=200):
             "gcells_per_s": round(64 ** 3 * 10 / t / 1e9, 2), "calls": reps}
 
 
-def _timed(torch, fn, reps=1):
-    """Wall time of fn() between device synchronizations (seconds per call)."""
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps
-
-
-def codec_rates(api, torch, u0):
-    """Field encode and decode of the 512^3 field at 8 bits per value:
-    values per second and algorithmic bytes (4 + rate/8 per value) per second."""
+def codec_rates(api, torch, u0, rate=8):
+    """Field encode and decode of the 512^3 heat field: values per second and
+    algorithmic bytes (4 + rate/8 per value) per second."""
     u = torch.from_numpy(u0).cuda()
-    w = api.codec_encode(u, HEADLINE_RATE)
+    w = api.codec_encode(u, rate)
     out = torch.empty_like(u)
-    api.codec_decode(w, SHAPE, HEADLINE_RATE, out=out)
+    api.codec_decode(w, HEAT_SHAPE, rate, out=out)
     n = u.numel()
-    te = _timed(torch, lambda: api.codec_encode(u, HEADLINE_RATE, out=w), reps=5)
-    td = _timed(torch, lambda: api.codec_decode(w, SHAPE, HEADLINE_RATE, out=out), reps=5)
-    b = n * (4 + HEADLINE_RATE / 8)
+    te = _timed(torch, lambda: api.codec_encode(u, rate, out=w), reps=5)
+    td = _timed(torch, lambda: api.codec_decode(w, HEAT_SHAPE, rate, out=out), reps=5)
+    b = n * (4 + rate / 8)
     return {
-        "rate": HEADLINE_RATE,
+        "rate": rate,
         "encode_Gvalues_per_s": round(n / te / 1e9, 1), "encode_GBps": round(b / te / 1e9, 1),
         "encode_hbm_frac": round(b / te / 1e9 / HBM_PEAK_GBS, 4),
         "decode_Gvalues_per_s": round(n / td / 1e9, 1), "decode_GBps": round(b / td / 1e9, 1),
@@ -238,49 +436,6 @@ def batched_rate(api, torch, inputs):
     return out
 
 
-WAVE_SHAPE = (1024, 1024, 1024)
-WAVE_K = 12
-WAVE_CAP = 8 << 30
-
-
-def wave_rates(api, torch, inputs, residencies=2):
-    """The 25-point wave on 1024^3 (layered model, Ricker source) out of core
-    under an 8 GiB device cap, 8 slabs, k = 12: `residencies` timed
-    residencies (12 steps each) after one untimed, uncompressed and at 12
-    bits per value for all three fields."""
-    import numpy as np
-
-    nz, ny, nx = WAVE_SHAPE
-    dt = inputs.wave_dt()
-    w = inputs.wave_coefficient(inputs.layered_velocity(WAVE_SHAPE, seed=1), dt)
-    z = np.zeros(WAVE_SHAPE, np.float32)
-    cell = inputs.source_cell(WAVE_SHAPE)
-    steps = WAVE_K * (residencies + 1)
-    amps = inputs.ricker(steps, dt)
-    res = {}
-    for rate in (0, 12):
-        plan = api.OutOfCorePlan(WAVE_SHAPE, api.WAVE25, 8, WAVE_K, [rate] * 3, WAVE_CAP, src_cell=cell)
-        st = [plan.new_store(f) for f in range(3)]
-        plan.put(0, z, st[0])
-        plan.put(1, z, st[1])
-        plan.put(2, w, st[2])
-        plan.run(st, WAVE_K, src_amps=amps[:WAVE_K])
-        t0 = time.perf_counter()
-        stats = plan.run(st, WAVE_K * residencies, src_amps=amps[WAVE_K:])
-        dt_s = time.perf_counter() - t0
-        cells = float(nx * ny * nz) * WAVE_K * residencies
-        res["uncompressed" if rate == 0 else f"rate{rate}"] = {
-            "gcells_per_s": round(cells / dt_s / 1e9, 2), "ms_per_step": round(dt_s / (WAVE_K * residencies) * 1e3, 2),
-            "group_planes": plan.info["group"], "arena_used_bytes": plan.info["arena_needed"],
-            "h2d_GBps": round(stats.h2d_bytes / dt_s / 1e9, 2), "d2h_GBps": round(stats.d2h_bytes / dt_s / 1e9, 2),
-        }
-        plan.close()
-        del st
-    res["speedup_vs_uncompressed"] = round(res["rate12"]["gcells_per_s"] / res["uncompressed"]["gcells_per_s"], 3)
-    res["sample"] = f"{residencies} residencies ({WAVE_K * residencies} steps) of the 4320-step run"
-    return res
-
-
 def adjoint_rate(api, torch, inputs, steps=100, every=10, rate=12):
     """Misfit gradient of the 25-point wave on 512^3 with 64 receivers on the
     top face: forward with (p, p_prev) checkpoints every 10 steps compressed
@@ -318,39 +473,47 @@ def adjoint_rate(api, torch, inputs, steps=100, every=10, rate=12):
     return out
 
 
-def cpu_baseline(u0, budget_s):
-    """The oracle (plain C, OpenMP) on a bounded sample of the workload:
-    whole residencies (4 FP64 steps + decode(encode()) at 8 bits/value) of
-    the same 512^3 field, repeated until about budget_s seconds."""
+# ---------------------------------------------------------------------------
+# CPU baseline and probes
+# ---------------------------------------------------------------------------
+
+CPU_SAMPLE_PLANES = 64
+
+
+def cpu_baseline(wi, state):
+    """The oracle (plain C, OpenMP, FP64) on a bounded sample of the headline
+    workload: one residency (12 FP64 wave steps, then decode(encode()) of
+    p(n) and p(n-1) at 12 bits per value) on the first 64 planes of the
+    1024^2 grid, from the developed state at step 2,160 (the source is in
+    these planes)."""
     import numpy as np
 
     import oracle as O
 
     O.lib()
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    u = u0.astype(np.float64)
-    n, t = 0, 0.0
-    while t < budget_s and n < 6:
-        t0 = time.perf_counter()
-        u = O.heat7_f64(u, ALPHA, K)
-        u = O.codec_roundtrip_f64(u, HEADLINE_RATE)
-        t += time.perf_counter() - t0
-        n += 1
-    cells = SHAPE[0] * SHAPE[1] * SHAPE[2] * K * n
+    sl = slice(0, CPU_SAMPLE_PLANES)
+    p = state[0][sl].astype(np.float64)
+    pm = state[1][sl].astype(np.float64)
+    w = wi.w[sl].astype(np.float64)
+    nz, ny, nx = p.shape
+    cx, cy, cz = wi.cell
+    src = (wi.amps[WAVE_START:WAVE_START + WAVE_K].astype(np.float64), cx + nx * (cy + ny * cz))
+    t0 = time.perf_counter()
+    p, pm = O.wave25_f64(p, pm, w, WAVE_K, src=src)
+    p = O.codec_roundtrip_f64(p, HEADLINE_RATE)
+    pm = O.codec_roundtrip_f64(pm, HEADLINE_RATE)
+    t = time.perf_counter() - t0
+    cells = float(nx * ny * nz) * WAVE_K
     return {
         "value": cells / t / 1e9,
         "unit": "GCell-updates/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{n} residencies ({K * n} FP64 heat steps + {n} decode(encode()) at {HEADLINE_RATE} bits/value) "
-                  f"of the 512^3 field, {t:.1f} s",
+        "sample": f"one residency ({WAVE_K} FP64 wave steps + decode(encode()) of p(n), p(n-1) at "
+                  f"{HEADLINE_RATE} bits/value) on planes 0..{CPU_SAMPLE_PLANES - 1} of the 1024^2 x 1024 grid "
+                  f"from the step-{WAVE_START} state, {t:.1f} s",
     }
-
-
-def _rounded(x):
-    if isinstance(x, dict):
-        return {k: _rounded(v) for k, v in x.items()}
-    return round(x, 3) if isinstance(x, float) else x
 
 
 def copy_probe():
@@ -367,26 +530,32 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 4, "copies": 3}), flush=True)
 
 
+def host_link(api, chunk, sdma=True):
+    """Achievable host-link bandwidth with pinned memory, moved with the
+    pipeline's engines in copies of the pipeline's size (one group of
+    planes of one field): each direction alone, and both at once (about
+    256 MiB each way, mean of 3 timed passes)."""
+    nbytes = max(1, (256 << 20) // chunk) * chunk
+    r = api.link_probe(nbytes, chunk, reps=3, sdma=sdma)
+    return {k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
+
+
+# ---------------------------------------------------------------------------
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed rounds (12 time steps of the whole grid each)")
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--rates", default=",".join(str(r) for r in VARIANTS),
-                    help="comma-separated rates to time (0 = uncompressed)")
-    ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
-    ap.add_argument("--graphs", type=int, default=0,
-                    help="1: replay each residency as a HIP graph; 0: issue it on the three streams directly")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline rate's rounds only (for profiler runs)")
+    ap.add_argument("--no-full-run", action="store_true", help="skip the 4,320-step runs and their error curve")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the other workloads (codec, batched heat, 1024^3 wave, adjoint)")
-    ap.add_argument("--pipeline-only", action="store_true",
-                    help="time the pipeline variants only (no in-core rate, no link probe); for profiler runs")
-    ap.add_argument("--kernel-transfers", type=int, default=0,
-                    help="1: move groups with transfer jobs inside the pipeline kernel instead of copy engines")
-    ap.add_argument("--sdma", type=int, default=1,
-                    help="1: write-back copies on an SDMA engine through HSA; 0: through hipMemcpyAsync")
+                    help="skip the heat, codec, batched and adjoint workloads")
+    ap.add_argument("--deadline", type=float, default=450.0,
+                    help="seconds after start beyond which the 4,320-step runs stop (the line is still printed)")
+    ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -397,46 +566,84 @@ def main():
         copy_probe()
         return
 
-    import numpy as np  # noqa: F401
     import torch
 
     from paper_2109_05410_amd import api, inputs
 
     torch.cuda.set_device(0)
-    u0 = inputs.heat_uniform(SHAPE, seed=0)
-    rates = [int(r) for r in args.rates.split(",")]
-    results = {}
-    for r in rates:
-        results[r] = run_variant(api, torch, u0, r, args.steps, args.warmup, bool(args.graphs),
-                                 bool(args.kernel_transfers), bool(args.sdma),
-                                 profile=(r == (HEADLINE_RATE if HEADLINE_RATE in rates else rates[-1])))
-        print(f"# rate {r}: {results[r]['gcells_per_s']:.1f} GCell-updates/s, "
-              f"{results[r]['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
-    head = results.get(HEADLINE_RATE, results[rates[-1]])
-    raw = results.get(0)
-    if args.pipeline_only:
-        print(json.dumps({"variants": {r: _rounded(res) for r, res in results.items()}}), flush=True)
+    wi = WaveInputs(inputs)
+    log(f"developing the wavefield to step {WAVE_START} in core")
+    state = wave_state(api, torch, wi, WAVE_START)
+    head_rates = [HEADLINE_RATE] * 3
+    log("headline rounds")
+    head = wave_window(api, torch, wi, state, head_rates, args.steps, args.warmup, profile=True)
+    log(f"rate {HEADLINE_RATE}: {head['gcells_per_s']:.1f} GCell-updates/s, {head['ms_per_round']:.1f} ms/round")
+    if args.headline_only:
+        print(json.dumps({"headline": _rounded(head)}), flush=True)
         return
-    incore = in_core_rate(api, torch, u0)
-    copy_bytes = int(head["group_planes"] * SHAPE[1] * SHAPE[2] * (head["rate"] / 8 if head["rate"] else 4))
-    link = link_probe(api, bool(args.sdma), copy_bytes)
-    link_hip = link_probe(api, False, copy_bytes) if args.sdma else None
+    variants = {f"rate{HEADLINE_RATE}": head}
+    vr = max(2, min(args.steps, 8))
+    for r in WAVE_RATES:
+        if r == HEADLINE_RATE:
+            continue
+        key = "uncompressed" if r == 0 else f"rate{r}"
+        variants[key] = wave_window(api, torch, wi, state, [r] * 3, args.steps if r else vr, 1)
+        log(f"{key}: {variants[key]['gcells_per_s']:.1f} GCell-updates/s")
+    # the read-only field kept decoded on the device instead of streamed
+    for r in (HEADLINE_RATE, 8):
+        key = f"rate{r}_resident_ro"
+        variants[key] = wave_window(api, torch, wi, state, [r] * 3, vr, 1, resident_ro=True)
+        log(f"{key}: {variants[key]['gcells_per_s']:.1f} GCell-updates/s")
+    # the paper's codes (Sec. VI): 2 = one read-write field (p(n-1)), 3 = the
+    # read-only field, 4 = both, at the headline rate
+    codes = {}
+    for code, rates in ((2, [0, HEADLINE_RATE, 0]), (3, [0, 0, HEADLINE_RATE]), (4, [0, HEADLINE_RATE, HEADLINE_RATE])):
+        codes[f"code{code}"] = wave_window(api, torch, wi, state, rates, vr, 1)
+        log(f"code {code}: {codes[f'code{code}']['gcells_per_s']:.1f} GCell-updates/s")
+    codes["code1"] = {"same_as": "uncompressed"}
+    # the per-block schedule of Fig. 2 (every block recomputes its halo)
+    restart = {}
+    for r in (HEADLINE_RATE, 0):
+        key = "uncompressed" if r == 0 else f"rate{r}"
+        restart[key] = wave_window(api, torch, wi, state, [r] * 3, 2, 1, block_restart=True)
+        log(f"block restart {key}: {restart[key]['gcells_per_s']:.1f} GCell-updates/s")
+    # per-stage breakdown (Sec. VI-B), 2 rounds per rate
+    breakdown = {}
+    for r in WAVE_RATES:
+        key = "uncompressed" if r == 0 else f"rate{r}"
+        b = wave_window(api, torch, wi, state, [r] * 3, 1, 0, breakdown_rounds=2)
+        breakdown[key] = {"ms_per_round": b["breakdown_ms_per_round"], "wall_ms_per_round": b["breakdown_wall_ms_per_round"]}
+        log(f"breakdown {key}: {breakdown[key]}")
     extras = {}
     if not args.no_extras:
+        u0 = inputs.heat_uniform(HEAT_SHAPE, seed=0)
+        heat = {}
+        for r in HEAT_RATES:
+            heat["uncompressed" if r == 0 else f"rate{r}"] = heat_variant(api, torch, u0, r, 3, 1, breakdown=True)
+        heat["block_restart_rate8"] = heat_variant(api, torch, u0, 8, 2, 1, block_restart=True)
+        heat["block_restart_uncompressed"] = heat_variant(api, torch, u0, 0, 1, 1, block_restart=True)
+        heat["in_core_gcells_per_s"] = heat_in_core_rate(api, torch, u0)
+        extras["heat_512"] = heat
+        log(f"heat 512^3: rate 8 {heat['rate8']['gcells_per_s']:.1f}, uncompressed "
+            f"{heat['uncompressed']['gcells_per_s']:.1f} GCell-updates/s")
         extras["in_core_64"] = small_in_core(api, torch, inputs)
-        print(f"# in-core 64^3: {extras['in_core_64']}", file=sys.stderr, flush=True)
         extras["codec_512"] = codec_rates(api, torch, u0)
-        print(f"# codec: {extras['codec_512']}", file=sys.stderr, flush=True)
         extras["batched_heat"] = batched_rate(api, torch, inputs)
-        print(f"# batched: {extras['batched_heat']}", file=sys.stderr, flush=True)
-        extras["wave_1024"] = wave_rates(api, torch, inputs)
-        print(f"# wave 1024^3: {extras['wave_1024']}", file=sys.stderr, flush=True)
+        log(f"batched: {extras['batched_heat']}")
         extras["adjoint_512"] = adjoint_rate(api, torch, inputs)
-        print(f"# adjoint: {extras['adjoint_512']}", file=sys.stderr, flush=True)
+        log(f"adjoint: {extras['adjoint_512']}")
+        del u0
+    chunk = head["group_planes"] * WAVE_SHAPE[1] * WAVE_SHAPE[2] * HEADLINE_RATE // 8
+    link = host_link(api, chunk)
+    full = None
+    if not args.no_full_run:
+        log("whole 4,320-step runs")
+        full = wave_full_run(api, torch, inputs, wi, FULL_RUN_RATES, args.deadline)
     traffic = measured_counters("hbm_bytes_per_launch")
     alu_ops = measured_counters("alu_ops_per_launch")
     kname, kstat = "fused_kernel", head["kernel"]
     achieved = kstat["achieved_GBps"]
+    raw = variants["uncompressed"]
     line = {
         "metric": METRIC,
         "value": round(head["gcells_per_s"], 3),
@@ -444,26 +651,28 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(head["ms_per_step"], 3),
+        "ms_per_step": round(head["ms_per_round"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "heat7 512^3 FP32, 8 z-slabs, k=4 (halo 4), 100 steps per bench step, "
-                        "device arena capped at 128 MiB (two slabs), host store at 8 bits/value",
-            "grid": list(SHAPE), "nslabs": NSLABS, "k": K, "time_steps": TIME_STEPS,
-            "device_cap_bytes": CAP, "rate_bits_per_value": head["rate"],
+            "workload": "wave25 1024^3 FP32 (p, p_prev, read-only w), layered 1500-4500 m/s model, 15 Hz Ricker, "
+                        "8 z-slabs, k=12 (halo 48), device arena capped at 8 GiB, all three host stores at "
+                        "12 bits/value; one bench step = one round (every block advanced 12 steps) from the "
+                        "step-2160 state of the 4320-step run",
+            "grid": list(WAVE_SHAPE), "nslabs": WAVE_SLABS, "k": WAVE_K, "time_steps_per_bench_step": WAVE_K,
+            "device_cap_bytes": WAVE_CAP, "rate_bits_per_value": HEADLINE_RATE,
         },
-        "speedup_vs_uncompressed": round(head["gcells_per_s"] / raw["gcells_per_s"], 3) if raw else None,
-        "variants": {("uncompressed" if r == 0 else f"rate{r}"): _rounded(res) for r, res in results.items()},
-        "in_core_gcells_per_s": round(incore, 1),
-        "in_core_hbm_frac": round(incore * 8 * in_core_launches(TIME_STEPS) / TIME_STEPS / HBM_PEAK_GBS, 4),
-        "other_workloads": extras,
-        "host_link": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in link.items()},
-        "host_link_d2h_hipMemcpyAsync": ({k: (round(v, 2) if isinstance(v, float) else v) for k, v in link_hip.items()}
-                                         if link_hip else None),
+        "speedup_vs_uncompressed": round(head["gcells_per_s"] / raw["gcells_per_s"], 3),
+        "variants": _rounded(variants),
+        "paper_codes": _rounded(codes),
+        "block_restart": _rounded(restart),
+        "breakdown_ms_per_round": _rounded(breakdown),
+        "full_run_4320": _rounded(full),
+        "other_workloads": _rounded(extras),
+        "host_link": link,
         "paper_context": "1.20x over uncompressed out-of-core (V100-PCIe, FP64 25-point wave, 24/64 bits, Sec. VI-A)",
         "roofline": {
             "bound": "hbm",
@@ -474,12 +683,9 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": traffic.get(kname) if isinstance(traffic, dict) else None,
             "bytes_per_launch": round(kstat["bytes_per_launch"]),
-            "avg_launch_us": round(kstat["avg_launch_us"], 2),
+            "avg_launch_us": round(kstat["avg_launch_us"], 2) if kstat["avg_launch_us"] else None,
         },
     }
-    # the same launches against the VALU issue peak: issued VALU lane operations
-    # per launch (counter run on the same kernel source) over the live average
-    # launch duration; the codec's bit-plane coding makes the kernel issue-heavy
     ops = alu_ops.get(kname) if isinstance(alu_ops, dict) else None
     alu_achieved = ops / (kstat["avg_launch_us"] * 1e-6) / 1e12 if ops and kstat["avg_launch_us"] else None
     line["alu_roofline"] = {
@@ -490,20 +696,20 @@ def main():
         "unit": "T VALU lane-ops/s",
         "frac": round(alu_achieved / VALU_PEAK_TOPS, 4) if alu_achieved else None,
         "ops_per_launch": ops,
-        "ops_source": "SQ_INSTS_VALU x 64 from profiles/heat512_rate8_counters.json (issued, not algorithmic)",
+        "ops_source": "SQ_INSTS_VALU x 64 from profiles/wave1024_rate12_counters.json (issued, not algorithmic)",
     }
-    # the transfers against the host link: both directions run at once, so the
-    # peak is the measured bidirectional rate per direction
     bidir = link.get("bidir_GBps_each")
     line["host_link_roofline"] = {
-        "achieved_GBps_each_way": round(head["h2d_GBps"], 2),
-        "peak_GBps_each_way": round(bidir, 2) if bidir else None,
+        "achieved_GBps_h2d": round(head["h2d_GBps"], 2),
+        "achieved_GBps_d2h": round(head["d2h_GBps"], 2),
+        "peak_GBps_each_way": bidir,
         "frac": round(head["h2d_GBps"] / bidir, 4) if bidir else None,
         "peak_source": "host_link: ~256 MiB each way in pinned copies of the pipeline's group size on its "
                        "engines, both directions at once",
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(u0, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(wi, state)
+    line["bench_wall_s"] = round(time.perf_counter() - T_START, 1)
     print(json.dumps(line), flush=True)
 
 

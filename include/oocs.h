@@ -130,6 +130,20 @@ int oocs_codec_decode_stages(const uint64_t* d_words, int64_t nblocks, int rate,
 int oocs_heat7_step_k(float* d_u, float* d_tmp, int64_t nx, int64_t ny, int64_t nz, float alpha, int64_t k,
                       void* stream);
 
+/* The same k heat steps for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no scratch argument and no allocation of any kind. The
+ * scratch field lives in a fixed array of OOCS_NOALLOC_MAX_CELLS floats
+ * (64 MiB) that the library holds on every GPU it runs on until the process
+ * ends; its device address is looked up on the first call on each device.
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (other streams or threads) race and must be ordered by the caller.
+ * The array needs no clearing: each call writes all of it that it reads.
+ * Errors: OOCS_E_ARG, OOCS_E_SIZE (nx*ny*nz > OOCS_NOALLOC_MAX_CELLS, checked
+ * before any HIP call), OOCS_E_ALIGN, OOCS_E_HIP. */
+#define OOCS_NOALLOC_MAX_CELLS (1 << 24)
+int oocs_heat7_step_k_noalloc(float* d_u, int64_t nx, int64_t ny, int64_t nz, float alpha, int64_t k, void* stream);
+
 /* k leapfrog steps of the 25-point acoustic wave (Sec. VI: two read-write
  * fields, one read-only field, radius HALO = 4):
  *   p(n+1) = 2 p(n) - p(n-1) + w * L p(n) + s(n) at the source cell,
@@ -213,6 +227,19 @@ typedef struct {
  * has its own ring of planes (always the case for the wave, for k > 4 and
  * with OOCS_PLAN_BLOCK_RESTART). Same results. */
 #define OOCS_PLAN_LEVEL_BY_LEVEL 4
+
+/* Plan flag (wave): keep the read-only field resident on the device instead
+ * of streaming its chunks every residency (the paper streams it, Sec. VI).
+ * Its store is decoded once into an arena buffer of nz planes, at the first
+ * oocs_run after the plan is created or after any oocs_store_put /
+ * oocs_store_get on the plan (those stream through the arena and overwrite
+ * it), and whenever oocs_run is given a different read-only store pointer;
+ * rewriting the store's contents in place between runs is not detected.
+ * Each residency then moves and decodes only the two read-write fields.
+ * Same results as streaming (the same decoded values are read). Needs an
+ * arena that holds the whole decoded field besides the rings (OOCS_E_CAP
+ * otherwise). */
+#define OOCS_PLAN_RESIDENT_RO 16
 
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be
@@ -329,6 +356,16 @@ typedef struct {
     /* Device-to-host copies of this call issued on SDMA engines through the
      * HSA runtime (oocs_plan_set_sdma); the others went through hipMemcpyAsync. */
     int64_t sdma_copies;
+    /* Per-stage breakdown (oocs_plan_set_breakdown on, op-by-op issue; else
+     * zeros): summed durations in ms of the work of each stage of Sec. V-B,
+     * [0] host-to-device copies, [1] decode jobs (raw copy-in when
+     * uncompressed), [2] stencil steps, [3] encode jobs (raw copy-out),
+     * [4] device-to-host copies (HIP events around each copy or launch; SDMA
+     * copies by the engine's own timestamps). Stages on different engines
+     * overlap, so the sum exceeds wall_ms. */
+    double stage_ms[5];
+    /* Device bytes the plan uses: its peak arena footprint (<= the cap). */
+    int64_t arena_bytes;
 } oocs_stats;
 
 /* Per-launch kernel timing for later oocs_run calls on this plan: 0 turns it
@@ -336,6 +373,14 @@ typedef struct {
  * launch (N = 1: every launch). The sum of their elapsed times is returned in
  * oocs_stats.kernel_ms, with the timed launches and their bytes. */
 int oocs_plan_set_profiling(oocs_plan* plan, int on);
+
+/* Per-stage breakdown for later oocs_run calls on this plan (default 0):
+ * with op-by-op issue, every tick's jobs are launched as one launch per
+ * stage (decode, stencil, encode) between timing events instead of one
+ * fused launch, and every copy is timed, so oocs_stats.stage_ms gives the
+ * time of each stage (the breakdown of Sec. VI-B). Same results; the
+ * split launches make the run slower, so time throughput with it off. */
+int oocs_plan_set_breakdown(oocs_plan* plan, int on);
 
 /* Choose how oocs_run issues a residency (default 0): as one replay of a HIP
  * graph built once per residency length and set of host stores (1), or op by

@@ -24,10 +24,12 @@ OOCS_HEAT7 = 1
 OOCS_WAVE25 = 2
 OOCS_MAX_FIELDS = 3
 OOCS_MAX_RATE = 34
+OOCS_NOALLOC_MAX_CELLS = 1 << 24
 OOCS_PLAN_BLOCK_RESTART = 1
 OOCS_PLAN_KERNEL_TRANSFERS = 2
 OOCS_PLAN_LEVEL_BY_LEVEL = 4
 OOCS_PLAN_KERNEL_STORES = 8
+OOCS_PLAN_RESIDENT_RO = 16
 
 OP_H2D, OP_DECODE, OP_LEVEL, OP_ENCODE, OP_D2H, OP_LAUNCH, OP_RECORD, OP_WAIT, OP_FETCH, OP_STORE = range(1, 11)
 
@@ -93,6 +95,7 @@ class Stats(C.Structure):
         ("launches", C.c_int64), ("codec_bytes", C.c_int64), ("stencil_bytes", C.c_int64),
         ("kernel_ms", C.c_double), ("xfer_bytes", C.c_int64),
         ("timed_launches", C.c_int64), ("timed_bytes", C.c_int64), ("sdma_copies", C.c_int64),
+        ("stage_ms", C.c_double * 5), ("arena_bytes", C.c_int64),
     ]
 
 
@@ -108,6 +111,7 @@ _SIGS = {
     "oocs_codec_encode_stages": (C.c_int, [_P, _I64, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
     "oocs_codec_decode_stages": (C.c_int, [_P, _I64, C.c_int, _P, _P, _P, _P, _P, _P]),
     "oocs_heat7_step_k": (C.c_int, [_P, _P, _I64, _I64, _I64, C.c_float, _I64, _P]),
+    "oocs_heat7_step_k_noalloc": (C.c_int, [_P, _I64, _I64, _I64, C.c_float, _I64, _P]),
     "oocs_wave25_step_k": (C.c_int, [_P, _P, _P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P]),
     "oocs_plan_create": (C.c_int, [C.POINTER(Config), _P, C.c_size_t, C.POINTER(_P)]),
     "oocs_plan_destroy": (C.c_int, [_P]),
@@ -120,6 +124,7 @@ _SIGS = {
     "oocs_store_get": (C.c_int, [_P, C.c_int, _P, _P]),
     "oocs_run": (C.c_int, [_P, C.POINTER(_P), _I64, _P, C.POINTER(Stats)]),
     "oocs_plan_set_profiling": (C.c_int, [_P, C.c_int]),
+    "oocs_plan_set_breakdown": (C.c_int, [_P, C.c_int]),
     "oocs_plan_set_graphs": (C.c_int, [_P, C.c_int]),
     "oocs_plan_set_host_waits": (C.c_int, [_P, C.c_int]),
     "oocs_plan_set_sdma": (C.c_int, [_P, C.c_int]),

@@ -186,6 +186,15 @@ class RunStats:
     timed_launches: int
     timed_bytes: int
     sdma_copies: int
+    stage_ms: tuple
+    arena_bytes: int
+
+    STAGES = ("h2d", "decode", "step", "encode", "d2h")
+
+    @property
+    def breakdown_ms(self) -> dict:
+        """Per-stage summed durations (plans with set_breakdown(True))."""
+        return dict(zip(self.STAGES, self.stage_ms))
 
     @property
     def gcells_per_s(self) -> float:
@@ -206,12 +215,15 @@ class OutOfCorePlan:
     write-back by STORE jobs in the pipeline kernel; kernel_transfers: loads
     by FETCH jobs as well. level_by_level (heat,
     k <= 4): one job and one ring per time level instead of one temporally
-    blocked job per tick. Results are identical."""
+    blocked job per tick. resident_ro (wave): the read-only field is decoded
+    once into the arena and stays there instead of being streamed every
+    residency. Results are identical."""
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
                  planning_only: bool = False, device=None, block_restart: bool = False,
-                 kernel_transfers: bool = False, level_by_level: bool = False, kernel_stores: bool = False):
+                 kernel_transfers: bool = False, level_by_level: bool = False, kernel_stores: bool = False,
+                 resident_ro: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -226,7 +238,8 @@ class OutOfCorePlan:
         cfg.flags = ((L.OOCS_PLAN_BLOCK_RESTART if block_restart else 0)
                      | (L.OOCS_PLAN_KERNEL_TRANSFERS if kernel_transfers else 0)
                      | (L.OOCS_PLAN_LEVEL_BY_LEVEL if level_by_level else 0)
-                     | (L.OOCS_PLAN_KERNEL_STORES if kernel_stores else 0))
+                     | (L.OOCS_PLAN_KERNEL_STORES if kernel_stores else 0)
+                     | (L.OOCS_PLAN_RESIDENT_RO if resident_ro else 0))
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg
@@ -308,11 +321,18 @@ class OutOfCorePlan:
         st = L.Stats()
         L.check(L.lib().oocs_run(self._h, ptrs, steps, amps.ctypes.data_as(C.c_void_p) if amps is not None else None,
                                  C.byref(st)))
-        return RunStats(*(getattr(st, name) for name, _ in L.Stats._fields_))
+        vals = [getattr(st, name) for name, _ in L.Stats._fields_]
+        vals[[n for n, _ in L.Stats._fields_].index("stage_ms")] = tuple(st.stage_ms)
+        return RunStats(*vals)
 
     def set_profiling(self, on, every: int = 1):
         """Time every `every`-th launch with events (on=False: no timing)."""
         L.check(L.lib().oocs_plan_set_profiling(self._h, int(every) if on else 0))
+
+    def set_breakdown(self, on: bool):
+        """Per-stage timing of later runs (one launch per stage per tick, every
+        copy timed); RunStats.breakdown_ms then holds the stage times."""
+        L.check(L.lib().oocs_plan_set_breakdown(self._h, 1 if on else 0))
 
     def set_graphs(self, on: bool):
         L.check(L.lib().oocs_plan_set_graphs(self._h, 1 if on else 0))

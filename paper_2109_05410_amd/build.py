@@ -32,6 +32,7 @@ DEVICE = [
 ]
 SOURCES = {
     "kernels.hip": True,   # device code
+    "noalloc.hip": True,   # device code (the library-held scratch array) and its entry point
     "plan.cpp": False,     # host only
     "host.cpp": False,     # host only (HIP runtime API)
     "adjoint.cpp": False,  # host only (HIP runtime API)

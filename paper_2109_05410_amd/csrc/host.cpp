@@ -76,6 +76,13 @@ struct oocs_plan {
     bool sdma_on = true;
     std::vector<int64_t> ev_ticket;  // per event: SDMA ticket if last recorded on the D2H stream, else -1
     std::vector<hipEvent_t> tev;  // eager timing events, two per launch, grown on demand
+    // per-stage breakdown (op-by-op issue): event pairs around every copy and
+    // every stage launch, grown on demand
+    bool breakdown = false;
+    std::vector<hipEvent_t> bev;
+    // resident read-only field: the store its ring was decoded from (null:
+    // not loaded, or overwritten by store I/O through the arena)
+    const void* ro_loaded = nullptr;
     // graphs by (residency length, store pointers, source on)
     std::map<std::tuple<int, const void*, const void*, const void*, bool, bool>, ResidencyGraph> gcache;
 };
@@ -310,6 +317,8 @@ int oocs_plan_destroy(oocs_plan* pl)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : pl->tev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : pl->bev)
+        if (e) (void)hipEventDestroy(e);
     for (auto& kv : pl->gcache) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         for (hipEvent_t e : kv.second.timing)
@@ -393,6 +402,7 @@ static int store_xfer(oocs_plan* pl, int f, bool put, const float* h_field_in, f
                       void* h_store_out)
 {
     const oocs::Planner& P = pl->P;
+    pl->ro_loaded = nullptr;  // the chunks below overwrite the start of the arena
     const int64_t pb = P.plane_elems() * 4;
     const int rate = P.cfg.rate[f];
     const int64_t spb = P.store_plane_bytes(f);
@@ -459,6 +469,22 @@ int oocs_plan_set_profiling(oocs_plan* pl, int on)
     return OOCS_OK;
 }
 
+// Stage of a job in the per-stage breakdown: 0 host-to-device transfer,
+// 1 decode (or raw copy in), 2 stencil steps, 3 encode (or raw copy out),
+// 4 device-to-host transfer.
+static int job_stage(int kind)
+{
+    switch (kind) {
+    case oocs::JOB_FETCH: return 0;
+    case oocs::JOB_DECODE:
+    case oocs::JOB_COPY_IN: return 1;
+    case oocs::JOB_ENCODE:
+    case oocs::JOB_COPY_OUT: return 3;
+    case oocs::JOB_STORE: return 4;
+    default: return 2;
+    }
+}
+
 // Algorithmic device-memory bytes of one job (each distinct input plane read
 // once, each output plane written once).
 static int64_t job_bytes(const oocs::Job& j, int64_t plane_elems)
@@ -475,6 +501,14 @@ static int64_t job_bytes(const oocs::Job& j, int64_t plane_elems)
     case oocs::JOB_STORE: return j.bytes;               // staging side; the other side is the host link
     default: return planes * pb * 2;                    // raw copies
     }
+}
+
+int oocs_plan_set_breakdown(oocs_plan* pl, int on)
+{
+    if (!pl) return fail(OOCS_E_ARG, "null pointer");
+    if (!pl->runnable) return fail(OOCS_E_STATE, "planning-only plan");
+    pl->breakdown = on != 0;
+    return OOCS_OK;
 }
 
 int oocs_plan_set_graphs(oocs_plan* pl, int on)
@@ -659,6 +693,38 @@ struct OpTranslator {
     }
 };
 
+// Decodes the read-only store into its resident ring (OOCS_PLAN_RESIDENT_RO),
+// one group of planes at a time through the field's one staging slot, on the
+// compute stream. Blocking.
+int load_resident_ro(oocs_plan* pl, const void* h_ro)
+{
+    const oocs::Planner& P = pl->P;
+    const int f = 2;
+    const int rate = P.cfg.rate[f];
+    const int64_t spb = P.store_plane_bytes(f);
+    hipStream_t s = pl->st[1];
+    char* slot = pl->arena + P.in_off[f];
+    for (int64_t z0 = 0; z0 < P.nz; z0 += P.G) {
+        const int64_t z1 = std::min(P.nz, z0 + P.G);
+        HIP_TRY(hipMemcpyAsync(slot, static_cast<const char*>(h_ro) + z0 * spb, (size_t)((z1 - z0) * spb),
+                               hipMemcpyHostToDevice, s));
+        oocs::LaunchParams lp = base_params(P.nx, P.ny, P.nz, P.cfg.alpha, -1, -1, -1);
+        oocs::Job& j = lp.jobs[0];
+        j.kind = rate ? oocs::JOB_DECODE : oocs::JOB_COPY_IN;
+        j.rate = rate;
+        j.z0 = (int32_t)z0;
+        j.z1 = (int32_t)z1;
+        j.dst = oocs::Ring{reinterpret_cast<float*>(pl->arena + P.ringOff[P.ro_ring()]), P.ringW[P.ro_ring()],
+                           P.plane_elems()};
+        j.stage = slot;
+        lp.njobs = 1;
+        HIP_TRY(oocs::launch_jobs(lp, s));
+        HIP_TRY(hipStreamSynchronize(s));  // the slot takes the next group
+    }
+    pl->ro_loaded = h_ro;
+    return OOCS_OK;
+}
+
 // Builds the graph of one residency of kr steps.
 int build_graph(oocs_plan* pl, int kr, void* const* h_store, void* const* d_store, bool src_on, ResidencyGraph& out)
 {
@@ -781,7 +847,12 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     oocs::Planner& P = pl->P;
     for (int f : P.in_fields)
         if (!h_store[f]) return fail(OOCS_E_ARG, "missing host store pointer");
+    if (P.resident_ro && !h_store[2]) return fail(OOCS_E_ARG, "missing read-only store pointer");
     const auto t_start = std::chrono::steady_clock::now();
+    if (P.resident_ro && pl->ro_loaded != h_store[2]) {
+        const int rc = load_resident_ro(pl, h_store[2]);
+        if (rc != OOCS_OK) return rc;
+    }
     const bool src_on = h_src != nullptr && P.cfg.stencil == OOCS_WAVE25 && P.cfg.src_x >= 0 && P.cfg.src_x < P.nx &&
                         P.cfg.src_y >= 0 && P.cfg.src_y < P.ny && P.cfg.src_z >= 0 && P.cfg.src_z < P.nz;
     int32_t* step_ctr = src_on ? reinterpret_cast<int32_t*>(pl->arena + P.step_ctr_off) : nullptr;
@@ -805,6 +876,25 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     double kms = 0.0;
     size_t tused = 0;
     const int ns = P.nstage;
+    // breakdown: event pairs (start, end) with the stage each one times
+    const bool bdown = pl->breakdown && !pl->graphs;
+    size_t bused = 0;
+    std::vector<int8_t> bstage;
+    auto bevent = [&](int stage, hipStream_t s) -> int {  // records the start of a pair
+        while (pl->bev.size() < bused + 2) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));  // timing only
+            pl->bev.push_back(e);
+        }
+        HIP_TRY(hipEventRecord(pl->bev[bused], s));
+        bstage.push_back((int8_t)stage);
+        return OOCS_OK;
+    };
+    auto bevent_end = [&](hipStream_t s) -> int {
+        HIP_TRY(hipEventRecord(pl->bev[bused + 1], s));
+        bused += 2;
+        return OOCS_OK;
+    };
     // Device-to-host copies go to an SDMA engine when the host honours the
     // cross-stream waits itself (op-by-op issue with host waits): a wait on
     // the write-back stream then becomes a wait for the copies issued before
@@ -819,6 +909,10 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
         if (use_sdma && !pl->sdma.host_agent(h_store[f], &cpu_agent[f])) use_sdma = false;
     std::fill(pl->ev_ticket.begin(), pl->ev_ticket.end(), (int64_t)-1);
     int64_t sdma_copies = 0;
+    if (use_sdma) {
+        const int rc = pl->sdma.set_timing(bdown);
+        if (rc != OOCS_OK) return rc;
+    }
 
     int64_t done = 0;
     while (done < steps) {
@@ -886,7 +980,9 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                         size_t bytes;
                         tr.copy_args(o, &dev, &host, &bytes);
                         if (o.kind == OOCS_OP_H2D) {
+                            if (bdown && bevent(0, pl->st[0]) != OOCS_OK) return OOCS_E_HIP;
                             HIP_TRY(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, pl->st[0]));
+                            if (bdown && bevent_end(pl->st[0]) != OOCS_OK) return OOCS_E_HIP;
                             h2d += (int64_t)bytes;
                         } else if (use_sdma) {
                             const int rc = pl->sdma.copy(host, cpu_agent[o.field], dev, bytes);
@@ -894,7 +990,9 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                             d2h += (int64_t)bytes;
                             ++sdma_copies;
                         } else {
+                            if (bdown && bevent(4, pl->st[2]) != OOCS_OK) return OOCS_E_HIP;
                             HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, pl->st[2]));
+                            if (bdown && bevent_end(pl->st[2]) != OOCS_OK) return OOCS_E_HIP;
                             d2h += (int64_t)bytes;
                         }
                         break;
@@ -922,7 +1020,22 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                                 }
                                 HIP_TRY(hipEventRecord(pl->tev[tused], pl->st[1]));
                             }
-                            HIP_TRY(oocs::launch_jobs(tr.lp, pl->st[1]));
+                            if (bdown) {
+                                // one launch per stage, in stage order (the jobs of a tick
+                                // are independent, so any order gives the same bits)
+                                for (int stage = 0; stage < 5; ++stage) {
+                                    oocs::LaunchParams sub = tr.lp;
+                                    sub.njobs = 0;
+                                    for (int q = 0; q < tr.lp.njobs; ++q)
+                                        if (job_stage(tr.lp.jobs[q].kind) == stage) sub.jobs[sub.njobs++] = tr.lp.jobs[q];
+                                    if (sub.njobs == 0) continue;
+                                    if (bevent(stage, pl->st[1]) != OOCS_OK) return OOCS_E_HIP;
+                                    HIP_TRY(oocs::launch_jobs(sub, pl->st[1]));
+                                    if (bevent_end(pl->st[1]) != OOCS_OK) return OOCS_E_HIP;
+                                }
+                            } else {
+                                HIP_TRY(oocs::launch_jobs(tr.lp, pl->st[1]));
+                            }
                             if (timed) {
                                 HIP_TRY(hipEventRecord(pl->tev[tused + 1], pl->st[1]));
                                 tused += 2;
@@ -994,6 +1107,17 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
         HIP_TRY(hipEventElapsedTime(&ms, pl->tev[i], pl->tev[i + 1]));
         kms += ms;
     }
+    double stage_ms[5] = {0, 0, 0, 0, 0};
+    for (size_t i = 0; i + 1 < bused; i += 2) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, pl->bev[i], pl->bev[i + 1]));
+        stage_ms[bstage[i / 2]] += ms;
+    }
+    if (use_sdma && bdown) {
+        stage_ms[4] += pl->sdma.busy_ms();
+        const int rc = pl->sdma.set_timing(false);
+        if (rc != OOCS_OK) return rc;
+    }
     if (st) {
         st->wall_ms = wall;
         st->enqueue_ms = enq;
@@ -1009,6 +1133,8 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
         st->timed_bytes = tbytes;
         st->sdma_copies = sdma_copies;
         st->kernel_ms = kms;
+        for (int q = 0; q < 5; ++q) st->stage_ms[q] = bdown ? stage_ms[q] : 0.0;
+        st->arena_bytes = P.arena_needed;
     }
     return OOCS_OK;
 }

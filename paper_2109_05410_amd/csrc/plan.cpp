@@ -55,7 +55,7 @@ int Planner::init(const oocs_config& c, std::string& err)
     if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
     if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS | OOCS_PLAN_LEVEL_BY_LEVEL |
-                    OOCS_PLAN_KERNEL_STORES)) {
+                    OOCS_PLAN_KERNEL_STORES | OOCS_PLAN_RESIDENT_RO)) {
         err = "unknown plan flags";
         return OOCS_E_ARG;
     }
@@ -63,6 +63,9 @@ int Planner::init(const oocs_config& c, std::string& err)
     fused = c.stencil == OOCS_HEAT7 && k <= kMaxFusedSteps && !restart && !(c.flags & OOCS_PLAN_LEVEL_BY_LEVEL);
     copy_engines = (c.flags & OOCS_PLAN_KERNEL_TRANSFERS) == 0;
     kernel_stores = copy_engines && (c.flags & OOCS_PLAN_KERNEL_STORES) != 0;
+    resident_ro = (c.flags & OOCS_PLAN_RESIDENT_RO) != 0;
+    if (resident_ro && !has_ro) { err = "a resident read-only field needs the wave stencil"; return OOCS_E_ARG; }
+    if (resident_ro) in_fields = {0, 1};  // the read-only field is loaded once, outside the residencies
     // kernel-driven transfers fetch one group ahead inside the launch: two slots suffice;
     // copy engines keep three groups in flight ahead of the decode
     nstage = c.nstage ? c.nstage : (copy_engines ? 4 : 2);
@@ -245,7 +248,7 @@ int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
                 read(L.lv - 1, L.z0 - (int64_t)r * L.steps, L.z1 + (int64_t)r * L.steps, ti);
                 if (nin == 2) {
                     read(L.lv - 2, L.z0, L.z1, ti);
-                    read(ro_ring(), L.z0, L.z1, ti);
+                    if (!resident_ro) read(ro_ring(), L.z0, L.z1, ti);
                 }
             }
             if (t.out_group >= 0)
@@ -269,6 +272,7 @@ int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
                 if (mx[ti] >= mn[ti]) W[ring] = std::max(W[ring], mx[ti] - mn[ti] + 1);
         }
     }
+    if (resident_ro) W[ro_ring()] = nz;  // the whole decoded field
     ringW = W;
     ringOff.assign(R, 0);
     const int64_t pb = plane_elems() * 4;
@@ -282,6 +286,11 @@ int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
         in_slot_bytes[fld] = align_up(G * store_plane_bytes(fld), 256);
         in_off[fld] = off;
         off += in_slot_bytes[fld] * nstage;
+    }
+    if (resident_ro) {  // one slot to load the read-only field group by group
+        in_slot_bytes[2] = align_up(G * store_plane_bytes(2), 256);
+        in_off[2] = off;
+        off += in_slot_bytes[2];
     }
     for (int fld : out_fields) {
         out_slot_bytes[fld] = align_up(G * store_plane_bytes(fld), 256);

@@ -82,6 +82,7 @@ public:
     bool copy_engines = true;   // loads by hipMemcpyAsync on a copy stream (else by the kernel)
     bool kernel_stores = false; // with copy_engines: write-back by STORE jobs in the launches (else by D2H copies)
     bool fused = false;         // heat: one temporally blocked job per tick computes all k levels
+    bool resident_ro = false;   // wave: the read-only field stays decoded in an nz-plane ring
     static constexpr int kMaxFusedSteps = 4;
     int64_t slab = 0, h = 0;
     std::vector<int64_t> a;  // n+1 block bounds

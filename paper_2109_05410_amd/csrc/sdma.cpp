@@ -28,6 +28,10 @@ struct HsaApi {
     decltype(&hsa_signal_store_relaxed) signal_store = nullptr;
     decltype(&hsa_amd_memory_async_copy) async_copy = nullptr;
     decltype(&hsa_amd_pointer_info) pointer_info = nullptr;
+    // copy timing (optional: only the breakdown mode needs them)
+    decltype(&hsa_amd_profiling_async_copy_enable) copy_prof_enable = nullptr;
+    decltype(&hsa_amd_profiling_get_async_copy_time) copy_time = nullptr;
+    decltype(&hsa_system_get_info) system_info = nullptr;
     bool ok = false;
 };
 
@@ -45,6 +49,10 @@ const HsaApi& api()
         r.signal_store = reinterpret_cast<decltype(r.signal_store)>(dlsym(h, "hsa_signal_store_relaxed"));
         r.async_copy = reinterpret_cast<decltype(r.async_copy)>(dlsym(h, "hsa_amd_memory_async_copy"));
         r.pointer_info = reinterpret_cast<decltype(r.pointer_info)>(dlsym(h, "hsa_amd_pointer_info"));
+        r.copy_prof_enable =
+            reinterpret_cast<decltype(r.copy_prof_enable)>(dlsym(h, "hsa_amd_profiling_async_copy_enable"));
+        r.copy_time = reinterpret_cast<decltype(r.copy_time)>(dlsym(h, "hsa_amd_profiling_get_async_copy_time"));
+        r.system_info = reinterpret_cast<decltype(r.system_info)>(dlsym(h, "hsa_system_get_info"));
         r.ok = r.agent_get_info && r.signal_create && r.signal_destroy && r.signal_load && r.signal_store &&
                r.async_copy && r.pointer_info;
         return r;
@@ -73,6 +81,7 @@ SdmaCopier::~SdmaCopier()
 {
     if (!ready_) return;
     (void)drain();
+    if (timing_) (void)api().copy_prof_enable(false);
     for (uint64_t s : sig_) api().signal_destroy(hsa_signal_t{s});
 }
 
@@ -114,13 +123,43 @@ bool SdmaCopier::host_agent(const void* host, uint64_t* agent) const
     return true;
 }
 
+int SdmaCopier::set_timing(bool on)
+{
+    if (!ready_) return fail(OOCS_E_STATE, "SDMA copier not initialised");
+    const HsaApi& a = api();
+    if (on && (!a.copy_prof_enable || !a.copy_time || !a.system_info))
+        return fail(OOCS_E_HIP, "HSA copy timing entry points not found");
+    if (on == timing_) {
+        busy_ms_ = 0.0;
+        return OOCS_OK;
+    }
+    const int rc = drain();  // copies in flight were issued under the old setting
+    if (rc != OOCS_OK) return rc;
+    if (on && tick_ms_ == 0.0) {
+        uint64_t freq = 0;
+        if (a.system_info(HSA_SYSTEM_INFO_TIMESTAMP_FREQUENCY, &freq) != HSA_STATUS_SUCCESS || freq == 0)
+            return fail(OOCS_E_HIP, "HSA timestamp frequency unavailable");
+        tick_ms_ = 1e3 / (double)freq;
+    }
+    if (a.copy_prof_enable(on) != HSA_STATUS_SUCCESS) return fail(OOCS_E_HIP, "hsa_amd_profiling_async_copy_enable failed");
+    timing_ = on;
+    busy_ms_ = 0.0;
+    return OOCS_OK;
+}
+
 int SdmaCopier::advance()
 {
     const HsaApi& a = api();
     while (done_ < issued_) {
-        const hsa_signal_value_t v = a.signal_load(hsa_signal_t{sig_[done_ % kRing]});
+        const hsa_signal_t s{sig_[done_ % kRing]};
+        const hsa_signal_value_t v = a.signal_load(s);
         if (v > 0) break;
         if (v < 0) return fail(OOCS_E_HIP, "SDMA device-to-host copy reported an error");
+        if (timing_) {  // before the signal can be reused by a later copy
+            hsa_amd_profiling_async_copy_time_t t{};
+            if (a.copy_time(s, &t) == HSA_STATUS_SUCCESS && t.end >= t.start)
+                busy_ms_ += (double)(t.end - t.start) * tick_ms_;
+        }
         ++done_;
     }
     return OOCS_OK;

@@ -47,6 +47,12 @@ public:
     int copy(void* dst, uint64_t agent, const void* src, size_t bytes);
 
     int64_t issued() const { return issued_; }
+    // Copy timing (off by default): while on, the engine timestamps every
+    // copy (hsa_amd_profiling_async_copy_enable, process-wide) and the
+    // summed start-to-end durations of the copies seen completing are
+    // accumulated. Turning it on resets the sum. OOCS_OK or OOCS_E_HIP.
+    int set_timing(bool on);
+    double busy_ms() const { return busy_ms_; }
     // Block until the first t copies have completed. OOCS_OK, or OOCS_E_HIP
     // on a copy error or after a minute without completion.
     int wait(int64_t t);
@@ -57,6 +63,9 @@ private:
 
     static constexpr int kRing = 64;
     bool ready_ = false;
+    bool timing_ = false;
+    double busy_ms_ = 0.0;
+    double tick_ms_ = 0.0;  // milliseconds per HSA system timestamp tick
     uint64_t gpu_ = 0;
     std::vector<uint64_t> sig_;
     int64_t issued_ = 0, done_ = 0;

@@ -1,6 +1,7 @@
 """The C ABI library loads without a GPU and exports every function that
 include/oocs.h declares; the Python binding covers exactly that set."""
 import ctypes
+import ctypes as C
 import os
 import re
 import subprocess
@@ -73,3 +74,13 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+def test_no_alloc_size_limit_is_checked_before_any_device_call():
+    """Fields beyond the library-held scratch are refused up front (no HIP
+    call is made, so this runs without a GPU)."""
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)  # never dereferenced: the size check comes first
+    n = L.OOCS_NOALLOC_MAX_CELLS
+    assert lib.oocs_heat7_step_k_noalloc(fake, 4096, 4096, n // (4096 * 4096) + 1, C.c_float(0.1), 1, None) == L.OOCS_E_SIZE
+    assert lib.oocs_heat7_step_k_noalloc(None, 4, 4, 4, C.c_float(0.1), 1, None) == L.OOCS_E_ARG

@@ -68,7 +68,10 @@ def test_heat_out_of_core_matches_replay(rate, k, steps, n, arena, graphs, ce):
 
 @pytest.mark.parametrize("graphs,ce", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("rates,k,steps", [([0, 0, 0], 4, 10), ([8, 12, 8], 4, 10), ([16, 16, 16], 3, 7),
-                                           ([12, 0, 12], 1, 3)])
+                                           ([12, 0, 12], 1, 3),
+                                           # the paper's codes 2, 3 and 4 (Sec. VI): one read-write field
+                                           # (p(n-1)), the read-only field, both compressed
+                                           ([0, 12, 0], 4, 9), ([0, 0, 12], 4, 9), ([0, 12, 12], 4, 9)])
 def test_wave_out_of_core_matches_replay(rates, k, steps, graphs, ce):
     shape = (96, 36, 40)
     rng = np.random.default_rng(k)
@@ -89,6 +92,38 @@ def test_wave_out_of_core_matches_replay(rates, k, steps, graphs, ce):
     assert np.array_equal(decoded(st[1], shape, rates[1]), wpm)
     # the read-only store is never rewritten
     assert np.array_equal(decoded(st[2], shape, rates[2]), O.codec_roundtrip(w, rates[2]) if rates[2] else w)
+
+
+@pytest.mark.parametrize("graphs,ce", MODES, ids=MODE_IDS)
+@pytest.mark.parametrize("rates", [[12, 12, 12], [0, 8, 8], [8, 8, 0]])
+def test_resident_read_only_matches_replay(rates, graphs, ce):
+    """The read-only field decoded once and kept on the device gives the
+    same stores as streaming it; the load is redone after store I/O through
+    the arena and for another read-only store."""
+    shape = (96, 36, 40)
+    rng = np.random.default_rng(3)
+    p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    pm0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    w2 = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    amps = rng.standard_normal(14).astype(np.float32)
+    cell = (17, 20, 50)
+    idx = cell[0] + shape[2] * (cell[1] + shape[1] * cell[2])
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 2, 4, rates, 16 * MiB, src_cell=cell, resident_ro=True, **xfer(ce))
+    plan.set_graphs(graphs)
+    st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
+    plan.run(st, 9, src_amps=amps[:9])
+    wp, wpm, _ = O.replay_wave_f32(p0, pm0, w, 9, 4, src=(amps[:9], idx), rate_p=rates[0], rate_pm=rates[1],
+                                   rate_w=rates[2])
+    assert np.array_equal(decoded(st[0], shape, rates[0]), wp)
+    assert np.array_equal(decoded(st[1], shape, rates[1]), wpm)
+    # a second read-only store (another velocity model) on the same plan
+    st2 = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w2)]
+    plan.run(st2, 5, src_amps=amps[9:14])
+    wp2, wpm2, _ = O.replay_wave_f32(p0, pm0, w2, 5, 4, src=(amps[9:14], idx), rate_p=rates[0], rate_pm=rates[1],
+                                     rate_w=rates[2])
+    assert np.array_equal(decoded(st2[0], shape, rates[0]), wp2)
+    assert np.array_equal(decoded(st2[1], shape, rates[1]), wpm2)
 
 
 @pytest.mark.parametrize("graphs,ce", MODES, ids=MODE_IDS)

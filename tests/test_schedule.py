@@ -371,6 +371,9 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
             return np.zeros((ny, nx), np.float32)
         return rings[R][z % g.W[R]]
 
+    if p.cfg.flags & L.OOCS_PLAN_RESIDENT_RO:  # decoded once, before the residencies
+        rings[g.ro][:nz] = from_store(store[2], p.shape, rates[2])
+
     done = 0
     while done < steps:
         kr = min(g.k, steps - done)
@@ -502,3 +505,47 @@ def test_schedule_staging_depths(nstage):
     store = [to_store(u0, 8)]
     execute(p, store, 11, None)
     assert np.array_equal(from_store(store[0], (48, 12, 16), 8), O.replay_heat_f32(u0, 0.1, 11, 4, 8))
+
+
+@pytest.mark.parametrize("rates", [[12, 12, 12], [0, 8, 8], [8, 8, 0]])
+@pytest.mark.parametrize("ce", ["copy", "hybrid", "kernel"])
+def test_resident_read_only_schedule(rates, ce):
+    """With the read-only field resident its ring holds the whole field, no
+    op of any residency moves or decodes it, the schedule has no races and
+    it still computes the oracle's replay."""
+    shape = (64, 12, 12)
+    rng = np.random.default_rng(7)
+    p0 = rng.standard_normal(shape).astype(np.float32)
+    pm0 = rng.standard_normal(shape).astype(np.float32)
+    w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    steps, k = 8, 3
+    amps = rng.standard_normal(steps).astype(np.float32)
+    src = (5, 6, 20)
+    p = plan(shape, WAVE25, 2, k, rates, 4 * MiB, src_cell=src, resident_ro=True, **xfer(ce))
+    g = Geometry(p)
+    assert g.W[g.ro] == shape[0]
+    for kr in range(1, k + 1):
+        assert all(o["field"] != 2 for o in p.schedule(kr))
+    race_check(p, steps)
+    race_check(p, steps, graph_mode=True)
+    store = [to_store(p0, rates[0]), to_store(pm0, rates[1]), to_store(w, rates[2])]
+    execute(p, store, steps, amps)
+    idx = src[0] + shape[2] * (src[1] + shape[1] * src[2])
+    wp, wpm, _ = O.replay_wave_f32(p0, pm0, w, steps, k, src=(amps, idx), rate_p=rates[0], rate_pm=rates[1],
+                                   rate_w=rates[2])
+    assert np.array_equal(from_store(store[0], shape, rates[0]), wp)
+    assert np.array_equal(from_store(store[1], shape, rates[1]), wpm)
+
+
+def test_resident_read_only_arena_and_errors():
+    """The resident field costs its nz planes of arena (the 1024^3 wave at
+    12 bits still fits 8 GiB, with smaller groups); heat has no read-only
+    field to keep."""
+    streamed = plan((1024, 1024, 1024), WAVE25, 8, 12, [12, 12, 12], 8 << 30)
+    resident = plan((1024, 1024, 1024), WAVE25, 8, 12, [12, 12, 12], 8 << 30, resident_ro=True)
+    ri = resident.info
+    assert ri["ring_planes"][-1] == 1024
+    assert ri["arena_needed"] <= 8 << 30
+    assert ri["group"] <= streamed.info["group"]
+    with pytest.raises(L.OocsError):
+        plan((64, 16, 16), HEAT7, 2, 2, [8], 4 * MiB, resident_ro=True)
