@@ -43,6 +43,7 @@ extern "C" {
 #define OOCS_E_SIZE -6   /* a caller buffer is too small */
 #define OOCS_E_HIP -7    /* a HIP runtime call failed (message has the HIP error) */
 #define OOCS_E_STATE -8  /* the object cannot do this (e.g. a planning-only plan asked to run) */
+#define OOCS_E_TIMEOUT -9 /* a bounded device-side wait gave up (the kernel still ended normally) */
 
 #define OOCS_HEAT7 1  /* 7-point Jacobi heat stencil, radius 1 */
 #define OOCS_WAVE25 2 /* 25-point 8th-order acoustic wave, radius 4, two time levels */
@@ -241,6 +242,21 @@ typedef struct {
  * otherwise). */
 #define OOCS_PLAN_RESIDENT_RO 16
 
+/* Plan flag: snake sweeps (alternating direction). Residency i of an
+ * oocs_run call streams the grid upward in z if i is even, downward if odd,
+ * and the block it ends with stays on the device for the next residency,
+ * which starts with it: its compressed (or raw) output is written into a
+ * retained buffer of the arena instead of the host store, and the next
+ * residency decodes it from there instead of loading it. The last block
+ * of every residency but the call's last therefore crosses the host link
+ * neither way; the read-only field is still streamed. Same results (the
+ * retained planes pass through the codec exactly as the stored ones).
+ * Needs the copy-engine transfers (no OOCS_PLAN_KERNEL_TRANSFERS or
+ * OOCS_PLAN_KERNEL_STORES), no OOCS_PLAN_BLOCK_RESTART and nslabs >= 2;
+ * the retained buffers take one slab of every read-write field from the
+ * arena. */
+#define OOCS_PLAN_SNAKE 32
+
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be
  * queried but not run (no HIP call is made for it). Chooses the group size
@@ -266,6 +282,7 @@ typedef struct {
     int64_t arena_needed;       /* device bytes the plan uses (<= arena size) */
     int64_t nstage;             /* staging slots per direction */
     int64_t store_bytes[OOCS_MAX_FIELDS]; /* host store bytes per field (0 for an unused slot) */
+    int64_t retained_planes;    /* planes of the retained block (snake plans), else 0 */
 } oocs_plan_info;
 
 int oocs_plan_get_info(const oocs_plan* plan, oocs_plan_info* out);
@@ -313,6 +330,20 @@ typedef struct {
  * building and caching it on first use. Returns < 0 on error. */
 int64_t oocs_plan_schedule_len(oocs_plan* plan, int kr);
 int oocs_plan_schedule_op(oocs_plan* plan, int kr, int64_t index, oocs_op* out);
+
+/* Schedule variants of snake plans (OOCS_PLAN_SNAKE), OR-ed: the residency
+ * runs downward in z (its op ranges and blocks are those of the upward
+ * schedule mirrored), takes its first block from the retained buffer, and
+ * leaves its last block there. oocs_run uses for residency i of R:
+ * MIRROR if i is odd, RETAIN_IN if i > 0, RETAIN_OUT if i < R - 1. Decode
+ * and encode ops on the retained buffer carry slot OOCS_SLOT_RETAINED and
+ * have no copy. Variant 0 is the schedule above. */
+#define OOCS_SCHED_MIRROR 1
+#define OOCS_SCHED_RETAIN_IN 2
+#define OOCS_SCHED_RETAIN_OUT 4
+#define OOCS_SLOT_RETAINED (-2)
+int64_t oocs_plan_schedule_variant_len(oocs_plan* plan, int kr, int variant);
+int oocs_plan_schedule_variant_op(oocs_plan* plan, int kr, int variant, int64_t index, oocs_op* out);
 
 /* Host store size for a field slot: the field's compressed stream, or
  * nx*ny*nz*4 bytes if uncompressed; 0 for an unused slot. */
@@ -437,12 +468,18 @@ int oocs_run(oocs_plan* plan, void* const* h_store, int64_t steps, const float* 
 
 /* ------------------------------------------------------------------------
  * Batched in-core heat domains. Many independent domains of uneven sizes
- * advance together: one launch covers every domain (a work-list table maps
- * each workgroup to its domain, tile and z-chunk) for k steps, and the
- * launches of a run are replayed as one HIP graph. k > 1 is temporal
- * blocking: a workgroup advances its tile k steps in one pass over z,
- * recomputing a k-cell halo, so each cell crosses HBM once per k steps.
- * The tile shape is chosen per size bucket by a timing autotuner whose
+ * advance together. By default a run is one persistent kernel launch (one
+ * node of a HIP graph): its workgroups take items (domain, tile, group of k
+ * steps) in order from a device queue, and an item of group g of a domain
+ * starts once every tile of group g-1 of that domain has finished (a
+ * per-domain count of finished tiles, raised after a device-scope release).
+ * Waits are bounded: a wait that exceeds its poll limit sets a status word
+ * and every workgroup leaves, so the kernel always ends; oocs_batch_check
+ * reports it. The alternative mode replays one launch per group (every
+ * domain, k steps) as a graph. k > 1 is temporal blocking: a workgroup
+ * advances its tile k steps in one pass over z, recomputing a k-cell halo,
+ * so each cell crosses HBM once per k steps. The tile shape is chosen per
+ * size bucket by a timing autotuner (three or more shapes per depth) whose
  * results persist in a cache file, and the depth k (1, 2 or 4) per batch.
  * ------------------------------------------------------------------------ */
 
@@ -454,7 +491,8 @@ typedef struct {
 
 typedef struct oocs_batch oocs_batch;
 
-/* Device bytes of the work-list tables for nd domains. */
+/* Device bytes of the work-list tables and the persistent launch's counters
+ * for nd domains. */
 size_t oocs_batch_table_bytes(int nd);
 
 /* Create a batch of nd domains (heat, u' = u + alpha*Laplacian, zero
@@ -473,10 +511,30 @@ size_t oocs_batch_table_bytes(int nd);
 int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_table, size_t table_bytes,
                       const char* tune_cache, int tune, int depth, void* stream, oocs_batch** out);
 
-/* Advance every domain `steps` steps as one graph launch on `stream`
- * (steps / k launches at depth k, then steps mod k launches at depth 1;
- * built once per step count). Asynchronous. */
+/* Advance every domain `steps` steps as one graph launch on `stream`, built
+ * once per step count. Persistent mode (default): one kernel for the
+ * steps / k groups at depth k; when steps mod k > 0, a second persistent
+ * kernel for the remaining depth-1 groups; when the number of groups is
+ * odd, copy items move the result from the scratch buffers to u (in the
+ * depth-1 kernel, or in a third small one). Launch mode: steps / k launches
+ * at depth k, then steps mod k at depth 1, then copies if needed.
+ * Asynchronous; with the persistent mode call oocs_batch_check to learn
+ * whether a wait gave up. */
 int oocs_batch_run(oocs_batch* b, int64_t steps, void* stream);
+
+/* 1 (default): runs are persistent launches; 0: one launch per group. */
+int oocs_batch_set_persistent(oocs_batch* b, int on);
+
+/* Poll limit of the persistent kernel's waits (default 2^21 polls, each
+ * after a short sleep; seconds in all). never_satisfied = 1 is a test hook:
+ * no wait is ever satisfied, so the first wait gives up after `polls`
+ * polls, sets the status and every workgroup leaves. */
+int oocs_batch_set_wait_limit(oocs_batch* b, int64_t polls, int never_satisfied);
+
+/* Synchronizes `stream`, then reads the persistent launches' status word:
+ * OOCS_OK, or OOCS_E_TIMEOUT if a wait gave up since the last check (the
+ * status is cleared; the domains' states are then undefined). */
+int oocs_batch_check(oocs_batch* b, void* stream);
 
 /* Baseline: the same launches as separate kernel launches, domain after
  * domain. */

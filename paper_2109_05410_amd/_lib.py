@@ -19,6 +19,7 @@ OOCS_E_RATE = -5
 OOCS_E_SIZE = -6
 OOCS_E_HIP = -7
 OOCS_E_STATE = -8
+OOCS_E_TIMEOUT = -9
 
 OOCS_HEAT7 = 1
 OOCS_WAVE25 = 2
@@ -30,6 +31,11 @@ OOCS_PLAN_KERNEL_TRANSFERS = 2
 OOCS_PLAN_LEVEL_BY_LEVEL = 4
 OOCS_PLAN_KERNEL_STORES = 8
 OOCS_PLAN_RESIDENT_RO = 16
+OOCS_PLAN_SNAKE = 32
+OOCS_SCHED_MIRROR = 1
+OOCS_SCHED_RETAIN_IN = 2
+OOCS_SCHED_RETAIN_OUT = 4
+OOCS_SLOT_RETAINED = -2
 
 OP_H2D, OP_DECODE, OP_LEVEL, OP_ENCODE, OP_D2H, OP_LAUNCH, OP_RECORD, OP_WAIT, OP_FETCH, OP_STORE = range(1, 11)
 
@@ -55,6 +61,7 @@ class PlanInfo(C.Structure):
         ("group", C.c_int64), ("halo", C.c_int64), ("radius", C.c_int64), ("nlevels", C.c_int64),
         ("nrings", C.c_int64), ("ring_planes", C.c_int64 * 16), ("plane_bytes", C.c_int64),
         ("arena_needed", C.c_int64), ("nstage", C.c_int64), ("store_bytes", C.c_int64 * OOCS_MAX_FIELDS),
+        ("retained_planes", C.c_int64),
     ]
 
 
@@ -119,6 +126,8 @@ _SIGS = {
     "oocs_plan_slab": (C.c_int, [_P, C.c_int, C.POINTER(SlabInfo)]),
     "oocs_plan_schedule_len": (C.c_int64, [_P, C.c_int]),
     "oocs_plan_schedule_op": (C.c_int, [_P, C.c_int, _I64, C.POINTER(Op)]),
+    "oocs_plan_schedule_variant_len": (C.c_int64, [_P, C.c_int, C.c_int]),
+    "oocs_plan_schedule_variant_op": (C.c_int, [_P, C.c_int, C.c_int, _I64, C.POINTER(Op)]),
     "oocs_store_bytes": (C.c_size_t, [_P, C.c_int]),
     "oocs_store_put": (C.c_int, [_P, C.c_int, _P, _P]),
     "oocs_store_get": (C.c_int, [_P, C.c_int, _P, _P]),
@@ -135,6 +144,9 @@ _SIGS = {
     "oocs_batch_create": (C.c_int, [C.POINTER(Domain), C.c_int, C.c_float, _P, C.c_size_t, C.c_char_p, C.c_int,
                                     C.c_int, _P, C.POINTER(_P)]),
     "oocs_batch_run": (C.c_int, [_P, _I64, _P]),
+    "oocs_batch_set_persistent": (C.c_int, [_P, C.c_int]),
+    "oocs_batch_set_wait_limit": (C.c_int, [_P, _I64, C.c_int]),
+    "oocs_batch_check": (C.c_int, [_P, _P]),
     "oocs_batch_run_per_domain": (C.c_int, [_P, _I64, _P]),
     "oocs_batch_domain_tile": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                          C.POINTER(C.c_int)]),

@@ -217,13 +217,15 @@ class OutOfCorePlan:
     k <= 4): one job and one ring per time level instead of one temporally
     blocked job per tick. resident_ro (wave): the read-only field is decoded
     once into the arena and stays there instead of being streamed every
-    residency. Results are identical."""
+    residency. snake: residencies alternate the sweep direction and the
+    block a residency ends with stays on the device (compressed, or raw if
+    uncompressed) for the next one. Results are identical."""
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
                  planning_only: bool = False, device=None, block_restart: bool = False,
                  kernel_transfers: bool = False, level_by_level: bool = False, kernel_stores: bool = False,
-                 resident_ro: bool = False):
+                 resident_ro: bool = False, snake: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -239,7 +241,8 @@ class OutOfCorePlan:
                      | (L.OOCS_PLAN_KERNEL_TRANSFERS if kernel_transfers else 0)
                      | (L.OOCS_PLAN_LEVEL_BY_LEVEL if level_by_level else 0)
                      | (L.OOCS_PLAN_KERNEL_STORES if kernel_stores else 0)
-                     | (L.OOCS_PLAN_RESIDENT_RO if resident_ro else 0))
+                     | (L.OOCS_PLAN_RESIDENT_RO if resident_ro else 0)
+                     | (L.OOCS_PLAN_SNAKE if snake else 0))
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg
@@ -274,6 +277,7 @@ class OutOfCorePlan:
             "group": i.group, "halo": i.halo, "radius": i.radius, "nlevels": i.nlevels, "nrings": i.nrings,
             "ring_planes": list(i.ring_planes[: i.nrings]), "plane_bytes": i.plane_bytes,
             "arena_needed": i.arena_needed, "nstage": i.nstage, "store_bytes": list(i.store_bytes),
+            "retained_planes": i.retained_planes,
         }
 
     def slab(self, i: int) -> dict:
@@ -281,14 +285,23 @@ class OutOfCorePlan:
         L.check(L.lib().oocs_plan_slab(self._h, i, C.byref(s)))
         return {k: (list(getattr(s, k)) if k.endswith(("_off", "_bytes")) else getattr(s, k)) for k, _ in s._fields_}
 
-    def schedule(self, kr: int) -> list[dict]:
-        n = L.check(L.lib().oocs_plan_schedule_len(self._h, kr))
+    def schedule(self, kr: int, variant: int = 0) -> list[dict]:
+        """Op list of a residency of kr steps; variant: OOCS_SCHED_* bits
+        (snake plans)."""
+        n = L.check(L.lib().oocs_plan_schedule_variant_len(self._h, kr, variant))
         ops = []
         o = L.Op()
         for i in range(n):
-            L.check(L.lib().oocs_plan_schedule_op(self._h, kr, i, C.byref(o)))
+            L.check(L.lib().oocs_plan_schedule_variant_op(self._h, kr, variant, i, C.byref(o)))
             ops.append({k: getattr(o, k) for k, _ in o._fields_})
         return ops
+
+    def variant(self, i: int, nres: int) -> int:
+        """Schedule variant oocs_run uses for residency i of nres."""
+        if not self.cfg.flags & L.OOCS_PLAN_SNAKE:
+            return 0
+        return ((L.OOCS_SCHED_MIRROR if i % 2 else 0) | (L.OOCS_SCHED_RETAIN_IN if i > 0 else 0)
+                | (L.OOCS_SCHED_RETAIN_OUT if i < nres - 1 else 0))
 
     def store_bytes(self, f: int) -> int:
         return int(L.lib().oocs_store_bytes(self._h, f))
@@ -447,8 +460,10 @@ class WaveMisfit(torch.autograd.Function):
 # ---------------------------------------------------------------------------
 
 class HeatBatch:
-    """Independent heat domains advanced together (one launch per k steps for
-    all domains, all launches replayed as one graph). `fields` are
+    """Independent heat domains advanced together: by default one persistent
+    kernel per run (items of every domain, tile and group of k steps from a
+    device queue), replayed as a graph; persistent=False: one launch per k
+    steps for all domains, all launches replayed as one graph. `fields` are
     (nz, ny, nx) float32 device tensors, updated in place by run(). depth:
     0 = temporal-blocking depth chosen by the autotuner, or 1, 2, 4."""
 
@@ -471,8 +486,21 @@ class HeatBatch:
                                           int(depth), _stream_ptr(), C.byref(h)))
         self._h = h
 
-    def run(self, steps: int, stream=None):
+    def run(self, steps: int, stream=None, check: bool = False):
+        """Advance every domain; check=True waits for the run and raises if a
+        persistent launch's bounded wait gave up."""
         L.check(L.lib().oocs_batch_run(self._h, steps, _stream_ptr(stream)))
+        if check:
+            self.check(stream)
+
+    def check(self, stream=None):
+        L.check(L.lib().oocs_batch_check(self._h, _stream_ptr(stream)))
+
+    def set_persistent(self, on: bool):
+        L.check(L.lib().oocs_batch_set_persistent(self._h, 1 if on else 0))
+
+    def set_wait_limit(self, polls: int, never_satisfied: bool = False):
+        L.check(L.lib().oocs_batch_set_wait_limit(self._h, int(polls), 1 if never_satisfied else 0))
 
     def run_per_domain(self, steps: int, stream=None):
         L.check(L.lib().oocs_batch_run_per_domain(self._h, steps, _stream_ptr(stream)))

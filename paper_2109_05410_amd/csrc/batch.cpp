@@ -27,10 +27,17 @@ struct oocs_batch {
     // (the steps left when the step count is not a multiple of the depth)
     std::vector<oocs::BatchDomain> table[2];
     oocs::BatchDomain* d_table = nullptr;  // both lists, [0] then [1]
+    int32_t* d_copy_begin = nullptr;       // nd + 1 prefix sums of copy items (persistent launches)
+    uint32_t* d_sync = nullptr;            // queue, exit count, status, per-domain counts
+    int32_t copy_items = 0;
     int32_t total_wg[2] = {0, 0};
     size_t lds[2] = {0, 0};
+    int grid[2] = {0, 0};                  // persistent grid: [0] blocked tiles, [1] depth-1 tiles
     int depth = 1;
     float alpha = 0.1f;
+    bool persistent = true;
+    int64_t spin_limit = (int64_t)1 << 21;
+    bool force_wait = false;
     std::map<int64_t, hipGraphExec_t> graphs;  // by step count
 };
 
@@ -163,7 +170,16 @@ int time_batch(oocs::BatchDomain* d_table, const std::vector<oocs::BatchDomain>&
 
 extern "C" {
 
-size_t oocs_batch_table_bytes(int nd) { return nd > 0 ? 2 * (size_t)nd * sizeof(oocs::BatchDomain) : 0; }
+// Device buffer layout: the two work lists, the copy-item prefix sums
+// (nd + 1 int32, padded to 16 bytes), then the persistent launch's counters
+// (kBatchSyncWords + nd uint32).
+static size_t copy_begin_offset(int nd) { return 2 * (size_t)nd * sizeof(oocs::BatchDomain); }
+static size_t sync_offset(int nd) { return copy_begin_offset(nd) + ((size_t)(nd + 1) * 4 + 15) / 16 * 16; }
+
+size_t oocs_batch_table_bytes(int nd)
+{
+    return nd > 0 ? sync_offset(nd) + ((size_t)oocs::kBatchSyncWords + nd) * 4 : 0;
+}
 
 int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_table, size_t table_bytes,
                       const char* tune_cache, int tune, int depth, void* stream, oocs_batch** out)
@@ -184,6 +200,8 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
     b->doms.assign(doms, doms + nd);
     b->alpha = alpha;
     b->d_table = static_cast<oocs::BatchDomain*>(d_table);
+    b->d_copy_begin = reinterpret_cast<int32_t*>(static_cast<char*>(d_table) + copy_begin_offset(nd));
+    b->d_sync = reinterpret_cast<uint32_t*>(static_cast<char*>(d_table) + sync_offset(nd));
     const std::string arch = arch_name();
     std::map<std::string, int> cache = read_cache(tune_cache);
     bool cache_dirty = false;
@@ -285,13 +303,111 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
         const int rc = build_table(w == 0 ? b->depth : 1, b->table[w], b->total_wg[w], b->lds[w]);
         if (rc) { delete b; return rc; }
     }
+    // copy items of each domain (a result left in the scratch buffer is moved
+    // back to u by items of kBatchCopyFloats floats)
+    std::vector<int32_t> copy_begin(nd + 1, 0);
+    for (int i = 0; i < nd; ++i) {
+        const int64_t n = doms[i].nx * doms[i].ny * doms[i].nz;
+        const int64_t items = (n + oocs::kBatchCopyFloats - 1) / oocs::kBatchCopyFloats;
+        if (copy_begin[i] + items > INT32_MAX / 2) { delete b; return fail(OOCS_E_ARG, "batch too large"); }
+        copy_begin[i + 1] = copy_begin[i] + (int32_t)items;
+    }
+    b->copy_items = copy_begin[nd];
+    for (int w = 0; w < 2; ++w) {
+        const int rc = oocs::batch_persistent_grid(w == 0, std::max(b->lds[0], b->lds[1]), &b->grid[w]);
+        if (rc != hipSuccess) { delete b; return oocs::hip_fail((hipError_t)rc, "occupancy query"); }
+    }
     hipError_t e = hipMemcpyAsync(b->d_table, b->table[0].data(), nd * sizeof(oocs::BatchDomain), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_table + nd, b->table[1].data(), nd * sizeof(oocs::BatchDomain), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_copy_begin, copy_begin.data(), (nd + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = oocs::launch_zero_words(b->d_sync, oocs::kBatchSyncWords + nd, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { delete b; return oocs::hip_fail(e, "table upload"); }
     *out = b;
     return OOCS_OK;
+}
+
+namespace {
+
+// The persistent launches of a run: the groups at the batch depth, then
+// those at depth 1 (steps mod depth), then the copy items if the number of
+// groups is odd (with the depth-1 launch, or alone after a blocked one).
+// Each launch is one kernel node; each waits for the one before.
+hipError_t add_persistent_nodes(const oocs_batch* b, int64_t steps, hipGraph_t g)
+{
+    const int nd = (int)b->doms.size();
+    const int64_t full = steps / b->depth, rest = steps % b->depth;
+    const bool odd = ((full + rest) & 1) != 0;
+    const size_t lds = std::max(b->lds[0], b->lds[1]);
+    struct L { int w; int64_t groups; int64_t parity0; bool copy; };
+    std::vector<L> ls;
+    const bool tb0 = b->depth > 1;
+    if (full > 0) ls.push_back({0, full, 0, odd && rest == 0 && !tb0});
+    if (rest > 0) ls.push_back({1, rest, full & 1, odd});
+    if (odd && !(ls.back().copy)) ls.push_back({1, 0, 0, true});
+    hipGraphNode_t prev = nullptr;
+    for (const L& l : ls) {
+        if ((int64_t)b->total_wg[l.w] * l.groups + (l.copy ? b->copy_items : 0) >= ((int64_t)1 << 31))
+            return hipErrorInvalidValue;
+        oocs::BatchPersistArgs a{};
+        a.tab = b->d_table + (size_t)l.w * nd;
+        a.copy_begin = b->d_copy_begin;
+        a.sync = b->d_sync;
+        a.nd = nd;
+        a.groups = (int32_t)l.groups;
+        a.parity0 = (int32_t)l.parity0;
+        a.total = b->total_wg[l.w];
+        a.copy_items = l.copy ? b->copy_items : 0;
+        a.force_wait = b->force_wait ? 1 : 0;
+        a.spin_limit = b->spin_limit;
+        a.alpha = b->alpha;
+        const bool tb = l.w == 0 && tb0 && !l.copy;
+        hipGraphNode_t n;
+        const hipError_t e = oocs::add_batch_persistent_node(a, tb, b->grid[tb ? 0 : 1], lds, g, prev ? &prev : nullptr,
+                                                             prev ? 1 : 0, &n);
+        if (e != hipSuccess) return e;
+        prev = n;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+int oocs_batch_set_persistent(oocs_batch* b, int on)
+{
+    if (!b) return fail(OOCS_E_ARG, "bad argument");
+    if (b->persistent != (on != 0)) {
+        for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+        b->graphs.clear();
+    }
+    b->persistent = on != 0;
+    return OOCS_OK;
+}
+
+int oocs_batch_set_wait_limit(oocs_batch* b, int64_t polls, int never_satisfied)
+{
+    if (!b || polls < 0) return fail(OOCS_E_ARG, "bad argument");
+    b->spin_limit = polls;
+    b->force_wait = never_satisfied != 0;
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+    return OOCS_OK;
+}
+
+int oocs_batch_check(oocs_batch* b, void* stream)
+{
+    if (!b) return fail(OOCS_E_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    uint32_t status = 0;
+    HIP_TRY(hipMemcpy(&status, b->d_sync + 2, sizeof status, hipMemcpyDeviceToHost));
+    if (status == 0) return OOCS_OK;
+    HIP_TRY(oocs::launch_zero_words(b->d_sync, oocs::kBatchSyncWords + (int64_t)b->doms.size(), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return fail(OOCS_E_TIMEOUT, "a persistent batch launch gave up waiting for a dependency; the domains' states "
+                                "are undefined");
 }
 
 int oocs_batch_run(oocs_batch* b, int64_t steps, void* stream)
@@ -300,6 +416,16 @@ int oocs_batch_run(oocs_batch* b, int64_t steps, void* stream)
     if (steps == 0) return OOCS_OK;
     hipStream_t s = (hipStream_t)stream;
     auto it = b->graphs.find(steps);
+    if (it == b->graphs.end() && b->persistent) {
+        hipGraph_t g;
+        HIP_TRY(hipGraphCreate(&g, 0));
+        hipError_t e = add_persistent_nodes(b, steps, g);
+        hipGraphExec_t exec = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return oocs::hip_fail(e, "persistent batch graph");
+        it = b->graphs.emplace(steps, exec).first;
+    }
     if (it == b->graphs.end()) {
         hipGraph_t g;
         HIP_TRY(hipGraphCreate(&g, 0));

@@ -200,7 +200,7 @@ int oocs_heat7_step_k(float* d_u, float* d_tmp, int64_t nx, int64_t ny, int64_t 
     // launch.
     int tb = -1;
     for (int c = 0; c < oocs::kNumTileCfgs; ++c)
-        if (oocs::kTileCfgs[c].k == 4) tb = c;
+        if (oocs::kTileCfgs[c].k == 4 && oocs::kTileCfgs[c].ty == 16 && oocs::kTileCfgs[c].zc == 64) tb = c;
     int64_t t = 0;
     if (tb >= 0 && k >= 4) {
         const oocs::TileCfg& c = oocs::kTileCfgs[tb];
@@ -345,6 +345,7 @@ int oocs_plan_get_info(const oocs_plan* pl, oocs_plan_info* out)
     out->arena_needed = P.arena_needed;
     out->nstage = P.nstage;
     for (int f = 0; f < OOCS_MAX_FIELDS; ++f) out->store_bytes[f] = P.store_bytes(f);
+    out->retained_planes = P.X;
     return OOCS_OK;
 }
 
@@ -370,24 +371,31 @@ int oocs_plan_slab(const oocs_plan* pl, int i, oocs_slab_info* out)
     return OOCS_OK;
 }
 
-int64_t oocs_plan_schedule_len(oocs_plan* pl, int kr)
+int64_t oocs_plan_schedule_variant_len(oocs_plan* pl, int kr, int variant)
 {
     if (!pl) return fail(OOCS_E_ARG, "null pointer");
     std::string err;
-    const oocs::Schedule* s = pl->P.schedule(kr, err);
+    const oocs::Schedule* s = pl->P.schedule(kr, err, variant);
     if (!s) return fail(OOCS_E_ARG, err);
     return (int64_t)s->ops.size();
 }
 
-int oocs_plan_schedule_op(oocs_plan* pl, int kr, int64_t index, oocs_op* out)
+int oocs_plan_schedule_variant_op(oocs_plan* pl, int kr, int variant, int64_t index, oocs_op* out)
 {
     if (!pl || !out) return fail(OOCS_E_ARG, "null pointer");
     std::string err;
-    const oocs::Schedule* s = pl->P.schedule(kr, err);
+    const oocs::Schedule* s = pl->P.schedule(kr, err, variant);
     if (!s) return fail(OOCS_E_ARG, err);
     if (index < 0 || index >= (int64_t)s->ops.size()) return fail(OOCS_E_ARG, "op index out of range");
     *out = s->ops[index];
     return OOCS_OK;
+}
+
+int64_t oocs_plan_schedule_len(oocs_plan* pl, int kr) { return oocs_plan_schedule_variant_len(pl, kr, 0); }
+
+int oocs_plan_schedule_op(oocs_plan* pl, int kr, int64_t index, oocs_op* out)
+{
+    return oocs_plan_schedule_variant_op(pl, kr, 0, index, out);
 }
 
 size_t oocs_store_bytes(const oocs_plan* pl, int field)
@@ -677,8 +685,11 @@ struct OpTranslator {
             j.kind = rate ? (dec ? oocs::JOB_DECODE : oocs::JOB_ENCODE) : (dec ? oocs::JOB_COPY_IN : oocs::JOB_COPY_OUT);
             j.rate = rate;
             j.dst = ring(o.level);
-            j.stage = dec ? (void*)(pl->arena + P.in_off[o.field] + (int64_t)o.slot * P.in_slot_bytes[o.field])
-                          : (void*)(pl->arena + P.out_off[o.field] + (int64_t)o.slot * P.out_slot_bytes[o.field]);
+            if (o.slot == OOCS_SLOT_RETAINED)  // snake: the retained block, laid out like the host store
+                j.stage = pl->arena + P.ret_off[o.field] + (o.z0 - P.ret_base(o.z0)) * P.store_plane_bytes(o.field);
+            else
+                j.stage = dec ? (void*)(pl->arena + P.in_off[o.field] + (int64_t)o.slot * P.in_slot_bytes[o.field])
+                              : (void*)(pl->arena + P.out_off[o.field] + (int64_t)o.slot * P.out_slot_bytes[o.field]);
         }
         return true;
     }
@@ -726,11 +737,12 @@ int load_resident_ro(oocs_plan* pl, const void* h_ro)
 }
 
 // Builds the graph of one residency of kr steps.
-int build_graph(oocs_plan* pl, int kr, void* const* h_store, void* const* d_store, bool src_on, ResidencyGraph& out)
+int build_graph(oocs_plan* pl, int kr, int variant, void* const* h_store, void* const* d_store, bool src_on,
+                ResidencyGraph& out)
 {
     oocs::Planner& P = pl->P;
     std::string err;
-    const oocs::Schedule* sch = P.schedule(kr, err);
+    const oocs::Schedule* sch = P.schedule(kr, err, variant);
     if (!sch) return fail(OOCS_E_STATE, err);
     hipGraph_t g = nullptr;
     HIP_TRY(hipGraphCreate(&g, 0));
@@ -915,6 +927,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     }
 
     int64_t done = 0;
+    const int64_t nres = (steps + P.k - 1) / P.k;  // residencies of this call (snake variants)
     while (done < steps) {
         const int64_t chunk_end = std::min(steps, done + chunk_steps);
         if (src_on) {  // amplitudes of this chunk, counter at 0
@@ -926,16 +939,18 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
         int64_t chunk_round = 0;
         while (done < chunk_end) {
             const int kr = (int)std::min<int64_t>(P.k, chunk_end - done);
+            const int variant = P.variant_of(rounds, nres);
             std::string err;
-            const oocs::Schedule* sch = P.schedule(kr, err);
+            const oocs::Schedule* sch = P.schedule(kr, err, variant);
             if (!sch) return fail(OOCS_E_STATE, err);
             if (pl->graphs) {
-                auto key = std::make_tuple(kr, (const void*)h_store[0], (const void*)(P.nfields > 1 ? h_store[1] : nullptr),
+                auto key = std::make_tuple(kr + 64 * variant, (const void*)h_store[0],
+                                           (const void*)(P.nfields > 1 ? h_store[1] : nullptr),
                                            (const void*)(P.nfields > 2 ? h_store[2] : nullptr), src_on, pl->profiling);
                 auto it = pl->gcache.find(key);
                 if (it == pl->gcache.end()) {
                     ResidencyGraph rg;
-                    const int rc = build_graph(pl, kr, h_store, d_store, src_on, rg);
+                    const int rc = build_graph(pl, kr, variant, h_store, d_store, src_on, rg);
                     if (rc != OOCS_OK) {
                         if (rg.exec) (void)hipGraphExecDestroy(rg.exec);
                         for (hipEvent_t e : rg.timing) (void)hipEventDestroy(e);

@@ -125,8 +125,16 @@ struct TileCfg {
     int tx, ty, zc;  // threads per tile in x and y (k = 1) or tile size in cells (k > 1); planes per chunk
     int k;           // steps per launch (temporal-blocking depth)
 };
-constexpr int kNumTileCfgs = 10;
-extern const TileCfg kTileCfgs[kNumTileCfgs];
+// k = 1: threads per tile (tx * ty = 256) and planes marched per thread.
+// k > 1: a 64 x ty cell tile (halo k cells on each side included) advanced k
+// steps per launch over z chunks of zc planes (heat_tb). Three or more
+// candidates per depth. (Taller tiles at k = 4 raise the register count of
+// every blocked kernel: 20 rows took them from 67 to 82 VGPRs.)
+constexpr int kNumTileCfgs = 12;
+inline constexpr TileCfg kTileCfgs[kNumTileCfgs] = {
+    {64, 4, 16, 1},  {64, 4, 32, 1},   {64, 4, 64, 1},  {32, 8, 16, 1},   {128, 2, 16, 1},
+    {64, 4, 8, 1},   {64, 16, 64, 2},  {64, 16, 128, 2}, {64, 16, 32, 2}, {64, 16, 64, 4},
+    {64, 16, 32, 4}, {64, 16, 128, 4}};
 
 struct BatchDomain {   // one entry of the device work-list table
     float* a;          // field at even steps (the caller's u)
@@ -142,6 +150,36 @@ int32_t batch_domain_workgroups(int nx, int ny, int nz, int cfg);
 
 // Dynamic LDS bytes a tile configuration needs (0 for k = 1).
 size_t tile_cfg_lds(int cfg);
+
+// The persistent batched launch: one kernel runs groups of k steps of every
+// domain, as items (domain, tile, group) taken in order from a device queue;
+// an item of group g of domain d starts once every tile of group g-1 of d
+// has finished (a per-domain count of finished tiles). A launch holds the
+// groups of one work list; copy items after its last group move a result
+// left in the scratch buffers back to u (depth-1 launches only).
+struct BatchPersistArgs {
+    const BatchDomain* tab;     // work list of this launch's groups
+    const int32_t* copy_begin;  // nd + 1 prefix sums of each domain's copy items
+    uint32_t* sync;             // [0] queue head, [1] workgroups exited, [2] status, [3] unused, [4 + d] tiles done
+    int32_t nd;
+    int32_t groups;             // groups of this launch
+    int32_t parity0;            // parity of its first group (0: reads a, writes b)
+    int32_t total;              // items of one group
+    int32_t copy_items;
+    int32_t force_wait;         // test hook: no wait is ever satisfied
+    int64_t spin_limit;         // polls before a wait gives up and sets the status
+    float alpha;
+};
+constexpr int kBatchSyncWords = 4;         // words of the sync area before the per-domain counts
+constexpr int kBatchCopyFloats = 1 << 16;  // floats one copy item moves
+// tb: the list's tiles are temporally blocked (no copy items then).
+hipError_t launch_batch_persistent(const BatchPersistArgs& a, bool tb, int grid, size_t lds, hipStream_t stream);
+hipError_t add_batch_persistent_node(const BatchPersistArgs& a, bool tb, int grid, size_t lds, hipGraph_t g,
+                                     const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node);
+// Workgroups of the persistent launch: those that fit the device at once.
+hipError_t batch_persistent_grid(bool tb, size_t lds, int* grid);
+// Zero n words of device memory (a fill kernel, so that it may be captured).
+hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t stream);
 
 // One step of every domain: parity 0 reads a and writes b, 1 the reverse.
 hipError_t launch_batch_step(const BatchDomain* d_table, int nd, int32_t total_wg, size_t lds, int parity,

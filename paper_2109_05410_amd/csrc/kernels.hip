@@ -448,13 +448,6 @@ hipError_t launch_swap(float* a, float* b, int64_t n, hipStream_t stream)
 // Batched heat domains: one launch advances every domain one step
 // ---------------------------------------------------------------------------
 
-// k = 1: threads per tile (tx * ty = 256) and planes marched per thread.
-// k > 1: a 64 x ty cell tile (halo k cells on each side included) advanced k
-// steps per launch over z chunks of zc planes (heat_tb).
-const TileCfg kTileCfgs[kNumTileCfgs] = {{64, 4, 16, 1},  {64, 4, 32, 1},   {64, 4, 64, 1}, {32, 8, 16, 1},
-                                         {128, 2, 16, 1}, {64, 4, 8, 1},    {64, 16, 64, 2}, {64, 16, 128, 2},
-                                         {64, 16, 32, 2}, {64, 16, 64, 4}};
-
 size_t tile_cfg_lds(int cfg)
 {
     const TileCfg& t = kTileCfgs[cfg];
@@ -465,16 +458,13 @@ template <int C>
 __device__ __attribute__((always_inline)) inline void heat_dense_cfg(const float* src, float* dst, int nx, int ny, int nz, float alpha, int wg,
                                       float* lds)
 {
-    if constexpr (C >= 6) {
-        constexpr int TY = 16, K = C == 9 ? 4 : 2, ZC = C == 7 ? 128 : (C == 8 ? 32 : 64);
+    constexpr TileCfg t = kTileCfgs[C];
+    if constexpr (t.k > 1) {
         const Ring rs{const_cast<float*>(src), nz, (int64_t)nx * ny}, rd{dst, nz, (int64_t)nx * ny};
-        const int tiles = stencil::heat_tb_tiles<TY, K>(nx, ny);
-        const int z0 = (wg / tiles) * ZC;
-        stencil::heat_tb<TY, K>(rs, rd, nx, ny, nz, alpha, z0, min(nz, z0 + ZC), wg % tiles, lds);
+        const int tiles = stencil::heat_tb_tiles<t.ty, t.k>(nx, ny);
+        const int z0 = (wg / tiles) * t.zc;
+        stencil::heat_tb<t.ty, t.k>(rs, rd, nx, ny, nz, alpha, z0, min(nz, z0 + t.zc), wg % tiles, lds);
     } else {
-        constexpr TileCfg t = C == 0 ? TileCfg{64, 4, 16, 1} : C == 1 ? TileCfg{64, 4, 32, 1}
-                            : C == 2 ? TileCfg{64, 4, 64, 1} : C == 3 ? TileCfg{32, 8, 16, 1}
-                            : C == 4 ? TileCfg{128, 2, 16, 1} : TileCfg{64, 4, 8, 1};
         stencil::heat_dense<t.tx, t.ty, t.zc>(src, dst, nx, ny, nz, alpha, wg);
     }
 }
@@ -491,6 +481,8 @@ __device__ __attribute__((always_inline)) inline void heat_dense_any(int cfg, co
         case 6: heat_dense_cfg<6>(src, dst, nx, ny, nz, alpha, wg, lds); break;
         case 7: heat_dense_cfg<7>(src, dst, nx, ny, nz, alpha, wg, lds); break;
         case 8: heat_dense_cfg<8>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        case 10: heat_dense_cfg<10>(src, dst, nx, ny, nz, alpha, wg, lds); break;
+        case 11: heat_dense_cfg<11>(src, dst, nx, ny, nz, alpha, wg, lds); break;
         default: heat_dense_cfg<9>(src, dst, nx, ny, nz, alpha, wg, lds); break;
         }
     } else {
@@ -538,6 +530,214 @@ __global__ void __launch_bounds__(kBlockThreads)
 heat_dense_kernel(const float* src, float* dst, int nx, int ny, int nz, float alpha, int cfg)
 {
     heat_dense_any<TB>(cfg, src, dst, nx, ny, nz, alpha, (int)blockIdx.x, reinterpret_cast<float*>(dyn_lds));
+}
+
+// ---- persistent batched launch ----------------------------------------------
+
+// Item i of the queue: a tile of one group of one domain, or a copy item.
+struct BatchItem {
+    const BatchDomain* e;  // the domain's work-list entry
+    int32_t d;             // domain
+    int32_t wg;            // tile (workgroup index within the domain) or copy item of the domain
+    int32_t g;             // group of this launch, or -1 for a copy item
+    uint32_t need;         // finished tiles of d this item waits for
+};
+
+__device__ inline BatchItem batch_item(const BatchPersistArgs& a, uint32_t i)
+{
+    BatchItem it;
+    const uint32_t n = (uint32_t)a.groups * (uint32_t)a.total;
+    int32_t r;
+    const int32_t* begin;  // per domain: first item (tile or copy item) of the domain
+    int stride;            // in int32 words
+    if (i < n) {
+        it.g = (int32_t)(i / (uint32_t)a.total);
+        r = (int32_t)(i % (uint32_t)a.total);
+        begin = &a.tab->wg_begin;
+        stride = (int)(sizeof(BatchDomain) / sizeof(int32_t));
+    } else {
+        it.g = -1;
+        r = (int32_t)(i - n);
+        begin = a.copy_begin;
+        stride = 1;
+    }
+    int lo = 0, hi = a.nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (begin[mid * stride] <= r) lo = mid; else hi = mid - 1;
+    }
+    it.d = lo;
+    it.e = a.tab + lo;
+    it.wg = r - begin[lo * stride];
+    const uint32_t tiles = (uint32_t)((lo + 1 < a.nd ? a.tab[lo + 1].wg_begin : a.total) - a.tab[lo].wg_begin);
+    it.need = (uint32_t)(it.g < 0 ? a.groups : it.g) * tiles;
+    return it;
+}
+
+// Thread 0: wait until *ctr >= need. Gives up (false) when another wait has
+// given up (status set) or after spin_limit polls, then setting the status.
+__device__ inline bool batch_wait(uint32_t* ctr, uint32_t need, uint32_t* status, int64_t spin_limit, bool force)
+{
+    for (int64_t spins = 0;; ++spins) {
+        if (!force && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+        if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+        if (spins >= spin_limit) {
+            __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// A work-list entry in scalar registers. The entry is the same for the whole
+// workgroup, but the compiler cannot tell (the list is read through a
+// structure field, so its loads are vector loads): every field goes through
+// readfirstlane, which keeps the tile code's addresses and its switch on the
+// configuration uniform.
+__device__ inline int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float* uni(float* p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint64_t lo = (uint32_t)uni((int32_t)(uint32_t)v), hi = (uint32_t)uni((int32_t)(uint32_t)(v >> 32));
+    return reinterpret_cast<float*>(lo | (hi << 32));
+}
+__device__ inline BatchDomain uniform_entry(const BatchDomain* p)
+{
+    BatchDomain e;
+    e.a = uni(p->a);
+    e.b = uni(p->b);
+    e.nx = uni(p->nx);
+    e.ny = uni(p->ny);
+    e.nz = uni(p->nz);
+    e.cfg = uni(p->cfg);
+    e.wg_begin = uni(p->wg_begin);
+    e.pad = 0;
+    return e;
+}
+
+// Every workgroup takes items from the queue in order until it is empty (or a
+// wait gave up). An item only waits for items earlier in the queue, which
+// running workgroups already hold, so the launch drains whatever number of
+// workgroups the device runs at once. Every wave releases its outputs at
+// device scope before the domain's count is raised, and acquires at device
+// scope before reading its inputs, so halo cells written by workgroups on
+// other dies (each with its own L2) are seen. The last workgroup to leave
+// resets the queue and the counts for the next launch; the status stays for
+// the host to read. TB: temporally blocked tiles only (a separate kernel, so
+// that the depth-1 path and the copy items do not raise its register count;
+// at 7 waves per SIMD it needs no spill).
+template <bool TB>
+__global__ void __launch_bounds__(kBlockThreads, TB ? 7 : 8) batch_persistent_kernel(BatchPersistArgs a)
+{
+    __shared__ uint32_t s_item;
+    uint32_t* head = a.sync;
+    uint32_t* exited = a.sync + 1;
+    uint32_t* status = a.sync + 2;
+    uint32_t* done = a.sync + kBatchSyncWords;
+    const uint32_t total = (uint32_t)a.groups * (uint32_t)a.total + (TB ? 0u : (uint32_t)a.copy_items);
+    float* lds = reinterpret_cast<float*>(dyn_lds);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            uint32_t item = 0xffffffffu;
+            if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                const uint32_t i = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (i < total) {
+                    const BatchItem it = batch_item(a, i);
+                    if (batch_wait(done + it.d, it.need, status, a.spin_limit, a.force_wait != 0)) item = i;
+                }
+            }
+            s_item = item;
+        }
+        __syncthreads();
+        // the same for every lane: kept in scalar registers
+        const uint32_t i = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
+        if (i == 0xffffffffu) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const BatchItem it = batch_item(a, i);
+        const BatchDomain e = uniform_entry(it.e);
+        if (TB || it.g >= 0) {
+            const bool odd = ((it.g + a.parity0) & 1) != 0;
+            const float* src = odd ? e.b : e.a;
+            float* dst = odd ? e.a : e.b;
+            heat_dense_any<TB>(e.cfg, src, dst, e.nx, e.ny, e.nz, a.alpha, it.wg, lds);
+        } else {
+            // the last group left the state in b: move kBatchCopyFloats of it
+            const int64_t n = (int64_t)e.nx * e.ny * e.nz;
+            const int64_t off = (int64_t)it.wg * kBatchCopyFloats;
+            const int m = (int)min((int64_t)kBatchCopyFloats, n - off);
+            const float* src = e.b + off;
+            float* dst = e.a + off;
+            for (int q = (int)threadIdx.x; q < m; q += kBlockThreads) dst[q] = src[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0 && (TB || it.g >= 0))
+            __hip_atomic_fetch_add(done + it.d, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t n = __hip_atomic_fetch_add(exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (n + 1u == gridDim.x) {
+            for (int d = 0; d < a.nd; ++d) __hip_atomic_store(done + d, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(exited, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+static const void* persistent_fn(bool tb)
+{
+    return tb ? reinterpret_cast<const void*>(&batch_persistent_kernel<true>)
+              : reinterpret_cast<const void*>(&batch_persistent_kernel<false>);
+}
+
+hipError_t launch_batch_persistent(const BatchPersistArgs& a, bool tb, int grid, size_t lds, hipStream_t stream)
+{
+    if (grid <= 0) return hipSuccess;
+    if (tb)
+        hipLaunchKernelGGL(batch_persistent_kernel<true>, dim3((unsigned)grid), dim3(kBlockThreads), lds, stream, a);
+    else
+        hipLaunchKernelGGL(batch_persistent_kernel<false>, dim3((unsigned)grid), dim3(kBlockThreads), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t add_batch_persistent_node(const BatchPersistArgs& a, bool tb, int grid, size_t lds, hipGraph_t g,
+                                     const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node)
+{
+    BatchPersistArgs copy = a;
+    void* args[] = {&copy};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(persistent_fn(tb));
+    kp.gridDim = dim3((unsigned)grid);
+    kp.blockDim = dim3(kBlockThreads);
+    kp.sharedMemBytes = (unsigned)lds;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, deps, ndeps, &kp);
+}
+
+hipError_t batch_persistent_grid(bool tb, size_t lds, int* grid)
+{
+    int dev = 0, per_cu = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_fn(tb), kBlockThreads, lds);
+    if (e != hipSuccess) return e;
+    *grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    return hipSuccess;
+}
+
+__global__ void zero_words_kernel(uint32_t* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((n + kBlockThreads - 1) / kBlockThreads)),
+                       dim3(kBlockThreads), 0, stream, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_step(const BatchDomain* d_table, int nd, int32_t total_wg, size_t lds, int parity,

@@ -55,7 +55,7 @@ int Planner::init(const oocs_config& c, std::string& err)
     if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
     if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS | OOCS_PLAN_LEVEL_BY_LEVEL |
-                    OOCS_PLAN_KERNEL_STORES | OOCS_PLAN_RESIDENT_RO)) {
+                    OOCS_PLAN_KERNEL_STORES | OOCS_PLAN_RESIDENT_RO | OOCS_PLAN_SNAKE)) {
         err = "unknown plan flags";
         return OOCS_E_ARG;
     }
@@ -66,6 +66,12 @@ int Planner::init(const oocs_config& c, std::string& err)
     resident_ro = (c.flags & OOCS_PLAN_RESIDENT_RO) != 0;
     if (resident_ro && !has_ro) { err = "a resident read-only field needs the wave stencil"; return OOCS_E_ARG; }
     if (resident_ro) in_fields = {0, 1};  // the read-only field is loaded once, outside the residencies
+    snake = (c.flags & OOCS_PLAN_SNAKE) != 0;
+    if (snake && (!copy_engines || kernel_stores || restart || n < 2)) {
+        err = "snake sweeps need copy-engine transfers, shared levels and at least two slabs";
+        return OOCS_E_ARG;
+    }
+    X = snake ? slab : 0;
     // kernel-driven transfers fetch one group ahead inside the launch: two slots suffice;
     // copy engines keep three groups in flight ahead of the decode
     nstage = c.nstage ? c.nstage : (copy_engines ? 4 : 2);
@@ -100,9 +106,15 @@ int64_t Planner::store_bytes(int f) const
     return store_plane_bytes(f) * nz;
 }
 
-int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
+int Planner::build_ticks(int kr, int variant, Schedule& s, std::string& err) const
 {
     s.ticks.clear(); s.in_groups.clear(); s.out_groups.clear();
+    // Snake variants: in pass order (z upward; a downward pass is built upward
+    // and mirrored at the end) the first X planes of the input may come from
+    // the retained buffer and the last X planes of the output may go to it,
+    // so no group crosses those boundaries.
+    const int64_t cut_in = (variant & OOCS_SCHED_RETAIN_IN) ? X : -1;
+    const int64_t cut_out = (variant & OOCS_SCHED_RETAIN_OUT) ? nz - X : -1;
     const int nl = nin + kr;  // levels in use: 0 .. nl-1
     std::vector<int64_t> f(nl), lo(nl), hi(nl);
     int64_t load_front = 0;
@@ -139,6 +151,7 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
                 t.in_group = (int64_t)s.in_groups.size();
                 t.dz0 = load_front;
                 t.dz1 = std::min(load_front + G, e_end);
+                if (load_front < cut_in) t.dz1 = std::min(t.dz1, cut_in);
                 s.in_groups.push_back({t.dz0, t.dz1, (int64_t)s.ticks.size(), restart ? pi : block_of(t.dz0), false});
                 load_front = t.dz1;
             }
@@ -177,6 +190,7 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
             const int64_t bend = restart ? a[ob + 1] : nz;
             int64_t e = fo >= bend ? bend : out_front + (fo - out_front) / align * align;
             e = std::min(e, out_front + G);
+            if (out_front < cut_out) e = std::min(e, cut_out);
             if (e > out_front) {
                 t.out_group = (int64_t)s.out_groups.size();
                 t.ez0 = out_front;
@@ -201,7 +215,36 @@ int Planner::build_ticks(int kr, Schedule& s, std::string& err) const
             s.ticks.push_back(std::move(t));
         }
     }
+    if (variant & OOCS_SCHED_MIRROR) {
+        // plane z of the upward pass is plane nz - 1 - z, block b is block
+        // n - 1 - b (the slabs are equal, so the mirrored slabs are slabs)
+        auto mz = [&](int64_t& z0, int64_t& z1) { const int64_t t0 = z0; z0 = nz - z1; z1 = nz - t0; };
+        auto mb = [&](int32_t b) { return (int32_t)(n - 1 - b); };
+        for (Tick& t : s.ticks) {
+            t.block = mb(t.block);
+            if (t.in_group >= 0) mz(t.dz0, t.dz1);
+            for (LevelRange& L : t.levels) mz(L.z0, L.z1);
+            if (t.out_group >= 0) {
+                mz(t.ez0, t.ez1);
+                t.out_block = mb(t.out_block);
+                if (t.done_b1 >= 0) {
+                    const int32_t b0 = mb(t.done_b1), b1 = mb(t.done_b0);
+                    t.done_b0 = b0;
+                    t.done_b1 = b1;
+                }
+            }
+        }
+        for (GroupRec& g : s.in_groups) { mz(g.z0, g.z1); g.block = mb(g.block); }
+        for (GroupRec& g : s.out_groups) { mz(g.z0, g.z1); g.block = mb(g.block); }
+    }
     return OOCS_OK;
+}
+
+int Planner::variant_of(int64_t i, int64_t R) const
+{
+    if (!snake) return 0;
+    return ((i & 1) ? OOCS_SCHED_MIRROR : 0) | (i > 0 ? OOCS_SCHED_RETAIN_IN : 0) |
+           (i < R - 1 ? OOCS_SCHED_RETAIN_OUT : 0);
 }
 
 int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
@@ -212,9 +255,13 @@ int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
     std::vector<int64_t> W(R, 1);
     // Size every ring by a liveness sweep over the tick lists of all
     // residency lengths 1..k (the last residency may be shorter).
-    for (int kr = 1; kr <= k; ++kr) {
+    // Snake plans: also every retain variant (mirroring keeps every span).
+    std::vector<int> variants{0};
+    if (snake) variants = {0, OOCS_SCHED_RETAIN_IN, OOCS_SCHED_RETAIN_OUT, OOCS_SCHED_RETAIN_IN | OOCS_SCHED_RETAIN_OUT};
+    for (int vi = 0; vi < (int)variants.size() * k; ++vi) {
+        const int kr = vi % k + 1, variant = variants[vi / k];
         Schedule s;
-        if (build_ticks(kr, s, err) != OOCS_OK) return -1;
+        if (build_ticks(kr, variant, s, err) != OOCS_OK) return -1;
         const int64_t T = (int64_t)s.ticks.size();
         // per ring: current version of each plane -> (write tick, last read tick)
         struct Live { int64_t w = -1, rd = -1; };
@@ -297,6 +344,10 @@ int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
         out_off[fld] = off;
         off += out_slot_bytes[fld] * nstage;
     }
+    for (int fld : out_fields) {
+        ret_off[fld] = off;
+        if (snake) off = align_up(off + X * store_plane_bytes(fld), 256);
+    }
     src_table_off = step_ctr_off = -1;
     if (cfg.stencil == OOCS_WAVE25) {
         src_table_off = off;
@@ -337,7 +388,7 @@ int Planner::choose(size_t arena_bytes, std::string& err)
     return OOCS_E_CAP;
 }
 
-int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
+int Planner::emit_ops(int kr, int variant, Schedule& s, std::string& err) const
 {
     s.ops.clear();
     auto op = [&](int kind, int stream) {
@@ -347,13 +398,39 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
     };
     if (!copy_engines) return emit_direct(kr, s, op);
     auto block_of = [&](int64_t z) { return (int)std::min<int64_t>(z / slab, n - 1); };
+    // Snake variants: the retained regions in real z. The residency takes its
+    // first X planes (pass order) from the retained buffer and leaves its
+    // last X planes there; a downward pass starts at the top.
+    const bool mirror = (variant & OOCS_SCHED_MIRROR) != 0;
+    const bool ret_in = (variant & OOCS_SCHED_RETAIN_IN) != 0, ret_out = (variant & OOCS_SCHED_RETAIN_OUT) != 0;
+    auto in_retained = [&](int64_t z0, int64_t z1) {
+        return ret_in && (mirror ? z0 >= nz - X : z1 <= X);
+    };
+    auto out_retained = [&](int64_t z0, int64_t z1) {
+        return ret_out && (mirror ? z1 <= X : z0 >= nz - X);
+    };
+    // fields a group's load copies: all streamed inputs, or only the
+    // read-only one when the read-write ones are retained
+    auto loaded_fields = [&](const GroupRec& g) {
+        std::vector<int> f;
+        for (int fld : in_fields)
+            if (!in_retained(g.z0, g.z1) || fld == 2) f.push_back(fld);
+        return f;
+    };
     auto emit_h2d = [&](int64_t j, int64_t tick, std::vector<oocs_op>& out) {
         const GroupRec& g = s.in_groups[j];
         const int sl = (int)(j % nstage);
+        const std::vector<int> flds = loaded_fields(g);
+        if (flds.empty()) return;
         oocs_op w = op(OOCS_OP_WAIT, 0); w.event = ev_decoded(sl); w.tick = (int)tick; out.push_back(w);
         // host planes were last written by the previous residency's write-back
-        oocs_op w2 = op(OOCS_OP_WAIT, 0); w2.event = ev_blk_prev(block_of(g.z1 - 1)); w2.tick = (int)tick; out.push_back(w2);
-        for (int fld : in_fields) {
+        // (the read-only store never is); with snake sweeps the previous
+        // residency may have run the other way, so every block of the group
+        if (!in_retained(g.z0, g.z1))
+            for (int b = snake ? block_of(g.z0) : block_of(g.z1 - 1); b <= block_of(g.z1 - 1); ++b) {
+                oocs_op w2 = op(OOCS_OP_WAIT, 0); w2.event = ev_blk_prev(b); w2.tick = (int)tick; out.push_back(w2);
+            }
+        for (int fld : flds) {
             oocs_op c = op(OOCS_OP_H2D, 0);
             c.field = fld; c.slot = sl; c.z0 = g.z0; c.z1 = g.z1; c.block = g.block; c.tick = (int)tick;
             c.level = in_ring(fld);
@@ -397,15 +474,20 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
     for (int64_t ti = 0; ti < (int64_t)s.ticks.size(); ++ti) {
         const Tick& t = s.ticks[ti];
         const int isl = t.in_group >= 0 ? (int)(t.in_group % nstage) : -1;
-        const int osl = t.out_group >= 0 ? (int)(t.out_group % nstage) : -1;
-        if (isl >= 0) { oocs_op w = op(OOCS_OP_WAIT, 1); w.event = ev_loaded(isl); w.tick = (int)ti; s.ops.push_back(w); }
+        const bool iret = isl >= 0 && in_retained(t.dz0, t.dz1);
+        const bool oret = t.out_group >= 0 && out_retained(t.ez0, t.ez1);
+        // a retained output group uses no staging slot and is not written back
+        const int osl = t.out_group >= 0 && !oret ? (int)(t.out_group % nstage) : -1;
+        const bool loaded = isl >= 0 && !loaded_fields(s.in_groups[t.in_group]).empty();
+        if (loaded) { oocs_op w = op(OOCS_OP_WAIT, 1); w.event = ev_loaded(isl); w.tick = (int)ti; s.ops.push_back(w); }
         if (osl >= 0 && !kernel_stores) {
             oocs_op w = op(OOCS_OP_WAIT, 1); w.event = ev_stored(osl); w.tick = (int)ti; s.ops.push_back(w);
         }
         if (isl >= 0)
             for (int fld : in_fields) {
                 oocs_op d = op(OOCS_OP_DECODE, 1);
-                d.field = fld; d.slot = isl; d.level = in_ring(fld); d.z0 = t.dz0; d.z1 = t.dz1; d.block = t.block; d.tick = (int)ti;
+                d.field = fld; d.slot = iret && fld != 2 ? OOCS_SLOT_RETAINED : isl; d.level = in_ring(fld);
+                d.z0 = t.dz0; d.z1 = t.dz1; d.block = t.block; d.tick = (int)ti;
                 s.ops.push_back(d);
             }
         for (const LevelRange& L : t.levels) {
@@ -413,10 +495,11 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
             l.level = L.lv; l.z0 = L.z0; l.z1 = L.z1; l.block = t.block; l.tick = (int)ti; l.slot = L.steps;
             s.ops.push_back(l);
         }
-        if (osl >= 0)
+        if (t.out_group >= 0)
             for (int fld : out_fields) {
                 oocs_op e = op(OOCS_OP_ENCODE, 1);
-                e.field = fld; e.slot = osl; e.level = out_ring(fld, kr); e.z0 = t.ez0; e.z1 = t.ez1; e.block = t.out_block; e.tick = (int)ti;
+                e.field = fld; e.slot = oret ? OOCS_SLOT_RETAINED : osl; e.level = out_ring(fld, kr);
+                e.z0 = t.ez0; e.z1 = t.ez1; e.block = t.out_block; e.tick = (int)ti;
                 s.ops.push_back(e);
             }
         const int64_t stored_now = pend_store;
@@ -428,7 +511,7 @@ int Planner::emit_ops(int kr, Schedule& s, std::string& err) const
         }
         if (isl >= 0) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_decoded(isl); r2.tick = (int)ti; s.ops.push_back(r2); }
         if (osl >= 0 && !kernel_stores) { oocs_op r2 = op(OOCS_OP_RECORD, 1); r2.event = ev_encoded(osl); r2.tick = (int)ti; s.ops.push_back(r2); }
-        if (kernel_stores && t.out_group >= 0) pend_store = t.out_group;
+        if (kernel_stores && osl >= 0) pend_store = t.out_group;
         if ((int)lagged.size() >= lag) {
             s.ops.insert(s.ops.end(), lagged.front().begin(), lagged.front().end());
             lagged.pop_front();
@@ -531,21 +614,23 @@ int Planner::emit_direct(int kr, Schedule& s, MakeOp op) const
     return OOCS_OK;
 }
 
-const Schedule* Planner::schedule(int kr, std::string& err)
+const Schedule* Planner::schedule(int kr, std::string& err, int variant)
 {
     if (kr < 1 || kr > k) { err = "residency length out of range"; return nullptr; }
-    auto it = cache_.find(kr);
+    if (variant < 0 || variant > 7 || (variant && !snake)) { err = "schedule variant needs a snake plan"; return nullptr; }
+    const int key = kr + 64 * variant;
+    auto it = cache_.find(key);
     if (it != cache_.end()) return &it->second;
     Schedule s;
-    if (build_ticks(kr, s, err) != OOCS_OK) return nullptr;
-    if (emit_ops(kr, s, err) != OOCS_OK) return nullptr;
+    if (build_ticks(kr, variant, s, err) != OOCS_OK) return nullptr;
+    if (emit_ops(kr, variant, s, err) != OOCS_OK) return nullptr;
     for (const Tick& t : s.ticks) {
         const size_t per_in = copy_engines ? 1 : 2, per_out = (copy_engines && !kernel_stores) ? 1 : 2;
         const size_t jobs = t.levels.size() + (t.in_group >= 0 ? per_in * in_fields.size() : 0) +
                             (t.out_group >= 0 ? per_out * out_fields.size() : 0);
         if (jobs > 24) { err = "too many jobs in one tick"; return nullptr; }
     }
-    return &cache_.emplace(kr, std::move(s)).first->second;
+    return &cache_.emplace(key, std::move(s)).first->second;
 }
 
 }  // namespace oocs

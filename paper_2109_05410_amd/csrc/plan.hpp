@@ -65,10 +65,13 @@ public:
     int64_t layout(int64_t G, int nstage, std::string& err);
     // Picks G (cfg.group or the largest fitting arena_bytes) and fixes the layout.
     int choose(size_t arena_bytes, std::string& err);
-    // Tick list for a residency of kr steps with the current G.
-    int build_ticks(int kr, Schedule& s, std::string& err) const;
-    // Full operation list for kr steps (cached).
-    const Schedule* schedule(int kr, std::string& err);
+    // Tick list for a residency of kr steps with the current G; variant:
+    // OOCS_SCHED_* bits (snake plans).
+    int build_ticks(int kr, int variant, Schedule& s, std::string& err) const;
+    // Full operation list for kr steps and a variant (cached).
+    const Schedule* schedule(int kr, std::string& err, int variant = 0);
+    // Variant of residency i of R in one run (0 unless snake).
+    int variant_of(int64_t i, int64_t R) const;
 
     // geometry
     oocs_config cfg{};
@@ -83,6 +86,8 @@ public:
     bool kernel_stores = false; // with copy_engines: write-back by STORE jobs in the launches (else by D2H copies)
     bool fused = false;         // heat: one temporally blocked job per tick computes all k levels
     bool resident_ro = false;   // wave: the read-only field stays decoded in an nz-plane ring
+    bool snake = false;         // alternating sweeps; the last block of a residency stays on the device
+    int64_t X = 0;              // snake: planes of the retained block (one slab)
     static constexpr int kMaxFusedSteps = 4;
     int64_t slab = 0, h = 0;
     std::vector<int64_t> a;  // n+1 block bounds
@@ -104,6 +109,10 @@ public:
     std::vector<int64_t> ringW, ringOff;
     int64_t in_slot_bytes[OOCS_MAX_FIELDS] = {0, 0, 0}, in_off[OOCS_MAX_FIELDS] = {0, 0, 0};
     int64_t out_slot_bytes[OOCS_MAX_FIELDS] = {0, 0, 0}, out_off[OOCS_MAX_FIELDS] = {0, 0, 0};
+    int64_t ret_off[OOCS_MAX_FIELDS] = {0, 0, 0};  // snake: retained block of each read-write field
+    // first plane of the retained region that holds plane z (the region is
+    // the top block after an upward pass, the bottom block after a downward one)
+    int64_t ret_base(int64_t z) const { return z >= nz - X ? nz - X : 0; }
     int64_t arena_needed = 0;
     // wave source: amplitudes of up to kSrcTable steps and the device step counter
     static constexpr int64_t kSrcTable = 65536;
@@ -119,7 +128,7 @@ public:
     int nevents_logical() const { return 4 * nstage + 2 * n; }
 
 private:
-    int emit_ops(int kr, Schedule& s, std::string& err) const;
+    int emit_ops(int kr, int variant, Schedule& s, std::string& err) const;
     template <class MakeOp>
     int emit_direct(int kr, Schedule& s, MakeOp op) const;
     std::map<int, Schedule> cache_;

@@ -413,3 +413,49 @@ def test_full_size_wave_configuration(rate):
         assert np.array_equal(got, p.cpu().numpy())
         del p, pm, w
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("graphs", [False, True], ids=["eager", "graph"])
+@pytest.mark.parametrize("rate,k,steps,n,arena,lbl", [
+    (8, 4, 13, 8, 2 * MiB, False), (0, 4, 10, 4, 2 * MiB, False), (16, 4, 9, 2, 3 * MiB, True),
+    (12, 4, 4, 4, 2 * MiB, False),
+])
+def test_heat_snake_matches_replay(rate, k, steps, n, arena, lbl, graphs):
+    """Snake sweeps (alternating direction, the last block kept on the
+    device between residencies) give the replay bit for bit: odd and even
+    numbers of residencies, a ragged last one, one residency only, fused and
+    level-by-level heat; a second run on the same plan continues."""
+    shape = (128, 64, 64)
+    u0 = inputs.heat_uniform(shape, seed=30 + rate)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena, snake=True, level_by_level=lbl)
+    plan.set_graphs(graphs)
+    s = store_of(plan, 0, u0)
+    plan.run([s], steps)
+    assert np.array_equal(decoded(s, shape, rate), O.replay_heat_f32(u0, 0.1, steps, k, rate))
+    plan.run([s], 2 * k)
+    want = O.replay_heat_f32(O.replay_heat_f32(u0, 0.1, steps, k, rate), 0.1, 2 * k, k, rate)
+    assert np.array_equal(decoded(s, shape, rate), want)
+
+
+@pytest.mark.parametrize("graphs", [False, True], ids=["eager", "graph"])
+@pytest.mark.parametrize("rates,resident_ro", [([12, 12, 12], False), ([0, 0, 0], False), ([8, 12, 8], True),
+                                               ([0, 12, 12], False)])
+def test_wave_snake_matches_replay(rates, resident_ro, graphs):
+    shape = (96, 36, 40)
+    rng = np.random.default_rng(5)
+    p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    pm0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    steps, k = 17, 4
+    amps = rng.standard_normal(steps).astype(np.float32)
+    cell = (17, 20, 50)
+    idx = cell[0] + shape[2] * (cell[1] + shape[1] * cell[2])
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 3, k, rates, 16 * MiB, src_cell=cell, snake=True,
+                             resident_ro=resident_ro)
+    plan.set_graphs(graphs)
+    st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
+    plan.run(st, steps, src_amps=amps)
+    wp, wpm, _ = O.replay_wave_f32(p0, pm0, w, steps, k, src=(amps, idx), rate_p=rates[0], rate_pm=rates[1],
+                                   rate_w=rates[2])
+    assert np.array_equal(decoded(st[0], shape, rates[0]), wp)
+    assert np.array_equal(decoded(st[1], shape, rates[1]), wpm)

@@ -143,6 +143,11 @@ class Geometry:
         self.ro = self.nin + self.k
         self.nslabs = p.cfg.nslabs
         self.nstage = self.info["nstage"]
+        self.X = self.info["retained_planes"]
+
+    def ret_base(self, z):
+        """First plane of the retained region holding plane z."""
+        return self.nz - self.X if z >= self.nz - self.X else 0
 
 
 def accesses(o, g):
@@ -156,11 +161,17 @@ def accesses(o, g):
         out.append((("out", o["field"], o["slot"]), False))
         out += [(("host", o["field"], z), True) for z in range(o["z0"], o["z1"])]
     elif K == L.OP_DECODE:
-        out.append((("in", o["field"], o["slot"]), False))
+        if o["slot"] == L.OOCS_SLOT_RETAINED:  # planes of the retained block, at their place in the buffer
+            out += [(("ret", o["field"], z - g.ret_base(z)), False) for z in range(o["z0"], o["z1"])]
+        else:
+            out.append((("in", o["field"], o["slot"]), False))
         R = o["level"]
         out += [(("ring", R, z % g.W[R]), True) for z in range(o["z0"], o["z1"])]
     elif K == L.OP_ENCODE:
-        out.append((("out", o["field"], o["slot"]), True))
+        if o["slot"] == L.OOCS_SLOT_RETAINED:
+            out += [(("ret", o["field"], z - g.ret_base(z)), True) for z in range(o["z0"], o["z1"])]
+        else:
+            out.append((("out", o["field"], o["slot"]), True))
         R = o["level"]
         out += [(("ring", R, z % g.W[R]), False) for z in range(o["z0"], o["z1"])]
     elif K == L.OP_LEVEL:
@@ -211,6 +222,7 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
             reads.setdefault(res, []).append((stream, stamp, lid))
 
     done, rnd = 0, 0
+    nres = -(-steps // g.k)
     while done < steps:
         kr = min(g.k, steps - done)
         par = rnd % 2
@@ -229,7 +241,7 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
                 i -= n
             return ("blk", (1 - par) if prev else par, i)
 
-        for o in p.schedule(kr):
+        for o in p.schedule(kr, p.variant(rnd, nres)):
             s = o["stream"]
             K = o["kind"]
             if K == L.OP_RECORD:
@@ -373,13 +385,37 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
 
     if p.cfg.flags & L.OOCS_PLAN_RESIDENT_RO:  # decoded once, before the residencies
         rings[g.ro][:nz] = from_store(store[2], p.shape, rates[2])
+    retained = {}  # snake: (field, plane) -> that plane's share of the retained block (words of its layer, or raw)
 
-    done = 0
+    done, rnd = 0, 0
+    nres = -(-steps // g.k)
     while done < steps:
         kr = min(g.k, steps - done)
-        for o in p.schedule(kr):
+        for o in p.schedule(kr, p.variant(rnd, nres)):
             K = o["kind"]
             z0, z1 = o["z0"], o["z1"]
+            if K == L.OP_DECODE and o["slot"] == L.OOCS_SLOT_RETAINED:
+                f, rate = o["field"], rates[o["field"]]
+                if rate:
+                    data = np.concatenate([retained[(f, z)] for z in range(z0, z1, 4)])
+                    planes = O.codec_decode(data, (z1 - z0, ny, nx), rate)
+                else:
+                    planes = np.stack([retained[(f, z)] for z in range(z0, z1)])
+                for z in range(z0, z1):
+                    rings[o["level"]][z % g.W[o["level"]]] = planes[z - z0]
+                continue
+            if K == L.OP_ENCODE and o["slot"] == L.OOCS_SLOT_RETAINED:
+                f, rate = o["field"], rates[o["field"]]
+                planes = np.stack([plane(o["level"], z) for z in range(z0, z1)])
+                if rate:
+                    words = O.codec_encode(planes, rate)
+                    lw = layer_words(rate)
+                    for q, z in enumerate(range(z0, z1, 4)):
+                        retained[(f, z)] = words[q * lw:(q + 1) * lw]
+                else:
+                    for z in range(z0, z1):
+                        retained[(f, z)] = planes[z - z0].copy()
+                continue
             if K in (L.OP_H2D, L.OP_FETCH):
                 f, rate = o["field"], rates[o["field"]]
                 if rate:
@@ -444,6 +480,7 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
                 else:
                     store[f][z0:z1] = data
         done += kr
+        rnd += 1
     return store
 
 
@@ -549,3 +586,108 @@ def test_resident_read_only_arena_and_errors():
     assert ri["group"] <= streamed.info["group"]
     with pytest.raises(L.OocsError):
         plan((64, 16, 16), HEAT7, 2, 2, [8], 4 * MiB, resident_ro=True)
+
+
+# ---------------------------------------------------------------------------
+# snake sweeps
+# ---------------------------------------------------------------------------
+
+SNAKE_CASES = [
+    ((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, 11),              # fused heat, compressed, 3 residencies
+    ((48, 12, 16), HEAT7, 4, 2, [0], MiB // 4, 9),               # raw, 5 residencies
+    ((48, 12, 16), HEAT7, 2, 4, [5], 2 * MiB, 16),               # 2 slabs: the two blocks alternate
+    ((64, 12, 12), WAVE25, 2, 3, [8, 12, 8], 4 * MiB, 8),
+    ((64, 12, 12), WAVE25, 2, 3, [0, 0, 0], 4 * MiB, 7),
+    ((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 8 * MiB, 14),
+]
+
+
+@pytest.mark.parametrize("shape,st,n,k,rates,arena,steps", SNAKE_CASES)
+def test_snake_schedule_has_no_races(shape, st, n, k, rates, arena, steps):
+    p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, snake=True)
+    race_check(p, steps)
+    race_check(p, steps, graph_mode=True)
+
+
+def test_full_size_snake_schedules_have_no_races():
+    race_check(plan((512, 512, 512), HEAT7, 8, 4, [8], 128 * MiB, snake=True), 12)
+    race_check(plan((1024, 16, 16), WAVE25, 8, 12, [8, 8, 8], 64 * MiB, snake=True, src_cell=(3, 3, 5)), 36)
+
+
+@pytest.mark.parametrize("shape,st,n,k,rates,arena,steps", SNAKE_CASES)
+@pytest.mark.parametrize("level_by_level", [False, True])
+def test_snake_schedule_computes_the_replay(shape, st, n, k, rates, arena, steps, level_by_level):
+    p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, snake=True,
+             level_by_level=level_by_level)
+    rng = np.random.default_rng(11)
+    if st == HEAT7:
+        u0 = rng.random(shape, dtype=np.float32)
+        store = [to_store(u0, rates[0])]
+        execute(p, store, steps, None)
+        assert np.array_equal(from_store(store[0], shape, rates[0]), O.replay_heat_f32(u0, 0.1, steps, k, rates[0]))
+    else:
+        p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+        pm0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+        w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+        amps = rng.standard_normal(steps).astype(np.float32)
+        store = [to_store(p0, rates[0]), to_store(pm0, rates[1]), to_store(w, rates[2])]
+        execute(p, store, steps, amps)
+        idx = 3 + shape[2] * (3 + shape[1] * 5)
+        wp, wpm, _ = O.replay_wave_f32(p0, pm0, w, steps, k, src=(amps, idx), rate_p=rates[0], rate_pm=rates[1],
+                                       rate_w=rates[2])
+        assert np.array_equal(from_store(store[0], shape, rates[0]), wp)
+        assert np.array_equal(from_store(store[1], shape, rates[1]), wpm)
+
+
+@pytest.mark.parametrize("resident_ro", [False, True])
+def test_snake_keeps_the_last_block_off_the_link(resident_ro):
+    """Residency i of R runs upward if i is even, downward if odd; the block
+    it ends with (one slab) is neither written back (unless i = R - 1) nor
+    loaded by the next residency, for the read-write fields; every other
+    plane crosses the link once each way per residency, and the read-only
+    field is loaded whole every residency (or never, if resident)."""
+    shape, n, k = (1024, 16, 16), 8, 12
+    slab = shape[0] // n
+    p = plan(shape, WAVE25, n, k, [12, 12, 12], 64 * MiB, snake=True, resident_ro=resident_ro)
+    assert p.info["retained_planes"] == slab
+    R = 4
+    for i in range(R):
+        v = p.variant(i, R)
+        ops = p.schedule(k, v)
+        up = i % 2 == 0
+        levels = [o for o in ops if o["kind"] == L.OP_LEVEL]
+        first, last = levels[0]["z0"], levels[-1]["z1"]
+        assert (first < last) if up else (first > last)
+        for f in (0, 1, 2):
+            h2d = np.zeros(shape[0], int)
+            d2h = np.zeros(shape[0], int)
+            for o in ops:
+                if o["field"] == f and o["kind"] == L.OP_H2D:
+                    h2d[o["z0"]:o["z1"]] += 1
+                if o["field"] == f and o["kind"] == L.OP_D2H:
+                    d2h[o["z0"]:o["z1"]] += 1
+            start = slice(0, slab) if up else slice(shape[0] - slab, shape[0])
+            end = slice(shape[0] - slab, shape[0]) if up else slice(0, slab)
+            want_in = np.ones(shape[0], int)
+            want_out = np.ones(shape[0], int)
+            if f == 2:
+                want_in[:] = 0 if resident_ro else 1
+                want_out[:] = 0
+            else:
+                if i > 0:
+                    want_in[start] = 0
+                if i < R - 1:
+                    want_out[end] = 0
+            assert np.array_equal(h2d, want_in), (i, f)
+            assert np.array_equal(d2h, want_out), (i, f)
+
+
+def test_snake_needs_copy_engines_shared_levels_and_two_slabs():
+    for kw in ({"kernel_transfers": True}, {"kernel_stores": True}, {"block_restart": True}):
+        with pytest.raises(L.OocsError) as e:
+            plan((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, snake=True, **kw)
+        assert e.value.code == L.OOCS_E_ARG
+    with pytest.raises(L.OocsError):
+        plan((48, 12, 16), HEAT7, 1, 4, [8], 2 * MiB, snake=True)
+    with pytest.raises(L.OocsError):
+        plan((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB).schedule(4, L.OOCS_SCHED_MIRROR)
