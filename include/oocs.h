@@ -89,7 +89,14 @@ int oocs_codec_encode(const float* d_in, int64_t nx, int64_t ny, int64_t nz, int
 /* Decode a stream made by oocs_codec_encode with the same dimensions and
  * rate into d_out. A corrupted stream decodes to some values without any
  * out-of-bounds access (every block has a fixed position and budget).
+ * rate may be OR-ed with OOCS_DECODE_MIDPOINT (here and in
+ * oocs_codec_decode_stages): the digits a block's budget cut off are then
+ * reconstructed at the middle of their range instead of as zeros (a
+ * coefficient with at least one nonzero digit read, and L digits cut off,
+ * gets floor((1 - (-2)^L) / 6) added: half of the value of L negabinary
+ * ones); the stream format is unchanged.
  * Errors as for encode. */
+#define OOCS_DECODE_MIDPOINT 0x100
 int oocs_codec_decode(const uint64_t* d_in, size_t in_bytes, int64_t nx, int64_t ny, int64_t nz, int rate, float* d_out,
                       int64_t ld_y, int64_t ld_z, void* stream);
 
@@ -256,6 +263,13 @@ typedef struct {
  * the retained buffers take one slab of every read-write field from the
  * arena. */
 #define OOCS_PLAN_SNAKE 32
+
+/* Plan flag: every decode of the plan (the residencies' decode jobs, the
+ * resident read-only load, oocs_store_get) uses mid-point reconstruction
+ * (OOCS_DECODE_MIDPOINT). The host stores are the same; the state a run
+ * reaches is that of decode-with-mid-points o encode applied where the
+ * plain plan applies decode o encode. */
+#define OOCS_PLAN_MIDPOINT 64
 
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be

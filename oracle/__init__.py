@@ -44,6 +44,14 @@ def lib() -> C.CDLL:
         L.orc_inv_xform.argtypes = [P, P]
         L.orc_encode_block.argtypes = [P, C.c_int, P, P]
         L.orc_decode_block.argtypes = [P, C.c_int, P, P]
+        L.orc_decode_block_mode.argtypes = [P, C.c_int, C.c_int, P, P]
+        L.orc_codec_decode_mode.argtypes = [P, l, l, l, C.c_int, C.c_int, P]
+        L.orc_codec_roundtrip_mode.argtypes = [P, l, l, l, C.c_int, C.c_int]
+        L.orc_codec_roundtrip_f64_mode.argtypes = [P, l, l, l, C.c_int, C.c_int]
+        L.orc_replay_heat_f32_mode.argtypes = [P, l, l, l, C.c_float, l, l, C.c_int, C.c_int]
+        L.orc_replay_heat_f64_mode.argtypes = [P, l, l, l, C.c_double, l, l, C.c_int, C.c_int]
+        L.orc_replay_wave_f32_mode.argtypes = [P, P, P, l, l, l, l, l, P, l, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.orc_replay_wave_f64_mode.argtypes = [P, P, P, l, l, l, l, l, P, l, C.c_int, C.c_int, C.c_int, C.c_int]
         L.orc_codec_words.argtypes = [l, l, l, C.c_int]
         L.orc_codec_words.restype = C.c_size_t
         L.orc_codec_encode.argtypes = [P, l, l, l, C.c_int, P]
@@ -53,6 +61,7 @@ def lib() -> C.CDLL:
         L.orc_code_ints.argtypes = [P, l, P]
         L.orc_code_ints.restype = C.c_long
         L.orc_decode_ints.argtypes = [P, l, P]
+        L.orc_decode_ints_stop.argtypes = [P, l, P, P]
         L.orc_wave_forward_states_f64.argtypes = [P, l, l, l, l, P, l, P, l, P, P]
         L.orc_wave_adjoint_f64.argtypes = [P, l, l, l, l, P, l, P, P, P, l, P]
         L.orc_wave_misfit_grad_f64.argtypes = [P, l, l, l, l, P, l, P, l, P, P, P]
@@ -152,6 +161,8 @@ class Stages(C.Structure):
         ("u", C.c_uint32 * 64),
         ("plane", C.c_uint64 * 32),
         ("bits_used", C.c_int32),
+        ("stop_plane", C.c_int32),
+        ("stop_known", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -162,6 +173,8 @@ class Stages(C.Structure):
             "u": np.array(self.u[:], dtype=np.uint32),
             "plane": np.array(self.plane[:], dtype=np.uint64),
             "bits_used": int(self.bits_used),
+            "stop_plane": int(self.stop_plane),
+            "stop_known": int(self.stop_known),
         }
 
 
@@ -197,11 +210,13 @@ def encode_block(vals64, rate: int):
     return out, st.as_dict()
 
 
-def decode_block(words, rate: int):
+def decode_block(words, rate: int, mid: bool = False):
+    """rate words -> (64 floats, stages dict); mid: mid-point reconstruction
+    of the digits the budget cut off (format step 9 in oracle.c)."""
     w = np.ascontiguousarray(words, dtype=np.uint64).reshape(rate)
     out = np.zeros(64, dtype=np.float32)
     st = Stages()
-    _check(lib().orc_decode_block(_ptr(w), int(rate), _ptr(out), C.byref(st)), "decode_block")
+    _check(lib().orc_decode_block_mode(_ptr(w), int(rate), int(bool(mid)), _ptr(out), C.byref(st)), "decode_block")
     return out, st.as_dict()
 
 
@@ -222,6 +237,18 @@ def decode_ints(words, budget: int) -> np.ndarray:
     return out
 
 
+def decode_ints_stop(words, budget: int):
+    """decode_ints plus where the budget ran out: (u, plane or -1, number of
+    coefficients whose digit of that plane is known)."""
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size * 64 < budget:
+        raise ValueError("stream shorter than budget")
+    out = np.zeros(64, dtype=np.uint32)
+    stop = np.zeros(2, dtype=np.int32)
+    _check(lib().orc_decode_ints_stop(_ptr(w), int(budget), _ptr(out), _ptr(stop)), "decode_ints_stop")
+    return out, int(stop[0]), int(stop[1])
+
+
 def codec_words(nx: int, ny: int, nz: int, rate: int) -> int:
     return int(lib().orc_codec_words(nx, ny, nz, rate))
 
@@ -235,27 +262,27 @@ def codec_encode(f: np.ndarray, rate: int) -> np.ndarray:
     return out
 
 
-def codec_decode(words: np.ndarray, shape, rate: int) -> np.ndarray:
+def codec_decode(words: np.ndarray, shape, rate: int, mid: bool = False) -> np.ndarray:
     nz, ny, nx = shape
     w = np.ascontiguousarray(words, dtype=np.uint64)
     if w.size != codec_words(nx, ny, nz, rate):
         raise ValueError("word count does not match shape and rate")
     out = np.zeros((nz, ny, nx), dtype=np.float32)
-    _check(lib().orc_codec_decode(_ptr(w), nx, ny, nz, int(rate), _ptr(out)), "codec_decode")
+    _check(lib().orc_codec_decode_mode(_ptr(w), nx, ny, nz, int(rate), int(bool(mid)), _ptr(out)), "codec_decode")
     return out
 
 
-def codec_roundtrip(f: np.ndarray, rate: int) -> np.ndarray:
+def codec_roundtrip(f: np.ndarray, rate: int, mid: bool = False) -> np.ndarray:
     """Q(f) = decode(encode(f)) for an FP32 field."""
     g = np.ascontiguousarray(f, dtype=np.float32).copy()
-    _check(lib().orc_codec_roundtrip(_ptr(g), *_dims(g), int(rate)), "codec_roundtrip")
+    _check(lib().orc_codec_roundtrip_mode(_ptr(g), *_dims(g), int(rate), int(bool(mid))), "codec_roundtrip")
     return g
 
 
-def codec_roundtrip_f64(f: np.ndarray, rate: int) -> np.ndarray:
+def codec_roundtrip_f64(f: np.ndarray, rate: int, mid: bool = False) -> np.ndarray:
     """Q for an FP64 field: round to FP32, decode(encode()), widen back."""
     g = np.ascontiguousarray(f, dtype=np.float64).copy()
-    _check(lib().orc_codec_roundtrip_f64(_ptr(g), *_dims(g), int(rate)), "codec_roundtrip_f64")
+    _check(lib().orc_codec_roundtrip_f64_mode(_ptr(g), *_dims(g), int(rate), int(bool(mid))), "codec_roundtrip_f64")
     return g
 
 
@@ -263,38 +290,39 @@ def codec_roundtrip_f64(f: np.ndarray, rate: int) -> np.ndarray:
 # Replay of the compressed out-of-core schedule (Sec. V-A)
 # --------------------------------------------------------------------------
 
-def replay_heat_f32(u0, alpha, steps, k, rate):
+def replay_heat_f32(u0, alpha, steps, k, rate, mid: bool = False):
+    """mid: every decode with mid-point reconstruction."""
     u = np.ascontiguousarray(u0, dtype=np.float32).copy()
-    _check(lib().orc_replay_heat_f32(_ptr(u), *_dims(u), float(np.float32(alpha)), int(steps), int(k), int(rate)),
-           "replay_heat_f32")
+    _check(lib().orc_replay_heat_f32_mode(_ptr(u), *_dims(u), float(np.float32(alpha)), int(steps), int(k),
+                                          int(rate), int(bool(mid))), "replay_heat_f32")
     return u
 
 
-def replay_heat_f64(u0, alpha, steps, k, rate):
+def replay_heat_f64(u0, alpha, steps, k, rate, mid: bool = False):
     u = np.ascontiguousarray(u0, dtype=np.float64).copy()
-    _check(lib().orc_replay_heat_f64(_ptr(u), *_dims(u), float(alpha), int(steps), int(k), int(rate)),
-           "replay_heat_f64")
+    _check(lib().orc_replay_heat_f64_mode(_ptr(u), *_dims(u), float(alpha), int(steps), int(k), int(rate),
+                                          int(bool(mid))), "replay_heat_f64")
     return u
 
 
-def replay_wave_f32(p0, pm0, w0, steps, k, src=None, rate_p=0, rate_pm=0, rate_w=0):
+def replay_wave_f32(p0, pm0, w0, steps, k, src=None, rate_p=0, rate_pm=0, rate_w=0, mid: bool = False):
     """Returns (p, pm, Q(w)) after `steps` with k steps per residency."""
     p = np.ascontiguousarray(p0, dtype=np.float32).copy()
     pm = np.ascontiguousarray(pm0, dtype=np.float32).copy()
     w = np.ascontiguousarray(w0, dtype=np.float32).copy()
     a, idx, ap = _src_args(src, np.float32, steps)
-    _check(lib().orc_replay_wave_f32(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), int(k), ap, idx,
-                                     int(rate_p), int(rate_pm), int(rate_w)), "replay_wave_f32")
+    _check(lib().orc_replay_wave_f32_mode(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), int(k), ap, idx,
+                                          int(rate_p), int(rate_pm), int(rate_w), int(bool(mid))), "replay_wave_f32")
     return p, pm, w
 
 
-def replay_wave_f64(p0, pm0, w0, steps, k, src=None, rate_p=0, rate_pm=0, rate_w=0):
+def replay_wave_f64(p0, pm0, w0, steps, k, src=None, rate_p=0, rate_pm=0, rate_w=0, mid: bool = False):
     p = np.ascontiguousarray(p0, dtype=np.float64).copy()
     pm = np.ascontiguousarray(pm0, dtype=np.float64).copy()
     w = np.ascontiguousarray(w0, dtype=np.float64).copy()
     a, idx, ap = _src_args(src, np.float64, steps)
-    _check(lib().orc_replay_wave_f64(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), int(k), ap, idx,
-                                     int(rate_p), int(rate_pm), int(rate_w)), "replay_wave_f64")
+    _check(lib().orc_replay_wave_f64_mode(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), int(k), ap, idx,
+                                          int(rate_p), int(rate_pm), int(rate_w), int(bool(mid))), "replay_wave_f64")
     return p, pm, w
 
 

@@ -228,12 +228,27 @@ int orc_wave25_f32(float* p, float* pm, const float* w, long nx, long ny, long n
 /*     the budget is zero. Bits are written least significant first into   */
 /*     little-endian 64-bit words; the rest of the block is zero.           */
 /*  8. decoding reads the same sequence with the same budget; bits never    */
-/*     read are zero. Then inverse negabinary, inverse reorder, the inverse */
+/*     read are zero (or, with mid-point reconstruction, see below). Then   */
+/*     inverse negabinary, inverse reorder, the inverse                     */
 /*     lifting along z, then y, then x:                                     */
 /*        b+=d>>1; d-=b>>1;  b+=d; d=2d-b;  c+=a; a=2a-c;                    */
 /*        b+=c; c=2c-b;  d+=a; a=2a-d;                                      */
 /*     and x = (float)q * 2^(emax-30) (round to nearest even, then exact    */
 /*     power-of-two scaling).                                               */
+/*  9. mid-point reconstruction (a decoding option; the stream is the same): */
+/*     when the budget ends inside the stream, the digits a coefficient did */
+/*     not receive are its L lowest planes: L = P for the coefficients     */
+/*     whose plane-P digit was read (or implied by a negative group test)  */
+/*     and L = P + 1 for the others, P being the plane in which the budget */
+/*     ran out with the plane incomplete (a plane that the last bit        */
+/*     completes makes the next plane P with none read). A coefficient     */
+/*     with a nonzero decoded digit then takes, instead of zero digits,    */
+/*     the middle of the values those L digits can add: they add           */
+/*     sum d_j (-2)^j, between the all-odd and all-even sums, whose middle */
+/*     is half of the all-ones sum (1 - (-2)^L) / 3; it is added rounded  */
+/*     down, in 32-bit wrap-around arithmetic, to the integer coefficient  */
+/*     before the inverse transform. Coefficients decoded as zero stay     */
+/*     zero. Nothing changes when the whole stream fits the budget.        */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -243,6 +258,8 @@ typedef struct {
     uint32_t u[64];      /* reordered (sequency order) and negabinary */
     uint64_t plane[32];  /* plane[p] = word X of bit plane p (bit i = bit p of u[i]) */
     int32_t bits_used;   /* bits written before padding, header included */
+    int32_t stop_plane;  /* decode: plane P in which the budget ran out (-1: stream complete) */
+    int32_t stop_known;  /* decode: coefficients (sequency order) whose plane-P digit is known */
 } orc_stages;
 
 static int g_perm_ready = 0;
@@ -389,29 +406,51 @@ static long code_planes(const uint32_t* u, long budget, bitw* s, uint64_t* plane
     return used;
 }
 
-static void decode_planes(uint32_t* u, long budget, bitr* s, uint64_t* planes_out)
+/* Decodes the planes; *stop_plane / *stop_known say where the budget ran
+ * out (format step 9): `known` counts the coefficients (a prefix in
+ * sequency order) whose digit of the current plane has been read or
+ * implied, 64 once the plane is complete. */
+static void decode_planes(uint32_t* u, long budget, bitr* s, uint64_t* planes_out, int* stop_plane, int* stop_known)
 {
     int n = 0;
+    *stop_plane = -1;
+    *stop_known = 0;
     for (int i = 0; i < 64; ++i) u[i] = 0;
     for (int p = 31; p >= 0; --p) {
         uint64_t X = 0;
         if (budget > 0) {
-            for (int i = 0; i < n && budget > 0; ++i) { X |= (uint64_t)get1(s) << i; budget--; }
+            int known = 0;
+            for (int i = 0; i < n && budget > 0; ++i) { X |= (uint64_t)get1(s) << i; budget--; known = i + 1; }
             while (n < 64 && budget > 0) {
                 int g = get1(s); budget--;
-                if (!g) break;
+                if (!g) { known = 64; break; }   /* every digit left in the plane is 0 */
                 for (;;) {
-                    if (n == 63) { X |= (uint64_t)1 << 63; n = 64; break; }
+                    if (n == 63) { X |= (uint64_t)1 << 63; n = 64; known = 64; break; }
                     if (budget <= 0) break;
                     int b = get1(s); budget--;
+                    known = n + 1;
                     if (b) { X |= (uint64_t)1 << n; n++; break; }
                     n++;
                 }
+            }
+            if (budget <= 0 && *stop_plane < 0) {
+                if (known < 64) { *stop_plane = p; *stop_known = known; }
+                else if (p > 0) { *stop_plane = p - 1; *stop_known = 0; }
             }
         }
         if (planes_out) planes_out[p] = X;
         for (int i = 0; i < 64; ++i) u[i] |= (uint32_t)((X >> i) & 1u) << p;
     }
+}
+
+/* Half of the all-ones sum of L negabinary digits, (1 - (-2)^L) / 3,
+ * rounded down (format step 9). */
+static int64_t midpoint_offset(int L)
+{
+    int64_t m = 1;
+    for (int j = 0; j < L; ++j) m *= -2;
+    const int64_t all_ones = (1 - m) / 3;
+    return all_ones >= 0 ? all_ones / 2 : -((-all_ones + 1) / 2);
 }
 
 /* One block: in64 natural order -> rate words. st may be NULL. */
@@ -452,9 +491,10 @@ int orc_encode_block(const float* in64, int rate, uint64_t* out, orc_stages* st)
     return rc;
 }
 
-/* One block: rate words -> 64 floats, natural order. st may be NULL
- * (st->q then holds the integers after the inverse transform). */
-int orc_decode_block(const uint64_t* in, int rate, float* out64, orc_stages* st)
+/* One block: rate words -> 64 floats, natural order; mid = 1 for mid-point
+ * reconstruction (format step 9). st may be NULL (st->q then holds the
+ * integers after the inverse transform). */
+int orc_decode_block_mode(const uint64_t* in, int rate, int mid, float* out64, orc_stages* st)
 {
     if (rate < 1 || rate > 64) return -1;
     build_perm();
@@ -471,11 +511,23 @@ int orc_decode_block(const uint64_t* in, int rate, float* out64, orc_stages* st)
     for (int b = 0; b < 8; ++b) biased |= get1(&s) << b;
     int emax = biased - 127;
     st->emax = emax;
-    decode_planes(st->u, 64L * rate - 9, &s, st->plane);
-    for (int k = 0; k < 64; ++k) st->t[g_perm[k]] = (int32_t)((st->u[k] ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
+    decode_planes(st->u, 64L * rate - 9, &s, st->plane, &st->stop_plane, &st->stop_known);
+    for (int k = 0; k < 64; ++k) {
+        uint32_t v = (st->u[k] ^ 0xAAAAAAAAu) - 0xAAAAAAAAu;
+        if (mid && st->stop_plane >= 0 && st->u[k] != 0) {
+            const int L = k < st->stop_known ? st->stop_plane : st->stop_plane + 1;
+            v += (uint32_t)midpoint_offset(L);  /* wraps like int32 */
+        }
+        st->t[g_perm[k]] = (int32_t)v;
+    }
     int rc = orc_inv_xform(st->t, st->q);
     for (int i = 0; i < 64; ++i) out64[i] = ldexpf((float)st->q[i], emax - 30);
     return rc;
+}
+
+int orc_decode_block(const uint64_t* in, int rate, float* out64, orc_stages* st)
+{
+    return orc_decode_block_mode(in, rate, 0, out64, st);
 }
 
 size_t orc_codec_words(long nx, long ny, long nz, int rate)
@@ -520,7 +572,7 @@ int orc_codec_encode(const float* f, long nx, long ny, long nz, int rate, uint64
     return bad ? -2 : 0;
 }
 
-int orc_codec_decode(const uint64_t* in, long nx, long ny, long nz, int rate, float* f)
+int orc_codec_decode_mode(const uint64_t* in, long nx, long ny, long nz, int rate, int mid, float* f)
 {
     if (nx % 4 || ny % 4 || nz % 4 || rate < 1 || rate > 64) return -1;
     long bxn = nx / 4, byn = ny / 4, bzn = nz / 4;
@@ -533,35 +585,50 @@ int orc_codec_decode(const uint64_t* in, long nx, long ny, long nz, int rate, fl
                 float blk[64];
                 size_t b = (size_t)bx + (size_t)bxn * ((size_t)by + (size_t)byn * (size_t)bz);
                 orc_stages st;
-                if (orc_decode_block(in + b * (size_t)rate, rate, blk, &st) != 0) bad = 1;
+                if (orc_decode_block_mode(in + b * (size_t)rate, rate, mid, blk, &st) != 0) bad = 1;
                 scatter_block(f, nx, ny, bx, by, bz, blk);
             }
     return bad ? -2 : 0;
 }
 
-/* Q = decode(encode(.)) in place on an FP32 field. */
-int orc_codec_roundtrip(float* f, long nx, long ny, long nz, int rate)
+int orc_codec_decode(const uint64_t* in, long nx, long ny, long nz, int rate, float* f)
+{
+    return orc_codec_decode_mode(in, nx, ny, nz, rate, 0, f);
+}
+
+/* Q = decode(encode(.)) in place on an FP32 field (mid: format step 9). */
+int orc_codec_roundtrip_mode(float* f, long nx, long ny, long nz, int rate, int mid)
 {
     size_t nw = orc_codec_words(nx, ny, nz, rate);
     uint64_t* w = (uint64_t*)calloc(nw ? nw : 1, sizeof(uint64_t));
     if (!w) return -1;
     int rc = orc_codec_encode(f, nx, ny, nz, rate, w);
-    if (rc == 0) rc = orc_codec_decode(w, nx, ny, nz, rate, f);
+    if (rc == 0) rc = orc_codec_decode_mode(w, nx, ny, nz, rate, mid, f);
     free(w);
     return rc;
 }
 
+int orc_codec_roundtrip(float* f, long nx, long ny, long nz, int rate)
+{
+    return orc_codec_roundtrip_mode(f, nx, ny, nz, rate, 0);
+}
+
 /* FP64 field through the FP32 codec: round to FP32, Q, widen back. */
-int orc_codec_roundtrip_f64(double* f, long nx, long ny, long nz, int rate)
+int orc_codec_roundtrip_f64_mode(double* f, long nx, long ny, long nz, int rate, int mid)
 {
     size_t n = (size_t)nx * ny * nz;
     float* t = (float*)malloc(n * sizeof(float));
     if (!t) return -1;
     for (size_t i = 0; i < n; ++i) t[i] = (float)f[i];
-    int rc = orc_codec_roundtrip(t, nx, ny, nz, rate);
+    int rc = orc_codec_roundtrip_mode(t, nx, ny, nz, rate, mid);
     for (size_t i = 0; i < n; ++i) f[i] = (double)t[i];
     free(t);
     return rc;
+}
+
+int orc_codec_roundtrip_f64(double* f, long nx, long ny, long nz, int rate)
+{
+    return orc_codec_roundtrip_f64_mode(f, nx, ny, nz, rate, 0);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -580,15 +647,34 @@ int orc_codec_roundtrip_f64(double* f, long nx, long ny, long nz, int rate)
 /* enters every step as Q(w). rate 0 means "not compressed".                */
 /* ------------------------------------------------------------------------ */
 
-int orc_replay_heat_f32(float* u, long nx, long ny, long nz, float alpha, long steps, long k, int rate)
+int orc_replay_heat_f32_mode(float* u, long nx, long ny, long nz, float alpha, long steps, long k, int rate, int mid)
 {
     if (k < 1) return -1;
     int rc = 0;
-    if (rate > 0 && (rc = orc_codec_roundtrip(u, nx, ny, nz, rate))) return rc;
+    if (rate > 0 && (rc = orc_codec_roundtrip_mode(u, nx, ny, nz, rate, mid))) return rc;
     for (long done = 0; done < steps;) {
         long kk = steps - done < k ? steps - done : k;
         if ((rc = orc_heat7_f32(u, nx, ny, nz, alpha, kk))) return rc;
-        if (rate > 0 && (rc = orc_codec_roundtrip(u, nx, ny, nz, rate))) return rc;
+        if (rate > 0 && (rc = orc_codec_roundtrip_mode(u, nx, ny, nz, rate, mid))) return rc;
+        done += kk;
+    }
+    return 0;
+}
+
+int orc_replay_heat_f32(float* u, long nx, long ny, long nz, float alpha, long steps, long k, int rate)
+{
+    return orc_replay_heat_f32_mode(u, nx, ny, nz, alpha, steps, k, rate, 0);
+}
+
+int orc_replay_heat_f64_mode(double* u, long nx, long ny, long nz, double alpha, long steps, long k, int rate, int mid)
+{
+    if (k < 1) return -1;
+    int rc = 0;
+    if (rate > 0 && (rc = orc_codec_roundtrip_f64_mode(u, nx, ny, nz, rate, mid))) return rc;
+    for (long done = 0; done < steps;) {
+        long kk = steps - done < k ? steps - done : k;
+        if ((rc = orc_heat7_f64(u, nx, ny, nz, alpha, kk))) return rc;
+        if (rate > 0 && (rc = orc_codec_roundtrip_f64_mode(u, nx, ny, nz, rate, mid))) return rc;
         done += kk;
     }
     return 0;
@@ -596,33 +682,48 @@ int orc_replay_heat_f32(float* u, long nx, long ny, long nz, float alpha, long s
 
 int orc_replay_heat_f64(double* u, long nx, long ny, long nz, double alpha, long steps, long k, int rate)
 {
+    return orc_replay_heat_f64_mode(u, nx, ny, nz, alpha, steps, k, rate, 0);
+}
+
+/* Wave: fields (pm, p) read-write at rates rate_pm / rate_p, w read-only at
+ * rate_w (0 = raw). src holds one amplitude per step (may be NULL). */
+int orc_replay_wave_f32_mode(float* p, float* pm, float* w, long nx, long ny, long nz, long steps, long k,
+                        const float* src, long src_index, int rate_p, int rate_pm, int rate_w, int mid)
+{
     if (k < 1) return -1;
     int rc = 0;
-    if (rate > 0 && (rc = orc_codec_roundtrip_f64(u, nx, ny, nz, rate))) return rc;
+    if (rate_w > 0 && (rc = orc_codec_roundtrip_mode(w, nx, ny, nz, rate_w, mid))) return rc;
+    if (rate_p > 0 && (rc = orc_codec_roundtrip_mode(p, nx, ny, nz, rate_p, mid))) return rc;
+    if (rate_pm > 0 && (rc = orc_codec_roundtrip_mode(pm, nx, ny, nz, rate_pm, mid))) return rc;
     for (long done = 0; done < steps;) {
         long kk = steps - done < k ? steps - done : k;
-        if ((rc = orc_heat7_f64(u, nx, ny, nz, alpha, kk))) return rc;
-        if (rate > 0 && (rc = orc_codec_roundtrip_f64(u, nx, ny, nz, rate))) return rc;
+        if ((rc = orc_wave25_f32(p, pm, w, nx, ny, nz, kk, src ? src + done : NULL, src_index))) return rc;
+        if (rate_p > 0 && (rc = orc_codec_roundtrip_mode(p, nx, ny, nz, rate_p, mid))) return rc;
+        if (rate_pm > 0 && (rc = orc_codec_roundtrip_mode(pm, nx, ny, nz, rate_pm, mid))) return rc;
         done += kk;
     }
     return 0;
 }
 
-/* Wave: fields (pm, p) read-write at rates rate_pm / rate_p, w read-only at
- * rate_w (0 = raw). src holds one amplitude per step (may be NULL). */
 int orc_replay_wave_f32(float* p, float* pm, float* w, long nx, long ny, long nz, long steps, long k,
                         const float* src, long src_index, int rate_p, int rate_pm, int rate_w)
 {
+    return orc_replay_wave_f32_mode(p, pm, w, nx, ny, nz, steps, k, src, src_index, rate_p, rate_pm, rate_w, 0);
+}
+
+int orc_replay_wave_f64_mode(double* p, double* pm, double* w, long nx, long ny, long nz, long steps, long k,
+                        const double* src, long src_index, int rate_p, int rate_pm, int rate_w, int mid)
+{
     if (k < 1) return -1;
     int rc = 0;
-    if (rate_w > 0 && (rc = orc_codec_roundtrip(w, nx, ny, nz, rate_w))) return rc;
-    if (rate_p > 0 && (rc = orc_codec_roundtrip(p, nx, ny, nz, rate_p))) return rc;
-    if (rate_pm > 0 && (rc = orc_codec_roundtrip(pm, nx, ny, nz, rate_pm))) return rc;
+    if (rate_w > 0 && (rc = orc_codec_roundtrip_f64_mode(w, nx, ny, nz, rate_w, mid))) return rc;
+    if (rate_p > 0 && (rc = orc_codec_roundtrip_f64_mode(p, nx, ny, nz, rate_p, mid))) return rc;
+    if (rate_pm > 0 && (rc = orc_codec_roundtrip_f64_mode(pm, nx, ny, nz, rate_pm, mid))) return rc;
     for (long done = 0; done < steps;) {
         long kk = steps - done < k ? steps - done : k;
-        if ((rc = orc_wave25_f32(p, pm, w, nx, ny, nz, kk, src ? src + done : NULL, src_index))) return rc;
-        if (rate_p > 0 && (rc = orc_codec_roundtrip(p, nx, ny, nz, rate_p))) return rc;
-        if (rate_pm > 0 && (rc = orc_codec_roundtrip(pm, nx, ny, nz, rate_pm))) return rc;
+        if ((rc = orc_wave25_f64(p, pm, w, nx, ny, nz, kk, src ? src + done : NULL, src_index))) return rc;
+        if (rate_p > 0 && (rc = orc_codec_roundtrip_f64_mode(p, nx, ny, nz, rate_p, mid))) return rc;
+        if (rate_pm > 0 && (rc = orc_codec_roundtrip_f64_mode(pm, nx, ny, nz, rate_pm, mid))) return rc;
         done += kk;
     }
     return 0;
@@ -631,19 +732,7 @@ int orc_replay_wave_f32(float* p, float* pm, float* w, long nx, long ny, long nz
 int orc_replay_wave_f64(double* p, double* pm, double* w, long nx, long ny, long nz, long steps, long k,
                         const double* src, long src_index, int rate_p, int rate_pm, int rate_w)
 {
-    if (k < 1) return -1;
-    int rc = 0;
-    if (rate_w > 0 && (rc = orc_codec_roundtrip_f64(w, nx, ny, nz, rate_w))) return rc;
-    if (rate_p > 0 && (rc = orc_codec_roundtrip_f64(p, nx, ny, nz, rate_p))) return rc;
-    if (rate_pm > 0 && (rc = orc_codec_roundtrip_f64(pm, nx, ny, nz, rate_pm))) return rc;
-    for (long done = 0; done < steps;) {
-        long kk = steps - done < k ? steps - done : k;
-        if ((rc = orc_wave25_f64(p, pm, w, nx, ny, nz, kk, src ? src + done : NULL, src_index))) return rc;
-        if (rate_p > 0 && (rc = orc_codec_roundtrip_f64(p, nx, ny, nz, rate_p))) return rc;
-        if (rate_pm > 0 && (rc = orc_codec_roundtrip_f64(pm, nx, ny, nz, rate_pm))) return rc;
-        done += kk;
-    }
-    return 0;
+    return orc_replay_wave_f64_mode(p, pm, w, nx, ny, nz, steps, k, src, src_index, rate_p, rate_pm, rate_w, 0);
 }
 
 /* The bit-plane coder alone (step 7/8 above) on 64 sequency-ordered
@@ -659,7 +748,21 @@ long orc_code_ints(const uint32_t* u64, long budget, uint64_t* out)
 int orc_decode_ints(const uint64_t* in, long budget, uint32_t* u64)
 {
     bitr s = {in, 0};
-    decode_planes(u64, budget, &s, NULL);
+    int stop_plane, stop_known;
+    decode_planes(u64, budget, &s, NULL, &stop_plane, &stop_known);
+    return 0;
+}
+
+/* The same, also returning where the budget ran out (format step 9):
+ * stop[0] = plane (-1 if the stream was complete), stop[1] = coefficients
+ * whose digit of that plane is known. */
+int orc_decode_ints_stop(const uint64_t* in, long budget, uint32_t* u64, int32_t* stop)
+{
+    bitr s = {in, 0};
+    int stop_plane, stop_known;
+    decode_planes(u64, budget, &s, NULL, &stop_plane, &stop_known);
+    stop[0] = stop_plane;
+    stop[1] = stop_known;
     return 0;
 }
 

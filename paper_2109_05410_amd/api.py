@@ -57,12 +57,15 @@ def codec_encode(field: torch.Tensor, rate: int, out: torch.Tensor | None = None
     return out
 
 
-def codec_decode(words: torch.Tensor, shape, rate: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+def codec_decode(words: torch.Tensor, shape, rate: int, out: torch.Tensor | None = None, stream=None,
+                 mid: bool = False) -> torch.Tensor:
+    """mid: mid-point reconstruction of the digits the budget cut off."""
     nz, ny, nx = shape
     if out is None:
         out = torch.empty((nz, ny, nx), dtype=torch.float32, device=words.device)
     _field(out, "out")
-    L.check(L.lib().oocs_codec_decode(_dptr(words), words.numel() * words.element_size(), nx, ny, nz, rate,
+    r = rate | (L.OOCS_DECODE_MIDPOINT if mid else 0)
+    L.check(L.lib().oocs_codec_decode(_dptr(words), words.numel() * words.element_size(), nx, ny, nz, r,
                                       _dptr(out), nx, nx * ny, _stream_ptr(stream)))
     return out
 
@@ -86,8 +89,8 @@ def codec_encode_stages(blocks: torch.Tensor, rate: int) -> dict:
     return o
 
 
-def codec_decode_stages(words: torch.Tensor, rate: int) -> dict:
-    """words: (N, rate) int64 device tensor."""
+def codec_decode_stages(words: torch.Tensor, rate: int, mid: bool = False) -> dict:
+    """words: (N, rate) int64 device tensor; mid: mid-point reconstruction."""
     n = words.shape[0]
     dev = words.device
     o = {
@@ -97,7 +100,8 @@ def codec_decode_stages(words: torch.Tensor, rate: int) -> dict:
         "q": torch.empty((n, 64), dtype=torch.int32, device=dev),
         "out": torch.empty((n, 64), dtype=torch.float32, device=dev),
     }
-    L.check(L.lib().oocs_codec_decode_stages(_dptr(words.contiguous()), n, rate, _dptr(o["emax"]), _dptr(o["plane"]),
+    L.check(L.lib().oocs_codec_decode_stages(_dptr(words.contiguous()), n, rate | (L.OOCS_DECODE_MIDPOINT if mid else 0),
+                                             _dptr(o["emax"]), _dptr(o["plane"]),
                                              _dptr(o["u"]), _dptr(o["q"]), _dptr(o["out"]), _stream_ptr()))
     return o
 
@@ -219,13 +223,15 @@ class OutOfCorePlan:
     once into the arena and stays there instead of being streamed every
     residency. snake: residencies alternate the sweep direction and the
     block a residency ends with stays on the device (compressed, or raw if
-    uncompressed) for the next one. Results are identical."""
+    uncompressed) for the next one. Results are identical. midpoint: every
+    decode reconstructs the digits the budget cut off at the middle of their
+    range (a different, lower-error state)."""
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
                  planning_only: bool = False, device=None, block_restart: bool = False,
                  kernel_transfers: bool = False, level_by_level: bool = False, kernel_stores: bool = False,
-                 resident_ro: bool = False, snake: bool = False):
+                 resident_ro: bool = False, snake: bool = False, midpoint: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -242,7 +248,8 @@ class OutOfCorePlan:
                      | (L.OOCS_PLAN_LEVEL_BY_LEVEL if level_by_level else 0)
                      | (L.OOCS_PLAN_KERNEL_STORES if kernel_stores else 0)
                      | (L.OOCS_PLAN_RESIDENT_RO if resident_ro else 0)
-                     | (L.OOCS_PLAN_SNAKE if snake else 0))
+                     | (L.OOCS_PLAN_SNAKE if snake else 0)
+                     | (L.OOCS_PLAN_MIDPOINT if midpoint else 0))
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg

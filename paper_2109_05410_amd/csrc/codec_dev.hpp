@@ -113,6 +113,25 @@ __device__ inline void from_sequency(const uint32_t (&u)[64], int (&t)[64], std:
     ((t[I] = (int)((u[kRank<I>] ^ kNB) - kNB)), ...);
 }
 
+// The same with mid-point reconstruction: a nonzero coefficient at sequency
+// position k gets off_a added if k < known (its digit of the stop plane was
+// read), else off_b (32-bit wrap-around).
+template <int... I>
+__device__ inline void from_sequency_mid(const uint32_t (&u)[64], int (&t)[64], int known, uint32_t off_a,
+                                         uint32_t off_b, std::integer_sequence<int, I...>)
+{
+    ((t[I] = (int)(((u[kRank<I>] ^ kNB) - kNB) + (u[kRank<I>] ? (kRank<I> < known ? off_a : off_b) : 0u))), ...);
+}
+
+// Middle of the values L cut-off negabinary digits can add: half of the
+// all-ones sum (1 - (-2)^L) / 3, rounded down.
+__device__ inline uint32_t midpoint_offset(int L)
+{
+    const int64_t pw = (L & 1) ? -((int64_t)1 << L) : ((int64_t)1 << L);
+    const int64_t all_ones = (1 - pw) / 3;
+    return (uint32_t)(all_ones >> 1);
+}
+
 // One stage of the in-place 32 x 32 bit transpose: swap the off-diagonal
 // S x S sub-blocks of every 2S x 2S block.
 template <int S, uint32_t M>
@@ -342,7 +361,11 @@ struct DecStageOut {
 };
 
 // Decode this lane's block from words w*64 of `lds` into x[64] (natural order).
-template <bool STAGES>
+// MID: mid-point reconstruction. Where the budget runs out the decoder
+// notes the plane and how many coefficients (a prefix in sequency order)
+// know their digit of it; a plane that the last bit completes makes the
+// next plane the stop plane with none known.
+template <bool STAGES, bool MID = false>
 __device__ inline void decode_lane(const uint64_t* lds, int rate, float (&x)[64], DecStageOut st = {}, int64_t b = 0)
 {
     LaneReader r{lds, rate, 0, 0, 0, 0, 0, 0};
@@ -366,6 +389,7 @@ __device__ inline void decode_lane(const uint64_t* lds, int rate, float (&x)[64]
     const int emax = (int)r.get(8) - 127;
     int budget = 64 * rate - 9;
     int n = 0;
+    int stop_p = -1, stop_m = 0;  // MID: where the budget ran out
     uint32_t lo[32], hi[32];
     for (int p = 31; p >= 0; --p) {
         uint64_t X = 0;
@@ -373,6 +397,7 @@ __device__ inline void decode_lane(const uint64_t* lds, int rate, float (&x)[64]
             const int m = n < budget ? n : budget;
             X = r.get(m);
             budget -= m;
+            int known = m;  // MID: digits of this plane read or implied (a prefix)
             // One window per group test: the test bit, the run of zeros and
             // the 1 that ends it are read together (the run is at most 62
             // bits unless it reaches the last coefficient or the budget).
@@ -394,9 +419,14 @@ __device__ inline void decode_lane(const uint64_t* lds, int rate, float (&x)[64]
                 X |= (!neg && !stop) ? (uint64_t)1 << n1 : 0;
                 X |= (!neg && last) ? (uint64_t)1 << 63 : 0;
                 r.skip(neg ? 1 : (stop ? 1 + z : 2 + z));
+                if (MID) known = (neg || last) ? 64 : (stop ? n1 : n1 + 1);
                 n = neg ? n : (last ? 64 : (stop ? n1 : n1 + 1));
                 budget = neg ? b1 : (stop ? b2 : b2 - 1);
                 more = !neg && !stop && budget > 0;
+            }
+            if (MID && budget == 0 && stop_p < 0) {
+                stop_p = known < 64 ? p : p - 1;
+                stop_m = known < 64 ? known : 0;
             }
         }
         const int pu = __builtin_amdgcn_readfirstlane(p);  // uniform: plain register indexing
@@ -407,7 +437,13 @@ __device__ inline void decode_lane(const uint64_t* lds, int rate, float (&x)[64]
     uint32_t u[64];
     coefficients_of(lo, hi, u);
     int t[64];
-    from_sequency(u, t, std::make_integer_sequence<int, 64>{});
+    if (MID) {
+        const uint32_t off_a = stop_p >= 0 ? midpoint_offset(stop_p) : 0u;
+        const uint32_t off_b = stop_p >= 0 ? midpoint_offset(stop_p + 1) : 0u;
+        from_sequency_mid(u, t, stop_m, off_a, off_b, std::make_integer_sequence<int, 64>{});
+    } else {
+        from_sequency(u, t, std::make_integer_sequence<int, 64>{});
+    }
     inv_xform(t);
     if (STAGES) {
         if (st.emax) st.emax[b] = emax;

@@ -132,10 +132,12 @@ int oocs_codec_decode(const uint64_t* d_in, size_t in_bytes, int64_t nx, int64_t
 {
     if (!d_in || !d_out) return fail(OOCS_E_ARG, "null pointer");
     if ((uintptr_t)d_out % 16 || (uintptr_t)d_in % 8) return fail(OOCS_E_ALIGN, "field must be 16-byte aligned, words 8-byte aligned");
+    const bool mid = (rate & OOCS_DECODE_MIDPOINT) != 0;
+    rate &= ~OOCS_DECODE_MIDPOINT;
     int rc = codec_check(nx, ny, nz, ld_y, ld_z, rate, in_bytes);
     if (rc) return rc;
     HIP_TRY(oocs::launch_codec_field(false, nullptr, d_out, d_in, nullptr, nx, ny, nz, ld_y, ld_z, rate,
-                                     (hipStream_t)stream));
+                                     (hipStream_t)stream, mid));
     return OOCS_OK;
 }
 
@@ -154,9 +156,11 @@ int oocs_codec_decode_stages(const uint64_t* d_words, int64_t nblocks, int rate,
                              uint32_t* d_u, int32_t* d_q, float* d_out, void* stream)
 {
     if (!d_words || nblocks < 0) return fail(OOCS_E_ARG, "bad block input");
+    const bool mid = (rate & OOCS_DECODE_MIDPOINT) != 0;
+    rate &= ~OOCS_DECODE_MIDPOINT;
     if (rate < 1 || rate > OOCS_MAX_RATE) return fail(OOCS_E_RATE, "rate must be in [1, 34]");
     oocs::DecStages s{d_emax, d_planes, d_u, d_q, d_out};
-    HIP_TRY(oocs::launch_decode_stages(d_words, nblocks, rate, s, (hipStream_t)stream));
+    HIP_TRY(oocs::launch_decode_stages(d_words, nblocks, rate, mid, s, (hipStream_t)stream));
     return OOCS_OK;
 }
 
@@ -433,7 +437,7 @@ static int store_xfer(oocs_plan* pl, int f, bool put, const float* h_field_in, f
             HIP_TRY(hipMemcpyAsync(comp, static_cast<const char*>(h_store_in) + z0 * spb, (size_t)(planes * spb),
                                    hipMemcpyHostToDevice, s));
             HIP_TRY(oocs::launch_codec_field(false, nullptr, reinterpret_cast<float*>(raw), comp, nullptr, P.nx, P.ny, planes,
-                                             P.nx, P.plane_elems(), rate, s));
+                                             P.nx, P.plane_elems(), rate, s, P.midpoint));
             HIP_TRY(hipMemcpyAsync(h_field_out + z0 * P.plane_elems(), raw, (size_t)(planes * pb), hipMemcpyDeviceToHost, s));
         }
         HIP_TRY(hipStreamSynchronize(s));
@@ -684,6 +688,7 @@ struct OpTranslator {
             const int rate = P.cfg.rate[o.field];
             j.kind = rate ? (dec ? oocs::JOB_DECODE : oocs::JOB_ENCODE) : (dec ? oocs::JOB_COPY_IN : oocs::JOB_COPY_OUT);
             j.rate = rate;
+            j.mid = dec && P.midpoint ? 1 : 0;
             j.dst = ring(o.level);
             if (o.slot == OOCS_SLOT_RETAINED)  // snake: the retained block, laid out like the host store
                 j.stage = pl->arena + P.ret_off[o.field] + (o.z0 - P.ret_base(o.z0)) * P.store_plane_bytes(o.field);
@@ -723,6 +728,7 @@ int load_resident_ro(oocs_plan* pl, const void* h_ro)
         oocs::Job& j = lp.jobs[0];
         j.kind = rate ? oocs::JOB_DECODE : oocs::JOB_COPY_IN;
         j.rate = rate;
+        j.mid = P.midpoint ? 1 : 0;
         j.z0 = (int32_t)z0;
         j.z1 = (int32_t)z1;
         j.dst = oocs::Ring{reinterpret_cast<float*>(pl->arena + P.ringOff[P.ro_ring()]), P.ringW[P.ro_ring()],

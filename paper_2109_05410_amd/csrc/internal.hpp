@@ -46,6 +46,8 @@ struct Job {
     float amp;         // the amplitude when LaunchParams::src_table is null
     int32_t src_off;   // else the amplitude is src_table[*step_ctr + src_off]
     int32_t wg_count;  // workgroups of this job
+    int32_t mid;       // decode jobs: mid-point reconstruction of the digits the budget cut off
+    int32_t pad_;
     Ring src, src2, ro, dst;  // stencil jobs (dst doubles as `ring` for codec/copy jobs)
     void* stage;              // codec/copy/transfer jobs
     void* host;               // transfer jobs: device address of the host-store bytes
@@ -95,10 +97,11 @@ hipError_t launch_step_ctr(int32_t* ctr, bool add, int32_t value, hipStream_t st
 hipError_t add_step_ctr_node(int32_t* ctr, bool add, int32_t value, hipGraph_t g, const hipGraphNode_t* deps,
                              size_t ndeps, hipGraphNode_t* node);
 
-// Standalone codec launches on dense (non-ring) fields.
+// Standalone codec launches on dense (non-ring) fields; mid: mid-point
+// reconstruction when decoding.
 hipError_t launch_codec_field(bool encode, const float* in_f, float* out_f, const uint64_t* in_w, uint64_t* out_w,
                               int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t ld_z, int rate,
-                              hipStream_t stream);
+                              hipStream_t stream, bool mid = false);
 
 // Exchange the contents of two device arrays of n floats.
 hipError_t launch_swap(float* a, float* b, int64_t n, hipStream_t stream);
@@ -199,6 +202,7 @@ struct DecStages {
     int32_t* emax; uint64_t* planes; uint32_t* u; int32_t* q; float* out;
 };
 hipError_t launch_encode_stages(const float* blocks, int64_t nblocks, int rate, EncStages s, hipStream_t stream);
-hipError_t launch_decode_stages(const uint64_t* words, int64_t nblocks, int rate, DecStages s, hipStream_t stream);
+hipError_t launch_decode_stages(const uint64_t* words, int64_t nblocks, int rate, bool mid, DecStages s,
+                                hipStream_t stream);
 
 }  // namespace oocs

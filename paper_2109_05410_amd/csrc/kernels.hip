@@ -31,6 +31,7 @@ extern __shared__ uint64_t dyn_lds[];  // codec jobs: 64 * rate words per wave
 // Each wave codes 64 blocks consecutive in x (one lane per block). Staging
 // slot of compressed words: the 4-plane layers of [z0, z1) in z order, each
 // layer's blocks x fastest then y; rate words per block.
+template <bool MID>
 __device__ inline void codec_job(const Job& j, int nx, int ny, int wg, bool encode)
 {
     const int lane = (int)(threadIdx.x & 63);
@@ -71,7 +72,7 @@ __device__ inline void codec_job(const Job& j, int nx, int ny, int wg, bool enco
         if (nblocks > 0) codec::words_to_lds(words, lds, rate, nblocks, lane);
         __syncthreads();
         if (active) {
-            codec::decode_lane<false>(lds + lane, rate, x);
+            codec::decode_lane<false, MID>(lds + lane, rate, x);
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
                 float* pl = ring_plane(j.dst, z + l) + row0;
@@ -152,7 +153,10 @@ __device__ inline void xfer_job(const Job& j, int wg)
 // whole tick; codec jobs come next
 // so that their workgroups, whose lanes each run a whole block's serial bit
 // coding, are dispatched first and the short stencil workgroups fill the
-// machine around them.
+// machine around them. MID: the decode jobs reconstruct cut-off digits at
+// mid-points (a separate kernel: the extra registers would make the common
+// kernel spill).
+template <bool MID>
 __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
 {
     const int wg = (int)blockIdx.x;
@@ -161,8 +165,8 @@ __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
     const Job& j = p.jobs[jdx];
     const int local = wg - p.wg_begin[jdx];
     switch (j.kind) {
-    case JOB_DECODE: codec_job(j, p.nx, p.ny, local, false); break;
-    case JOB_ENCODE: codec_job(j, p.nx, p.ny, local, true); break;
+    case JOB_DECODE: codec_job<MID>(j, p.nx, p.ny, local, false); break;
+    case JOB_ENCODE: codec_job<false>(j, p.nx, p.ny, local, true); break;
     case JOB_HEAT: stencil::heat_level<kHeatBatch>(j, p.nx, p.ny, p.nz, p.alpha, local); break;
     case JOB_WAVE:
         stencil::wave_tile(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr, local,
@@ -287,8 +291,10 @@ static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, siz
         if (p.jobs[i].kind == JOB_HEAT_TB && heat_tb_lds(p.jobs[i].rate) > tb_lds) tb_lds = heat_tb_lds(p.jobs[i].rate);
         if (p.jobs[i].kind == JOB_WAVE && stencil::wave_tile_lds() > tb_lds) tb_lds = stencil::wave_tile_lds();
     }
+    bool mid = false;
+    for (int i = 0; i < n; ++i) mid = mid || (p.jobs[i].kind == JOB_DECODE && p.jobs[i].mid);
     if (max_rate > 0) {
-        *func = reinterpret_cast<const void*>(&fused_kernel);
+        *func = mid ? reinterpret_cast<const void*>(&fused_kernel<true>) : reinterpret_cast<const void*>(&fused_kernel<false>);
         const size_t codec_lds = (size_t)kWavesPerWG * 64 * max_rate * sizeof(uint64_t);
         *lds = codec_lds > tb_lds ? codec_lds : tb_lds;
     } else {
@@ -306,8 +312,10 @@ hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
     unsigned grid;
     size_t lds;
     if (!prepare_jobs(p, &func, &grid, &lds)) return hipSuccess;
-    if (func == reinterpret_cast<const void*>(&fused_kernel))
-        hipLaunchKernelGGL(fused_kernel, dim3(grid), dim3(kBlockThreads), lds, stream, p);
+    if (func == reinterpret_cast<const void*>(&fused_kernel<false>))
+        hipLaunchKernelGGL(fused_kernel<false>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
+    else if (func == reinterpret_cast<const void*>(&fused_kernel<true>))
+        hipLaunchKernelGGL(fused_kernel<true>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
     else if (func == reinterpret_cast<const void*>(&stencil_kernel<kStencilWave>))
         hipLaunchKernelGGL(stencil_kernel<kStencilWave>, dim3(grid), dim3(kBlockThreads), lds, stream, p);
     else if (func == reinterpret_cast<const void*>(&stencil_kernel<kStencilHeat>))
@@ -365,6 +373,9 @@ hipError_t add_step_ctr_node(int32_t* ctr, bool add, int32_t value, hipGraph_t g
 // Standalone codec on dense fields
 // ---------------------------------------------------------------------------
 
+// MID: decode with mid-point reconstruction (its own kernel, for the
+// registers).
+template <bool MID>
 __global__ void __launch_bounds__(kBlockThreads)
 codec_field_kernel(bool encode, const float* in_f, float* out_f, const uint64_t* in_w, uint64_t* out_w, int nbx,
                    int nby, int nbz, int64_t ld_y, int64_t ld_z, int rate)
@@ -401,7 +412,7 @@ codec_field_kernel(bool encode, const float* in_f, float* out_f, const uint64_t*
         if (nblocks > 0) codec::words_to_lds(in_w + blk0 * rate, lds, rate, nblocks, lane);
         __syncthreads();
         if (active) {
-            codec::decode_lane<false>(lds + lane, rate, x);
+            codec::decode_lane<false, MID>(lds + lane, rate, x);
 #pragma unroll
             for (int l = 0; l < 4; ++l)
 #pragma unroll
@@ -414,15 +425,19 @@ codec_field_kernel(bool encode, const float* in_f, float* out_f, const uint64_t*
 
 hipError_t launch_codec_field(bool encode, const float* in_f, float* out_f, const uint64_t* in_w, uint64_t* out_w,
                               int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t ld_z, int rate,
-                              hipStream_t stream)
+                              hipStream_t stream, bool mid)
 {
     const int nbx = (int)(nx / 4), nby = (int)(ny / 4), nbz = (int)(nz / 4);
     const int64_t waves = (int64_t)((nbx + 63) / 64) * nby * nbz;
     const int64_t groups = (waves + kWavesPerWG - 1) / kWavesPerWG;
     if (groups == 0) return hipSuccess;
     const size_t lds = (size_t)kWavesPerWG * 64 * rate * sizeof(uint64_t);
-    hipLaunchKernelGGL(codec_field_kernel, dim3((unsigned)groups), dim3(kBlockThreads), lds, stream, encode, in_f,
-                       out_f, in_w, out_w, nbx, nby, nbz, ld_y, ld_z, rate);
+    if (mid && !encode)
+        hipLaunchKernelGGL(codec_field_kernel<true>, dim3((unsigned)groups), dim3(kBlockThreads), lds, stream, false,
+                           in_f, out_f, in_w, out_w, nbx, nby, nbz, ld_y, ld_z, rate);
+    else
+        hipLaunchKernelGGL(codec_field_kernel<false>, dim3((unsigned)groups), dim3(kBlockThreads), lds, stream, encode,
+                           in_f, out_f, in_w, out_w, nbx, nby, nbz, ld_y, ld_z, rate);
     return hipGetLastError();
 }
 
@@ -924,7 +939,7 @@ encode_stages_kernel(const float* blocks, int64_t nblocks, int rate, EncStages s
 }
 
 __global__ void __launch_bounds__(kBlockThreads)
-decode_stages_kernel(const uint64_t* words, int64_t nblocks, int rate, DecStages s)
+decode_stages_kernel(const uint64_t* words, int64_t nblocks, int rate, bool mid, DecStages s)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int wave = (int)(threadIdx.x >> 6);
@@ -937,7 +952,8 @@ decode_stages_kernel(const uint64_t* words, int64_t nblocks, int rate, DecStages
     if (lane < nb) {
         float x[64];
         codec::DecStageOut st{s.emax, s.planes, s.u, s.q};
-        codec::decode_lane<true>(lds + lane, rate, x, st, b);
+        if (mid) codec::decode_lane<true, true>(lds + lane, rate, x, st, b);
+        else codec::decode_lane<true, false>(lds + lane, rate, x, st, b);
         if (s.out) {
 #pragma unroll
             for (int i = 0; i < 64; ++i) s.out[64 * b + i] = x[i];
@@ -954,12 +970,13 @@ hipError_t launch_encode_stages(const float* blocks, int64_t nblocks, int rate, 
     return hipGetLastError();
 }
 
-hipError_t launch_decode_stages(const uint64_t* words, int64_t nblocks, int rate, DecStages s, hipStream_t stream)
+hipError_t launch_decode_stages(const uint64_t* words, int64_t nblocks, int rate, bool mid, DecStages s,
+                                hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
     const unsigned g = (unsigned)((nblocks + 64 * kWavesPerWG - 1) / (64 * kWavesPerWG));
     const size_t lds = (size_t)kWavesPerWG * 64 * rate * sizeof(uint64_t);
-    hipLaunchKernelGGL(decode_stages_kernel, dim3(g), dim3(kBlockThreads), lds, stream, words, nblocks, rate, s);
+    hipLaunchKernelGGL(decode_stages_kernel, dim3(g), dim3(kBlockThreads), lds, stream, words, nblocks, rate, mid, s);
     return hipGetLastError();
 }
 

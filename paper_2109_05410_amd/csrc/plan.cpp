@@ -55,7 +55,7 @@ int Planner::init(const oocs_config& c, std::string& err)
     if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
     if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS | OOCS_PLAN_LEVEL_BY_LEVEL |
-                    OOCS_PLAN_KERNEL_STORES | OOCS_PLAN_RESIDENT_RO | OOCS_PLAN_SNAKE)) {
+                    OOCS_PLAN_KERNEL_STORES | OOCS_PLAN_RESIDENT_RO | OOCS_PLAN_SNAKE | OOCS_PLAN_MIDPOINT)) {
         err = "unknown plan flags";
         return OOCS_E_ARG;
     }
@@ -72,6 +72,7 @@ int Planner::init(const oocs_config& c, std::string& err)
         return OOCS_E_ARG;
     }
     X = snake ? slab : 0;
+    midpoint = (c.flags & OOCS_PLAN_MIDPOINT) != 0;
     // kernel-driven transfers fetch one group ahead inside the launch: two slots suffice;
     // copy engines keep three groups in flight ahead of the decode
     nstage = c.nstage ? c.nstage : (copy_engines ? 4 : 2);

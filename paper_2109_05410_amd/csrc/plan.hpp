@@ -87,6 +87,7 @@ public:
     bool fused = false;         // heat: one temporally blocked job per tick computes all k levels
     bool resident_ro = false;   // wave: the read-only field stays decoded in an nz-plane ring
     bool snake = false;         // alternating sweeps; the last block of a residency stays on the device
+    bool midpoint = false;      // every decode with mid-point reconstruction
     int64_t X = 0;              // snake: planes of the retained block (one slab)
     static constexpr int kMaxFusedSteps = 4;
     int64_t slab = 0, h = 0;

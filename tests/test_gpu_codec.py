@@ -146,3 +146,37 @@ def test_full_size_sampled_blocks():
         blk = f[4 * bz:4 * bz + 4, 4 * by:4 * by + 4, 4 * bx:4 * bx + 4].reshape(64)
         want, _ = O.encode_block(blk, rate)
         assert np.array_equal(words[b * rate:(b + 1) * rate], want), b
+
+
+@pytest.mark.parametrize("rate", RATES)
+def test_midpoint_decode_stages_bit_exact(rate):
+    """Mid-point reconstruction: the digits read are the same, and the
+    integers after the inverse transform and the values equal the oracle's
+    bit for bit (the stop plane and known prefix decide every offset)."""
+    blocks = block_zoo(seed=200 + rate)
+    words = np.stack([O.encode_block(b, rate)[0] for b in blocks])
+    st = api.codec_decode_stages(torch.from_numpy(words.view(np.int64)).to(DEV), rate, mid=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in st.items()}
+    changed = 0
+    for b in range(blocks.shape[0]):
+        vals, o = O.decode_block(words[b], rate, mid=True)
+        zf, _ = O.decode_block(words[b], rate)
+        assert np.array_equal(g["u"][b].view(np.uint32), o["u"]), b
+        if o["emax"] != O.EMAX_ZERO:
+            assert np.array_equal(g["q"][b], o["q"]), b
+        assert np.array_equal(g["out"][b].view(np.uint32), vals.view(np.uint32)), b
+        changed += int(not np.array_equal(vals, zf))
+    if rate < 34:
+        assert changed > 0
+
+
+@pytest.mark.parametrize("shape", [(20, 36, 68), (8, 12, 260)])
+@pytest.mark.parametrize("rate", [1, 8, 12, 16])
+def test_midpoint_field_decode_matches_oracle(shape, rate):
+    f = np.random.default_rng(rate + 7).standard_normal(shape).astype(np.float32)
+    want_w = O.codec_encode(f, rate)
+    dec = api.codec_decode(torch.from_numpy(want_w.view(np.int64)).to(DEV), shape, rate, mid=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(dec.cpu().numpy().view(np.uint32),
+                          O.codec_decode(want_w, shape, rate, mid=True).view(np.uint32))

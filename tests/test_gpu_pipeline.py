@@ -459,3 +459,35 @@ def test_wave_snake_matches_replay(rates, resident_ro, graphs):
                                    rate_w=rates[2])
     assert np.array_equal(decoded(st[0], shape, rates[0]), wp)
     assert np.array_equal(decoded(st[1], shape, rates[1]), wpm)
+
+
+@pytest.mark.parametrize("snake", [False, True])
+def test_midpoint_pipeline_matches_replay(snake):
+    """Plans with mid-point decoding compute the replay in which every
+    decode o encode reconstructs mid-points: heat (fused levels) and the
+    wave with every field compressed; the store read back by get() too."""
+    shape = (128, 64, 64)
+    u0 = inputs.heat_uniform(shape, seed=9)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, 4, 4, [8], 2 * MiB, midpoint=True, snake=snake)
+    s = store_of(plan, 0, u0)
+    plan.run([s], 13)
+    want = O.replay_heat_f32(u0, 0.1, 13, 4, 8, mid=True)
+    assert np.array_equal(O.codec_decode(s.numpy().view(np.uint64), shape, 8, mid=True), want)
+    assert np.array_equal(plan.get(0, s), want)
+    assert not np.array_equal(want, O.replay_heat_f32(u0, 0.1, 13, 4, 8))
+
+    wshape = (96, 36, 40)
+    rng = np.random.default_rng(8)
+    p0 = (rng.standard_normal(wshape) * 0.1).astype(np.float32)
+    pm0 = (rng.standard_normal(wshape) * 0.1).astype(np.float32)
+    w = (0.02 + 0.1 * rng.random(wshape)).astype(np.float32)
+    amps = rng.standard_normal(13).astype(np.float32)
+    cell = (17, 20, 50)
+    idx = cell[0] + wshape[2] * (cell[1] + wshape[1] * cell[2])
+    wp = api.OutOfCorePlan(wshape, api.WAVE25, 3, 4, [12, 12, 12], 16 * MiB, src_cell=cell, midpoint=True,
+                           snake=snake)
+    st = [store_of(wp, 0, p0), store_of(wp, 1, pm0), store_of(wp, 2, w)]
+    wp.run(st, 13, src_amps=amps)
+    rp, rpm, _ = O.replay_wave_f32(p0, pm0, w, 13, 4, src=(amps, idx), rate_p=12, rate_pm=12, rate_w=12, mid=True)
+    assert np.array_equal(O.codec_decode(st[0].numpy().view(np.uint64), wshape, 12, mid=True), rp)
+    assert np.array_equal(O.codec_decode(st[1].numpy().view(np.uint64), wshape, 12, mid=True), rpm)

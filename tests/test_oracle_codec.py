@@ -258,3 +258,126 @@ def test_subnormal_exponent_clamp():
     assert st["emax"] == -126
     d, _ = O.decode_block(w, 34)
     assert np.max(np.abs(d - x)) <= 2.0 ** (-126 - 20)
+
+
+# ---------------------------------------------------------------------------
+# mid-point reconstruction (a decoding option; format step 9 in oracle.c)
+# ---------------------------------------------------------------------------
+
+def nb_value(u):
+    """Integer of a 32-digit negabinary word, by its digits."""
+    return sum(((int(u) >> j) & 1) * (-2) ** j for j in range(32))
+
+
+def known_digits(u, budget):
+    """Brute force: digit p of coefficient i is determined by the first
+    `budget` bits unless some other block with that digit flipped codes to
+    the same bits. The candidates are the block with only that digit
+    flipped, and with one more digit of the same plane flipped (which is
+    what keeps a group test's answer, 'some digit at or after position n is
+    1', unchanged)."""
+    base, used = O.code_ints(u, budget)
+    known = np.zeros((64, 32), bool)
+    for p in range(32):
+        bit = np.uint32(1 << p)
+        for i in range(64):
+            v = u.copy()
+            v[i] ^= bit
+            if np.array_equal(O.code_ints(v, budget)[0], base):
+                continue
+            same = False
+            for j in range(64):
+                if j == i:
+                    continue
+                v2 = v.copy()
+                v2[j] ^= bit
+                if np.array_equal(O.code_ints(v2, budget)[0], base):
+                    same = True
+                    break
+            known[i, p] = not same
+    return known
+
+
+def sample_coefficients(rng, n):
+    """Negabinary coefficient blocks with the energy decay of smooth data:
+    large low-sequency coefficients, small high-sequency ones."""
+    out = []
+    for _ in range(n):
+        mag = (2.0 ** rng.uniform(0, 28, 64)) * np.exp(-np.arange(64) / rng.uniform(4, 40))
+        q = (rng.choice([-1, 1], 64) * mag).astype(np.int64)
+        out.append(((q.astype(np.uint32) + np.uint32(0xAAAAAAAA)) ^ np.uint32(0xAAAAAAAA)).astype(np.uint32))
+    return out
+
+
+@pytest.mark.parametrize("budget", [40, 137, 300, 555, 1001])
+def test_stop_point_matches_brute_force_known_digits(budget):
+    """The decoder's stop plane P and known prefix m agree with the digits
+    the stream actually depends on: coefficient i knows exactly its digits
+    at planes >= P + (i >= m) (all of them if the stream is complete)."""
+    rng = np.random.default_rng(budget)
+    for u in sample_coefficients(rng, 3):
+        known = known_digits(u, budget)
+        w, _ = O.code_ints(u, budget)
+        _, P, m = O.decode_ints_stop(w, budget)
+        for i in range(64):
+            L = 0 if P < 0 else (P if i < m else P + 1)
+            assert np.array_equal(known[i], np.arange(32) >= L), (i, P, m)
+
+
+def test_midpoint_is_the_middle_of_the_consistent_integers():
+    """With mid-point reconstruction a nonzero coefficient whose L low digits
+    were cut off becomes the middle (rounded down) of the smallest and
+    largest integers its known digits allow, found by enumerating every
+    completion of the L digits (L <= 12 here); zero coefficients stay zero;
+    the result is never farther from the true integer than half the range."""
+    rng = np.random.default_rng(7)
+    seen = 0
+    for rate in (14, 18, 24, 28):
+        for _ in range(30):
+            x = rng.standard_normal(64).astype(np.float32) * np.float32(2.0 ** rng.integers(-8, 8))
+            words, est = O.encode_block(x, rate)
+            _, zf = O.decode_block(words, rate)
+            _, md = O.decode_block(words, rate, mid=True)
+            P, m = md["stop_plane"], md["stop_known"]
+            assert (P, m) == (zf["stop_plane"], zf["stop_known"])
+            assert np.array_equal(md["u"], zf["u"])  # the digits read are the same
+            perm = O.codec_perm()
+            for k in range(64):
+                L = 0 if P < 0 else (P if k < m else P + 1)
+                got = int(md["t"][perm[k]])
+                if zf["u"][k] == 0 or L == 0:
+                    assert got == int(zf["t"][perm[k]])
+                    continue
+                if L > 12:
+                    continue
+                base = nb_value(zf["u"][k])
+                vals = [base + sum(((c >> j) & 1) * (-2) ** j for j in range(L)) for c in range(1 << L)]
+                lo, hi = min(vals), max(vals)
+                assert got == (lo + hi) // 2, (k, L)
+                truth = nb_value(est["u"][k])
+                assert lo <= truth <= hi
+                assert abs(got - truth) <= (hi - lo + 1) // 2
+                seen += 1
+    assert seen > 200
+
+
+def test_midpoint_changes_nothing_when_the_stream_is_complete():
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((8, 8, 8)).astype(np.float32)
+    w = O.codec_encode(f, 34)
+    assert np.array_equal(O.codec_decode(w, f.shape, 34, mid=True), O.codec_decode(w, f.shape, 34))
+    z = np.zeros((4, 8, 8), np.float32)
+    assert not np.any(O.codec_decode(O.codec_encode(z, 4), z.shape, 4, mid=True))
+
+
+@pytest.mark.parametrize("rate", [4, 8, 12])
+def test_midpoint_lowers_the_error_on_smooth_data(rate):
+    """On a smooth field plus noise (the diffused heat and the developed
+    wavefield are of this kind) mid-point reconstruction lowers the L2
+    error of decode(encode()) against the input."""
+    rng = np.random.default_rng(rate)
+    z, y, x = np.meshgrid(*(np.linspace(0, 1, 32),) * 3, indexing="ij")
+    f = (np.sin(3 * x + 1) * np.cos(2 * y) * np.exp(-z) + 1e-3 * rng.standard_normal(x.shape)).astype(np.float32)
+    e0 = np.linalg.norm(O.codec_roundtrip(f, rate) - f)
+    e1 = np.linalg.norm(O.codec_roundtrip(f, rate, mid=True) - f)
+    assert e1 < 0.9 * e0
