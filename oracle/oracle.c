@@ -766,6 +766,320 @@ int orc_decode_ints_stop(const uint64_t* in, long budget, uint32_t* u64, int32_t
     return 0;
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* The fixed-rate method for FP64 values (the precision of the paper's      */
+/* experiments, Sec. VI). Same blocks, lifting steps, sequency order, group */
+/* testing and layout as the FP32 format above, with 64-bit integers:       */
+/*  - e(x) from frexp, clamped below at -1022; header: a 1 bit and the      */
+/*    11-bit field emax + 1023, least significant bit first (12 bits); an   */
+/*    all-zero block is one 0 bit;                                          */
+/*  - q = trunc(x * 2^(62 - emax)) as int64 (so |q| < 2^62, the same two    */
+/*    bits of headroom as 2^30 in int32), the lifting on int64;             */
+/*  - negabinary u = (q + 0xAAAA...AA) ^ 0xAAAA...AA on uint64;             */
+/*  - bit planes 63..0 with budget 64*rate - 12 bits; rates 1..68 bits per */
+/*    value (the worst case, 12 + 64*64 + 64 + 64 bits, fits rate 67);    */
+/*  - decoding: x = (double)q * 2^(emax - 62).                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t emax;        /* INT32_MIN for an all-zero block */
+    int64_t q[64];       /* natural order */
+    int64_t t[64];       /* after the forward transform, natural order */
+    uint64_t u[64];      /* sequency order, negabinary */
+    uint64_t plane[64];  /* plane[p]: bit i = bit p of u[i] */
+    int32_t bits_used;
+} orc_stages64;
+
+/* Lifting on int64 values, checked with 128-bit intermediates: every
+ * intermediate must stay inside int64 (reported, never wrapped). */
+static _Thread_local int g_range64 = 0;
+static __int128 chk64(__int128 v)
+{
+    if (v > (__int128)INT64_MAX || v < (__int128)INT64_MIN) g_range64 = 1;
+    return v;
+}
+static __int128 asr1_128(__int128 v) { return v >> 1; }
+
+static void fwd4_64(__int128* a, __int128* b, __int128* c, __int128* d)
+{
+    __int128 A = *a, B = *b, C = *c, D = *d;
+    A = chk64(asr1_128(chk64(A + D))); D = chk64(D - A);
+    C = chk64(asr1_128(chk64(C + B))); B = chk64(B - C);
+    A = chk64(asr1_128(chk64(A + C))); C = chk64(C - A);
+    D = chk64(asr1_128(chk64(D + B))); B = chk64(B - D);
+    D = chk64(D + asr1_128(B));        B = chk64(B - asr1_128(D));
+    *a = A; *b = B; *c = C; *d = D;
+}
+
+static void inv4_64(__int128* a, __int128* b, __int128* c, __int128* d)
+{
+    __int128 A = *a, B = *b, C = *c, D = *d;
+    B = chk64(B + asr1_128(D)); D = chk64(D - asr1_128(B));
+    B = chk64(B + D);           D = chk64(2 * D - B);
+    C = chk64(C + A);           A = chk64(2 * A - C);
+    B = chk64(B + C);           C = chk64(2 * C - B);
+    D = chk64(D + A);           A = chk64(2 * A - D);
+    *a = A; *b = B; *c = C; *d = D;
+}
+
+static void lift_axis64(__int128* v, int axis, int inverse)
+{
+    int stride = axis == 0 ? 1 : (axis == 1 ? 4 : 16);
+    for (int o1 = 0; o1 < 4; ++o1)
+        for (int o2 = 0; o2 < 4; ++o2) {
+            int base;
+            if (axis == 0) base = 4 * o1 + 16 * o2;
+            else if (axis == 1) base = o1 + 16 * o2;
+            else base = o1 + 4 * o2;
+            __int128* a = &v[base];
+            __int128* b = &v[base + stride];
+            __int128* c = &v[base + 2 * stride];
+            __int128* d = &v[base + 3 * stride];
+            if (inverse) inv4_64(a, b, c, d); else fwd4_64(a, b, c, d);
+        }
+}
+
+int orc64_fwd_xform(const int64_t* in64, int64_t* out64)
+{
+    __int128 v[64];
+    g_range64 = 0;
+    for (int i = 0; i < 64; ++i) v[i] = in64[i];
+    lift_axis64(v, 0, 0); lift_axis64(v, 1, 0); lift_axis64(v, 2, 0);
+    for (int i = 0; i < 64; ++i) out64[i] = (int64_t)v[i];
+    return g_range64 ? -2 : 0;
+}
+
+int orc64_inv_xform(const int64_t* in64, int64_t* out64)
+{
+    __int128 v[64];
+    g_range64 = 0;
+    for (int i = 0; i < 64; ++i) v[i] = in64[i];
+    lift_axis64(v, 2, 1); lift_axis64(v, 1, 1); lift_axis64(v, 0, 1);
+    for (int i = 0; i < 64; ++i) out64[i] = (int64_t)v[i];
+    return g_range64 ? -2 : 0;
+}
+
+static int exponent64_of(double x)
+{
+    int e;
+    (void)frexp(x, &e);
+    return e < -1022 ? -1022 : e;
+}
+
+/* Group-testing bit-plane coder on 64 sequency-ordered 64-bit negabinary
+ * words: the FP32 coder's rules with planes 63..0. */
+static long code_planes64(const uint64_t* u, long budget, bitw* s, uint64_t* planes_out)
+{
+    long used = 0;
+    int n = 0;
+    for (int p = 63; p >= 0; --p) {
+        uint64_t X = 0;
+        for (int i = 0; i < 64; ++i) X |= ((u[i] >> p) & 1u) << i;
+        if (planes_out) planes_out[p] = X;
+        if (budget <= 0) continue;
+        for (int i = 0; i < n && budget > 0; ++i) { put1(s, (int)((X >> i) & 1u)); budget--; used++; }
+        while (n < 64 && budget > 0) {
+            int g = (X >> n) != 0;
+            put1(s, g); budget--; used++;
+            if (!g) break;
+            for (;;) {
+                if (n == 63) { n = 64; break; }
+                if (budget <= 0) break;
+                int b = (int)((X >> n) & 1u);
+                put1(s, b); budget--; used++;
+                n++;
+                if (b) break;
+            }
+        }
+    }
+    return used;
+}
+
+static void decode_planes64(uint64_t* u, long budget, bitr* s, uint64_t* planes_out)
+{
+    int n = 0;
+    for (int i = 0; i < 64; ++i) u[i] = 0;
+    for (int p = 63; p >= 0; --p) {
+        uint64_t X = 0;
+        if (budget > 0) {
+            for (int i = 0; i < n && budget > 0; ++i) { X |= (uint64_t)get1(s) << i; budget--; }
+            while (n < 64 && budget > 0) {
+                int g = get1(s); budget--;
+                if (!g) break;
+                for (;;) {
+                    if (n == 63) { X |= (uint64_t)1 << 63; n = 64; break; }
+                    if (budget <= 0) break;
+                    int b = get1(s); budget--;
+                    if (b) { X |= (uint64_t)1 << n; n++; break; }
+                    n++;
+                }
+            }
+        }
+        if (planes_out) planes_out[p] = X;
+        for (int i = 0; i < 64; ++i) u[i] |= ((X >> i) & 1u) << p;
+    }
+}
+
+#define NB64 0xAAAAAAAAAAAAAAAAull
+
+int orc64_encode_block(const double* in64, int rate, uint64_t* out, orc_stages64* st)
+{
+    if (rate < 1 || rate > 68) return -1;
+    build_perm();
+    memset(out, 0, (size_t)rate * sizeof(uint64_t));
+    orc_stages64 local;
+    if (!st) st = &local;
+    memset(st, 0, sizeof(*st));
+    int nonzero = 0, emax = -100000;
+    for (int i = 0; i < 64; ++i)
+        if (in64[i] != 0.0) {
+            nonzero = 1;
+            int e = exponent64_of(in64[i]);
+            if (e > emax) emax = e;
+        }
+    bitw s = {out, 0};
+    if (!nonzero) {
+        st->emax = INT32_MIN;
+        put1(&s, 0);
+        st->bits_used = 1;
+        return 0;
+    }
+    st->emax = emax;
+    put1(&s, 1);
+    int biased = emax + 1023;
+    for (int b = 0; b < 11; ++b) put1(&s, (biased >> b) & 1);
+    for (int i = 0; i < 64; ++i) st->q[i] = (int64_t)ldexp(in64[i], 62 - emax); /* C conversion truncates */
+    int rc = orc64_fwd_xform(st->q, st->t);
+    for (int k = 0; k < 64; ++k) st->u[k] = ((uint64_t)st->t[g_perm[k]] + NB64) ^ NB64;
+    long used = code_planes64(st->u, 64L * rate - 12, &s, st->plane);
+    st->bits_used = (int32_t)(12 + used);
+    return rc;
+}
+
+int orc64_decode_block(const uint64_t* in, int rate, double* out64, orc_stages64* st)
+{
+    if (rate < 1 || rate > 68) return -1;
+    build_perm();
+    orc_stages64 local;
+    if (!st) st = &local;
+    memset(st, 0, sizeof(*st));
+    bitr s = {in, 0};
+    if (!get1(&s)) {
+        st->emax = INT32_MIN;
+        for (int i = 0; i < 64; ++i) out64[i] = 0.0;
+        return 0;
+    }
+    int biased = 0;
+    for (int b = 0; b < 11; ++b) biased |= get1(&s) << b;
+    int emax = biased - 1023;
+    st->emax = emax;
+    decode_planes64(st->u, 64L * rate - 12, &s, st->plane);
+    for (int k = 0; k < 64; ++k) st->t[g_perm[k]] = (int64_t)((st->u[k] ^ NB64) - NB64);
+    int rc = orc64_inv_xform(st->t, st->q);
+    for (int i = 0; i < 64; ++i) out64[i] = ldexp((double)st->q[i], emax - 62);
+    return rc;
+}
+
+long orc64_code_ints(const uint64_t* u64, long budget, uint64_t* out)
+{
+    bitw s = {out, 0};
+    return code_planes64(u64, budget, &s, NULL);
+}
+
+int orc64_decode_ints(const uint64_t* in, long budget, uint64_t* u64)
+{
+    bitr s = {in, 0};
+    decode_planes64(u64, budget, &s, NULL);
+    return 0;
+}
+
+static void gather_block64(const double* f, long nx, long ny, long bx, long by, long bz, double* blk)
+{
+    for (int l = 0; l < 4; ++l)
+        for (int j = 0; j < 4; ++j)
+            for (int i = 0; i < 4; ++i)
+                blk[i + 4 * j + 16 * l] = f[IDX(4 * bx + i, 4 * by + j, 4 * bz + l, nx, ny)];
+}
+
+static void scatter_block64(double* f, long nx, long ny, long bx, long by, long bz, const double* blk)
+{
+    for (int l = 0; l < 4; ++l)
+        for (int j = 0; j < 4; ++j)
+            for (int i = 0; i < 4; ++i)
+                f[IDX(4 * bx + i, 4 * by + j, 4 * bz + l, nx, ny)] = blk[i + 4 * j + 16 * l];
+}
+
+int orc64_codec_encode(const double* f, long nx, long ny, long nz, int rate, uint64_t* out)
+{
+    if (nx % 4 || ny % 4 || nz % 4 || rate < 1 || rate > 68) return -1;
+    long bxn = nx / 4, byn = ny / 4, bzn = nz / 4;
+    int bad = 0;
+    build_perm();
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long bz = 0; bz < bzn; ++bz)
+        for (long by = 0; by < byn; ++by)
+            for (long bx = 0; bx < bxn; ++bx) {
+                double blk[64];
+                gather_block64(f, nx, ny, bx, by, bz, blk);
+                size_t b = (size_t)bx + (size_t)bxn * ((size_t)by + (size_t)byn * (size_t)bz);
+                orc_stages64 st;
+                if (orc64_encode_block(blk, rate, out + b * (size_t)rate, &st) != 0) bad = 1;
+            }
+    return bad ? -2 : 0;
+}
+
+int orc64_codec_decode(const uint64_t* in, long nx, long ny, long nz, int rate, double* f)
+{
+    if (nx % 4 || ny % 4 || nz % 4 || rate < 1 || rate > 68) return -1;
+    long bxn = nx / 4, byn = ny / 4, bzn = nz / 4;
+    int bad = 0;
+    build_perm();
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long bz = 0; bz < bzn; ++bz)
+        for (long by = 0; by < byn; ++by)
+            for (long bx = 0; bx < bxn; ++bx) {
+                double blk[64];
+                size_t b = (size_t)bx + (size_t)bxn * ((size_t)by + (size_t)byn * (size_t)bz);
+                orc_stages64 st;
+                if (orc64_decode_block(in + b * (size_t)rate, rate, blk, &st) != 0) bad = 1;
+                scatter_block64(f, nx, ny, bx, by, bz, blk);
+            }
+    return bad ? -2 : 0;
+}
+
+/* Q = decode(encode(.)) in place on an FP64 field with the FP64 format. */
+int orc64_codec_roundtrip(double* f, long nx, long ny, long nz, int rate)
+{
+    size_t nw = orc_codec_words(nx, ny, nz, rate);
+    uint64_t* w = (uint64_t*)calloc(nw ? nw : 1, sizeof(uint64_t));
+    if (!w) return -1;
+    int rc = orc64_codec_encode(f, nx, ny, nz, rate, w);
+    if (rc == 0) rc = orc64_codec_decode(w, nx, ny, nz, rate, f);
+    free(w);
+    return rc;
+}
+
+/* The compressed schedule's state in FP64 with the FP64 format (the
+ * paper's setting): as orc_replay_wave_f64, Q being the FP64 codec. */
+int orc64_replay_wave(double* p, double* pm, double* w, long nx, long ny, long nz, long steps, long k,
+                      const double* src, long src_index, int rate_p, int rate_pm, int rate_w)
+{
+    if (k < 1) return -1;
+    int rc = 0;
+    if (rate_w > 0 && (rc = orc64_codec_roundtrip(w, nx, ny, nz, rate_w))) return rc;
+    if (rate_p > 0 && (rc = orc64_codec_roundtrip(p, nx, ny, nz, rate_p))) return rc;
+    if (rate_pm > 0 && (rc = orc64_codec_roundtrip(pm, nx, ny, nz, rate_pm))) return rc;
+    for (long done = 0; done < steps;) {
+        long kk = steps - done < k ? steps - done : k;
+        if ((rc = orc_wave25_f64(p, pm, w, nx, ny, nz, kk, src ? src + done : NULL, src_index))) return rc;
+        if (rate_p > 0 && (rc = orc64_codec_roundtrip(p, nx, ny, nz, rate_p))) return rc;
+        if (rate_pm > 0 && (rc = orc64_codec_roundtrip(pm, nx, ny, nz, rate_pm))) return rc;
+        done += kk;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Misfit gradient of the wave propagator by the discrete adjoint.          */
 /*                                                                          */
