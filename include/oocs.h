@@ -482,15 +482,14 @@ int oocs_run(oocs_plan* plan, void* const* h_store, int64_t steps, const float* 
 
 /* ------------------------------------------------------------------------
  * Batched in-core heat domains. Many independent domains of uneven sizes
- * advance together. A run can be one persistent kernel launch (one node
- * of a HIP graph; switched off in this version, see
- * oocs_batch_set_persistent): its workgroups take items (domain, tile, group of k
+ * advance together. By default a run is one persistent kernel launch (one
+ * node of a HIP graph): its workgroups take items (domain, tile, group of k
  * steps) in order from a device queue, and an item of group g of a domain
  * starts once every tile of group g-1 of that domain has finished (a
  * per-domain count of finished tiles, raised after a device-scope release).
  * Waits are bounded: a wait that exceeds its poll limit sets a status word
  * and every workgroup leaves, so the kernel always ends; oocs_batch_check
- * reports it. The default mode replays one launch per group (every
+ * reports it. The alternative mode replays one launch per group (every
  * domain, k steps) as a graph. k > 1 is temporal blocking: a workgroup
  * advances its tile k steps in one pass over z, recomputing a k-cell halo,
  * so each cell crosses HBM once per k steps. The tile shape is chosen per
@@ -537,10 +536,7 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
  * whether a wait gave up. */
 int oocs_batch_run(oocs_batch* b, int64_t steps, void* stream);
 
-/* 1: runs are persistent launches; 0 (default): one launch per group.
- * The persistent launch is switched off in this version (its first GPU
- * test hung in a dependency wait, cause not yet found): 1 returns
- * OOCS_E_STATE. */
+/* 1 (default): runs are persistent launches; 0: one launch per group. */
 int oocs_batch_set_persistent(oocs_batch* b, int on);
 
 /* Poll limit of the persistent kernel's waits (default 2^21 polls, each

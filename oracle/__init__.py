@@ -62,6 +62,17 @@ def lib() -> C.CDLL:
         L.orc_code_ints.restype = C.c_long
         L.orc_decode_ints.argtypes = [P, l, P]
         L.orc_decode_ints_stop.argtypes = [P, l, P, P]
+        L.orc64_fwd_xform.argtypes = [P, P]
+        L.orc64_inv_xform.argtypes = [P, P]
+        L.orc64_encode_block.argtypes = [P, C.c_int, P, P]
+        L.orc64_decode_block.argtypes = [P, C.c_int, P, P]
+        L.orc64_code_ints.argtypes = [P, l, P]
+        L.orc64_code_ints.restype = C.c_long
+        L.orc64_decode_ints.argtypes = [P, l, P]
+        L.orc64_codec_encode.argtypes = [P, l, l, l, C.c_int, P]
+        L.orc64_codec_decode.argtypes = [P, l, l, l, C.c_int, P]
+        L.orc64_codec_roundtrip.argtypes = [P, l, l, l, C.c_int]
+        L.orc64_replay_wave.argtypes = [P, P, P, l, l, l, l, l, P, l, C.c_int, C.c_int, C.c_int]
         L.orc_wave_forward_states_f64.argtypes = [P, l, l, l, l, P, l, P, l, P, P]
         L.orc_wave_adjoint_f64.argtypes = [P, l, l, l, l, P, l, P, P, P, l, P]
         L.orc_wave_misfit_grad_f64.argtypes = [P, l, l, l, l, P, l, P, l, P, P, P]
@@ -411,3 +422,113 @@ def errors(a: np.ndarray, ref: np.ndarray, per_plane: int = 100, seed: int = 0) 
         "sampled_points": int(idx.size),
         "sampled_used": int(pw.size),
     }
+
+
+# --------------------------------------------------------------------------
+# The FP64 format (oracle.c: "The fixed-rate method for FP64 values")
+# --------------------------------------------------------------------------
+
+class Stages64(C.Structure):
+    _fields_ = [
+        ("emax", C.c_int32),
+        ("q", C.c_int64 * 64),
+        ("t", C.c_int64 * 64),
+        ("u", C.c_uint64 * 64),
+        ("plane", C.c_uint64 * 64),
+        ("bits_used", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "emax": int(self.emax),
+            "q": np.array(self.q[:], dtype=np.int64),
+            "t": np.array(self.t[:], dtype=np.int64),
+            "u": np.array(self.u[:], dtype=np.uint64),
+            "plane": np.array(self.plane[:], dtype=np.uint64),
+            "bits_used": int(self.bits_used),
+        }
+
+
+MAX_RATE64 = 68
+
+
+def fwd_xform64(q64: np.ndarray) -> np.ndarray:
+    q = np.ascontiguousarray(q64, dtype=np.int64).reshape(64)
+    out = np.zeros(64, dtype=np.int64)
+    _check(lib().orc64_fwd_xform(_ptr(q), _ptr(out)), "fwd_xform64")
+    return out
+
+
+def inv_xform64(t64: np.ndarray) -> np.ndarray:
+    t = np.ascontiguousarray(t64, dtype=np.int64).reshape(64)
+    out = np.zeros(64, dtype=np.int64)
+    _check(lib().orc64_inv_xform(_ptr(t), _ptr(out)), "inv_xform64")
+    return out
+
+
+def encode_block64(vals64, rate: int):
+    v = np.ascontiguousarray(vals64, dtype=np.float64).reshape(64)
+    out = np.zeros(rate, dtype=np.uint64)
+    st = Stages64()
+    _check(lib().orc64_encode_block(_ptr(v), int(rate), _ptr(out), C.byref(st)), "encode_block64")
+    return out, st.as_dict()
+
+
+def decode_block64(words, rate: int):
+    w = np.ascontiguousarray(words, dtype=np.uint64).reshape(rate)
+    out = np.zeros(64, dtype=np.float64)
+    st = Stages64()
+    _check(lib().orc64_decode_block(_ptr(w), int(rate), _ptr(out), C.byref(st)), "decode_block64")
+    return out, st.as_dict()
+
+
+def code_ints64(u64, budget: int):
+    u = np.ascontiguousarray(u64, dtype=np.uint64).reshape(64)
+    out = np.zeros(max(1, (budget + 63) // 64), dtype=np.uint64)
+    used = int(lib().orc64_code_ints(_ptr(u), int(budget), _ptr(out)))
+    return out, used
+
+
+def decode_ints64(words, budget: int) -> np.ndarray:
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size * 64 < budget:
+        raise ValueError("stream shorter than budget")
+    out = np.zeros(64, dtype=np.uint64)
+    _check(lib().orc64_decode_ints(_ptr(w), int(budget), _ptr(out)), "decode_ints64")
+    return out
+
+
+def codec64_encode(f: np.ndarray, rate: int) -> np.ndarray:
+    """Whole FP64 field (nz, ny, nx), dims multiples of 4 -> uint64 words."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nx, ny, nz = _dims(f)
+    out = np.zeros(codec_words(nx, ny, nz, rate), dtype=np.uint64)
+    _check(lib().orc64_codec_encode(_ptr(f), nx, ny, nz, int(rate), _ptr(out)), "codec64_encode")
+    return out
+
+
+def codec64_decode(words: np.ndarray, shape, rate: int) -> np.ndarray:
+    nz, ny, nx = shape
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size != codec_words(nx, ny, nz, rate):
+        raise ValueError("word count does not match shape and rate")
+    out = np.zeros((nz, ny, nx), dtype=np.float64)
+    _check(lib().orc64_codec_decode(_ptr(w), nx, ny, nz, int(rate), _ptr(out)), "codec64_decode")
+    return out
+
+
+def codec64_roundtrip(f: np.ndarray, rate: int) -> np.ndarray:
+    g = np.ascontiguousarray(f, dtype=np.float64).copy()
+    _check(lib().orc64_codec_roundtrip(_ptr(g), *_dims(g), int(rate)), "codec64_roundtrip")
+    return g
+
+
+def replay_wave64(p0, pm0, w0, steps, k, src=None, rate_p=0, rate_pm=0, rate_w=0):
+    """FP64 stencil with the FP64 format as Q (the paper's precision)."""
+    p = np.ascontiguousarray(p0, dtype=np.float64).copy()
+    pm = np.ascontiguousarray(pm0, dtype=np.float64).copy()
+    w = np.ascontiguousarray(w0, dtype=np.float64).copy()
+    a, idx, ap = _src_args(src, np.float64, steps)
+    _check(lib().orc64_replay_wave(_ptr(p), _ptr(pm), _ptr(w), *_dims(p), int(steps), int(k), ap, idx,
+                                   int(rate_p), int(rate_pm), int(rate_w)), "replay_wave64")
+    return p, pm, w

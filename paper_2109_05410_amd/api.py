@@ -467,10 +467,10 @@ class WaveMisfit(torch.autograd.Function):
 # ---------------------------------------------------------------------------
 
 class HeatBatch:
-    """Independent heat domains advanced together: one launch per k steps
-    for all domains, all launches replayed as one graph (the persistent
-    launch, one kernel taking items of every domain, tile and group from a
-    device queue, is switched off in this version). `fields` are
+    """Independent heat domains advanced together: by default one persistent
+    kernel per run (items of every domain, tile and group of k steps from a
+    device queue), replayed as a graph; persistent=False: one launch per k
+    steps for all domains, all launches replayed as one graph. `fields` are
     (nz, ny, nx) float32 device tensors, updated in place by run(). depth:
     0 = temporal-blocking depth chosen by the autotuner, or 1, 2, 4."""
 

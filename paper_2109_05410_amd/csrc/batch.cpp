@@ -35,10 +35,7 @@ struct oocs_batch {
     int grid[2] = {0, 0};                  // persistent grid: [0] blocked tiles, [1] depth-1 tiles
     int depth = 1;
     float alpha = 0.1f;
-    // The persistent launch is off by default: its first GPU test run hung
-    // (a bounded wait did not end within minutes) and the cause is not yet
-    // found; oocs_batch_set_persistent refuses to turn it on.
-    bool persistent = false;
+    bool persistent = true;
     int64_t spin_limit = (int64_t)1 << 21;
     bool force_wait = false;
     std::map<int64_t, hipGraphExec_t> graphs;  // by step count
@@ -381,7 +378,6 @@ hipError_t add_persistent_nodes(const oocs_batch* b, int64_t steps, hipGraph_t g
 int oocs_batch_set_persistent(oocs_batch* b, int on)
 {
     if (!b) return fail(OOCS_E_ARG, "bad argument");
-    if (on) return fail(OOCS_E_STATE, "the persistent batched launch is switched off (its waits hung on the GPU)");
     if (b->persistent != (on != 0)) {
         for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
         b->graphs.clear();

@@ -589,15 +589,36 @@ __device__ inline BatchItem batch_item(const BatchPersistArgs& a, uint32_t i)
     return it;
 }
 
-// Thread 0: wait until *ctr >= need. Gives up (false) when another wait has
+// Queue accesses of the persistent kernel. Only lane 0 of wave 0 touches
+// the counters, but the whole of wave 0 runs the grab and the waits, with
+// every value made uniform by readfirstlane, so no loop sits inside a
+// region that only some lanes of a wave enter. (With the poll loop inside
+// `if (threadIdx.x == 0)`, the compiler kept the other lanes in an inner
+// loop around the barrier that re-read the old item and never left it:
+// the launch never ended.)
+__device__ inline uint32_t lane0_load(uint32_t* p)
+{
+    uint32_t v = 0;
+    if ((threadIdx.x & 63) == 0) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ inline uint32_t lane0_fetch_add(uint32_t* p, uint32_t v)
+{
+    uint32_t old = 0;
+    if ((threadIdx.x & 63) == 0) old = __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)old);
+}
+
+// Wave 0: wait until *ctr >= need. Gives up (false) when another wait has
 // given up (status set) or after spin_limit polls, then setting the status.
 __device__ inline bool batch_wait(uint32_t* ctr, uint32_t need, uint32_t* status, int64_t spin_limit, bool force)
 {
     for (int64_t spins = 0;; ++spins) {
-        if (!force && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
-        if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+        if (!force && lane0_load(ctr) >= need) return true;
+        if (lane0_load(status) != 0u) return false;
         if (spins >= spin_limit) {
-            __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
         __builtin_amdgcn_s_sleep(2);
@@ -652,16 +673,16 @@ __global__ void __launch_bounds__(kBlockThreads, TB ? 7 : 8) batch_persistent_ke
     const uint32_t total = (uint32_t)a.groups * (uint32_t)a.total + (TB ? 0u : (uint32_t)a.copy_items);
     float* lds = reinterpret_cast<float*>(dyn_lds);
     for (;;) {
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < 64) {  // wave 0, all lanes (a wave-uniform branch)
             uint32_t item = 0xffffffffu;
-            if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
-                const uint32_t i = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane0_load(status) == 0u) {
+                const uint32_t i = lane0_fetch_add(head, 1u);
                 if (i < total) {
                     const BatchItem it = batch_item(a, i);
                     if (batch_wait(done + it.d, it.need, status, a.spin_limit, a.force_wait != 0)) item = i;
                 }
             }
-            s_item = item;
+            if (threadIdx.x == 0) s_item = item;
         }
         __syncthreads();
         // the same for every lane: kept in scalar registers
@@ -686,7 +707,7 @@ __global__ void __launch_bounds__(kBlockThreads, TB ? 7 : 8) batch_persistent_ke
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (threadIdx.x == 0 && (TB || it.g >= 0))
+        if (threadIdx.x == 0 && (TB || it.g >= 0))  // a single atomic, no loop: safe for one lane
             __hip_atomic_fetch_add(done + it.d, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (threadIdx.x == 0) {

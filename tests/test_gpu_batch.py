@@ -19,8 +19,6 @@ from paper_2109_05410_amd import api, inputs
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
-PERSISTENT_OFF = ("the persistent batched launch is switched off: its first GPU run hung in a dependency wait "
-                  "(test_forced_depth_matches_oracle[2-7]) and the cause is not found yet")
 
 
 @pytest.mark.parametrize("steps", [7, 8, 1])
@@ -84,13 +82,18 @@ def test_full_size_batched_workload(tmp_path):
     sides = inputs.batch_sides()
     fields = [torch.from_numpy(inputs.heat_uniform((s, s, s), seed=3 + j)).to(DEV) for j, s in enumerate(sides)]
     ref = [f.clone() for f in fields]
+    ref2 = [f.clone() for f in fields]
     b = api.HeatBatch(fields, tune=True, tune_cache=str(tmp_path / "tune.json"))
-    b.run(200)
+    b.run(200, check=True)
     b2 = api.HeatBatch(ref, tune=False, tune_cache=str(tmp_path / "tune.json"))
     b2.run_per_domain(200)
+    b3 = api.HeatBatch(ref2, tune=False, tune_cache=str(tmp_path / "tune.json"))
+    b3.set_persistent(False)
+    b3.run(200)
     torch.cuda.synchronize()
-    for f, g in zip(fields, ref):
+    for f, g, h in zip(fields, ref, ref2):
         assert torch.equal(f, g)
+        assert torch.equal(f, h)
     j = int(np.argmin(sides))
     s = int(sides[j])
     want = O.heat7_f32(inputs.heat_uniform((s, s, s), seed=3 + j), 0.1, 200)
@@ -116,7 +119,7 @@ def test_tuning_leaves_the_states_unchanged(tmp_path):
         assert np.array_equal(f.cpu().numpy(), O.heat7_f32(u, 0.1, 6))
 
 
-@pytest.mark.parametrize("persistent", [pytest.param(True, marks=pytest.mark.skip(reason=PERSISTENT_OFF)), False])
+@pytest.mark.parametrize("persistent", [True, False])
 @pytest.mark.parametrize("depth,steps", [(4, 8), (4, 12), (4, 6), (2, 5), (1, 3), (1, 4)])
 def test_persistent_and_launch_modes_match_oracle(depth, steps, persistent):
     """Both modes, with groups only at the batch depth (even and odd counts)
@@ -148,13 +151,11 @@ def test_every_depth4_tile_matches_oracle(cfg, tmp_path):
     b = api.HeatBatch(fields, alpha=0.1, tune=False, tune_cache=str(cache), depth=4)
     tiles = {b.tile(i) for i in range(len(shapes))}
     assert tiles == {(64, 16, {9: 64, 10: 32, 11: 128}[cfg], 4)}
-    b.run(9)
-    torch.cuda.synchronize()
+    b.run(9, check=True)
     for u, f in zip(u0, fields):
         assert np.array_equal(f.cpu().numpy(), O.heat7_f32(u, 0.1, 9))
 
 
-@pytest.mark.skip(reason=PERSISTENT_OFF)
 def test_persistent_wait_gives_up_and_is_reported():
     """A wait that is never satisfied (test hook) gives up after its poll
     limit; every workgroup leaves, the kernel ends, check() reports it, and
@@ -175,11 +176,3 @@ def test_persistent_wait_gives_up_and_is_reported():
     b.run(8, check=True)
     for u, f in zip(u0, fields):
         assert np.array_equal(f.cpu().numpy(), O.heat7_f32(u, 0.1, 8))
-
-
-def test_persistent_mode_is_refused_while_switched_off():
-    fields = [torch.from_numpy(inputs.heat_uniform((8, 8, 8), seed=1)).to(DEV)]
-    b = api.HeatBatch(fields, tune=False, depth=1)
-    with pytest.raises(L.OocsError) as e:
-        b.set_persistent(True)
-    assert e.value.code == L.OOCS_E_STATE
