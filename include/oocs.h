@@ -481,6 +481,44 @@ int oocs_link_probe(void* d_a, void* d_b, void* h_in, void* h_out, size_t bytes,
 int oocs_run(oocs_plan* plan, void* const* h_store, int64_t steps, const float* h_src, oocs_stats* st);
 
 /* ------------------------------------------------------------------------
+ * FP64 (the precision of the paper's experiments, Sec. VI). The same
+ * fixed-rate 4^3 block method with 64-bit integers: exponent from frexp
+ * clamped at -1022, header 1 bit + (emax + 1023) in 11 bits, q =
+ * trunc(x * 2^(62 - emax)) as int64, the same lifting, sequency order and
+ * group-test coding over bit planes 63..0, 64 * rate - 12 bits of budget;
+ * block b at word b * rate. Rates 1..68 bits per value.
+ * ------------------------------------------------------------------------ */
+#define OOCS_MAX_RATE64 68
+
+/* Bytes of an FP64 field's stream; 0 on bad dims or rate. */
+size_t oocs_codec64_bytes(int64_t nx, int64_t ny, int64_t nz, int rate);
+
+/* Encode / decode an FP64 field (x fastest, leading dimensions ld_y >= nx,
+ * ld_z >= ld_y * ny in elements; 8-byte aligned buffers). Stream-ordered, no
+ * allocation. Errors: OOCS_E_ARG, OOCS_E_ALIGN, OOCS_E_RATE, OOCS_E_SIZE,
+ * OOCS_E_HIP. */
+int oocs_codec64_encode(const double* d_in, int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t ld_z, int rate,
+                        uint64_t* d_out, size_t out_bytes, void* stream);
+int oocs_codec64_decode(const uint64_t* d_in, size_t in_bytes, int64_t nx, int64_t ny, int64_t nz, int rate,
+                        double* d_out, int64_t ld_y, int64_t ld_z, void* stream);
+
+/* Per-block stages for parity checks (nblocks blocks of 64 values in
+ * natural in-block order): as oocs_codec_encode_stages / _decode_stages
+ * with 64-bit integers and 64 plane words per block. */
+int oocs_codec64_encode_stages(const double* d_blocks, int64_t nblocks, int rate, int32_t* d_emax, int64_t* d_q,
+                               int64_t* d_t, uint64_t* d_u, uint64_t* d_planes, uint64_t* d_words, int32_t* d_bits,
+                               void* stream);
+int oocs_codec64_decode_stages(const uint64_t* d_words, int64_t nblocks, int rate, int32_t* d_emax, uint64_t* d_planes,
+                               uint64_t* d_u, int64_t* d_q, double* d_out, void* stream);
+
+/* k FP64 leapfrog steps of the 25-point wave in place on (d_pm, d_p) =
+ * (p(n-1), p(n)), d_w read-only; the FP32 step's formula and operation
+ * order in double (the paper's precision). h_src: k amplitudes added at
+ * the source cell (host memory), or NULL. */
+int oocs_wave25_step_k_f64(double* d_p, double* d_pm, const double* d_w, int64_t nx, int64_t ny, int64_t nz,
+                           int64_t k, const double* h_src, int64_t src_x, int64_t src_y, int64_t src_z, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched in-core heat domains. Many independent domains of uneven sizes
  * advance together. By default a run is one persistent kernel launch (one
  * node of a HIP graph): its workgroups take items (domain, tile, group of k

@@ -25,6 +25,7 @@ OOCS_HEAT7 = 1
 OOCS_WAVE25 = 2
 OOCS_MAX_FIELDS = 3
 OOCS_MAX_RATE = 34
+OOCS_MAX_RATE64 = 68
 OOCS_NOALLOC_MAX_CELLS = 1 << 24
 OOCS_PLAN_BLOCK_RESTART = 1
 OOCS_PLAN_KERNEL_TRANSFERS = 2
@@ -142,6 +143,12 @@ _SIGS = {
     "oocs_plan_sdma_available": (C.c_int, [_P]),
     "oocs_link_probe": (C.c_int, [_P, _P, _P, _P, C.c_size_t, C.c_size_t, C.c_int, C.c_int,
                                   C.POINTER(C.c_double)]),
+    "oocs_codec64_bytes": (C.c_size_t, [_I64, _I64, _I64, C.c_int]),
+    "oocs_codec64_encode": (C.c_int, [_P, _I64, _I64, _I64, _I64, _I64, C.c_int, _P, C.c_size_t, _P]),
+    "oocs_codec64_decode": (C.c_int, [_P, C.c_size_t, _I64, _I64, _I64, C.c_int, _P, _I64, _I64, _P]),
+    "oocs_codec64_encode_stages": (C.c_int, [_P, _I64, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "oocs_codec64_decode_stages": (C.c_int, [_P, _I64, C.c_int, _P, _P, _P, _P, _P, _P]),
+    "oocs_wave25_step_k_f64": (C.c_int, [_P, _P, _P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P]),
     "oocs_batch_table_bytes": (C.c_size_t, [C.c_int]),
     "oocs_batch_create": (C.c_int, [C.POINTER(Domain), C.c_int, C.c_float, _P, C.c_size_t, C.c_char_p, C.c_int,
                                     C.c_int, _P, C.POINTER(_P)]),

@@ -107,6 +107,125 @@ def codec_decode_stages(words: torch.Tensor, rate: int, mid: bool = False) -> di
 
 
 # ---------------------------------------------------------------------------
+# FP64 format and FP64 wave step (the paper's precision)
+# ---------------------------------------------------------------------------
+
+def _field64(t: torch.Tensor, name: str):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 3:
+        raise ValueError(f"{name} must be a contiguous float64 (nz, ny, nx) device tensor")
+    nz, ny, nx = t.shape
+    return nx, ny, nz
+
+
+def codec64_encode(field: torch.Tensor, rate: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    nx, ny, nz = _field64(field, "field")
+    nb = int(L.lib().oocs_codec64_bytes(nx, ny, nz, rate))
+    if nb == 0:
+        L.check(L.OOCS_E_ALIGN if rate > 0 else L.OOCS_E_RATE)
+    if out is None:
+        out = torch.empty(nb // 8, dtype=torch.int64, device=field.device)
+    L.check(L.lib().oocs_codec64_encode(_dptr(field), nx, ny, nz, nx, nx * ny, rate, _dptr(out), out.numel() * 8,
+                                        _stream_ptr(stream)))
+    return out
+
+
+def codec64_decode(words: torch.Tensor, shape, rate: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    nz, ny, nx = shape
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float64, device=words.device)
+    _field64(out, "out")
+    L.check(L.lib().oocs_codec64_decode(_dptr(words), words.numel() * words.element_size(), nx, ny, nz, rate,
+                                        _dptr(out), nx, nx * ny, _stream_ptr(stream)))
+    return out
+
+
+def codec64_encode_stages(blocks: torch.Tensor, rate: int) -> dict:
+    """blocks: (N, 64) float64 device tensor, natural in-block order."""
+    n = blocks.shape[0]
+    dev = blocks.device
+    o = {
+        "emax": torch.empty(n, dtype=torch.int32, device=dev),
+        "q": torch.empty((n, 64), dtype=torch.int64, device=dev),
+        "t": torch.empty((n, 64), dtype=torch.int64, device=dev),
+        "u": torch.empty((n, 64), dtype=torch.int64, device=dev),
+        "plane": torch.empty((n, 64), dtype=torch.int64, device=dev),
+        "words": torch.empty((n, rate), dtype=torch.int64, device=dev),
+        "bits_used": torch.empty(n, dtype=torch.int32, device=dev),
+    }
+    L.check(L.lib().oocs_codec64_encode_stages(_dptr(blocks.contiguous()), n, rate, _dptr(o["emax"]), _dptr(o["q"]),
+                                               _dptr(o["t"]), _dptr(o["u"]), _dptr(o["plane"]), _dptr(o["words"]),
+                                               _dptr(o["bits_used"]), _stream_ptr()))
+    return o
+
+
+def codec64_decode_stages(words: torch.Tensor, rate: int) -> dict:
+    n = words.shape[0]
+    dev = words.device
+    o = {
+        "emax": torch.empty(n, dtype=torch.int32, device=dev),
+        "plane": torch.empty((n, 64), dtype=torch.int64, device=dev),
+        "u": torch.empty((n, 64), dtype=torch.int64, device=dev),
+        "q": torch.empty((n, 64), dtype=torch.int64, device=dev),
+        "out": torch.empty((n, 64), dtype=torch.float64, device=dev),
+    }
+    L.check(L.lib().oocs_codec64_decode_stages(_dptr(words.contiguous()), n, rate, _dptr(o["emax"]), _dptr(o["plane"]),
+                                               _dptr(o["u"]), _dptr(o["q"]), _dptr(o["out"]), _stream_ptr()))
+    return o
+
+
+def wave25_step_k_f64(p: torch.Tensor, pm: torch.Tensor, w: torch.Tensor, k: int, src=None, stream=None):
+    """k FP64 leapfrog steps in place on (pm, p) = (p(n-1), p(n)).
+    src = (amplitudes (k,), (x, y, z)) or None."""
+    nx, ny, nz = _field64(p, "p")
+    _field64(pm, "pm")
+    _field64(w, "w")
+    amps = None
+    sx = sy = sz = -1
+    if src is not None:
+        a, (sx, sy, sz) = src
+        amps = np.ascontiguousarray(a, dtype=np.float64)
+        if amps.size < k:
+            raise ValueError("need one source amplitude per step")
+    ap = amps.ctypes.data_as(C.c_void_p) if amps is not None else None
+    L.check(L.lib().oocs_wave25_step_k_f64(_dptr(p), _dptr(pm), _dptr(w), nx, ny, nz, k, ap, sx, sy, sz,
+                                           _stream_ptr(stream)))
+    return p, pm
+
+
+def codec64_roundtrip_(f: torch.Tensor, rate: int, scratch: torch.Tensor | None = None) -> torch.Tensor:
+    """f <- decode(encode(f)) in place with the FP64 format (on the device)."""
+    words = codec64_encode(f, rate, out=scratch)
+    codec64_decode(words, tuple(f.shape), rate, out=f)
+    return f
+
+
+def wave64_compressed_run(p, pm, w, steps: int, k: int, src=None, rate_p=0, rate_pm=0, rate_w=0,
+                          initial: bool = True):
+    """The compressed out-of-core schedule's state in FP64, on the GPU: the
+    stores start as decode(encode()) of the initial fields (initial=True;
+    the read-only w only then), and every k steps the read-write fields pass
+    through decode(encode()) with the FP64 format. The out-of-core
+    decomposition is exact, so this is the state a blocked FP64 run
+    reaches. Works in place on the device tensors (pm, p, w).
+    src = (amplitudes (steps,), (x, y, z)) or None."""
+    if initial:
+        for f, r in ((w, rate_w), (p, rate_p), (pm, rate_pm)):
+            if r:
+                codec64_roundtrip_(f, r)
+    done = 0
+    while done < steps:
+        n = min(k, steps - done)
+        s = None if src is None else (np.asarray(src[0])[done:done + n], src[1])
+        wave25_step_k_f64(p, pm, w, n, src=s)
+        if rate_p:
+            codec64_roundtrip_(p, rate_p)
+        if rate_pm:
+            codec64_roundtrip_(pm, rate_pm)
+        done += n
+    return p, pm
+
+
+# ---------------------------------------------------------------------------
 # In-core steps
 # ---------------------------------------------------------------------------
 

@@ -33,6 +33,7 @@ DEVICE = [
 SOURCES = {
     "kernels.hip": True,   # device code
     "noalloc.hip": True,   # device code (the library-held scratch array) and its entry point
+    "codec64.hip": True,   # device code: the FP64 format and the FP64 wave step
     "plan.cpp": False,     # host only
     "host.cpp": False,     # host only (HIP runtime API)
     "adjoint.cpp": False,  # host only (HIP runtime API)

@@ -1,0 +1,431 @@
+// codec64.hip -- the fixed-rate 4^3 block format for FP64 values, the
+// precision of the paper's experiments (Sec. VI): the method of the FP32
+// codec (Sec. IV; Lindstrom, IEEE TVCG 20(12), 2014) with 64-bit integers,
+// an 11-bit exponent field (12-bit header) and 64 bit planes.
+//
+// Mapping: one wavefront codes one block, one lane per value. The value's
+// lane k is its in-block index i + 4j + 16l; the lifting along x, y and z
+// exchanges the four values of a line with ds_bpermute (each lane runs its
+// line's 4-point step and keeps its own output); the block exponent is a
+// wave reduction; after the sequency reorder (another permute) lane s holds
+// the s-th coefficient, so the word of bit plane p is one ballot. The
+// group-test coding then runs on those plane words as wave-uniform (scalar)
+// code with a bit writer / reader over the block's words in LDS, and the
+// decoder hands every lane its digits back from the plane words.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "codec_dev.hpp"
+#include "internal.hpp"
+
+namespace oocs {
+namespace codec64 {
+
+constexpr uint64_t kNB = 0xAAAAAAAAAAAAAAAAull;
+constexpr int kMaxRate = 68;
+
+struct PermTables {
+    int fwd[64];   // fwd[s] = in-block index of the s-th coefficient (sequency order)
+    int rank[64];  // rank[k] = sequency position of in-block index k
+};
+
+constexpr PermTables make_perm()
+{
+    PermTables t{};
+    for (int k = 0; k < 64; ++k) {
+        t.rank[k] = codec::seq_rank(k);
+        t.fwd[codec::seq_rank(k)] = k;
+    }
+    return t;
+}
+__constant__ constexpr PermTables kPerm = make_perm();
+
+__device__ inline int lane_id() { return (int)(threadIdx.x & 63); }
+
+__device__ inline uint64_t shfl64(uint64_t v, int src)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)v);
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ inline uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// ---- lifting on int64 (wrap-around adds, arithmetic shifts) ------------------
+__device__ inline int64_t add_(int64_t a, int64_t b) { return (int64_t)((uint64_t)a + (uint64_t)b); }
+__device__ inline int64_t sub_(int64_t a, int64_t b) { return (int64_t)((uint64_t)a - (uint64_t)b); }
+
+__device__ inline void fwd_lift(int64_t& a, int64_t& b, int64_t& c, int64_t& d)
+{
+    a = add_(a, d) >> 1; d = sub_(d, a);
+    c = add_(c, b) >> 1; b = sub_(b, c);
+    a = add_(a, c) >> 1; c = sub_(c, a);
+    d = add_(d, b) >> 1; b = sub_(b, d);
+    d = add_(d, b >> 1); b = sub_(b, d >> 1);
+}
+
+__device__ inline void inv_lift(int64_t& a, int64_t& b, int64_t& c, int64_t& d)
+{
+    b = add_(b, d >> 1); d = sub_(d, b >> 1);
+    b = add_(b, d);      d = sub_(add_(d, d), b);
+    c = add_(c, a);      a = sub_(add_(a, a), c);
+    b = add_(b, c);      c = sub_(add_(c, c), b);
+    d = add_(d, a);      a = sub_(add_(a, a), d);
+}
+
+// One 4-point step along the axis whose index bits are at `shift` (x: 0,
+// y: 2, z: 4): the lane gathers its line, runs the step, keeps its output.
+template <bool INV>
+__device__ inline int64_t lift_axis(int64_t v, int shift)
+{
+    const int k = lane_id();
+    const int base = k & ~(3 << shift), s = 1 << shift, pos = (k >> shift) & 3;
+    int64_t a = (int64_t)shfl64((uint64_t)v, base), b = (int64_t)shfl64((uint64_t)v, base + s);
+    int64_t c = (int64_t)shfl64((uint64_t)v, base + 2 * s), d = (int64_t)shfl64((uint64_t)v, base + 3 * s);
+    if (INV) inv_lift(a, b, c, d); else fwd_lift(a, b, c, d);
+    return pos == 0 ? a : (pos == 1 ? b : (pos == 2 ? c : d));
+}
+
+__device__ inline int exponent_of(double x)
+{
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    return e < -1022 ? -1022 : e;
+}
+
+// ---- bits of one block in LDS (rate words, zeroed before encoding) ---------
+// Writer and reader keep their state in wave-uniform values; only lane 0
+// stores to LDS.
+struct BitWriter {
+    uint64_t* words;
+    int pos = 0;
+    __device__ void put(uint64_t bits, int n)  // n in [0, 64]; bits has no bit at or above n
+    {
+        if (n == 0) return;
+        const int w = pos >> 6, o = pos & 63;
+        if (lane_id() == 0) {
+            words[w] |= bits << o;
+            if (o + n > 64) words[w + 1] |= bits >> (64 - o);
+        }
+        pos += n;
+    }
+};
+
+struct BitReader {
+    const uint64_t* words;
+    int rate;
+    int pos = 0;
+    __device__ uint64_t word(int w) const { return w < rate ? uniform64(words[w]) : 0; }
+    __device__ uint64_t peek64() const  // the next 64 bits (zeros past the block)
+    {
+        const int w = pos >> 6, o = pos & 63;
+        const uint64_t lo = word(w);
+        return o ? (lo >> o) | (word(w + 1) << (64 - o)) : lo;
+    }
+    __device__ uint64_t get(int n)  // n in [0, 64]
+    {
+        if (n == 0) return 0;
+        uint64_t v = peek64();
+        if (n < 64) v &= ((uint64_t)1 << n) - 1;
+        pos += n;
+        return v;
+    }
+};
+
+__device__ inline int ctz64(uint64_t v) { return v ? __builtin_ctzll(v) : 64; }
+
+// Group-testing bit-plane coder on this lane's coefficient u (sequency
+// position = lane): the FP32 format's rules with planes 63..0.
+__device__ inline int code_planes(uint64_t u, int budget, BitWriter& bw, uint64_t* planes_out)
+{
+    int n = 0, used = 0;
+    for (int p = 63; p >= 0; --p) {
+        const uint64_t X = __ballot((u >> p) & 1);
+        if (planes_out && lane_id() == 0) planes_out[p] = X;
+        if (budget <= 0) continue;
+        const int m = n < budget ? n : budget;
+        bw.put(m < 64 ? X & (((uint64_t)1 << m) - 1) : X, m);
+        budget -= m;
+        used += m;
+        while (n < 64 && budget > 0) {
+            const bool g = n < 64 && (X >> n) != 0;
+            bw.put(g ? 1 : 0, 1);
+            --budget;
+            ++used;
+            if (!g) break;
+            const int z = ctz64(X >> n);  // zeros before the next 1 (it exists)
+            if (n + z == 63) {             // the last coefficient's 1 is implied
+                const int e = z < budget ? z : budget;
+                bw.put(0, e);
+                budget -= e;
+                used += e;
+                n = e == z ? 64 : n + e;
+            } else {
+                const int e = z + 1 <= budget ? z + 1 : budget;
+                bw.put(e == z + 1 ? (uint64_t)1 << z : 0, e);
+                budget -= e;
+                used += e;
+                n += e;
+            }
+        }
+    }
+    return used;
+}
+
+// The decoder's mirror: returns this lane's coefficient digits.
+__device__ inline uint64_t decode_planes(int budget, BitReader& br, uint64_t* planes_out)
+{
+    const int lane = lane_id();
+    int n = 0;
+    uint64_t u = 0;
+    for (int p = 63; p >= 0; --p) {
+        uint64_t X = 0;
+        if (budget > 0) {
+            const int m = n < budget ? n : budget;
+            X = br.get(m);
+            budget -= m;
+            while (n < 64 && budget > 0) {
+                const uint64_t g = br.get(1);
+                --budget;
+                if (!g) break;
+                const int lim = (63 - n) < budget ? (63 - n) : budget;  // zeros readable before 63 / the end
+                const int z = ctz64(br.peek64());
+                if (z < lim) {  // the run's 1 is read
+                    br.get(z + 1);
+                    budget -= z + 1;
+                    X |= (uint64_t)1 << (n + z);
+                    n += z + 1;
+                } else {        // lim zeros, then either the implied last 1 or the end of the budget
+                    br.get(lim);
+                    budget -= lim;
+                    n += lim;
+                    if (n == 63) {
+                        X |= (uint64_t)1 << 63;
+                        n = 64;
+                    }
+                }
+            }
+        }
+        if (planes_out && lane == 0) planes_out[p] = X;
+        u |= ((X >> lane) & 1) << p;
+    }
+    return u;
+}
+
+struct EncOut { int32_t* emax; int64_t* q; int64_t* t; uint64_t* u; uint64_t* planes; int32_t* bits; };
+struct DecOut { int32_t* emax; uint64_t* planes; uint64_t* u; int64_t* q; };
+
+// Encode one block: x = this lane's value (in-block index = lane). `words`:
+// the block's rate words in LDS, zeroed by the caller. Stage outputs for
+// block b where given.
+__device__ inline void encode_block(double x, int rate, uint64_t* words, EncOut st = {}, int64_t b = 0)
+{
+    const int lane = lane_id();
+    const uint64_t nz = __ballot(x != 0.0);
+    BitWriter bw{words};
+    if (!nz) {
+        bw.put(0, 1);
+        if (st.emax && lane == 0) st.emax[b] = INT32_MIN;
+        if (st.bits && lane == 0) st.bits[b] = 1;
+        return;
+    }
+    int e = x != 0.0 ? exponent_of(x) : -100000;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int other = __builtin_amdgcn_ds_bpermute((lane ^ o) << 2, e);
+        e = e > other ? e : other;
+    }
+    const int emax = __builtin_amdgcn_readfirstlane(e);
+    bw.put(1, 1);
+    bw.put((uint64_t)(emax + 1023), 11);
+    const int64_t q = (int64_t)ldexp(x, 62 - emax);  // the conversion truncates toward zero
+    int64_t t = lift_axis<false>(q, 0);
+    t = lift_axis<false>(t, 2);
+    t = lift_axis<false>(t, 4);
+    const int64_t ts = (int64_t)shfl64((uint64_t)t, kPerm.fwd[lane]);  // sequency order
+    const uint64_t u = ((uint64_t)ts + kNB) ^ kNB;
+    if (st.emax && lane == 0) st.emax[b] = emax;
+    if (st.q) st.q[64 * b + lane] = q;
+    if (st.t) st.t[64 * b + lane] = t;
+    if (st.u) st.u[64 * b + lane] = u;
+    const int used = code_planes(u, 64 * rate - 12, bw, st.planes ? st.planes + 64 * b : nullptr);
+    if (st.bits && lane == 0) st.bits[b] = 12 + used;
+}
+
+// Decode one block from its words in LDS; returns this lane's value.
+__device__ inline double decode_block(const uint64_t* words, int rate, DecOut st = {}, int64_t b = 0)
+{
+    const int lane = lane_id();
+    BitReader br{words, rate};
+    if (!br.get(1)) {
+        if (st.emax && lane == 0) st.emax[b] = INT32_MIN;
+        if (st.u) st.u[64 * b + lane] = 0;
+        if (st.q) st.q[64 * b + lane] = 0;
+        if (st.planes && lane == 0)
+            for (int p = 0; p < 64; ++p) st.planes[64 * b + p] = 0;
+        return 0.0;
+    }
+    const int emax = (int)br.get(11) - 1023;
+    const uint64_t u = decode_planes(64 * rate - 12, br, st.planes ? st.planes + 64 * b : nullptr);
+    const int64_t ts = (int64_t)((u ^ kNB) - kNB);
+    int64_t t = (int64_t)shfl64((uint64_t)ts, kPerm.rank[lane]);  // natural order
+    t = lift_axis<true>(t, 4);
+    t = lift_axis<true>(t, 2);
+    t = lift_axis<true>(t, 0);
+    if (st.emax && lane == 0) st.emax[b] = emax;
+    if (st.u) st.u[64 * b + lane] = u;
+    if (st.q) st.q[64 * b + lane] = t;
+    return ldexp((double)t, emax - 62);
+}
+
+// ---- kernels ----------------------------------------------------------------
+constexpr int kWaves = kBlockThreads / 64;
+
+// Whole fields: each wave codes blocks w, w + W, ... (W = waves in the grid).
+// Block b of the stream is block (bx, by, bz), x fastest.
+__global__ void __launch_bounds__(kBlockThreads)
+field_kernel(bool encode, const double* in_f, double* out_f, const uint64_t* in_w, uint64_t* out_w, int nbx, int nby,
+             int64_t nblocks, int64_t ld_y, int64_t ld_z, int rate)
+{
+    __shared__ uint64_t buf[kWaves][kMaxRate];
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+    uint64_t* words = buf[wave];
+    const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+    const int i = lane & 3, j = (lane >> 2) & 3, l = lane >> 4;
+    for (int64_t b = (int64_t)blockIdx.x * kWaves + wave; b < nblocks; b += nwaves) {
+        const int bx = (int)(b % nbx), by = (int)((b / nbx) % nby);
+        const int64_t bz = b / ((int64_t)nbx * nby);
+        const int64_t at = (4 * bz + l) * ld_z + (int64_t)(4 * by + j) * ld_y + 4 * bx + i;
+        if (encode) {
+            for (int w = lane; w < rate; w += 64) words[w] = 0;
+            __builtin_amdgcn_wave_barrier();
+            encode_block(in_f[at], rate, words);
+            __builtin_amdgcn_wave_barrier();
+            for (int w = lane; w < rate; w += 64) out_w[b * rate + w] = words[w];
+        } else {
+            for (int w = lane; w < rate; w += 64) words[w] = in_w[b * rate + w];
+            __builtin_amdgcn_wave_barrier();
+            out_f[at] = decode_block(words, rate);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__global__ void __launch_bounds__(kBlockThreads)
+encode_stages_kernel(const double* blocks, int64_t nblocks, int rate, EncOut st, uint64_t* out_w)
+{
+    __shared__ uint64_t buf[kWaves][kMaxRate];
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+    const int64_t b = (int64_t)blockIdx.x * kWaves + wave;
+    if (b >= nblocks) return;  // the whole wave leaves together
+    uint64_t* words = buf[wave];
+    for (int w = lane; w < rate; w += 64) words[w] = 0;
+    __builtin_amdgcn_wave_barrier();
+    encode_block(blocks[64 * b + lane], rate, words, st, b);
+    __builtin_amdgcn_wave_barrier();
+    for (int w = lane; w < rate; w += 64) out_w[b * rate + w] = words[w];
+}
+
+__global__ void __launch_bounds__(kBlockThreads)
+decode_stages_kernel(const uint64_t* in_w, int64_t nblocks, int rate, DecOut st, double* out)
+{
+    __shared__ uint64_t buf[kWaves][kMaxRate];
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+    const int64_t b = (int64_t)blockIdx.x * kWaves + wave;
+    if (b >= nblocks) return;
+    uint64_t* words = buf[wave];
+    for (int w = lane; w < rate; w += 64) words[w] = in_w[b * rate + w];
+    __builtin_amdgcn_wave_barrier();
+    const double v = decode_block(words, rate, st, b);
+    if (out) out[64 * b + lane] = v;
+}
+
+}  // namespace codec64
+
+hipError_t launch_codec64_field(bool encode, const double* in_f, double* out_f, const uint64_t* in_w, uint64_t* out_w,
+                                int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t ld_z, int rate,
+                                hipStream_t stream)
+{
+    const int nbx = (int)(nx / 4), nby = (int)(ny / 4);
+    const int64_t nblocks = (int64_t)nbx * nby * (nz / 4);
+    if (nblocks == 0) return hipSuccess;
+    // enough waves to fill the chip several times over; each loops over blocks
+    const int64_t groups = std::min<int64_t>((nblocks + codec64::kWaves - 1) / codec64::kWaves, 256 * 64);
+    hipLaunchKernelGGL(codec64::field_kernel, dim3((unsigned)groups), dim3(kBlockThreads), 0, stream, encode, in_f,
+                       out_f, in_w, out_w, nbx, nby, nblocks, ld_y, ld_z, rate);
+    return hipGetLastError();
+}
+
+hipError_t launch_codec64_stages(bool encode, const double* blocks, const uint64_t* in_w, int64_t nblocks, int rate,
+                                 int32_t* emax, int64_t* q, int64_t* t, uint64_t* u, uint64_t* planes,
+                                 uint64_t* out_w, int32_t* bits, double* out, hipStream_t stream)
+{
+    if (nblocks <= 0) return hipSuccess;
+    const unsigned g = (unsigned)((nblocks + codec64::kWaves - 1) / codec64::kWaves);
+    if (encode)
+        hipLaunchKernelGGL(codec64::encode_stages_kernel, dim3(g), dim3(kBlockThreads), 0, stream, blocks, nblocks,
+                           rate, codec64::EncOut{emax, q, t, u, planes, bits}, out_w);
+    else
+        hipLaunchKernelGGL(codec64::decode_stages_kernel, dim3(g), dim3(kBlockThreads), 0, stream, in_w, nblocks,
+                           rate, codec64::DecOut{emax, planes, u, q}, out);
+    return hipGetLastError();
+}
+
+}  // namespace oocs
+
+// ---------------------------------------------------------------------------
+// FP64 wave step (the paper's precision): one thread per cell, x fastest;
+// the same formula and operation order as the FP32 level, in double:
+//   acc = 3 c0 p;  acc = acc + c_m * (((x+m + x-m) + (y+m + y-m)) + (z+m + z-m)),  m = 1..4
+//   p(n+1) = (2 p - p(n-1)) + w * acc   (+ the source amplitude at its cell)
+// p(n+1) is written over p(n-1) (each thread reads and writes only its own
+// cell of that array). Cells outside the grid are zero.
+// ---------------------------------------------------------------------------
+namespace oocs {
+namespace codec64 {
+
+__global__ void __launch_bounds__(kBlockThreads)
+wave_f64_kernel(const double* __restrict__ p, double* pm, const double* __restrict__ w, int nx, int ny, int nz,
+                int64_t src_cell, double amp)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t c = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+    if (c >= plane * nz) return;
+    const int i = (int)(c % nx), j = (int)((c / nx) % ny), l = (int)(c / plane);
+    const double C0X3 = -205.0 / 24.0;
+    const double CM[5] = {0.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+    auto at = [&](int ii, int jj, int ll) -> double {
+        return (ii < 0 || ii >= nx || jj < 0 || jj >= ny || ll < 0 || ll >= nz) ? 0.0 : p[ll * plane + (int64_t)jj * nx + ii];
+    };
+    const double pc = p[c];
+    double acc = C0X3 * pc;
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) {
+        double sm = (at(i + m, j, l) + at(i - m, j, l)) + (at(i, j + m, l) + at(i, j - m, l));
+        sm = sm + (at(i, j, l + m) + at(i, j, l - m));
+        acc = acc + CM[m] * sm;
+    }
+    double v = (2.0 * pc - pm[c]) + w[c] * acc;
+    if (c == src_cell) v = v + amp;
+    pm[c] = v;
+}
+
+}  // namespace codec64
+
+hipError_t launch_wave_f64(const double* p, double* pm, const double* w, int64_t nx, int64_t ny, int64_t nz,
+                           int64_t src_cell, double amp, hipStream_t stream)
+{
+    const int64_t n = nx * ny * nz;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(codec64::wave_f64_kernel, dim3((unsigned)((n + kBlockThreads - 1) / kBlockThreads)),
+                       dim3(kBlockThreads), 0, stream, p, pm, w, (int)nx, (int)ny, (int)nz, src_cell, amp);
+    return hipGetLastError();
+}
+
+}  // namespace oocs

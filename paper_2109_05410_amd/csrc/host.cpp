@@ -165,6 +165,92 @@ int oocs_codec_decode_stages(const uint64_t* d_words, int64_t nblocks, int rate,
 }
 
 // ---------------------------------------------------------------------------
+// FP64 format and FP64 wave step (codec64.hip)
+// ---------------------------------------------------------------------------
+
+size_t oocs_codec64_bytes(int64_t nx, int64_t ny, int64_t nz, int rate)
+{
+    if (!dims_ok4(nx, ny, nz) || rate < 1 || rate > OOCS_MAX_RATE64) return 0;
+    return (size_t)(nx / 4) * (size_t)(ny / 4) * (size_t)(nz / 4) * (size_t)rate * 8u;
+}
+
+static int codec64_check(int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t ld_z, int rate, size_t bytes)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(OOCS_E_ARG, "dimensions must be positive");
+    if (!dims_ok4(nx, ny, nz)) return fail(OOCS_E_ALIGN, "codec dimensions must be multiples of 4");
+    if (rate < 1 || rate > OOCS_MAX_RATE64) return fail(OOCS_E_RATE, "FP64 rate must be in [1, 68]");
+    if (ld_y < nx || ld_z < ld_y * ny) return fail(OOCS_E_ARG, "leading dimensions too small");
+    if (bytes < oocs_codec64_bytes(nx, ny, nz, rate)) return fail(OOCS_E_SIZE, "compressed buffer too small");
+    if (nx / 4 > (1 << 30) || ny / 4 > (1 << 30)) return fail(OOCS_E_ARG, "field too large");
+    return OOCS_OK;
+}
+
+int oocs_codec64_encode(const double* d_in, int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t ld_z, int rate,
+                        uint64_t* d_out, size_t out_bytes, void* stream)
+{
+    if (!d_in || !d_out) return fail(OOCS_E_ARG, "null pointer");
+    if ((uintptr_t)d_in % 8 || (uintptr_t)d_out % 8) return fail(OOCS_E_ALIGN, "buffers must be 8-byte aligned");
+    const int rc = codec64_check(nx, ny, nz, ld_y, ld_z, rate, out_bytes);
+    if (rc) return rc;
+    HIP_TRY(oocs::launch_codec64_field(true, d_in, nullptr, nullptr, d_out, nx, ny, nz, ld_y, ld_z, rate,
+                                       (hipStream_t)stream));
+    return OOCS_OK;
+}
+
+int oocs_codec64_decode(const uint64_t* d_in, size_t in_bytes, int64_t nx, int64_t ny, int64_t nz, int rate,
+                        double* d_out, int64_t ld_y, int64_t ld_z, void* stream)
+{
+    if (!d_in || !d_out) return fail(OOCS_E_ARG, "null pointer");
+    if ((uintptr_t)d_in % 8 || (uintptr_t)d_out % 8) return fail(OOCS_E_ALIGN, "buffers must be 8-byte aligned");
+    const int rc = codec64_check(nx, ny, nz, ld_y, ld_z, rate, in_bytes);
+    if (rc) return rc;
+    HIP_TRY(oocs::launch_codec64_field(false, nullptr, d_out, d_in, nullptr, nx, ny, nz, ld_y, ld_z, rate,
+                                       (hipStream_t)stream));
+    return OOCS_OK;
+}
+
+int oocs_codec64_encode_stages(const double* d_blocks, int64_t nblocks, int rate, int32_t* d_emax, int64_t* d_q,
+                               int64_t* d_t, uint64_t* d_u, uint64_t* d_planes, uint64_t* d_words, int32_t* d_bits,
+                               void* stream)
+{
+    if (!d_blocks || !d_words || nblocks < 0) return fail(OOCS_E_ARG, "bad block input");
+    if (rate < 1 || rate > OOCS_MAX_RATE64) return fail(OOCS_E_RATE, "FP64 rate must be in [1, 68]");
+    HIP_TRY(oocs::launch_codec64_stages(true, d_blocks, nullptr, nblocks, rate, d_emax, d_q, d_t, d_u, d_planes,
+                                        d_words, d_bits, nullptr, (hipStream_t)stream));
+    return OOCS_OK;
+}
+
+int oocs_codec64_decode_stages(const uint64_t* d_words, int64_t nblocks, int rate, int32_t* d_emax, uint64_t* d_planes,
+                               uint64_t* d_u, int64_t* d_q, double* d_out, void* stream)
+{
+    if (!d_words || nblocks < 0) return fail(OOCS_E_ARG, "bad block input");
+    if (rate < 1 || rate > OOCS_MAX_RATE64) return fail(OOCS_E_RATE, "FP64 rate must be in [1, 68]");
+    HIP_TRY(oocs::launch_codec64_stages(false, nullptr, d_words, nblocks, rate, d_emax, d_q, nullptr, d_u, d_planes,
+                                        nullptr, nullptr, d_out, (hipStream_t)stream));
+    return OOCS_OK;
+}
+
+int oocs_wave25_step_k_f64(double* d_p, double* d_pm, const double* d_w, int64_t nx, int64_t ny, int64_t nz,
+                           int64_t k, const double* h_src, int64_t src_x, int64_t src_y, int64_t src_z, void* stream)
+{
+    if (!d_p || !d_pm || !d_w || k < 0 || nx <= 0 || ny <= 0 || nz <= 0) return fail(OOCS_E_ARG, "bad argument");
+    if (nx * ny * nz >= ((int64_t)1 << 40) || nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20))
+        return fail(OOCS_E_ARG, "grid too large");
+    const bool src_on = h_src && src_x >= 0 && src_x < nx && src_y >= 0 && src_y < ny && src_z >= 0 && src_z < nz;
+    const int64_t cell = src_on ? src_x + nx * (src_y + ny * src_z) : -1;
+    hipStream_t s = (hipStream_t)stream;
+    double* p = d_p;
+    double* pm = d_pm;
+    for (int64_t t = 0; t < k; ++t) {
+        HIP_TRY(oocs::launch_wave_f64(p, pm, d_w, nx, ny, nz, cell, src_on ? h_src[t] : 0.0, s));
+        std::swap(p, pm);  // pm now holds p(n+1)
+    }
+    if (p != d_p)  // an odd number of steps: exchange the two arrays' contents (bitwise, as float pairs)
+        HIP_TRY(oocs::launch_swap(reinterpret_cast<float*>(d_p), reinterpret_cast<float*>(d_pm), 2 * nx * ny * nz, s));
+    return OOCS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // In-core stencil steps (same level kernels as the pipeline, whole field as
 // one ring with no wrap-around)
 // ---------------------------------------------------------------------------

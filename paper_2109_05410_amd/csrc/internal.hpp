@@ -195,6 +195,17 @@ hipError_t add_batch_step_node(const BatchDomain* d_table, int nd, int32_t total
 hipError_t launch_heat_dense(const float* src, float* dst, int nx, int ny, int nz, float alpha, int cfg,
                              hipStream_t stream);
 
+// FP64 format (codec64.hip): whole fields, and per-block stages.
+hipError_t launch_codec64_field(bool encode, const double* in_f, double* out_f, const uint64_t* in_w, uint64_t* out_w,
+                                int64_t nx, int64_t ny, int64_t nz, int64_t ld_y, int64_t ld_z, int rate,
+                                hipStream_t stream);
+hipError_t launch_codec64_stages(bool encode, const double* blocks, const uint64_t* in_w, int64_t nblocks, int rate,
+                                 int32_t* emax, int64_t* q, int64_t* t, uint64_t* u, uint64_t* planes,
+                                 uint64_t* out_w, int32_t* bits, double* out, hipStream_t stream);
+// One FP64 wave step on a dense field; p(n+1) is written over pm.
+hipError_t launch_wave_f64(const double* p, double* pm, const double* w, int64_t nx, int64_t ny, int64_t nz,
+                           int64_t src_cell, double amp, hipStream_t stream);
+
 struct EncStages {
     int32_t* emax; int32_t* q; int32_t* t; uint32_t* u; uint64_t* planes; uint64_t* words; int32_t* bits;
 };
