@@ -271,6 +271,16 @@ typedef struct {
  * plain plan applies decode o encode. */
 #define OOCS_PLAN_MIDPOINT 64
 
+/* Plan flag (wave): the fields are FP64 (the precision of the paper's
+ * experiments, Sec. VI): device planes of doubles, raw host stores of
+ * nx*ny*nz*8 bytes, compressed stores in the FP64 format (rates 1..68, see
+ * oocs_codec64_encode), the FP64 wave step (oocs_wave25_step_k_f64's
+ * arithmetic). oocs_store_put / oocs_store_get take double fields; source
+ * amplitudes stay float (converted exactly to double). Not with
+ * OOCS_PLAN_MIDPOINT, the heat stencil or transfer jobs
+ * (OOCS_PLAN_KERNEL_TRANSFERS, OOCS_PLAN_KERNEL_STORES). */
+#define OOCS_PLAN_FP64 128
+
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be
  * queried but not run (no HIP call is made for it). Chooses the group size
@@ -360,16 +370,19 @@ int64_t oocs_plan_schedule_variant_len(oocs_plan* plan, int kr, int variant);
 int oocs_plan_schedule_variant_op(oocs_plan* plan, int kr, int variant, int64_t index, oocs_op* out);
 
 /* Host store size for a field slot: the field's compressed stream, or
- * nx*ny*nz*4 bytes if uncompressed; 0 for an unused slot. */
+ * nx*ny*nz*4 bytes if uncompressed (nx*ny*nz*8 in an FP64 plan); 0 for an
+ * unused slot. */
 size_t oocs_store_bytes(const oocs_plan* plan, int field);
 
-/* Build a field's host store from the FP32 host field h_field (initial
- * compression, done once; for the read-only field the only time it is ever
- * compressed). Streams through the plan's arena on the GPU. Blocking. */
-int oocs_store_put(oocs_plan* plan, int field, const float* h_field, void* h_store);
+/* Build a field's host store from the host field h_field (nx*ny*nz values,
+ * x fastest: float, or double in an FP64 plan): the initial compression,
+ * done once; for the read-only field the only time it is ever compressed.
+ * Streams through the plan's arena on the GPU. Blocking. */
+int oocs_store_put(oocs_plan* plan, int field, const void* h_field, void* h_store);
 
-/* Decode a field's host store into the FP32 host field h_field. Blocking. */
-int oocs_store_get(oocs_plan* plan, int field, const void* h_store, float* h_field);
+/* Decode a field's host store into the host field h_field (float, or
+ * double in an FP64 plan). Blocking. */
+int oocs_store_get(oocs_plan* plan, int field, const void* h_store, void* h_field);
 
 typedef struct {
     double wall_ms;          /* host wall time of the call */
@@ -520,15 +533,19 @@ int oocs_wave25_step_k_f64(double* d_p, double* d_pm, const double* d_w, int64_t
 
 /* ------------------------------------------------------------------------
  * Batched in-core heat domains. Many independent domains of uneven sizes
- * advance together. By default a run is one persistent kernel launch (one
- * node of a HIP graph): its workgroups take items (domain, tile, group of k
- * steps) in order from a device queue, and an item of group g of a domain
- * starts once every tile of group g-1 of that domain has finished (a
- * per-domain count of finished tiles, raised after a device-scope release).
- * Waits are bounded: a wait that exceeds its poll limit sets a status word
- * and every workgroup leaves, so the kernel always ends; oocs_batch_check
- * reports it. The alternative mode replays one launch per group (every
- * domain, k steps) as a graph. k > 1 is temporal blocking: a workgroup
+ * advance together. By default a run replays, as one HIP graph, one launch
+ * per group (every tile of every domain, k steps). The persistent mode runs
+ * the same work as one kernel launch: its workgroups take items (domain,
+ * tile, group of k steps) in order from a device queue, and an item of
+ * group g of a domain starts once every tile of group g-1 of that domain
+ * has finished (a per-domain count of finished tiles, raised after a
+ * device-scope release). Waits are bounded: a wait that exceeds its poll
+ * limit sets a status word and every workgroup leaves, so the kernel always
+ * ends; oocs_batch_check reports it. On a chip whose dies each have their
+ * own L2, the device-scope release and acquire around every tile write back
+ * and invalidate that L2, which costs more than the launch boundaries it
+ * saves: the persistent mode is the slower one there and stays opt-in.
+ * k > 1 is temporal blocking: a workgroup
  * advances its tile k steps in one pass over z, recomputing a k-cell halo,
  * so each cell crosses HBM once per k steps. The tile shape is chosen per
  * size bucket by a timing autotuner (three or more shapes per depth) whose
@@ -564,7 +581,7 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
                       const char* tune_cache, int tune, int depth, void* stream, oocs_batch** out);
 
 /* Advance every domain `steps` steps as one graph launch on `stream`, built
- * once per step count. Persistent mode (default): one kernel for the
+ * once per step count. Persistent mode: one kernel for the
  * steps / k groups at depth k; when steps mod k > 0, a second persistent
  * kernel for the remaining depth-1 groups; when the number of groups is
  * odd, copy items move the result from the scratch buffers to u (in the
@@ -574,7 +591,7 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
  * whether a wait gave up. */
 int oocs_batch_run(oocs_batch* b, int64_t steps, void* stream);
 
-/* 1 (default): runs are persistent launches; 0: one launch per group. */
+/* 1: runs are persistent launches; 0 (default): one launch per group. */
 int oocs_batch_set_persistent(oocs_batch* b, int on);
 
 /* Poll limit of the persistent kernel's waits (default 2^21 polls, each

@@ -34,6 +34,7 @@ OOCS_PLAN_KERNEL_STORES = 8
 OOCS_PLAN_RESIDENT_RO = 16
 OOCS_PLAN_SNAKE = 32
 OOCS_PLAN_MIDPOINT = 64
+OOCS_PLAN_FP64 = 128
 OOCS_DECODE_MIDPOINT = 0x100
 OOCS_SCHED_MIRROR = 1
 OOCS_SCHED_RETAIN_IN = 2

@@ -344,13 +344,15 @@ class OutOfCorePlan:
     block a residency ends with stays on the device (compressed, or raw if
     uncompressed) for the next one. Results are identical. midpoint: every
     decode reconstructs the digits the budget cut off at the middle of their
-    range (a different, lower-error state)."""
+    range (a different, lower-error state). fp64 (wave): FP64 fields and
+    the FP64 block format (rates up to 68); put/get take and return float64
+    arrays; copy-engine transfers only."""
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
                  planning_only: bool = False, device=None, block_restart: bool = False,
                  kernel_transfers: bool = False, level_by_level: bool = False, kernel_stores: bool = False,
-                 resident_ro: bool = False, snake: bool = False, midpoint: bool = False):
+                 resident_ro: bool = False, snake: bool = False, midpoint: bool = False, fp64: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -368,11 +370,13 @@ class OutOfCorePlan:
                      | (L.OOCS_PLAN_KERNEL_STORES if kernel_stores else 0)
                      | (L.OOCS_PLAN_RESIDENT_RO if resident_ro else 0)
                      | (L.OOCS_PLAN_SNAKE if snake else 0)
-                     | (L.OOCS_PLAN_MIDPOINT if midpoint else 0))
+                     | (L.OOCS_PLAN_MIDPOINT if midpoint else 0)
+                     | (L.OOCS_PLAN_FP64 if fp64 else 0))
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg
         self.shape = (nz, ny, nx)
+        self.dtype = np.float64 if fp64 else np.float32
         self.stencil = stencil
         self.arena = None
         ptr = None
@@ -437,14 +441,15 @@ class OutOfCorePlan:
         return torch.empty(self.store_bytes(f), dtype=torch.uint8, pin_memory=True)
 
     def put(self, f: int, field, store: torch.Tensor):
-        """Build store f from a host FP32 field (numpy or CPU tensor)."""
-        a = np.ascontiguousarray(field.numpy() if isinstance(field, torch.Tensor) else field, dtype=np.float32)
+        """Build store f from a host field (numpy or CPU tensor; FP32, or FP64
+        in an fp64 plan)."""
+        a = np.ascontiguousarray(field.numpy() if isinstance(field, torch.Tensor) else field, dtype=self.dtype)
         if a.shape != self.shape:
             raise ValueError("field shape mismatch")
         L.check(L.lib().oocs_store_put(self._h, f, a.ctypes.data_as(C.c_void_p), C.c_void_p(store.data_ptr())))
 
     def get(self, f: int, store: torch.Tensor) -> np.ndarray:
-        out = np.empty(self.shape, dtype=np.float32)
+        out = np.empty(self.shape, dtype=self.dtype)
         L.check(L.lib().oocs_store_get(self._h, f, C.c_void_p(store.data_ptr()), out.ctypes.data_as(C.c_void_p)))
         return out
 
@@ -586,10 +591,10 @@ class WaveMisfit(torch.autograd.Function):
 # ---------------------------------------------------------------------------
 
 class HeatBatch:
-    """Independent heat domains advanced together: by default one persistent
-    kernel per run (items of every domain, tile and group of k steps from a
-    device queue), replayed as a graph; persistent=False: one launch per k
-    steps for all domains, all launches replayed as one graph. `fields` are
+    """Independent heat domains advanced together: by default one launch per
+    k steps for all domains, all launches replayed as one graph;
+    set_persistent(True): one persistent kernel per run (items of every
+    domain, tile and group of k steps from a device queue). `fields` are
     (nz, ny, nx) float32 device tensors, updated in place by run(). depth:
     0 = temporal-blocking depth chosen by the autotuner, or 1, 2, 4."""
 

@@ -35,7 +35,7 @@ struct oocs_batch {
     int grid[2] = {0, 0};                  // persistent grid: [0] blocked tiles, [1] depth-1 tiles
     int depth = 1;
     float alpha = 0.1f;
-    bool persistent = true;
+    bool persistent = false;
     int64_t spin_limit = (int64_t)1 << 21;
     bool force_wait = false;
     std::map<int64_t, hipGraphExec_t> graphs;  // by step count

@@ -428,4 +428,172 @@ hipError_t launch_wave_f64(const double* p, double* pm, const double* w, int64_t
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Pipeline jobs on FP64 ring planes. A ring slot holds one plane of doubles
+// (the ring's plane stride counts floats, two per double). The jobs and the
+// staging layouts are those of the FP32 pipeline kernel: a tick's jobs share
+// one launch and the workgroup index selects the job; compressed staging
+// holds the 4-plane layers of [z0, z1) in z order, each layer's blocks x
+// fastest then y, `rate` words per block; raw staging holds the planes back
+// to back.
+// ---------------------------------------------------------------------------
+namespace codec64 {
+
+constexpr int kCopy4PerThread = 4;
+
+__device__ inline double* plane64(const Ring& r, int64_t z) { return reinterpret_cast<double*>(ring_plane(r, z)); }
+
+// One FP64 wave time level at one cell per thread, planes [z0, z1): the
+// arithmetic of wave_f64_kernel, reading p(n) from src (neighbours outside
+// the grid are zero), p(n-1) from src2 and w from ro, writing p(n+1) to dst.
+__device__ inline void wave_level_job(const Job& j, const LaunchParams& p, int wg)
+{
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t per_plane = (plane + kBlockThreads - 1) / kBlockThreads;
+    const int z = j.z0 + (int)(wg / per_plane);
+    const int64_t c = (wg % per_plane) * kBlockThreads + threadIdx.x;
+    if (z >= j.z1 || c >= plane) return;
+    const int x = (int)(c % nx), y = (int)(c / nx);
+    const double C0X3 = -205.0 / 24.0;
+    const double CM[5] = {0.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+    const double* pz = plane64(j.src, z);
+    auto in_xy = [&](int xx, int yy) -> double {
+        return (xx < 0 || xx >= nx || yy < 0 || yy >= ny) ? 0.0 : pz[(int64_t)yy * nx + xx];
+    };
+    auto in_z = [&](int zz) -> double { return (zz < 0 || zz >= nz) ? 0.0 : plane64(j.src, zz)[c]; };
+    const double pc = pz[c];
+    double acc = C0X3 * pc;
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) {
+        double sm = (in_xy(x + m, y) + in_xy(x - m, y)) + (in_xy(x, y + m) + in_xy(x, y - m));
+        sm = sm + (in_z(z + m) + in_z(z - m));
+        acc = acc + CM[m] * sm;
+    }
+    double v = (2.0 * pc - plane64(j.src2, z)[c]) + plane64(j.ro, z)[c] * acc;
+    if (j.has_src && x == p.src_x && y == p.src_y && z == p.src_z)
+        v = v + (double)(p.src_table ? p.src_table[*p.step_ctr + j.src_off] : j.amp);
+    plane64(j.dst, z)[c] = v;
+}
+
+// One wave per block (the field kernel's mapping), blocks of the job's layers.
+__device__ inline void ring_codec_job(const Job& j, int nx, int ny, int wg, bool encode, uint64_t* words)
+{
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+    const int nbx = nx >> 2, nby = ny >> 2;
+    const int64_t layer_blocks = (int64_t)nbx * nby;
+    const int64_t b = (int64_t)wg * kWaves + wave;
+    if (b >= (int64_t)((j.z1 - j.z0 + 3) / 4) * layer_blocks) return;  // the whole wave leaves together
+    const int bx = (int)(b % nbx), by = (int)((b / nbx) % nby);
+    const int layer = (int)(b / layer_blocks);
+    const int i = lane & 3, jj = (lane >> 2) & 3, l = lane >> 4;
+    double* at = plane64(j.dst, j.z0 + 4 * layer + l) + (int64_t)(4 * by + jj) * nx + 4 * bx + i;
+    uint64_t* stage = static_cast<uint64_t*>(j.stage) + b * j.rate;
+    if (encode) {
+        for (int w = lane; w < j.rate; w += 64) words[w] = 0;
+        __builtin_amdgcn_wave_barrier();
+        encode_block(*at, j.rate, words);
+        __builtin_amdgcn_wave_barrier();
+        for (int w = lane; w < j.rate; w += 64) stage[w] = words[w];
+    } else {
+        for (int w = lane; w < j.rate; w += 64) words[w] = stage[w];
+        __builtin_amdgcn_wave_barrier();
+        *at = decode_block(words, j.rate);
+    }
+}
+
+// Raw planes of doubles between staging and ring, as float4 moves.
+__device__ inline void ring_copy_job(const Job& j, int nx, int ny, int wg, bool in)
+{
+    const int64_t plane_f = 2 * (int64_t)nx * ny;  // floats per plane
+    const int64_t n4 = plane_f / 4;
+    const int64_t per_wg = (int64_t)kBlockThreads * kCopy4PerThread;
+    const int64_t wg_per_plane = (n4 + per_wg - 1) / per_wg;
+    const int pz = (int)(wg / wg_per_plane);
+    const int z = j.z0 + pz;
+    if (z >= j.z1) return;
+    const int64_t base = (wg % wg_per_plane) * per_wg;
+    float4* r = reinterpret_cast<float4*>(ring_plane(j.dst, z));
+    float4* st = reinterpret_cast<float4*>(static_cast<float*>(j.stage) + (int64_t)pz * plane_f);
+#pragma unroll
+    for (int k = 0; k < kCopy4PerThread; ++k) {
+        const int64_t e = base + (int64_t)k * kBlockThreads + threadIdx.x;
+        if (e < n4) {
+            if (in) r[e] = st[e]; else st[e] = r[e];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlockThreads) fused64_kernel(LaunchParams p)
+{
+    __shared__ uint64_t buf[kWaves][kMaxRate];
+    const int wg = (int)blockIdx.x;
+    int jdx = 0;
+    while (jdx + 1 < p.njobs && wg >= p.wg_begin[jdx + 1]) ++jdx;
+    const Job& j = p.jobs[jdx];
+    const int local = wg - p.wg_begin[jdx];
+    switch (j.kind) {
+    case JOB_WAVE: wave_level_job(j, p, local); break;
+    case JOB_DECODE: ring_codec_job(j, p.nx, p.ny, local, false, buf[threadIdx.x >> 6]); break;
+    case JOB_ENCODE: ring_codec_job(j, p.nx, p.ny, local, true, buf[threadIdx.x >> 6]); break;
+    case JOB_COPY_IN: ring_copy_job(j, p.nx, p.ny, local, true); break;
+    case JOB_COPY_OUT: ring_copy_job(j, p.nx, p.ny, local, false); break;
+    default: break;
+    }
+}
+
+static int32_t job_workgroups64(const Job& j, int nx, int ny)
+{
+    const int64_t planes = j.z1 - j.z0;
+    if (planes <= 0) return 0;
+    const int64_t plane = (int64_t)nx * ny;
+    switch (j.kind) {
+    case JOB_WAVE: return (int32_t)(((plane + kBlockThreads - 1) / kBlockThreads) * planes);
+    case JOB_DECODE:
+    case JOB_ENCODE: return (int32_t)(((planes + 3) / 4 * (nx / 4) * (ny / 4) + kWaves - 1) / kWaves);
+    case JOB_COPY_IN:
+    case JOB_COPY_OUT: {
+        const int64_t per_wg = (int64_t)kBlockThreads * kCopy4PerThread;
+        return (int32_t)(((2 * plane / 4 + per_wg - 1) / per_wg) * planes);
+    }
+    default: return 0;
+    }
+}
+
+}  // namespace codec64
+
+// Stencil and copy jobs first, codec jobs last (as in the FP32 kernel: the
+// codec waves fill the slots the others leave).
+bool prepare_jobs_f64(LaunchParams& p, const void** func, unsigned* grid, size_t* lds)
+{
+    Job sorted[kMaxJobs];
+    int n = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < p.njobs; ++i)
+            if ((p.jobs[i].kind == JOB_DECODE || p.jobs[i].kind == JOB_ENCODE) == (pass == 1)) sorted[n++] = p.jobs[i];
+    int32_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        p.jobs[i] = sorted[i];
+        p.wg_begin[i] = total;
+        p.jobs[i].wg_count = codec64::job_workgroups64(p.jobs[i], p.nx, p.ny);
+        total += p.jobs[i].wg_count;
+    }
+    p.wg_begin[p.njobs] = total;
+    if (total == 0) return false;
+    *func = reinterpret_cast<const void*>(&codec64::fused64_kernel);
+    *grid = (unsigned)total;
+    *lds = 0;
+    return true;
+}
+
+hipError_t launch_jobs_f64(LaunchParams& p, hipStream_t stream)
+{
+    const void* func;
+    unsigned grid;
+    size_t lds;
+    if (!prepare_jobs_f64(p, &func, &grid, &lds)) return hipSuccess;
+    hipLaunchKernelGGL(codec64::fused64_kernel, dim3(grid), dim3(kBlockThreads), 0, stream, p);
+    return hipGetLastError();
+}
+
 }  // namespace oocs

@@ -431,7 +431,7 @@ int oocs_plan_get_info(const oocs_plan* pl, oocs_plan_info* out)
     out->nlevels = P.nin + P.k;
     out->nrings = P.nrings();
     for (int i = 0; i < P.nrings() && i < 16; ++i) out->ring_planes[i] = P.ringW[i];
-    out->plane_bytes = P.plane_elems() * 4;
+    out->plane_bytes = P.plane_bytes();
     out->arena_needed = P.arena_needed;
     out->nstage = P.nstage;
     for (int f = 0; f < OOCS_MAX_FIELDS; ++f) out->store_bytes[f] = P.store_bytes(f);
@@ -496,12 +496,12 @@ size_t oocs_store_bytes(const oocs_plan* pl, int field)
 
 // Initial compression of a field into its host store, and decompression of
 // a host store, streamed through the arena in chunks of 4-plane layers.
-static int store_xfer(oocs_plan* pl, int f, bool put, const float* h_field_in, float* h_field_out, const void* h_store_in,
+static int store_xfer(oocs_plan* pl, int f, bool put, const void* h_field_in, void* h_field_out, const void* h_store_in,
                       void* h_store_out)
 {
     const oocs::Planner& P = pl->P;
     pl->ro_loaded = nullptr;  // the chunks below overwrite the start of the arena
-    const int64_t pb = P.plane_elems() * 4;
+    const int64_t pb = P.plane_bytes();
     const int rate = P.cfg.rate[f];
     const int64_t spb = P.store_plane_bytes(f);
     hipStream_t s = pl->st[1];
@@ -514,24 +514,34 @@ static int store_xfer(oocs_plan* pl, int f, bool put, const float* h_field_in, f
         const int64_t z1 = std::min(P.nz, z0 + chunk);
         const int64_t planes = z1 - z0;
         if (put) {
-            HIP_TRY(hipMemcpyAsync(raw, h_field_in + z0 * P.plane_elems(), (size_t)(planes * pb), hipMemcpyHostToDevice, s));
-            HIP_TRY(oocs::launch_codec_field(true, reinterpret_cast<float*>(raw), nullptr, nullptr, comp, P.nx, P.ny, planes,
-                                             P.nx, P.plane_elems(), rate, s));
+            HIP_TRY(hipMemcpyAsync(raw, static_cast<const char*>(h_field_in) + z0 * pb, (size_t)(planes * pb),
+                                   hipMemcpyHostToDevice, s));
+            if (P.fp64)
+                HIP_TRY(oocs::launch_codec64_field(true, reinterpret_cast<double*>(raw), nullptr, nullptr, comp, P.nx,
+                                                   P.ny, planes, P.nx, P.plane_elems(), rate, s));
+            else
+                HIP_TRY(oocs::launch_codec_field(true, reinterpret_cast<float*>(raw), nullptr, nullptr, comp, P.nx, P.ny,
+                                                 planes, P.nx, P.plane_elems(), rate, s));
             HIP_TRY(hipMemcpyAsync(static_cast<char*>(h_store_out) + z0 * spb, comp, (size_t)(planes * spb),
                                    hipMemcpyDeviceToHost, s));
         } else {
             HIP_TRY(hipMemcpyAsync(comp, static_cast<const char*>(h_store_in) + z0 * spb, (size_t)(planes * spb),
                                    hipMemcpyHostToDevice, s));
-            HIP_TRY(oocs::launch_codec_field(false, nullptr, reinterpret_cast<float*>(raw), comp, nullptr, P.nx, P.ny, planes,
-                                             P.nx, P.plane_elems(), rate, s, P.midpoint));
-            HIP_TRY(hipMemcpyAsync(h_field_out + z0 * P.plane_elems(), raw, (size_t)(planes * pb), hipMemcpyDeviceToHost, s));
+            if (P.fp64)
+                HIP_TRY(oocs::launch_codec64_field(false, nullptr, reinterpret_cast<double*>(raw), comp, nullptr, P.nx,
+                                                   P.ny, planes, P.nx, P.plane_elems(), rate, s));
+            else
+                HIP_TRY(oocs::launch_codec_field(false, nullptr, reinterpret_cast<float*>(raw), comp, nullptr, P.nx,
+                                                 P.ny, planes, P.nx, P.plane_elems(), rate, s, P.midpoint));
+            HIP_TRY(hipMemcpyAsync(static_cast<char*>(h_field_out) + z0 * pb, raw, (size_t)(planes * pb),
+                                   hipMemcpyDeviceToHost, s));
         }
         HIP_TRY(hipStreamSynchronize(s));
     }
     return OOCS_OK;
 }
 
-int oocs_store_put(oocs_plan* pl, int f, const float* h_field, void* h_store)
+int oocs_store_put(oocs_plan* pl, int f, const void* h_field, void* h_store)
 {
     if (!pl || !h_field || !h_store) return fail(OOCS_E_ARG, "null pointer");
     if (f < 0 || f >= pl->P.nfields) return fail(OOCS_E_ARG, "field slot out of range");
@@ -543,7 +553,7 @@ int oocs_store_put(oocs_plan* pl, int f, const float* h_field, void* h_store)
     return store_xfer(pl, f, true, h_field, nullptr, nullptr, h_store);
 }
 
-int oocs_store_get(oocs_plan* pl, int f, const void* h_store, float* h_field)
+int oocs_store_get(oocs_plan* pl, int f, const void* h_store, void* h_field)
 {
     if (!pl || !h_field || !h_store) return fail(OOCS_E_ARG, "null pointer");
     if (f < 0 || f >= pl->P.nfields) return fail(OOCS_E_ARG, "field slot out of range");
@@ -588,7 +598,7 @@ static int job_stage(int kind)
 static int64_t job_bytes(const oocs::Job& j, int64_t plane_elems)
 {
     const int64_t planes = j.z1 - j.z0;
-    const int64_t pb = plane_elems * 4;
+    const int64_t pb = plane_elems * (j.f64 ? 8 : 4);
     switch (j.kind) {
     case oocs::JOB_HEAT: return planes * pb * 2;        // read u, write u'
     case oocs::JOB_HEAT_TB: return planes * pb * 2;     // read u(t), write u(t+k): k updates per cell
@@ -724,7 +734,7 @@ struct OpTranslator {
     oocs::Ring ring(int idx) const
     {
         const oocs::Planner& P = pl->P;
-        return oocs::Ring{reinterpret_cast<float*>(pl->arena + P.ringOff[idx]), P.ringW[idx], P.plane_elems()};
+        return oocs::Ring{reinterpret_cast<float*>(pl->arena + P.ringOff[idx]), P.ringW[idx], P.ring_ld()};
     }
     // H2D / D2H of an op: device pointer, host pointer, bytes
     void copy_args(const oocs_op& o, void** dev, void** host, size_t* bytes) const
@@ -745,6 +755,7 @@ struct OpTranslator {
         std::memset(&j, 0, sizeof j);
         j.z0 = (int32_t)o.z0;
         j.z1 = (int32_t)o.z1;
+        j.f64 = P.fp64 ? 1 : 0;
         if (o.kind == OOCS_OP_FETCH || o.kind == OOCS_OP_STORE) {
             const bool in = o.kind == OOCS_OP_FETCH;
             const int64_t spb = P.store_plane_bytes(o.field);
@@ -818,7 +829,8 @@ int load_resident_ro(oocs_plan* pl, const void* h_ro)
         j.z0 = (int32_t)z0;
         j.z1 = (int32_t)z1;
         j.dst = oocs::Ring{reinterpret_cast<float*>(pl->arena + P.ringOff[P.ro_ring()]), P.ringW[P.ro_ring()],
-                           P.plane_elems()};
+                           P.ring_ld()};
+        j.f64 = P.fp64 ? 1 : 0;
         j.stage = slot;
         lp.njobs = 1;
         HIP_TRY(oocs::launch_jobs(lp, s));

@@ -47,7 +47,7 @@ struct Job {
     int32_t src_off;   // else the amplitude is src_table[*step_ctr + src_off]
     int32_t wg_count;  // workgroups of this job
     int32_t mid;       // decode jobs: mid-point reconstruction of the digits the budget cut off
-    int32_t pad_;
+    int32_t f64;       // FP64 planes (rings hold doubles; codec jobs use the FP64 format)
     Ring src, src2, ro, dst;  // stencil jobs (dst doubles as `ring` for codec/copy jobs)
     void* stage;              // codec/copy/transfer jobs
     void* host;               // transfer jobs: device address of the host-store bytes
@@ -90,6 +90,12 @@ hipError_t launch_jobs(LaunchParams& p, hipStream_t stream);
 // The same launch as a kernel node of graph g after `deps` (node left in *node;
 // no node and hipSuccess if there is no work).
 hipError_t add_jobs_node(LaunchParams& p, hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node);
+
+// FP64 jobs (Job::f64; every job of the launch): the FP64 pipeline kernel,
+// which runs wave levels, FP64-format codec jobs and raw copies. launch_jobs
+// and add_jobs_node hand such launches to these.
+bool prepare_jobs_f64(LaunchParams& p, const void** func, unsigned* grid, size_t* lds);
+hipError_t launch_jobs_f64(LaunchParams& p, hipStream_t stream);
 
 // Device step counter of the wave source table: set to `value` (add = false)
 // or advanced by `value` (add = true); as a launch or as a graph node.

@@ -266,6 +266,7 @@ static int dispatch_class(int kind) { return is_xfer_job(kind) ? 0 : (is_codec_j
 
 static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, size_t* lds)
 {
+    if (p.njobs > 0 && p.jobs[0].f64) return prepare_jobs_f64(p, func, grid, lds);
     Job sorted[kMaxJobs];
     int n = 0;
     for (int pass = 0; pass < 3; ++pass)
@@ -308,6 +309,7 @@ static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, siz
 
 hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
 {
+    if (p.njobs > 0 && p.jobs[0].f64) return launch_jobs_f64(p, stream);
     const void* func;
     unsigned grid;
     size_t lds;

@@ -41,9 +41,21 @@ int Planner::init(const oocs_config& c, std::string& err)
     slab = nz / n;
     h = (int64_t)r * k;
     if (2 * h > slab && n > 1) { err = fmt("halo 2h = %lld exceeds the slab thickness %lld", 2 * h, slab); return OOCS_E_HALO; }
+    fp64 = (c.flags & OOCS_PLAN_FP64) != 0;
+    if (fp64 && c.stencil != OOCS_WAVE25) { err = "FP64 plans are for the wave stencil"; return OOCS_E_ARG; }
+    if (fp64 && (c.flags & OOCS_PLAN_MIDPOINT)) { err = "mid-point decoding is not available in FP64"; return OOCS_E_ARG; }
+    if (fp64 && (c.flags & (OOCS_PLAN_KERNEL_TRANSFERS | OOCS_PLAN_KERNEL_STORES))) {
+        err = "FP64 plans move data with the copy engines (no transfer jobs)";
+        return OOCS_E_ARG;
+    }
+    esize = fp64 ? 8 : 4;
+    const int max_rate = fp64 ? OOCS_MAX_RATE64 : OOCS_MAX_RATE;
     bool any_rate = false;
     for (int f = 0; f < nfields; ++f) {
-        if (c.rate[f] < 0 || c.rate[f] > OOCS_MAX_RATE) { err = fmt("rate[%lld] = %lld outside [0, 34]", f, c.rate[f]); return OOCS_E_RATE; }
+        if (c.rate[f] < 0 || c.rate[f] > max_rate) {
+            err = fmt("rate[%lld] = %lld outside [0, %lld]", f, c.rate[f], max_rate);
+            return OOCS_E_RATE;
+        }
         any_rate |= c.rate[f] > 0;
     }
     for (int f = nfields; f < OOCS_MAX_FIELDS; ++f)
@@ -55,7 +67,8 @@ int Planner::init(const oocs_config& c, std::string& err)
     if (c.group < 0 || (c.group > 0 && any_rate && c.group % 4)) { err = "group must be a positive multiple of 4"; return OOCS_E_ALIGN; }
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
     if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS | OOCS_PLAN_LEVEL_BY_LEVEL |
-                    OOCS_PLAN_KERNEL_STORES | OOCS_PLAN_RESIDENT_RO | OOCS_PLAN_SNAKE | OOCS_PLAN_MIDPOINT)) {
+                    OOCS_PLAN_KERNEL_STORES | OOCS_PLAN_RESIDENT_RO | OOCS_PLAN_SNAKE | OOCS_PLAN_MIDPOINT |
+                    OOCS_PLAN_FP64)) {
         err = "unknown plan flags";
         return OOCS_E_ARG;
     }
@@ -97,7 +110,7 @@ int Planner::out_ring(int f, int kr) const
 int64_t Planner::store_plane_bytes(int f) const
 {
     const int rate = cfg.rate[f];
-    if (rate == 0) return plane_elems() * 4;
+    if (rate == 0) return plane_bytes();
     return (nx / 4) * (ny / 4) * (int64_t)rate * 8 / 4;  // one 4-plane layer / 4
 }
 
@@ -323,7 +336,7 @@ int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
     if (resident_ro) W[ro_ring()] = nz;  // the whole decoded field
     ringW = W;
     ringOff.assign(R, 0);
-    const int64_t pb = plane_elems() * 4;
+    const int64_t pb = plane_bytes();
     int64_t off = 0;
     for (int ring = 0; ring < R; ++ring) {
         ringOff[ring] = off;

@@ -88,6 +88,8 @@ public:
     bool resident_ro = false;   // wave: the read-only field stays decoded in an nz-plane ring
     bool snake = false;         // alternating sweeps; the last block of a residency stays on the device
     bool midpoint = false;      // every decode with mid-point reconstruction
+    bool fp64 = false;          // FP64 fields (wave): 8-byte values, the FP64 format
+    int esize = 4;              // bytes per value
     int64_t X = 0;              // snake: planes of the retained block (one slab)
     static constexpr int kMaxFusedSteps = 4;
     int64_t slab = 0, h = 0;
@@ -101,6 +103,8 @@ public:
     int ro_ring() const { return nin + k; }
     int nrings() const { return fused ? 2 : nin + k + (has_ro ? 1 : 0); }
     int64_t plane_elems() const { return nx * ny; }
+    int64_t plane_bytes() const { return nx * ny * esize; }
+    int64_t ring_ld() const { return nx * ny * (esize / 4); }  // plane stride of a ring, in floats
     int64_t store_plane_bytes(int f) const;  // host-store bytes per plane of field f (compressed or raw)
     int64_t store_bytes(int f) const;
 

@@ -1,6 +1,6 @@
-"""Batched uneven heat domains (by default one persistent kernel per run,
-items of every domain, tile and group taken from a device queue; or one
-launch per k steps for all domains, all launches in one graph launch;
+"""Batched uneven heat domains (by default one launch per k steps for all
+domains, all launches in one graph launch; or one persistent kernel per run,
+items of every domain, tile and group taken from a device queue;
 autotuned tiles and temporal-blocking depth): every domain equals the
 oracle's FP32 steps bit for bit (small domains, every depth, step counts that
 are not multiples of the depth, odd and even numbers of groups), both modes
@@ -88,8 +88,8 @@ def test_full_size_batched_workload(tmp_path):
     b2 = api.HeatBatch(ref, tune=False, tune_cache=str(tmp_path / "tune.json"))
     b2.run_per_domain(200)
     b3 = api.HeatBatch(ref2, tune=False, tune_cache=str(tmp_path / "tune.json"))
-    b3.set_persistent(False)
-    b3.run(200)
+    b3.set_persistent(True)
+    b3.run(200, check=True)
     torch.cuda.synchronize()
     for f, g, h in zip(fields, ref, ref2):
         assert torch.equal(f, g)

@@ -369,22 +369,32 @@ def shift(a, d, axis):
     return out
 
 
+C0X3_64 = -205.0 / 24.0
+CM_64 = [None, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0]
+
+
 def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
+    """FP32 arithmetic and format, or FP64 for an fp64 plan."""
     g = Geometry(p)
     nz, ny, nx = p.shape
     rates = list(p.cfg.rate)
-    rings = [np.zeros((w, ny, nx), np.float32) for w in g.W]
+    f64 = bool(p.cfg.flags & L.OOCS_PLAN_FP64)
+    dt = np.float64 if f64 else np.float32
+    enc = O.codec64_encode if f64 else O.codec_encode
+    dec = O.codec64_decode if f64 else O.codec_decode
+    c0x3, cm, two = (C0X3_64, CM_64, 2.0) if f64 else (C0X3, CM, np.float32(2.0))
+    rings = [np.zeros((w, ny, nx), dt) for w in g.W]
     stage_in, stage_out = {}, {}
     sx, sy, sz = p.cfg.src_x, p.cfg.src_y, p.cfg.src_z
     layer_words = lambda rate: (nx // 4) * (ny // 4) * rate
 
     def plane(R, z):
         if z < 0 or z >= nz:
-            return np.zeros((ny, nx), np.float32)
+            return np.zeros((ny, nx), dt)
         return rings[R][z % g.W[R]]
 
     if p.cfg.flags & L.OOCS_PLAN_RESIDENT_RO:  # decoded once, before the residencies
-        rings[g.ro][:nz] = from_store(store[2], p.shape, rates[2])
+        rings[g.ro][:nz] = dec(store[2], p.shape, rates[2]) if rates[2] else store[2]
     retained = {}  # snake: (field, plane) -> that plane's share of the retained block (words of its layer, or raw)
 
     done, rnd = 0, 0
@@ -398,7 +408,7 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
                 f, rate = o["field"], rates[o["field"]]
                 if rate:
                     data = np.concatenate([retained[(f, z)] for z in range(z0, z1, 4)])
-                    planes = O.codec_decode(data, (z1 - z0, ny, nx), rate)
+                    planes = dec(data, (z1 - z0, ny, nx), rate)
                 else:
                     planes = np.stack([retained[(f, z)] for z in range(z0, z1)])
                 for z in range(z0, z1):
@@ -408,7 +418,7 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
                 f, rate = o["field"], rates[o["field"]]
                 planes = np.stack([plane(o["level"], z) for z in range(z0, z1)])
                 if rate:
-                    words = O.codec_encode(planes, rate)
+                    words = enc(planes, rate)
                     lw = layer_words(rate)
                     for q, z in enumerate(range(z0, z1, 4)):
                         retained[(f, z)] = words[q * lw:(q + 1) * lw]
@@ -425,7 +435,7 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
             elif K == L.OP_DECODE:
                 f, rate = o["field"], rates[o["field"]]
                 data = stage_in[(f, o["slot"])]
-                planes = O.codec_decode(data, (z1 - z0, ny, nx), rate) if rate else data
+                planes = dec(data, (z1 - z0, ny, nx), rate) if rate else data
                 for z in range(z0, z1):
                     rings[o["level"]][z % g.W[o["level"]]] = planes[z - z0]
             elif K == L.OP_LEVEL and o["slot"] > 1:
@@ -458,20 +468,20 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
                         s = s - np.float32(6.0) * c
                         v = c + alpha * s
                     else:
-                        acc = C0X3 * c
+                        acc = c0x3 * c
                         for m in range(1, 5):
                             sm = (shift(c, m, 1) + shift(c, -m, 1)) + (shift(c, m, 0) + shift(c, -m, 0))
                             sm = sm + (plane(lv - 1, z + m) + plane(lv - 1, z - m))
-                            acc = acc + CM[m] * sm
-                        v = (np.float32(2.0) * c - plane(lv - 2, z)) + plane(g.ro, z) * acc
+                            acc = acc + cm[m] * sm
+                        v = (two * c - plane(lv - 2, z)) + plane(g.ro, z) * acc
                         if src_amps is not None and z == sz:
                             v = v.copy()
-                            v[sy, sx] = v[sy, sx] + src_amps[done + lv - g.nin]
+                            v[sy, sx] = v[sy, sx] + dt(src_amps[done + lv - g.nin])
                     rings[lv][z % g.W[lv]] = v
             elif K == L.OP_ENCODE:
                 f, rate = o["field"], rates[o["field"]]
                 planes = np.stack([plane(o["level"], z) for z in range(z0, z1)])
-                stage_out[(f, o["slot"])] = O.codec_encode(planes, rate) if rate else planes.copy()
+                stage_out[(f, o["slot"])] = enc(planes, rate) if rate else planes.copy()
             elif K in (L.OP_D2H, L.OP_STORE):
                 f, rate = o["field"], rates[o["field"]]
                 data = stage_out[(f, o["slot"])]
@@ -691,3 +701,73 @@ def test_snake_needs_copy_engines_shared_levels_and_two_slabs():
         plan((48, 12, 16), HEAT7, 1, 4, [8], 2 * MiB, snake=True)
     with pytest.raises(L.OocsError):
         plan((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB).schedule(4, L.OOCS_SCHED_MIRROR)
+
+
+# ---------------------------------------------------------------------------
+# FP64 plans (the paper's precision, Sec. VI): the same schedules over planes
+# of doubles and the FP64 block format
+# ---------------------------------------------------------------------------
+
+def to_store64(field, rate):
+    return O.codec64_encode(field, rate) if rate else field.astype(np.float64).copy()
+
+
+def from_store64(s, shape, rate):
+    return O.codec64_decode(s, shape, rate) if rate else s
+
+
+@pytest.mark.parametrize("rates,k,steps,kw", [
+    ([0, 0, 0], 3, 7, {}), ([24, 32, 24], 4, 9, {}), ([32, 0, 24], 4, 9, {"block_restart": True}),
+    ([40, 40, 40], 4, 11, {"snake": True}), ([24, 24, 24], 4, 9, {"snake": True, "resident_ro": True}),
+    ([68, 12, 0], 2, 5, {}),
+])
+def test_fp64_wave_schedule_computes_the_fp64_replay(rates, k, steps, kw):
+    shape = (64, 12, 12)
+    rng = np.random.default_rng(k + len(kw))
+    p0 = rng.standard_normal(shape)
+    pm0 = rng.standard_normal(shape)
+    w = 0.02 + 0.1 * rng.random(shape)
+    amps = rng.standard_normal(steps).astype(np.float32)  # float amplitudes, exact in double
+    src = (5, 6, 20)
+    p = plan(shape, WAVE25, 2, k, rates, 8 * MiB, src_cell=src, fp64=True, **kw)
+    store = [to_store64(p0, rates[0]), to_store64(pm0, rates[1]), to_store64(w, rates[2])]
+    execute(p, store, steps, amps)
+    idx = src[0] + shape[2] * (src[1] + shape[1] * src[2])
+    wp, wpm, _ = O.replay_wave64(p0, pm0, w, steps, k, src=(amps.astype(np.float64), idx), rate_p=rates[0],
+                                 rate_pm=rates[1], rate_w=rates[2])
+    assert np.array_equal(from_store64(store[0], shape, rates[0]), wp)
+    assert np.array_equal(from_store64(store[1], shape, rates[1]), wpm)
+
+
+def test_fp64_plan_sizes():
+    """Planes and raw stores hold 8-byte values; a compressed store holds
+    rate bits per value whatever the precision; the device rings double."""
+    shape = (64, 16, 16)
+    p32 = plan(shape, WAVE25, 2, 4, [0, 0, 0], 64 * MiB)
+    p64 = plan(shape, WAVE25, 2, 4, [0, 0, 0], 64 * MiB, fp64=True)
+    assert p64.info["plane_bytes"] == 8 * 16 * 16 == 2 * p32.info["plane_bytes"]
+    assert p64.store_bytes(0) == 8 * 64 * 16 * 16
+    assert p64.info["ring_planes"] == p32.info["ring_planes"]
+    assert p64.info["arena_needed"] > p32.info["arena_needed"]
+    c64 = plan(shape, WAVE25, 2, 4, [24, 68, 32], 64 * MiB, fp64=True)
+    assert [c64.store_bytes(f) for f in range(3)] == [64 * 16 * 16 * r // 8 for r in (24, 68, 32)]
+    race_check(c64, 9)
+    race_check(plan(shape, WAVE25, 2, 4, [24, 24, 24], 64 * MiB, fp64=True, snake=True), 13)
+
+
+def test_fp64_plan_errors():
+    shape = (64, 16, 16)
+    for rates in ([69, 0, 0], [-1, 0, 0]):
+        with pytest.raises(L.OocsError) as e:
+            plan(shape, WAVE25, 2, 4, rates, 64 * MiB, fp64=True)
+        assert e.value.code == L.OOCS_E_RATE
+    with pytest.raises(L.OocsError) as e:  # FP32 stays capped at 34
+        plan(shape, WAVE25, 2, 4, [35, 0, 0], 64 * MiB)
+    assert e.value.code == L.OOCS_E_RATE
+    for kw in ({"midpoint": True}, {"kernel_transfers": True}, {"kernel_stores": True}):
+        with pytest.raises(L.OocsError) as e:
+            plan(shape, WAVE25, 2, 4, [24, 24, 24], 64 * MiB, fp64=True, **kw)
+        assert e.value.code == L.OOCS_E_ARG
+    with pytest.raises(L.OocsError) as e:
+        plan((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, fp64=True)
+    assert e.value.code == L.OOCS_E_ARG
