@@ -335,6 +335,85 @@ def wave_full_run(api, torch, inputs, wi, rates, deadline_s):
 
 
 # ---------------------------------------------------------------------------
+# FP64 replica of the paper's experiment (Sec. VI-A): FP64 fields, the FP64
+# format at 24 and 32 bits per value, the paper's decomposition (8 blocks of
+# 144 planes, k = 12)
+# ---------------------------------------------------------------------------
+
+FP64_SHAPE = (1152, 1152, 1152)  # the interior of the paper's (1152 + 2*4)^3 grid; outside cells are zero
+FP64_SLABS = 8
+FP64_K = 12
+FP64_CAP = 24 << 30              # device arena: ~0.7 of the 37 GB of host data, as 32 GB was of 46 GB
+FP64_CODES = (("code1", [0, 0, 0]), ("code2", [0, 32, 0]), ("code3", [0, 0, 32]), ("code4", [0, 24, 24]),
+              ("all24", [24, 24, 24]))
+
+
+def fp64_replica(api, torch, inputs, wi, state, rounds=2):
+    """The paper's four codes in FP64 (1 = no compression, 2 = p(n-1) at 32
+    bits/value, 3 = the read-only field at 32, 4 = both at 24; and every
+    field at 24) on the 1152^3 grid. Synthetic data: the 1024^3 FP32 state
+    at step WAVE_START placed in the grid's low corner, cast to double, and
+    the layered model on the whole grid in double. One untimed round, then
+    `rounds` timed rounds per code; snake sweeps."""
+    import numpy as np
+
+    nz, ny, nx = FP64_SHAPE
+    n0 = WAVE_SHAPE[0]
+    p = np.zeros(FP64_SHAPE)
+    p[:n0, :n0, :n0] = state[0]
+    pm = np.zeros(FP64_SHAPE)
+    pm[:n0, :n0, :n0] = state[1]
+    v = inputs.layered_velocity((nz, 4, 4), seed=1)[:, 0, 0].astype(np.float64)
+    w = np.empty(FP64_SHAPE)
+    w[...] = ((v * wi.dt / 10.0) ** 2)[:, None, None]
+    cell = inputs.source_cell(FP64_SHAPE)
+    if hasattr(torch._C, "_host_emptyCache"):
+        torch._C._host_emptyCache()  # pinned blocks cached by earlier sections
+    raw = nx * ny * nz * 8
+    bufs = [torch.empty(raw, dtype=torch.uint8, pin_memory=True) for _ in range(3)]
+    out = {"grid": list(FP64_SHAPE), "nslabs": FP64_SLABS, "k": FP64_K, "device_cap_bytes": FP64_CAP,
+           "data": f"1024^3 FP32 wavefield of step {WAVE_START} in the low corner, cast to double; layered model "
+                   "in double", "codes": {}}
+    cells = float(nx * ny * nz) * FP64_K * rounds
+    for name, rates in FP64_CODES:
+        plan = api.OutOfCorePlan(FP64_SHAPE, api.WAVE25, FP64_SLABS, FP64_K, rates, FP64_CAP, src_cell=cell,
+                                 fp64=True, snake=True)
+        st = [bufs[f][:plan.store_bytes(f)] for f in range(3)]
+        for f, a in enumerate((p, pm, w)):
+            plan.put(f, a, st[f])
+        t = WAVE_START
+        plan.run(st, FP64_K, src_amps=wi.amps[t:t + FP64_K])
+        t += FP64_K
+        n = FP64_K * rounds
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = plan.run(st, n, src_amps=wi.amps[t:t + n])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["codes"][name] = {
+            "rates_bits_per_double": rates,
+            "gcells_per_s": cells / dt / 1e9,
+            "ms_per_round": dt / rounds * 1e3,
+            "h2d_GBps": s.h2d_bytes / dt / 1e9,
+            "d2h_GBps": s.d2h_bytes / dt / 1e9,
+            "h2d_bytes_per_round": s.h2d_bytes // rounds,
+            "d2h_bytes_per_round": s.d2h_bytes // rounds,
+            "group_planes": plan.info["group"],
+            "arena_used_bytes": s.arena_bytes,
+        }
+        log(f"FP64 {name}: {out['codes'][name]['gcells_per_s']:.1f} GCell-updates/s, "
+            f"{out['codes'][name]['ms_per_round']:.0f} ms/round")
+        plan.close()
+    base = out["codes"]["code1"]["gcells_per_s"]
+    out["speedup_vs_code1"] = {k: v["gcells_per_s"] / base for k, v in out["codes"].items() if k != "code1"}
+    out["paper_context"] = "V100-PCIe 32 GB, 4 x 1160^3 doubles: code 2 1.16x, code 3 1.18x, code 4 1.20x (Sec. VI-A)"
+    del bufs, p, pm, w
+    if hasattr(torch._C, "_host_emptyCache"):
+        torch._C._host_emptyCache()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # 512^3 heat
 # ---------------------------------------------------------------------------
 
@@ -614,6 +693,8 @@ def main():
     ap.add_argument("--deadline", type=float, default=450.0,
                     help="seconds after start beyond which the 4,320-step runs stop (the line is still printed)")
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 replica of the paper's codes")
+    ap.add_argument("--fp64-only", action="store_true", help="run the FP64 replica only (for profiler runs)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -639,6 +720,9 @@ def main():
     if args.headline_only:
         print(json.dumps({"headline": _rounded(head)}), flush=True)
         return
+    if args.fp64_only:
+        print(json.dumps({"fp64_replica": _rounded(fp64_replica(api, torch, inputs, wi, state))}), flush=True)
+        return
     variants = {f"rate{HEADLINE_RATE}": head}
     vr = max(2, min(args.steps, 8))
     for r in WAVE_RATES:
@@ -659,6 +743,10 @@ def main():
         codes[f"code{code}"] = wave_window(api, torch, wi, state, rates, vr, 1)
         log(f"code {code}: {codes[f'code{code}']['gcells_per_s']:.1f} GCell-updates/s")
     codes["code1"] = {"same_as": "uncompressed"}
+    fp64 = None
+    if not args.no_fp64:
+        log("FP64 replica (1152^3, the paper's codes)")
+        fp64 = fp64_replica(api, torch, inputs, wi, state)
     # one-way sweeps (every residency upward, every block through the host
     # link): the schedule without the snake's retained block
     oneway = {}
@@ -736,6 +824,7 @@ def main():
         "speedup_vs_uncompressed": round(head["gcells_per_s"] / raw["gcells_per_s"], 3),
         "variants": _rounded(variants),
         "paper_codes": _rounded(codes),
+        "fp64_replica": _rounded(fp64) if fp64 else None,
         "block_restart": _rounded(restart),
         "one_way_sweeps": _rounded(oneway),
         "breakdown_ms_per_round": _rounded(breakdown),

@@ -164,6 +164,7 @@ def test_persistent_wait_gives_up_and_is_reported():
     u0 = [inputs.heat_uniform(s, seed=80 + i) for i, s in enumerate(shapes)]
     fields = [torch.from_numpy(u).to(DEV) for u in u0]
     b = api.HeatBatch(fields, alpha=0.1, tune=False, depth=4)
+    b.set_persistent(True)
     b.set_wait_limit(1000, never_satisfied=True)
     b.run(8)
     with pytest.raises(L.OocsError) as e:
