@@ -460,7 +460,11 @@ int oocs_plan_set_host_waits(oocs_plan* plan, int on);
  * engines of their own). The SDMA path applies only when every written-back
  * store is pinned host memory the runtime knows and the engine is available
  * (oocs_plan_sdma_available); otherwise hipMemcpyAsync is used. Graph issue,
- * stream waits and kernel-driven transfers never use it. Same results. */
+ * stream waits and kernel-driven transfers never use it. Same results.
+ * on >= 2: every copy is split into `on` parts, each on an SDMA engine of
+ * its own (as many as the runtime reports available for the direction, up
+ * to `on`; one engine chosen by the runtime if it reports fewer than two);
+ * at most 16. */
 int oocs_plan_set_sdma(oocs_plan* plan, int on);
 
 /* 1 if the plan found the HSA runtime and the GPU agent of its arena, else 0. */
@@ -471,7 +475,8 @@ int oocs_plan_sdma_available(const oocs_plan* plan);
  * device d_a and from device d_b to pinned host h_out in chunks of `chunk`
  * bytes, with the engines the pipeline uses: hipMemcpyAsync on one stream
  * host to device; device to host on an SDMA engine through HSA if `sdma` and
- * available, else hipMemcpyAsync on a second stream. Each direction alone,
+ * available (sdma >= 2: each chunk split over that many engines, as in
+ * oocs_plan_set_sdma), else hipMemcpyAsync on a second stream. Each direction alone,
  * then both at once; one untimed pass, then `reps` timed ones (host wall
  * clock). out[4]: GB/s host to device alone, device to host alone, each way
  * with both at once, and 1.0 if the SDMA path was used (else 0.0). All four

@@ -278,17 +278,18 @@ HEAT7 = L.OOCS_HEAT7
 WAVE25 = L.OOCS_WAVE25
 
 
-def link_probe(nbytes: int = 256 << 20, chunk: int = 4 << 20, reps: int = 3, sdma: bool = True) -> dict:
+def link_probe(nbytes: int = 256 << 20, chunk: int = 4 << 20, reps: int = 3, sdma: int = 1) -> dict:
     """Host-link bandwidth with pinned buffers, moved with the pipeline's
     engines (host to device by hipMemcpyAsync, device to host on an SDMA
-    engine where available): each direction alone and both at once, GB/s."""
+    engine where available; sdma >= 2: each chunk split over that many
+    engines): each direction alone and both at once, GB/s."""
     h_in = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
     h_out = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
     d_a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     d_b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     out = (C.c_double * 4)()
     L.check(L.lib().oocs_link_probe(d_a.data_ptr(), d_b.data_ptr(), h_in.data_ptr(), h_out.data_ptr(), nbytes, chunk,
-                                    reps, 1 if sdma else 0, out))
+                                    reps, int(sdma), out))
     return {"h2d_GBps": out[0], "d2h_GBps": out[1], "bidir_GBps_each": out[2],
             "d2h_engine": "sdma" if out[3] else "hipMemcpyAsync", "bytes": nbytes, "chunk_bytes": chunk}
 
@@ -486,10 +487,11 @@ class OutOfCorePlan:
         default) or make the stream wait on them (False)."""
         L.check(L.lib().oocs_plan_set_host_waits(self._h, 1 if on else 0))
 
-    def set_sdma(self, on: bool):
+    def set_sdma(self, on):
         """Device-to-host copies on an SDMA engine through the HSA runtime
-        (True, default, where available) or with hipMemcpyAsync (False)."""
-        L.check(L.lib().oocs_plan_set_sdma(self._h, 1 if on else 0))
+        (True or 1, default, where available), split over `on` engines (an
+        int >= 2), or with hipMemcpyAsync (False or 0)."""
+        L.check(L.lib().oocs_plan_set_sdma(self._h, int(on)))
 
     @property
     def sdma_available(self) -> bool:

@@ -16,9 +16,11 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "codec_dev.hpp"
 #include "internal.hpp"
+#include "stencil_dev.hpp"
 
 namespace oocs {
 namespace codec64 {
@@ -380,40 +382,34 @@ hipError_t launch_codec64_stages(bool encode, const double* blocks, const uint64
 }  // namespace oocs
 
 // ---------------------------------------------------------------------------
-// FP64 wave step (the paper's precision): one thread per cell, x fastest;
-// the same formula and operation order as the FP32 level, in double:
+// FP64 wave step (the paper's precision) on dense fields: the pipeline's
+// LDS-staged wave tile in double, over the whole grid as one job whose
+// "rings" are the dense fields (ring size nz: no wrap-around). The formula
+// and operation order are the FP32 level's, in double:
 //   acc = 3 c0 p;  acc = acc + c_m * (((x+m + x-m) + (y+m + y-m)) + (z+m + z-m)),  m = 1..4
 //   p(n+1) = (2 p - p(n-1)) + w * acc   (+ the source amplitude at its cell)
-// p(n+1) is written over p(n-1) (each thread reads and writes only its own
-// cell of that array). Cells outside the grid are zero.
+// p(n+1) is written over p(n-1): a thread reads p(n-1) only at its own
+// cells, just before writing them. The source amplitude (a double) is added
+// by a one-thread launch after the step: the same single addition.
 // ---------------------------------------------------------------------------
 namespace oocs {
 namespace codec64 {
 
-__global__ void __launch_bounds__(kBlockThreads)
-wave_f64_kernel(const double* __restrict__ p, double* pm, const double* __restrict__ w, int nx, int ny, int nz,
-                int64_t src_cell, double amp)
+extern __shared__ double dyn_lds64[];  // wave tiles: two staged planes
+
+// FP64 tiles are 64 x 8 cells (2 cells per thread). With the FP32 tile's
+// 16 rows a thread keeps 4 cells' 9-plane columns of doubles and the kernel
+// needs 186 VGPRs (2 waves per SIMD); 8 rows: 116 (4 waves per SIMD).
+constexpr int kTileY64 = 8;
+
+__global__ void __launch_bounds__(kBlockThreads) wave_f64_kernel(Job j, int nx, int ny, int nz)
 {
-    const int64_t plane = (int64_t)nx * ny;
-    const int64_t c = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
-    if (c >= plane * nz) return;
-    const int i = (int)(c % nx), j = (int)((c / nx) % ny), l = (int)(c / plane);
-    const double C0X3 = -205.0 / 24.0;
-    const double CM[5] = {0.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
-    auto at = [&](int ii, int jj, int ll) -> double {
-        return (ii < 0 || ii >= nx || jj < 0 || jj >= ny || ll < 0 || ll >= nz) ? 0.0 : p[ll * plane + (int64_t)jj * nx + ii];
-    };
-    const double pc = p[c];
-    double acc = C0X3 * pc;
-#pragma unroll
-    for (int m = 1; m <= 4; ++m) {
-        double sm = (at(i + m, j, l) + at(i - m, j, l)) + (at(i, j + m, l) + at(i, j - m, l));
-        sm = sm + (at(i, j, l + m) + at(i, j, l - m));
-        acc = acc + CM[m] * sm;
-    }
-    double v = (2.0 * pc - pm[c]) + w[c] * acc;
-    if (c == src_cell) v = v + amp;
-    pm[c] = v;
+    stencil::wave_tile<double, kTileY64>(j, nx, ny, nz, -1, -1, -1, nullptr, nullptr, (int)blockIdx.x, dyn_lds64);
+}
+
+__global__ void add_at_kernel(double* f, int64_t cell, double v)
+{
+    if (threadIdx.x == 0) f[cell] = f[cell] + v;
 }
 
 }  // namespace codec64
@@ -421,10 +417,24 @@ wave_f64_kernel(const double* __restrict__ p, double* pm, const double* __restri
 hipError_t launch_wave_f64(const double* p, double* pm, const double* w, int64_t nx, int64_t ny, int64_t nz,
                            int64_t src_cell, double amp, hipStream_t stream)
 {
-    const int64_t n = nx * ny * nz;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(codec64::wave_f64_kernel, dim3((unsigned)((n + kBlockThreads - 1) / kBlockThreads)),
-                       dim3(kBlockThreads), 0, stream, p, pm, w, (int)nx, (int)ny, (int)nz, src_cell, amp);
+    if (nx * ny * nz == 0) return hipSuccess;
+    Job j;
+    memset(&j, 0, sizeof j);
+    j.kind = JOB_WAVE;
+    j.z0 = 0;
+    j.z1 = (int32_t)nz;
+    j.f64 = 1;
+    const int64_t ld = 2 * nx * ny;  // a plane of doubles, in floats
+    j.src = Ring{reinterpret_cast<float*>(const_cast<double*>(p)), nz, ld};
+    j.src2 = Ring{reinterpret_cast<float*>(pm), nz, ld};
+    j.ro = Ring{reinterpret_cast<float*>(const_cast<double*>(w)), nz, ld};
+    j.dst = j.src2;
+    const int64_t tiles = ((nx + 63) / 64) * ((ny + codec64::kTileY64 - 1) / codec64::kTileY64);
+    const int64_t grid = tiles * ((nz + kZChunk - 1) / kZChunk);
+    const size_t lds = stencil::wave_tile_lds<double, codec64::kTileY64>();
+    hipLaunchKernelGGL(codec64::wave_f64_kernel, dim3((unsigned)grid), dim3(kBlockThreads), lds, stream, j, (int)nx,
+                       (int)ny, (int)nz);
+    if (src_cell >= 0) hipLaunchKernelGGL(codec64::add_at_kernel, dim3(1), dim3(64), 0, stream, pm, src_cell, amp);
     return hipGetLastError();
 }
 
@@ -442,39 +452,6 @@ namespace codec64 {
 constexpr int kCopy4PerThread = 4;
 
 __device__ inline double* plane64(const Ring& r, int64_t z) { return reinterpret_cast<double*>(ring_plane(r, z)); }
-
-// One FP64 wave time level at one cell per thread, planes [z0, z1): the
-// arithmetic of wave_f64_kernel, reading p(n) from src (neighbours outside
-// the grid are zero), p(n-1) from src2 and w from ro, writing p(n+1) to dst.
-__device__ inline void wave_level_job(const Job& j, const LaunchParams& p, int wg)
-{
-    const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int64_t plane = (int64_t)nx * ny;
-    const int64_t per_plane = (plane + kBlockThreads - 1) / kBlockThreads;
-    const int z = j.z0 + (int)(wg / per_plane);
-    const int64_t c = (wg % per_plane) * kBlockThreads + threadIdx.x;
-    if (z >= j.z1 || c >= plane) return;
-    const int x = (int)(c % nx), y = (int)(c / nx);
-    const double C0X3 = -205.0 / 24.0;
-    const double CM[5] = {0.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
-    const double* pz = plane64(j.src, z);
-    auto in_xy = [&](int xx, int yy) -> double {
-        return (xx < 0 || xx >= nx || yy < 0 || yy >= ny) ? 0.0 : pz[(int64_t)yy * nx + xx];
-    };
-    auto in_z = [&](int zz) -> double { return (zz < 0 || zz >= nz) ? 0.0 : plane64(j.src, zz)[c]; };
-    const double pc = pz[c];
-    double acc = C0X3 * pc;
-#pragma unroll
-    for (int m = 1; m <= 4; ++m) {
-        double sm = (in_xy(x + m, y) + in_xy(x - m, y)) + (in_xy(x, y + m) + in_xy(x, y - m));
-        sm = sm + (in_z(z + m) + in_z(z - m));
-        acc = acc + CM[m] * sm;
-    }
-    double v = (2.0 * pc - plane64(j.src2, z)[c]) + plane64(j.ro, z)[c] * acc;
-    if (j.has_src && x == p.src_x && y == p.src_y && z == p.src_z)
-        v = v + (double)(p.src_table ? p.src_table[*p.step_ctr + j.src_off] : j.amp);
-    plane64(j.dst, z)[c] = v;
-}
 
 // One wave per block (the field kernel's mapping), blocks of the job's layers.
 __device__ inline void ring_codec_job(const Job& j, int nx, int ny, int wg, bool encode, uint64_t* words)
@@ -524,6 +501,8 @@ __device__ inline void ring_copy_job(const Job& j, int nx, int ny, int wg, bool 
     }
 }
 
+// Wave levels are the FP32 pipeline's LDS-staged tile in double (the same
+// operation order as the FP64 step above).
 __global__ void __launch_bounds__(kBlockThreads) fused64_kernel(LaunchParams p)
 {
     __shared__ uint64_t buf[kWaves][kMaxRate];
@@ -533,7 +512,10 @@ __global__ void __launch_bounds__(kBlockThreads) fused64_kernel(LaunchParams p)
     const Job& j = p.jobs[jdx];
     const int local = wg - p.wg_begin[jdx];
     switch (j.kind) {
-    case JOB_WAVE: wave_level_job(j, p, local); break;
+    case JOB_WAVE:
+        stencil::wave_tile<double, kTileY64>(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr,
+                                             local, dyn_lds64);
+        break;
     case JOB_DECODE: ring_codec_job(j, p.nx, p.ny, local, false, buf[threadIdx.x >> 6]); break;
     case JOB_ENCODE: ring_codec_job(j, p.nx, p.ny, local, true, buf[threadIdx.x >> 6]); break;
     case JOB_COPY_IN: ring_copy_job(j, p.nx, p.ny, local, true); break;
@@ -548,7 +530,10 @@ static int32_t job_workgroups64(const Job& j, int nx, int ny)
     if (planes <= 0) return 0;
     const int64_t plane = (int64_t)nx * ny;
     switch (j.kind) {
-    case JOB_WAVE: return (int32_t)(((plane + kBlockThreads - 1) / kBlockThreads) * planes);
+    case JOB_WAVE: {
+        const int64_t tiles = (int64_t)((nx + 63) / 64) * ((ny + kTileY64 - 1) / kTileY64);
+        return (int32_t)(tiles * ((planes + kZChunk - 1) / kZChunk));
+    }
     case JOB_DECODE:
     case JOB_ENCODE: return (int32_t)(((planes + 3) / 4 * (nx / 4) * (ny / 4) + kWaves - 1) / kWaves);
     case JOB_COPY_IN:
@@ -580,9 +565,11 @@ bool prepare_jobs_f64(LaunchParams& p, const void** func, unsigned* grid, size_t
     }
     p.wg_begin[p.njobs] = total;
     if (total == 0) return false;
+    bool wave = false;
+    for (int i = 0; i < n; ++i) wave = wave || p.jobs[i].kind == JOB_WAVE;
     *func = reinterpret_cast<const void*>(&codec64::fused64_kernel);
     *grid = (unsigned)total;
-    *lds = 0;
+    *lds = wave ? stencil::wave_tile_lds<double, codec64::kTileY64>() : 0;
     return true;
 }
 
@@ -592,7 +579,7 @@ hipError_t launch_jobs_f64(LaunchParams& p, hipStream_t stream)
     unsigned grid;
     size_t lds;
     if (!prepare_jobs_f64(p, &func, &grid, &lds)) return hipSuccess;
-    hipLaunchKernelGGL(codec64::fused64_kernel, dim3(grid), dim3(kBlockThreads), 0, stream, p);
+    hipLaunchKernelGGL(codec64::fused64_kernel, dim3(grid), dim3(kBlockThreads), lds, stream, p);
     return hipGetLastError();
 }
 

@@ -639,6 +639,12 @@ int oocs_plan_set_sdma(oocs_plan* pl, int on)
 {
     if (!pl) return fail(OOCS_E_ARG, "null pointer");
     if (!pl->runnable) return fail(OOCS_E_STATE, "planning-only plan");
+    if (on < 0 || on > 16) return fail(OOCS_E_ARG, "sdma must be 0, 1 or an engine count up to 16");
+    if (on > 0 && pl->sdma.ready()) {
+        const int rc = pl->sdma.drain();  // copies in flight were split the old way
+        if (rc != OOCS_OK) return rc;
+        (void)pl->sdma.set_engines(on);
+    }
     pl->sdma_on = on != 0;
     return OOCS_OK;
 }
@@ -657,7 +663,9 @@ int oocs_link_probe(void* d_a, void* d_b, void* h_in, void* h_out, size_t bytes,
     oocs::SdmaCopier cp;
     std::string why;
     uint64_t agent = 0;
+    if (sdma < 0 || sdma > 16) return fail(OOCS_E_ARG, "sdma must be 0, 1 or an engine count up to 16");
     const bool use_sdma = sdma && cp.init(d_b, &why) && cp.host_agent(h_out, &agent);
+    if (use_sdma) (void)cp.set_engines(sdma);
     struct Streams {
         hipStream_t s[2] = {nullptr, nullptr};
         ~Streams()

@@ -7,6 +7,7 @@
 
 #include <dlfcn.h>
 
+#include <algorithm>
 #include <chrono>
 
 #include <hsa/hsa.h>
@@ -27,6 +28,9 @@ struct HsaApi {
     decltype(&hsa_signal_load_scacquire) signal_load = nullptr;
     decltype(&hsa_signal_store_relaxed) signal_store = nullptr;
     decltype(&hsa_amd_memory_async_copy) async_copy = nullptr;
+    // copies on chosen engines (optional: only split copies need them)
+    decltype(&hsa_amd_memory_async_copy_on_engine) async_copy_on_engine = nullptr;
+    decltype(&hsa_amd_memory_copy_engine_status) engine_status = nullptr;
     decltype(&hsa_amd_pointer_info) pointer_info = nullptr;
     // copy timing (optional: only the breakdown mode needs them)
     decltype(&hsa_amd_profiling_async_copy_enable) copy_prof_enable = nullptr;
@@ -49,6 +53,9 @@ const HsaApi& api()
         r.signal_store = reinterpret_cast<decltype(r.signal_store)>(dlsym(h, "hsa_signal_store_relaxed"));
         r.async_copy = reinterpret_cast<decltype(r.async_copy)>(dlsym(h, "hsa_amd_memory_async_copy"));
         r.pointer_info = reinterpret_cast<decltype(r.pointer_info)>(dlsym(h, "hsa_amd_pointer_info"));
+        r.async_copy_on_engine =
+            reinterpret_cast<decltype(r.async_copy_on_engine)>(dlsym(h, "hsa_amd_memory_async_copy_on_engine"));
+        r.engine_status = reinterpret_cast<decltype(r.engine_status)>(dlsym(h, "hsa_amd_memory_copy_engine_status"));
         r.copy_prof_enable =
             reinterpret_cast<decltype(r.copy_prof_enable)>(dlsym(h, "hsa_amd_profiling_async_copy_enable"));
         r.copy_time = reinterpret_cast<decltype(r.copy_time)>(dlsym(h, "hsa_amd_profiling_get_async_copy_time"));
@@ -180,22 +187,61 @@ int SdmaCopier::wait(int64_t t)
     }
 }
 
+int SdmaCopier::set_engines(int n)
+{
+    if (n < 1 || n > 16) return fail(OOCS_E_ARG, "engine count must be in [1, 16]");
+    engines_ = n;
+    mask_agent_ = 0;  // looked up again at the next copy
+    return OOCS_OK;
+}
+
+// The engines a split copy to CPU agent `agent` uses: the first engines_
+// of those the runtime reports available for this direction.
+int SdmaCopier::engines_for(uint64_t agent)
+{
+    if (engines_ <= 1) return 1;
+    if (mask_agent_ == agent) return (int)ids_.size();
+    const HsaApi& a = api();
+    ids_.clear();
+    uint32_t mask = 0;
+    if (a.async_copy_on_engine && a.engine_status &&
+        a.engine_status(hsa_agent_t{agent}, hsa_agent_t{gpu_}, &mask) == HSA_STATUS_SUCCESS)
+        for (int b = 0; b < 16 && (int)ids_.size() < engines_; ++b)
+            if (mask & (1u << b)) ids_.push_back(1u << b);
+    if (ids_.size() < 2) ids_.clear();  // fewer than two: the runtime's own choice
+    mask_agent_ = agent;
+    return ids_.empty() ? 1 : (int)ids_.size();
+}
+
 int SdmaCopier::copy(void* dst, uint64_t agent, const void* src, size_t bytes)
 {
     if (!ready_) return fail(OOCS_E_STATE, "SDMA copier not initialised");
-    if (issued_ - done_ >= kRing) {
-        const int rc = wait(issued_ - kRing + 1);
-        if (rc != OOCS_OK) return rc;
-    }
     const HsaApi& a = api();
-    const hsa_signal_t s{sig_[issued_ % kRing]};
-    a.signal_store(s, 1);
-    const hsa_status_t st = a.async_copy(dst, hsa_agent_t{agent}, src, hsa_agent_t{gpu_}, bytes, 0, nullptr, s);
-    if (st != HSA_STATUS_SUCCESS) {
-        a.signal_store(s, 0);
-        return fail(OOCS_E_HIP, "hsa_amd_memory_async_copy failed (status " + std::to_string((int)st) + ")");
+    const int parts = engines_for(agent);
+    // split on 4 KiB boundaries; every part is a copy of its own
+    const size_t step = ((bytes + (size_t)parts - 1) / (size_t)parts + 4095) & ~(size_t)4095;
+    for (int q = 0; q < parts; ++q) {
+        const size_t off = (size_t)q * step;
+        if (off >= bytes && q > 0) break;
+        const size_t len = parts == 1 ? bytes : std::min(step, bytes - off);
+        if (issued_ - done_ >= kRing) {
+            const int rc = wait(issued_ - kRing + 1);
+            if (rc != OOCS_OK) return rc;
+        }
+        const hsa_signal_t s{sig_[issued_ % kRing]};
+        a.signal_store(s, 1);
+        void* d = static_cast<char*>(dst) + off;
+        const void* sp = static_cast<const char*>(src) + off;
+        const hsa_status_t st =
+            parts == 1 ? a.async_copy(d, hsa_agent_t{agent}, sp, hsa_agent_t{gpu_}, len, 0, nullptr, s)
+                       : a.async_copy_on_engine(d, hsa_agent_t{agent}, sp, hsa_agent_t{gpu_}, len, 0, nullptr, s,
+                                                (hsa_amd_sdma_engine_id_t)ids_[q], false);
+        if (st != HSA_STATUS_SUCCESS) {
+            a.signal_store(s, 0);
+            return fail(OOCS_E_HIP, "HSA device-to-host copy failed (status " + std::to_string((int)st) + ")");
+        }
+        ++issued_;
     }
-    ++issued_;
     return OOCS_OK;
 }
 

@@ -46,6 +46,15 @@ public:
     // that). Blocks only while the signal ring is full. OOCS_OK or OOCS_E_HIP.
     int copy(void* dst, uint64_t agent, const void* src, size_t bytes);
 
+    // Split every later copy into n parts (on 4 KiB boundaries), each on
+    // an engine of its own (hsa_amd_memory_async_copy_on_engine), where the
+    // runtime reports n engines available for the direction (else as many
+    // as it has; with fewer than two, the runtime's own choice). n = 1: one
+    // copy on the engine the runtime picks (the default). Each part counts
+    // as a copy for issued() and wait(). OOCS_OK or OOCS_E_ARG.
+    int set_engines(int n);
+    int engines() const { return engines_; }
+
     int64_t issued() const { return issued_; }
     // Copy timing (off by default): while on, the engine timestamps every
     // copy (hsa_amd_profiling_async_copy_enable, process-wide) and the
@@ -60,6 +69,7 @@ public:
 
 private:
     int advance();  // moves done_ over completed copies
+    int engines_for(uint64_t agent);  // parts of a copy to that CPU agent (fills ids_)
 
     static constexpr int kRing = 64;
     bool ready_ = false;
@@ -69,6 +79,9 @@ private:
     uint64_t gpu_ = 0;
     std::vector<uint64_t> sig_;
     int64_t issued_ = 0, done_ = 0;
+    int engines_ = 1;
+    uint64_t mask_agent_ = 0;   // CPU agent ids_ was looked up for
+    std::vector<uint32_t> ids_; // engine ids of a split copy
 };
 
 }  // namespace oocs

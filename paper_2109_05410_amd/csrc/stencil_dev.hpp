@@ -289,27 +289,36 @@ __host__ __device__ inline int heat_tb_tiles(int nx, int ny)
 // loads are issued before the current plane is computed; one barrier per
 // plane), so the 16 x / y neighbours of a cell are LDS reads, and every
 // thread keeps its cells' p(z-4 .. z+4) in registers.
-constexpr int kWaveTileW = 64 + 8, kWaveTileH = kWaveTileY + 8;
-constexpr int kWaveTilePlane = kWaveTileW * kWaveTileH;  // floats of one staged plane
-__host__ __device__ constexpr size_t wave_tile_lds() { return 2 * (size_t)kWaveTilePlane * sizeof(float); }
+constexpr int kWaveTileW = 64 + 8;
+template <int TY = kWaveTileY>
+constexpr int wave_tile_plane() { return kWaveTileW * (TY + 8); }  // values of one staged plane
+template <typename T = float, int TY = kWaveTileY>
+__host__ __device__ constexpr size_t wave_tile_lds() { return 2 * (size_t)wave_tile_plane<TY>() * sizeof(T); }
 
+// T = float: the FP32 pipeline; T = double: FP64 rings (a ring's plane
+// stride counts floats, so a plane of doubles is read through a cast).
+template <typename T>
+__device__ inline T* ring_plane_t(const Ring& r, int64_t z) { return reinterpret_cast<T*>(ring_plane(r, z)); }
+
+// TY: tile rows (a multiple of 4); each thread has TY / 4 cells.
+template <typename T, int TY = kWaveTileY>
 __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, int sy, int sz, const float* src_table,
-                                 const int32_t* step_ctr, int wg, float* lds)
+                                 const int32_t* step_ctr, int wg, T* lds)
 {
-    const float C0X3 = (float)(-205.0 / 24.0);
-    const float C1 = (float)(8.0 / 5.0);
-    const float C2 = (float)(-1.0 / 5.0);
-    const float C3 = (float)(8.0 / 315.0);
-    const float C4 = (float)(-1.0 / 560.0);
-    const float CM[4] = {C1, C2, C3, C4};
-    constexpr int R = kWaveTileY / 4;                                   // cells per thread
-    constexpr int TW = kWaveTileW, TP = kWaveTilePlane;
-    constexpr int LPT = (TP + kBlockThreads - 1) / kBlockThreads;      // staged floats per thread
+    const T C0X3 = (T)(-205.0 / 24.0);
+    const T C1 = (T)(8.0 / 5.0);
+    const T C2 = (T)(-1.0 / 5.0);
+    const T C3 = (T)(8.0 / 315.0);
+    const T C4 = (T)(-1.0 / 560.0);
+    const T CM[4] = {C1, C2, C3, C4};
+    constexpr int R = TY / 4;                                           // cells per thread
+    constexpr int TW = kWaveTileW, TP = wave_tile_plane<TY>();
+    constexpr int LPT = (TP + kBlockThreads - 1) / kBlockThreads;      // staged values per thread
     const int tiles_x = (nx + 63) / 64;
-    const int tiles_y = (ny + kWaveTileY - 1) / kWaveTileY;
+    const int tiles_y = (ny + TY - 1) / TY;
     const int tile = wg % (tiles_x * tiles_y);
     const int zc = wg / (tiles_x * tiles_y);
-    const int x0 = (tile % tiles_x) * 64, y0 = (tile / tiles_x) * kWaveTileY;
+    const int x0 = (tile % tiles_x) * 64, y0 = (tile / tiles_x) * TY;
     const int z0 = j.z0 + zc * kZChunk;
     const int z1 = min(j.z1, z0 + kZChunk);
     if (z0 >= z1) return;  // the same for the whole workgroup
@@ -334,20 +343,20 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
         sok[i] = e < TP && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
         soff[i] = (int64_t)gy * nx + gx;
     }
-    float st[LPT];
+    T st[LPT];
     auto stage_load = [&](int z) {
-        const float* pl = ring_plane(j.src, z);
+        const T* pl = ring_plane_t<T>(j.src, z);
 #pragma unroll
-        for (int i = 0; i < LPT; ++i) st[i] = sok[i] ? pl[soff[i]] : 0.0f;
+        for (int i = 0; i < LPT; ++i) st[i] = sok[i] ? pl[soff[i]] : (T)0;
     };
     auto stage_store = [&](int buf) {
-        float* t = lds + buf * TP;
+        T* t = lds + buf * TP;
 #pragma unroll
         for (int i = 0; i < LPT; ++i)
             if (tid + kBlockThreads * i < TP) t[tid + kBlockThreads * i] = st[i];
     };
-    auto col = [&](int c, int z) -> float { return (cin[c] && z >= 0 && z < nz) ? ring_plane(j.src, z)[off[c]] : 0.0f; };
-    float q[R][9];  // q[c][i] = p(z - 4 + i) at cell c
+    auto col = [&](int c, int z) -> T { return (cin[c] && z >= 0 && z < nz) ? ring_plane_t<T>(j.src, z)[off[c]] : (T)0; };
+    T q[R][9];  // q[c][i] = p(z - 4 + i) at cell c
 #pragma unroll
     for (int c = 0; c < R; ++c)
 #pragma unroll
@@ -359,24 +368,24 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
         const int b = (z - z0) & 1;
         const bool more = z + 1 < z1;
         if (more) stage_load(z + 1);  // in flight while this plane is computed
-        float pm[R], w[R];
+        T pm[R], w[R];
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             q[c][8] = col(c, z + 4);
-            pm[c] = cin[c] ? ring_plane(j.src2, z)[off[c]] : 0.0f;
-            w[c] = cin[c] ? ring_plane(j.ro, z)[off[c]] : 0.0f;
+            pm[c] = cin[c] ? ring_plane_t<T>(j.src2, z)[off[c]] : (T)0;
+            w[c] = cin[c] ? ring_plane_t<T>(j.ro, z)[off[c]] : (T)0;
         }
-        const float* t = lds + b * TP + (wv * R + 4) * TW + lx + 4;
+        const T* t = lds + b * TP + (wv * R + 4) * TW + lx + 4;
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            const float* tc = t + c * TW;
-            float acc = C0X3 * q[c][4];
+            const T* tc = t + c * TW;
+            T acc = C0X3 * q[c][4];
 #pragma unroll
             for (int m = 1; m <= 4; ++m)
                 acc = acc + CM[m - 1] * (((tc[m] + tc[-m]) + (tc[m * TW] + tc[-m * TW])) + (q[c][4 + m] + q[c][4 - m]));
-            float v = (2.0f * q[c][4] - pm[c]) + w[c] * acc;
-            if (srcc[c] && z == sz) v = v + (src_table ? src_table[*step_ctr + j.src_off] : j.amp);
-            if (cin[c]) ring_plane(j.dst, z)[off[c]] = v;
+            T v = ((T)2 * q[c][4] - pm[c]) + w[c] * acc;
+            if (srcc[c] && z == sz) v = v + (T)(src_table ? src_table[*step_ctr + j.src_off] : j.amp);
+            if (cin[c]) ring_plane_t<T>(j.dst, z)[off[c]] = v;
         }
         if (more) stage_store(b ^ 1);
         __syncthreads();

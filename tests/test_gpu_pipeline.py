@@ -237,10 +237,12 @@ def test_sdma_writeback_matches_hip_copies(stencil):
                   (0.02 + 0.1 * rng.random(shape)).astype(np.float32)]
         mk = lambda: api.OutOfCorePlan(shape, api.WAVE25, 2, k, rates, 16 * MiB)  # noqa: E731
     outs = {}
-    for mode in ("sdma", "hip", "graph", "stream"):
+    for mode in ("sdma", "hip", "graph", "stream", "sdma2", "sdma4"):
         plan = mk()
         assert plan.sdma_available
         plan.set_sdma(mode == "sdma")
+        if mode in ("sdma2", "sdma4"):  # every copy split over engines of its own
+            plan.set_sdma(int(mode[-1]))
         if mode == "graph":
             plan.set_sdma(True)
             plan.set_graphs(True)
@@ -250,12 +252,12 @@ def test_sdma_writeback_matches_hip_copies(stencil):
         st = [store_of(plan, f, a) for f, a in enumerate(fields)]
         r1 = plan.run(st, 8)  # k divides the first call: two calls replay as one
         r2 = plan.run(st, steps - 8)
-        if mode == "sdma":
+        if mode.startswith("sdma"):
             assert r1.sdma_copies > 0 and r2.sdma_copies > 0
         else:
             assert r1.sdma_copies == 0 and r2.sdma_copies == 0
         outs[mode] = [s.clone() for s in st]
-    for mode in ("hip", "graph", "stream"):
+    for mode in ("hip", "graph", "stream", "sdma2", "sdma4"):
         for a, b in zip(outs["sdma"], outs[mode]):
             assert torch.equal(a, b), mode
     if stencil == "heat":
@@ -265,7 +267,7 @@ def test_sdma_writeback_matches_hip_copies(stencil):
 def test_link_probe_reports_both_engines():
     """The host-link probe runs on the pipeline's engines (SDMA write-back)
     and on hipMemcpyAsync alone, and reports positive rates for each."""
-    for sdma in (True, False):
+    for sdma in (1, 0, 2, 4):
         r = api.link_probe(32 << 20, 4 << 20, reps=1, sdma=sdma)
         assert r["d2h_engine"] == ("sdma" if sdma else "hipMemcpyAsync")
         assert min(r["h2d_GBps"], r["d2h_GBps"], r["bidir_GBps_each"]) > 1.0
