@@ -281,6 +281,16 @@ typedef struct {
  * (OOCS_PLAN_KERNEL_TRANSFERS, OOCS_PLAN_KERNEL_STORES). */
 #define OOCS_PLAN_FP64 128
 
+/* Plan flag (wave): the read-only field's host store (compressed, or raw
+ * at rate 0) is copied once into the arena (oocs_run copies it when the
+ * read-only store pointer differs from the last one it copied; store I/O
+ * on the plan forgets it), and every residency decodes the read-only
+ * chunks from there instead of copying them over the host link: the
+ * host-to-device traffic of a residency drops by that field's store bytes,
+ * and the arena holds oocs_store_bytes(plan, 2) more bytes. Results are
+ * identical. Copy-engine transfers only; not with OOCS_PLAN_RESIDENT_RO. */
+#define OOCS_PLAN_RO_DEVICE_STORE 256
+
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be
  * queried but not run (no HIP call is made for it). Chooses the group size
@@ -366,6 +376,9 @@ int oocs_plan_schedule_op(oocs_plan* plan, int kr, int64_t index, oocs_op* out);
 #define OOCS_SCHED_RETAIN_IN 2
 #define OOCS_SCHED_RETAIN_OUT 4
 #define OOCS_SLOT_RETAINED (-2)
+/* Decode ops of the read-only field in an OOCS_PLAN_RO_DEVICE_STORE plan
+ * read its chunk from the device copy of the store and carry this slot. */
+#define OOCS_SLOT_DEVICE_STORE (-3)
 int64_t oocs_plan_schedule_variant_len(oocs_plan* plan, int kr, int variant);
 int oocs_plan_schedule_variant_op(oocs_plan* plan, int kr, int variant, int64_t index, oocs_op* out);
 

@@ -35,11 +35,13 @@ OOCS_PLAN_RESIDENT_RO = 16
 OOCS_PLAN_SNAKE = 32
 OOCS_PLAN_MIDPOINT = 64
 OOCS_PLAN_FP64 = 128
+OOCS_PLAN_RO_DEVICE_STORE = 256
 OOCS_DECODE_MIDPOINT = 0x100
 OOCS_SCHED_MIRROR = 1
 OOCS_SCHED_RETAIN_IN = 2
 OOCS_SCHED_RETAIN_OUT = 4
 OOCS_SLOT_RETAINED = -2
+OOCS_SLOT_DEVICE_STORE = -3
 
 OP_H2D, OP_DECODE, OP_LEVEL, OP_ENCODE, OP_D2H, OP_LAUNCH, OP_RECORD, OP_WAIT, OP_FETCH, OP_STORE = range(1, 11)
 

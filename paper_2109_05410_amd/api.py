@@ -347,13 +347,17 @@ class OutOfCorePlan:
     decode reconstructs the digits the budget cut off at the middle of their
     range (a different, lower-error state). fp64 (wave): FP64 fields and
     the FP64 block format (rates up to 68); put/get take and return float64
-    arrays; copy-engine transfers only."""
+    arrays; copy-engine transfers only. ro_device_store (wave): the
+    read-only field's store is copied once into the arena and decoded from
+    there every residency (no host-link traffic for it after the first
+    run)."""
 
     def __init__(self, shape, stencil: int, nslabs: int, k: int, rates, arena_bytes: int,
                  alpha: float = 0.1, src_cell=None, group: int = 0, nstage: int = 0,
                  planning_only: bool = False, device=None, block_restart: bool = False,
                  kernel_transfers: bool = False, level_by_level: bool = False, kernel_stores: bool = False,
-                 resident_ro: bool = False, snake: bool = False, midpoint: bool = False, fp64: bool = False):
+                 resident_ro: bool = False, snake: bool = False, midpoint: bool = False, fp64: bool = False,
+                 ro_device_store: bool = False):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -372,7 +376,8 @@ class OutOfCorePlan:
                      | (L.OOCS_PLAN_RESIDENT_RO if resident_ro else 0)
                      | (L.OOCS_PLAN_SNAKE if snake else 0)
                      | (L.OOCS_PLAN_MIDPOINT if midpoint else 0)
-                     | (L.OOCS_PLAN_FP64 if fp64 else 0))
+                     | (L.OOCS_PLAN_FP64 if fp64 else 0)
+                     | (L.OOCS_PLAN_RO_DEVICE_STORE if ro_device_store else 0))
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
         self.cfg = cfg

@@ -797,6 +797,8 @@ struct OpTranslator {
             j.dst = ring(o.level);
             if (o.slot == OOCS_SLOT_RETAINED)  // snake: the retained block, laid out like the host store
                 j.stage = pl->arena + P.ret_off[o.field] + (o.z0 - P.ret_base(o.z0)) * P.store_plane_bytes(o.field);
+            else if (o.slot == OOCS_SLOT_DEVICE_STORE)  // the device copy of the read-only store
+                j.stage = pl->arena + P.ro_dev_off + o.z0 * P.store_plane_bytes(o.field);
             else
                 j.stage = dec ? (void*)(pl->arena + P.in_off[o.field] + (int64_t)o.slot * P.in_slot_bytes[o.field])
                               : (void*)(pl->arena + P.out_off[o.field] + (int64_t)o.slot * P.out_slot_bytes[o.field]);
@@ -976,6 +978,12 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
     if (P.resident_ro && pl->ro_loaded != h_store[2]) {
         const int rc = load_resident_ro(pl, h_store[2]);
         if (rc != OOCS_OK) return rc;
+    }
+    if (P.ro_dev && pl->ro_loaded != h_store[2]) {  // the read-only store, copied once into the arena
+        HIP_TRY(hipMemcpyAsync(pl->arena + P.ro_dev_off, h_store[2], (size_t)P.store_bytes(2), hipMemcpyHostToDevice,
+                               pl->st[1]));
+        HIP_TRY(hipStreamSynchronize(pl->st[1]));
+        pl->ro_loaded = h_store[2];
     }
     const bool src_on = h_src != nullptr && P.cfg.stencil == OOCS_WAVE25 && P.cfg.src_x >= 0 && P.cfg.src_x < P.nx &&
                         P.cfg.src_y >= 0 && P.cfg.src_y < P.ny && P.cfg.src_z >= 0 && P.cfg.src_z < P.nz;

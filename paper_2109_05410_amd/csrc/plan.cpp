@@ -68,7 +68,7 @@ int Planner::init(const oocs_config& c, std::string& err)
     if (c.nstage != 0 && (c.nstage < 2 || c.nstage > 16)) { err = "nstage must be 0 or in [2, 16]"; return OOCS_E_ARG; }
     if (c.flags & ~(OOCS_PLAN_BLOCK_RESTART | OOCS_PLAN_KERNEL_TRANSFERS | OOCS_PLAN_LEVEL_BY_LEVEL |
                     OOCS_PLAN_KERNEL_STORES | OOCS_PLAN_RESIDENT_RO | OOCS_PLAN_SNAKE | OOCS_PLAN_MIDPOINT |
-                    OOCS_PLAN_FP64)) {
+                    OOCS_PLAN_FP64 | OOCS_PLAN_RO_DEVICE_STORE)) {
         err = "unknown plan flags";
         return OOCS_E_ARG;
     }
@@ -79,6 +79,11 @@ int Planner::init(const oocs_config& c, std::string& err)
     resident_ro = (c.flags & OOCS_PLAN_RESIDENT_RO) != 0;
     if (resident_ro && !has_ro) { err = "a resident read-only field needs the wave stencil"; return OOCS_E_ARG; }
     if (resident_ro) in_fields = {0, 1};  // the read-only field is loaded once, outside the residencies
+    ro_dev = (c.flags & OOCS_PLAN_RO_DEVICE_STORE) != 0;
+    if (ro_dev && (!has_ro || resident_ro || !copy_engines)) {
+        err = "a device-held read-only store needs the wave stencil, copy-engine transfers and no resident read-only field";
+        return OOCS_E_ARG;
+    }
     snake = (c.flags & OOCS_PLAN_SNAKE) != 0;
     if (snake && (!copy_engines || kernel_stores || restart || n < 2)) {
         err = "snake sweeps need copy-engine transfers, shared levels and at least two slabs";
@@ -344,9 +349,15 @@ int64_t Planner::layout(int64_t Gc, int ns, std::string& err)
     }
     for (int f = 0; f < OOCS_MAX_FIELDS; ++f) { in_slot_bytes[f] = out_slot_bytes[f] = in_off[f] = out_off[f] = 0; }
     for (int fld : in_fields) {
+        if (ro_dev && fld == 2) continue;  // decoded from the device copy of its store
         in_slot_bytes[fld] = align_up(G * store_plane_bytes(fld), 256);
         in_off[fld] = off;
         off += in_slot_bytes[fld] * nstage;
+    }
+    ro_dev_off = -1;
+    if (ro_dev) {
+        ro_dev_off = off;
+        off = align_up(off + store_bytes(2), 256);
     }
     if (resident_ro) {  // one slot to load the read-only field group by group
         in_slot_bytes[2] = align_up(G * store_plane_bytes(2), 256);
@@ -428,7 +439,7 @@ int Planner::emit_ops(int kr, int variant, Schedule& s, std::string& err) const
     auto loaded_fields = [&](const GroupRec& g) {
         std::vector<int> f;
         for (int fld : in_fields)
-            if (!in_retained(g.z0, g.z1) || fld == 2) f.push_back(fld);
+            if ((!in_retained(g.z0, g.z1) || fld == 2) && !(ro_dev && fld == 2)) f.push_back(fld);
         return f;
     };
     auto emit_h2d = [&](int64_t j, int64_t tick, std::vector<oocs_op>& out) {
@@ -500,7 +511,9 @@ int Planner::emit_ops(int kr, int variant, Schedule& s, std::string& err) const
         if (isl >= 0)
             for (int fld : in_fields) {
                 oocs_op d = op(OOCS_OP_DECODE, 1);
-                d.field = fld; d.slot = iret && fld != 2 ? OOCS_SLOT_RETAINED : isl; d.level = in_ring(fld);
+                d.field = fld;
+                d.slot = ro_dev && fld == 2 ? OOCS_SLOT_DEVICE_STORE : (iret && fld != 2 ? OOCS_SLOT_RETAINED : isl);
+                d.level = in_ring(fld);
                 d.z0 = t.dz0; d.z1 = t.dz1; d.block = t.block; d.tick = (int)ti;
                 s.ops.push_back(d);
             }

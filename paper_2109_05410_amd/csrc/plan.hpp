@@ -88,6 +88,8 @@ public:
     bool resident_ro = false;   // wave: the read-only field stays decoded in an nz-plane ring
     bool snake = false;         // alternating sweeps; the last block of a residency stays on the device
     bool midpoint = false;      // every decode with mid-point reconstruction
+    bool ro_dev = false;        // wave: the read-only store copied once into the arena
+    int64_t ro_dev_off = -1;    // its offset there
     bool fp64 = false;          // FP64 fields (wave): 8-byte values, the FP64 format
     int esize = 4;              // bytes per value
     int64_t X = 0;              // snake: planes of the retained block (one slab)

@@ -493,3 +493,46 @@ def test_midpoint_pipeline_matches_replay(snake):
     rp, rpm, _ = O.replay_wave_f32(p0, pm0, w, 13, 4, src=(amps, idx), rate_p=12, rate_pm=12, rate_w=12, mid=True)
     assert np.array_equal(O.codec_decode(st[0].numpy().view(np.uint64), wshape, 12, mid=True), rp)
     assert np.array_equal(O.codec_decode(st[1].numpy().view(np.uint64), wshape, 12, mid=True), rpm)
+
+
+@pytest.mark.parametrize("graphs,ce", [(g, m) for m in ("copy", "hybrid") for g in (False, True)],
+                         ids=[f"{m}-{'graph' if g else 'eager'}" for m in ("copy", "hybrid") for g in (False, True)])
+@pytest.mark.parametrize("rates,snake", [([12, 12, 12], False), ([8, 12, 8], True), ([0, 0, 0], True),
+                                         ([0, 12, 12], False)])
+def test_device_read_only_store_matches_replay(rates, snake, graphs, ce):
+    """The read-only store copied once into the arena and decoded from there
+    every residency: the stores equal the replay bit for bit, the host link
+    carries nothing of the read-only field after the first run, and a new
+    read-only store pointer is copied again."""
+    shape, k, steps = (96, 36, 40), 4, 13
+    rng = np.random.default_rng(31)
+    p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    pm0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    w2 = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    amps = rng.standard_normal(steps + 5).astype(np.float32)
+    cell = (17, 20, 50)
+    kw = dict(src_cell=cell, snake=snake, **xfer(ce))
+    ref = api.OutOfCorePlan(shape, api.WAVE25, 2, k, rates, 16 * MiB, **kw)
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 2, k, rates, 16 * MiB, ro_device_store=True, **kw)
+    plan.set_graphs(graphs)
+    sr = [store_of(ref, 0, p0), store_of(ref, 1, pm0), store_of(ref, 2, w)]
+    st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
+    a = ref.run(sr, steps, src_amps=amps)
+    b = plan.run(st, steps, src_amps=amps)
+    nz, ny, nx = shape
+    idx = cell[0] + nx * (cell[1] + ny * cell[2])
+    wp, wpm, _ = O.replay_wave_f32(p0, pm0, w, steps, k, src=(amps[:steps], idx), rate_p=rates[0], rate_pm=rates[1],
+                                   rate_w=rates[2])
+    assert np.array_equal(decoded(st[0], shape, rates[0]), wp)
+    assert np.array_equal(decoded(st[1], shape, rates[1]), wpm)
+    nres = -(-steps // k)
+    assert a.h2d_bytes - b.h2d_bytes == nres * plan.store_bytes(2)
+    # another read-only store: copied again, results follow it
+    s2 = store_of(plan, 2, w2)
+    st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), s2]
+    plan.run(st, 5, src_amps=amps)
+    wp, wpm, _ = O.replay_wave_f32(p0, pm0, w2, 5, k, src=(amps[:5], idx), rate_p=rates[0], rate_pm=rates[1],
+                                   rate_w=rates[2])
+    assert np.array_equal(decoded(st[0], shape, rates[0]), wp)
+    assert np.array_equal(decoded(st[1], shape, rates[1]), wpm)

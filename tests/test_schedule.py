@@ -163,6 +163,8 @@ def accesses(o, g):
     elif K == L.OP_DECODE:
         if o["slot"] == L.OOCS_SLOT_RETAINED:  # planes of the retained block, at their place in the buffer
             out += [(("ret", o["field"], z - g.ret_base(z)), False) for z in range(o["z0"], o["z1"])]
+        elif o["slot"] == L.OOCS_SLOT_DEVICE_STORE:  # the device copy of the read-only store (never written)
+            out += [(("devstore", o["field"], z), False) for z in range(o["z0"], o["z1"])]
         else:
             out.append((("in", o["field"], o["slot"]), False))
         R = o["level"]
@@ -404,6 +406,14 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
         for o in p.schedule(kr, p.variant(rnd, nres)):
             K = o["kind"]
             z0, z1 = o["z0"], o["z1"]
+            if K == L.OP_DECODE and o["slot"] == L.OOCS_SLOT_DEVICE_STORE:
+                f, rate = o["field"], rates[o["field"]]
+                lw = layer_words(rate)
+                data = store[f][z0 // 4 * lw: z1 // 4 * lw] if rate else store[f][z0:z1]
+                planes = dec(data, (z1 - z0, ny, nx), rate) if rate else data
+                for z in range(z0, z1):
+                    rings[o["level"]][z % g.W[o["level"]]] = planes[z - z0]
+                continue
             if K == L.OP_DECODE and o["slot"] == L.OOCS_SLOT_RETAINED:
                 f, rate = o["field"], rates[o["field"]]
                 if rate:
@@ -770,4 +780,60 @@ def test_fp64_plan_errors():
         assert e.value.code == L.OOCS_E_ARG
     with pytest.raises(L.OocsError) as e:
         plan((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, fp64=True)
+    assert e.value.code == L.OOCS_E_ARG
+
+
+# ---------------------------------------------------------------------------
+# the read-only store held on the device
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rates,k,steps,kw", [
+    ([8, 12, 8], 4, 9, {}), ([0, 0, 0], 3, 7, {}), ([12, 12, 12], 4, 13, {"snake": True}),
+    ([0, 12, 12], 4, 9, {"block_restart": True}), ([12, 0, 8], 4, 9, {"kernel_stores": True}),
+    ([24, 24, 24], 4, 9, {"fp64": True}),
+])
+def test_device_store_schedule_computes_the_replay(rates, k, steps, kw):
+    """Decoding the read-only chunks from the device copy of the store gives
+    the replay bit for bit; no host-to-device copy of that field remains;
+    the schedule has no races."""
+    shape = (64, 12, 12)
+    rng = np.random.default_rng(steps)
+    f64 = kw.get("fp64", False)
+    dt = np.float64 if f64 else np.float32
+    p0 = rng.standard_normal(shape).astype(dt)
+    pm0 = rng.standard_normal(shape).astype(dt)
+    w = (0.02 + 0.1 * rng.random(shape)).astype(dt)
+    amps = rng.standard_normal(steps).astype(np.float32)
+    src = (5, 6, 20)
+    p = plan(shape, WAVE25, 2, k, rates, 8 * MiB, src_cell=src, ro_device_store=True, **kw)
+    for kr in range(1, k + 1):
+        ops = p.schedule(kr)
+        assert not any(o["field"] == 2 and o["kind"] in (L.OP_H2D, L.OP_FETCH) for o in ops)
+        assert any(o["kind"] == L.OP_DECODE and o["slot"] == L.OOCS_SLOT_DEVICE_STORE for o in ops)
+    race_check(p, steps)
+    race_check(p, steps, graph_mode=True)
+    ts, fs = (to_store64, from_store64) if f64 else (to_store, from_store)
+    store = [ts(p0, rates[0]), ts(pm0, rates[1]), ts(w, rates[2])]
+    execute(p, store, steps, amps)
+    idx = src[0] + shape[2] * (src[1] + shape[1] * src[2])
+    replay = O.replay_wave64 if f64 else O.replay_wave_f32
+    a = amps.astype(np.float64) if f64 else amps
+    wp, wpm, _ = replay(p0, pm0, w, steps, k, src=(a, idx), rate_p=rates[0], rate_pm=rates[1], rate_w=rates[2])
+    assert np.array_equal(fs(store[0], shape, rates[0]), wp)
+    assert np.array_equal(fs(store[1], shape, rates[1]), wpm)
+
+
+def test_device_store_arena_and_errors():
+    shape = (64, 16, 16)
+    a = plan(shape, WAVE25, 2, 4, [12, 12, 12], 64 * MiB)
+    b = plan(shape, WAVE25, 2, 4, [12, 12, 12], 64 * MiB, ro_device_store=True)
+    # the streamed slots of the read-only field go, its whole store comes in
+    assert b.info["arena_needed"] > a.info["arena_needed"] - a.info["nstage"] * a.info["group"] * 16 * 16 * 12 // 8
+    assert b.info["arena_needed"] >= b.store_bytes(2)
+    for kw in ({"resident_ro": True}, {"kernel_transfers": True}):
+        with pytest.raises(L.OocsError) as e:
+            plan(shape, WAVE25, 2, 4, [12, 12, 12], 64 * MiB, ro_device_store=True, **kw)
+        assert e.value.code == L.OOCS_E_ARG
+    with pytest.raises(L.OocsError) as e:
+        plan((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, ro_device_store=True)
     assert e.value.code == L.OOCS_E_ARG
