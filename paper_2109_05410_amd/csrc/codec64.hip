@@ -102,40 +102,62 @@ __device__ inline int exponent_of(double x)
 }
 
 // ---- bits of one block in LDS (rate words, zeroed before encoding) ---------
-// Writer and reader keep their state in wave-uniform values; only lane 0
-// stores to LDS.
+// Writer and reader keep their state, including the 64-bit word being
+// filled or read, in wave-uniform values (scalar registers), so a word of
+// LDS is touched once: the writer stores each word when it is full (lane 0)
+// and the last partial one at flush(); the reader loads each word once, as
+// the window (lo, hi) slides over it.
 struct BitWriter {
     uint64_t* words;
-    int pos = 0;
+    int rate;
+    uint64_t cur = 0;  // the bits of word w written so far
+    int w = 0, o = 0;  // word index, bits in cur
     __device__ void put(uint64_t bits, int n)  // n in [0, 64]; bits has no bit at or above n
     {
         if (n == 0) return;
-        const int w = pos >> 6, o = pos & 63;
-        if (lane_id() == 0) {
-            words[w] |= bits << o;
-            if (o + n > 64) words[w + 1] |= bits >> (64 - o);
+        cur |= bits << o;
+        if (o + n >= 64) {
+            if (lane_id() == 0 && w < rate) words[w] = cur;
+            ++w;
+            cur = o ? bits >> (64 - o) : 0;
+            o = o + n - 64;
+        } else {
+            o += n;
         }
-        pos += n;
+    }
+    __device__ void flush()
+    {
+        if (o > 0 && lane_id() == 0 && w < rate) words[w] = cur;
     }
 };
 
 struct BitReader {
     const uint64_t* words;
     int rate;
-    int pos = 0;
-    __device__ uint64_t word(int w) const { return w < rate ? uniform64(words[w]) : 0; }
+    int w = 0, o = 0;  // lo = word w, hi = word w + 1; o = bits of lo consumed
+    uint64_t lo = 0, hi = 0;
+    __device__ uint64_t word(int i) const { return i < rate ? uniform64(words[i]) : 0; }
+    __device__ BitReader(const uint64_t* ws, int r) : words(ws), rate(r) { lo = word(0); hi = word(1); }
     __device__ uint64_t peek64() const  // the next 64 bits (zeros past the block)
     {
-        const int w = pos >> 6, o = pos & 63;
-        const uint64_t lo = word(w);
-        return o ? (lo >> o) | (word(w + 1) << (64 - o)) : lo;
+        return o ? (lo >> o) | (hi << (64 - o)) : lo;
+    }
+    __device__ void skip(int n)  // n in [0, 64]
+    {
+        o += n;
+        if (o >= 64) {
+            o -= 64;
+            ++w;
+            lo = hi;
+            hi = word(w + 1);
+        }
     }
     __device__ uint64_t get(int n)  // n in [0, 64]
     {
         if (n == 0) return 0;
         uint64_t v = peek64();
         if (n < 64) v &= ((uint64_t)1 << n) - 1;
-        pos += n;
+        skip(n);
         return v;
     }
 };
@@ -230,7 +252,7 @@ __device__ inline void encode_block(double x, int rate, uint64_t* words, EncOut 
 {
     const int lane = lane_id();
     const uint64_t nz = __ballot(x != 0.0);
-    BitWriter bw{words};
+    BitWriter bw{words, rate};
     if (!nz) {
         bw.put(0, 1);
         if (st.emax && lane == 0) st.emax[b] = INT32_MIN;
@@ -257,6 +279,7 @@ __device__ inline void encode_block(double x, int rate, uint64_t* words, EncOut 
     if (st.t) st.t[64 * b + lane] = t;
     if (st.u) st.u[64 * b + lane] = u;
     const int used = code_planes(u, 64 * rate - 12, bw, st.planes ? st.planes + 64 * b : nullptr);
+    bw.flush();
     if (st.bits && lane == 0) st.bits[b] = 12 + used;
 }
 
@@ -264,7 +287,7 @@ __device__ inline void encode_block(double x, int rate, uint64_t* words, EncOut 
 __device__ inline double decode_block(const uint64_t* words, int rate, DecOut st = {}, int64_t b = 0)
 {
     const int lane = lane_id();
-    BitReader br{words, rate};
+    BitReader br(words, rate);
     if (!br.get(1)) {
         if (st.emax && lane == 0) st.emax[b] = INT32_MIN;
         if (st.u) st.u[64 * b + lane] = 0;

@@ -392,7 +392,12 @@ int Planner::choose(size_t arena_bytes, std::string& err)
     if (cfg.group > 0) {
         cands.push_back(cfg.group);
     } else {
-        for (int64_t g = 32; g >= 4; g -= 4) cands.push_back(g);
+        // the wave's levels read 9 planes of p and write one ring each, so its
+        // ticks are long already at 16 planes: larger groups only delay the
+        // first transfers of a residency (1024^3 at 12 bits in 8 GiB: groups
+        // of 8-16 planes ran 4-7 % faster than 20-24)
+        const int64_t gmax = cfg.stencil == OOCS_WAVE25 ? 16 : 32;
+        for (int64_t g = gmax; g >= 4; g -= 4) cands.push_back(g);
         if (!any_rate) { cands.push_back(2); cands.push_back(1); }
     }
     // staging depth: the caller's, else 4 then 3 slots for copy engines (a larger

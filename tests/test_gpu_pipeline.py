@@ -504,6 +504,8 @@ def test_device_read_only_store_matches_replay(rates, snake, graphs, ce):
     every residency: the stores equal the replay bit for bit, the host link
     carries nothing of the read-only field after the first run, and a new
     read-only store pointer is copied again."""
+    if snake and ce == "hybrid":
+        pytest.skip("snake sweeps need copy-engine write-back")
     shape, k, steps = (96, 36, 40), 4, 13
     rng = np.random.default_rng(31)
     p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
