@@ -411,14 +411,17 @@ def fp64_replica(api, torch, inputs, wi, state, rounds=2):
         log(f"FP64 {name}: {out['codes'][name]['gcells_per_s']:.1f} GCell-updates/s, "
             f"{out['codes'][name]['ms_per_round']:.0f} ms/round")
         plan.close()
+        del plan, st  # the views keep the pinned buffers alive
     out["codec64_512"] = codec64_rates(api, torch, state)
     log(f"FP64 codec: {out['codec64_512']}")
     base = out["codes"]["code1"]["gcells_per_s"]
     out["speedup_vs_code1"] = {k: v["gcells_per_s"] / base for k, v in out["codes"].items() if k != "code1"}
     out["paper_context"] = "V100-PCIe 32 GB, 4 x 1160^3 doubles: code 2 1.16x, code 3 1.18x, code 4 1.20x (Sec. VI-A)"
     del bufs, p, pm, w
+    torch.cuda.synchronize()
     if hasattr(torch._C, "_host_emptyCache"):
-        torch._C._host_emptyCache()
+        torch._C._host_emptyCache()  # give the 37 GB of pinned stores back before the next sections pin theirs
+    torch.cuda.empty_cache()
     return out
 
 
