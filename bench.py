@@ -770,9 +770,9 @@ def host_link(api, chunk, sdma=True):
     """Achievable host-link bandwidth with pinned memory, moved with the
     pipeline's engines in copies of the pipeline's size (one group of
     planes of one field): each direction alone, and both at once (about
-    256 MiB each way, mean of 3 timed passes)."""
-    nbytes = max(1, (256 << 20) // chunk) * chunk
-    r = api.link_probe(nbytes, chunk, reps=3, sdma=sdma)
+    1 GiB each way, mean of 5 timed passes)."""
+    nbytes = max(1, (1 << 30) // chunk) * chunk
+    r = api.link_probe(nbytes, chunk, reps=5, sdma=sdma)
     return {k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
 
 
@@ -986,7 +986,7 @@ def main():
         "link_bound_ms_per_round": round(t_bound, 2) if t_bound else None,
         "ms_per_round": round(head["ms_per_round"], 2),
         "frac": round(t_bound / head["ms_per_round"], 4) if t_bound else None,
-        "peak_source": "host_link: ~256 MiB one way at a time in pinned copies of the pipeline's group size on "
+        "peak_source": "host_link: ~1 GiB one way at a time in pinned copies of the pipeline's group size on "
                        "its engines (hipMemcpyAsync up, SDMA down); frac = link-bound time / measured round time "
                        "(the probe's single copy queue per direction can read a little below what the "
                        "pipeline reaches, so frac can pass 1 slightly)",
