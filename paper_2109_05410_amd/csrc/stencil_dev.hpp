@@ -282,13 +282,16 @@ __host__ __device__ inline int heat_tb_tiles(int nx, int ny)
 // Wave, 25 points:
 //   acc = C0X3*p;  for m = 1..4: acc = acc + C_m * (((x+m + x-m) + (y+m + y-m)) + (z+m + z-m))
 //   p'  = (2p - pm) + w*acc  (+ amp at the source cell)
-// Mapping: a workgroup owns a 64 x kWaveTileY cell tile (each wave 64
-// lanes x kWaveTileY/4 consecutive rows, so a thread has kWaveTileY/4
-// cells) and marches up to kZChunk planes. Each plane of p, with its 4-cell
-// halo in x and y, is staged through LDS (double buffered; the next plane's
-// loads are issued before the current plane is computed; one barrier per
-// plane), so the 16 x / y neighbours of a cell are LDS reads, and every
-// thread keeps its cells' p(z-4 .. z+4) in registers.
+// Mapping: a workgroup owns a 64 x TY cell tile (each wave 64 lanes x TY/4
+// consecutive rows, so a thread has TY/4 cells) and marches up to kZChunk
+// planes. Each plane of p, with its 4-cell halo in x and y, is staged
+// through LDS, so the 16 x / y neighbours of a cell are LDS reads, and every
+// thread keeps its cells' p(z-4 .. z+4) in registers. Two staged planes
+// (double buffered): the next plane's loads are issued before the current
+// plane is computed; one barrier per plane. (A ring of six staged planes that
+// also supplied p(z+4) at the cell, instead of a second read of p, was
+// slower: 214 against 237 GCell/s in core at 1024^3, its 41 KiB of LDS
+// leaving room for three workgroups per CU instead of four.)
 constexpr int kWaveTileW = 64 + 8;
 template <int TY = kWaveTileY>
 constexpr int wave_tile_plane() { return kWaveTileW * (TY + 8); }  // values of one staged plane
@@ -299,6 +302,18 @@ __host__ __device__ constexpr size_t wave_tile_lds() { return 2 * (size_t)wave_t
 // stride counts floats, so a plane of doubles is read through a cast).
 template <typename T>
 __device__ inline T* ring_plane_t(const Ring& r, int64_t z) { return reinterpret_cast<T*>(ring_plane(r, z)); }
+
+// Planes of a ring visited in order z, z+1, ...: the slot advances without
+// the division of ring_plane (wave-uniform, so it stays in scalar registers).
+template <typename T>
+struct PlaneCursor {
+    float* base;
+    int64_t ld;
+    uint32_t W, slot;
+    __device__ PlaneCursor(const Ring& r, int z) : base(r.base), ld(r.ld_z), W((uint32_t)r.W), slot((uint32_t)z % (uint32_t)r.W) {}
+    __device__ T* plane() const { return reinterpret_cast<T*>(base + (int64_t)slot * ld); }
+    __device__ void next() { slot = slot + 1 == W ? 0u : slot + 1; }
+};
 
 // TY: tile rows (a multiple of 4); each thread has TY / 4 cells.
 template <typename T, int TY = kWaveTileY>
@@ -344,36 +359,49 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
         soff[i] = (int64_t)gy * nx + gx;
     }
     T st[LPT];
-    auto stage_load = [&](int z) {
-        const T* pl = ring_plane_t<T>(j.src, z);
+    // staged planes are taken in order z0, z0 + 1, ...
+    PlaneCursor<T> cs(j.src, z0), cpm(j.src2, z0), cw(j.ro, z0), cd(j.dst, z0);
+    auto stage_load = [&](int z) {  // the cursor's plane, z; planes outside the grid stage as zeros
+        const bool zin = z < nz;
+        const T* pl = cs.plane();
+        cs.next();
 #pragma unroll
-        for (int i = 0; i < LPT; ++i) st[i] = sok[i] ? pl[soff[i]] : (T)0;
+        for (int i = 0; i < LPT; ++i) st[i] = (zin && sok[i]) ? pl[soff[i]] : (T)0;
     };
-    auto stage_store = [&](int buf) {
-        T* t = lds + buf * TP;
+    auto stage_store = [&](T* t) {
 #pragma unroll
         for (int i = 0; i < LPT; ++i)
             if (tid + kBlockThreads * i < TP) t[tid + kBlockThreads * i] = st[i];
     };
     auto col = [&](int c, int z) -> T { return (cin[c] && z >= 0 && z < nz) ? ring_plane_t<T>(j.src, z)[off[c]] : (T)0; };
+    PlaneCursor<T> ccol(j.src, z0 + 4);  // p(z + 4) at the cell, read plane by plane
     T q[R][9];  // q[c][i] = p(z - 4 + i) at cell c
 #pragma unroll
     for (int c = 0; c < R; ++c)
 #pragma unroll
         for (int i = 0; i < 8; ++i) q[c][i] = col(c, z0 - 4 + i);
     stage_load(z0);
-    stage_store(0);
+    stage_store(lds);
     __syncthreads();
     for (int z = z0; z < z1; ++z) {
         const int b = (z - z0) & 1;
         const bool more = z + 1 < z1;
         if (more) stage_load(z + 1);  // in flight while this plane is computed
         T pm[R], w[R];
+        const T* ppm = cpm.plane();
+        const T* pw = cw.plane();
+        const T* pc = ccol.plane();
+        T* pd = cd.plane();
+        cpm.next();
+        cw.next();
+        ccol.next();
+        cd.next();
+        const bool cz = z + 4 < nz;
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            q[c][8] = col(c, z + 4);
-            pm[c] = cin[c] ? ring_plane_t<T>(j.src2, z)[off[c]] : (T)0;
-            w[c] = cin[c] ? ring_plane_t<T>(j.ro, z)[off[c]] : (T)0;
+            q[c][8] = (cin[c] && cz) ? pc[off[c]] : (T)0;
+            pm[c] = cin[c] ? ppm[off[c]] : (T)0;
+            w[c] = cin[c] ? pw[off[c]] : (T)0;
         }
         const T* t = lds + b * TP + (wv * R + 4) * TW + lx + 4;
 #pragma unroll
@@ -385,9 +413,9 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
                 acc = acc + CM[m - 1] * (((tc[m] + tc[-m]) + (tc[m * TW] + tc[-m * TW])) + (q[c][4 + m] + q[c][4 - m]));
             T v = ((T)2 * q[c][4] - pm[c]) + w[c] * acc;
             if (srcc[c] && z == sz) v = v + (T)(src_table ? src_table[*step_ctr + j.src_off] : j.amp);
-            if (cin[c]) ring_plane_t<T>(j.dst, z)[off[c]] = v;
+            if (cin[c]) pd[off[c]] = v;
         }
-        if (more) stage_store(b ^ 1);
+        if (more) stage_store(lds + (b ^ 1) * TP);
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < R; ++c)
