@@ -351,14 +351,17 @@ FP64_SHAPE = (1152, 1152, 1152)  # the interior of the paper's (1152 + 2*4)^3 gr
 FP64_SLABS = 8
 FP64_K = 12
 FP64_CAP = 32 << 30              # device arena: the 32 GB of the paper's GPU
-FP64_CODES = (("code1", [0, 0, 0]), ("code2", [0, 32, 0]), ("code3", [0, 0, 32]), ("code4", [0, 24, 24]),
-              ("all24", [24, 24, 24]))
+FP64_CODES = (("code1", [0, 0, 0], False), ("code2", [0, 32, 0], False), ("code3", [0, 0, 32], False),
+              ("code4", [0, 24, 24], False), ("all24", [24, 24, 24], False),
+              ("code4_ro_device_store", [0, 24, 24], True), ("all24_ro_device_store", [24, 24, 24], True))
 
 
 def fp64_replica(api, torch, inputs, wi, state, rounds=2):
     """The paper's four codes in FP64 (1 = no compression, 2 = p(n-1) at 32
     bits/value, 3 = the read-only field at 32, 4 = both at 24; and every
-    field at 24) on the 1152^3 grid. Synthetic data: the 1024^3 FP32 state
+    field at 24) on the 1152^3 grid, in the paper's flow (the read-only
+    chunks streamed every residency), and codes 4 and all-24 with the
+    read-only store held in the arena. Synthetic data: the 1024^3 FP32 state
     at step WAVE_START placed in the grid's low corner, cast to double, and
     the layered model on the whole grid in double. One untimed round, then
     `rounds` timed rounds per code; snake sweeps."""
@@ -382,9 +385,9 @@ def fp64_replica(api, torch, inputs, wi, state, rounds=2):
            "data": f"1024^3 FP32 wavefield of step {WAVE_START} in the low corner, cast to double; layered model "
                    "in double", "codes": {}}
     cells = float(nx * ny * nz) * FP64_K * rounds
-    for name, rates in FP64_CODES:
+    for name, rates, ro_dev in FP64_CODES:
         plan = api.OutOfCorePlan(FP64_SHAPE, api.WAVE25, FP64_SLABS, FP64_K, rates, FP64_CAP, src_cell=cell,
-                                 fp64=True, snake=True)
+                                 fp64=True, snake=True, ro_device_store=ro_dev)
         st = [bufs[f][:plan.store_bytes(f)] for f in range(3)]
         for f, a in enumerate((p, pm, w)):
             plan.put(f, a, st[f])
@@ -399,6 +402,7 @@ def fp64_replica(api, torch, inputs, wi, state, rounds=2):
         dt = time.perf_counter() - t0
         out["codes"][name] = {
             "rates_bits_per_double": rates,
+            "read_only_store_on_device": ro_dev,
             "gcells_per_s": cells / dt / 1e9,
             "ms_per_round": dt / rounds * 1e3,
             "h2d_GBps": s.h2d_bytes / dt / 1e9,

@@ -70,6 +70,11 @@ struct LaunchParams {
     int32_t njobs;
     const float* src_table;    // wave source amplitudes of the current run chunk (device), or null
     const int32_t* step_ctr;   // device counter: steps done in the chunk before this residency
+    // Workgroups of the jobs before the codec jobs, and of the codec jobs:
+    // with both present, workgroup b of the launch runs the (b*ncodec /
+    // (nfirst+ncodec))-th codec workgroup where that index steps up, so the
+    // codec workgroups are spread evenly among the others (0: plain order).
+    int32_t nfirst, ncodec;
     int32_t wg_begin[kMaxJobs + 1];  // prefix sums of wg_count
     Job jobs[kMaxJobs];
 };

@@ -156,10 +156,23 @@ __device__ inline void xfer_job(const Job& j, int wg)
 // machine around them. MID: the decode jobs reconstruct cut-off digits at
 // mid-points (a separate kernel: the extra registers would make the common
 // kernel spill).
+// Launch-order workgroup index: with codec jobs and other jobs present,
+// block b takes the next codec workgroup wherever floor(b*C/T) steps up
+// (T = all workgroups, C = codec ones), else the next other workgroup; the
+// codec jobs come last in the job list, so codec workgroup c is nfirst + c.
+__device__ inline int spread_wg(const LaunchParams& p)
+{
+    const int b = (int)blockIdx.x;
+    if (p.ncodec == 0 || p.nfirst == 0) return b;
+    const int64_t T = (int64_t)p.nfirst + p.ncodec;
+    const int c0 = (int)((int64_t)b * p.ncodec / T), c1 = (int)((int64_t)(b + 1) * p.ncodec / T);
+    return c1 > c0 ? p.nfirst + c0 : b - c0;
+}
+
 template <bool MID>
 __global__ void __launch_bounds__(kBlockThreads) fused_kernel(LaunchParams p)
 {
-    const int wg = (int)blockIdx.x;
+    const int wg = spread_wg(p);
     int jdx = 0;
     while (jdx + 1 < p.njobs && wg >= p.wg_begin[jdx + 1]) ++jdx;
     const Job& j = p.jobs[jdx];
@@ -284,6 +297,8 @@ static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, siz
     p.wg_begin[p.njobs] = total;
     if (total == 0) return false;
     *grid = (unsigned)total;
+    p.nfirst = p.ncodec = 0;
+    for (int i = 0; i < n; ++i) (is_codec_job(p.jobs[i].kind) ? p.ncodec : p.nfirst) += p.jobs[i].wg_count;
     size_t tb_lds = 0;  // stencil jobs' LDS: blocked heat edge rows, staged wave planes
     bool wave = false, heat_only = true;
     for (int i = 0; i < n; ++i) {
