@@ -316,9 +316,21 @@ __device__ inline void ring_copy_job(const Job& j, int nx, int ny, int wg, bool 
 
 // Wave levels are the FP32 pipeline's LDS-staged tile in double (the same
 // operation order as the FP64 step above).
+// The codec workgroups (the last ones of the job list) spread evenly among
+// the others, as in the FP32 pipeline kernel: block b takes the next codec
+// workgroup wherever floor(b*C/T) steps up.
+__device__ inline int spread64(const LaunchParams& p)
+{
+    const int b = (int)blockIdx.x;
+    if (p.ncodec == 0 || p.nfirst == 0) return b;
+    const int64_t T = (int64_t)p.nfirst + p.ncodec;
+    const int c0 = (int)((int64_t)b * p.ncodec / T), c1 = (int)((int64_t)(b + 1) * p.ncodec / T);
+    return c1 > c0 ? p.nfirst + c0 : b - c0;
+}
+
 __global__ void __launch_bounds__(kBlockThreads) fused64_kernel(LaunchParams p)
 {
-    const int wg = (int)blockIdx.x;
+    const int wg = spread64(p);
     int jdx = 0;
     while (jdx + 1 < p.njobs && wg >= p.wg_begin[jdx + 1]) ++jdx;
     const Job& j = p.jobs[jdx];
@@ -380,6 +392,9 @@ bool prepare_jobs_f64(LaunchParams& p, const void** func, unsigned* grid, size_t
     }
     p.wg_begin[p.njobs] = total;
     if (total == 0) return false;
+    p.nfirst = p.ncodec = 0;
+    for (int i = 0; i < n; ++i)
+        ((p.jobs[i].kind == JOB_DECODE || p.jobs[i].kind == JOB_ENCODE) ? p.ncodec : p.nfirst) += p.jobs[i].wg_count;
     size_t need = 0;
     for (int i = 0; i < n; ++i) {
         if (p.jobs[i].kind == JOB_WAVE) need = std::max(need, stencil::wave_tile_lds<double, codec64::kTileY64>());
