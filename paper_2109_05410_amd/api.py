@@ -510,11 +510,14 @@ class OutOfCorePlan:
 
 class WaveProblem:
     """A wave misfit problem: source wavelet, receivers, observed records and
-    checkpoint policy. Holds the device workspace and the pinned host
-    checkpoint store (allocated here with torch, handed to the library)."""
+    checkpoint policy. Holds the device workspace and the host checkpoint
+    store (allocated here with torch, handed to the library). pinned: True =
+    pinned host memory, False = pageable memory (the runtime stages the
+    copies), None = pinned where the host can pin the whole store, else
+    pageable (ckpt_pinned says which)."""
 
     def __init__(self, shape, steps: int, src_amps, src_cell, rcv_cells, observed, vscale: float,
-                 ckpt_every: int = 10, ckpt_rate: int = 0, device="cuda"):
+                 ckpt_every: int = 10, ckpt_rate: int = 0, device="cuda", pinned: bool | None = None):
         nz, ny, nx = shape
         c = L.AdjointCfg()
         c.nx, c.ny, c.nz = nx, ny, nz
@@ -540,7 +543,17 @@ class WaveProblem:
         if wb == 0:
             L.check(L.OOCS_E_ARG)
         self.work = torch.empty(wb, dtype=torch.uint8, device=device)
-        self.ckpt = torch.empty(int(L.lib().oocs_adjoint_ckpt_bytes(C.byref(c))), dtype=torch.uint8, pin_memory=True)
+        nbytes = int(L.lib().oocs_adjoint_ckpt_bytes(C.byref(c)))
+        self.ckpt = None
+        if pinned is not False:
+            try:
+                self.ckpt = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+            except (RuntimeError, torch.OutOfMemoryError):
+                if pinned:
+                    raise
+        self.ckpt_pinned = self.ckpt is not None
+        if self.ckpt is None:
+            self.ckpt = torch.empty(nbytes, dtype=torch.uint8)
         # forward() overwrites the one checkpoint store and residual buffer:
         # each call gets a new generation, and a gradient is only valid for
         # the generation it was taken from

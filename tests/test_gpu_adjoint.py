@@ -117,6 +117,28 @@ def test_compressed_checkpoints_match_oracle_fp32_bitwise(ckpt_every, steps):
     assert np.array_equal(g, gv)
 
 
+@pytest.mark.parametrize("rate", [0, 12])
+def test_pageable_checkpoint_store_gives_the_same_gradient(rate):
+    """The checkpoint store in pageable host memory (what the bench falls
+    back to where the host cannot pin it whole): the same residuals and the
+    same gradient bit for bit as with pinned memory."""
+    shape = (32, 28, 36)
+    steps = 45
+    v, v_true, c, amps, cell, src_idx, rcv = problem_inputs(shape, steps)
+    _, obs = O.wave_forward_states(w_of(v_true, c), steps, (amps, src_idx), rcv, dtype=np.float32)
+    vd = torch.from_numpy(v).to(DEV)
+    out = []
+    for pinned in (True, False):
+        prob = api.WaveProblem(shape, steps, amps, cell, rcv, obs, float(c), ckpt_every=10, ckpt_rate=rate,
+                               pinned=pinned)
+        assert prob.ckpt_pinned == pinned
+        J = prob.forward(vd)
+        out.append((J, prob.res.clone(), prob.gradient(vd), prob.ckpt.clone()))
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1:], out[1][1:]):
+        assert torch.equal(a.cpu(), b.cpu())
+
+
 def test_compressed_checkpoints_report_gradient_deviation():
     shape = (32, 28, 36)
     steps = 60
