@@ -384,17 +384,21 @@ def wave_light_cone_point(d, steps, z, y, x):
     return p[z - z0, y - y0, x - x0]
 
 
+@pytest.mark.parametrize("policy", ["plain", "bench"])
 @pytest.mark.parametrize("rate", [0, 12])
-def test_full_size_wave_configuration(rate):
+def test_full_size_wave_configuration(rate, policy):
     """1024^3 wave, 8 slabs of 128 planes, k = 12 (h = 48), device arena
-    capped at 8 GiB, two residencies (the benchmark's wave configuration):
-    uncompressed, sampled cells on and around slab boundaries and near the
-    source equal the oracle on their light cones; at 12 bits per value the
-    store equals the GPU's in-core replay (12 steps, then decode(encode())
-    of both time levels; w quantised once) bit for bit."""
+    capped at 8 GiB, two residencies (the benchmark's wave configuration;
+    "bench": the flags the benchmark runs with, snake sweeps and the
+    read-only store held in the arena): uncompressed, sampled cells on and
+    around slab boundaries and near the source equal the oracle on their
+    light cones; at 12 bits per value the store equals the GPU's in-core
+    replay (12 steps, then decode(encode()) of both time levels; w quantised
+    once) bit for bit."""
     d = _wave_full_inputs()
     shape, steps, k = d["shape"], 24, 12
-    plan = api.OutOfCorePlan(shape, api.WAVE25, 8, k, [rate] * 3, 8 << 30, src_cell=d["cell"])
+    flags = {"snake": True, "ro_device_store": True} if policy == "bench" else {}
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 8, k, [rate] * 3, 8 << 30, src_cell=d["cell"], **flags)
     assert plan.info["arena_needed"] <= 8 << 30
     st = [store_of(plan, 0, d["p0"]), store_of(plan, 1, d["pm0"]), store_of(plan, 2, d["w"])]
     plan.run(st, steps, src_amps=d["amps"])

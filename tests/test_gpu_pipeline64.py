@@ -87,3 +87,28 @@ def test_fp64_uncompressed_out_of_core_equals_in_core_step():
     torch.cuda.synchronize()
     assert np.array_equal(decoded(st[0], shape, 0), p.cpu().numpy())
     assert np.array_equal(decoded(st[1], shape, 0), pm.cpu().numpy())
+
+
+@pytest.mark.parametrize("rates,flags", [([24, 24, 24], {"snake": True, "ro_device_store": True}),
+                                         ([0, 24, 24], {"snake": True}), ([0, 0, 0], {})])
+def test_fp64_at_the_papers_decomposition(rates, flags):
+    """The paper's z decomposition (1152 planes, 8 blocks of 144, k = 12,
+    halo 48) on a 128 x 128 cross-section, three residencies, the bench's
+    flags: the stores equal the GPU's in-core FP64 replay of the compressed
+    schedule bit for bit (the replay's own parity with the oracle is pinned
+    on small grids above)."""
+    shape = (1152, 128, 128)
+    steps, k = 36, 12
+    p0, pm0, w, amps = fields(shape, 7, steps)
+    cell = (64, 64, 16)
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 8, k, rates, 256 * MiB, src_cell=cell, fp64=True, **flags)
+    st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
+    plan.run(st, steps, src_amps=amps)
+    p = torch.from_numpy(p0).to(DEV)
+    pm = torch.from_numpy(pm0).to(DEV)
+    wd = torch.from_numpy(w).to(DEV)
+    api.wave64_compressed_run(p, pm, wd, steps, k, src=(amps.astype(np.float64), cell), rate_p=rates[0],
+                              rate_pm=rates[1], rate_w=rates[2])
+    torch.cuda.synchronize()
+    assert np.array_equal(decoded(st[0], shape, rates[0]), p.cpu().numpy())
+    assert np.array_equal(decoded(st[1], shape, rates[1]), pm.cpu().numpy())
