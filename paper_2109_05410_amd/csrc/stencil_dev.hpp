@@ -328,7 +328,6 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
     const T CM[4] = {C1, C2, C3, C4};
     constexpr int R = TY / 4;                                           // cells per thread
     constexpr int TW = kWaveTileW, TP = wave_tile_plane<TY>();
-    constexpr int LPT = (TP + kBlockThreads - 1) / kBlockThreads;      // staged values per thread
     const int tiles_x = (nx + 63) / 64;
     const int tiles_y = (ny + TY - 1) / TY;
     const int tile = wg % (tiles_x * tiles_y);
@@ -348,40 +347,65 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
         srcc[c] = j.has_src && x == sx && y == sy;
         off[c] = (int64_t)y * nx + x;
     }
-    // staged element e = tid + kBlockThreads*i is (x0-4 + e % TW, y0-4 + e / TW)
-    int64_t soff[LPT];
-    bool sok[LPT];
+    // A staged plane is the tile's centre (this workgroup's cells, TY rows of
+    // 64) and its 4-cell halo ring. The centre values are p(z') at the
+    // thread's own cells, which the thread already holds in its column
+    // queue (read as p(z+4) three planes earlier), so only the halo ring is
+    // loaded: halo element h = tid + kBlockThreads*i is the h-th cell of the
+    // ring (the 4 rows above, the 4 rows below, then 4 columns left and 4
+    // right of each centre row).
+    constexpr int HALO = TP - 64 * TY;
+    constexpr int HPT = (HALO + kBlockThreads - 1) / kBlockThreads;  // halo values per thread
+    int64_t soff[HPT];
+    int sidx[HPT];  // position in the staged plane
+    bool sok[HPT], shas[HPT];
 #pragma unroll
-    for (int i = 0; i < LPT; ++i) {
-        const int e = tid + kBlockThreads * i;
-        const int gx = x0 - 4 + e % TW, gy = y0 - 4 + e / TW;
-        sok[i] = e < TP && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    for (int i = 0; i < HPT; ++i) {
+        const int h = tid + kBlockThreads * i;
+        int r, cl;
+        if (h < 4 * TW) {
+            r = h / TW; cl = h % TW;
+        } else if (h < 8 * TW) {
+            r = TY + 4 + (h - 4 * TW) / TW; cl = (h - 4 * TW) % TW;
+        } else {
+            const int e = h - 8 * TW;  // side columns: 8 per centre row
+            r = 4 + e / 8;
+            cl = (e % 8) < 4 ? (e % 8) : 64 + (e % 8);
+        }
+        shas[i] = h < HALO;
+        sidx[i] = shas[i] ? r * TW + cl : 0;
+        const int gx = x0 - 4 + cl, gy = y0 - 4 + r;
+        sok[i] = shas[i] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
         soff[i] = (int64_t)gy * nx + gx;
     }
-    T st[LPT];
+    T st[HPT];
     // staged planes are taken in order z0, z0 + 1, ...
     PlaneCursor<T> cs(j.src, z0), cpm(j.src2, z0), cw(j.ro, z0), cd(j.dst, z0);
-    auto stage_load = [&](int z) {  // the cursor's plane, z; planes outside the grid stage as zeros
+    auto stage_load = [&](int z) {  // the halo of the cursor's plane, z; planes outside the grid stage as zeros
         const bool zin = z < nz;
         const T* pl = cs.plane();
         cs.next();
 #pragma unroll
-        for (int i = 0; i < LPT; ++i) st[i] = (zin && sok[i]) ? pl[soff[i]] : (T)0;
+        for (int i = 0; i < HPT; ++i) st[i] = (zin && sok[i]) ? pl[soff[i]] : (T)0;
     };
-    auto stage_store = [&](T* t) {
+    T q[R][9];  // q[c][i] = p(z - 4 + i) at cell c
+    // the staged halo, and the centre from the column queue entry `at` (this
+    // thread's cells of the plane being staged; zero outside the grid)
+    auto stage_store = [&](T* t, int at) {
 #pragma unroll
-        for (int i = 0; i < LPT; ++i)
-            if (tid + kBlockThreads * i < TP) t[tid + kBlockThreads * i] = st[i];
+        for (int i = 0; i < HPT; ++i)
+            if (shas[i]) t[sidx[i]] = st[i];
+#pragma unroll
+        for (int c = 0; c < R; ++c) t[(wv * R + c + 4) * TW + lx + 4] = q[c][at];
     };
     auto col = [&](int c, int z) -> T { return (cin[c] && z >= 0 && z < nz) ? ring_plane_t<T>(j.src, z)[off[c]] : (T)0; };
     PlaneCursor<T> ccol(j.src, z0 + 4);  // p(z + 4) at the cell, read plane by plane
-    T q[R][9];  // q[c][i] = p(z - 4 + i) at cell c
 #pragma unroll
     for (int c = 0; c < R; ++c)
 #pragma unroll
         for (int i = 0; i < 8; ++i) q[c][i] = col(c, z0 - 4 + i);
     stage_load(z0);
-    stage_store(lds);
+    stage_store(lds, 4);
     __syncthreads();
     for (int z = z0; z < z1; ++z) {
         const int b = (z - z0) & 1;
@@ -415,7 +439,7 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
             if (srcc[c] && z == sz) v = v + (T)(src_table ? src_table[*step_ctr + j.src_off] : j.amp);
             if (cin[c]) pd[off[c]] = v;
         }
-        if (more) stage_store(lds + (b ^ 1) * TP);
+        if (more) stage_store(lds + (b ^ 1) * TP, 5);  // plane z + 1
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < R; ++c)
