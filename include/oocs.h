@@ -188,7 +188,7 @@ typedef struct {
     int32_t stencil;                /* OOCS_HEAT7 or OOCS_WAVE25 */
     int32_t nslabs;                 /* blocks along z; nz % nslabs == 0 */
     int32_t k;                      /* steps per residency (temporal blocking), >= 1 */
-    int32_t group;                  /* planes per pipeline group (multiple of 4); 0 = largest that fits */
+    int32_t group;                  /* planes per pipeline group (multiple of 4); 0 = the largest that fits, at most 32 (16 for the wave) */
     int32_t rate[OOCS_MAX_FIELDS];  /* bits per value of each field's host store; 0 = uncompressed */
     int32_t nstage;                 /* staging slots per direction (>= 2); 0 = default (4, or 2 with kernel transfers) */
     float alpha;                    /* heat diffusion number (u += alpha * Laplacian) */
@@ -294,8 +294,9 @@ typedef struct {
 /* Create a plan. d_arena (arena_bytes long) is the only device memory the
  * pipeline will use; pass NULL to make a planning-only plan that can be
  * queried but not run (no HIP call is made for it). Chooses the group size
- * (when cfg->group == 0) as the largest multiple of 4 whose rings and
- * staging fit arena_bytes. The plan keeps d_arena; the caller keeps it
+ * (when cfg->group == 0) as the largest multiple of 4, at most 32 planes (16
+ * for the wave, whose ticks are long already), whose rings and staging fit
+ * arena_bytes. The plan keeps d_arena; the caller keeps it
  * alive until oocs_plan_destroy.
  * Errors: OOCS_E_ARG, OOCS_E_ALIGN (a compressed field with nz/nslabs or h
  * not a multiple of 4), OOCS_E_HALO (2h > nz/nslabs), OOCS_E_RATE, OOCS_E_CAP
