@@ -741,7 +741,7 @@ def cpu_baseline(wi, state):
     pm = O.codec_roundtrip_f64(pm, HEADLINE_RATE)
     t = time.perf_counter() - t0
     cells = float(nx * ny * nz) * WAVE_K
-    return {
+    out = {
         "value": cells / t / 1e9,
         "unit": "GCell-updates/s",
         "cores": threads,
@@ -749,7 +749,60 @@ def cpu_baseline(wi, state):
         "sample": f"one residency ({WAVE_K} FP64 wave steps + decode(encode()) of p(n), p(n-1) at "
                   f"{HEADLINE_RATE} bits/value) on planes 0..{CPU_SAMPLE_PLANES - 1} of the 1024^2 x 1024 grid "
                   f"from the step-{WAVE_START} state, {t:.1f} s",
+        "host_cpu": _cpu_model(),
     }
+    out["single_thread"] = _oracle_one_thread(wi, state)
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+CPU_ONE_THREAD_PLANES = 8
+
+
+def _oracle_one_thread(wi, state):
+    """The same residency on planes 0..7 with one OpenMP thread, in a child
+    process (the thread count is fixed when the oracle's runtime starts)."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
+    sl = slice(0, CPU_ONE_THREAD_PLANES)
+    cx, cy, cz = wi.cell
+    with tempfile.TemporaryDirectory() as td:
+        np.save(os.path.join(td, "p.npy"), state[0][sl])
+        np.save(os.path.join(td, "pm.npy"), state[1][sl])
+        np.save(os.path.join(td, "w.npy"), wi.w[sl])
+        np.save(os.path.join(td, "a.npy"), wi.amps[WAVE_START:WAVE_START + WAVE_K])
+        code = (
+            "import sys, time, numpy as np; sys.path.insert(0, sys.argv[1]); import oracle as O; d = sys.argv[2]\n"
+            "p, pm, w = (np.load(d + f).astype(np.float64) for f in ('/p.npy', '/pm.npy', '/w.npy'))\n"
+            "a = np.load(d + '/a.npy').astype(np.float64); nz, ny, nx = p.shape\n"
+            f"src = (a, {cx} + nx * ({cy} + ny * {cz}))\n"
+            "O.lib(); t0 = time.perf_counter()\n"
+            f"p, pm = O.wave25_f64(p, pm, w, {WAVE_K}, src=src)\n"
+            f"p = O.codec_roundtrip_f64(p, {HEADLINE_RATE}); pm = O.codec_roundtrip_f64(pm, {HEADLINE_RATE})\n"
+            "print(time.perf_counter() - t0)\n"
+        )
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code, ROOT, td], capture_output=True, text=True, env=env,
+                           timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr[-300:]}
+    t = float(r.stdout.strip().splitlines()[-1])
+    cells = float(CPU_ONE_THREAD_PLANES * WAVE_SHAPE[1] * WAVE_SHAPE[2]) * WAVE_K
+    return {"value": cells / t / 1e9, "unit": "GCell-updates/s", "cores": 1,
+            "sample": f"the same residency on planes 0..{CPU_ONE_THREAD_PLANES - 1}, {t:.1f} s"}
 
 
 def copy_probe():
