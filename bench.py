@@ -766,11 +766,11 @@ def _cpu_model():
     return None
 
 
-CPU_ONE_THREAD_PLANES = 8
+CPU_ONE_THREAD_PLANES = 32
 
 
 def _oracle_one_thread(wi, state):
-    """The same residency on planes 0..7 with one OpenMP thread, in a child
+    """The same residency on planes 0..31 with one OpenMP thread, in a child
     process (the thread count is fixed when the oracle's runtime starts)."""
     import subprocess
     import tempfile
