@@ -194,6 +194,7 @@ typedef struct {
     float alpha;                    /* heat diffusion number (u += alpha * Laplacian) */
     int32_t flags;                  /* OOCS_PLAN_* flags, or 0 */
     int64_t src_x, src_y, src_z;    /* wave source cell; any < 0 = no source */
+    int32_t retain;                 /* snake plans: slabs in the retained region (see OOCS_PLAN_SNAKE); 0 = one */
 } oocs_config;
 
 /* Plan flag. Without it a residency streams the whole grid through the
@@ -259,10 +260,18 @@ typedef struct {
  * neither way; the read-only field is still streamed. Same results (the
  * retained planes pass through the codec exactly as the stored ones).
  * Needs the copy-engine transfers (no OOCS_PLAN_KERNEL_TRANSFERS or
- * OOCS_PLAN_KERNEL_STORES), no OOCS_PLAN_BLOCK_RESTART and nslabs >= 2;
- * the retained buffers take one slab of every read-write field from the
- * arena. */
+ * OOCS_PLAN_KERNEL_STORES), no OOCS_PLAN_BLOCK_RESTART and nslabs >= 2.
+ * oocs_config.retain sets how many slabs the retained region spans: 0 or 1
+ * = the last block only; 1 < m <= nslabs / 2 = the last m blocks (a
+ * region that also holds the planes a residency writes back while its
+ * pipeline drains, and the next one loads while its pipeline fills, keeps
+ * both phases off the host link); OOCS_RETAIN_MAX = the most slabs, up to
+ * nslabs / 2, that fit in the arena beside the pipeline chosen with one.
+ * The retained buffers take retain * slab planes of every read-write
+ * field's store from the arena; oocs_plan_get_info reports the planes.
+ * Any other value, or a nonzero retain without this flag, is OOCS_E_ARG. */
 #define OOCS_PLAN_SNAKE 32
+#define OOCS_RETAIN_MAX (-1)
 
 /* Plan flag: every decode of the plan (the residencies' decode jobs, the
  * resident read-only load, oocs_store_get) uses mid-point reconstruction
@@ -317,7 +326,7 @@ typedef struct {
     int64_t arena_needed;       /* device bytes the plan uses (<= arena size) */
     int64_t nstage;             /* staging slots per direction */
     int64_t store_bytes[OOCS_MAX_FIELDS]; /* host store bytes per field (0 for an unused slot) */
-    int64_t retained_planes;    /* planes of the retained block (snake plans), else 0 */
+    int64_t retained_planes;    /* planes of the retained region (snake plans), else 0 */
 } oocs_plan_info;
 
 int oocs_plan_get_info(const oocs_plan* plan, oocs_plan_info* out);

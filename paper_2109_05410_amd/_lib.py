@@ -33,6 +33,7 @@ OOCS_PLAN_LEVEL_BY_LEVEL = 4
 OOCS_PLAN_KERNEL_STORES = 8
 OOCS_PLAN_RESIDENT_RO = 16
 OOCS_PLAN_SNAKE = 32
+OOCS_RETAIN_MAX = -1
 OOCS_PLAN_MIDPOINT = 64
 OOCS_PLAN_FP64 = 128
 OOCS_PLAN_RO_DEVICE_STORE = 256
@@ -59,6 +60,7 @@ class Config(C.Structure):
         ("rate", C.c_int32 * OOCS_MAX_FIELDS), ("nstage", C.c_int32),
         ("alpha", C.c_float), ("flags", C.c_int32),
         ("src_x", C.c_int64), ("src_y", C.c_int64), ("src_z", C.c_int64),
+        ("retain", C.c_int32),
     ]
 
 

@@ -276,6 +276,7 @@ def wave25_step_k(p: torch.Tensor, pm: torch.Tensor, w: torch.Tensor, k: int, sr
 
 HEAT7 = L.OOCS_HEAT7
 WAVE25 = L.OOCS_WAVE25
+RETAIN_MAX = L.OOCS_RETAIN_MAX
 
 
 def link_probe(nbytes: int = 256 << 20, chunk: int = 4 << 20, reps: int = 3, sdma: int = 1) -> dict:
@@ -343,7 +344,9 @@ class OutOfCorePlan:
     once into the arena and stays there instead of being streamed every
     residency. snake: residencies alternate the sweep direction and the
     block a residency ends with stays on the device (compressed, or raw if
-    uncompressed) for the next one. Results are identical. midpoint: every
+    uncompressed) for the next one; retain (snake): the region kept there
+    spans that many slabs (0 = one, at most nslabs // 2), or as many as the
+    arena holds with OOCS_RETAIN_MAX. Results are identical. midpoint: every
     decode reconstructs the digits the budget cut off at the middle of their
     range (a different, lower-error state). fp64 (wave): FP64 fields and
     the FP64 block format (rates up to 68); put/get take and return float64
@@ -357,7 +360,7 @@ class OutOfCorePlan:
                  planning_only: bool = False, device=None, block_restart: bool = False,
                  kernel_transfers: bool = False, level_by_level: bool = False, kernel_stores: bool = False,
                  resident_ro: bool = False, snake: bool = False, midpoint: bool = False, fp64: bool = False,
-                 ro_device_store: bool = False):
+                 ro_device_store: bool = False, retain: int = 0):
         nz, ny, nx = shape
         cfg = L.Config()
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
@@ -380,6 +383,7 @@ class OutOfCorePlan:
                      | (L.OOCS_PLAN_RO_DEVICE_STORE if ro_device_store else 0))
         sx, sy, sz = src_cell if src_cell is not None else (-1, -1, -1)
         cfg.src_x, cfg.src_y, cfg.src_z = sx, sy, sz
+        cfg.retain = retain
         self.cfg = cfg
         self.shape = (nz, ny, nx)
         self.dtype = np.float64 if fp64 else np.float32

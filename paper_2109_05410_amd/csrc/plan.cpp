@@ -89,7 +89,15 @@ int Planner::init(const oocs_config& c, std::string& err)
         err = "snake sweeps need copy-engine transfers, shared levels and at least two slabs";
         return OOCS_E_ARG;
     }
-    X = snake ? slab : 0;
+    // retained region: whole slabs, at most half the grid, so that the top
+    // and bottom regions a snake alternates between never overlap
+    if (!snake && c.retain != 0) { err = "retain needs a snake plan"; return OOCS_E_ARG; }
+    retain_max = snake && c.retain == OOCS_RETAIN_MAX;
+    if (snake && !retain_max && (c.retain < 0 || c.retain > std::max(1, n / 2))) {
+        err = fmt("retain (%lld) must be 0, OOCS_RETAIN_MAX or in [1, nslabs / 2 = %lld]", c.retain, n / 2);
+        return OOCS_E_ARG;
+    }
+    X = snake ? slab * (retain_max ? 1 : std::max(1, (int)c.retain)) : 0;
     midpoint = (c.flags & OOCS_PLAN_MIDPOINT) != 0;
     // kernel-driven transfers fetch one group ahead inside the launch: two slots suffice;
     // copy engines keep three groups in flight ahead of the decode
@@ -412,7 +420,23 @@ int Planner::choose(size_t arena_bytes, std::string& err)
             const int64_t need = layout(g, ns, err);
             if (need < 0) return OOCS_E_STATE;
             if (best_need < 0 || need < best_need) best_need = need;
-            if ((size_t)need <= arena_bytes) { cache_.clear(); return OOCS_OK; }
+            if ((size_t)need <= arena_bytes) {
+                // OOCS_RETAIN_MAX: grow the retained region slab by slab in the
+                // room the pipeline leaves (it comes after G: a smaller group
+                // for a larger region slows every tick)
+                while (retain_max && X + slab <= nz / 2) {
+                    X += slab;
+                    const int64_t more = layout(g, ns, err);
+                    if (more < 0) return OOCS_E_STATE;
+                    if ((size_t)more > arena_bytes) {
+                        X -= slab;
+                        if (layout(g, ns, err) < 0) return OOCS_E_STATE;
+                        break;
+                    }
+                }
+                cache_.clear();
+                return OOCS_OK;
+            }
         }
     err = fmt("the pipeline needs at least %lld bytes of device arena, %lld given", best_need, (long long)arena_bytes);
     return OOCS_E_CAP;

@@ -92,7 +92,8 @@ public:
     int64_t ro_dev_off = -1;    // its offset there
     bool fp64 = false;          // FP64 fields (wave): 8-byte values, the FP64 format
     int esize = 4;              // bytes per value
-    int64_t X = 0;              // snake: planes of the retained block (one slab)
+    int64_t X = 0;              // snake: planes of the retained region (whole slabs, at most nz / 2)
+    bool retain_max = false;    // snake: X grown to what the arena holds
     static constexpr int kMaxFusedSteps = 4;
     int64_t slab = 0, h = 0;
     std::vector<int64_t> a;  // n+1 block bounds

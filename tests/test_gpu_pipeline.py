@@ -389,15 +389,16 @@ def wave_light_cone_point(d, steps, z, y, x):
 def test_full_size_wave_configuration(rate, policy):
     """1024^3 wave, 8 slabs of 128 planes, k = 12 (h = 48), device arena
     capped at 8 GiB, two residencies (the benchmark's wave configuration;
-    "bench": the flags the benchmark runs with, snake sweeps and the
-    read-only store held in the arena): uncompressed, sampled cells on and
+    "bench": the flags the benchmark runs with, snake sweeps retaining as
+    many slabs as the arena holds and the read-only store held in the
+    arena): uncompressed, sampled cells on and
     around slab boundaries and near the source equal the oracle on their
     light cones; at 12 bits per value the store equals the GPU's in-core
     replay (12 steps, then decode(encode()) of both time levels; w quantised
     once) bit for bit."""
     d = _wave_full_inputs()
     shape, steps, k = d["shape"], 24, 12
-    flags = {"snake": True, "ro_device_store": True} if policy == "bench" else {}
+    flags = {"snake": True, "ro_device_store": True, "retain": api.RETAIN_MAX} if policy == "bench" else {}
     plan = api.OutOfCorePlan(shape, api.WAVE25, 8, k, [rate] * 3, 8 << 30, src_cell=d["cell"], **flags)
     assert plan.info["arena_needed"] <= 8 << 30
     st = [store_of(plan, 0, d["p0"]), store_of(plan, 1, d["pm0"]), store_of(plan, 2, d["w"])]
@@ -422,18 +423,22 @@ def test_full_size_wave_configuration(rate, policy):
 
 
 @pytest.mark.parametrize("graphs", [False, True], ids=["eager", "graph"])
-@pytest.mark.parametrize("rate,k,steps,n,arena,lbl", [
-    (8, 4, 13, 8, 2 * MiB, False), (0, 4, 10, 4, 2 * MiB, False), (16, 4, 9, 2, 3 * MiB, True),
-    (12, 4, 4, 4, 2 * MiB, False),
+@pytest.mark.parametrize("rate,k,steps,n,arena,lbl,retain", [
+    (8, 4, 13, 8, 2 * MiB, False, 0), (0, 4, 10, 4, 2 * MiB, False, 0), (16, 4, 9, 2, 3 * MiB, True, 0),
+    (12, 4, 4, 4, 2 * MiB, False, 0), (8, 4, 13, 8, 3 * MiB, False, 4), (0, 4, 10, 4, 3 * MiB, True, 2),
+    (12, 4, 17, 8, 5 * MiB, False, api.RETAIN_MAX),
 ])
-def test_heat_snake_matches_replay(rate, k, steps, n, arena, lbl, graphs):
-    """Snake sweeps (alternating direction, the last block kept on the
-    device between residencies) give the replay bit for bit: odd and even
-    numbers of residencies, a ragged last one, one residency only, fused and
-    level-by-level heat; a second run on the same plan continues."""
+def test_heat_snake_matches_replay(rate, k, steps, n, arena, lbl, retain, graphs):
+    """Snake sweeps (alternating direction, the last block, or the last
+    `retain` blocks, kept on the device between residencies) give the replay
+    bit for bit: odd and even numbers of residencies, a ragged last one, one
+    residency only, fused and level-by-level heat; a second run on the same
+    plan continues."""
     shape = (128, 64, 64)
     u0 = inputs.heat_uniform(shape, seed=30 + rate)
-    plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena, snake=True, level_by_level=lbl)
+    plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena, snake=True, level_by_level=lbl, retain=retain)
+    if retain:
+        assert plan.info["retained_planes"] == (64 if retain == api.RETAIN_MAX else 128 // n * retain)
     plan.set_graphs(graphs)
     s = store_of(plan, 0, u0)
     plan.run([s], steps)
@@ -458,6 +463,36 @@ def test_wave_snake_matches_replay(rates, resident_ro, graphs):
     idx = cell[0] + shape[2] * (cell[1] + shape[1] * cell[2])
     plan = api.OutOfCorePlan(shape, api.WAVE25, 3, k, rates, 16 * MiB, src_cell=cell, snake=True,
                              resident_ro=resident_ro)
+    plan.set_graphs(graphs)
+    st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
+    plan.run(st, steps, src_amps=amps)
+    wp, wpm, _ = O.replay_wave_f32(p0, pm0, w, steps, k, src=(amps, idx), rate_p=rates[0], rate_pm=rates[1],
+                                   rate_w=rates[2])
+    assert np.array_equal(decoded(st[0], shape, rates[0]), wp)
+    assert np.array_equal(decoded(st[1], shape, rates[1]), wpm)
+
+
+@pytest.mark.parametrize("graphs", [False, True], ids=["eager", "graph"])
+@pytest.mark.parametrize("rates,retain,ro_dev", [([12, 12, 12], 2, True), ([0, 0, 0], 2, False),
+                                                  ([8, 12, 16], api.RETAIN_MAX, True)])
+def test_wave_retained_region_matches_replay(rates, retain, ro_dev, graphs):
+    """Snake sweeps whose retained region spans two of four slabs (half the
+    grid): the region's planes stay compressed (or raw) in the arena from
+    the residency that writes them to the next one, which decodes them
+    first; five residencies, a ragged last one, the source inside the
+    region; bit for bit the replay."""
+    shape = (96, 36, 40)
+    rng = np.random.default_rng(6)
+    p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    pm0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    w = (0.02 + 0.1 * rng.random(shape)).astype(np.float32)
+    steps, k = 14, 3
+    amps = rng.standard_normal(steps).astype(np.float32)
+    cell = (17, 20, 70)
+    idx = cell[0] + shape[2] * (cell[1] + shape[1] * cell[2])
+    plan = api.OutOfCorePlan(shape, api.WAVE25, 4, k, rates, 16 * MiB, src_cell=cell, snake=True, retain=retain,
+                             ro_device_store=ro_dev)
+    assert plan.info["retained_planes"] == 48
     plan.set_graphs(graphs)
     st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
     plan.run(st, steps, src_amps=amps)

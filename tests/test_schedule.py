@@ -637,8 +637,12 @@ def test_full_size_snake_schedules_have_no_races():
 @pytest.mark.parametrize("shape,st,n,k,rates,arena,steps", SNAKE_CASES)
 @pytest.mark.parametrize("level_by_level", [False, True])
 def test_snake_schedule_computes_the_replay(shape, st, n, k, rates, arena, steps, level_by_level):
+    _snake_replay(shape, st, n, k, rates, arena, steps, level_by_level)
+
+
+def _snake_replay(shape, st, n, k, rates, arena, steps, level_by_level, retain=0):
     p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, snake=True,
-             level_by_level=level_by_level)
+             level_by_level=level_by_level, retain=retain)
     rng = np.random.default_rng(11)
     if st == HEAT7:
         u0 = rng.random(shape, dtype=np.float32)
@@ -659,16 +663,17 @@ def test_snake_schedule_computes_the_replay(shape, st, n, k, rates, arena, steps
         assert np.array_equal(from_store(store[1], shape, rates[1]), wpm)
 
 
-@pytest.mark.parametrize("resident_ro", [False, True])
-def test_snake_keeps_the_last_block_off_the_link(resident_ro):
-    """Residency i of R runs upward if i is even, downward if odd; the block
-    it ends with (one slab) is neither written back (unless i = R - 1) nor
-    loaded by the next residency, for the read-write fields; every other
-    plane crosses the link once each way per residency, and the read-only
-    field is loaded whole every residency (or never, if resident)."""
+@pytest.mark.parametrize("resident_ro,retain", [(False, 0), (True, 0), (False, 2), (True, 4)])
+def test_snake_keeps_the_last_block_off_the_link(resident_ro, retain):
+    """Residency i of R runs upward if i is even, downward if odd; the
+    region it ends with (one slab, or `retain` slabs) is neither written
+    back (unless i = R - 1) nor loaded by the next residency, for the
+    read-write fields; every other plane crosses the link once each way per
+    residency, and the read-only field is loaded whole every residency (or
+    never, if resident)."""
     shape, n, k = (1024, 16, 16), 8, 12
-    slab = shape[0] // n
-    p = plan(shape, WAVE25, n, k, [12, 12, 12], 64 * MiB, snake=True, resident_ro=resident_ro)
+    slab = shape[0] // n * max(retain, 1)
+    p = plan(shape, WAVE25, n, k, [12, 12, 12], 64 * MiB, snake=True, resident_ro=resident_ro, retain=retain)
     assert p.info["retained_planes"] == slab
     R = 4
     for i in range(R):
@@ -700,6 +705,56 @@ def test_snake_keeps_the_last_block_off_the_link(resident_ro):
                     want_out[end] = 0
             assert np.array_equal(h2d, want_in), (i, f)
             assert np.array_equal(d2h, want_out), (i, f)
+
+
+# retained regions of several slabs: (case, retain)
+RETAIN_CASES = [
+    (((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, 11), 2),          # half the grid, fused heat
+    (((48, 12, 16), HEAT7, 4, 2, [0], MiB // 4, 9), 2),          # raw
+    (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 8 * MiB, 14), 2),
+    (((96, 12, 12), WAVE25, 6, 2, [8, 0, 8], 8 * MiB, 9), 3),
+    (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 8 * MiB, 14), L.OOCS_RETAIN_MAX),
+]
+
+
+@pytest.mark.parametrize("case,retain", RETAIN_CASES)
+def test_retained_regions_have_no_races(case, retain):
+    shape, st, n, k, rates, arena, steps = case
+    p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, snake=True, retain=retain)
+    assert p.info["retained_planes"] == (shape[0] // 2 if retain == L.OOCS_RETAIN_MAX else shape[0] // n * retain)
+    race_check(p, steps)
+    race_check(p, steps, graph_mode=True)
+
+
+@pytest.mark.parametrize("case,retain", RETAIN_CASES)
+def test_retained_regions_compute_the_replay(case, retain):
+    shape, st, n, k, rates, arena, steps = case
+    _snake_replay(shape, st, n, k, rates, arena, steps, False, retain=retain)
+
+
+def test_retain_max_at_the_wave_size():
+    """1024^3 wave, 8 slabs, k = 12, 8 GiB: at 12 bits per value half the
+    grid's compressed p and p(n-1) fit beside the pipeline (the most a
+    region may hold); raw planes leave room for the one slab only; the
+    group size is the one the plan takes with a single retained slab."""
+    kw = dict(snake=True, ro_device_store=True)
+    one = plan((1024, 1024, 1024), WAVE25, 8, 12, [12, 12, 12], 8 << 30, **kw)
+    most = plan((1024, 1024, 1024), WAVE25, 8, 12, [12, 12, 12], 8 << 30, retain=L.OOCS_RETAIN_MAX, **kw)
+    assert most.info["retained_planes"] == 512 and most.info["arena_needed"] <= 8 << 30
+    assert most.info["group"] == one.info["group"] and most.info["nstage"] == one.info["nstage"]
+    raw = plan((1024, 1024, 1024), WAVE25, 8, 12, [0, 0, 0], 8 << 30, retain=L.OOCS_RETAIN_MAX, **kw)
+    assert raw.info["retained_planes"] == 128
+    race_check(plan((1024, 16, 16), WAVE25, 8, 12, [8, 8, 8], 64 * MiB, snake=True, src_cell=(3, 3, 5),
+                    retain=L.OOCS_RETAIN_MAX), 36)
+
+
+def test_retain_errors():
+    for kw in ({"retain": 3}, {"retain": -2}, {"snake": False, "retain": 1}):
+        with pytest.raises(L.OocsError) as e:
+            plan((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, **{"snake": True, **kw})
+        assert e.value.code == L.OOCS_E_ARG
+    # three slabs: one is the most
+    assert plan((48, 12, 16), HEAT7, 3, 4, [8], 2 * MiB, snake=True, retain=L.OOCS_RETAIN_MAX).info["retained_planes"] == 16
 
 
 def test_snake_needs_copy_engines_shared_levels_and_two_slabs():
