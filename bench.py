@@ -12,8 +12,8 @@ uncompressed and at 8 and 16 bits per value.
 
 Schedule: shared time levels between neighbouring blocks and snake sweeps
 (residencies alternate direction; the blocks a residency ends with stay on
-the device, compressed, for the next one: as many slabs as the arena holds,
-up to half the grid), the orchestration the paper leaves to future work
+the device, compressed, for the next one: as many slabs as the arena holds),
+the orchestration the paper leaves to future work
 (Sec. VII); one retained slab, one-way sweeps and the paper's per-block
 schedule of Fig. 2 are reported beside it. The read-only field's host store
 is copied into the arena once (1.5 GiB at 12 bits, inside the 8 GiB cap) and
@@ -990,11 +990,11 @@ def main():
         "config": {
             "workload": "wave25 1024^3 FP32 (p, p_prev, read-only w), layered 1500-4500 m/s model, 15 Hz Ricker, "
                         "8 z-slabs, k=12 (halo 48), device arena capped at 8 GiB, all three host stores at "
-                        "12 bits/value, snake sweeps retaining up to half the grid, w's compressed store held in "
-                        "the arena; one bench step = one "
+                        "12 bits/value, snake sweeps retaining as many slabs as the arena holds, w's compressed "
+                        "store held in the arena; one bench step = one "
                         "round (every block advanced 12 steps) from the step-2160 state of the 4320-step run",
             "schedule": "shared levels, snake sweeps (alternating direction; the last blocks of a residency, as "
-                        "many slabs as the arena holds up to half the grid, kept compressed on the device); the "
+                        "many slabs as the arena holds, kept compressed on the device); the "
                         "read-only store copied into the arena once and decoded from there every residency",
             "grid": list(WAVE_SHAPE), "nslabs": WAVE_SLABS, "k": WAVE_K, "time_steps_per_bench_step": WAVE_K,
             "device_cap_bytes": WAVE_CAP, "rate_bits_per_value": HEADLINE_RATE,

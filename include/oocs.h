@@ -262,14 +262,20 @@ typedef struct {
  * Needs the copy-engine transfers (no OOCS_PLAN_KERNEL_TRANSFERS or
  * OOCS_PLAN_KERNEL_STORES), no OOCS_PLAN_BLOCK_RESTART and nslabs >= 2.
  * oocs_config.retain sets how many slabs the retained region spans: 0 or 1
- * = the last block only; 1 < m <= nslabs / 2 = the last m blocks (a
- * region that also holds the planes a residency writes back while its
- * pipeline drains, and the next one loads while its pipeline fills, keeps
- * both phases off the host link); OOCS_RETAIN_MAX = the most slabs, up to
- * nslabs / 2, that fit in the arena beside the pipeline chosen with one.
- * The retained buffers take retain * slab planes of every read-write
- * field's store from the arena; oocs_plan_get_info reports the planes.
- * Any other value, or a nonzero retain without this flag, is OOCS_E_ARG. */
+ * = the last block only; 1 < m <= nslabs = the last m blocks (a region
+ * that also holds the planes a residency writes back while its pipeline
+ * drains, and the next one loads while its pipeline fills, keeps both
+ * phases off the host link; with m = nslabs the read-write fields cross
+ * the link only in a call's first and last residency); OOCS_RETAIN_MAX =
+ * the most slabs that fit in the arena beside the pipeline chosen with
+ * one. A residency decodes the region it starts with from the buffer and
+ * encodes the one it ends with into it, plane z of a region at place
+ * z - (its first plane); beyond half the grid the two regions overlap, and
+ * a plane of both is encoded to another place than the one it was decoded
+ * from, after every decode of what that place held. The retained buffers
+ * take retain * slab planes of every read-write field's store from the
+ * arena; oocs_plan_get_info reports the planes. Any other value, or a
+ * nonzero retain without this flag, is OOCS_E_ARG. */
 #define OOCS_PLAN_SNAKE 32
 #define OOCS_RETAIN_MAX (-1)
 

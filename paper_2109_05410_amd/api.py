@@ -345,8 +345,8 @@ class OutOfCorePlan:
     residency. snake: residencies alternate the sweep direction and the
     block a residency ends with stays on the device (compressed, or raw if
     uncompressed) for the next one; retain (snake): the region kept there
-    spans that many slabs (0 = one, at most nslabs // 2), or as many as the
-    arena holds with OOCS_RETAIN_MAX. Results are identical. midpoint: every
+    spans that many slabs (0 = one, at most nslabs), or as many as the
+    arena holds with RETAIN_MAX. Results are identical. midpoint: every
     decode reconstructs the digits the budget cut off at the middle of their
     range (a different, lower-error state). fp64 (wave): FP64 fields and
     the FP64 block format (rates up to 68); put/get take and return float64

@@ -727,10 +727,12 @@ struct OpTranslator {
     void* const* h_store;
     void* const* d_store;  // device addresses of the host stores (kernel-driven transfers), or null
     bool src_on;
+    int variant;  // schedule variant of the residency (addressing of the retained region)
     oocs::LaunchParams lp;
     int64_t h2d = 0, d2h = 0;  // bytes of the transfer jobs added so far
 
-    OpTranslator(oocs_plan* p, void* const* hs, void* const* ds, bool src) : pl(p), h_store(hs), d_store(ds), src_on(src)
+    OpTranslator(oocs_plan* p, void* const* hs, void* const* ds, bool src, int var)
+        : pl(p), h_store(hs), d_store(ds), src_on(src), variant(var)
     {
         const oocs::Planner& P = pl->P;
         lp = base_params(P.nx, P.ny, P.nz, P.cfg.alpha, P.cfg.src_x, P.cfg.src_y, P.cfg.src_z);
@@ -795,8 +797,8 @@ struct OpTranslator {
             j.rate = rate;
             j.mid = dec && P.midpoint ? 1 : 0;
             j.dst = ring(o.level);
-            if (o.slot == OOCS_SLOT_RETAINED)  // snake: the retained block, laid out like the host store
-                j.stage = pl->arena + P.ret_off[o.field] + (o.z0 - P.ret_base(o.z0)) * P.store_plane_bytes(o.field);
+            if (o.slot == OOCS_SLOT_RETAINED)  // snake: the retained region, laid out like the host store
+                j.stage = pl->arena + P.ret_off[o.field] + (o.z0 - P.ret_base(!dec, variant)) * P.store_plane_bytes(o.field);
             else if (o.slot == OOCS_SLOT_DEVICE_STORE)  // the device copy of the read-only store
                 j.stage = pl->arena + P.ro_dev_off + o.z0 * P.store_plane_bytes(o.field);
             else
@@ -872,7 +874,7 @@ int build_graph(oocs_plan* pl, int kr, int variant, void* const* h_store, void* 
         pending[s].clear();
         return d;
     };
-    OpTranslator tr(pl, h_store, d_store, src_on);
+    OpTranslator tr(pl, h_store, d_store, src_on, variant);
     for (const oocs_op& o : sch->ops) {
         switch (o.kind) {
         case OOCS_OP_H2D:
@@ -1106,7 +1108,7 @@ int oocs_run(oocs_plan* pl, void* const* h_store, int64_t steps, const float* h_
                     const int par = prev ? 1 - parity : parity;
                     return 4 * ns + par * P.n + i;
                 };
-                OpTranslator tr(pl, h_store, d_store, src_on);
+                OpTranslator tr(pl, h_store, d_store, src_on, variant);
                 for (const oocs_op& o : sch->ops) {
                     switch (o.kind) {
                     case OOCS_OP_H2D:

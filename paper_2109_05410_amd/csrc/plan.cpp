@@ -89,12 +89,11 @@ int Planner::init(const oocs_config& c, std::string& err)
         err = "snake sweeps need copy-engine transfers, shared levels and at least two slabs";
         return OOCS_E_ARG;
     }
-    // retained region: whole slabs, at most half the grid, so that the top
-    // and bottom regions a snake alternates between never overlap
+    // retained region: whole slabs, up to the whole grid
     if (!snake && c.retain != 0) { err = "retain needs a snake plan"; return OOCS_E_ARG; }
     retain_max = snake && c.retain == OOCS_RETAIN_MAX;
-    if (snake && !retain_max && (c.retain < 0 || c.retain > std::max(1, n / 2))) {
-        err = fmt("retain (%lld) must be 0, OOCS_RETAIN_MAX or in [1, nslabs / 2 = %lld]", c.retain, n / 2);
+    if (snake && !retain_max && (c.retain < 0 || c.retain > n)) {
+        err = fmt("retain (%lld) must be 0, OOCS_RETAIN_MAX or in [1, nslabs = %lld]", c.retain, n);
         return OOCS_E_ARG;
     }
     X = snake ? slab * (retain_max ? 1 : std::max(1, (int)c.retain)) : 0;
@@ -424,7 +423,7 @@ int Planner::choose(size_t arena_bytes, std::string& err)
                 // OOCS_RETAIN_MAX: grow the retained region slab by slab in the
                 // room the pipeline leaves (it comes after G: a smaller group
                 // for a larger region slows every tick)
-                while (retain_max && X + slab <= nz / 2) {
+                while (retain_max && X + slab <= nz) {
                     X += slab;
                     const int64_t more = layout(g, ns, err);
                     if (more < 0) return OOCS_E_STATE;

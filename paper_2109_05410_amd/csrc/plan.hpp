@@ -92,7 +92,7 @@ public:
     int64_t ro_dev_off = -1;    // its offset there
     bool fp64 = false;          // FP64 fields (wave): 8-byte values, the FP64 format
     int esize = 4;              // bytes per value
-    int64_t X = 0;              // snake: planes of the retained region (whole slabs, at most nz / 2)
+    int64_t X = 0;              // snake: planes of the retained region (whole slabs)
     bool retain_max = false;    // snake: X grown to what the arena holds
     static constexpr int kMaxFusedSteps = 4;
     int64_t slab = 0, h = 0;
@@ -118,9 +118,18 @@ public:
     int64_t in_slot_bytes[OOCS_MAX_FIELDS] = {0, 0, 0}, in_off[OOCS_MAX_FIELDS] = {0, 0, 0};
     int64_t out_slot_bytes[OOCS_MAX_FIELDS] = {0, 0, 0}, out_off[OOCS_MAX_FIELDS] = {0, 0, 0};
     int64_t ret_off[OOCS_MAX_FIELDS] = {0, 0, 0};  // snake: retained block of each read-write field
-    // first plane of the retained region that holds plane z (the region is
-    // the top block after an upward pass, the bottom block after a downward one)
-    int64_t ret_base(int64_t z) const { return z >= nz - X ? nz - X : 0; }
+    // First plane of the retained region a decode (encode = false) or an
+    // encode of a residency with schedule variant `variant` addresses: a
+    // residency decodes the region it starts with (the bottom X planes when
+    // it runs upward, the top X downward) and encodes the one it ends with;
+    // the buffer holds plane z of a region at z - base. With X > nz / 2 the
+    // regions overlap and a plane of both is encoded to another place than
+    // the one it was decoded from, later in the residency than any decode
+    // of what that place held (the output front trails the input front).
+    int64_t ret_base(bool encode, int variant) const
+    {
+        return encode != ((variant & OOCS_SCHED_MIRROR) != 0) ? nz - X : 0;
+    }
     int64_t arena_needed = 0;
     // wave source: amplitudes of up to kSrcTable steps and the device step counter
     static constexpr int64_t kSrcTable = 65536;

@@ -426,19 +426,21 @@ def test_full_size_wave_configuration(rate, policy):
 @pytest.mark.parametrize("rate,k,steps,n,arena,lbl,retain", [
     (8, 4, 13, 8, 2 * MiB, False, 0), (0, 4, 10, 4, 2 * MiB, False, 0), (16, 4, 9, 2, 3 * MiB, True, 0),
     (12, 4, 4, 4, 2 * MiB, False, 0), (8, 4, 13, 8, 3 * MiB, False, 4), (0, 4, 10, 4, 3 * MiB, True, 2),
-    (12, 4, 17, 8, 5 * MiB, False, api.RETAIN_MAX),
+    (12, 4, 17, 8, 5 * MiB, False, 6), (12, 4, 17, 8, 5 * MiB, False, api.RETAIN_MAX),
 ])
 def test_heat_snake_matches_replay(rate, k, steps, n, arena, lbl, retain, graphs):
     """Snake sweeps (alternating direction, the last block, or the last
     `retain` blocks, kept on the device between residencies) give the replay
     bit for bit: odd and even numbers of residencies, a ragged last one, one
-    residency only, fused and level-by-level heat; a second run on the same
-    plan continues."""
+    residency only, fused and level-by-level heat, retained regions of half
+    the grid, of more (the regions a residency starts and ends with
+    overlap) and of the whole grid; a second run on the same plan
+    continues."""
     shape = (128, 64, 64)
     u0 = inputs.heat_uniform(shape, seed=30 + rate)
     plan = api.OutOfCorePlan(shape, api.HEAT7, n, k, [rate], arena, snake=True, level_by_level=lbl, retain=retain)
     if retain:
-        assert plan.info["retained_planes"] == (64 if retain == api.RETAIN_MAX else 128 // n * retain)
+        assert plan.info["retained_planes"] == (128 if retain == api.RETAIN_MAX else 128 // n * retain)
     plan.set_graphs(graphs)
     s = store_of(plan, 0, u0)
     plan.run([s], steps)
@@ -474,13 +476,15 @@ def test_wave_snake_matches_replay(rates, resident_ro, graphs):
 
 @pytest.mark.parametrize("graphs", [False, True], ids=["eager", "graph"])
 @pytest.mark.parametrize("rates,retain,ro_dev", [([12, 12, 12], 2, True), ([0, 0, 0], 2, False),
-                                                  ([8, 12, 16], api.RETAIN_MAX, True)])
+                                                  ([12, 12, 12], 3, True), ([8, 12, 16], api.RETAIN_MAX, True)])
 def test_wave_retained_region_matches_replay(rates, retain, ro_dev, graphs):
-    """Snake sweeps whose retained region spans two of four slabs (half the
-    grid): the region's planes stay compressed (or raw) in the arena from
+    """Snake sweeps whose retained region spans two, three or all four
+    slabs: the region's planes stay compressed (or raw) in the arena from
     the residency that writes them to the next one, which decodes them
-    first; five residencies, a ragged last one, the source inside the
-    region; bit for bit the replay."""
+    first (with three slabs the regions a residency starts and ends with
+    overlap; with four nothing crosses the link between a call's first and
+    last residency); five residencies, a ragged last one, the source inside
+    the region; bit for bit the replay."""
     shape = (96, 36, 40)
     rng = np.random.default_rng(6)
     p0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
@@ -492,7 +496,7 @@ def test_wave_retained_region_matches_replay(rates, retain, ro_dev, graphs):
     idx = cell[0] + shape[2] * (cell[1] + shape[1] * cell[2])
     plan = api.OutOfCorePlan(shape, api.WAVE25, 4, k, rates, 16 * MiB, src_cell=cell, snake=True, retain=retain,
                              ro_device_store=ro_dev)
-    assert plan.info["retained_planes"] == 48
+    assert plan.info["retained_planes"] == {2: 48, 3: 72, api.RETAIN_MAX: 96}[retain]
     plan.set_graphs(graphs)
     st = [store_of(plan, 0, p0), store_of(plan, 1, pm0), store_of(plan, 2, w)]
     plan.run(st, steps, src_amps=amps)

@@ -49,6 +49,7 @@ def fields(shape, seed, steps):
     ([40, 24, 24], 4, 13, {"snake": True, "resident_ro": True}),
     ([68, 12, 1], 2, 5, {}),
     ([24, 24, 32], 4, 13, {"snake": True, "ro_device_store": True}),
+    ([24, 24, 32], 4, 13, {"snake": True, "ro_device_store": True, "retain": api.RETAIN_MAX}),
 ])
 def test_fp64_wave_out_of_core_matches_fp64_replay(rates, k, steps, kw, graphs):
     shape = (96, 36, 40)

@@ -145,13 +145,17 @@ class Geometry:
         self.nstage = self.info["nstage"]
         self.X = self.info["retained_planes"]
 
-    def ret_base(self, z):
-        """First plane of the retained region holding plane z."""
-        return self.nz - self.X if z >= self.nz - self.X else 0
+    def ret_base(self, encode, variant):
+        """First plane of the retained region that a decode or an encode of
+        a residency with this schedule variant addresses: the region it
+        starts with (bottom upward, top downward) or the one it ends with;
+        plane z sits at z - base in the buffer."""
+        return self.nz - self.X if encode != bool(variant & L.OOCS_SCHED_MIRROR) else 0
 
 
-def accesses(o, g):
-    """(resource, is_write) pairs of one op."""
+def accesses(o, g, variant=0):
+    """(resource, is_write) pairs of one op of a residency with schedule
+    variant `variant`."""
     K = o["kind"]
     out = []
     if K in (L.OP_H2D, L.OP_FETCH):
@@ -161,8 +165,10 @@ def accesses(o, g):
         out.append((("out", o["field"], o["slot"]), False))
         out += [(("host", o["field"], z), True) for z in range(o["z0"], o["z1"])]
     elif K == L.OP_DECODE:
-        if o["slot"] == L.OOCS_SLOT_RETAINED:  # planes of the retained block, at their place in the buffer
-            out += [(("ret", o["field"], z - g.ret_base(z)), False) for z in range(o["z0"], o["z1"])]
+        if o["slot"] == L.OOCS_SLOT_RETAINED:  # planes of the retained region, at their place in the buffer
+            base = g.ret_base(False, variant)
+            assert 0 <= o["z0"] - base and o["z1"] - base <= g.X, "outside the retained buffer"
+            out += [(("ret", o["field"], z - base), False) for z in range(o["z0"], o["z1"])]
         elif o["slot"] == L.OOCS_SLOT_DEVICE_STORE:  # the device copy of the read-only store (never written)
             out += [(("devstore", o["field"], z), False) for z in range(o["z0"], o["z1"])]
         else:
@@ -171,7 +177,9 @@ def accesses(o, g):
         out += [(("ring", R, z % g.W[R]), True) for z in range(o["z0"], o["z1"])]
     elif K == L.OP_ENCODE:
         if o["slot"] == L.OOCS_SLOT_RETAINED:
-            out += [(("ret", o["field"], z - g.ret_base(z)), True) for z in range(o["z0"], o["z1"])]
+            base = g.ret_base(True, variant)
+            assert 0 <= o["z0"] - base and o["z1"] - base <= g.X, "outside the retained buffer"
+            out += [(("ret", o["field"], z - base), True) for z in range(o["z0"], o["z1"])]
         else:
             out.append((("out", o["field"], o["slot"]), True))
         R = o["level"]
@@ -243,7 +251,8 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
                 i -= n
             return ("blk", (1 - par) if prev else par, i)
 
-        for o in p.schedule(kr, p.variant(rnd, nres)):
+        var = p.variant(rnd, nres)
+        for o in p.schedule(kr, var):
             s = o["stream"]
             K = o["kind"]
             if K == L.OP_RECORD:
@@ -263,7 +272,7 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
                 # gather the launch's accesses, then check them together
                 acc = []
                 for j in pending:
-                    acc += accesses(j, g)
+                    acc += accesses(j, g, var)
                 writes = {}
                 for res, w in acc:
                     if w:
@@ -277,7 +286,7 @@ def race_check(p: OutOfCorePlan, steps: int, graph_mode: bool = False):
                 pending.clear()
             else:  # copies
                 vc[s][s] += 1
-                for res, w in accesses(o, g):
+                for res, w in accesses(o, g, var):
                     access(res, w, s, vc[s][s], -1)
         assert not pending
         done += kr
@@ -397,13 +406,17 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
 
     if p.cfg.flags & L.OOCS_PLAN_RESIDENT_RO:  # decoded once, before the residencies
         rings[g.ro][:nz] = dec(store[2], p.shape, rates[2]) if rates[2] else store[2]
-    retained = {}  # snake: (field, plane) -> that plane's share of the retained block (words of its layer, or raw)
+    # snake: the retained buffer, (field, place) -> the share of the plane
+    # at that place (words of its 4-plane layer, or raw); plane z of the
+    # region an op addresses sits at z - base
+    retained = {}
 
     done, rnd = 0, 0
     nres = -(-steps // g.k)
     while done < steps:
         kr = min(g.k, steps - done)
-        for o in p.schedule(kr, p.variant(rnd, nres)):
+        var = p.variant(rnd, nres)
+        for o in p.schedule(kr, var):
             K = o["kind"]
             z0, z1 = o["z0"], o["z1"]
             if K == L.OP_DECODE and o["slot"] == L.OOCS_SLOT_DEVICE_STORE:
@@ -416,25 +429,29 @@ def execute(p: OutOfCorePlan, store, steps, src_amps, alpha=np.float32(0.1)):
                 continue
             if K == L.OP_DECODE and o["slot"] == L.OOCS_SLOT_RETAINED:
                 f, rate = o["field"], rates[o["field"]]
+                b = g.ret_base(False, var)
+                assert 0 <= z0 - b and z1 - b <= g.X
                 if rate:
-                    data = np.concatenate([retained[(f, z)] for z in range(z0, z1, 4)])
+                    data = np.concatenate([retained[(f, z - b)] for z in range(z0, z1, 4)])
                     planes = dec(data, (z1 - z0, ny, nx), rate)
                 else:
-                    planes = np.stack([retained[(f, z)] for z in range(z0, z1)])
+                    planes = np.stack([retained[(f, z - b)] for z in range(z0, z1)])
                 for z in range(z0, z1):
                     rings[o["level"]][z % g.W[o["level"]]] = planes[z - z0]
                 continue
             if K == L.OP_ENCODE and o["slot"] == L.OOCS_SLOT_RETAINED:
                 f, rate = o["field"], rates[o["field"]]
+                b = g.ret_base(True, var)
+                assert 0 <= z0 - b and z1 - b <= g.X
                 planes = np.stack([plane(o["level"], z) for z in range(z0, z1)])
                 if rate:
                     words = enc(planes, rate)
                     lw = layer_words(rate)
                     for q, z in enumerate(range(z0, z1, 4)):
-                        retained[(f, z)] = words[q * lw:(q + 1) * lw]
+                        retained[(f, z - b)] = words[q * lw:(q + 1) * lw]
                 else:
                     for z in range(z0, z1):
-                        retained[(f, z)] = planes[z - z0].copy()
+                        retained[(f, z - b)] = planes[z - z0].copy()
                 continue
             if K in (L.OP_H2D, L.OP_FETCH):
                 f, rate = o["field"], rates[o["field"]]
@@ -663,7 +680,7 @@ def _snake_replay(shape, st, n, k, rates, arena, steps, level_by_level, retain=0
         assert np.array_equal(from_store(store[1], shape, rates[1]), wpm)
 
 
-@pytest.mark.parametrize("resident_ro,retain", [(False, 0), (True, 0), (False, 2), (True, 4)])
+@pytest.mark.parametrize("resident_ro,retain", [(False, 0), (True, 0), (False, 2), (True, 4), (False, 6)])
 def test_snake_keeps_the_last_block_off_the_link(resident_ro, retain):
     """Residency i of R runs upward if i is even, downward if odd; the
     region it ends with (one slab, or `retain` slabs) is neither written
@@ -707,41 +724,54 @@ def test_snake_keeps_the_last_block_off_the_link(resident_ro, retain):
             assert np.array_equal(d2h, want_out), (i, f)
 
 
-# retained regions of several slabs: (case, retain)
+# retained regions of several slabs: (case, retain, planes retained)
 RETAIN_CASES = [
-    (((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, 11), 2),          # half the grid, fused heat
-    (((48, 12, 16), HEAT7, 4, 2, [0], MiB // 4, 9), 2),          # raw
-    (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 8 * MiB, 14), 2),
-    (((96, 12, 12), WAVE25, 6, 2, [8, 0, 8], 8 * MiB, 9), 3),
-    (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 8 * MiB, 14), L.OOCS_RETAIN_MAX),
+    (((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, 11), 2, 24),          # half the grid, fused heat
+    (((48, 12, 16), HEAT7, 4, 2, [0], MiB // 4, 9), 2, 24),          # raw
+    (((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, 11), 3, 36),          # the regions overlap
+    (((48, 12, 16), HEAT7, 4, 4, [5], 2 * MiB, 9), 4, 48),           # the whole grid
+    (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 8 * MiB, 14), 2, 64),
+    (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 8 * MiB, 14), 3, 96),
+    (((96, 12, 12), WAVE25, 6, 2, [8, 0, 8], 8 * MiB, 9), 5, 80),
+    (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 8 * MiB, 14), L.OOCS_RETAIN_MAX, 128),
+    (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 600_000, 14), L.OOCS_RETAIN_MAX, 64),
+    (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 560_000, 14), L.OOCS_RETAIN_MAX, 32),
 ]
 
 
-@pytest.mark.parametrize("case,retain", RETAIN_CASES)
-def test_retained_regions_have_no_races(case, retain):
+@pytest.mark.parametrize("case,retain,planes", RETAIN_CASES)
+def test_retained_regions_have_no_races(case, retain, planes):
     shape, st, n, k, rates, arena, steps = case
     p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, snake=True, retain=retain)
-    assert p.info["retained_planes"] == (shape[0] // 2 if retain == L.OOCS_RETAIN_MAX else shape[0] // n * retain)
+    assert p.info["retained_planes"] == planes
     race_check(p, steps)
     race_check(p, steps, graph_mode=True)
 
 
-@pytest.mark.parametrize("case,retain", RETAIN_CASES)
-def test_retained_regions_compute_the_replay(case, retain):
+@pytest.mark.parametrize("case,retain,planes", RETAIN_CASES)
+def test_retained_regions_compute_the_replay(case, retain, planes):
     shape, st, n, k, rates, arena, steps = case
     _snake_replay(shape, st, n, k, rates, arena, steps, False, retain=retain)
 
 
 def test_retain_max_at_the_wave_size():
-    """1024^3 wave, 8 slabs, k = 12, 8 GiB: at 12 bits per value half the
-    grid's compressed p and p(n-1) fit beside the pipeline (the most a
-    region may hold); raw planes leave room for the one slab only; the
-    group size is the one the plan takes with a single retained slab."""
+    """1024^3 wave, 8 slabs, k = 12, 8 GiB: at 12 bits per value five of
+    the eight slabs of compressed p and p(n-1) fit beside the pipeline, at
+    8 bits all of them (the grid then crosses the link only in a call's
+    first and last residency), raw planes leave room for the one slab
+    only; the group size is the one the plan takes with a single retained
+    slab, and the plan one slab larger would not fit."""
     kw = dict(snake=True, ro_device_store=True)
     one = plan((1024, 1024, 1024), WAVE25, 8, 12, [12, 12, 12], 8 << 30, **kw)
     most = plan((1024, 1024, 1024), WAVE25, 8, 12, [12, 12, 12], 8 << 30, retain=L.OOCS_RETAIN_MAX, **kw)
-    assert most.info["retained_planes"] == 512 and most.info["arena_needed"] <= 8 << 30
+    assert most.info["retained_planes"] == 640 and most.info["arena_needed"] <= 8 << 30
     assert most.info["group"] == one.info["group"] and most.info["nstage"] == one.info["nstage"]
+    with pytest.raises(L.OocsError) as e:
+        plan((1024, 1024, 1024), WAVE25, 8, 12, [12, 12, 12], 8 << 30, retain=6, group=most.info["group"],
+             nstage=most.info["nstage"], **kw)
+    assert e.value.code == L.OOCS_E_CAP
+    assert plan((1024, 1024, 1024), WAVE25, 8, 12, [8, 8, 8], 8 << 30, retain=L.OOCS_RETAIN_MAX,
+                **kw).info["retained_planes"] == 1024
     raw = plan((1024, 1024, 1024), WAVE25, 8, 12, [0, 0, 0], 8 << 30, retain=L.OOCS_RETAIN_MAX, **kw)
     assert raw.info["retained_planes"] == 128
     race_check(plan((1024, 16, 16), WAVE25, 8, 12, [8, 8, 8], 64 * MiB, snake=True, src_cell=(3, 3, 5),
@@ -749,12 +779,11 @@ def test_retain_max_at_the_wave_size():
 
 
 def test_retain_errors():
-    for kw in ({"retain": 3}, {"retain": -2}, {"snake": False, "retain": 1}):
+    for kw in ({"retain": 5}, {"retain": -2}, {"snake": False, "retain": 1}):
         with pytest.raises(L.OocsError) as e:
             plan((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, **{"snake": True, **kw})
         assert e.value.code == L.OOCS_E_ARG
-    # three slabs: one is the most
-    assert plan((48, 12, 16), HEAT7, 3, 4, [8], 2 * MiB, snake=True, retain=L.OOCS_RETAIN_MAX).info["retained_planes"] == 16
+    assert plan((48, 12, 16), HEAT7, 3, 4, [8], 2 * MiB, snake=True, retain=L.OOCS_RETAIN_MAX).info["retained_planes"] == 48
 
 
 def test_snake_needs_copy_engines_shared_levels_and_two_slabs():
