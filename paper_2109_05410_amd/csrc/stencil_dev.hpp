@@ -315,8 +315,10 @@ struct PlaneCursor {
     __device__ void next() { slot = slot + 1 == W ? 0u : slot + 1; }
 };
 
-// TY: tile rows (a multiple of 4); each thread has TY / 4 cells.
-template <typename T, int TY = kWaveTileY>
+// TY: tile rows (a multiple of 4); each thread has TY / 4 cells. ZC: planes
+// a workgroup marches. PF: the loads of plane z + 1 (p(n-1), w and p(z+5)
+// at the thread's cells) are issued before plane z is computed.
+template <typename T, int TY = kWaveTileY, int ZC = kZChunk, bool PF = true>
 __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, int sy, int sz, const float* src_table,
                                  const int32_t* step_ctr, int wg, T* lds)
 {
@@ -333,8 +335,8 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
     const int tile = wg % (tiles_x * tiles_y);
     const int zc = wg / (tiles_x * tiles_y);
     const int x0 = (tile % tiles_x) * 64, y0 = (tile / tiles_x) * TY;
-    const int z0 = j.z0 + zc * kZChunk;
-    const int z1 = min(j.z1, z0 + kZChunk);
+    const int z0 = j.z0 + zc * ZC;
+    const int z1 = min(j.z1, z0 + ZC);
     if (z0 >= z1) return;  // the same for the whole workgroup
     const int tid = (int)threadIdx.x, lx = tid & 63, wv = tid >> 6;
     const int x = x0 + lx;
@@ -404,29 +406,42 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
     for (int c = 0; c < R; ++c)
 #pragma unroll
         for (int i = 0; i < 8; ++i) q[c][i] = col(c, z0 - 4 + i);
+    // p(n-1), w and p(z+4) at the thread's cells, plane by plane
+    T npm[R], nw[R], nq[R];
+    auto fetch = [&](int z) {
+        const T* ppm = cpm.plane();
+        const T* pw = cw.plane();
+        const T* pc = ccol.plane();
+        cpm.next();
+        cw.next();
+        ccol.next();
+        const bool cz = z + 4 < nz;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            nq[c] = (cin[c] && cz) ? pc[off[c]] : (T)0;
+            npm[c] = cin[c] ? ppm[off[c]] : (T)0;
+            nw[c] = cin[c] ? pw[off[c]] : (T)0;
+        }
+    };
+    if (PF) fetch(z0);
     stage_load(z0);
     stage_store(lds, 4);
     __syncthreads();
     for (int z = z0; z < z1; ++z) {
         const int b = (z - z0) & 1;
         const bool more = z + 1 < z1;
-        if (more) stage_load(z + 1);  // in flight while this plane is computed
+        if (!PF) fetch(z);
         T pm[R], w[R];
-        const T* ppm = cpm.plane();
-        const T* pw = cw.plane();
-        const T* pc = ccol.plane();
-        T* pd = cd.plane();
-        cpm.next();
-        cw.next();
-        ccol.next();
-        cd.next();
-        const bool cz = z + 4 < nz;
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            q[c][8] = (cin[c] && cz) ? pc[off[c]] : (T)0;
-            pm[c] = cin[c] ? ppm[off[c]] : (T)0;
-            w[c] = cin[c] ? pw[off[c]] : (T)0;
+            q[c][8] = nq[c];
+            pm[c] = npm[c];
+            w[c] = nw[c];
         }
+        if (more) stage_load(z + 1);  // in flight while this plane is computed
+        if (PF && more) fetch(z + 1);
+        T* pd = cd.plane();
+        cd.next();
         const T* t = lds + b * TP + (wv * R + 4) * TW + lx + 4;
 #pragma unroll
         for (int c = 0; c < R; ++c) {
