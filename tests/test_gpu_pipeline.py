@@ -318,10 +318,37 @@ def light_cone_point(u0, steps, z, y, x, alpha=0.1):
     return out[z - z0, y - y0, x - x0]
 
 
+def heat_light_cone_block_q(u0, rate, k, steps, zb, yb, xb, alpha=0.1):
+    """Oracle FP32 values of the 4x4x4 codec block at (zb, yb, xb) after
+    `steps` (a multiple of k) steps of the compressed heat schedule (the
+    store holds decode(encode()) of u after every k steps), from the block's
+    light cone: the box widened by k cells per remaining residency, each a
+    union of whole codec blocks when k is a multiple of 4."""
+    nz, ny, nx = u0.shape
+    m = steps // k
+    q = lambda a: O.codec_decode(O.codec_encode(np.ascontiguousarray(a), rate), a.shape, rate)  # noqa: E731
+
+    def box(r):
+        return (max(zb - r, 0), min(zb + 4 + r, nz), max(yb - r, 0), min(yb + 4 + r, ny),
+                max(xb - r, 0), min(xb + 4 + r, nx))
+
+    z0, z1, y0, y1, x0, x1 = box(k * m)
+    u = q(u0[z0:z1, y0:y1, x0:x1])
+    for r in range(m):
+        u = O.heat7_f32(u, alpha, k)
+        a0, a1, b0, b1, c0, c1 = box(k * (m - 1 - r))
+        u = q(u[a0 - z0:a1 - z0, b0 - y0:b1 - y0, c0 - x0:c1 - x0])
+        z0, z1, y0, y1, x0, x1 = a0, a1, b0, b1, c0, c1
+    return u
+
+
 @pytest.mark.parametrize("rate", [0, 8])
 def test_full_size_benchmark_configuration(rate):
     """512^3, 8 slabs of 64 planes, k = 4 (h = 4), 100 steps, device arena
-    capped at two slabs (128 MiB): the configuration the benchmark times."""
+    capped at two slabs (128 MiB): the configuration the benchmark times.
+    Compressed: the store equals the GPU's in-core replay bit for bit, and
+    sampled codec blocks equal the CPU oracle's values of the same schedule
+    on their light cones."""
     shape = (512, 512, 512)
     steps, k = 100, 4
     u0 = inputs.heat_uniform(shape, seed=0)
@@ -343,6 +370,11 @@ def test_full_size_benchmark_configuration(rate):
     if rate == 0:
         for (z, y, x) in ((0, 0, 0), (63, 255, 300), (64, 17, 511), (300, 500, 2)):
             assert got[z, y, x] == light_cone_point(u0, steps, z, y, x), (z, y, x)
+    else:  # codec blocks across a slab boundary and at a corner against the CPU oracle's schedule
+        for (zb, yb, xb) in ((60, 256, 300), (508, 508, 0)):
+            print(f"oracle block z={zb} y={yb} x={xb}", flush=True)
+            want = heat_light_cone_block_q(u0, rate, k, steps, zb, yb, xb)
+            assert np.array_equal(got[zb:zb + 4, yb:yb + 4, xb:xb + 4], want), (zb, yb, xb)
 
 
 _WAVE_FULL = {}
@@ -384,6 +416,42 @@ def wave_light_cone_point(d, steps, z, y, x):
     return p[z - z0, y - y0, x - x0]
 
 
+def wave_light_cone_block_q(d, rate, k, steps, zb, yb, xb):
+    """Oracle FP32 values of p on the 4x4x4 codec block at (zb, yb, xb) after
+    `steps` (a multiple of k) steps of the compressed schedule: the host
+    stores hold decode(encode()) of p and p(n-1) after every k steps, and w is
+    quantised once. Worked backwards from the block: after the last k steps
+    it needs the quantised state on the block widened by 4k cells (the light
+    cone), which needs the state k steps earlier on a box widened by 4k more,
+    and so on; every box is a union of whole codec blocks (4k is a multiple
+    of 4, and the grid's faces are block faces), so quantising a box equals
+    quantising the grid and cutting the box out. Zero ghosts at the real
+    faces; the artificial faces are dropped after each residency."""
+    nz, ny, nx = d["shape"]
+    m = steps // k
+    h = 4 * k
+    q = lambda a: O.codec_decode(O.codec_encode(np.ascontiguousarray(a), rate), a.shape, rate)  # noqa: E731
+
+    def box(r):  # the block widened by r cells, clipped to the grid
+        return (max(zb - r, 0), min(zb + 4 + r, nz), max(yb - r, 0), min(yb + 4 + r, ny),
+                max(xb - r, 0), min(xb + 4 + r, nx))
+
+    z0, z1, y0, y1, x0, x1 = box(h * m)
+    cut = lambda a: a[z0:z1, y0:y1, x0:x1]  # noqa: E731
+    p, pm, w = q(cut(d["p0"])), q(cut(d["pm0"])), q(cut(d["w"]))
+    sx, sy, sz = d["cell"]
+    for r in range(m):
+        src = None
+        if z0 <= sz < z1 and y0 <= sy < y1 and x0 <= sx < x1:
+            src = (d["amps"][r * k:(r + 1) * k], (sx - x0) + (x1 - x0) * ((sy - y0) + (y1 - y0) * (sz - z0)))
+        p, pm = O.wave25_f32(p, pm, w, k, src=src)
+        a0, a1, b0, b1, c0, c1 = box(h * (m - 1 - r))
+        sl = (slice(a0 - z0, a1 - z0), slice(b0 - y0, b1 - y0), slice(c0 - x0, c1 - x0))
+        p, pm, w = q(p[sl]), q(pm[sl]), w[sl]
+        z0, z1, y0, y1, x0, x1 = a0, a1, b0, b1, c0, c1
+    return p
+
+
 @pytest.mark.parametrize("policy", ["plain", "bench"])
 @pytest.mark.parametrize("rate", [0, 12])
 def test_full_size_wave_configuration(rate, policy):
@@ -395,7 +463,10 @@ def test_full_size_wave_configuration(rate, policy):
     around slab boundaries and near the source equal the oracle on their
     light cones; at 12 bits per value the store equals the GPU's in-core
     replay (12 steps, then decode(encode()) of both time levels; w quantised
-    once) bit for bit."""
+    once) bit for bit, and sampled codec blocks (at the source, across a
+    slab boundary, at both ends of the retained region, at a corner of the
+    grid) equal the CPU oracle's values of the same schedule on their light
+    cones."""
     d = _wave_full_inputs()
     shape, steps, k = d["shape"], 24, 12
     flags = {"snake": True, "ro_device_store": True, "retain": api.RETAIN_MAX} if policy == "bench" else {}
@@ -419,6 +490,10 @@ def test_full_size_wave_configuration(rate, policy):
             p, pm = q(p), q(pm)
         assert np.array_equal(got, p.cpu().numpy())
         del p, pm, w
+        for (zb, yb, xb) in ((16, 512, 512), (124, 300, 700), (384, 1020, 64), (640, 0, 512), (1020, 1020, 0)):
+            print(f"oracle block z={zb} y={yb} x={xb}", flush=True)
+            want = wave_light_cone_block_q(d, rate, k, steps, zb, yb, xb)
+            assert np.array_equal(got[zb:zb + 4, yb:yb + 4, xb:xb + 4], want), (zb, yb, xb)
     torch.cuda.empty_cache()
 
 
