@@ -570,15 +570,16 @@ int oocs_wave25_step_k_f64(double* d_p, double* d_pm, const double* d_w, int64_t
  * advance together. By default a run replays, as one HIP graph, one launch
  * per group (every tile of every domain, k steps). The persistent mode runs
  * the same work as one kernel launch: its workgroups take items (domain,
- * tile, group of k steps) in order from a device queue, and an item of
- * group g of a domain starts once every tile of group g-1 of that domain
- * has finished (a per-domain count of finished tiles, raised after a
- * device-scope release). Waits are bounded: a wait that exceeds its poll
- * limit sets a status word and every workgroup leaves, so the kernel always
- * ends; oocs_batch_check reports it. On a chip whose dies each have their
- * own L2, the device-scope release and acquire around every tile write back
- * and invalidate that L2, which costs more than the launch boundaries it
- * saves: the persistent mode is the slower one there and stays opt-in.
+ * up to 32 consecutive tiles, group of k steps) in order from a device
+ * queue, and an item of group g of a domain starts once every tile of group
+ * g-1 of that domain has finished (a per-domain count of finished tiles,
+ * raised after a device-scope release). Waits are bounded: a wait that
+ * exceeds its poll limit sets a status word and every workgroup leaves, so
+ * the kernel always ends; oocs_batch_check reports it. On a chip whose dies
+ * each have their own L2, the device-scope release and acquire around every
+ * item write back and invalidate that L2, which costs more than the launch
+ * boundaries it saves: the persistent mode is the slower one there and
+ * stays opt-in.
  * k > 1 is temporal blocking: a workgroup
  * advances its tile k steps in one pass over z, recomputing a k-cell halo,
  * so each cell crosses HBM once per k steps. The tile shape is chosen per

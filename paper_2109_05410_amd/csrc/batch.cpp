@@ -31,6 +31,7 @@ struct oocs_batch {
     uint32_t* d_sync = nullptr;            // queue, exit count, status, per-domain counts
     int32_t copy_items = 0;
     int32_t total_wg[2] = {0, 0};
+    int32_t total_items[2] = {0, 0};       // persistent items of one group
     size_t lds[2] = {0, 0};
     int grid[2] = {0, 0};                  // persistent grid: [0] blocked tiles, [1] depth-1 tiles
     int depth = 1;
@@ -248,9 +249,11 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
     }
     if (cache_dirty) write_cache(tune_cache, cache);
     // work list of every domain at depth dk, with its workgroup total and LDS
-    auto build_table = [&](int dk, std::vector<oocs::BatchDomain>& tab, int32_t& total, size_t& lds) -> int {
+    auto build_table = [&](int dk, std::vector<oocs::BatchDomain>& tab, int32_t& total, size_t& lds,
+                           int32_t* items = nullptr) -> int {
         total = 0;
         lds = 0;
+        int32_t nitems = 0;
         tab.resize(nd);
         for (int i = 0; i < nd; ++i) {
             oocs::BatchDomain& e = tab[i];
@@ -259,12 +262,14 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
             e.nx = (int32_t)doms[i].nx; e.ny = (int32_t)doms[i].ny; e.nz = (int32_t)doms[i].nz;
             e.cfg = best[{bucket_of(doms[i]), dk}].first;
             e.wg_begin = total;
-            e.pad = 0;
+            e.item_begin = nitems;
             const int64_t wgs = oocs::batch_domain_workgroups(e.nx, e.ny, e.nz, e.cfg);
             if (total + wgs > INT32_MAX / 2) return fail(OOCS_E_ARG, "batch too large for one launch");
             total += (int32_t)wgs;
+            nitems += (int32_t)((wgs + oocs::kBatchTilesPerItem - 1) / oocs::kBatchTilesPerItem);
             lds = std::max(lds, oocs::tile_cfg_lds(e.cfg));
         }
+        if (items) *items = nitems;
         return OOCS_OK;
     };
     // depth: the forced one; else, when tuning, the one whose launch over the
@@ -300,7 +305,7 @@ int oocs_batch_create(const oocs_domain* doms, int nd, float alpha, void* d_tabl
         if (best_t < 0) b->depth = 1;
     }
     for (int w = 0; w < 2; ++w) {
-        const int rc = build_table(w == 0 ? b->depth : 1, b->table[w], b->total_wg[w], b->lds[w]);
+        const int rc = build_table(w == 0 ? b->depth : 1, b->table[w], b->total_wg[w], b->lds[w], &b->total_items[w]);
         if (rc) { delete b; return rc; }
     }
     // copy items of each domain (a result left in the scratch buffer is moved
@@ -359,6 +364,7 @@ hipError_t add_persistent_nodes(const oocs_batch* b, int64_t steps, hipGraph_t g
         a.groups = (int32_t)l.groups;
         a.parity0 = (int32_t)l.parity0;
         a.total = b->total_wg[l.w];
+        a.items = b->total_items[l.w];
         a.copy_items = l.copy ? b->copy_items : 0;
         a.force_wait = b->force_wait ? 1 : 0;
         a.spin_limit = b->spin_limit;

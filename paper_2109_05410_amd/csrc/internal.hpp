@@ -154,9 +154,9 @@ struct BatchDomain {   // one entry of the device work-list table
     float* a;          // field at even steps (the caller's u)
     float* b;          // field at odd steps (the caller's scratch)
     int32_t nx, ny, nz;
-    int32_t cfg;       // index into kTileCfgs
-    int32_t wg_begin;  // first workgroup of this domain in a launch
-    int32_t pad;
+    int32_t cfg;         // index into kTileCfgs
+    int32_t wg_begin;    // first workgroup of this domain in a launch
+    int32_t item_begin;  // first item of this domain in a group of a persistent launch
 };
 
 // Workgroups one domain needs with tile configuration cfg.
@@ -166,11 +166,14 @@ int32_t batch_domain_workgroups(int nx, int ny, int nz, int cfg);
 size_t tile_cfg_lds(int cfg);
 
 // The persistent batched launch: one kernel runs groups of k steps of every
-// domain, as items (domain, tile, group) taken in order from a device queue;
-// an item of group g of domain d starts once every tile of group g-1 of d
-// has finished (a per-domain count of finished tiles). A launch holds the
-// groups of one work list; copy items after its last group move a result
-// left in the scratch buffers back to u (depth-1 launches only).
+// domain, as items (domain, up to kBatchTilesPerItem consecutive tiles,
+// group) taken in order from a device queue; an item of group g of domain d
+// starts once every tile of group g-1 of d has finished (a per-domain count
+// of finished tiles). A launch holds the groups of one work list; copy items
+// after its last group move a result left in the scratch buffers back to u
+// (depth-1 launches only). Each item costs a device-scope acquire and
+// release (on gfx950 an L2 invalidate and write-back, since the dies' L2s
+// are not coherent with each other), so items take several tiles.
 struct BatchPersistArgs {
     const BatchDomain* tab;     // work list of this launch's groups
     const int32_t* copy_begin;  // nd + 1 prefix sums of each domain's copy items
@@ -178,7 +181,8 @@ struct BatchPersistArgs {
     int32_t nd;
     int32_t groups;             // groups of this launch
     int32_t parity0;            // parity of its first group (0: reads a, writes b)
-    int32_t total;              // items of one group
+    int32_t total;              // tiles of one group
+    int32_t items;              // items of one group
     int32_t copy_items;
     int32_t force_wait;         // test hook: no wait is ever satisfied
     int64_t spin_limit;         // polls before a wait gives up and sets the status
@@ -186,6 +190,11 @@ struct BatchPersistArgs {
 };
 constexpr int kBatchSyncWords = 4;         // words of the sync area before the per-domain counts
 constexpr int kBatchCopyFloats = 1 << 16;  // floats one copy item moves
+// Tiles of one item: 64 heat cubes of sides 64..384 at depth 4 ran 186
+// GCell/s with one tile per item, 508 / 611 / 680 / 360 with 8 / 16 / 32 /
+// 128 (beyond 32 the items of the largest domain, done one after another
+// by a workgroup, make each group's critical path the limit).
+constexpr int kBatchTilesPerItem = 32;
 // tb: the list's tiles are temporally blocked (no copy items then).
 hipError_t launch_batch_persistent(const BatchPersistArgs& a, bool tb, int grid, size_t lds, hipStream_t stream);
 hipError_t add_batch_persistent_node(const BatchPersistArgs& a, bool tb, int grid, size_t lds, hipGraph_t g,

@@ -570,7 +570,8 @@ heat_dense_kernel(const float* src, float* dst, int nx, int ny, int nz, float al
 struct BatchItem {
     const BatchDomain* e;  // the domain's work-list entry
     int32_t d;             // domain
-    int32_t wg;            // tile (workgroup index within the domain) or copy item of the domain
+    int32_t wg;            // first tile (workgroup index within the domain) or copy item of the domain
+    int32_t nt;            // tiles of the item (1 for a copy item)
     int32_t g;             // group of this launch, or -1 for a copy item
     uint32_t need;         // finished tiles of d this item waits for
 };
@@ -578,14 +579,14 @@ struct BatchItem {
 __device__ inline BatchItem batch_item(const BatchPersistArgs& a, uint32_t i)
 {
     BatchItem it;
-    const uint32_t n = (uint32_t)a.groups * (uint32_t)a.total;
+    const uint32_t n = (uint32_t)a.groups * (uint32_t)a.items;
     int32_t r;
-    const int32_t* begin;  // per domain: first item (tile or copy item) of the domain
+    const int32_t* begin;  // per domain: first item (tiles or copy) of the domain
     int stride;            // in int32 words
     if (i < n) {
-        it.g = (int32_t)(i / (uint32_t)a.total);
-        r = (int32_t)(i % (uint32_t)a.total);
-        begin = &a.tab->wg_begin;
+        it.g = (int32_t)(i / (uint32_t)a.items);
+        r = (int32_t)(i % (uint32_t)a.items);
+        begin = &a.tab->item_begin;
         stride = (int)(sizeof(BatchDomain) / sizeof(int32_t));
     } else {
         it.g = -1;
@@ -600,9 +601,15 @@ __device__ inline BatchItem batch_item(const BatchPersistArgs& a, uint32_t i)
     }
     it.d = lo;
     it.e = a.tab + lo;
-    it.wg = r - begin[lo * stride];
-    const uint32_t tiles = (uint32_t)((lo + 1 < a.nd ? a.tab[lo + 1].wg_begin : a.total) - a.tab[lo].wg_begin);
-    it.need = (uint32_t)(it.g < 0 ? a.groups : it.g) * tiles;
+    const int32_t tiles = (lo + 1 < a.nd ? a.tab[lo + 1].wg_begin : a.total) - a.tab[lo].wg_begin;
+    if (it.g >= 0) {
+        it.wg = (r - begin[lo * stride]) * kBatchTilesPerItem;
+        it.nt = min(kBatchTilesPerItem, tiles - it.wg);
+    } else {
+        it.wg = r - begin[lo * stride];
+        it.nt = 1;
+    }
+    it.need = (uint32_t)(it.g < 0 ? a.groups : it.g) * (uint32_t)tiles;
     return it;
 }
 
@@ -664,7 +671,7 @@ __device__ inline BatchDomain uniform_entry(const BatchDomain* p)
     e.nz = uni(p->nz);
     e.cfg = uni(p->cfg);
     e.wg_begin = uni(p->wg_begin);
-    e.pad = 0;
+    e.item_begin = uni(p->item_begin);
     return e;
 }
 
@@ -687,7 +694,7 @@ __global__ void __launch_bounds__(kBlockThreads, TB ? 7 : 8) batch_persistent_ke
     uint32_t* exited = a.sync + 1;
     uint32_t* status = a.sync + 2;
     uint32_t* done = a.sync + kBatchSyncWords;
-    const uint32_t total = (uint32_t)a.groups * (uint32_t)a.total + (TB ? 0u : (uint32_t)a.copy_items);
+    const uint32_t total = (uint32_t)a.groups * (uint32_t)a.items + (TB ? 0u : (uint32_t)a.copy_items);
     float* lds = reinterpret_cast<float*>(dyn_lds);
     for (;;) {
         if (threadIdx.x < 64) {  // wave 0, all lanes (a wave-uniform branch)
@@ -708,11 +715,16 @@ __global__ void __launch_bounds__(kBlockThreads, TB ? 7 : 8) batch_persistent_ke
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const BatchItem it = batch_item(a, i);
         const BatchDomain e = uniform_entry(it.e);
+        const int nt = uni(it.nt);
         if (TB || it.g >= 0) {
             const bool odd = ((it.g + a.parity0) & 1) != 0;
             const float* src = odd ? e.b : e.a;
             float* dst = odd ? e.a : e.b;
-            heat_dense_any<TB>(e.cfg, src, dst, e.nx, e.ny, e.nz, a.alpha, it.wg, lds);
+            const int wg0 = uni(it.wg);
+            for (int t = 0; t < nt; ++t) {
+                if (t) __syncthreads();  // the tiles share the workgroup's LDS
+                heat_dense_any<TB>(e.cfg, src, dst, e.nx, e.ny, e.nz, a.alpha, wg0 + t, lds);
+            }
         } else {
             // the last group left the state in b: move kBatchCopyFloats of it
             const int64_t n = (int64_t)e.nx * e.ny * e.nz;
@@ -725,7 +737,7 @@ __global__ void __launch_bounds__(kBlockThreads, TB ? 7 : 8) batch_persistent_ke
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (threadIdx.x == 0 && (TB || it.g >= 0))  // a single atomic, no loop: safe for one lane
-            __hip_atomic_fetch_add(done + it.d, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(done + it.d, (uint32_t)nt, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (threadIdx.x == 0) {
         const uint32_t n = __hip_atomic_fetch_add(exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
