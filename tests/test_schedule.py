@@ -813,7 +813,7 @@ def from_store64(s, shape, rate):
 @pytest.mark.parametrize("rates,k,steps,kw", [
     ([0, 0, 0], 3, 7, {}), ([24, 32, 24], 4, 9, {}), ([32, 0, 24], 4, 9, {"block_restart": True}),
     ([40, 40, 40], 4, 11, {"snake": True}), ([24, 24, 24], 4, 9, {"snake": True, "resident_ro": True}),
-    ([68, 12, 0], 2, 5, {}),
+    ([68, 12, 0], 2, 5, {}), ([24, 32, 24], 4, 13, {"snake": True, "retain": 2, "ro_device_store": True}),
 ])
 def test_fp64_wave_schedule_computes_the_fp64_replay(rates, k, steps, kw):
     shape = (64, 12, 12)
@@ -847,6 +847,7 @@ def test_fp64_plan_sizes():
     assert [c64.store_bytes(f) for f in range(3)] == [64 * 16 * 16 * r // 8 for r in (24, 68, 32)]
     race_check(c64, 9)
     race_check(plan(shape, WAVE25, 2, 4, [24, 24, 24], 64 * MiB, fp64=True, snake=True), 13)
+    race_check(plan(shape, WAVE25, 2, 4, [24, 24, 24], 64 * MiB, fp64=True, snake=True, retain=2), 13)
 
 
 def test_fp64_plan_errors():
