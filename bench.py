@@ -17,10 +17,10 @@ the orchestration the paper leaves to future work
 (Sec. VII); one retained slab, one-way sweeps and the paper's per-block
 schedule of Fig. 2 are reported beside it. The read-only field's host store
 is copied into the arena once (1.5 GiB at 12 bits, inside the 8 GiB cap) and
-decoded from there every residency; p and p(n-1) cross the host link both
-ways every round. The paper's flow, which streams the read-only chunks over
-the link every residency, is reported beside it, and the paper's codes 2-4
-use it.
+decoded from there every residency; the planes of p and p(n-1) outside the
+retained region cross the host link both ways every round. The paper's flow, which streams every field's chunks (the
+read-only ones included) over the link every residency, with one retained
+slab, is reported beside it, and the paper's codes 2-4 use it.
 
 One bench step = one round of the method: every block of the grid advanced
 k = 12 steps (12 * 1024^3 cell updates), all transfers included. The timed
@@ -894,13 +894,13 @@ def main():
         key = "uncompressed" if r == 0 else f"rate{r}"
         variants[key] = wave_window(api, torch, wi, state, [r] * 3, args.steps if r else vr, 1)
         log(f"{key}: {variants[key]['gcells_per_s']:.1f} GCell-updates/s")
-    # the paper's flow: the read-only chunks streamed over the link every
-    # residency
+    # the paper's flow: every field's chunks streamed over the link every
+    # residency (the snake's one retained slab aside)
     streamed = {}
     for r in (HEADLINE_RATE, 0):
         key = "uncompressed" if r == 0 else f"rate{r}"
         streamed[key] = wave_window(api, torch, wi, state, [r] * 3, args.steps if r else vr, 1,
-                                    ro_device_store=False)
+                                    ro_device_store=False, retain=1)
         log(f"streamed read-only {key}: {streamed[key]['gcells_per_s']:.1f} GCell-updates/s")
     # one retained slab (the plain snake)
     variants[f"rate{HEADLINE_RATE}_retain_one_slab"] = wave_window(api, torch, wi, state, head_rates, args.steps, 1,
@@ -914,7 +914,7 @@ def main():
     # the headline rate
     codes = {}
     for code, rates in ((2, [0, HEADLINE_RATE, 0]), (3, [0, 0, HEADLINE_RATE]), (4, [0, HEADLINE_RATE, HEADLINE_RATE])):
-        codes[f"code{code}"] = wave_window(api, torch, wi, state, rates, vr, 1, ro_device_store=False)
+        codes[f"code{code}"] = wave_window(api, torch, wi, state, rates, vr, 1, ro_device_store=False, retain=1)
         log(f"code {code}: {codes[f'code{code}']['gcells_per_s']:.1f} GCell-updates/s")
     codes["code1"] = {"same_as": "streamed_read_only.uncompressed"}
     fp64 = None
