@@ -425,9 +425,9 @@ int Planner::choose(size_t arena_bytes, std::string& err)
                 // for a larger region slows every tick)
                 while (retain_max && X + slab <= nz) {
                     X += slab;
-                    const int64_t more = layout(g, ns, err);
-                    if (more < 0) return OOCS_E_STATE;
-                    if ((size_t)more > arena_bytes) {
+                    std::string e2;
+                    const int64_t more = layout(g, ns, e2);
+                    if (more < 0 || (size_t)more > arena_bytes) {  // does not fit (or cannot be scheduled)
                         X -= slab;
                         if (layout(g, ns, err) < 0) return OOCS_E_STATE;
                         break;
