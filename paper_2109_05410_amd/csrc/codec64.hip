@@ -315,36 +315,35 @@ __device__ inline void ring_copy_job(const Job& j, int nx, int ny, int wg, bool 
 }
 
 // Wave levels are the FP32 pipeline's LDS-staged tile in double (the same
-// operation order as the FP64 step above).
-// The codec workgroups (the last ones of the job list) spread evenly among
-// the others, as in the FP32 pipeline kernel: block b takes the next codec
-// workgroup wherever floor(b*C/T) steps up.
-__device__ inline int spread64(const LaunchParams& p)
-{
-    const int b = (int)blockIdx.x;
-    if (p.ncodec == 0 || p.nfirst == 0) return b;
-    const int64_t T = (int64_t)p.nfirst + p.ncodec;
-    const int c0 = (int)((int64_t)b * p.ncodec / T), c1 = (int)((int64_t)(b + 1) * p.ncodec / T);
-    return c1 > c0 ? p.nfirst + c0 : b - c0;
-}
-
+// operation order as the FP64 step above). The jobs of a tick run as two
+// kernels, the stencil and copy jobs (the first workgroups of the list),
+// then the codec jobs (the last ones): the FP64 codec needs about 215 VGPRs
+// per lane and the wave tile 116, and one kernel holding both ran every job
+// at two waves per SIMD (with spills), where the stencil kernel alone keeps
+// four. PART 1: workgroup b runs workgroup b of the list; PART 2: workgroup
+// nfirst + b.
+template <int PART>
 __global__ void __launch_bounds__(kBlockThreads) fused64_kernel(LaunchParams p)
 {
-    const int wg = spread64(p);
+    const int wg = PART == 1 ? (int)blockIdx.x : p.nfirst + (int)blockIdx.x;
     int jdx = 0;
     while (jdx + 1 < p.njobs && wg >= p.wg_begin[jdx + 1]) ++jdx;
     const Job& j = p.jobs[jdx];
     const int local = wg - p.wg_begin[jdx];
-    switch (j.kind) {
-    case JOB_WAVE:
-        stencil::wave_tile<double, kTileY64>(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table, p.step_ctr,
-                                             local, reinterpret_cast<double*>(dyn_lds64));
-        break;
-    case JOB_DECODE: ring_codec_job(j, p.nx, p.ny, local, false); break;
-    case JOB_ENCODE: ring_codec_job(j, p.nx, p.ny, local, true); break;
-    case JOB_COPY_IN: ring_copy_job(j, p.nx, p.ny, local, true); break;
-    case JOB_COPY_OUT: ring_copy_job(j, p.nx, p.ny, local, false); break;
-    default: break;
+    if constexpr (PART == 1) {
+        switch (j.kind) {
+        case JOB_WAVE:
+            stencil::wave_tile<double, kTileY64>(j, p.nx, p.ny, p.nz, p.src_x, p.src_y, p.src_z, p.src_table,
+                                                 p.step_ctr, local, reinterpret_cast<double*>(dyn_lds64));
+            break;
+        case JOB_COPY_IN: ring_copy_job(j, p.nx, p.ny, local, true); break;
+        case JOB_COPY_OUT: ring_copy_job(j, p.nx, p.ny, local, false); break;
+        default: break;
+        }
+    } else if (j.kind == JOB_DECODE || j.kind == JOB_ENCODE) {
+        // one call with the direction as a value: two inlined copies, one per
+        // direction, made the kernel spill 400 bytes per lane
+        ring_codec_job(j, p.nx, p.ny, local, j.kind == JOB_ENCODE);
     }
 }
 
@@ -374,15 +373,16 @@ static int32_t job_workgroups64(const Job& j, int nx, int ny)
 
 }  // namespace codec64
 
-// Stencil and copy jobs first, codec jobs last (as in the FP32 kernel: the
-// codec waves fill the slots the others leave).
-bool prepare_jobs_f64(LaunchParams& p, const void** func, unsigned* grid, size_t* lds)
+// Stencil and copy jobs first, codec jobs last; up to two kernels in launch
+// order (the first part, then the codec part), each with its grid and LDS.
+int prepare_jobs_f64(LaunchParams& p, const void* func[2], unsigned grid[2], size_t lds[2])
 {
     Job sorted[kMaxJobs];
     int n = 0;
+    auto codec = [](int kind) { return kind == JOB_DECODE || kind == JOB_ENCODE; };
     for (int pass = 0; pass < 2; ++pass)
         for (int i = 0; i < p.njobs; ++i)
-            if ((p.jobs[i].kind == JOB_DECODE || p.jobs[i].kind == JOB_ENCODE) == (pass == 1)) sorted[n++] = p.jobs[i];
+            if (codec(p.jobs[i].kind) == (pass == 1)) sorted[n++] = p.jobs[i];
     int32_t total = 0;
     for (int i = 0; i < n; ++i) {
         p.jobs[i] = sorted[i];
@@ -391,30 +391,47 @@ bool prepare_jobs_f64(LaunchParams& p, const void** func, unsigned* grid, size_t
         total += p.jobs[i].wg_count;
     }
     p.wg_begin[p.njobs] = total;
-    if (total == 0) return false;
     p.nfirst = p.ncodec = 0;
-    for (int i = 0; i < n; ++i)
-        ((p.jobs[i].kind == JOB_DECODE || p.jobs[i].kind == JOB_ENCODE) ? p.ncodec : p.nfirst) += p.jobs[i].wg_count;
-    size_t need = 0;
+    size_t lds_first = 0, lds_codec = 0;
     for (int i = 0; i < n; ++i) {
-        if (p.jobs[i].kind == JOB_WAVE) need = std::max(need, stencil::wave_tile_lds<double, codec64::kTileY64>());
-        if (p.jobs[i].kind == JOB_DECODE || p.jobs[i].kind == JOB_ENCODE)
-            need = std::max(need, (size_t)codec64::kWaves * 64 * p.jobs[i].rate * sizeof(uint64_t));
+        if (codec(p.jobs[i].kind)) {
+            p.ncodec += p.jobs[i].wg_count;
+            lds_codec = std::max(lds_codec, (size_t)codec64::kWaves * 64 * p.jobs[i].rate * sizeof(uint64_t));
+        } else {
+            p.nfirst += p.jobs[i].wg_count;
+            if (p.jobs[i].kind == JOB_WAVE)
+                lds_first = std::max(lds_first, stencil::wave_tile_lds<double, codec64::kTileY64>());
+        }
     }
-    *func = reinterpret_cast<const void*>(&codec64::fused64_kernel);
-    *grid = (unsigned)total;
-    *lds = need;
-    return true;
+    int k = 0;
+    if (p.nfirst > 0) {
+        func[k] = reinterpret_cast<const void*>(&codec64::fused64_kernel<1>);
+        grid[k] = (unsigned)p.nfirst;
+        lds[k++] = lds_first;
+    }
+    if (p.ncodec > 0) {
+        func[k] = reinterpret_cast<const void*>(&codec64::fused64_kernel<2>);
+        grid[k] = (unsigned)p.ncodec;
+        lds[k++] = lds_codec;
+    }
+    return k;
 }
 
 hipError_t launch_jobs_f64(LaunchParams& p, hipStream_t stream)
 {
-    const void* func;
-    unsigned grid;
-    size_t lds;
-    if (!prepare_jobs_f64(p, &func, &grid, &lds)) return hipSuccess;
-    hipLaunchKernelGGL(codec64::fused64_kernel, dim3(grid), dim3(kBlockThreads), lds, stream, p);
-    return hipGetLastError();
+    const void* func[2];
+    unsigned grid[2];
+    size_t lds[2];
+    const int nk = prepare_jobs_f64(p, func, grid, lds);
+    for (int i = 0; i < nk; ++i) {
+        if (func[i] == reinterpret_cast<const void*>(&codec64::fused64_kernel<1>))
+            hipLaunchKernelGGL(codec64::fused64_kernel<1>, dim3(grid[i]), dim3(kBlockThreads), lds[i], stream, p);
+        else
+            hipLaunchKernelGGL(codec64::fused64_kernel<2>, dim3(grid[i]), dim3(kBlockThreads), lds[i], stream, p);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace oocs

@@ -99,7 +99,9 @@ hipError_t add_jobs_node(LaunchParams& p, hipGraph_t g, const hipGraphNode_t* de
 // FP64 jobs (Job::f64; every job of the launch): the FP64 pipeline kernel,
 // which runs wave levels, FP64-format codec jobs and raw copies. launch_jobs
 // and add_jobs_node hand such launches to these.
-bool prepare_jobs_f64(LaunchParams& p, const void** func, unsigned* grid, size_t* lds);
+// FP64 jobs: up to two kernels per tick (the stencil and copy jobs, then the
+// codec jobs), returned in launch order; the count is the return value.
+int prepare_jobs_f64(LaunchParams& p, const void* func[2], unsigned grid[2], size_t lds[2]);
 hipError_t launch_jobs_f64(LaunchParams& p, hipStream_t stream);
 
 // Device step counter of the wave source table: set to `value` (add = false)

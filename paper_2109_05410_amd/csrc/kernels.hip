@@ -279,7 +279,6 @@ static int dispatch_class(int kind) { return is_xfer_job(kind) ? 0 : (is_codec_j
 
 static bool prepare_jobs(LaunchParams& p, const void** func, unsigned* grid, size_t* lds)
 {
-    if (p.njobs > 0 && p.jobs[0].f64) return prepare_jobs_f64(p, func, grid, lds);
     Job sorted[kMaxJobs];
     int n = 0;
     for (int pass = 0; pass < 3; ++pass)
@@ -344,20 +343,32 @@ hipError_t launch_jobs(LaunchParams& p, hipStream_t stream)
 
 hipError_t add_jobs_node(LaunchParams& p, hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps, hipGraphNode_t* node)
 {
-    const void* func;
-    unsigned grid;
-    size_t lds;
+    const void* func[2];
+    unsigned grid[2];
+    size_t lds[2];
+    int nk;
     *node = nullptr;
-    if (!prepare_jobs(p, &func, &grid, &lds)) return hipSuccess;
-    void* args[] = {&p};
-    hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(func);
-    kp.gridDim = dim3(grid);
-    kp.blockDim = dim3(kBlockThreads);
-    kp.sharedMemBytes = (unsigned)lds;
-    kp.kernelParams = args;
-    kp.extra = nullptr;
-    return hipGraphAddKernelNode(node, g, deps, ndeps, &kp);
+    if (p.njobs > 0 && p.jobs[0].f64) {
+        nk = prepare_jobs_f64(p, func, grid, lds);
+    } else {
+        nk = prepare_jobs(p, &func[0], &grid[0], &lds[0]) ? 1 : 0;
+    }
+    // the kernels of a tick in a chain; *node is the last one
+    for (int i = 0; i < nk; ++i) {
+        void* args[] = {&p};
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void*>(func[i]);
+        kp.gridDim = dim3(grid[i]);
+        kp.blockDim = dim3(kBlockThreads);
+        kp.sharedMemBytes = (unsigned)lds[i];
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t prev = *node;
+        const hipError_t e = i == 0 ? hipGraphAddKernelNode(node, g, deps, ndeps, &kp)
+                                    : hipGraphAddKernelNode(node, g, &prev, 1, &kp);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 __global__ void step_ctr_kernel(int32_t* ctr, int add, int32_t value)
