@@ -160,7 +160,8 @@ int oocs_heat7_step_k_noalloc(float* d_u, int64_t nx, int64_t ny, int64_t nz, fl
  * On entry (d_pm, d_p) = (p(n-1), p(n)); on exit (p(n+k-1), p(n+k)).
  * h_src holds k host amplitudes (s(n) .. s(n+k-1)) or is NULL; the source
  * cell is (src_x, src_y, src_z) or any coordinate < 0 for none.
- * Errors: OOCS_E_ARG, OOCS_E_HIP. */
+ * Errors: OOCS_E_ARG (also for planes of 4 GiB or more: nx * ny * 4 >=
+ * 2^32), OOCS_E_HIP. */
 int oocs_wave25_step_k(float* d_p, float* d_pm, const float* d_w, int64_t nx, int64_t ny, int64_t nz, int64_t k,
                        const float* h_src, int64_t src_x, int64_t src_y, int64_t src_z, void* stream);
 
@@ -313,9 +314,10 @@ typedef struct {
  * for the wave, whose ticks are long already), whose rings and staging fit
  * arena_bytes. The plan keeps d_arena; the caller keeps it
  * alive until oocs_plan_destroy.
- * Errors: OOCS_E_ARG, OOCS_E_ALIGN (a compressed field with nz/nslabs or h
- * not a multiple of 4), OOCS_E_HALO (2h > nz/nslabs), OOCS_E_RATE, OOCS_E_CAP
- * (nothing fits arena_bytes), OOCS_E_HIP (stream or event creation). */
+ * Errors: OOCS_E_ARG (also a wave plane of 4 GiB or more), OOCS_E_ALIGN (a
+ * compressed field with nz/nslabs or h not a multiple of 4), OOCS_E_HALO
+ * (2h > nz/nslabs), OOCS_E_RATE, OOCS_E_CAP (nothing fits arena_bytes),
+ * OOCS_E_HIP (stream or event creation). */
 int oocs_plan_create(const oocs_config* cfg, void* d_arena, size_t arena_bytes, oocs_plan** out);
 
 /* Release the plan's streams and events (not the arena). NULL is allowed. */
@@ -561,7 +563,8 @@ int oocs_codec64_decode_stages(const uint64_t* d_words, int64_t nblocks, int rat
 /* k FP64 leapfrog steps of the 25-point wave in place on (d_pm, d_p) =
  * (p(n-1), p(n)), d_w read-only; the FP32 step's formula and operation
  * order in double (the paper's precision). h_src: k amplitudes added at
- * the source cell (host memory), or NULL. */
+ * the source cell (host memory), or NULL. Planes must hold less than 4 GiB
+ * (nx * ny * 8 < 2^32), else OOCS_E_ARG. */
 int oocs_wave25_step_k_f64(double* d_p, double* d_pm, const double* d_w, int64_t nx, int64_t ny, int64_t nz,
                            int64_t k, const double* h_src, int64_t src_x, int64_t src_y, int64_t src_z, void* stream);
 

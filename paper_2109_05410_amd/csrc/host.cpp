@@ -236,6 +236,7 @@ int oocs_wave25_step_k_f64(double* d_p, double* d_pm, const double* d_w, int64_t
     if (!d_p || !d_pm || !d_w || k < 0 || nx <= 0 || ny <= 0 || nz <= 0) return fail(OOCS_E_ARG, "bad argument");
     if (nx * ny * nz >= ((int64_t)1 << 40) || nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20))
         return fail(OOCS_E_ARG, "grid too large");
+    if (nx * ny * 8 >= ((int64_t)1 << 32)) return fail(OOCS_E_ARG, "a plane of the wave must hold less than 4 GiB");
     const bool src_on = h_src && src_x >= 0 && src_x < nx && src_y >= 0 && src_y < ny && src_z >= 0 && src_z < nz;
     const int64_t cell = src_on ? src_x + nx * (src_y + ny * src_z) : -1;
     hipStream_t s = (hipStream_t)stream;
@@ -334,6 +335,7 @@ int oocs_wave25_step_k(float* d_p, float* d_pm, const float* d_w, int64_t nx, in
 {
     if (!d_p || !d_pm || !d_w || k < 0) return fail(OOCS_E_ARG, "bad argument");
     if (!grid_ok(nx, ny, nz)) return fail(OOCS_E_ARG, "bad grid (nx must be a multiple of 4)");
+    if (nx * ny * 4 >= ((int64_t)1 << 32)) return fail(OOCS_E_ARG, "a plane of the wave must hold less than 4 GiB");
     hipStream_t s = (hipStream_t)stream;
     float* p = d_p;
     float* pm = d_pm;

@@ -49,6 +49,10 @@ int Planner::init(const oocs_config& c, std::string& err)
         return OOCS_E_ARG;
     }
     esize = fp64 ? 8 : 4;
+    if (c.stencil == OOCS_WAVE25 && nx * ny * esize >= ((int64_t)1 << 32)) {
+        err = "a plane of the wave must hold less than 4 GiB";  // the wave tile addresses a plane with 32-bit offsets
+        return OOCS_E_ARG;
+    }
     const int max_rate = fp64 ? OOCS_MAX_RATE64 : OOCS_MAX_RATE;
     bool any_rate = false;
     for (int f = 0; f < nfields; ++f) {

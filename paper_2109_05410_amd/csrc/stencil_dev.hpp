@@ -340,15 +340,22 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
     if (z0 >= z1) return;  // the same for the whole workgroup
     const int tid = (int)threadIdx.x, lx = tid & 63, wv = tid >> 6;
     const int x = x0 + lx;
+    // Offsets within a plane are 32-bit byte offsets (planes of the wave hold
+    // less than 4 GiB, which the planner and the in-core entry points check),
+    // so every load and store is a wave-uniform plane address plus one 32-bit
+    // register.
     bool cin[R], srcc[R];
-    int64_t off[R];
+    uint32_t off[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const int y = y0 + wv * R + c;
         cin[c] = x < nx && y < ny;
         srcc[c] = j.has_src && x == sx && y == sy;
-        off[c] = (int64_t)y * nx + x;
+        off[c] = cin[c] ? (uint32_t)(((uint64_t)y * nx + x) * sizeof(T)) : 0u;
     }
+    auto at = [](const T* plane, uint32_t boff) -> const T& {
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + boff);
+    };
     // A staged plane is the tile's centre (this workgroup's cells, TY rows of
     // 64) and its 4-cell halo ring. The centre values are p(z') at the
     // thread's own cells, which the thread already holds in its column
@@ -358,7 +365,7 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
     // right of each centre row).
     constexpr int HALO = TP - 64 * TY;
     constexpr int HPT = (HALO + kBlockThreads - 1) / kBlockThreads;  // halo values per thread
-    int64_t soff[HPT];
+    uint32_t soff[HPT];
     int sidx[HPT];  // position in the staged plane
     bool sok[HPT], shas[HPT];
 #pragma unroll
@@ -378,7 +385,7 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
         sidx[i] = shas[i] ? r * TW + cl : 0;
         const int gx = x0 - 4 + cl, gy = y0 - 4 + r;
         sok[i] = shas[i] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-        soff[i] = (int64_t)gy * nx + gx;
+        soff[i] = sok[i] ? (uint32_t)(((uint64_t)gy * nx + gx) * sizeof(T)) : 0u;
     }
     T st[HPT];
     // staged planes are taken in order z0, z0 + 1, ...
@@ -388,7 +395,7 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
         const T* pl = cs.plane();
         cs.next();
 #pragma unroll
-        for (int i = 0; i < HPT; ++i) st[i] = (zin && sok[i]) ? pl[soff[i]] : (T)0;
+        for (int i = 0; i < HPT; ++i) st[i] = (zin && sok[i]) ? at(pl, soff[i]) : (T)0;
     };
     T q[R][9];  // q[c][i] = p(z - 4 + i) at cell c
     // the staged halo, and the centre from the column queue entry `at` (this
@@ -400,7 +407,7 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
 #pragma unroll
         for (int c = 0; c < R; ++c) t[(wv * R + c + 4) * TW + lx + 4] = q[c][at];
     };
-    auto col = [&](int c, int z) -> T { return (cin[c] && z >= 0 && z < nz) ? ring_plane_t<T>(j.src, z)[off[c]] : (T)0; };
+    auto col = [&](int c, int z) -> T { return (cin[c] && z >= 0 && z < nz) ? at(ring_plane_t<T>(j.src, z), off[c]) : (T)0; };
     PlaneCursor<T> ccol(j.src, z0 + 4);  // p(z + 4) at the cell, read plane by plane
 #pragma unroll
     for (int c = 0; c < R; ++c)
@@ -418,9 +425,9 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
         const bool cz = z + 4 < nz;
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            nq[c] = (cin[c] && cz) ? pc[off[c]] : (T)0;
-            npm[c] = cin[c] ? ppm[off[c]] : (T)0;
-            nw[c] = cin[c] ? pw[off[c]] : (T)0;
+            nq[c] = (cin[c] && cz) ? at(pc, off[c]) : (T)0;
+            npm[c] = cin[c] ? at(ppm, off[c]) : (T)0;
+            nw[c] = cin[c] ? at(pw, off[c]) : (T)0;
         }
     };
     if (PF) fetch(z0);
@@ -452,7 +459,7 @@ __device__ inline void wave_tile(const Job& j, int nx, int ny, int nz, int sx, i
                 acc = acc + CM[m - 1] * (((tc[m] + tc[-m]) + (tc[m * TW] + tc[-m * TW])) + (q[c][4 + m] + q[c][4 - m]));
             T v = ((T)2 * q[c][4] - pm[c]) + w[c] * acc;
             if (srcc[c] && z == sz) v = v + (T)(src_table ? src_table[*step_ctr + j.src_off] : j.amp);
-            if (cin[c]) pd[off[c]] = v;
+            if (cin[c]) *reinterpret_cast<T*>(reinterpret_cast<char*>(pd) + off[c]) = v;
         }
         if (more) stage_store(lds + (b ^ 1) * TP, 5);  // plane z + 1
         __syncthreads();

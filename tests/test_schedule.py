@@ -11,6 +11,8 @@ copies, compute, device-to-host copies; Sec. V-B) is
      replay of the compressed schedule. Together with 1 this covers every
      legal concurrent execution.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -776,6 +778,28 @@ def test_retain_max_at_the_wave_size():
     assert raw.info["retained_planes"] == 128
     race_check(plan((1024, 16, 16), WAVE25, 8, 12, [8, 8, 8], 64 * MiB, snake=True, src_cell=(3, 3, 5),
                     retain=L.OOCS_RETAIN_MAX), 36)
+
+
+def test_wave_planes_under_4_gib():
+    """The wave tile addresses a plane with 32-bit byte offsets: a wave plan
+    or an in-core wave step whose planes hold 4 GiB or more is refused
+    before any device call (heat has no such limit)."""
+    big = (16, 32768, 32768)  # 2^30 values per plane: 4 GiB in FP32
+    for kw in ({}, {"fp64": True}):
+        with pytest.raises(L.OocsError) as e:
+            plan(big, WAVE25, 2, 1, [0, 0, 0], 1 << 40, **kw)
+        assert e.value.code == L.OOCS_E_ARG
+    with pytest.raises(L.OocsError) as e:  # FP64: 2^29 values per plane are 4 GiB already
+        plan((16, 16384, 32768), WAVE25, 2, 1, [0, 0, 0], 1 << 40, fp64=True)
+    assert e.value.code == L.OOCS_E_ARG
+    plan((16, 16384, 32768), WAVE25, 2, 1, [0, 0, 0], 1 << 40)  # 2 GiB FP32 planes are fine
+    plan(big, HEAT7, 2, 1, [0], 1 << 40)
+    fake = C.c_void_p(1)  # never dereferenced: the check comes first
+    for fn, esz in ((L.lib().oocs_wave25_step_k, 4), (L.lib().oocs_wave25_step_k_f64, 8)):
+        ny = (1 << 32) // esz // 32768
+        rc = fn(fake, fake, fake, C.c_int64(32768), C.c_int64(ny), C.c_int64(8), C.c_int64(1), None,
+                C.c_int64(-1), C.c_int64(-1), C.c_int64(-1), None)
+        assert rc == L.OOCS_E_ARG
 
 
 def test_retain_errors():
