@@ -756,6 +756,26 @@ def test_retained_regions_compute_the_replay(case, retain, planes):
     _snake_replay(shape, st, n, k, rates, arena, steps, False, retain=retain)
 
 
+@pytest.mark.parametrize("rule", ["zero", "swapped"])
+def test_retained_addressing_mistakes_are_caught(rule, monkeypatch):
+    """The race detector and the executor are not vacuous for retained
+    regions: with a wrong buffer-place rule planted in their model (every op
+    at base 0, or the decode and encode bases swapped), a plan whose regions
+    overlap fails the race check or the replay."""
+    wrong = {
+        "zero": lambda self, encode, variant: 0,
+        "swapped": lambda self, encode, variant: self.nz - self.X if encode == bool(variant & L.OOCS_SCHED_MIRROR) else 0,
+    }[rule]
+    monkeypatch.setattr(Geometry, "ret_base", wrong)
+    for (shape, st, n, k, rates, arena, steps), retain in [(((48, 12, 16), HEAT7, 4, 4, [8], 2 * MiB, 11), 3),
+                                                            (((128, 12, 12), WAVE25, 4, 4, [12, 12, 12], 8 * MiB, 14), 3)]:
+        p = plan(shape, st, n, k, rates, arena, src_cell=(3, 3, 5) if st == WAVE25 else None, snake=True,
+                 retain=retain)
+        with pytest.raises((AssertionError, KeyError)):
+            race_check(p, steps)
+            _snake_replay(shape, st, n, k, rates, arena, steps, False, retain=retain)
+
+
 def test_retain_max_at_the_wave_size():
     """1024^3 wave, 8 slabs, k = 12, 8 GiB: at 12 bits per value five of
     the eight slabs of compressed p and p(n-1) fit beside the pipeline, at
